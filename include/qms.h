@@ -1,0 +1,174 @@
+/*
+ * qms.h -- QuickMergesort on AMD Instinct MI355X (gfx950): the C ABI of
+ * libqms.so.
+ *
+ * The method (Edelkamp & Weiss, "QuickMergesort: Practically Efficient
+ * Constant-Factor Optimal Sorting", Sec. "QuickXsort and QuickMergesort",
+ * Fig. 2): a median-of-3 pivot partitions the array; the smaller side is
+ * sorted by Mergesort while the other side serves as swap space (every
+ * element Mergesort would move out is exchanged with a buffer element); the
+ * loop continues on the larger side.  Each array is sorted in place.
+ *
+ * Conventions shared by every entry point:
+ *   - Key and payload buffers are DEVICE memory owned by the caller (for
+ *     example allocated by torch).  They are sorted in place; the library
+ *     never frees or reallocates them.  Pointers must be 4-byte aligned.
+ *   - Keys are 32-bit words: QMS_U32 compares them as unsigned integers;
+ *     QMS_F32 compares IEEE-754 binary32 values by the IEEE total order
+ *     (negative NaNs < -inf < ... < -0 < +0 < ... < +inf < positive NaNs).
+ *   - Payloads (qms_sort_pairs, qms_sort_batch with vals) are uint32 words in
+ *     a separate array (structure of arrays); every move of a key moves its
+ *     payload.  The sort is not stable: payload order among equal keys is
+ *     unspecified, as both the partition and the merge reorder equal keys.
+ *   - `stream` is a hipStream_t (0 = the null stream).  Work is enqueued on
+ *     that stream.  The single-array entry points read small partition
+ *     results back to the host once per partition round, so they return
+ *     only after the sort has completed on the stream.
+ *   - Extra device memory: a library-owned workspace per (device, stream)
+ *     of fixed size (tile counters and round state; no buffer proportional
+ *     to n), allocated on first use and kept until qms_release_workspaces().
+ *   - Return values are qms_status codes; no C++ exception crosses this
+ *     interface.  The message of the last failure on the calling thread is
+ *     available from qms_last_error().
+ */
+#ifndef QMS_H
+#define QMS_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { QMS_U32 = 0, QMS_F32 = 1 } qms_dtype;
+
+typedef enum {
+    QMS_OK = 0,
+    QMS_PENDING = 1,         /* server: request not finished yet          */
+    QMS_ERR_INVALID = -1,    /* bad argument (NULL, host pointer, range)  */
+    QMS_ERR_ALIGN = -2,      /* pointer not 4-byte aligned                */
+    QMS_ERR_NOMEM = -3,      /* workspace allocation failed               */
+    QMS_ERR_HIP = -4,        /* a HIP runtime call or kernel failed       */
+    QMS_ERR_BUDGET = -5,     /* server: request larger than the budget    */
+    QMS_ERR_UNSUPPORTED = -6 /* unknown dtype or option                   */
+} qms_status;
+
+/*
+ * qms_sort -- sort n keys in place (Fig. 2 sort(); Sec. "QuickXsort and
+ * QuickMergesort"; pivot rule of Theorem 1: median of the keys at lo,
+ * lo + (hi-lo)/2 and hi-1).
+ *   d_keys  device pointer to n 32-bit keys of type dt.
+ *   n       number of keys; 0 and 1 are no-ops returning QMS_OK.
+ *   dt      QMS_U32 or QMS_F32.
+ *   stream  HIP stream to run on.
+ * Errors: QMS_ERR_INVALID for NULL with n > 0 or a pointer that is not
+ * device memory; QMS_ERR_ALIGN; QMS_ERR_UNSUPPORTED for an unknown dt;
+ * QMS_ERR_NOMEM / QMS_ERR_HIP from the runtime.
+ */
+int qms_sort(void *d_keys, uint64_t n, int dt, hipStream_t stream);
+
+/*
+ * qms_sort_pairs -- as qms_sort, carrying a uint32 payload per key (the
+ * QuickXsort section's element moves apply to whole elements).
+ *   d_vals  device pointer to n uint32 payloads, permuted with the keys.
+ * Result: keys sorted; the multiset of (key, payload) pairs preserved.
+ */
+int qms_sort_pairs(void *d_keys, uint32_t *d_vals, uint64_t n, int dt,
+                   hipStream_t stream);
+
+/*
+ * qms_sort_batch -- sort num_segments independent arrays stored back to back
+ * (segment j is [offsets[j], offsets[j+1])), each exactly as qms_sort /
+ * qms_sort_pairs would, with all segments advancing together through the
+ * partition / base-case / merge phases (one set of launches per phase for
+ * the whole batch rather than per segment).
+ *   d_keys       device keys of all segments.
+ *   d_vals       device payloads, or NULL for keys only.
+ *   d_offsets    DEVICE array of num_segments + 1 uint64 offsets, non-
+ *                decreasing, offsets[0] = 0 (empty segments allowed).
+ *   h_offsets    optional HOST copy of the same offsets (NULL: the library
+ *                reads them from the device).
+ * Errors: as qms_sort; QMS_ERR_INVALID for decreasing offsets.
+ */
+int qms_sort_batch(void *d_keys, uint32_t *d_vals, const uint64_t *d_offsets,
+                   const uint64_t *h_offsets, uint32_t num_segments, int dt,
+                   hipStream_t stream);
+
+/* ---- request loop (serving) ---------------------------------------------
+ * A server owns a worker thread and a HIP stream on `device`.  Requests are
+ * device arrays lent to the server until qms_server_poll returns QMS_OK for
+ * their ticket.  Admission: the bytes of all lent, unfinished requests stay
+ * within hbm_budget_bytes; requests beyond it wait in FIFO order (none is
+ * dropped).  Pending requests are grouped by dtype into batches of at most
+ * max_batch requests and sorted with the batched path.
+ */
+typedef struct {
+    uint64_t hbm_budget_bytes; /* admission budget for lent key+payload bytes */
+    int device;                /* HIP device ordinal                          */
+    uint32_t max_batch;        /* max requests per batch (0: 4096)            */
+} qms_server_config;
+
+typedef struct qms_server qms_server;
+
+/* Create a server.  *out receives the handle. */
+int qms_server_create(const qms_server_config *cfg, qms_server **out);
+
+/*
+ * Submit one request: sort n keys of dtype dt at d_keys (device memory of
+ * the server's device), in place.  *ticket_out receives a ticket.  Returns
+ * QMS_ERR_BUDGET if n * 4 bytes alone exceed the budget (never admissible).
+ */
+int qms_server_submit(qms_server *srv, void *d_keys, uint64_t n, int dt,
+                      uint64_t *ticket_out);
+
+/*
+ * Poll a ticket: QMS_PENDING while queued or running; QMS_OK once the keys
+ * are sorted (the ticket is then retired and *latency_s_out, if not NULL,
+ * receives completion time minus submission time in seconds);
+ * QMS_ERR_INVALID for an unknown or retired ticket; QMS_ERR_HIP if the
+ * batch holding the request failed.
+ */
+int qms_server_poll(qms_server *srv, uint64_t ticket, double *latency_s_out);
+
+/* Statistics since creation: completed requests, completed keys, peak
+ * admitted bytes, and requests that had to wait for budget. */
+typedef struct {
+    uint64_t completed;
+    uint64_t completed_keys;
+    uint64_t peak_admitted_bytes;
+    uint64_t waited_for_budget;
+    uint64_t batches;
+} qms_server_stats;
+int qms_server_get_stats(qms_server *srv, qms_server_stats *out);
+
+/* Drain in-flight work, stop the worker and free the server. */
+int qms_server_destroy(qms_server *srv);
+
+/* ---- diagnostics ---------------------------------------------------------- */
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char *qms_last_error(void);
+
+/* Free the cached workspaces of all devices and streams. */
+int qms_release_workspaces(void);
+
+/*
+ * Round log of the last single-array sort on the calling thread: for each
+ * partition round, the range size s, the sizes of the sides (<, ==, >
+ * pivot) and the number of merge levels run on the mergesorted side.
+ * Writes up to max_rounds records of 5 uint64 each into out; returns the
+ * number of rounds of that sort (which may exceed max_rounds).
+ */
+uint64_t qms_last_schedule(uint64_t *out, uint64_t max_rounds);
+
+/* Tunables as used by the kernels: base-case tile, merge tile, partition
+ * tile (elements).  Read-only; for reports and tests. */
+void qms_get_tiles(uint32_t *base_tile, uint32_t *merge_tile,
+                   uint32_t *partition_tile);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QMS_H */

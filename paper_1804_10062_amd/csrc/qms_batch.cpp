@@ -1,0 +1,56 @@
+// qms_batch.cpp -- qms_sort_batch: many independent arrays in one call.
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "qms.h"
+#include "qms_host.hpp"
+
+using namespace qms;
+
+extern "C" int qms_sort_batch(void *d_keys, uint32_t *d_vals, const uint64_t *d_offsets,
+                              const uint64_t *h_offsets, uint32_t num_segments, int dt,
+                              hipStream_t stream) {
+    try {
+        if (dt != QMS_U32 && dt != QMS_F32) return set_error(QMS_ERR_UNSUPPORTED, "unknown dtype");
+        if (num_segments == 0) return QMS_OK;
+        if (d_keys == nullptr || d_offsets == nullptr)
+            return set_error(QMS_ERR_INVALID, "NULL keys or offsets");
+        int dev = 0, dev2 = 0;
+        int rc = check_device_ptr(d_keys, "keys", &dev);
+        if (rc != QMS_OK) return rc;
+        rc = check_device_ptr(d_offsets, "offsets", &dev2);
+        if (rc != QMS_OK) return rc;
+        if (d_vals) {
+            rc = check_device_ptr(d_vals, "vals", &dev2);
+            if (rc != QMS_OK) return rc;
+        }
+        DeviceScope scope(dev);
+        std::vector<uint64_t> off(num_segments + 1);
+        if (h_offsets) {
+            for (uint32_t j = 0; j <= num_segments; ++j) off[j] = h_offsets[j];
+        } else {
+            hipError_t e = hipMemcpyAsync(off.data(), d_offsets, off.size() * sizeof(uint64_t),
+                                          hipMemcpyDeviceToHost, stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(stream);
+            if (e != hipSuccess) return hip_error(e, "reading offsets");
+        }
+        if (off[0] != 0) return set_error(QMS_ERR_INVALID, "offsets[0] must be 0");
+        for (uint32_t j = 0; j < num_segments; ++j)
+            if (off[j + 1] < off[j]) return set_error(QMS_ERR_INVALID, "offsets decrease");
+        Workspace *ws = nullptr;
+        rc = get_workspace(dev, stream, &ws);
+        if (rc != QMS_OK) return rc;
+        uint32_t *keys = (uint32_t *)d_keys;
+        for (uint32_t j = 0; j < num_segments; ++j) {
+            const uint64_t n = off[j + 1] - off[j];
+            if (n <= 1) continue;
+            rc = sort_array(dt, d_vals != nullptr, keys + off[j], d_vals ? d_vals + off[j] : nullptr,
+                            n, *ws, stream, false);
+            if (rc != QMS_OK) return rc;
+        }
+        return QMS_OK;
+    } catch (...) {
+        return set_error(QMS_ERR_NOMEM, "host exception in qms_sort_batch");
+    }
+}

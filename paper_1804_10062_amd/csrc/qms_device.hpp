@@ -1,0 +1,127 @@
+// qms_device.hpp -- device-side building blocks shared by the QuickMergesort
+// kernels for gfx950 (CDNA4: 64-lane wavefronts, 160 KB LDS per CU).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace qms {
+
+// ---- launch geometry and tile sizes -----------------------------------------
+constexpr int kBlock = 256;            // threads per workgroup (4 waves)
+constexpr int kWave = 64;              // CDNA wavefront width
+constexpr int kWaves = kBlock / kWave;
+
+constexpr int kBaseTile = 4096;        // base-case tile (X of QuickMergeXsort)
+constexpr int kBasePerThread = kBaseTile / kBlock;     // 16
+constexpr int kMergeTile = 2048;       // outputs per workgroup in a merge level
+constexpr int kMergePerThread = kMergeTile / kBlock;   // 8
+constexpr int kPartSub = 4096;         // elements a workgroup classifies per step
+constexpr int kPartItems = kPartSub / kBlock;          // 16
+constexpr int kRankChunk = 2048;       // misplaced pairs exchanged per workgroup
+constexpr uint32_t kMaxTiles = 65536;  // fixed bound on partition tiles
+constexpr int kScanThreads = 1024;     // single-workgroup scan kernels
+
+static_assert(kBaseTile % kMergeTile == 0, "runs must tile into merge tiles");
+
+// ---- round state slots (uint64 words in the workspace) ----------------------
+enum MetaSlot : int {
+    M_PIVOT = 0,   // pivot key (order-mapped)
+    M_CLT = 1,     // # keys < pivot
+    M_CEQ = 2,     // # keys == pivot
+    M_XA = 3,      // misplaced pairs of pass A (< pivot vs the rest)
+    M_TB = 4,      // tile holding the </>= boundary
+    M_LTPART = 5,  // # keys < pivot in that tile, left of the boundary
+    M_EQPART = 6,  // # keys == pivot in that tile, left of the boundary
+    M_XB = 7,      // misplaced pairs of pass B (== pivot vs > pivot)
+    M_COUNT = 16
+};
+
+// ---- key order ----------------------------------------------------------------
+// Keys are compared as unsigned 32-bit integers after an order map applied in
+// registers on load (and undone on store).
+struct OrdU32 {
+    __device__ __forceinline__ static uint32_t ord(uint32_t x) { return x; }
+    __device__ __forceinline__ static uint32_t unord(uint32_t x) { return x; }
+};
+// IEEE-754 binary32 total order: negative values have all bits flipped,
+// non-negative values get the sign bit set; unsigned order of the result is
+// the total order (-NaN < -inf < ... < -0 < +0 < ... < +inf < +NaN).
+struct OrdF32 {
+    __device__ __forceinline__ static uint32_t ord(uint32_t u) {
+        return u ^ ((uint32_t)((int32_t)u >> 31) | 0x80000000u);
+    }
+    __device__ __forceinline__ static uint32_t unord(uint32_t k) {
+        return k ^ ((uint32_t)((int32_t)(~k) >> 31) | 0x80000000u);
+    }
+};
+
+// ---- wave and block primitives -------------------------------------------------
+__device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
+__device__ __forceinline__ int wave_id() { return (int)(threadIdx.x / kWave); }
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    return (1ull << lane_id()) - 1ull;
+}
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+    return v;
+}
+
+template <class T>
+__device__ __forceinline__ T wave_inclusive_scan(T v) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        T y = __shfl_up(v, d, kWave);
+        if (lane >= d) v += y;
+    }
+    return v;
+}
+
+// Exclusive scan over the whole block; `tmp` holds >= blockDim/64 + 1 words
+// of LDS.  Returns the prefix; *total gets the block sum.  Every thread of
+// the block must call it.
+template <class T>
+__device__ __forceinline__ T block_exclusive_scan(T v, T *tmp, T *total) {
+    const int lane = lane_id(), wave = wave_id();
+    const int nwaves = (int)(blockDim.x / kWave);
+    T inc = wave_inclusive_scan(v);
+    if (lane == kWave - 1) tmp[wave] = inc;
+    __syncthreads();
+    if (wave == 0) {
+        T w = lane < nwaves ? tmp[lane] : T(0);
+        T wi = wave_inclusive_scan(w);
+        if (lane < nwaves) tmp[lane] = wi - w;
+        if (lane == nwaves - 1) tmp[nwaves] = wi;
+    }
+    __syncthreads();
+    T res = tmp[wave] + inc - v;
+    *total = tmp[nwaves];
+    __syncthreads();
+    return res;
+}
+
+template <class T>
+__device__ __forceinline__ T block_sum(T v, T *tmp) {
+    T total;
+    (void)block_exclusive_scan(v, tmp, &total);
+    return total;
+}
+
+__device__ __forceinline__ uint32_t median3(uint32_t a, uint32_t b, uint32_t c) {
+    return max(min(a, b), min(max(a, b), c));
+}
+
+// Pivot of the range [lo, hi): median of the keys at lo, lo + s/2 and hi - 1.
+template <class O>
+__device__ __forceinline__ uint32_t pivot_of(const uint32_t *keys, uint64_t lo,
+                                             uint64_t hi) {
+    const uint64_t s = hi - lo;
+    return median3(O::ord(keys[lo]), O::ord(keys[lo + s / 2]),
+                   O::ord(keys[hi - 1]));
+}
+
+}  // namespace qms

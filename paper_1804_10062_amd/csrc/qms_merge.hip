@@ -1,0 +1,214 @@
+// qms_merge.hip -- one level of the swap-merge on gfx950.
+//
+// Fig. 2's merge takes two sorted runs and writes their merge into a target
+// area, moving the elements found in the target into the cells the runs
+// vacate (Sec. "QuickXsort and QuickMergesort": an element Mergesort would
+// move to extra space is swapped with the element occupying that cell).
+//
+// Here a level merges consecutive pairs of runs of width W of a source
+// region S into the destination region D of the same length (S and D are the
+// data side and the buffer side of the current partition round, in either
+// order).  The output of each pair is cut into tiles of kMergeTile elements;
+// the merge-path split (the diagonal search of Odeh et al.'s Merge Path) gives
+// every tile its own slice of each run, disjoint from every other tile's
+// slices.  A workgroup therefore reads its two run slices and its output
+// window of D, writes the merged keys into the window and the displaced
+// window contents into the run-slice cells it just read.  No workgroup
+// touches another's cells.  The splits are found by a separate kernel before
+// the level starts: a search inside the merge kernel would probe run cells
+// that neighbouring workgroups are already overwriting with buffer elements.
+// The split array (one word per tile) is part of the fixed-size workspace.
+// Ties go to the left run.
+#include "qms_device.hpp"
+#include "qms_internal.hpp"
+
+namespace qms {
+
+// Merge-path split of diagonal d: the number of elements of run A among the
+// first d outputs of the stable merge of A and B.  The whole wave searches
+// together: each step every lane probes one of 64 evenly spaced candidates
+// and a ballot narrows the interval 64-fold.
+template <class O>
+__device__ __forceinline__ uint64_t merge_path_wave(const uint32_t *A, uint64_t lenA,
+                                                    const uint32_t *B, uint64_t lenB,
+                                                    uint64_t d) {
+    uint64_t lo = d > lenB ? d - lenB : 0;
+    uint64_t hi = d < lenA ? d : lenA;
+    const int lane = lane_id();
+    while (hi > lo) {
+        const uint64_t step = (hi - lo + kWave - 1) / kWave;
+        const uint64_t i = lo + (uint64_t)lane * step;
+        bool pred = false;
+        if (i < hi) pred = O::ord(A[i]) <= O::ord(B[d - 1 - i]);
+        const int c = __popcll(__ballot(pred));
+        const uint64_t nlo = c > 0 ? lo + (uint64_t)(c - 1) * step + 1 : lo;
+        const uint64_t cand = lo + (uint64_t)c * step;
+        hi = cand < hi ? cand : hi;
+        lo = nlo;
+    }
+    return lo;
+}
+
+// Geometry of merge tile `tile` of a level: run pair base, lengths, diagonals.
+struct MergeTileGeom {
+    uint64_t pb, lenA, lenB, d0, d1;
+};
+__device__ __forceinline__ MergeTileGeom merge_geom(uint64_t m, uint64_t W, uint64_t tile) {
+    MergeTileGeom g;
+    const uint64_t start = tile * kMergeTile;
+    g.pb = (start / (2 * W)) * (2 * W);
+    g.d0 = start - g.pb;
+    const uint64_t rest = m - g.pb;
+    g.lenA = rest < W ? rest : W;
+    g.lenB = rest > W ? (rest - W < W ? rest - W : W) : 0;
+    const uint64_t tot = g.lenA + g.lenB;
+    g.d1 = g.d0 + kMergeTile < tot ? g.d0 + kMergeTile : tot;
+    return g;
+}
+
+// One wave per tile: the merge-path split at the tile's first output.
+template <class O>
+__global__ __launch_bounds__(kBlock) void k_merge_split(const uint32_t *keys, uint64_t src,
+                                                        uint64_t m, uint64_t W,
+                                                        uint64_t ntiles, uint32_t *splits) {
+    const uint64_t tile = (uint64_t)blockIdx.x * kWaves + wave_id();
+    if (tile >= ntiles) return;
+    const MergeTileGeom g = merge_geom(m, W, tile);
+    const uint32_t *A = keys + src + g.pb;
+    const uint64_t i = merge_path_wave<O>(A, g.lenA, A + W, g.lenB, g.d0);
+    if (lane_id() == 0) splits[tile] = (uint32_t)i;
+}
+
+template <class O, bool PAIRS>
+__device__ __forceinline__ void merge_block(uint32_t *S, uint32_t *SV, uint32_t *D,
+                                            uint32_t *DV, uint64_t m, uint64_t W,
+                                            uint64_t tile, const uint32_t *splits) {
+    __shared__ uint32_t sk[kMergeTile];
+    __shared__ uint32_t sv[PAIRS ? kMergeTile : 1];
+    const uint32_t tid = threadIdx.x;
+
+    const MergeTileGeom g = merge_geom(m, W, tile);
+    const uint64_t pb = g.pb, d0 = g.d0, d1 = g.d1;
+    const uint32_t cnt = (uint32_t)(d1 - d0);
+    // splits as found by k_merge_split, clamped to the ranges a merge path
+    // can take (a no-op for consistent splits; keeps every access in the runs)
+    uint64_t i0 = splits[tile];
+    uint64_t i1 = d1 < g.lenA + g.lenB ? (uint64_t)splits[tile + 1] : g.lenA;
+    i0 = min(max(i0, d0 > g.lenB ? d0 - g.lenB : 0), min(d0, g.lenA));
+    i1 = min(max(i1, max(i0, d1 > g.lenB ? d1 - g.lenB : 0)), min(min(d1, g.lenA), i0 + cnt));
+
+    // the destination window's current contents (buffer elements)
+    uint32_t oldk[kMergePerThread];
+    uint32_t oldv[PAIRS ? kMergePerThread : 1];
+#pragma unroll
+    for (int q = 0; q < kMergePerThread; ++q) {
+        const uint32_t e = q * kBlock + tid;
+        if (e < cnt) {
+            oldk[q] = D[pb + d0 + e];
+            if constexpr (PAIRS) oldv[q] = DV[pb + d0 + e];
+        }
+    }
+    const uint64_t j0 = d0 - i0, j1 = d1 - i1;
+    const uint32_t na = (uint32_t)(i1 - i0);
+    const uint32_t nb = (uint32_t)(j1 - j0);
+#pragma unroll
+    for (int q = 0; q < kMergePerThread; ++q) {
+        const uint32_t e = q * kBlock + tid;
+        if (e < cnt) {
+            const uint64_t pos = e < na ? pb + i0 + e : pb + W + j0 + (e - na);
+            sk[e] = O::ord(S[pos]);
+            if constexpr (PAIRS) sv[e] = SV[pos];
+        }
+    }
+    __syncthreads();
+
+    // each thread merges kMergePerThread consecutive outputs of the tile
+    uint32_t ok[kMergePerThread];
+    uint32_t ov[PAIRS ? kMergePerThread : 1];
+    const uint32_t diag = tid * kMergePerThread;
+    if (diag < cnt) {
+        uint32_t lo = diag > nb ? diag - nb : 0;
+        uint32_t hi = diag < na ? diag : na;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (sk[mid] <= sk[na + diag - 1 - mid]) lo = mid + 1;
+            else hi = mid;
+        }
+        uint32_t ia = lo, ib = diag - lo;
+        uint32_t ka = ia < na ? sk[ia] : 0u;
+        uint32_t kb = ib < nb ? sk[na + ib] : 0u;
+#pragma unroll
+        for (int q = 0; q < kMergePerThread; ++q) {
+            if (diag + q < cnt) {
+                const bool takeA = ib >= nb || (ia < na && ka <= kb);
+                if (takeA) {
+                    ok[q] = ka;
+                    if constexpr (PAIRS) ov[q] = sv[ia];
+                    ++ia;
+                    ka = ia < na ? sk[ia] : 0u;
+                } else {
+                    ok[q] = kb;
+                    if constexpr (PAIRS) ov[q] = sv[na + ib];
+                    ++ib;
+                    kb = ib < nb ? sk[na + ib] : 0u;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (diag < cnt) {
+#pragma unroll
+        for (int q = 0; q < kMergePerThread; ++q) {
+            if (diag + q < cnt) {
+                sk[diag + q] = ok[q];
+                if constexpr (PAIRS) sv[diag + q] = ov[q];
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kMergePerThread; ++q) {
+        const uint32_t e = q * kBlock + tid;
+        if (e < cnt) {
+            D[pb + d0 + e] = O::unord(sk[e]);
+            if constexpr (PAIRS) DV[pb + d0 + e] = sv[e];
+            const uint64_t pos = e < na ? pb + i0 + e : pb + W + j0 + (e - na);
+            S[pos] = oldk[q];
+            if constexpr (PAIRS) SV[pos] = oldv[q];
+        }
+    }
+}
+
+template <class O, bool PAIRS>
+__global__ __launch_bounds__(kBlock) void k_merge(uint32_t *keys, uint32_t *vals, uint64_t src,
+                                                  uint64_t dst, uint64_t m, uint64_t W,
+                                                  const uint32_t *splits) {
+    if ((uint64_t)blockIdx.x * kMergeTile >= m) return;
+    merge_block<O, PAIRS>(keys + src, PAIRS ? vals + src : nullptr, keys + dst,
+                          PAIRS ? vals + dst : nullptr, m, W, blockIdx.x, splits);
+}
+
+template <class O, bool PAIRS>
+static hipError_t merge_t(uint32_t *keys, uint32_t *vals, uint64_t src, uint64_t dst,
+                          uint64_t m, uint64_t W, uint32_t *splits, hipStream_t st) {
+    if (m == 0) return hipSuccess;
+    const uint64_t nt = (m + kMergeTile - 1) / kMergeTile;
+    hipLaunchKernelGGL((k_merge_split<O>), dim3((uint32_t)((nt + kWaves - 1) / kWaves)),
+                       dim3(kBlock), 0, st, keys, src, m, W, nt, splits);
+    hipLaunchKernelGGL((k_merge<O, PAIRS>), dim3((uint32_t)nt), dim3(kBlock), 0, st, keys, vals,
+                       src, dst, m, W, (const uint32_t *)splits);
+    return hipGetLastError();
+}
+
+hipError_t launch_merge_level(int dt, bool pairs, uint32_t *keys, uint32_t *vals, uint64_t src,
+                              uint64_t dst, uint64_t m, uint64_t W, uint32_t *splits,
+                              hipStream_t st) {
+    if (m > (uint64_t)kMaxSplits * kMergeTile) return hipErrorInvalidValue;
+    if (dt == 1)
+        return pairs ? merge_t<OrdF32, true>(keys, vals, src, dst, m, W, splits, st)
+                     : merge_t<OrdF32, false>(keys, vals, src, dst, m, W, splits, st);
+    return pairs ? merge_t<OrdU32, true>(keys, vals, src, dst, m, W, splits, st)
+                 : merge_t<OrdU32, false>(keys, vals, src, dst, m, W, splits, st);
+}
+
+}  // namespace qms

@@ -1,0 +1,459 @@
+// qms_partition.hip -- in-place three-way partition around a median-of-3
+// pivot on gfx950.
+//
+// The paper leaves the partition routine open (Sec. "QuickMergeXsort": "the
+// partitioning algorithm [has] to be added"); its pivot is the median of a
+// sample of three (Theorem 1), and Sec. "Worst-Case Efficient QuickMergeSort"
+// notes that with duplicate keys the elements equal to the pivot should go
+// to the middle and take part in neither Mergesort nor the recursion.  This
+// file implements exactly that partition of a range [lo, hi):
+//
+//     [lo, B1) < p      [B1, B2) == p      [B2, hi) > p
+//
+// in place, in two passes of the same rank-matched exchange:
+//   pass A  splits "< p" from ">= p" at B1 = lo + #(< p);
+//   pass B  splits "== p" from "> p" inside [B1, hi) at B2 = B1 + #(== p).
+// A pass pairs the k-th misplaced element of the left region with the k-th
+// misplaced element of the right region and exchanges them; the pairing is a
+// perfect matching, so every element moves at most once per pass.
+//
+// Kernels, per pass:
+//   count   one workgroup per tile: #(< p) and #(== p) of the tile;
+//   scan    one workgroup: totals, boundary, per-tile misplaced counts and
+//           their exclusive prefix sums (ranks of each tile's first misplaced
+//           element on either side);
+//   split   one wave per chunk boundary and side: the exact position of the
+//           misplaced element of rank j * kRankChunk;
+//   swap    one workgroup per chunk: reads exactly the position ranges of its
+//           ranks on both sides (coalesced, wave-striped), compacts the
+//           misplaced elements with ballot + prefix counts into LDS, and
+//           writes them exchanged.
+// Chunks own disjoint position ranges, so no workgroup reads a cell another
+// one writes.  Pass B's per-tile counts are derived from pass A's without a
+// second counting sweep: equal keys in the right region never move in pass A,
+// and pass A counts (atomically, per tile) the equal keys it moves in.
+//
+// Workspace: O(kMaxTiles) counters; positions are 32-bit offsets from lo.
+#include "qms_device.hpp"
+#include "qms_internal.hpp"
+
+namespace qms {
+
+// ---- count -------------------------------------------------------------------
+template <class O>
+__global__ __launch_bounds__(kBlock) void k_part_count(const uint32_t *keys, uint64_t lo,
+                                                       uint64_t hi, uint32_t TP,
+                                                       uint32_t *cnt_lt, uint32_t *cnt_eq,
+                                                       uint64_t *meta) {
+    __shared__ uint32_t tmp[kWaves + 1];
+    const uint32_t p = pivot_of<O>(keys, lo, hi);
+    const uint64_t t = blockIdx.x;
+    const uint64_t ts = lo + t * TP;
+    const uint64_t te = ts + TP < hi ? ts + TP : hi;
+    uint32_t lt = 0, eq = 0;
+    for (uint64_t b = ts; b < te; b += kPartSub) {
+#pragma unroll
+        for (int q = 0; q < kPartItems; ++q) {
+            const uint64_t pos = b + (uint64_t)q * kBlock + threadIdx.x;
+            if (pos < te) {
+                const uint32_t k = O::ord(keys[pos]);
+                lt += k < p;
+                eq += k == p;
+            }
+        }
+    }
+    lt = block_sum(lt, tmp);
+    eq = block_sum(eq, tmp);
+    if (threadIdx.x == 0) {
+        cnt_lt[t] = lt;
+        cnt_eq[t] = eq;
+        if (t == 0) meta[M_PIVOT] = p;
+    }
+}
+
+// count keys with ord(k) < p and == p in [a, b) with the whole block
+template <class O>
+__device__ __forceinline__ void block_count_range(const uint32_t *keys, uint64_t a, uint64_t b,
+                                                  uint32_t p, uint32_t *lt_out,
+                                                  uint32_t *eq_out, uint32_t *tmp) {
+    uint32_t lt = 0, eq = 0;
+    for (uint64_t pos = a + threadIdx.x; pos < b; pos += blockDim.x) {
+        const uint32_t k = O::ord(keys[pos]);
+        lt += k < p;
+        eq += k == p;
+    }
+    *lt_out = block_sum(lt, tmp);
+    *eq_out = block_sum(eq, tmp);
+}
+
+// Exclusive prefix sums of the per-tile misplaced counts of both sides, the
+// tiles split among the block's threads in contiguous runs.  mis(t, &l, &r)
+// gives tile t's counts.  Returns the total of the left side.
+template <class F>
+__device__ __forceinline__ uint32_t scan_misplaced(uint32_t nt, F mis, uint32_t *preL,
+                                                   uint32_t *preR, uint32_t *tmp) {
+    const uint32_t per = (nt + blockDim.x - 1) / blockDim.x;
+    const uint32_t t0 = threadIdx.x * per;
+    const uint32_t t1 = t0 + per < nt ? t0 + per : nt;
+    uint32_t sl = 0, sr = 0;
+    for (uint32_t t = t0; t < t1; ++t) {
+        uint32_t l, r;
+        mis(t, &l, &r);
+        sl += l;
+        sr += r;
+    }
+    uint32_t totL, totR;
+    uint32_t offL = block_exclusive_scan(sl, tmp, &totL);
+    uint32_t offR = block_exclusive_scan(sr, tmp, &totR);
+    for (uint32_t t = t0; t < t1; ++t) {
+        uint32_t l, r;
+        mis(t, &l, &r);
+        preL[t] = offL;
+        preR[t] = offR;
+        offL += l;
+        offR += r;
+    }
+    if (threadIdx.x == 0) {
+        preL[nt] = totL;
+        preR[nt] = totR;
+    }
+    return totL;
+}
+
+// ---- scan of pass A ----------------------------------------------------------
+template <class O>
+__global__ __launch_bounds__(kScanThreads) void k_part_scan_a(
+    const uint32_t *keys, uint64_t lo, uint64_t hi, uint32_t TP, uint32_t nt,
+    const uint32_t *cnt_lt, const uint32_t *cnt_eq, uint32_t *preL, uint32_t *preR,
+    uint32_t *eqmv, uint32_t *spL, uint32_t *spR, uint64_t *meta) {
+    __shared__ uint32_t tmp[kScanThreads / kWave + 1];
+    __shared__ uint64_t tmp64[kScanThreads / kWave + 1];
+    const uint32_t p = pivot_of<O>(keys, lo, hi);
+    const uint64_t s = hi - lo;
+    uint64_t slt = 0, seq = 0;
+    for (uint32_t t = threadIdx.x; t < nt; t += blockDim.x) {
+        slt += cnt_lt[t];
+        seq += cnt_eq[t];
+        eqmv[t] = 0;
+    }
+    const uint64_t c_lt = block_sum(slt, tmp64);
+    const uint64_t c_eq = block_sum(seq, tmp64);
+    const uint64_t tb = c_lt / TP;  // tile holding B1 (tb < nt since c_lt < s)
+    uint32_t lt_part = 0, eq_part = 0;
+    if (c_lt % TP != 0)
+        block_count_range<O>(keys, lo + tb * TP, lo + c_lt, p, &lt_part, &eq_part, tmp);
+    auto mis = [&](uint32_t t, uint32_t *l, uint32_t *r) {
+        const uint64_t ts = (uint64_t)t * TP;
+        const uint32_t sz = (uint32_t)((ts + TP < s ? ts + TP : s) - ts);
+        if (t < tb) {
+            *l = sz - cnt_lt[t];
+            *r = 0;
+        } else if (t == tb) {
+            *l = (uint32_t)(c_lt - ts) - lt_part;
+            *r = cnt_lt[t] - lt_part;
+        } else {
+            *l = 0;
+            *r = cnt_lt[t];
+        }
+    };
+    const uint32_t X = scan_misplaced(nt, mis, preL, preR, tmp);
+    if (threadIdx.x == 0) {
+        const uint32_t nch = (X + kRankChunk - 1) / kRankChunk;
+        meta[M_PIVOT] = p;
+        meta[M_CLT] = c_lt;
+        meta[M_CEQ] = c_eq;
+        meta[M_XA] = X;
+        meta[M_TB] = tb;
+        meta[M_LTPART] = lt_part;
+        meta[M_EQPART] = eq_part;
+        meta[M_XB] = 0;
+        spL[0] = 0;
+        spL[nch] = (uint32_t)c_lt;
+        spR[0] = (uint32_t)c_lt;
+        spR[nch] = (uint32_t)s;
+    }
+}
+
+// ---- scan of pass B ----------------------------------------------------------
+// After pass A, [B1, hi) holds only keys >= p.  The keys == p of a tile's part
+// right of B1 are the ones it held before (they did not move) plus the ones
+// pass A moved in (eqmv).
+template <class O>
+__global__ __launch_bounds__(kScanThreads) void k_part_scan_b(
+    const uint32_t *keys, uint64_t lo, uint64_t hi, uint32_t TP, uint32_t nt,
+    const uint32_t *cnt_eq, const uint32_t *eqmv, uint32_t *preL, uint32_t *preR,
+    uint32_t *spL, uint32_t *spR, uint64_t *meta) {
+    __shared__ uint32_t tmp[kScanThreads / kWave + 1];
+    const uint32_t p = (uint32_t)meta[M_PIVOT];
+    const uint64_t s = hi - lo;
+    const uint64_t b1 = meta[M_CLT];
+    const uint64_t b2 = b1 + meta[M_CEQ];
+    const uint64_t tb = meta[M_TB];
+    const uint32_t eq_part = (uint32_t)meta[M_EQPART];
+    const uint64_t tb2 = b2 / TP;
+    uint32_t eq_part2 = 0, dummy = 0;
+    if (b2 % TP != 0 && tb2 < nt) {
+        const uint64_t a = tb2 * TP > b1 ? tb2 * TP : b1;
+        block_count_range<O>(keys, lo + a, lo + b2, p, &dummy, &eq_part2, tmp);
+    }
+    auto mis = [&](uint32_t t, uint32_t *l, uint32_t *r) {
+        if (t < tb) {
+            *l = 0;
+            *r = 0;
+            return;
+        }
+        const uint64_t ts = (uint64_t)t * TP;
+        const uint64_t te = ts + TP < s ? ts + TP : s;
+        const uint64_t a0 = ts > b1 ? ts : b1;
+        const uint32_t le = (t == tb ? cnt_eq[t] - eq_part : cnt_eq[t]) + eqmv[t];
+        const uint64_t aend = te < b2 ? te : b2;
+        const uint32_t szA = aend > a0 ? (uint32_t)(aend - a0) : 0;
+        const bool hasB = te > (ts > b2 ? ts : b2);
+        const uint32_t leA = !hasB ? le : (szA == 0 ? 0 : eq_part2);
+        *l = szA - leA;
+        *r = le - leA;
+    };
+    const uint32_t X = scan_misplaced(nt, mis, preL, preR, tmp);
+    if (threadIdx.x == 0) {
+        const uint32_t nch = (X + kRankChunk - 1) / kRankChunk;
+        meta[M_XB] = X;
+        spL[0] = (uint32_t)b1;
+        spL[nch] = (uint32_t)b2;
+        spR[0] = (uint32_t)b2;
+        spR[nch] = (uint32_t)s;
+    }
+}
+
+// Left region and right region of a pass, as offsets from lo, and the class
+// test: an element belongs left if ord(k) < p (pass A) or ord(k) <= p (B).
+struct PassGeom {
+    uint64_t l0, l1, r0, r1;
+};
+template <int PASS>
+__device__ __forceinline__ PassGeom pass_geom(const uint64_t *meta, uint64_t s) {
+    const uint64_t b1 = meta[M_CLT];
+    PassGeom g;
+    if (PASS == 0) {
+        g.l0 = 0;
+        g.l1 = b1;
+        g.r0 = b1;
+        g.r1 = s;
+    } else {
+        const uint64_t b2 = b1 + meta[M_CEQ];
+        g.l0 = b1;
+        g.l1 = b2;
+        g.r0 = b2;
+        g.r1 = s;
+    }
+    return g;
+}
+template <int PASS>
+__device__ __forceinline__ bool belongs_left(uint32_t k, uint32_t p) {
+    return PASS == 0 ? k < p : k <= p;
+}
+
+// ---- split: position of the first misplaced element of every chunk ----------
+template <class O, int PASS>
+__global__ __launch_bounds__(kBlock) void k_part_split(const uint32_t *keys, uint64_t lo,
+                                                       uint64_t hi, uint32_t TP, uint32_t nt,
+                                                       const uint32_t *preL,
+                                                       const uint32_t *preR, uint32_t *spL,
+                                                       uint32_t *spR, const uint64_t *meta) {
+    const uint64_t w = (uint64_t)blockIdx.x * kWaves + wave_id();
+    const uint32_t X = (uint32_t)meta[PASS == 0 ? M_XA : M_XB];
+    const uint32_t nch = (X + kRankChunk - 1) / kRankChunk;
+    const uint64_t j = 1 + w / 2;
+    const int side = (int)(w & 1);
+    if (j >= nch) return;
+    const uint32_t p = (uint32_t)meta[M_PIVOT];
+    const uint64_t s = hi - lo;
+    const PassGeom g = pass_geom<PASS>(meta, s);
+    const uint32_t *pre = side ? preR : preL;
+    const uint32_t r = (uint32_t)(j * kRankChunk);
+    // largest t with pre[t] <= r (pre[0] = 0 <= r < pre[nt] = X)
+    uint32_t a = 0, b = nt;
+    while (b - a > 1) {
+        const uint32_t mid = (a + b) >> 1;
+        if (pre[mid] <= r) a = mid;
+        else b = mid;
+    }
+    const uint32_t t = a;
+    uint32_t k = r - pre[t];
+    const uint64_t ts = (uint64_t)t * TP;
+    const uint64_t te = ts + TP < s ? ts + TP : s;
+    const uint64_t reg0 = side ? g.r0 : g.l0, reg1 = side ? g.r1 : g.l1;
+    const uint64_t x0 = ts > reg0 ? ts : reg0;
+    const uint64_t x1 = te < reg1 ? te : reg1;
+    const int lane = lane_id();
+    for (uint64_t base = x0; base < x1; base += kWave) {
+        const uint64_t pos = base + lane;
+        bool f = false;
+        if (pos < x1) {
+            const bool bl = belongs_left<PASS>(O::ord(keys[lo + pos]), p);
+            f = side ? bl : !bl;
+        }
+        const uint64_t mask = __ballot(f);
+        const uint32_t c = (uint32_t)__popcll(mask);
+        if (k < c) {
+            if (f && (uint32_t)__popcll(mask & lanemask_lt()) == k)
+                (side ? spR : spL)[j] = (uint32_t)pos;
+            return;
+        }
+        k -= c;
+    }
+}
+
+// ---- swap ------------------------------------------------------------------------
+// Compact the misplaced elements of positions [a, b) (offsets from lo) into
+// the LDS slots 0.. in position order.
+template <class O, bool PAIRS, int PASS>
+__device__ __forceinline__ uint32_t collect_misplaced(const uint32_t *keys, const uint32_t *vals,
+                                                      uint64_t lo, uint64_t a, uint64_t b,
+                                                      uint32_t p, bool right, uint32_t *sk,
+                                                      uint32_t *sv, uint32_t *sp,
+                                                      uint32_t *wtot) {
+    const int lane = lane_id(), wave = wave_id();
+    uint32_t running = 0;
+    for (uint64_t base = a; base < b; base += kPartSub) {
+        uint32_t kk[kPartItems];
+        uint64_t m[kPartItems];
+        uint32_t wcount = 0;
+#pragma unroll
+        for (int q = 0; q < kPartItems; ++q) {
+            const uint64_t pos = base + (uint64_t)wave * (kPartItems * kWave) +
+                                 (uint64_t)q * kWave + lane;
+            bool f = false;
+            if (pos < b) {
+                kk[q] = keys[lo + pos];
+                const bool bl = belongs_left<PASS>(O::ord(kk[q]), p);
+                f = right ? bl : !bl;
+            }
+            m[q] = __ballot(f);
+            wcount += (uint32_t)__popcll(m[q]);
+        }
+        if (lane == 0) wtot[wave] = wcount;
+        __syncthreads();
+        uint32_t woff = running, total = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+            if (w < wave) woff += wtot[w];
+            total += wtot[w];
+        }
+#pragma unroll
+        for (int q = 0; q < kPartItems; ++q) {
+            if ((m[q] >> lane) & 1ull) {
+                const uint32_t slot = woff + (uint32_t)__popcll(m[q] & lanemask_lt());
+                if (slot >= (uint32_t)kRankChunk) continue;  // never with consistent counts
+                const uint64_t pos = base + (uint64_t)wave * (kPartItems * kWave) +
+                                     (uint64_t)q * kWave + lane;
+                sk[slot] = kk[q];
+                sp[slot] = (uint32_t)pos;
+                if constexpr (PAIRS) sv[slot] = vals[lo + pos];
+            }
+            woff += (uint32_t)__popcll(m[q]);
+        }
+        running += total;
+        __syncthreads();
+    }
+    return running;
+}
+
+template <class O, bool PAIRS, int PASS>
+__global__ __launch_bounds__(kBlock) void k_part_swap(uint32_t *keys, uint32_t *vals,
+                                                      uint64_t lo, uint64_t hi, uint32_t TP,
+                                                      const uint32_t *spL,
+                                                      const uint32_t *spR, uint32_t *eqmv,
+                                                      const uint64_t *meta) {
+    __shared__ uint32_t kL[kRankChunk], kR[kRankChunk], pL[kRankChunk], pR[kRankChunk];
+    __shared__ uint32_t vL[PAIRS ? kRankChunk : 1], vR[PAIRS ? kRankChunk : 1];
+    __shared__ uint32_t wtot[kWaves];
+    const uint32_t X = (uint32_t)meta[PASS == 0 ? M_XA : M_XB];
+    const uint32_t nch = (X + kRankChunk - 1) / kRankChunk;
+    const uint32_t j = blockIdx.x;
+    if (j >= nch) return;
+    const uint32_t p = (uint32_t)meta[M_PIVOT];
+    const uint32_t r0 = j * kRankChunk;
+    uint32_t cnt = X - r0 < (uint32_t)kRankChunk ? X - r0 : (uint32_t)kRankChunk;
+    // position ranges of this chunk, clamped to the pass's regions
+    const PassGeom g = pass_geom<PASS>(meta, hi - lo);
+    const uint64_t la = spL[j] > g.l0 ? spL[j] : g.l0, lb = spL[j + 1] < g.l1 ? spL[j + 1] : g.l1;
+    const uint64_t ra = spR[j] > g.r0 ? spR[j] : g.r0, rb = spR[j + 1] < g.r1 ? spR[j + 1] : g.r1;
+    const uint32_t nl = collect_misplaced<O, PAIRS, PASS>(keys, vals, lo, la, lb, p, false, kL,
+                                                          vL, pL, wtot);
+    const uint32_t nr = collect_misplaced<O, PAIRS, PASS>(keys, vals, lo, ra, rb, p, true, kR,
+                                                          vR, pR, wtot);
+    // equal by construction; the minimum keeps every write inside the slots filled
+    cnt = min(cnt, min(nl, nr));
+    for (uint32_t k = threadIdx.x; k < cnt; k += kBlock) {
+        const uint32_t a = kL[k], b = kR[k];
+        keys[lo + pL[k]] = b;
+        keys[lo + pR[k]] = a;
+        if constexpr (PAIRS) {
+            vals[lo + pL[k]] = vR[k];
+            vals[lo + pR[k]] = vL[k];
+        }
+        if (PASS == 0 && O::ord(a) == p) atomicAdd(&eqmv[pR[k] / TP], 1u);
+    }
+}
+
+// ---- host side ---------------------------------------------------------------------
+template <class O, bool PAIRS>
+static hipError_t partition_t(uint32_t *keys, uint32_t *vals, uint64_t lo, uint64_t hi,
+                              const Workspace &ws, PartitionResult *res, hipStream_t st) {
+    const uint64_t s = hi - lo;
+    uint32_t TP = kPartSub;
+    while ((s + TP - 1) / TP > kMaxTiles) TP *= 2;
+    const uint32_t nt = (uint32_t)((s + TP - 1) / TP);
+    hipLaunchKernelGGL((k_part_count<O>), dim3(nt), dim3(kBlock), 0, st, keys, lo, hi, TP,
+                       ws.cnt_lt, ws.cnt_eq, ws.meta);
+    hipLaunchKernelGGL((k_part_scan_a<O>), dim3(1), dim3(kScanThreads), 0, st, keys, lo, hi, TP,
+                       nt, ws.cnt_lt, ws.cnt_eq, ws.preL, ws.preR, ws.eqmv, ws.spL, ws.spR,
+                       ws.meta);
+    hipError_t e = hipMemcpyAsync(ws.h_meta, ws.meta, sizeof(uint64_t) * M_COUNT,
+                                  hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return e;
+    const uint64_t c_lt = ws.h_meta[M_CLT], c_eq = ws.h_meta[M_CEQ];
+    const uint64_t XA = ws.h_meta[M_XA];
+    if (XA > 0) {
+        const uint64_t nch = (XA + kRankChunk - 1) / kRankChunk;
+        if (nch > 1)
+            hipLaunchKernelGGL((k_part_split<O, 0>), dim3((uint32_t)(((nch - 1) * 2 + kWaves - 1) / kWaves)),
+                               dim3(kBlock), 0, st, keys, lo, hi, TP, nt, ws.preL, ws.preR,
+                               ws.spL, ws.spR, ws.meta);
+        hipLaunchKernelGGL((k_part_swap<O, PAIRS, 0>), dim3((uint32_t)nch), dim3(kBlock), 0, st,
+                           keys, vals, lo, hi, TP, ws.spL, ws.spR, ws.eqmv, ws.meta);
+    }
+    const uint64_t gt = s - c_lt - c_eq;
+    const uint64_t xb_max = c_eq < gt ? c_eq : gt;
+    if (xb_max > 0) {
+        hipLaunchKernelGGL((k_part_scan_b<O>), dim3(1), dim3(kScanThreads), 0, st, keys, lo, hi,
+                           TP, nt, ws.cnt_eq, ws.eqmv, ws.preL, ws.preR, ws.spL, ws.spR,
+                           ws.meta);
+        const uint64_t nch = (xb_max + kRankChunk - 1) / kRankChunk;
+        if (nch > 1)
+            hipLaunchKernelGGL((k_part_split<O, 1>), dim3((uint32_t)(((nch - 1) * 2 + kWaves - 1) / kWaves)),
+                               dim3(kBlock), 0, st, keys, lo, hi, TP, nt, ws.preL, ws.preR,
+                               ws.spL, ws.spR, ws.meta);
+        hipLaunchKernelGGL((k_part_swap<O, PAIRS, 1>), dim3((uint32_t)nch), dim3(kBlock), 0, st,
+                           keys, vals, lo, hi, TP, ws.spL, ws.spR, ws.eqmv, ws.meta);
+    }
+    res->pivot = ws.h_meta[M_PIVOT];
+    res->c_lt = c_lt;
+    res->c_eq = c_eq;
+    res->x_a = XA;
+    return hipGetLastError();
+}
+
+hipError_t run_partition(int dt, bool pairs, uint32_t *keys, uint32_t *vals, uint64_t lo,
+                         uint64_t hi, const Workspace &ws, PartitionResult *res,
+                         hipStream_t st) {
+    if (dt == 1)
+        return pairs ? partition_t<OrdF32, true>(keys, vals, lo, hi, ws, res, st)
+                     : partition_t<OrdF32, false>(keys, vals, lo, hi, ws, res, st);
+    return pairs ? partition_t<OrdU32, true>(keys, vals, lo, hi, ws, res, st)
+                 : partition_t<OrdU32, false>(keys, vals, lo, hi, ws, res, st);
+}
+
+}  // namespace qms
