@@ -1,0 +1,220 @@
+"""Benchmark: QuickMergesort of one array of 2^28 uint32 keys on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+A step is one complete in-place sort (partition rounds, base case, swap-merge
+levels) of a fresh, device-resident copy of the 2^28-key workload: K + W
+copies are uploaded before the timed region, so the timed region holds
+exactly K sorts and nothing else.  The headline is uniform keys (seed 2);
+nearly-sorted (1% random transpositions, seed 3) and reverse-sorted inputs
+are timed the same way and reported beside it.
+
+One JSON line goes to stdout with, besides the contract fields:
+  roofline      for the dominant kernel (the swap-merge level, k_merge):
+                algorithmic bytes per launch (16 B per element of the merged
+                side) over its mean launch duration, timed with HIP events on
+                the sorting stream in a second pass of K sorts right after the
+                timed region (events around ~500 launches per sort add a few
+                percent, so the headline region runs without them); `traffic` is the
+                HBM traffic per launch measured by rocprofv3 counters
+                (profiles/k_merge_traffic.json) while the kernel source is
+                unchanged since that measurement, else null;
+  cpu_baseline  the CPU oracle (single thread) on a bounded sample of the
+                same workload (the first 2^26 keys), in Gkeys/s;
+  kernels       per-kernel-class launches, time and achieved GB/s;
+  distributions Gkeys/s of the three inputs.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+N_KEYS = 1 << 28
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_merge_traffic.json")
+MERGE_SRC = os.path.join(ROOT, "paper_1804_10062_amd", "csrc", "qms_merge.hip")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--dist-steps", type=int, default=3,
+                    help="timed sorts for the nearly-sorted and reverse inputs")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-log2", type=int, default=26)
+    ap.add_argument("--only-uniform", action="store_true")
+    return ap.parse_args()
+
+
+def merge_source_hash() -> str:
+    return hashlib.sha256(open(MERGE_SRC, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per k_merge launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source."""
+    try:
+        d = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if d.get("source_sha256_16") != merge_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def time_sorts(copies, qms, torch, profile: bool):
+    """Sort every tensor in `copies` (one step each); returns (seconds, profile)."""
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    if profile:
+        qms.qms_profile_begin()
+    t0 = time.perf_counter()
+    for t in copies:
+        qms.qms_sort(t, stream=stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = qms.qms_profile_end() if profile else None
+    return t1 - t0, prof
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the sort of one array is not sharded across GPUs here)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_1804_10062_amd import inputs, qms
+
+    qms.load_library()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    K, W = args.steps, args.warmup
+
+    print(f"[bench] generating uniform u32 n=2^28 seed 2", file=sys.stderr, flush=True)
+    host = inputs.uniform_u32(N_KEYS, seed=2)
+    src = torch.from_numpy(host.view(np.int32)).to(dev)
+    copies = [src.clone() for _ in range(K + W)]
+    torch.cuda.synchronize()
+
+    print(f"[bench] warmup {W}", file=sys.stderr, flush=True)
+    time_sorts(copies[:W], qms, torch, profile=False)
+    print(f"[bench] timed {K} steps", file=sys.stderr, flush=True)
+    secs, _ = time_sorts(copies[W:], qms, torch, profile=False)
+    sched = qms.qms_last_schedule()
+    # the last sorted copy must be sorted and a permutation of the input
+    from tests.gpu_helpers import is_sorted, multiset_hash
+    ok = is_sorted(copies[-1]) and multiset_hash(copies[-1]) == multiset_hash(src)
+    if not ok:
+        print("bench.py: output check FAILED", file=sys.stderr)
+        sys.exit(1)
+    # the same K steps again on fresh copies, every launch bracketed by HIP
+    # events on the sorting stream (per-kernel durations for the roofline);
+    # kept out of the headline timing because the events add a little time
+    print(f"[bench] event-timed {K} steps", file=sys.stderr, flush=True)
+    for i in range(K):
+        copies[W + i].copy_(src)
+    secs_prof, prof = time_sorts(copies[W:], qms, torch, profile=True)
+    del copies
+
+    ms = secs / K * 1e3
+    value = N_KEYS / (secs / K) / 1e9
+
+    kernels = {}
+    for name, d in prof.items():
+        if d["launches"] == 0:
+            continue
+        kernels[name] = {
+            "launches_per_step": d["launches"] / K,
+            "ms_per_step": d["total_ms"] / K,
+            "mean_launch_us": d["total_ms"] / d["launches"] * 1e3,
+            "algorithmic_GB_per_step": d["bytes"] / K / 1e9,
+            "achieved_GBs": (d["bytes"] / 1e9) / (d["total_ms"] / 1e3) if d["bytes"] else None,
+        }
+    mk = prof["merge"]
+    achieved = (mk["bytes"] / 1e9) / (mk["total_ms"] / 1e3)
+    traffic = measured_traffic()
+    roofline = {
+        "kernel": "k_merge (swap-merge level)",
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": traffic,
+        "algorithmic_bytes_per_launch": mk["bytes"] / mk["launches"],
+        "mean_launch_us": mk["total_ms"] / mk["launches"] * 1e3,
+        "launches": mk["launches"],
+    }
+
+    dists = {"uniform": round(value, 3)}
+    if not args.only_uniform:
+        for name, kind, seed in (("nearly_sorted_1pct", "sorted_swaps", 3),
+                                 ("reverse", "reverse", 0)):
+            print(f"[bench] {name}", file=sys.stderr, flush=True)
+            h = inputs.make_keys(kind, N_KEYS, seed)
+            s2 = torch.from_numpy(h.view(np.int32)).to(dev)
+            cps = [s2.clone() for _ in range(args.dist_steps + 1)]
+            time_sorts(cps[:1], qms, torch, profile=False)
+            sec2, _ = time_sorts(cps[1:], qms, torch, profile=False)
+            if not is_sorted(cps[-1]):
+                print(f"bench.py: {name} output not sorted", file=sys.stderr)
+                sys.exit(1)
+            dists[name] = round(N_KEYS / (sec2 / args.dist_steps) / 1e9, 3)
+            del cps, s2
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        m = 1 << args.cpu_sample_log2
+        sample = host[:m].copy()
+        print(f"[bench] cpu oracle on 2^{args.cpu_sample_log2} keys", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        oracle.sort_inplace_fast(sample, False)
+        dt = time.perf_counter() - t0
+        assert np.all(sample[1:] >= sample[:-1])
+        cpu = {"value": round(m / dt / 1e9, 5), "unit": "Gkeys/s", "cores": 1,
+               "kind": "oracle", "seconds": round(dt, 2),
+               "sample": f"first 2^{args.cpu_sample_log2} keys of the uniform 2^28 workload "
+                         "(seed 2), single-threaded C oracle (QuickMergesort of Fig. 2, "
+                         "counters compiled out)"}
+
+    out = {
+        "metric": "Gkeys/s (uint32, n=2^28) + HBM roofline %",
+        "value": round(value, 3),
+        "unit": "Gkeys/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": round(ms, 3),
+        "ms_per_step_with_event_timing": round(secs_prof / K * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic: uniform uint32 keys from a seeded SplitMix64 stream",
+        "config": {"workload": "one array of 2^28 uint32 keys (1 GiB), uniform on [0, 2^32), "
+                               "seed 2; in-place QuickMergesort",
+                   "n": N_KEYS, "rounds": len(sched)},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "distributions_Gkeys_per_s": dists,
+        "kernels": kernels,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -162,6 +162,27 @@ int qms_release_workspaces(void);
  */
 uint64_t qms_last_schedule(uint64_t *out, uint64_t max_rounds);
 
+/*
+ * Per-kernel-class timing of the sorts issued by the calling thread between
+ * qms_profile_begin and qms_profile_end.  Each launch is bracketed by HIP
+ * events recorded on its own stream; qms_profile_end waits for them and
+ * returns, per class ("tile_sort", "merge_split", "merge", "part_count",
+ * "part_scan", "part_split", "part_swap"), the number of launches, their
+ * summed duration and their summed algorithmic bytes (the bytes the method
+ * must move: 16 per key per swap-merge level and per swapping base-case
+ * pass, 8 per key for an in-place base-case pass, 4 per key for counting,
+ * doubled for key/payload pairs).  Writes up to max_entries records;
+ * *n_out gets the number written.
+ */
+typedef struct {
+    char name[32];
+    uint64_t launches;
+    double total_ms;
+    double bytes;
+} qms_kernel_stat;
+int qms_profile_begin(void);
+int qms_profile_end(qms_kernel_stat *out, int max_entries, int *n_out);
+
 /* Tunables as used by the kernels: base-case tile, merge tile, partition
  * tile (elements).  Read-only; for reports and tests. */
 void qms_get_tiles(uint32_t *base_tile, uint32_t *merge_tile,

@@ -6,6 +6,6 @@ seeded synthetic workloads.
 """
 from .qms import (  # noqa: F401
     QMS_F32, QMS_U32, QmsError, Server, load_library, qms_get_tiles,
-    qms_last_schedule, qms_release_workspaces, qms_sort, qms_sort_batch,
+    qms_last_schedule, qms_profile_begin, qms_profile_end, qms_release_workspaces, qms_sort, qms_sort_batch,
     qms_sort_pairs,
 )

@@ -37,7 +37,8 @@ static std::mutex g_ws_mutex;
 static std::map<std::pair<int, hipStream_t>, Workspace *> g_ws;
 
 static size_t ws_words() {
-    return 3ull * kMaxTiles + 2ull * (kMaxTiles + 1) + 2ull * kMaxChunks + kMaxSplits;
+    return 3ull * kCapTiles + 2ull * (kCapTiles + kCapSegs) + 2ull * kCapChunks + kCapSplits +
+           4ull * kCapSegs;
 }
 
 int get_workspace(int device, hipStream_t stream, Workspace **out) {
@@ -51,39 +52,49 @@ int get_workspace(int device, hipStream_t stream, Workspace **out) {
     Workspace *ws = new Workspace();
     ws->device = device;
     ws->stream = stream;
-    const size_t words = ws_words();
-    const size_t bytes = words * sizeof(uint32_t) + M_COUNT * sizeof(uint64_t) + 256;
+    ws->tab_bytes = tab_arena_bytes();
+    const size_t meta_bytes = (size_t)kCapSegs * M_COUNT * sizeof(uint64_t);
+    const size_t bytes = meta_bytes + ws_words() * sizeof(uint32_t) + ws->tab_bytes + 4096;
     hipError_t e = hipMalloc(&ws->block, bytes);
     if (e != hipSuccess) {
         delete ws;
         (void)hipGetLastError();
         return set_error(QMS_ERR_NOMEM, std::string("workspace allocation: ") + hipGetErrorString(e));
     }
-    e = hipHostMalloc((void **)&ws->h_meta, M_COUNT * sizeof(uint64_t), hipHostMallocDefault);
+    void *h = nullptr;
+    e = hipHostMalloc(&h, 2 * ws->tab_bytes + 4 * kCapSegs * sizeof(uint32_t), hipHostMallocDefault);
     if (e != hipSuccess) {
         (void)hipFree(ws->block);
         delete ws;
         (void)hipGetLastError();
         return set_error(QMS_ERR_NOMEM, std::string("pinned host allocation: ") + hipGetErrorString(e));
     }
-    uint64_t *meta = (uint64_t *)ws->block;
-    uint32_t *w = (uint32_t *)(meta + M_COUNT);
-    ws->meta = meta;
+    ws->htab[0] = h;
+    ws->htab[1] = (char *)h + ws->tab_bytes;
+    ws->h_res = (uint32_t *)((char *)h + 2 * ws->tab_bytes);
+    char *b = (char *)ws->block;
+    ws->meta = (uint64_t *)b;
+    b += meta_bytes;
+    ws->dtab = b;
+    b += (ws->tab_bytes + 255) & ~(size_t)255;
+    uint32_t *w = (uint32_t *)b;
     ws->cnt_lt = w;
-    w += kMaxTiles;
+    w += kCapTiles;
     ws->cnt_eq = w;
-    w += kMaxTiles;
+    w += kCapTiles;
     ws->eqmv = w;
-    w += kMaxTiles;
+    w += kCapTiles;
     ws->preL = w;
-    w += kMaxTiles + 1;
+    w += kCapTiles + kCapSegs;
     ws->preR = w;
-    w += kMaxTiles + 1;
+    w += kCapTiles + kCapSegs;
     ws->spL = w;
-    w += kMaxChunks;
+    w += kCapChunks;
     ws->spR = w;
-    w += kMaxChunks;
+    w += kCapChunks;
     ws->splits = w;
+    w += kCapSplits;
+    ws->res = w;
     g_ws[key] = ws;
     *out = ws;
     return QMS_OK;
@@ -98,7 +109,7 @@ int release_workspaces() {
         (void)hipSetDevice(ws->device);
         (void)hipStreamSynchronize(ws->stream);
         (void)hipFree(ws->block);
-        (void)hipHostFree(ws->h_meta);
+        (void)hipHostFree(ws->htab[0]);
         delete ws;
     }
     g_ws.clear();
@@ -132,66 +143,6 @@ DeviceScope::~DeviceScope() {
     if (prev_ != dev_) (void)hipSetDevice(prev_);
 }
 
-// ---- the QuickMergesort loop ------------------------------------------------------------
-static thread_local std::vector<std::array<uint64_t, 5>> g_schedule;
-
-// Mergesort of the m elements at D with the m cells at Bf as swap space
-// (Fig. 2's out()/msort()/merge(), bottom-up with power-of-two run widths).
-// The base case writes into the buffer when the number of merge levels is
-// odd, so that the last level lands in D.  Returns the number of levels.
-int mergesort_side(int dt, bool pairs, uint32_t *keys, uint32_t *vals, uint64_t D,
-                   uint64_t Bf, uint64_t m, const Workspace &ws, hipStream_t st, int *levels) {
-    *levels = 0;
-    if (m == 0) return QMS_OK;
-    const uint64_t ntiles = (m + kBaseTile - 1) / kBaseTile;
-    int L = 0;
-    while ((1ull << L) < ntiles) ++L;
-    const bool odd = (L & 1) != 0;
-    hipError_t e = launch_tile_sort(dt, pairs, keys, vals, D, odd ? Bf : D, m, odd, st);
-    if (e != hipSuccess) return hip_error(e, "base case launch");
-    uint64_t cur = odd ? Bf : D, oth = odd ? D : Bf;
-    uint64_t W = kBaseTile;
-    for (int l = 0; l < L; ++l) {
-        e = launch_merge_level(dt, pairs, keys, vals, cur, oth, m, W, ws.splits, st);
-        if (e != hipSuccess) return hip_error(e, "merge launch");
-        std::swap(cur, oth);
-        W *= 2;
-    }
-    *levels = L;
-    return QMS_OK;
-}
-
-int sort_array(int dt, bool pairs, uint32_t *keys, uint32_t *vals, uint64_t n,
-               const Workspace &ws, hipStream_t st, bool log) {
-    if (log) g_schedule.clear();
-    uint64_t lo = 0, hi = n;
-    while (hi - lo > (uint64_t)kBaseTile) {
-        PartitionResult pr;
-        hipError_t e = run_partition(dt, pairs, keys, vals, lo, hi, ws, &pr, st);
-        if (e != hipSuccess) return hip_error(e, "partition");
-        const uint64_t s = hi - lo;
-        if (pr.c_lt + pr.c_eq > s || pr.c_eq == 0)
-            return set_error(QMS_ERR_HIP, "partition returned inconsistent counts");
-        const uint64_t b1 = lo + pr.c_lt, b2 = b1 + pr.c_eq;
-        const uint64_t mL = pr.c_lt, mR = hi - b2;
-        int levels = 0, rc;
-        if (mL <= mR) {
-            rc = mergesort_side(dt, pairs, keys, vals, lo, b2, mL, ws, st, &levels);
-            lo = b2;
-        } else {
-            rc = mergesort_side(dt, pairs, keys, vals, b2, b1 - mR, mR, ws, st, &levels);
-            hi = b1;
-        }
-        if (rc != QMS_OK) return rc;
-        if (log) g_schedule.push_back({s, pr.c_lt, pr.c_eq, s - pr.c_lt - pr.c_eq, (uint64_t)levels});
-    }
-    if (hi - lo > 1) {
-        hipError_t e = launch_tile_sort(dt, pairs, keys, vals, lo, lo, hi - lo, false, st);
-        if (e != hipSuccess) return hip_error(e, "final base case launch");
-    }
-    return QMS_OK;
-}
-
 static int sort_entry(void *d_keys, uint32_t *d_vals, uint64_t n, int dt, hipStream_t stream,
                       bool pairs) {
     if (dt != QMS_U32 && dt != QMS_F32) return set_error(QMS_ERR_UNSUPPORTED, "unknown dtype");
@@ -212,7 +163,8 @@ static int sort_entry(void *d_keys, uint32_t *d_vals, uint64_t n, int dt, hipStr
     Workspace *ws = nullptr;
     rc = get_workspace(dev, stream, &ws);
     if (rc != QMS_OK) return rc;
-    return sort_array(dt, pairs, (uint32_t *)d_keys, d_vals, n, *ws, stream, true);
+    HostSeg seg{(uint32_t *)d_keys, pairs ? d_vals : nullptr, n};
+    return sort_segments(dt, pairs, &seg, 1, *ws, stream, true);
 }
 
 }  // namespace qms
@@ -248,10 +200,11 @@ int qms_release_workspaces(void) {
 }
 
 uint64_t qms_last_schedule(uint64_t *out, uint64_t max_rounds) {
-    const uint64_t n = g_schedule.size();
+    const auto &sched = last_schedule();
+    const uint64_t n = sched.size();
     if (out) {
         for (uint64_t i = 0; i < n && i < max_rounds; ++i)
-            for (int j = 0; j < 5; ++j) out[i * 5 + j] = g_schedule[i][j];
+            for (int j = 0; j < 5; ++j) out[i * 5 + j] = sched[i][j];
     }
     return n;
 }

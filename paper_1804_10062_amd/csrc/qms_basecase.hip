@@ -17,6 +17,7 @@
 
 #include "qms_device.hpp"
 #include "qms_internal.hpp"
+#include "qms_prof.hpp"
 
 namespace qms {
 
@@ -147,35 +148,36 @@ __device__ __forceinline__ void tile_sort_block(uint32_t *sk, uint32_t *sv, uint
     }
 }
 
+// One workgroup per base tile of every Mergesort task in the table.
 template <class O, bool PAIRS>
-__global__ __launch_bounds__(kBlock) void k_tile_sort(uint32_t *keys, uint32_t *vals,
-                                                      uint64_t src, uint64_t dst,
-                                                      uint64_t m, int swap) {
-    const uint64_t t0 = (uint64_t)blockIdx.x * kBaseTile;
-    if (t0 >= m) return;
-    const uint32_t len = (uint32_t)min((uint64_t)kBaseTile, m - t0);
-    tile_sort_block<O, PAIRS>(keys + src + t0, PAIRS ? vals + src + t0 : nullptr,
-                              keys + dst + t0, PAIRS ? vals + dst + t0 : nullptr, len,
-                              swap != 0);
+__global__ __launch_bounds__(kBlock) void k_tile_sort(TaskRef<SortSeg> tasks) {
+    uint32_t t, a;
+    const SortSeg g = task_of(tasks, blockIdx.x, &t, &a);
+    const uint32_t t0 = t * kBaseTile;
+    if (t0 >= g.m) return;
+    const uint32_t len = min((uint32_t)kBaseTile, g.m - t0);
+    const bool swap = (g.L & 1u) != 0;
+    const uint32_t src = g.D + t0, dst = (swap ? g.Bf : g.D) + t0;
+    tile_sort_block<O, PAIRS>(g.keys + src, PAIRS ? g.vals + src : nullptr, g.keys + dst,
+                              PAIRS ? g.vals + dst : nullptr, len, swap);
 }
 
 template <class O, bool PAIRS>
-static hipError_t tile_sort_t(uint32_t *keys, uint32_t *vals, uint64_t src, uint64_t dst,
-                              uint64_t m, bool swap, hipStream_t st) {
-    if (m == 0) return hipSuccess;
-    const uint64_t nb = (m + kBaseTile - 1) / kBaseTile;
-    hipLaunchKernelGGL((k_tile_sort<O, PAIRS>), dim3((uint32_t)nb), dim3(kBlock), 0, st, keys,
-                       vals, src, dst, m, swap ? 1 : 0);
+static hipError_t tile_sort_t(const TaskRef<SortSeg> &tasks, uint32_t tiles, double bytes,
+                              hipStream_t st) {
+    if (tiles == 0) return hipSuccess;
+    ProfScope prof(st, K_TILE_SORT, bytes);
+    hipLaunchKernelGGL((k_tile_sort<O, PAIRS>), dim3(tiles), dim3(kBlock), 0, st, tasks);
     return hipGetLastError();
 }
 
-hipError_t launch_tile_sort(int dt, bool pairs, uint32_t *keys, uint32_t *vals, uint64_t src,
-                            uint64_t dst, uint64_t m, bool swap, hipStream_t st) {
+hipError_t launch_tile_sort(int dt, bool pairs, const TaskRef<SortSeg> &tasks, uint32_t tiles,
+                            double bytes, hipStream_t st) {
     if (dt == 1)
-        return pairs ? tile_sort_t<OrdF32, true>(keys, vals, src, dst, m, swap, st)
-                     : tile_sort_t<OrdF32, false>(keys, vals, src, dst, m, swap, st);
-    return pairs ? tile_sort_t<OrdU32, true>(keys, vals, src, dst, m, swap, st)
-                 : tile_sort_t<OrdU32, false>(keys, vals, src, dst, m, swap, st);
+        return pairs ? tile_sort_t<OrdF32, true>(tasks, tiles, bytes, st)
+                     : tile_sort_t<OrdF32, false>(tasks, tiles, bytes, st);
+    return pairs ? tile_sort_t<OrdU32, true>(tasks, tiles, bytes, st)
+                 : tile_sort_t<OrdU32, false>(tasks, tiles, bytes, st);
 }
 
 }  // namespace qms

@@ -1,4 +1,5 @@
-// qms_batch.cpp -- qms_sort_batch: many independent arrays in one call.
+// qms_batch.cpp -- qms_sort_batch: many independent arrays in one call; all
+// arrays advance together through the phases of the QuickMergesort loop.
 #include <hip/hip_runtime.h>
 
 #include <vector>
@@ -42,14 +43,14 @@ extern "C" int qms_sort_batch(void *d_keys, uint32_t *d_vals, const uint64_t *d_
         rc = get_workspace(dev, stream, &ws);
         if (rc != QMS_OK) return rc;
         uint32_t *keys = (uint32_t *)d_keys;
+        std::vector<HostSeg> segs;
+        segs.reserve(num_segments);
         for (uint32_t j = 0; j < num_segments; ++j) {
             const uint64_t n = off[j + 1] - off[j];
             if (n <= 1) continue;
-            rc = sort_array(dt, d_vals != nullptr, keys + off[j], d_vals ? d_vals + off[j] : nullptr,
-                            n, *ws, stream, false);
-            if (rc != QMS_OK) return rc;
+            segs.push_back(HostSeg{keys + off[j], d_vals ? d_vals + off[j] : nullptr, n});
         }
-        return QMS_OK;
+        return sort_segments(dt, d_vals != nullptr, segs.data(), segs.size(), *ws, stream, false);
     } catch (...) {
         return set_error(QMS_ERR_NOMEM, "host exception in qms_sort_batch");
     }

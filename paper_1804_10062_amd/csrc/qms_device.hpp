@@ -12,10 +12,15 @@ constexpr int kBlock = 256;            // threads per workgroup (4 waves)
 constexpr int kWave = 64;              // CDNA wavefront width
 constexpr int kWaves = kBlock / kWave;
 
+// Build-time tunables (defaults are the shipped configuration).
+#ifndef QMS_MERGE_ITEMS
+#define QMS_MERGE_ITEMS 8
+#endif
+
 constexpr int kBaseTile = 4096;        // base-case tile (X of QuickMergeXsort)
 constexpr int kBasePerThread = kBaseTile / kBlock;     // 16
-constexpr int kMergeTile = 2048;       // outputs per workgroup in a merge level
-constexpr int kMergePerThread = kMergeTile / kBlock;   // 8
+constexpr int kMergePerThread = QMS_MERGE_ITEMS;       // outputs per thread
+constexpr int kMergeTile = kBlock * kMergePerThread;   // outputs per workgroup
 constexpr int kPartSub = 4096;         // elements a workgroup classifies per step
 constexpr int kPartItems = kPartSub / kBlock;          // 16
 constexpr int kRankChunk = 2048;       // misplaced pairs exchanged per workgroup
@@ -34,8 +39,89 @@ enum MetaSlot : int {
     M_LTPART = 5,  // # keys < pivot in that tile, left of the boundary
     M_EQPART = 6,  // # keys == pivot in that tile, left of the boundary
     M_XB = 7,      // misplaced pairs of pass B (== pivot vs > pivot)
+    M_RCA = 8,     // misplaced pairs per chunk, pass A
+    M_RCB = 9,     // misplaced pairs per chunk, pass B
     M_COUNT = 16
 };
+
+// Misplaced pairs per swap chunk for a pass with X pairs over a range of s
+// keys: at most kRankChunk (the LDS slots of a workgroup), and small enough
+// that there are about s / (2 kPartSub) chunks, so that sparse misplacement
+// (nearly sorted input) still spreads the range scans over many workgroups.
+__host__ __device__ inline uint32_t rank_chunk(uint64_t X, uint64_t s) {
+    const uint64_t target = (s + 2 * kPartSub - 1) / (2 * kPartSub);
+    uint64_t rc = (X + target - 1) / target;
+    if (rc < 1) rc = 1;
+    if (rc > (uint64_t)kRankChunk) rc = kRankChunk;
+    return (uint32_t)rc;
+}
+__host__ __device__ inline uint64_t chunk_count(uint64_t X, uint64_t s) {
+    const uint32_t rc = rank_chunk(X, s);
+    return (X + rc - 1) / rc;
+}
+
+// ---- task tables ----------------------------------------------------------------
+// A launch serves many independent segments (arrays) at once.  The host lists
+// the segments of a phase in a table and gives each a number of work items
+// (workgroups or waves); `pre` is the exclusive prefix of those counts, so
+// work item g belongs to the segment a with pre[a] <= g < pre[a + 1].  With a
+// single segment the table travels by value in the kernel arguments and no
+// lookup is done.
+
+// One segment in a partition round: the keys of the range [lo, lo + s).
+struct PartSeg {
+    uint32_t *keys;      // segment base
+    uint32_t *vals;      // payloads (nullptr for keys only)
+    uint32_t lo, s;      // current range, relative to keys
+    uint32_t tile_off;   // first entry of the segment in the per-tile arrays
+    uint32_t nt;         // partition tiles of the range
+    uint32_t chunk_off;  // first entry in the chunk-boundary arrays
+    uint32_t slot;       // index of the segment's round-state words
+};
+
+// One Mergesort of a round: m keys at D, swap space at Bf (offsets from keys),
+// L merge levels; the base case swaps into Bf when L is odd.
+struct SortSeg {
+    uint32_t *keys;
+    uint32_t *vals;
+    uint32_t D, Bf, m;
+    uint32_t L;          // merge levels
+    uint32_t split_off;  // first entry in the merge split array
+    uint32_t pad;
+};
+
+template <class T>
+struct TaskRef {
+    const T *tab;        // device table (A > 1)
+    const uint32_t *pre; // device prefix of work items, A + 1 entries (A > 1)
+    uint32_t A;          // segments
+    T one;               // the segment itself when A == 1
+};
+
+// Work item g -> segment index (largest a with pre[a] <= g).
+__device__ __forceinline__ uint32_t find_task(const uint32_t *pre, uint32_t A, uint32_t g) {
+    uint32_t lo = 0, hi = A;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (pre[mid] <= g) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <class T>
+__device__ __forceinline__ T task_of(const TaskRef<T> &r, uint32_t g, uint32_t *local,
+                                     uint32_t *index) {
+    if (r.A == 1) {
+        *local = g;
+        *index = 0;
+        return r.one;
+    }
+    const uint32_t a = find_task(r.pre, r.A, g);
+    *local = g - r.pre[a];
+    *index = a;
+    return r.tab[a];
+}
 
 // ---- key order ----------------------------------------------------------------
 // Keys are compared as unsigned 32-bit integers after an order map applied in

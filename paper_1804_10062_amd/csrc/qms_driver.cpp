@@ -1,0 +1,330 @@
+// qms_driver.cpp -- the QuickMergesort loop (Fig. 2's sort()) run for many
+// independent segments at once.
+//
+// Every segment follows the paper's loop: partition its range around the
+// median of three keys, Mergesort the smaller side with the larger side as
+// swap space, continue on the larger side; a range of at most kBaseTile keys
+// is finished by the base case in place.  All segments advance in lockstep
+// rounds, and every phase of a round is one launch for all segments (task
+// tables, qms_device.hpp): count + scan, [split +] swap of pass A, scan,
+// [split +] swap of pass B, base case, then one launch pair per merge level.
+// The host reads three counters per segment back once per round to size the
+// later launches of the round.  A single array is a batch of one (its task
+// tables travel by value in the kernel arguments).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cstring>
+#include <vector>
+
+#include "qms.h"
+#include "qms_host.hpp"
+#include "qms_internal.hpp"
+
+namespace qms {
+
+namespace {
+
+uint32_t ceil_log2(uint64_t x) {
+    uint32_t l = 0;
+    while ((1ull << l) < x) ++l;
+    return l;
+}
+
+// bump allocator over a pinned host arena mirrored at the same offsets in
+// device memory
+struct Arena {
+    char *h;
+    char *d;
+    size_t cap, used = 0;
+    template <class T>
+    T *take(size_t count, size_t *off) {
+        const size_t o = used;
+        used += (count * sizeof(T) + 255) & ~(size_t)255;
+        if (used > cap) return nullptr;
+        *off = o;
+        return (T *)(h + o);
+    }
+    template <class T>
+    const T *dev(size_t off) const {
+        return (const T *)(d + off);
+    }
+};
+
+struct Seg {
+    uint32_t *keys, *vals;
+    uint32_t lo, hi;
+};
+
+// One round's tables.
+int upload(Arena &ar, size_t from, hipStream_t st) {
+    if (ar.used <= from) return QMS_OK;
+    hipError_t e =
+        hipMemcpyAsync(ar.d + from, ar.h + from, ar.used - from, hipMemcpyHostToDevice, st);
+    return e == hipSuccess ? QMS_OK : hip_error(e, "task table upload");
+}
+
+thread_local std::vector<std::array<uint64_t, 5>> g_schedule;
+
+}  // namespace
+
+size_t tab_arena_bytes() {
+    // per segment: partition entry, 5 prefixes, up to 2 sort tasks, 2 prefixes
+    const size_t per = sizeof(PartSeg) + 5 * 4 + 2 * sizeof(SortSeg) + 2 * 2 * 4;
+    return per * kCapSegs + 64 * 1024;
+}
+
+const std::vector<std::array<uint64_t, 5>> &last_schedule() { return g_schedule; }
+
+// Sort a group of segments (count <= kCapSegs, total keys < 2^32).
+static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
+                      hipStream_t st, bool log) {
+    const double w = pairs ? 2.0 : 1.0;
+    std::vector<uint32_t> active, next;
+    // ranges of at most kBaseTile keys, sorted in place by the base case.  A
+    // range that becomes small in a round still holds that round's swap
+    // buffer, so it runs one round later (next_finals -> ready_finals).
+    std::vector<SortSeg> ready_finals, next_finals, tasks;
+    for (uint32_t i = 0; i < segs.size(); ++i) {
+        const Seg &g = segs[i];
+        const uint32_t s = g.hi - g.lo;
+        if (s > (uint32_t)kBaseTile) active.push_back(i);
+        else if (s > 1) ready_finals.push_back(SortSeg{g.keys, g.vals, g.lo, 0, s, 0, 0, 0});
+    }
+    while (!active.empty() || !ready_finals.empty()) {
+        // alternate arenas: the one used two rounds ago has no copy in flight
+        // (the previous round's readback synchronised the stream after them)
+        Arena ar{(char *)ws.htab[ws.rounds & 1], (char *)ws.dtab, ws.tab_bytes};
+        ++ws.rounds;
+        tasks.clear();
+        const uint32_t A = (uint32_t)active.size();
+        if (A > 0) {
+            // ---- partition: count + scan A, then read three counters back ----
+            uint64_t sum_s = 0;
+            for (uint32_t i : active) sum_s += segs[i].hi - segs[i].lo;
+            uint32_t TP = kPartSub;
+            for (;;) {
+                uint64_t tot = 0;
+                for (uint32_t i : active) tot += (segs[i].hi - segs[i].lo + TP - 1) / TP;
+                if (tot <= kCapTiles) break;
+                TP *= 2;
+            }
+            size_t o_tab, o_pre;
+            PartSeg *pt = ar.take<PartSeg>(A, &o_tab);
+            uint32_t *pc = ar.take<uint32_t>(A + 1, &o_pre);
+            if (!pt || !pc) return set_error(QMS_ERR_NOMEM, "task table arena too small");
+            uint32_t toff = 0, coff = 0, max_nt = 0;
+            pc[0] = 0;
+            for (uint32_t a = 0; a < A; ++a) {
+                const Seg &g = segs[active[a]];
+                const uint32_t s = g.hi - g.lo;
+                const uint32_t nt = (s + TP - 1) / TP;
+                pt[a] = PartSeg{g.keys, g.vals, g.lo, s, toff, nt, coff, a};
+                toff += nt;
+                coff += (s + 4095) / 4096 + 2;
+                pc[a + 1] = toff;
+                max_nt = std::max(max_nt, nt);
+            }
+            if (coff > kCapChunks) return set_error(QMS_ERR_UNSUPPORTED, "batch too large for one round");
+            if (A > 1) {
+                int rc = upload(ar, 0, st);
+                if (rc != QMS_OK) return rc;
+            }
+            PartitionLaunch L{};
+            L.tasks.A = A;
+            L.tasks.one = pt[0];
+            L.tasks.tab = ar.dev<PartSeg>(o_tab);
+            L.tasks.pre = ar.dev<uint32_t>(o_pre);
+            L.TP = TP;
+            L.scan_threads = max_nt > 4 * kBlock ? kScanThreads : kBlock;
+            L.keys_total = (double)sum_s;
+            L.ws = &ws;
+            L.phase = 0;
+            L.work = toff;
+            hipError_t e = launch_partition_phase(dt, pairs, L, st);
+            if (e != hipSuccess) return hip_error(e, "partition count/scan");
+            e = hipMemcpyAsync(ws.h_res, ws.res, sizeof(uint32_t) * 4 * A, hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+            if (e != hipSuccess) return hip_error(e, "partition readback");
+
+            // ---- work of pass A and pass B per segment ----
+            const size_t mark = ar.used;
+            size_t o_ca, o_wa, o_cb, o_wb;
+            uint32_t *ca = ar.take<uint32_t>(A + 1, &o_ca), *wa = ar.take<uint32_t>(A + 1, &o_wa);
+            uint32_t *cb = ar.take<uint32_t>(A + 1, &o_cb), *wb = ar.take<uint32_t>(A + 1, &o_wb);
+            if (!ca || !wa || !cb || !wb) return set_error(QMS_ERR_NOMEM, "task table arena too small");
+            ca[0] = wa[0] = cb[0] = wb[0] = 0;
+            double swap_bytes = 0;
+            bool any_b = false;
+            for (uint32_t a = 0; a < A; ++a) {
+                const uint64_t s = pt[a].s;
+                const uint64_t c_lt = ws.h_res[4 * a], c_eq = ws.h_res[4 * a + 1];
+                const uint64_t X = ws.h_res[4 * a + 2];
+                if (c_eq == 0 || c_lt + c_eq > s)
+                    return set_error(QMS_ERR_HIP, "partition returned inconsistent counts");
+                const uint64_t nch = chunk_count(X, s);
+                ca[a + 1] = ca[a] + (uint32_t)nch;
+                wa[a + 1] = wa[a] + (uint32_t)(nch > 1 ? 2 * (nch - 1) : 0);
+                if (X > 0) swap_bytes += 4.0 * (double)s + 2.0 * 4.0 * w * (double)X;
+                // pass B pairs are at most min(#==, #>); size its grids for that
+                const uint64_t gt = s - c_lt - c_eq;
+                const uint64_t xb = std::min(c_eq, gt);
+                uint64_t nb = 0;
+                if (xb > 0) {
+                    const uint64_t full = (xb + kRankChunk - 1) / kRankChunk;
+                    const uint64_t target = (s + 2 * kPartSub - 1) / (2 * kPartSub);
+                    nb = std::min(xb, std::max(full, target));
+                    any_b = true;
+                }
+                cb[a + 1] = cb[a] + (uint32_t)nb;
+                wb[a + 1] = wb[a] + (uint32_t)(nb > 1 ? 2 * (nb - 1) : 0);
+            }
+            if (A > 1) {
+                int rc = upload(ar, mark, st);
+                if (rc != QMS_OK) return rc;
+            }
+            if (ca[A] > 0) {
+                L.phase = 1;
+                L.tasks.pre = ar.dev<uint32_t>(o_wa);
+                L.work = wa[A];
+                if ((e = launch_partition_phase(dt, pairs, L, st)) != hipSuccess)
+                    return hip_error(e, "split A");
+                L.phase = 2;
+                L.tasks.pre = ar.dev<uint32_t>(o_ca);
+                L.work = ca[A];
+                L.bytes = swap_bytes;
+                if ((e = launch_partition_phase(dt, pairs, L, st)) != hipSuccess)
+                    return hip_error(e, "swap A");
+            }
+            if (any_b) {
+                L.phase = 4;
+                L.work = A;
+                if ((e = launch_partition_phase(dt, pairs, L, st)) != hipSuccess)
+                    return hip_error(e, "scan B");
+                L.phase = 3;
+                L.tasks.pre = ar.dev<uint32_t>(o_wb);
+                L.work = wb[A];
+                if ((e = launch_partition_phase(dt, pairs, L, st)) != hipSuccess)
+                    return hip_error(e, "split B");
+                L.phase = 5;
+                L.tasks.pre = ar.dev<uint32_t>(o_cb);
+                L.work = cb[A];
+                if ((e = launch_partition_phase(dt, pairs, L, st)) != hipSuccess)
+                    return hip_error(e, "swap B");
+            }
+
+            // ---- side choice (Fig. 2 sort(): the smaller side is mergesorted
+            // with the larger side as swap space; the loop keeps the larger) ----
+            next.clear();
+            for (uint32_t a = 0; a < A; ++a) {
+                Seg &g = segs[active[a]];
+                const uint32_t s = g.hi - g.lo;
+                const uint32_t c_lt = ws.h_res[4 * a], c_eq = ws.h_res[4 * a + 1];
+                const uint32_t b1 = g.lo + c_lt, b2 = b1 + c_eq;
+                const uint32_t mL = c_lt, mR = g.hi - b2;
+                SortSeg t{g.keys, g.vals, 0, 0, 0, 0, 0, 0};
+                if (mL <= mR) {
+                    t.D = g.lo;
+                    t.Bf = b2;
+                    t.m = mL;
+                    g.lo = b2;
+                } else {
+                    t.D = b2;
+                    t.Bf = b1 - mR;
+                    t.m = mR;
+                    g.hi = b1;
+                }
+                t.L = t.m > (uint32_t)kBaseTile ? ceil_log2((t.m + kBaseTile - 1) / kBaseTile) : 0;
+                if (t.m > 1) tasks.push_back(t);
+                if (log) g_schedule.push_back({s, c_lt, c_eq, (uint64_t)(s - c_lt - c_eq), t.L});
+                const uint32_t s2 = g.hi - g.lo;
+                if (s2 > (uint32_t)kBaseTile) next.push_back(active[a]);
+                else if (s2 > 1) next_finals.push_back(SortSeg{g.keys, g.vals, g.lo, 0, s2, 0, 0, 0});
+            }
+            active.swap(next);
+        }
+
+        // ---- Mergesort tasks of this round and the finals that may run ----
+        for (const SortSeg &f : ready_finals) tasks.push_back(f);
+        ready_finals.swap(next_finals);
+        next_finals.clear();
+        if (tasks.empty()) continue;
+        // order by merge levels, descending: the tasks of level l are a prefix
+        std::stable_sort(tasks.begin(), tasks.end(),
+                         [](const SortSeg &x, const SortSeg &y) { return x.L > y.L; });
+        const uint32_t T = (uint32_t)tasks.size();
+        const size_t mark = ar.used;
+        size_t o_st, o_pt, o_pm;
+        SortSeg *stab = ar.take<SortSeg>(T, &o_st);
+        uint32_t *ptile = ar.take<uint32_t>(T + 1, &o_pt);
+        uint32_t *pmerge = ar.take<uint32_t>(T + 1, &o_pm);
+        if (!stab || !ptile || !pmerge) return set_error(QMS_ERR_NOMEM, "task table arena too small");
+        ptile[0] = pmerge[0] = 0;
+        double base_bytes = 0;
+        uint32_t maxL = 0;
+        for (uint32_t a = 0; a < T; ++a) {
+            SortSeg t = tasks[a];
+            t.split_off = pmerge[a];
+            stab[a] = t;
+            ptile[a + 1] = ptile[a] + (t.m + kBaseTile - 1) / kBaseTile;
+            pmerge[a + 1] = pmerge[a] + (t.m + kMergeTile - 1) / kMergeTile;
+            base_bytes += ((t.L & 1) ? 16.0 : 8.0) * w * (double)t.m;
+            maxL = std::max(maxL, t.L);
+        }
+        if (pmerge[T] > kCapSplits) return set_error(QMS_ERR_UNSUPPORTED, "too many merge tiles");
+        if (T > 1) {
+            int rc = upload(ar, mark, st);
+            if (rc != QMS_OK) return rc;
+        }
+        TaskRef<SortSeg> R;
+        R.A = T;
+        R.one = stab[0];
+        R.tab = ar.dev<SortSeg>(o_st);
+        R.pre = ar.dev<uint32_t>(o_pt);
+        hipError_t e = launch_tile_sort(dt, pairs, R, ptile[T], base_bytes, st);
+        if (e != hipSuccess) return hip_error(e, "base case");
+        R.pre = ar.dev<uint32_t>(o_pm);
+        for (uint32_t l = 0; l < maxL; ++l) {
+            uint32_t Al = 0;
+            double mb = 0;
+            while (Al < T && stab[Al].L > l) {
+                mb += 16.0 * w * (double)stab[Al].m;
+                ++Al;
+            }
+            TaskRef<SortSeg> Rl = R;
+            Rl.A = Al;
+            e = launch_merge_level(dt, pairs, Rl, l, pmerge[Al], mb, ws.splits, st);
+            if (e != hipSuccess) return hip_error(e, "merge level");
+        }
+    }
+    return QMS_OK;
+}
+
+int sort_segments(int dt, bool pairs, const HostSeg *segs, size_t count, Workspace &ws,
+                  hipStream_t st, bool log) {
+    if (log) g_schedule.clear();
+    std::vector<Seg> group;
+    uint64_t group_keys = 0;
+    auto flush = [&]() -> int {
+        if (group.empty()) return QMS_OK;
+        int rc = sort_group(dt, pairs, group, ws, st, log);
+        group.clear();
+        group_keys = 0;
+        return rc;
+    };
+    for (size_t i = 0; i < count; ++i) {
+        const HostSeg &h = segs[i];
+        if (h.n <= 1) continue;
+        if (h.n >= (1ull << 32)) return set_error(QMS_ERR_UNSUPPORTED, "segment of 2^32 keys or more");
+        if (group.size() == kCapSegs || group_keys + h.n >= (1ull << 32)) {
+            int rc = flush();
+            if (rc != QMS_OK) return rc;
+        }
+        group.push_back(Seg{h.keys, h.vals, 0, (uint32_t)h.n});
+        group_keys += h.n;
+    }
+    return flush();
+}
+
+}  // namespace qms

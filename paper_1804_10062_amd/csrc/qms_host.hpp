@@ -4,7 +4,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <array>
 #include <string>
+#include <vector>
 
 #include "qms_internal.hpp"
 
@@ -16,9 +18,19 @@ int check_device_ptr(const void *p, const char *what, int *device);
 int get_workspace(int device, hipStream_t stream, Workspace **out);
 int release_workspaces();
 
-// One array [0, n) of keys (and payloads): the full QuickMergesort loop.
-int sort_array(int dt, bool pairs, uint32_t *keys, uint32_t *vals, uint64_t n,
-               const Workspace &ws, hipStream_t st, bool log);
+// One array to sort: n keys (and payloads) at device addresses.
+struct HostSeg {
+    uint32_t *keys;
+    uint32_t *vals;  // nullptr for keys only
+    uint64_t n;
+};
+
+// The QuickMergesort loop for every array of the list, all arrays advancing
+// through each phase in one launch.  log: record the per-round schedule.
+int sort_segments(int dt, bool pairs, const HostSeg *segs, size_t count, Workspace &ws,
+                  hipStream_t st, bool log);
+size_t tab_arena_bytes();
+const std::vector<std::array<uint64_t, 5>> &last_schedule();
 
 // Makes `dev` current for the lifetime of the object.
 class DeviceScope {

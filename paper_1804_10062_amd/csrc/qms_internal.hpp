@@ -5,44 +5,70 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "qms_device.hpp"
+
 namespace qms {
 
-// Fixed capacity of the merge split array: enough for a mergesorted side of
-// up to 2^31 elements (the smaller side of any array of < 2^32 keys).
-constexpr uint64_t kMaxSplits = (1ull << 31) / 2048 + 2;
-// Capacity of the partition chunk-boundary arrays: at most half of a range of
-// < 2^32 keys is misplaced, in chunks of kRankChunk (2048).
-constexpr uint64_t kMaxChunks = (1ull << 31) / 2048 + 2;
+// ---- fixed workspace capacities (independent of the number of keys) ---------------
+// Segments served by one round of launches; larger batches run in groups.
+constexpr uint32_t kCapSegs = 32768;
+// Partition tiles of one round (the tile grows beyond kPartSub if needed).
+constexpr uint64_t kCapTiles = 1ull << 20;
+// Chunk boundaries of one round: each segment reserves ceil(s / 4096) + 2.
+constexpr uint64_t kCapChunks = (1ull << 20) + 2ull * kCapSegs + 16;
+// Merge splits of one level: ceil(m / kMergeTile) per task, m < 2^31.
+constexpr uint64_t kCapSplits = (1ull << 31) / kMergeTile + kCapSegs + 16;
+// Merge levels a task can need: ceil(log2(2^31 / kBaseTile)).
+constexpr int kMaxLevels = 20;
 
-// Library-owned scratch of one (device, stream): counters and round state.
-// Its size does not depend on n.
+// Library-owned scratch of one (device, stream): counters, round state and
+// task tables.  Its size does not depend on the number of keys sorted.
 struct Workspace {
     int device = -1;
     hipStream_t stream = nullptr;
-    void *block = nullptr;       // one device allocation holding the arrays
-    uint32_t *cnt_lt = nullptr;  // [kMaxTiles]
-    uint32_t *cnt_eq = nullptr;  // [kMaxTiles]
-    uint32_t *eqmv = nullptr;    // [kMaxTiles]
-    uint32_t *preL = nullptr;    // [kMaxTiles + 1]
-    uint32_t *preR = nullptr;    // [kMaxTiles + 1]
-    uint32_t *spL = nullptr;     // [kMaxChunks]
-    uint32_t *spR = nullptr;     // [kMaxChunks]
-    uint32_t *splits = nullptr;  // [kMaxSplits]
-    uint64_t *meta = nullptr;    // [M_COUNT]
-    uint64_t *h_meta = nullptr;  // pinned host mirror of meta
+    void *block = nullptr;       // one device allocation holding everything below
+    uint32_t *cnt_lt = nullptr;  // [kCapTiles]
+    uint32_t *cnt_eq = nullptr;  // [kCapTiles]
+    uint32_t *eqmv = nullptr;    // [kCapTiles]
+    uint32_t *preL = nullptr;    // [kCapTiles + kCapSegs]
+    uint32_t *preR = nullptr;    // [kCapTiles + kCapSegs]
+    uint32_t *spL = nullptr;     // [kCapChunks]
+    uint32_t *spR = nullptr;     // [kCapChunks]
+    uint32_t *splits = nullptr;  // [kCapSplits]
+    uint64_t *meta = nullptr;    // [kCapSegs * M_COUNT]
+    uint32_t *res = nullptr;     // [4 * kCapSegs] per-segment partition results
+    // task tables: device copies of the host arena below
+    void *dtab = nullptr;        // [tab_bytes]
+    void *htab[2] = {nullptr, nullptr};  // pinned host arenas (alternating rounds)
+    size_t tab_bytes = 0;
+    uint32_t *h_res = nullptr;   // pinned host mirror of res
+    uint64_t rounds = 0;         // rounds run with this workspace (arena parity)
 };
 
-struct PartitionResult {
-    uint64_t pivot, c_lt, c_eq, x_a;
+// Layout of a task-table arena (offsets in bytes; same on host and device).
+struct TabLayout {
+    size_t part_tab, pre_count, pre_chunk_a, pre_wave_a, pre_chunk_b, pre_wave_b;
+    size_t sort_tab, pre_tile, pre_level;  // pre_level: kMaxLevels arrays
+    size_t total;
+};
+TabLayout tab_layout();
+
+// One partition phase launch.
+struct PartitionLaunch {
+    int phase;                 // 0 count+scanA, 1 splitA, 2 swapA, 3 splitB, 4 scanB, 5 swapB
+    TaskRef<PartSeg> tasks;    // table + work prefix of the phase
+    uint32_t work;             // work items (workgroups, or waves for splits)
+    uint32_t TP;               // partition tile
+    uint32_t scan_threads;     // block size of the scans
+    double keys_total;         // keys in all ranges (byte figures)
+    double bytes;              // algorithmic bytes of the launch (swap A)
+    const Workspace *ws;
 };
 
-hipError_t launch_tile_sort(int dt, bool pairs, uint32_t *keys, uint32_t *vals, uint64_t src,
-                            uint64_t dst, uint64_t m, bool swap, hipStream_t st);
-hipError_t launch_merge_level(int dt, bool pairs, uint32_t *keys, uint32_t *vals, uint64_t src,
-                              uint64_t dst, uint64_t m, uint64_t W, uint32_t *splits,
-                              hipStream_t st);
-hipError_t run_partition(int dt, bool pairs, uint32_t *keys, uint32_t *vals, uint64_t lo,
-                         uint64_t hi, const Workspace &ws, PartitionResult *res,
-                         hipStream_t st);
+hipError_t launch_partition_phase(int dt, bool pairs, const PartitionLaunch &L, hipStream_t st);
+hipError_t launch_tile_sort(int dt, bool pairs, const TaskRef<SortSeg> &tasks, uint32_t tiles,
+                            double bytes, hipStream_t st);
+hipError_t launch_merge_level(int dt, bool pairs, const TaskRef<SortSeg> &tasks, uint32_t level,
+                              uint32_t tiles, double bytes, uint32_t *splits, hipStream_t st);
 
 }  // namespace qms

@@ -21,6 +21,7 @@
 // Ties go to the left run.
 #include "qms_device.hpp"
 #include "qms_internal.hpp"
+#include "qms_prof.hpp"
 
 namespace qms {
 
@@ -66,17 +67,32 @@ __device__ __forceinline__ MergeTileGeom merge_geom(uint64_t m, uint64_t W, uint
     return g;
 }
 
-// One wave per tile: the merge-path split at the tile's first output.
+// Regions of a merge level: the base case leaves the runs in R0 (the buffer
+// when the level count is odd, the data region otherwise); level l reads
+// R(l mod 2) and writes the other region, so the last level ends in D.
+__device__ __forceinline__ void level_regions(const SortSeg &g, uint32_t level, uint32_t *src,
+                                              uint32_t *dst) {
+    const bool odd = (g.L & 1u) != 0;
+    const uint32_t r0 = odd ? g.Bf : g.D, r1 = odd ? g.D : g.Bf;
+    *src = (level & 1u) ? r1 : r0;
+    *dst = (level & 1u) ? r0 : r1;
+}
+
+// One wave per merge tile: the merge-path split at the tile's first output.
 template <class O>
-__global__ __launch_bounds__(kBlock) void k_merge_split(const uint32_t *keys, uint64_t src,
-                                                        uint64_t m, uint64_t W,
-                                                        uint64_t ntiles, uint32_t *splits) {
-    const uint64_t tile = (uint64_t)blockIdx.x * kWaves + wave_id();
-    if (tile >= ntiles) return;
-    const MergeTileGeom g = merge_geom(m, W, tile);
-    const uint32_t *A = keys + src + g.pb;
-    const uint64_t i = merge_path_wave<O>(A, g.lenA, A + W, g.lenB, g.d0);
-    if (lane_id() == 0) splits[tile] = (uint32_t)i;
+__global__ __launch_bounds__(kBlock) void k_merge_split(TaskRef<SortSeg> tasks, uint32_t level,
+                                                        uint32_t total, uint32_t *splits) {
+    const uint32_t w = blockIdx.x * kWaves + wave_id();
+    if (w >= total) return;
+    uint32_t tile, a;
+    const SortSeg g = task_of(tasks, w, &tile, &a);
+    uint32_t src, dst;
+    level_regions(g, level, &src, &dst);
+    const uint64_t W = (uint64_t)kBaseTile << level;
+    const MergeTileGeom geo = merge_geom(g.m, W, tile);
+    const uint32_t *A = g.keys + src + geo.pb;
+    const uint64_t i = merge_path_wave<O>(A, geo.lenA, A + W, geo.lenB, geo.d0);
+    if (lane_id() == 0) splits[g.split_off + tile] = (uint32_t)i;
 }
 
 template <class O, bool PAIRS>
@@ -180,35 +196,43 @@ __device__ __forceinline__ void merge_block(uint32_t *S, uint32_t *SV, uint32_t 
 }
 
 template <class O, bool PAIRS>
-__global__ __launch_bounds__(kBlock) void k_merge(uint32_t *keys, uint32_t *vals, uint64_t src,
-                                                  uint64_t dst, uint64_t m, uint64_t W,
+__global__ __launch_bounds__(kBlock) void k_merge(TaskRef<SortSeg> tasks, uint32_t level,
                                                   const uint32_t *splits) {
-    if ((uint64_t)blockIdx.x * kMergeTile >= m) return;
-    merge_block<O, PAIRS>(keys + src, PAIRS ? vals + src : nullptr, keys + dst,
-                          PAIRS ? vals + dst : nullptr, m, W, blockIdx.x, splits);
+    uint32_t tile, a;
+    const SortSeg g = task_of(tasks, blockIdx.x, &tile, &a);
+    if (tile * (uint64_t)kMergeTile >= g.m) return;
+    uint32_t src, dst;
+    level_regions(g, level, &src, &dst);
+    merge_block<O, PAIRS>(g.keys + src, PAIRS ? g.vals + src : nullptr, g.keys + dst,
+                          PAIRS ? g.vals + dst : nullptr, g.m, (uint64_t)kBaseTile << level,
+                          tile, splits + g.split_off);
 }
 
 template <class O, bool PAIRS>
-static hipError_t merge_t(uint32_t *keys, uint32_t *vals, uint64_t src, uint64_t dst,
-                          uint64_t m, uint64_t W, uint32_t *splits, hipStream_t st) {
-    if (m == 0) return hipSuccess;
-    const uint64_t nt = (m + kMergeTile - 1) / kMergeTile;
-    hipLaunchKernelGGL((k_merge_split<O>), dim3((uint32_t)((nt + kWaves - 1) / kWaves)),
-                       dim3(kBlock), 0, st, keys, src, m, W, nt, splits);
-    hipLaunchKernelGGL((k_merge<O, PAIRS>), dim3((uint32_t)nt), dim3(kBlock), 0, st, keys, vals,
-                       src, dst, m, W, (const uint32_t *)splits);
+static hipError_t merge_t(const TaskRef<SortSeg> &tasks, uint32_t level, uint32_t tiles,
+                          double bytes, uint32_t *splits, hipStream_t st) {
+    if (tiles == 0) return hipSuccess;
+    {
+        ProfScope prof(st, K_MERGE_SPLIT, 0.0);
+        hipLaunchKernelGGL((k_merge_split<O>), dim3((tiles + kWaves - 1) / kWaves), dim3(kBlock),
+                           0, st, tasks, level, tiles, splits);
+    }
+    {
+        // per element: read the run cell and the window cell, write both
+        ProfScope prof(st, K_MERGE, bytes);
+        hipLaunchKernelGGL((k_merge<O, PAIRS>), dim3(tiles), dim3(kBlock), 0, st, tasks, level,
+                           (const uint32_t *)splits);
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_merge_level(int dt, bool pairs, uint32_t *keys, uint32_t *vals, uint64_t src,
-                              uint64_t dst, uint64_t m, uint64_t W, uint32_t *splits,
-                              hipStream_t st) {
-    if (m > (uint64_t)kMaxSplits * kMergeTile) return hipErrorInvalidValue;
+hipError_t launch_merge_level(int dt, bool pairs, const TaskRef<SortSeg> &tasks, uint32_t level,
+                              uint32_t tiles, double bytes, uint32_t *splits, hipStream_t st) {
     if (dt == 1)
-        return pairs ? merge_t<OrdF32, true>(keys, vals, src, dst, m, W, splits, st)
-                     : merge_t<OrdF32, false>(keys, vals, src, dst, m, W, splits, st);
-    return pairs ? merge_t<OrdU32, true>(keys, vals, src, dst, m, W, splits, st)
-                 : merge_t<OrdU32, false>(keys, vals, src, dst, m, W, splits, st);
+        return pairs ? merge_t<OrdF32, true>(tasks, level, tiles, bytes, splits, st)
+                     : merge_t<OrdF32, false>(tasks, level, tiles, bytes, splits, st);
+    return pairs ? merge_t<OrdU32, true>(tasks, level, tiles, bytes, splits, st)
+                 : merge_t<OrdU32, false>(tasks, level, tiles, bytes, splits, st);
 }
 
 }  // namespace qms

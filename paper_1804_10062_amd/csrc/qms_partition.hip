@@ -33,23 +33,29 @@
 // second counting sweep: equal keys in the right region never move in pass A,
 // and pass A counts (atomically, per tile) the equal keys it moves in.
 //
-// Workspace: O(kMaxTiles) counters; positions are 32-bit offsets from lo.
+// All kernels serve every segment of a round at once (task tables, see
+// qms_device.hpp).  Workspace: per-tile counters and per-chunk boundaries of
+// fixed capacity; positions are 32-bit offsets from the segment base.
 #include "qms_device.hpp"
 #include "qms_internal.hpp"
+#include "qms_prof.hpp"
 
 namespace qms {
 
 // ---- count -------------------------------------------------------------------
+// One workgroup per tile: #(< p) and #(== p).  Tile 0 of a segment also
+// records the segment's pivot.
 template <class O>
-__global__ __launch_bounds__(kBlock) void k_part_count(const uint32_t *keys, uint64_t lo,
-                                                       uint64_t hi, uint32_t TP,
+__global__ __launch_bounds__(kBlock) void k_part_count(TaskRef<PartSeg> tasks, uint32_t TP,
                                                        uint32_t *cnt_lt, uint32_t *cnt_eq,
                                                        uint64_t *meta) {
     __shared__ uint32_t tmp[kWaves + 1];
-    const uint32_t p = pivot_of<O>(keys, lo, hi);
-    const uint64_t t = blockIdx.x;
-    const uint64_t ts = lo + t * TP;
-    const uint64_t te = ts + TP < hi ? ts + TP : hi;
+    uint32_t t, a;
+    const PartSeg g = task_of(tasks, blockIdx.x, &t, &a);
+    const uint32_t *keys = g.keys + g.lo;
+    const uint32_t p = pivot_of<O>(keys, 0, g.s);
+    const uint64_t ts = (uint64_t)t * TP;
+    const uint64_t te = ts + TP < g.s ? ts + TP : g.s;
     uint32_t lt = 0, eq = 0;
     for (uint64_t b = ts; b < te; b += kPartSub) {
 #pragma unroll
@@ -65,9 +71,9 @@ __global__ __launch_bounds__(kBlock) void k_part_count(const uint32_t *keys, uin
     lt = block_sum(lt, tmp);
     eq = block_sum(eq, tmp);
     if (threadIdx.x == 0) {
-        cnt_lt[t] = lt;
-        cnt_eq[t] = eq;
-        if (t == 0) meta[M_PIVOT] = p;
+        cnt_lt[g.tile_off + t] = lt;
+        cnt_eq[g.tile_off + t] = eq;
+        if (t == 0) meta[(uint64_t)g.slot * M_COUNT + M_PIVOT] = p;
     }
 }
 
@@ -120,16 +126,31 @@ __device__ __forceinline__ uint32_t scan_misplaced(uint32_t nt, F mis, uint32_t 
     return totL;
 }
 
+__device__ __forceinline__ const PartSeg &seg_by_index(const TaskRef<PartSeg> &r, uint32_t a) {
+    return r.A == 1 ? r.one : r.tab[a];
+}
+
 // ---- scan of pass A ----------------------------------------------------------
+// One workgroup per segment.  res[4 a + 0..2] = (#<p, #==p, pass-A pairs) for
+// the host.
 template <class O>
-__global__ __launch_bounds__(kScanThreads) void k_part_scan_a(
-    const uint32_t *keys, uint64_t lo, uint64_t hi, uint32_t TP, uint32_t nt,
-    const uint32_t *cnt_lt, const uint32_t *cnt_eq, uint32_t *preL, uint32_t *preR,
-    uint32_t *eqmv, uint32_t *spL, uint32_t *spR, uint64_t *meta) {
+__global__ void k_part_scan_a(TaskRef<PartSeg> tasks, uint32_t TP, const uint32_t *cnt_lt_all,
+                              const uint32_t *cnt_eq_all, uint32_t *preL_all,
+                              uint32_t *preR_all, uint32_t *eqmv_all, uint32_t *spL_all,
+                              uint32_t *spR_all, uint64_t *meta_all, uint32_t *res) {
     __shared__ uint32_t tmp[kScanThreads / kWave + 1];
     __shared__ uint64_t tmp64[kScanThreads / kWave + 1];
-    const uint32_t p = pivot_of<O>(keys, lo, hi);
-    const uint64_t s = hi - lo;
+    const PartSeg g = seg_by_index(tasks, blockIdx.x);
+    const uint32_t *keys = g.keys + g.lo;
+    const uint32_t *cnt_lt = cnt_lt_all + g.tile_off;
+    const uint32_t *cnt_eq = cnt_eq_all + g.tile_off;
+    uint32_t *preL = preL_all + g.tile_off + g.slot;
+    uint32_t *preR = preR_all + g.tile_off + g.slot;
+    uint32_t *eqmv = eqmv_all + g.tile_off;
+    uint64_t *meta = meta_all + (uint64_t)g.slot * M_COUNT;
+    const uint32_t nt = g.nt;
+    const uint64_t s = g.s;
+    const uint32_t p = pivot_of<O>(keys, 0, s);
     uint64_t slt = 0, seq = 0;
     for (uint32_t t = threadIdx.x; t < nt; t += blockDim.x) {
         slt += cnt_lt[t];
@@ -140,8 +161,7 @@ __global__ __launch_bounds__(kScanThreads) void k_part_scan_a(
     const uint64_t c_eq = block_sum(seq, tmp64);
     const uint64_t tb = c_lt / TP;  // tile holding B1 (tb < nt since c_lt < s)
     uint32_t lt_part = 0, eq_part = 0;
-    if (c_lt % TP != 0)
-        block_count_range<O>(keys, lo + tb * TP, lo + c_lt, p, &lt_part, &eq_part, tmp);
+    if (c_lt % TP != 0) block_count_range<O>(keys, tb * TP, c_lt, p, &lt_part, &eq_part, tmp);
     auto mis = [&](uint32_t t, uint32_t *l, uint32_t *r) {
         const uint64_t ts = (uint64_t)t * TP;
         const uint32_t sz = (uint32_t)((ts + TP < s ? ts + TP : s) - ts);
@@ -158,7 +178,9 @@ __global__ __launch_bounds__(kScanThreads) void k_part_scan_a(
     };
     const uint32_t X = scan_misplaced(nt, mis, preL, preR, tmp);
     if (threadIdx.x == 0) {
-        const uint32_t nch = (X + kRankChunk - 1) / kRankChunk;
+        const uint32_t nch = (uint32_t)chunk_count(X, s);
+        uint32_t *spL = spL_all + g.chunk_off, *spR = spR_all + g.chunk_off;
+        meta[M_RCA] = rank_chunk(X, s);
         meta[M_PIVOT] = p;
         meta[M_CLT] = c_lt;
         meta[M_CEQ] = c_eq;
@@ -171,30 +193,46 @@ __global__ __launch_bounds__(kScanThreads) void k_part_scan_a(
         spL[nch] = (uint32_t)c_lt;
         spR[0] = (uint32_t)c_lt;
         spR[nch] = (uint32_t)s;
+        res[4 * blockIdx.x + 0] = (uint32_t)c_lt;
+        res[4 * blockIdx.x + 1] = (uint32_t)c_eq;
+        res[4 * blockIdx.x + 2] = X;
+        res[4 * blockIdx.x + 3] = 0;
     }
 }
 
 // ---- scan of pass B ----------------------------------------------------------
-// After pass A, [B1, hi) holds only keys >= p.  The keys == p of a tile's part
+// After pass A, [B1, s) holds only keys >= p.  The keys == p of a tile's part
 // right of B1 are the ones it held before (they did not move) plus the ones
-// pass A moved in (eqmv).
+// pass A moved in (eqmv).  One workgroup per segment; segments without
+// possible pass-B pairs return at once.
 template <class O>
-__global__ __launch_bounds__(kScanThreads) void k_part_scan_b(
-    const uint32_t *keys, uint64_t lo, uint64_t hi, uint32_t TP, uint32_t nt,
-    const uint32_t *cnt_eq, const uint32_t *eqmv, uint32_t *preL, uint32_t *preR,
-    uint32_t *spL, uint32_t *spR, uint64_t *meta) {
+__global__ void k_part_scan_b(TaskRef<PartSeg> tasks, uint32_t TP, const uint32_t *cnt_eq_all,
+                              const uint32_t *eqmv_all, uint32_t *preL_all, uint32_t *preR_all,
+                              uint32_t *spL_all, uint32_t *spR_all, uint64_t *meta_all) {
     __shared__ uint32_t tmp[kScanThreads / kWave + 1];
-    const uint32_t p = (uint32_t)meta[M_PIVOT];
-    const uint64_t s = hi - lo;
+    const PartSeg g = seg_by_index(tasks, blockIdx.x);
+    uint64_t *meta = meta_all + (uint64_t)g.slot * M_COUNT;
+    const uint64_t s = g.s;
     const uint64_t b1 = meta[M_CLT];
     const uint64_t b2 = b1 + meta[M_CEQ];
+    if (b2 >= s || b2 == b1) {
+        if (threadIdx.x == 0) meta[M_XB] = 0;
+        return;
+    }
+    const uint32_t *keys = g.keys + g.lo;
+    const uint32_t *cnt_eq = cnt_eq_all + g.tile_off;
+    const uint32_t *eqmv = eqmv_all + g.tile_off;
+    uint32_t *preL = preL_all + g.tile_off + g.slot;
+    uint32_t *preR = preR_all + g.tile_off + g.slot;
+    const uint32_t nt = g.nt;
+    const uint32_t p = (uint32_t)meta[M_PIVOT];
     const uint64_t tb = meta[M_TB];
     const uint32_t eq_part = (uint32_t)meta[M_EQPART];
     const uint64_t tb2 = b2 / TP;
     uint32_t eq_part2 = 0, dummy = 0;
     if (b2 % TP != 0 && tb2 < nt) {
         const uint64_t a = tb2 * TP > b1 ? tb2 * TP : b1;
-        block_count_range<O>(keys, lo + a, lo + b2, p, &dummy, &eq_part2, tmp);
+        block_count_range<O>(keys, a, b2, p, &dummy, &eq_part2, tmp);
     }
     auto mis = [&](uint32_t t, uint32_t *l, uint32_t *r) {
         if (t < tb) {
@@ -215,7 +253,9 @@ __global__ __launch_bounds__(kScanThreads) void k_part_scan_b(
     };
     const uint32_t X = scan_misplaced(nt, mis, preL, preR, tmp);
     if (threadIdx.x == 0) {
-        const uint32_t nch = (X + kRankChunk - 1) / kRankChunk;
+        const uint32_t nch = (uint32_t)chunk_count(X, s);
+        uint32_t *spL = spL_all + g.chunk_off, *spR = spR_all + g.chunk_off;
+        meta[M_RCB] = rank_chunk(X, s);
         meta[M_XB] = X;
         spL[0] = (uint32_t)b1;
         spL[nch] = (uint32_t)b2;
@@ -224,8 +264,9 @@ __global__ __launch_bounds__(kScanThreads) void k_part_scan_b(
     }
 }
 
-// Left region and right region of a pass, as offsets from lo, and the class
-// test: an element belongs left if ord(k) < p (pass A) or ord(k) <= p (B).
+// Left region and right region of a pass, as offsets from the range start,
+// and the class test: an element belongs left if ord(k) < p (pass A) or
+// ord(k) <= p (pass B).
 struct PassGeom {
     uint64_t l0, l1, r0, r1;
 };
@@ -253,50 +294,60 @@ __device__ __forceinline__ bool belongs_left(uint32_t k, uint32_t p) {
 }
 
 // ---- split: position of the first misplaced element of every chunk ----------
+// One wave per (chunk boundary j >= 1, side).  The host gives each segment an
+// upper bound of 2 (chunks - 1) waves; surplus waves return.
 template <class O, int PASS>
-__global__ __launch_bounds__(kBlock) void k_part_split(const uint32_t *keys, uint64_t lo,
-                                                       uint64_t hi, uint32_t TP, uint32_t nt,
-                                                       const uint32_t *preL,
-                                                       const uint32_t *preR, uint32_t *spL,
-                                                       uint32_t *spR, const uint64_t *meta) {
-    const uint64_t w = (uint64_t)blockIdx.x * kWaves + wave_id();
+__global__ __launch_bounds__(kBlock) void k_part_split(TaskRef<PartSeg> tasks, uint32_t TP,
+                                                       uint32_t total, const uint32_t *preL_all,
+                                                       const uint32_t *preR_all,
+                                                       uint32_t *spL_all, uint32_t *spR_all,
+                                                       const uint64_t *meta_all) {
+    const uint32_t gw = blockIdx.x * kWaves + wave_id();
+    if (gw >= total) return;
+    uint32_t w, a;
+    const PartSeg g = task_of(tasks, gw, &w, &a);
+    const uint64_t *meta = meta_all + (uint64_t)g.slot * M_COUNT;
     const uint32_t X = (uint32_t)meta[PASS == 0 ? M_XA : M_XB];
-    const uint32_t nch = (X + kRankChunk - 1) / kRankChunk;
+    const uint32_t rc = (uint32_t)meta[PASS == 0 ? M_RCA : M_RCB];
+    if (X == 0) return;
+    const uint32_t nch = (X + rc - 1) / rc;
     const uint64_t j = 1 + w / 2;
     const int side = (int)(w & 1);
     if (j >= nch) return;
+    const uint32_t *keys = g.keys + g.lo;
+    const uint32_t nt = g.nt;
     const uint32_t p = (uint32_t)meta[M_PIVOT];
-    const uint64_t s = hi - lo;
-    const PassGeom g = pass_geom<PASS>(meta, s);
-    const uint32_t *pre = side ? preR : preL;
-    const uint32_t r = (uint32_t)(j * kRankChunk);
+    const uint64_t s = g.s;
+    const PassGeom geo = pass_geom<PASS>(meta, s);
+    const uint32_t *pre = (side ? preR_all : preL_all) + g.tile_off + g.slot;
+    const uint32_t r = (uint32_t)(j * rc);
     // largest t with pre[t] <= r (pre[0] = 0 <= r < pre[nt] = X)
-    uint32_t a = 0, b = nt;
-    while (b - a > 1) {
-        const uint32_t mid = (a + b) >> 1;
-        if (pre[mid] <= r) a = mid;
-        else b = mid;
+    uint32_t lo = 0, hi = nt;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (pre[mid] <= r) lo = mid;
+        else hi = mid;
     }
-    const uint32_t t = a;
+    const uint32_t t = lo;
     uint32_t k = r - pre[t];
     const uint64_t ts = (uint64_t)t * TP;
     const uint64_t te = ts + TP < s ? ts + TP : s;
-    const uint64_t reg0 = side ? g.r0 : g.l0, reg1 = side ? g.r1 : g.l1;
+    const uint64_t reg0 = side ? geo.r0 : geo.l0, reg1 = side ? geo.r1 : geo.l1;
     const uint64_t x0 = ts > reg0 ? ts : reg0;
     const uint64_t x1 = te < reg1 ? te : reg1;
     const int lane = lane_id();
+    uint32_t *sp = (side ? spR_all : spL_all) + g.chunk_off;
     for (uint64_t base = x0; base < x1; base += kWave) {
         const uint64_t pos = base + lane;
         bool f = false;
         if (pos < x1) {
-            const bool bl = belongs_left<PASS>(O::ord(keys[lo + pos]), p);
+            const bool bl = belongs_left<PASS>(O::ord(keys[pos]), p);
             f = side ? bl : !bl;
         }
         const uint64_t mask = __ballot(f);
         const uint32_t c = (uint32_t)__popcll(mask);
         if (k < c) {
-            if (f && (uint32_t)__popcll(mask & lanemask_lt()) == k)
-                (side ? spR : spL)[j] = (uint32_t)pos;
+            if (f && (uint32_t)__popcll(mask & lanemask_lt()) == k) sp[j] = (uint32_t)pos;
             return;
         }
         k -= c;
@@ -304,17 +355,34 @@ __global__ __launch_bounds__(kBlock) void k_part_split(const uint32_t *keys, uin
 }
 
 // ---- swap ------------------------------------------------------------------------
-// Compact the misplaced elements of positions [a, b) (offsets from lo) into
-// the LDS slots 0.. in position order.
+// Compact the misplaced elements of positions [a, b) (offsets from the range
+// start) into the LDS slots 0.. in position order.  Tiles whose prefix counts
+// show no misplaced element on this side are skipped without being read.
 template <class O, bool PAIRS, int PASS>
 __device__ __forceinline__ uint32_t collect_misplaced(const uint32_t *keys, const uint32_t *vals,
-                                                      uint64_t lo, uint64_t a, uint64_t b,
-                                                      uint32_t p, bool right, uint32_t *sk,
-                                                      uint32_t *sv, uint32_t *sp,
+                                                      uint64_t a, uint64_t b, uint32_t p,
+                                                      bool right, const uint32_t *pre,
+                                                      uint32_t TP, uint32_t nt, uint32_t cap,
+                                                      uint32_t *sk, uint32_t *sv, uint32_t *sp,
                                                       uint32_t *wtot) {
     const int lane = lane_id(), wave = wave_id();
     uint32_t running = 0;
     for (uint64_t base = a; base < b; base += kPartSub) {
+        const uint64_t t = base / TP;
+        const uint32_t pt = pre[t];
+        if (pre[t + 1] == pt) {
+            // nothing to collect in tile t: jump to the first later tile whose
+            // prefix count grows (binary search; pre is non-decreasing)
+            uint64_t x = t + 1, y = nt;  // first i in (t, nt] with pre[i] > pt
+            while (x < y) {
+                const uint64_t mid = (x + y) >> 1;
+                if (pre[mid] > pt) y = mid;
+                else x = mid + 1;
+            }
+            const uint64_t next = (x - 1) * TP;  // tile x - 1 holds the next element
+            base = (next > base ? next : base + kPartSub) - kPartSub;
+            continue;
+        }
         uint32_t kk[kPartItems];
         uint64_t m[kPartItems];
         uint32_t wcount = 0;
@@ -324,7 +392,7 @@ __device__ __forceinline__ uint32_t collect_misplaced(const uint32_t *keys, cons
                                  (uint64_t)q * kWave + lane;
             bool f = false;
             if (pos < b) {
-                kk[q] = keys[lo + pos];
+                kk[q] = keys[pos];
                 const bool bl = belongs_left<PASS>(O::ord(kk[q]), p);
                 f = right ? bl : !bl;
             }
@@ -343,12 +411,13 @@ __device__ __forceinline__ uint32_t collect_misplaced(const uint32_t *keys, cons
         for (int q = 0; q < kPartItems; ++q) {
             if ((m[q] >> lane) & 1ull) {
                 const uint32_t slot = woff + (uint32_t)__popcll(m[q] & lanemask_lt());
-                if (slot >= (uint32_t)kRankChunk) continue;  // never with consistent counts
-                const uint64_t pos = base + (uint64_t)wave * (kPartItems * kWave) +
-                                     (uint64_t)q * kWave + lane;
-                sk[slot] = kk[q];
-                sp[slot] = (uint32_t)pos;
-                if constexpr (PAIRS) sv[slot] = vals[lo + pos];
+                if (slot < cap) {  // always true with consistent counts
+                    const uint64_t pos = base + (uint64_t)wave * (kPartItems * kWave) +
+                                         (uint64_t)q * kWave + lane;
+                    sk[slot] = kk[q];
+                    sp[slot] = (uint32_t)pos;
+                    if constexpr (PAIRS) sv[slot] = vals[pos];
+                }
             }
             woff += (uint32_t)__popcll(m[q]);
         }
@@ -358,102 +427,124 @@ __device__ __forceinline__ uint32_t collect_misplaced(const uint32_t *keys, cons
     return running;
 }
 
+// One workgroup per chunk: exchange the chunk's misplaced elements.
 template <class O, bool PAIRS, int PASS>
-__global__ __launch_bounds__(kBlock) void k_part_swap(uint32_t *keys, uint32_t *vals,
-                                                      uint64_t lo, uint64_t hi, uint32_t TP,
-                                                      const uint32_t *spL,
-                                                      const uint32_t *spR, uint32_t *eqmv,
-                                                      const uint64_t *meta) {
+__global__ __launch_bounds__(kBlock) void k_part_swap(TaskRef<PartSeg> tasks, uint32_t TP,
+                                                      const uint32_t *preL_all,
+                                                      const uint32_t *preR_all,
+                                                      const uint32_t *spL_all,
+                                                      const uint32_t *spR_all,
+                                                      uint32_t *eqmv_all,
+                                                      const uint64_t *meta_all) {
     __shared__ uint32_t kL[kRankChunk], kR[kRankChunk], pL[kRankChunk], pR[kRankChunk];
     __shared__ uint32_t vL[PAIRS ? kRankChunk : 1], vR[PAIRS ? kRankChunk : 1];
     __shared__ uint32_t wtot[kWaves];
+    uint32_t j, a;
+    const PartSeg g = task_of(tasks, blockIdx.x, &j, &a);
+    const uint64_t *meta = meta_all + (uint64_t)g.slot * M_COUNT;
     const uint32_t X = (uint32_t)meta[PASS == 0 ? M_XA : M_XB];
-    const uint32_t nch = (X + kRankChunk - 1) / kRankChunk;
-    const uint32_t j = blockIdx.x;
+    const uint32_t rc = (uint32_t)meta[PASS == 0 ? M_RCA : M_RCB];
+    if (X == 0) return;
+    const uint32_t nch = (X + rc - 1) / rc;
     if (j >= nch) return;
+    uint32_t *keys = g.keys + g.lo;
+    uint32_t *vals = PAIRS ? g.vals + g.lo : nullptr;
     const uint32_t p = (uint32_t)meta[M_PIVOT];
-    const uint32_t r0 = j * kRankChunk;
-    uint32_t cnt = X - r0 < (uint32_t)kRankChunk ? X - r0 : (uint32_t)kRankChunk;
+    const uint32_t r0 = j * rc;
+    uint32_t cnt = X - r0 < rc ? X - r0 : rc;
+    const uint32_t *spL = spL_all + g.chunk_off, *spR = spR_all + g.chunk_off;
+    const uint32_t *preL = preL_all + g.tile_off + g.slot;
+    const uint32_t *preR = preR_all + g.tile_off + g.slot;
     // position ranges of this chunk, clamped to the pass's regions
-    const PassGeom g = pass_geom<PASS>(meta, hi - lo);
-    const uint64_t la = spL[j] > g.l0 ? spL[j] : g.l0, lb = spL[j + 1] < g.l1 ? spL[j + 1] : g.l1;
-    const uint64_t ra = spR[j] > g.r0 ? spR[j] : g.r0, rb = spR[j + 1] < g.r1 ? spR[j + 1] : g.r1;
-    const uint32_t nl = collect_misplaced<O, PAIRS, PASS>(keys, vals, lo, la, lb, p, false, kL,
-                                                          vL, pL, wtot);
-    const uint32_t nr = collect_misplaced<O, PAIRS, PASS>(keys, vals, lo, ra, rb, p, true, kR,
-                                                          vR, pR, wtot);
-    // equal by construction; the minimum keeps every write inside the slots filled
+    const PassGeom geo = pass_geom<PASS>(meta, g.s);
+    const uint64_t la = spL[j] > geo.l0 ? spL[j] : geo.l0;
+    const uint64_t lb = spL[j + 1] < geo.l1 ? spL[j + 1] : geo.l1;
+    const uint64_t ra = spR[j] > geo.r0 ? spR[j] : geo.r0;
+    const uint64_t rb = spR[j + 1] < geo.r1 ? spR[j + 1] : geo.r1;
+    const uint32_t nl = collect_misplaced<O, PAIRS, PASS>(keys, vals, la, lb, p, false, preL, TP,
+                                                          g.nt, kRankChunk, kL, vL, pL, wtot);
+    const uint32_t nr = collect_misplaced<O, PAIRS, PASS>(keys, vals, ra, rb, p, true, preR, TP,
+                                                          g.nt, kRankChunk, kR, vR, pR, wtot);
+    // equal by construction; the minimum keeps every write inside the filled slots
     cnt = min(cnt, min(nl, nr));
+    uint32_t *eqmv = eqmv_all + g.tile_off;
     for (uint32_t k = threadIdx.x; k < cnt; k += kBlock) {
-        const uint32_t a = kL[k], b = kR[k];
-        keys[lo + pL[k]] = b;
-        keys[lo + pR[k]] = a;
+        const uint32_t x = kL[k], y = kR[k];
+        keys[pL[k]] = y;
+        keys[pR[k]] = x;
         if constexpr (PAIRS) {
-            vals[lo + pL[k]] = vR[k];
-            vals[lo + pR[k]] = vL[k];
+            vals[pL[k]] = vR[k];
+            vals[pR[k]] = vL[k];
         }
-        if (PASS == 0 && O::ord(a) == p) atomicAdd(&eqmv[pR[k] / TP], 1u);
+        if (PASS == 0 && O::ord(x) == p) atomicAdd(&eqmv[pR[k] / TP], 1u);
     }
 }
 
 // ---- host side ---------------------------------------------------------------------
 template <class O, bool PAIRS>
-static hipError_t partition_t(uint32_t *keys, uint32_t *vals, uint64_t lo, uint64_t hi,
-                              const Workspace &ws, PartitionResult *res, hipStream_t st) {
-    const uint64_t s = hi - lo;
-    uint32_t TP = kPartSub;
-    while ((s + TP - 1) / TP > kMaxTiles) TP *= 2;
-    const uint32_t nt = (uint32_t)((s + TP - 1) / TP);
-    hipLaunchKernelGGL((k_part_count<O>), dim3(nt), dim3(kBlock), 0, st, keys, lo, hi, TP,
-                       ws.cnt_lt, ws.cnt_eq, ws.meta);
-    hipLaunchKernelGGL((k_part_scan_a<O>), dim3(1), dim3(kScanThreads), 0, st, keys, lo, hi, TP,
-                       nt, ws.cnt_lt, ws.cnt_eq, ws.preL, ws.preR, ws.eqmv, ws.spL, ws.spR,
-                       ws.meta);
-    hipError_t e = hipMemcpyAsync(ws.h_meta, ws.meta, sizeof(uint64_t) * M_COUNT,
-                                  hipMemcpyDeviceToHost, st);
-    if (e != hipSuccess) return e;
-    e = hipStreamSynchronize(st);
-    if (e != hipSuccess) return e;
-    const uint64_t c_lt = ws.h_meta[M_CLT], c_eq = ws.h_meta[M_CEQ];
-    const uint64_t XA = ws.h_meta[M_XA];
-    if (XA > 0) {
-        const uint64_t nch = (XA + kRankChunk - 1) / kRankChunk;
-        if (nch > 1)
-            hipLaunchKernelGGL((k_part_split<O, 0>), dim3((uint32_t)(((nch - 1) * 2 + kWaves - 1) / kWaves)),
-                               dim3(kBlock), 0, st, keys, lo, hi, TP, nt, ws.preL, ws.preR,
-                               ws.spL, ws.spR, ws.meta);
-        hipLaunchKernelGGL((k_part_swap<O, PAIRS, 0>), dim3((uint32_t)nch), dim3(kBlock), 0, st,
-                           keys, vals, lo, hi, TP, ws.spL, ws.spR, ws.eqmv, ws.meta);
+static hipError_t partition_t(const PartitionLaunch &L, hipStream_t st) {
+    const Workspace &ws = *L.ws;
+    switch (L.phase) {
+    case 0: {  // count + scan A
+        {
+            ProfScope prof(st, K_PART_COUNT, 4.0 * (double)L.keys_total);
+            hipLaunchKernelGGL((k_part_count<O>), dim3(L.work), dim3(kBlock), 0, st, L.tasks,
+                               L.TP, ws.cnt_lt, ws.cnt_eq, ws.meta);
+        }
+        {
+            ProfScope prof(st, K_PART_SCAN, 0.0);
+            hipLaunchKernelGGL((k_part_scan_a<O>), dim3(L.tasks.A), dim3(L.scan_threads), 0, st,
+                               L.tasks, L.TP, ws.cnt_lt, ws.cnt_eq, ws.preL, ws.preR, ws.eqmv,
+                               ws.spL, ws.spR, ws.meta, ws.res);
+        }
+        break;
     }
-    const uint64_t gt = s - c_lt - c_eq;
-    const uint64_t xb_max = c_eq < gt ? c_eq : gt;
-    if (xb_max > 0) {
-        hipLaunchKernelGGL((k_part_scan_b<O>), dim3(1), dim3(kScanThreads), 0, st, keys, lo, hi,
-                           TP, nt, ws.cnt_eq, ws.eqmv, ws.preL, ws.preR, ws.spL, ws.spR,
+    case 1:    // split of pass A
+    case 3: {  // split of pass B
+        if (L.work == 0) break;
+        ProfScope prof(st, K_PART_SPLIT, 0.0);
+        if (L.phase == 1)
+            hipLaunchKernelGGL((k_part_split<O, 0>), dim3((L.work + kWaves - 1) / kWaves),
+                               dim3(kBlock), 0, st, L.tasks, L.TP, L.work, ws.preL, ws.preR,
+                               ws.spL, ws.spR, ws.meta);
+        else
+            hipLaunchKernelGGL((k_part_split<O, 1>), dim3((L.work + kWaves - 1) / kWaves),
+                               dim3(kBlock), 0, st, L.tasks, L.TP, L.work, ws.preL, ws.preR,
+                               ws.spL, ws.spR, ws.meta);
+        break;
+    }
+    case 2: {  // swap of pass A
+        if (L.work == 0) break;
+        ProfScope prof(st, K_PART_SWAP, L.bytes);
+        hipLaunchKernelGGL((k_part_swap<O, PAIRS, 0>), dim3(L.work), dim3(kBlock), 0, st,
+                           L.tasks, L.TP, ws.preL, ws.preR, ws.spL, ws.spR, ws.eqmv, ws.meta);
+        break;
+    }
+    case 4: {  // scan B
+        ProfScope prof(st, K_PART_SCAN, 0.0);
+        hipLaunchKernelGGL((k_part_scan_b<O>), dim3(L.tasks.A), dim3(L.scan_threads), 0, st,
+                           L.tasks, L.TP, ws.cnt_eq, ws.eqmv, ws.preL, ws.preR, ws.spL, ws.spR,
                            ws.meta);
-        const uint64_t nch = (xb_max + kRankChunk - 1) / kRankChunk;
-        if (nch > 1)
-            hipLaunchKernelGGL((k_part_split<O, 1>), dim3((uint32_t)(((nch - 1) * 2 + kWaves - 1) / kWaves)),
-                               dim3(kBlock), 0, st, keys, lo, hi, TP, nt, ws.preL, ws.preR,
-                               ws.spL, ws.spR, ws.meta);
-        hipLaunchKernelGGL((k_part_swap<O, PAIRS, 1>), dim3((uint32_t)nch), dim3(kBlock), 0, st,
-                           keys, vals, lo, hi, TP, ws.spL, ws.spR, ws.eqmv, ws.meta);
+        break;
     }
-    res->pivot = ws.h_meta[M_PIVOT];
-    res->c_lt = c_lt;
-    res->c_eq = c_eq;
-    res->x_a = XA;
+    case 5: {  // swap of pass B
+        if (L.work == 0) break;
+        // pass B's pair count is known only on the device: no byte figure
+        ProfScope prof(st, K_PART_SWAP, 0.0);
+        hipLaunchKernelGGL((k_part_swap<O, PAIRS, 1>), dim3(L.work), dim3(kBlock), 0, st,
+                           L.tasks, L.TP, ws.preL, ws.preR, ws.spL, ws.spR, ws.eqmv, ws.meta);
+        break;
+    }
+    default:
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
-hipError_t run_partition(int dt, bool pairs, uint32_t *keys, uint32_t *vals, uint64_t lo,
-                         uint64_t hi, const Workspace &ws, PartitionResult *res,
-                         hipStream_t st) {
+hipError_t launch_partition_phase(int dt, bool pairs, const PartitionLaunch &L, hipStream_t st) {
     if (dt == 1)
-        return pairs ? partition_t<OrdF32, true>(keys, vals, lo, hi, ws, res, st)
-                     : partition_t<OrdF32, false>(keys, vals, lo, hi, ws, res, st);
-    return pairs ? partition_t<OrdU32, true>(keys, vals, lo, hi, ws, res, st)
-                 : partition_t<OrdU32, false>(keys, vals, lo, hi, ws, res, st);
+        return pairs ? partition_t<OrdF32, true>(L, st) : partition_t<OrdF32, false>(L, st);
+    return pairs ? partition_t<OrdU32, true>(L, st) : partition_t<OrdU32, false>(L, st);
 }
 
 }  // namespace qms

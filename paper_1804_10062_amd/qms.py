@@ -13,7 +13,8 @@ import os
 from typing import Optional
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libqms.so")
+# QMS_LIBRARY may point at another build of the same library (tuning runs)
+LIB_PATH = os.environ.get("QMS_LIBRARY") or os.path.join(PKG, "libqms.so")
 
 QMS_U32 = 0
 QMS_F32 = 1
@@ -33,7 +34,7 @@ EXPORTS = (
     "qms_server_create", "qms_server_submit", "qms_server_poll",
     "qms_server_get_stats", "qms_server_destroy",
     "qms_last_error", "qms_release_workspaces", "qms_last_schedule",
-    "qms_get_tiles",
+    "qms_get_tiles", "qms_profile_begin", "qms_profile_end",
 )
 
 
@@ -52,6 +53,11 @@ class ServerStats(ctypes.Structure):
     _fields_ = [("completed", ctypes.c_uint64), ("completed_keys", ctypes.c_uint64),
                 ("peak_admitted_bytes", ctypes.c_uint64),
                 ("waited_for_budget", ctypes.c_uint64), ("batches", ctypes.c_uint64)]
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_uint64),
+                ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
 _lib = None
@@ -94,6 +100,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.qms_last_schedule.restype = u64
     lib.qms_get_tiles.argtypes = [u32p, u32p, u32p]
     lib.qms_get_tiles.restype = None
+    lib.qms_profile_begin.argtypes = []
+    lib.qms_profile_begin.restype = i32
+    lib.qms_profile_end.argtypes = [ctypes.POINTER(KernelStat), i32, ctypes.POINTER(i32)]
+    lib.qms_profile_end.restype = i32
     _lib = lib
     return lib
 
@@ -192,6 +202,20 @@ def qms_get_tiles():
     a, b, c = ctypes.c_uint32(), ctypes.c_uint32(), ctypes.c_uint32()
     lib.qms_get_tiles(ctypes.byref(a), ctypes.byref(b), ctypes.byref(c))
     return {"base_tile": a.value, "merge_tile": b.value, "partition_tile": c.value}
+
+
+def qms_profile_begin() -> None:
+    _check(load_library().qms_profile_begin(), "qms_profile_begin")
+
+
+def qms_profile_end() -> dict:
+    """{class: {"launches", "total_ms", "bytes"}} for the sorts since begin."""
+    lib = load_library()
+    buf = (KernelStat * 16)()
+    n = ctypes.c_int()
+    _check(lib.qms_profile_end(buf, 16, ctypes.byref(n)), "qms_profile_end")
+    return {buf[i].name.decode(): {"launches": buf[i].launches, "total_ms": buf[i].total_ms,
+                                   "bytes": buf[i].bytes} for i in range(n.value)}
 
 
 def qms_release_workspaces() -> None:

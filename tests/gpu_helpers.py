@@ -77,3 +77,37 @@ def check_pairs_exact(keys_in: torch.Tensor, keys_out: torch.Tensor, vals_out: t
     seen.index_fill_(0, v, 1)
     assert int(seen.sum().item()) == n
     assert bool((as_u64(keys_in)[v] == as_u64(keys_out)).all().item())
+
+
+def segment_ids(offsets: torch.Tensor, n: int) -> torch.Tensor:
+    """Segment index of every position, from offsets (device int64)."""
+    lens = offsets[1:] - offsets[:-1]
+    return torch.repeat_interleave(torch.arange(lens.numel(), device=offsets.device), lens,
+                                   output_size=n)
+
+
+def segments_sorted(t: torch.Tensor, offsets: torch.Tensor) -> bool:
+    """Every segment non-decreasing (boundaries between segments ignored)."""
+    n = t.numel()
+    if n < 2:
+        return True
+    k = order_key(t)
+    ok = k[1:] >= k[:-1]
+    starts = offsets[1:-1]
+    starts = starts[(starts > 0) & (starts < n)]
+    ok[starts - 1] = True
+    return bool(ok.all().item())
+
+
+def segment_multiset_hash(t: torch.Tensor, seg: torch.Tensor) -> tuple:
+    """Order-independent hash of the (segment, word) multiset: equal only if
+    every segment kept its own multiset (up to hash collisions)."""
+    x = as_u64(t) ^ (seg.to(torch.int64) * _C3)
+    out = []
+    for a, b in ((_C1, _C2), (_C2, _C4)):
+        h = x * a
+        h = h ^ ((h >> 29) & ((1 << 35) - 1))
+        h = h * b
+        h = h ^ ((h >> 32) & 0xFFFFFFFF)
+        out.append(int(h.sum().item()))
+    return tuple(out)
