@@ -22,7 +22,11 @@ One JSON line goes to stdout with, besides the contract fields:
   cpu_baseline  the CPU oracle (single thread) on a bounded sample of the
                 same workload (the first 2^26 keys), in Gkeys/s;
   kernels       per-kernel-class launches, time and achieved GB/s;
-  distributions Gkeys/s of the three inputs.
+  distributions Gkeys/s of the three inputs;
+  batched       20,000 float32 arrays in one qms_sort_batch call against one
+                qms_sort call per array (a 1-in-10 sample of the arrays);
+  serving       open-loop Poisson request streams at 2k/10k/50k requests/s
+                through the library's server: throughput, p50/p99 latency.
 """
 from __future__ import annotations
 
@@ -53,6 +57,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-log2", type=int, default=26)
     ap.add_argument("--only-uniform", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--per-array-stride", type=int, default=10)
+    ap.add_argument("--serving-requests", type=int, default=3000)
     return ap.parse_args()
 
 
@@ -85,6 +93,123 @@ def time_sorts(copies, qms, torch, profile: bool):
     t1 = time.perf_counter()
     prof = qms.qms_profile_end() if profile else None
     return t1 - t0, prof
+
+
+def bench_batched(qms, torch, np, inputs, per_array_stride: int, reps: int = 3):
+    """20,000 arrays, lengths log-uniform in [2^6, 2^20] (seed 5), float32
+    N(0,1) keys drawn on the device: one qms_sort_batch call for all of them
+    against one qms_sort call per array (every `per_array_stride`-th array,
+    same kernels, same stream)."""
+    lens = inputs.log_uniform_lengths(20000, seed=5, lo_exp=6, hi_exp=20)
+    off = inputs.offsets_from_lengths(lens)
+    n = int(off[-1])
+    g = torch.Generator(device="cuda")
+    g.manual_seed(5)
+    src = torch.randn(n, generator=g, device="cuda", dtype=torch.float32)
+    src[src == 0] = 0.0
+    ot = torch.from_numpy(off.view(np.int64)).cuda()
+    work = src.clone()
+    times = []
+    for _ in range(reps + 1):
+        work.copy_(src)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        qms.qms_sort_batch(work, ot, host_offsets=off)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    from tests.gpu_helpers import segments_sorted
+    assert segments_sorted(work, ot), "batched output not sorted"
+    t_batch = min(times[1:])
+    work.copy_(src)
+    idx = list(range(0, lens.size, per_array_stride))
+    keys_sub = int(sum(int(lens[j]) for j in idx))
+    views = [work[int(off[j]):int(off[j + 1])] for j in idx]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for v in views:
+        qms.qms_sort(v)
+    torch.cuda.synchronize()
+    t_per = time.perf_counter() - t0
+    batched = n / t_batch / 1e9
+    per_array = keys_sub / t_per / 1e9
+    del work, src
+    return {
+        "workload": "20,000 float32 arrays, lengths log-uniform in [2^6, 2^20] (seed 5), "
+                    f"N(0,1) keys; {n} keys in all",
+        "batched_Gkeys_per_s": round(batched, 3),
+        "batched_ms": round(t_batch * 1e3, 2),
+        "per_array_Gkeys_per_s": round(per_array, 4),
+        "per_array_sample": f"every {per_array_stride}th array ({len(idx)} arrays, "
+                            f"{keys_sub} keys), one qms_sort call each",
+        "speedup": round(batched / per_array, 2),
+    }
+
+
+def bench_serving(qms, torch, np, inputs, loads, count: int, budget: int = 64 << 30):
+    """Open-loop Poisson arrivals of sort requests (sizes floor(2^(10+14u)),
+    uint32 or float32 with probability 1/2, uniform values) submitted to the
+    library's server; latency = completion - scheduled arrival."""
+    u = inputs.unit_f64(count, seed=7, stream=11)
+    sizes = np.floor(2.0 ** (10 + 14 * u)).astype(np.int64)
+    is_f = (inputs.uniform_u32(count, seed=7, stream=12) & 1).astype(bool)
+    off = np.zeros(count + 1, dtype=np.int64)
+    np.cumsum(sizes, out=off[1:])
+    total = int(off[-1])
+    pool_u = torch.empty(total, dtype=torch.int32, device="cuda")
+    pool_f = torch.empty(total, dtype=torch.float32, device="cuda")
+    views = [(pool_f if is_f[j] else pool_u)[int(off[j]):int(off[j + 1])] for j in range(count)]
+    out = {}
+    for rate in loads:
+        pool_u.random_(-(1 << 31), (1 << 31) - 1)
+        pool_f.uniform_(0.0, 1.0)
+        torch.cuda.synchronize()
+        arr = inputs.poisson_arrivals(count, float(rate), seed=100 + int(rate))
+        srv = qms.Server(hbm_budget_bytes=budget, device=0)
+        tickets = []
+        late = np.zeros(count)
+        t0 = time.perf_counter()
+        for j in range(count):
+            due = t0 + arr[j]
+            while True:
+                now = time.perf_counter()
+                if now >= due:
+                    break
+            tickets.append(srv.submit(views[j]))
+            late[j] = time.perf_counter() - due
+        lat = np.zeros(count)
+        pending = dict(enumerate(tickets))
+        while pending:
+            for j, t in list(pending.items()):
+                st, l = srv.poll(t)
+                if st == qms.QMS_OK:
+                    lat[j] = l + late[j]
+                    del pending[j]
+            if pending:
+                time.sleep(0.0002)
+        t_end = time.perf_counter()
+        st = srv.stats()
+        srv.close()
+        from tests.gpu_helpers import is_sorted
+        bad = sum(0 if is_sorted(views[j]) else 1 for j in range(0, count, max(1, count // 200)))
+        assert bad == 0, "served output not sorted"
+        wall = t_end - t0
+        # completions end before the last poll; use the latest completion
+        done_at = max(arr[j] + lat[j] for j in range(count))
+        out[f"{rate}_req_per_s"] = {
+            "offered_Gkeys_per_s": round(float(sizes.sum()) / arr[-1] / 1e9, 2),
+            "completed_req_per_s": round(count / done_at, 1),
+            "throughput_Gkeys_per_s": round(total / done_at / 1e9, 3),
+            "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+            "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+            "batches": st["batches"],
+            "peak_admitted_GB": round(st["peak_admitted_bytes"] / 1e9, 3),
+            "waited_for_budget": st["waited_for_budget"],
+            "submit_late_p99_ms": round(float(np.percentile(late, 99)) * 1e3, 3),
+        }
+        del wall
+    del pool_u, pool_f, views
+    return {"requests_per_load": count, "hbm_budget_GB": budget / 2**30,
+            "sizes": "floor(2^(10 + 14u)) keys, u uniform (seed 7)", "loads": out}
 
 
 def main():
@@ -175,6 +300,16 @@ def main():
             dists[name] = round(N_KEYS / (sec2 / args.dist_steps) / 1e9, 3)
             del cps, s2
 
+    batched = None
+    if not args.no_batched:
+        print("[bench] batched vs per-array", file=sys.stderr, flush=True)
+        batched = bench_batched(qms, torch, np, inputs, args.per_array_stride)
+    serving = None
+    if not args.no_serving:
+        print("[bench] serving", file=sys.stderr, flush=True)
+        serving = bench_serving(qms, torch, np, inputs, (2000, 10000, 50000),
+                                args.serving_requests)
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -192,7 +327,7 @@ def main():
                          "counters compiled out)"}
 
     out = {
-        "metric": "Gkeys/s (uint32, n=2^28) + HBM roofline %",
+        "metric": "Gkeys/s (uint32, n=2^28) + HBM roofline %; batched vs per-array; p99 latency",
         "value": round(value, 3),
         "unit": "Gkeys/s",
         "n_gpus": 1,
@@ -211,6 +346,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "distributions_Gkeys_per_s": dists,
+        "batched": batched,
+        "serving": serving,
         "kernels": kernels,
     }
     print(json.dumps(out))

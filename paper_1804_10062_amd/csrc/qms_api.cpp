@@ -100,18 +100,31 @@ int get_workspace(int device, hipStream_t stream, Workspace **out) {
     return QMS_OK;
 }
 
+static void free_workspace(Workspace *ws) {
+    (void)hipSetDevice(ws->device);
+    (void)hipStreamSynchronize(ws->stream);
+    (void)hipFree(ws->block);
+    (void)hipHostFree(ws->htab[0]);
+    delete ws;
+}
+
+int release_workspace(int device, hipStream_t stream) {
+    std::lock_guard<std::mutex> lock(g_ws_mutex);
+    auto it = g_ws.find(std::make_pair(device, stream));
+    if (it == g_ws.end()) return QMS_OK;
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    free_workspace(it->second);
+    g_ws.erase(it);
+    (void)hipSetDevice(cur);
+    return QMS_OK;
+}
+
 int release_workspaces() {
     std::lock_guard<std::mutex> lock(g_ws_mutex);
     int cur = 0;
     (void)hipGetDevice(&cur);
-    for (auto &kv : g_ws) {
-        Workspace *ws = kv.second;
-        (void)hipSetDevice(ws->device);
-        (void)hipStreamSynchronize(ws->stream);
-        (void)hipFree(ws->block);
-        (void)hipHostFree(ws->htab[0]);
-        delete ws;
-    }
+    for (auto &kv : g_ws) free_workspace(kv.second);
     g_ws.clear();
     (void)hipSetDevice(cur);
     return QMS_OK;

@@ -17,6 +17,7 @@ int hip_error(hipError_t e, const char *where);
 int check_device_ptr(const void *p, const char *what, int *device);
 int get_workspace(int device, hipStream_t stream, Workspace **out);
 int release_workspaces();
+int release_workspace(int device, hipStream_t stream);
 
 // One array to sort: n keys (and payloads) at device addresses.
 struct HostSeg {
