@@ -61,6 +61,9 @@ def parse():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--per-array-stride", type=int, default=10)
     ap.add_argument("--serving-requests", type=int, default=3000)
+    ap.add_argument("--pmc-run", action="store_true",
+                    help="short run for rocprofv3 counter passes: one 1 GiB device copy "
+                         "(calibration kernel of known size) and one sort of the workload")
     return ap.parse_args()
 
 
@@ -231,6 +234,17 @@ def main():
     print(f"[bench] generating uniform u32 n=2^28 seed 2", file=sys.stderr, flush=True)
     host = inputs.uniform_u32(N_KEYS, seed=2)
     src = torch.from_numpy(host.view(np.int32)).to(dev)
+    if args.pmc_run:
+        # calibration: a plain copy of exactly 2^30 bytes (read 1 GiB, write 1 GiB)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        qms.qms_sort(dst)
+        torch.cuda.synchronize()
+        print(json.dumps({"pmc_run": True, "copy_bytes": N_KEYS * 4,
+                          "rounds": len(qms.qms_last_schedule())}))
+        return
     copies = [src.clone() for _ in range(K + W)]
     torch.cuda.synchronize()
 

@@ -25,31 +25,6 @@
 
 namespace qms {
 
-// Merge-path split of diagonal d: the number of elements of run A among the
-// first d outputs of the stable merge of A and B.  The whole wave searches
-// together: each step every lane probes one of 64 evenly spaced candidates
-// and a ballot narrows the interval 64-fold.
-template <class O>
-__device__ __forceinline__ uint64_t merge_path_wave(const uint32_t *A, uint64_t lenA,
-                                                    const uint32_t *B, uint64_t lenB,
-                                                    uint64_t d) {
-    uint64_t lo = d > lenB ? d - lenB : 0;
-    uint64_t hi = d < lenA ? d : lenA;
-    const int lane = lane_id();
-    while (hi > lo) {
-        const uint64_t step = (hi - lo + kWave - 1) / kWave;
-        const uint64_t i = lo + (uint64_t)lane * step;
-        bool pred = false;
-        if (i < hi) pred = O::ord(A[i]) <= O::ord(B[d - 1 - i]);
-        const int c = __popcll(__ballot(pred));
-        const uint64_t nlo = c > 0 ? lo + (uint64_t)(c - 1) * step + 1 : lo;
-        const uint64_t cand = lo + (uint64_t)c * step;
-        hi = cand < hi ? cand : hi;
-        lo = nlo;
-    }
-    return lo;
-}
-
 // Geometry of merge tile `tile` of a level: run pair base, lengths, diagonals.
 struct MergeTileGeom {
     uint64_t pb, lenA, lenB, d0, d1;
@@ -78,11 +53,31 @@ __device__ __forceinline__ void level_regions(const SortSeg &g, uint32_t level, 
     *dst = (level & 1u) ? r0 : r1;
 }
 
-// One wave per merge tile: the merge-path split at the tile's first output.
+// Merge-path split of diagonal d by binary search (one thread): the number
+// of elements of run A among the first d outputs of the stable merge of A
+// and B (ties taken from A first).
+template <class O>
+__device__ __forceinline__ uint64_t merge_path_thread(const uint32_t *A, uint64_t lenA,
+                                                      const uint32_t *B, uint64_t lenB,
+                                                      uint64_t d) {
+    uint64_t lo = d > lenB ? d - lenB : 0;
+    uint64_t hi = d < lenA ? d : lenA;
+    while (lo < hi) {
+        const uint64_t mid = (lo + hi) >> 1;
+        if (O::ord(A[mid]) <= O::ord(B[d - 1 - mid])) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// One thread per merge tile: the split at the tile's first output.  A plain
+// binary search touches about 2 log2(W) cache lines per split; a wave-wide
+// 64-way search would touch over ten times more, which costs more than the
+// lower latency saves once there are thousands of splits.
 template <class O>
 __global__ __launch_bounds__(kBlock) void k_merge_split(TaskRef<SortSeg> tasks, uint32_t level,
                                                         uint32_t total, uint32_t *splits) {
-    const uint32_t w = blockIdx.x * kWaves + wave_id();
+    const uint32_t w = blockIdx.x * kBlock + threadIdx.x;
     if (w >= total) return;
     uint32_t tile, a;
     const SortSeg g = task_of(tasks, w, &tile, &a);
@@ -91,8 +86,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_split(TaskRef<SortSeg> tasks, 
     const uint64_t W = (uint64_t)kBaseTile << level;
     const MergeTileGeom geo = merge_geom(g.m, W, tile);
     const uint32_t *A = g.keys + src + geo.pb;
-    const uint64_t i = merge_path_wave<O>(A, geo.lenA, A + W, geo.lenB, geo.d0);
-    if (lane_id() == 0) splits[g.split_off + tile] = (uint32_t)i;
+    splits[g.split_off + tile] = (uint32_t)merge_path_thread<O>(A, geo.lenA, A + W, geo.lenB, geo.d0);
 }
 
 template <class O, bool PAIRS>
@@ -214,7 +208,7 @@ static hipError_t merge_t(const TaskRef<SortSeg> &tasks, uint32_t level, uint32_
     if (tiles == 0) return hipSuccess;
     {
         ProfScope prof(st, K_MERGE_SPLIT, 0.0);
-        hipLaunchKernelGGL((k_merge_split<O>), dim3((tiles + kWaves - 1) / kWaves), dim3(kBlock),
+        hipLaunchKernelGGL((k_merge_split<O>), dim3((tiles + kBlock - 1) / kBlock), dim3(kBlock),
                            0, st, tasks, level, tiles, splits);
     }
     {

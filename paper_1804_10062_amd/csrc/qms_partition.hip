@@ -337,20 +337,32 @@ __global__ __launch_bounds__(kBlock) void k_part_split(TaskRef<PartSeg> tasks, u
     const uint64_t x1 = te < reg1 ? te : reg1;
     const int lane = lane_id();
     uint32_t *sp = (side ? spR_all : spL_all) + g.chunk_off;
-    for (uint64_t base = x0; base < x1; base += kWave) {
-        const uint64_t pos = base + lane;
-        bool f = false;
-        if (pos < x1) {
-            const bool bl = belongs_left<PASS>(O::ord(keys[pos]), p);
-            f = side ? bl : !bl;
+    // the wave walks the tile 1024 elements a step, 16 consecutive per lane
+    constexpr int kPer = 16;
+    for (uint64_t base = x0; base < x1; base += kWave * kPer) {
+        const uint64_t lb = base + (uint64_t)lane * kPer;
+        uint32_t flags = 0;
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const uint64_t pos = lb + q;
+            if (pos < x1) {
+                const bool bl = belongs_left<PASS>(O::ord(keys[pos]), p);
+                flags |= (uint32_t)(side ? bl : !bl) << q;
+            }
         }
-        const uint64_t mask = __ballot(f);
-        const uint32_t c = (uint32_t)__popcll(mask);
-        if (k < c) {
-            if (f && (uint32_t)__popcll(mask & lanemask_lt()) == k) sp[j] = (uint32_t)pos;
+        const uint32_t c = (uint32_t)__popc(flags);
+        const uint32_t incl = wave_inclusive_scan(c);
+        const uint32_t total = __shfl(incl, kWave - 1, kWave);
+        if (k < total) {
+            const uint32_t excl = incl - c;
+            if (excl <= k && k < incl) {
+                uint32_t f = flags;
+                for (uint32_t r = k - excl; r > 0; --r) f &= f - 1;  // drop lower set bits
+                sp[j] = (uint32_t)(lb + (uint32_t)__ffs(f) - 1);
+            }
             return;
         }
-        k -= c;
+        k -= total;
     }
 }
 
