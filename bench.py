@@ -312,6 +312,7 @@ def main():
                 print(f"bench.py: {name} output not sorted", file=sys.stderr)
                 sys.exit(1)
             dists[name] = round(N_KEYS / (sec2 / args.dist_steps) / 1e9, 3)
+            dists[name + "_rounds"] = len(qms.qms_last_schedule())
             del cps, s2
 
     batched = None

@@ -223,7 +223,7 @@ uint64_t qms_last_schedule(uint64_t *out, uint64_t max_rounds) {
 }
 
 void qms_get_tiles(uint32_t *base_tile, uint32_t *merge_tile, uint32_t *partition_tile) {
-    if (base_tile) *base_tile = kBaseTile;
+    if (base_tile) *base_tile = kBaseTileKeys;
     if (merge_tile) *merge_tile = kMergeTile;
     if (partition_tile) *partition_tile = kPartSub;
 }

@@ -17,8 +17,9 @@ constexpr int kWaves = kBlock / kWave;
 #define QMS_MERGE_ITEMS 8
 #endif
 
-constexpr int kBaseTile = 4096;        // base-case tile (X of QuickMergeXsort)
-constexpr int kBasePerThread = kBaseTile / kBlock;     // 16
+constexpr int kSortThreads = 512;      // threads of the base-case workgroup
+constexpr uint32_t kBaseTileKeys = 16384;  // base-case tile, keys only
+constexpr uint32_t kBaseTilePairs = 8192;  // base-case tile, key/payload pairs
 constexpr int kMergePerThread = QMS_MERGE_ITEMS;       // outputs per thread
 constexpr int kMergeTile = kBlock * kMergePerThread;   // outputs per workgroup
 constexpr int kPartSub = 4096;         // elements a workgroup classifies per step
@@ -26,8 +27,10 @@ constexpr int kPartItems = kPartSub / kBlock;          // 16
 constexpr int kRankChunk = 2048;       // misplaced pairs exchanged per workgroup
 constexpr uint32_t kMaxTiles = 65536;  // fixed bound on partition tiles
 constexpr int kScanThreads = 1024;     // single-workgroup scan kernels
+constexpr uint64_t kEqBlockMin = 64;   // pivot-equal keys that always get their own block
 
-static_assert(kBaseTile % kMergeTile == 0, "runs must tile into merge tiles");
+static_assert(kBaseTileKeys % kMergeTile == 0 && kBaseTilePairs % kMergeTile == 0,
+              "runs must tile into merge tiles");
 
 // ---- round state slots (uint64 words in the workspace) ----------------------
 enum MetaSlot : int {
@@ -77,17 +80,22 @@ struct PartSeg {
     uint32_t nt;         // partition tiles of the range
     uint32_t chunk_off;  // first entry in the chunk-boundary arrays
     uint32_t slot;       // index of the segment's round-state words
+    uint32_t flags;      // kPivotFromSample: pivot precomputed by k_part_pivot
+    uint32_t pad;
 };
+constexpr uint32_t kPivotFromSample = 1;
+constexpr int kPivotSample = 1023;  // sample of the fallback pivot
 
 // One Mergesort of a round: m keys at D, swap space at Bf (offsets from keys),
-// L merge levels; the base case swaps into Bf when L is odd.
+// L merge levels over runs of w0 << level keys; the base case (tiles of w0
+// keys) swaps into Bf when L is odd.
 struct SortSeg {
     uint32_t *keys;
     uint32_t *vals;
     uint32_t D, Bf, m;
     uint32_t L;          // merge levels
     uint32_t split_off;  // first entry in the merge split array
-    uint32_t pad;
+    uint32_t w0;         // base-case tile (run width of level 0)
 };
 
 template <class T>

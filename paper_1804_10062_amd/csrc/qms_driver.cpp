@@ -3,7 +3,7 @@
 //
 // Every segment follows the paper's loop: partition its range around the
 // median of three keys, Mergesort the smaller side with the larger side as
-// swap space, continue on the larger side; a range of at most kBaseTile keys
+// swap space, continue on the larger side; a range of at most one base tile
 // is finished by the base case in place.  All segments advance in lockstep
 // rounds, and every phase of a round is one launch for all segments (task
 // tables, qms_device.hpp): count + scan, [split +] swap of pass A, scan,
@@ -55,6 +55,7 @@ struct Arena {
 struct Seg {
     uint32_t *keys, *vals;
     uint32_t lo, hi;
+    bool bad_split;  // the last round's smaller side held less than 1/16 of its range
 };
 
 // One round's tables.
@@ -81,16 +82,17 @@ const std::vector<std::array<uint64_t, 5>> &last_schedule() { return g_schedule;
 static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
                       hipStream_t st, bool log) {
     const double w = pairs ? 2.0 : 1.0;
+    const uint32_t T0 = pairs ? kBaseTilePairs : kBaseTileKeys;  // base-case tile
     std::vector<uint32_t> active, next;
-    // ranges of at most kBaseTile keys, sorted in place by the base case.  A
+    // ranges of at most T0 keys, sorted in place by the base case.  A
     // range that becomes small in a round still holds that round's swap
     // buffer, so it runs one round later (next_finals -> ready_finals).
     std::vector<SortSeg> ready_finals, next_finals, tasks;
     for (uint32_t i = 0; i < segs.size(); ++i) {
         const Seg &g = segs[i];
         const uint32_t s = g.hi - g.lo;
-        if (s > (uint32_t)kBaseTile) active.push_back(i);
-        else if (s > 1) ready_finals.push_back(SortSeg{g.keys, g.vals, g.lo, 0, s, 0, 0, 0});
+        if (s > T0) active.push_back(i);
+        else if (s > 1) ready_finals.push_back(SortSeg{g.keys, g.vals, g.lo, 0, s, 0, 0, T0});
     }
     while (!active.empty() || !ready_finals.empty()) {
         // alternate arenas: the one used two rounds ago has no copy in flight
@@ -115,12 +117,15 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
             uint32_t *pc = ar.take<uint32_t>(A + 1, &o_pre);
             if (!pt || !pc) return set_error(QMS_ERR_NOMEM, "task table arena too small");
             uint32_t toff = 0, coff = 0, max_nt = 0;
+            bool any_sample = false;
             pc[0] = 0;
             for (uint32_t a = 0; a < A; ++a) {
                 const Seg &g = segs[active[a]];
                 const uint32_t s = g.hi - g.lo;
                 const uint32_t nt = (s + TP - 1) / TP;
-                pt[a] = PartSeg{g.keys, g.vals, g.lo, s, toff, nt, coff, a};
+                const uint32_t fl = g.bad_split ? kPivotFromSample : 0u;
+                any_sample |= g.bad_split;
+                pt[a] = PartSeg{g.keys, g.vals, g.lo, s, toff, nt, coff, a, fl, 0};
                 toff += nt;
                 coff += (s + 4095) / 4096 + 2;
                 pc[a + 1] = toff;
@@ -139,6 +144,7 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
             L.TP = TP;
             L.scan_threads = max_nt > 4 * kBlock ? kScanThreads : kBlock;
             L.keys_total = (double)sum_s;
+            L.sample_pivots = any_sample;
             L.ws = &ws;
             L.phase = 0;
             L.work = toff;
@@ -161,7 +167,9 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
                 const uint64_t s = pt[a].s;
                 const uint64_t c_lt = ws.h_res[4 * a], c_eq = ws.h_res[4 * a + 1];
                 const uint64_t X = ws.h_res[4 * a + 2];
-                if (c_eq == 0 || c_lt + c_eq > s)
+                // c_eq is 0 when the pivot-equal keys stay in the ">= p" side;
+                // then the "< p" side is not empty
+                if ((c_eq == 0 && c_lt == 0) || c_lt + c_eq > s)
                     return set_error(QMS_ERR_HIP, "partition returned inconsistent counts");
                 const uint64_t nch = chunk_count(X, s);
                 ca[a + 1] = ca[a] + (uint32_t)nch;
@@ -223,7 +231,7 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
                 const uint32_t c_lt = ws.h_res[4 * a], c_eq = ws.h_res[4 * a + 1];
                 const uint32_t b1 = g.lo + c_lt, b2 = b1 + c_eq;
                 const uint32_t mL = c_lt, mR = g.hi - b2;
-                SortSeg t{g.keys, g.vals, 0, 0, 0, 0, 0, 0};
+                SortSeg t{g.keys, g.vals, 0, 0, 0, 0, 0, T0};
                 if (mL <= mR) {
                     t.D = g.lo;
                     t.Bf = b2;
@@ -235,12 +243,15 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
                     t.m = mR;
                     g.hi = b1;
                 }
-                t.L = t.m > (uint32_t)kBaseTile ? ceil_log2((t.m + kBaseTile - 1) / kBaseTile) : 0;
+                t.L = t.m > T0 ? ceil_log2((t.m + T0 - 1) / T0) : 0;
+                // HybridQuickMergesort's rule with delta = 1/16: a split outside
+                // [s/16, 15 s/16] makes the next pivot of this array a sample median
+                g.bad_split = (uint64_t)std::min(mL, mR) * 16 < s;
                 if (t.m > 1) tasks.push_back(t);
                 if (log) g_schedule.push_back({s, c_lt, c_eq, (uint64_t)(s - c_lt - c_eq), t.L});
                 const uint32_t s2 = g.hi - g.lo;
-                if (s2 > (uint32_t)kBaseTile) next.push_back(active[a]);
-                else if (s2 > 1) next_finals.push_back(SortSeg{g.keys, g.vals, g.lo, 0, s2, 0, 0, 0});
+                if (s2 > T0) next.push_back(active[a]);
+                else if (s2 > 1) next_finals.push_back(SortSeg{g.keys, g.vals, g.lo, 0, s2, 0, 0, T0});
             }
             active.swap(next);
         }
@@ -267,7 +278,7 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
             SortSeg t = tasks[a];
             t.split_off = pmerge[a];
             stab[a] = t;
-            ptile[a + 1] = ptile[a] + (t.m + kBaseTile - 1) / kBaseTile;
+            ptile[a + 1] = ptile[a] + (t.m + T0 - 1) / T0;
             pmerge[a + 1] = pmerge[a] + (t.m + kMergeTile - 1) / kMergeTile;
             base_bytes += ((t.L & 1) ? 16.0 : 8.0) * w * (double)t.m;
             maxL = std::max(maxL, t.L);
@@ -321,7 +332,7 @@ int sort_segments(int dt, bool pairs, const HostSeg *segs, size_t count, Workspa
             int rc = flush();
             if (rc != QMS_OK) return rc;
         }
-        group.push_back(Seg{h.keys, h.vals, 0, (uint32_t)h.n});
+        group.push_back(Seg{h.keys, h.vals, 0, (uint32_t)h.n, false});
         group_keys += h.n;
     }
     return flush();

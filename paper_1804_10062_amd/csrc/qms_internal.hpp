@@ -18,8 +18,8 @@ constexpr uint64_t kCapTiles = 1ull << 20;
 constexpr uint64_t kCapChunks = (1ull << 20) + 2ull * kCapSegs + 16;
 // Merge splits of one level: ceil(m / kMergeTile) per task, m < 2^31.
 constexpr uint64_t kCapSplits = (1ull << 31) / kMergeTile + kCapSegs + 16;
-// Merge levels a task can need: ceil(log2(2^31 / kBaseTile)).
-constexpr int kMaxLevels = 20;
+// Merge levels a task can need: ceil(log2(2^31 / 8192)).
+constexpr int kMaxLevels = 18;
 
 // Library-owned scratch of one (device, stream): counters, round state and
 // task tables.  Its size does not depend on the number of keys sorted.
@@ -60,6 +60,7 @@ struct PartitionLaunch {
     uint32_t work;             // work items (workgroups, or waves for splits)
     uint32_t TP;               // partition tile
     uint32_t scan_threads;     // block size of the scans
+    bool sample_pivots;        // some segment takes its pivot from a sample
     double keys_total;         // keys in all ranges (byte figures)
     double bytes;              // algorithmic bytes of the launch (swap A)
     const Workspace *ws;

@@ -83,7 +83,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_split(TaskRef<SortSeg> tasks, 
     const SortSeg g = task_of(tasks, w, &tile, &a);
     uint32_t src, dst;
     level_regions(g, level, &src, &dst);
-    const uint64_t W = (uint64_t)kBaseTile << level;
+    const uint64_t W = (uint64_t)g.w0 << level;
     const MergeTileGeom geo = merge_geom(g.m, W, tile);
     const uint32_t *A = g.keys + src + geo.pb;
     splits[g.split_off + tile] = (uint32_t)merge_path_thread<O>(A, geo.lenA, A + W, geo.lenB, geo.d0);
@@ -198,7 +198,7 @@ __global__ __launch_bounds__(kBlock) void k_merge(TaskRef<SortSeg> tasks, uint32
     uint32_t src, dst;
     level_regions(g, level, &src, &dst);
     merge_block<O, PAIRS>(g.keys + src, PAIRS ? g.vals + src : nullptr, g.keys + dst,
-                          PAIRS ? g.vals + dst : nullptr, g.m, (uint64_t)kBaseTile << level,
+                          PAIRS ? g.vals + dst : nullptr, g.m, (uint64_t)g.w0 << level,
                           tile, splits + g.split_off);
 }
 

@@ -42,6 +42,46 @@
 
 namespace qms {
 
+__device__ __forceinline__ const PartSeg &seg_by_index(const TaskRef<PartSeg> &r, uint32_t a) {
+    return r.A == 1 ? r.one : r.tab[a];
+}
+
+// ---- fallback pivot -----------------------------------------------------------
+// After a round whose smaller side held less than s/16 keys, the next pivot of
+// the segment is the median of kPivotSample keys at evenly spaced positions
+// (the median-of-a-larger-sample pivot of Sec. "QuickXsort and QuickMergesort"
+// and Theorem 3, used in the spirit of Sec. "Worst-Case Efficient
+// QuickMergeSort": median-of-3 as long as the splits stay within
+// [s/16, 15 s/16], a stronger pivot for the round after one that did not).
+// One workgroup per segment; segments without the flag return at once.
+template <class O>
+__global__ __launch_bounds__(1024) void k_part_pivot(TaskRef<PartSeg> tasks, uint64_t *meta_all) {
+    __shared__ uint32_t smp[1024];
+    const PartSeg g = seg_by_index(tasks, blockIdx.x);
+    if (!(g.flags & kPivotFromSample)) return;
+    const uint32_t *keys = g.keys + g.lo;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t S = g.s < (uint32_t)kPivotSample ? g.s : (uint32_t)kPivotSample;
+    smp[tid] = tid < S ? O::ord(keys[(uint64_t)(2 * tid + 1) * g.s / (2 * S)]) : 0xFFFFFFFFu;
+    // bitonic sort of the 1024 sampled keys in LDS
+    for (uint32_t k = 2; k <= 1024; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            __syncthreads();
+            const uint32_t l = tid ^ j;
+            if (l > tid) {
+                const uint32_t a = smp[tid], b = smp[l];
+                const bool asc = (tid & k) == 0;
+                if ((a > b) == asc) {
+                    smp[tid] = b;
+                    smp[l] = a;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    if (tid == 0) meta_all[(uint64_t)g.slot * M_COUNT + M_PIVOT] = smp[S / 2];
+}
+
 // ---- count -------------------------------------------------------------------
 // One workgroup per tile: #(< p) and #(== p).  Tile 0 of a segment also
 // records the segment's pivot.
@@ -53,7 +93,9 @@ __global__ __launch_bounds__(kBlock) void k_part_count(TaskRef<PartSeg> tasks, u
     uint32_t t, a;
     const PartSeg g = task_of(tasks, blockIdx.x, &t, &a);
     const uint32_t *keys = g.keys + g.lo;
-    const uint32_t p = pivot_of<O>(keys, 0, g.s);
+    const uint32_t p = (g.flags & kPivotFromSample)
+                           ? (uint32_t)meta[(uint64_t)g.slot * M_COUNT + M_PIVOT]
+                           : pivot_of<O>(keys, 0, g.s);
     const uint64_t ts = (uint64_t)t * TP;
     const uint64_t te = ts + TP < g.s ? ts + TP : g.s;
     uint32_t lt = 0, eq = 0;
@@ -73,7 +115,6 @@ __global__ __launch_bounds__(kBlock) void k_part_count(TaskRef<PartSeg> tasks, u
     if (threadIdx.x == 0) {
         cnt_lt[g.tile_off + t] = lt;
         cnt_eq[g.tile_off + t] = eq;
-        if (t == 0) meta[(uint64_t)g.slot * M_COUNT + M_PIVOT] = p;
     }
 }
 
@@ -126,10 +167,6 @@ __device__ __forceinline__ uint32_t scan_misplaced(uint32_t nt, F mis, uint32_t 
     return totL;
 }
 
-__device__ __forceinline__ const PartSeg &seg_by_index(const TaskRef<PartSeg> &r, uint32_t a) {
-    return r.A == 1 ? r.one : r.tab[a];
-}
-
 // ---- scan of pass A ----------------------------------------------------------
 // One workgroup per segment.  res[4 a + 0..2] = (#<p, #==p, pass-A pairs) for
 // the host.
@@ -150,7 +187,8 @@ __global__ void k_part_scan_a(TaskRef<PartSeg> tasks, uint32_t TP, const uint32_
     uint64_t *meta = meta_all + (uint64_t)g.slot * M_COUNT;
     const uint32_t nt = g.nt;
     const uint64_t s = g.s;
-    const uint32_t p = pivot_of<O>(keys, 0, s);
+    const uint32_t p = (g.flags & kPivotFromSample) ? (uint32_t)meta[M_PIVOT]
+                                                    : pivot_of<O>(keys, 0, s);
     uint64_t slt = 0, seq = 0;
     for (uint32_t t = threadIdx.x; t < nt; t += blockDim.x) {
         slt += cnt_lt[t];
@@ -158,7 +196,14 @@ __global__ void k_part_scan_a(TaskRef<PartSeg> tasks, uint32_t TP, const uint32_
         eqmv[t] = 0;
     }
     const uint64_t c_lt = block_sum(slt, tmp64);
-    const uint64_t c_eq = block_sum(seq, tmp64);
+    const uint64_t c_eq_all = block_sum(seq, tmp64);
+    // Keys equal to the pivot get a block of their own (pass B) only when
+    // there are many of them, or when nothing is smaller than the pivot (then
+    // excluding them is what makes the round progress).  Otherwise they stay
+    // in the ">= p" side, where the sort treats them like any other key; the
+    // round still removes at least one key from the range (the "< p" side).
+    const bool eq_block = c_lt == 0 || c_eq_all > kEqBlockMin + s / 4096;
+    const uint64_t c_eq = eq_block ? c_eq_all : 0;
     const uint64_t tb = c_lt / TP;  // tile holding B1 (tb < nt since c_lt < s)
     uint32_t lt_part = 0, eq_part = 0;
     if (c_lt % TP != 0) block_count_range<O>(keys, tb * TP, c_lt, p, &lt_part, &eq_part, tmp);
@@ -497,7 +542,12 @@ template <class O, bool PAIRS>
 static hipError_t partition_t(const PartitionLaunch &L, hipStream_t st) {
     const Workspace &ws = *L.ws;
     switch (L.phase) {
-    case 0: {  // count + scan A
+    case 0: {  // [fallback pivot +] count + scan A
+        if (L.sample_pivots) {
+            ProfScope prof(st, K_PART_SCAN, 0.0);
+            hipLaunchKernelGGL((k_part_pivot<O>), dim3(L.tasks.A), dim3(1024), 0, st, L.tasks,
+                               ws.meta);
+        }
         {
             ProfScope prof(st, K_PART_COUNT, 4.0 * (double)L.keys_total);
             hipLaunchKernelGGL((k_part_count<O>), dim3(L.work), dim3(kBlock), 0, st, L.tasks,

@@ -34,8 +34,8 @@ def _sort_and_compare(x: np.ndarray):
     np.testing.assert_array_equal(got.view(np.uint32), want.view(np.uint32))
 
 
-SIZES = [0, 1, 2, 3, 17, 255, 4095, 4096, 4097, 8191, 8192, 8193, 12345, 40000,
-         65543, 1 << 17, 300007]
+SIZES = [0, 1, 2, 3, 17, 255, 4095, 4096, 4097, 8191, 8192, 8193, 12345, 16383, 16384,
+         16385, 32769, 40000, 65543, 1 << 17, 300007]
 
 
 @needs_gpu
@@ -96,7 +96,8 @@ def test_extreme_u32_values():
 
 @needs_gpu
 @pytest.mark.parametrize("kind,n", [("zipf", 300007), ("uniform", 65543), ("equal", 9000),
-                                    ("uniform_f32", 123457)])
+                                    ("uniform_f32", 123457), ("uniform", 8191),
+                                    ("uniform", 8193), ("sorted_swaps", 70001)])
 def test_pairs(kind, n):
     k = inputs.make_keys(kind, n, seed=4)
     kt = to_device(k)
@@ -123,7 +124,8 @@ def test_sort_on_side_stream_and_schedule_log():
     assert len(sched) > 0
     lo_hi = 1 << 18
     for (s_, lt, eq, gt, levels) in sched:
-        assert s_ == lo_hi and lt + eq + gt == s_ and eq >= 1
+        # eq == 0: the pivot-equal keys stayed in the ">= p" side (then lt > 0)
+        assert s_ == lo_hi and lt + eq + gt == s_ and (eq >= 1 or lt >= 1)
         lo_hi = max(lt, gt)
     assert lo_hi <= qms.qms_get_tiles()["base_tile"]
 
@@ -171,3 +173,43 @@ def test_config2_pairs_zipf_2_26():
     # keys against the oracle's sort of the same keys
     want, _, _ = oracle.sort(k, counted=False)
     np.testing.assert_array_equal(to_host(kt), want)
+
+
+def _structured(kind, n):
+    i = np.arange(n, dtype=np.int64)
+    if kind == "organ_pipe":
+        x = np.minimum(i, n - 1 - i)
+    elif kind == "sawtooth":
+        x = i % 1000
+    elif kind == "reverse_blocks":
+        x = (n - 1 - i) // 7
+    elif kind == "interleaved":
+        x = np.where(i % 2 == 0, i, n - i)
+    elif kind == "one_different":
+        x = np.zeros(n, dtype=np.int64)
+        x[n // 3] = 5
+    else:
+        raise ValueError(kind)
+    return (x * 16).astype(np.uint32)
+
+
+@needs_gpu
+@pytest.mark.parametrize("kind", ["organ_pipe", "sawtooth", "reverse_blocks", "interleaved",
+                                  "one_different"])
+@pytest.mark.parametrize("n", [100003, 1 << 21])
+def test_structured_inputs_bounded_rounds(kind, n):
+    """Sorted correctly, and the round count stays logarithmic: after a round
+    whose smaller side holds less than 1/16 of the range, the next pivot is a
+    sample median."""
+    x = _structured(kind, n)
+    _sort_and_compare(x)
+    rounds = len(qms.qms_last_schedule())
+    assert rounds <= 8 * int(np.log2(max(2, n // 16384))) + 16, rounds
+
+
+@needs_gpu
+@pytest.mark.parametrize("n", [1 << 22])
+def test_reverse_rounds(n):
+    x = inputs.reverse_u32(n)
+    _sort_and_compare(x)
+    assert len(qms.qms_last_schedule()) <= 40
