@@ -78,23 +78,46 @@ __device__ __forceinline__ void tile_sort_block(uint32_t *sk, uint32_t *sv, uint
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & (kWave - 1);
 
-    // 1. coalesced loads; in swap mode each thread moves the buffer elements of
-    //    exactly the source cells it has read into those cells
-#pragma unroll 8
-    for (int r = 0; r < ITEMS; ++r) {
-        const uint32_t e = (uint32_t)r * NT + tid;
-        E x;
-        if (e < len) {
-            x = TE::make(O::ord(sk[e]), e);
-            if constexpr (PAIRS) sp[e] = sv[e];
-            if (swap) {
-                sk[e] = dk[e];
-                if constexpr (PAIRS) sv[e] = dv[e];
-            }
-        } else {
-            x = TE::pad(e);
+    // 1. coalesced loads (clamped indices, all issued together); in swap mode
+    //    each thread then moves the buffer elements of exactly the source
+    //    cells it has read into those cells
+    {
+        uint32_t kv[ITEMS];
+#pragma unroll
+        for (int r = 0; r < ITEMS; ++r) kv[r] = ldg(sk + min((uint32_t)r * NT + tid, len - 1));
+#pragma unroll
+        for (int r = 0; r < ITEMS; ++r) {
+            const uint32_t e = (uint32_t)r * NT + tid;
+            s[nat_idx<ITEMS>(e)] = e < len ? TE::make(O::ord(kv[r]), e) : TE::pad(e);
         }
-        s[nat_idx<ITEMS>(e)] = x;
+        if constexpr (PAIRS) {
+#pragma unroll
+            for (int r = 0; r < ITEMS; ++r) kv[r] = ldg(sv + min((uint32_t)r * NT + tid, len - 1));
+#pragma unroll
+            for (int r = 0; r < ITEMS; ++r) {
+                const uint32_t e = (uint32_t)r * NT + tid;
+                if (e < len) sp[e] = kv[r];
+            }
+        }
+        if (swap) {
+#pragma unroll
+            for (int r = 0; r < ITEMS; ++r) kv[r] = ldg(dk + min((uint32_t)r * NT + tid, len - 1));
+#pragma unroll
+            for (int r = 0; r < ITEMS; ++r) {
+                const uint32_t e = (uint32_t)r * NT + tid;
+                if (e < len) stg(sk + e, kv[r]);
+            }
+            if constexpr (PAIRS) {
+#pragma unroll
+                for (int r = 0; r < ITEMS; ++r)
+                    kv[r] = ldg(dv + min((uint32_t)r * NT + tid, len - 1));
+#pragma unroll
+                for (int r = 0; r < ITEMS; ++r) {
+                    const uint32_t e = (uint32_t)r * NT + tid;
+                    if (e < len) stg(sv + e, kv[r]);
+                }
+            }
+        }
     }
     __syncthreads();
 
@@ -143,11 +166,14 @@ __device__ __forceinline__ void tile_sort_block(uint32_t *sk, uint32_t *sv, uint
             const uint32_t lm = j / ITEMS;
             const bool lower = (lane & lm) == 0;
             const bool keep_min = asc == lower;
+            // all exchanges of the stage first, so that they overlap
+            E y[ITEMS];
+#pragma unroll
+            for (int i = 0; i < ITEMS; ++i) y[i] = __shfl_xor(r[i], (int)lm, kWave);
 #pragma unroll
             for (int i = 0; i < ITEMS; ++i) {
-                const E y = __shfl_xor(r[i], (int)lm, kWave);
-                const E mn = r[i] < y ? r[i] : y;
-                const E mx = r[i] < y ? y : r[i];
+                const E mn = r[i] < y[i] ? r[i] : y[i];
+                const E mx = r[i] < y[i] ? y[i] : r[i];
                 r[i] = keep_min ? mn : mx;
             }
         }
@@ -172,8 +198,8 @@ __device__ __forceinline__ void tile_sort_block(uint32_t *sk, uint32_t *sv, uint
         const uint32_t e = (uint32_t)q * NT + tid;
         if (e < len) {
             const E x = s[nat_idx<ITEMS>(e)];
-            dk[e] = O::unord(TE::key(x));
-            if constexpr (PAIRS) dv[e] = sp[TE::index(x)];
+            stg(dk + e, O::unord(TE::key(x)));
+            if constexpr (PAIRS) stg(dv + e, sp[TE::index(x)]);
         }
     }
 }

@@ -24,7 +24,7 @@ constexpr int kMergePerThread = QMS_MERGE_ITEMS;       // outputs per thread
 constexpr int kMergeTile = kBlock * kMergePerThread;   // outputs per workgroup
 constexpr int kPartSub = 4096;         // elements a workgroup classifies per step
 constexpr int kPartItems = kPartSub / kBlock;          // 16
-constexpr int kRankChunk = 2048;       // misplaced pairs exchanged per workgroup
+constexpr int kRankChunk = 4096;       // misplaced pairs exchanged per workgroup
 constexpr uint32_t kMaxTiles = 65536;  // fixed bound on partition tiles
 constexpr int kScanThreads = 1024;     // single-workgroup scan kernels
 constexpr uint64_t kEqBlockMin = 64;   // pivot-equal keys that always get their own block
@@ -49,10 +49,11 @@ enum MetaSlot : int {
 
 // Misplaced pairs per swap chunk for a pass with X pairs over a range of s
 // keys: at most kRankChunk (the LDS slots of a workgroup), and small enough
-// that there are about s / (2 kPartSub) chunks, so that sparse misplacement
+// that there are about s / (4 kPartSub) chunks, so that sparse misplacement
 // (nearly sorted input) still spreads the range scans over many workgroups.
+constexpr uint64_t kChunkSpan = 4 * kPartSub;  // target positions per chunk
 __host__ __device__ inline uint32_t rank_chunk(uint64_t X, uint64_t s) {
-    const uint64_t target = (s + 2 * kPartSub - 1) / (2 * kPartSub);
+    const uint64_t target = (s + kChunkSpan - 1) / kChunkSpan;
     uint64_t rc = (X + target - 1) / target;
     if (rc < 1) rc = 1;
     if (rc > (uint64_t)kRankChunk) rc = kRankChunk;
@@ -149,6 +150,13 @@ struct OrdF32 {
         return k ^ ((uint32_t)((int32_t)(~k) >> 31) | 0x80000000u);
     }
 };
+
+// ---- global memory access -------------------------------------------------------
+// Pointers taken from task tables are generic; accessing them through the
+// global address space lets the compiler emit global_load/store (not flat).
+typedef __attribute__((address_space(1))) uint32_t g_u32;
+__device__ __forceinline__ uint32_t ldg(const uint32_t *p) { return *(const g_u32 *)p; }
+__device__ __forceinline__ void stg(uint32_t *p, uint32_t v) { *(g_u32 *)p = v; }
 
 // ---- wave and block primitives -------------------------------------------------
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }

@@ -181,7 +181,7 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
                 uint64_t nb = 0;
                 if (xb > 0) {
                     const uint64_t full = (xb + kRankChunk - 1) / kRankChunk;
-                    const uint64_t target = (s + 2 * kPartSub - 1) / (2 * kPartSub);
+                    const uint64_t target = (s + kChunkSpan - 1) / kChunkSpan;
                     nb = std::min(xb, std::max(full, target));
                     any_b = true;
                 }

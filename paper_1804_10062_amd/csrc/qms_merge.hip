@@ -64,7 +64,7 @@ __device__ __forceinline__ uint64_t merge_path_thread(const uint32_t *A, uint64_
     uint64_t hi = d < lenA ? d : lenA;
     while (lo < hi) {
         const uint64_t mid = (lo + hi) >> 1;
-        if (O::ord(A[mid]) <= O::ord(B[d - 1 - mid])) lo = mid + 1;
+        if (O::ord(ldg(A + mid)) <= O::ord(ldg(B + d - 1 - mid))) lo = mid + 1;
         else hi = mid;
     }
     return lo;
@@ -108,26 +108,33 @@ __device__ __forceinline__ void merge_block(uint32_t *S, uint32_t *SV, uint32_t 
     i1 = min(max(i1, max(i0, d1 > g.lenB ? d1 - g.lenB : 0)), min(min(d1, g.lenA), i0 + cnt));
 
     // the destination window's current contents (buffer elements)
+    // clamped, unconditional loads so that all of them are in flight together
     uint32_t oldk[kMergePerThread];
     uint32_t oldv[PAIRS ? kMergePerThread : 1];
 #pragma unroll
     for (int q = 0; q < kMergePerThread; ++q) {
-        const uint32_t e = q * kBlock + tid;
-        if (e < cnt) {
-            oldk[q] = D[pb + d0 + e];
-            if constexpr (PAIRS) oldv[q] = DV[pb + d0 + e];
-        }
+        const uint32_t e = min((uint32_t)(q * kBlock + tid), cnt - 1);
+        oldk[q] = ldg(D + pb + d0 + e);
+        if constexpr (PAIRS) oldv[q] = ldg(DV + pb + d0 + e);
     }
     const uint64_t j0 = d0 - i0, j1 = d1 - i1;
     const uint32_t na = (uint32_t)(i1 - i0);
     const uint32_t nb = (uint32_t)(j1 - j0);
+    uint32_t nk[kMergePerThread];
+    uint32_t nv[PAIRS ? kMergePerThread : 1];
+#pragma unroll
+    for (int q = 0; q < kMergePerThread; ++q) {
+        const uint32_t e = min((uint32_t)(q * kBlock + tid), cnt - 1);
+        const uint64_t pos = e < na ? pb + i0 + e : pb + W + j0 + (e - na);
+        nk[q] = ldg(S + pos);
+        if constexpr (PAIRS) nv[q] = ldg(SV + pos);
+    }
 #pragma unroll
     for (int q = 0; q < kMergePerThread; ++q) {
         const uint32_t e = q * kBlock + tid;
         if (e < cnt) {
-            const uint64_t pos = e < na ? pb + i0 + e : pb + W + j0 + (e - na);
-            sk[e] = O::ord(S[pos]);
-            if constexpr (PAIRS) sv[e] = SV[pos];
+            sk[e] = O::ord(nk[q]);
+            if constexpr (PAIRS) sv[e] = nv[q];
         }
     }
     __syncthreads();
@@ -180,11 +187,11 @@ __device__ __forceinline__ void merge_block(uint32_t *S, uint32_t *SV, uint32_t 
     for (int q = 0; q < kMergePerThread; ++q) {
         const uint32_t e = q * kBlock + tid;
         if (e < cnt) {
-            D[pb + d0 + e] = O::unord(sk[e]);
-            if constexpr (PAIRS) DV[pb + d0 + e] = sv[e];
+            stg(D + pb + d0 + e, O::unord(sk[e]));
+            if constexpr (PAIRS) stg(DV + pb + d0 + e, sv[e]);
             const uint64_t pos = e < na ? pb + i0 + e : pb + W + j0 + (e - na);
-            S[pos] = oldk[q];
-            if constexpr (PAIRS) SV[pos] = oldv[q];
+            stg(S + pos, oldk[q]);
+            if constexpr (PAIRS) stg(SV + pos, oldv[q]);
         }
     }
 }

@@ -100,14 +100,21 @@ __global__ __launch_bounds__(kBlock) void k_part_count(TaskRef<PartSeg> tasks, u
     const uint64_t te = ts + TP < g.s ? ts + TP : g.s;
     uint32_t lt = 0, eq = 0;
     for (uint64_t b = ts; b < te; b += kPartSub) {
+        // clamped, unconditional loads (all in flight together); the tail
+        // positions are masked out of the counts
+        uint32_t k[kPartItems];
 #pragma unroll
         for (int q = 0; q < kPartItems; ++q) {
             const uint64_t pos = b + (uint64_t)q * kBlock + threadIdx.x;
-            if (pos < te) {
-                const uint32_t k = O::ord(keys[pos]);
-                lt += k < p;
-                eq += k == p;
-            }
+            k[q] = ldg(keys + (pos < te ? pos : te - 1));
+        }
+#pragma unroll
+        for (int q = 0; q < kPartItems; ++q) {
+            const uint64_t pos = b + (uint64_t)q * kBlock + threadIdx.x;
+            const uint32_t x = O::ord(k[q]);
+            const bool in = pos < te;
+            lt += in && x < p;
+            eq += in && x == p;
         }
     }
     lt = block_sum(lt, tmp);
@@ -386,14 +393,14 @@ __global__ __launch_bounds__(kBlock) void k_part_split(TaskRef<PartSeg> tasks, u
     constexpr int kPer = 16;
     for (uint64_t base = x0; base < x1; base += kWave * kPer) {
         const uint64_t lb = base + (uint64_t)lane * kPer;
+        uint32_t kv[kPer];
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) kv[q] = ldg(keys + (lb + q < x1 ? lb + q : x1 - 1));
         uint32_t flags = 0;
 #pragma unroll
         for (int q = 0; q < kPer; ++q) {
-            const uint64_t pos = lb + q;
-            if (pos < x1) {
-                const bool bl = belongs_left<PASS>(O::ord(keys[pos]), p);
-                flags |= (uint32_t)(side ? bl : !bl) << q;
-            }
+            const bool bl = belongs_left<PASS>(O::ord(kv[q]), p);
+            flags |= (uint32_t)(lb + q < x1 && (side ? bl : !bl)) << q;
         }
         const uint32_t c = (uint32_t)__popc(flags);
         const uint32_t incl = wave_inclusive_scan(c);
@@ -412,79 +419,86 @@ __global__ __launch_bounds__(kBlock) void k_part_split(TaskRef<PartSeg> tasks, u
 }
 
 // ---- swap ------------------------------------------------------------------------
-// Compact the misplaced elements of positions [a, b) (offsets from the range
-// start) into the LDS slots 0.. in position order.  Tiles whose prefix counts
-// show no misplaced element on this side are skipped without being read.
-template <class O, bool PAIRS, int PASS>
-__device__ __forceinline__ uint32_t collect_misplaced(const uint32_t *keys, const uint32_t *vals,
-                                                      uint64_t a, uint64_t b, uint32_t p,
-                                                      bool right, const uint32_t *pre,
-                                                      uint32_t TP, uint32_t nt, uint32_t cap,
-                                                      uint32_t *sk, uint32_t *sv, uint32_t *sp,
-                                                      uint32_t *wtot) {
-    const int lane = lane_id(), wave = wave_id();
-    uint32_t running = 0;
-    for (uint64_t base = a; base < b; base += kPartSub) {
-        const uint64_t t = base / TP;
-        const uint32_t pt = pre[t];
-        if (pre[t + 1] == pt) {
-            // nothing to collect in tile t: jump to the first later tile whose
-            // prefix count grows (binary search; pre is non-decreasing)
-            uint64_t x = t + 1, y = nt;  // first i in (t, nt] with pre[i] > pt
-            while (x < y) {
-                const uint64_t mid = (x + y) >> 1;
-                if (pre[mid] > pt) y = mid;
-                else x = mid + 1;
-            }
-            const uint64_t next = (x - 1) * TP;  // tile x - 1 holds the next element
-            base = (next > base ? next : base + kPartSub) - kPartSub;
-            continue;
+// Scan state of one side of a chunk: its position range [pos, end) (offsets
+// from the range start), the prefix counts of its tiles and the number of
+// misplaced elements found so far.
+struct SideScan {
+    uint64_t pos, end;
+    const uint32_t *pre;
+    uint32_t found;
+};
+
+// Advance `sc.pos` past tiles whose prefix counts show no misplaced element
+// (binary search for the next tile whose count grows).
+__device__ __forceinline__ void skip_empty_tiles(SideScan &sc, uint32_t TP, uint32_t nt) {
+    while (sc.pos < sc.end) {
+        const uint64_t t = sc.pos / TP;
+        const uint32_t pt = sc.pre[t];
+        if (sc.pre[t + 1] != pt) return;
+        uint64_t x = t + 1, y = nt;  // first i in (t, nt] with pre[i] > pt
+        while (x < y) {
+            const uint64_t mid = (x + y) >> 1;
+            if (sc.pre[mid] > pt) y = mid;
+            else x = mid + 1;
         }
-        uint32_t kk[kPartItems];
-        uint64_t m[kPartItems];
-        uint32_t wcount = 0;
-#pragma unroll
-        for (int q = 0; q < kPartItems; ++q) {
-            const uint64_t pos = base + (uint64_t)wave * (kPartItems * kWave) +
-                                 (uint64_t)q * kWave + lane;
-            bool f = false;
-            if (pos < b) {
-                kk[q] = keys[pos];
-                const bool bl = belongs_left<PASS>(O::ord(kk[q]), p);
-                f = right ? bl : !bl;
-            }
-            m[q] = __ballot(f);
-            wcount += (uint32_t)__popcll(m[q]);
-        }
-        if (lane == 0) wtot[wave] = wcount;
-        __syncthreads();
-        uint32_t woff = running, total = 0;
-#pragma unroll
-        for (int w = 0; w < kWaves; ++w) {
-            if (w < wave) woff += wtot[w];
-            total += wtot[w];
-        }
-#pragma unroll
-        for (int q = 0; q < kPartItems; ++q) {
-            if ((m[q] >> lane) & 1ull) {
-                const uint32_t slot = woff + (uint32_t)__popcll(m[q] & lanemask_lt());
-                if (slot < cap) {  // always true with consistent counts
-                    const uint64_t pos = base + (uint64_t)wave * (kPartItems * kWave) +
-                                         (uint64_t)q * kWave + lane;
-                    sk[slot] = kk[q];
-                    sp[slot] = (uint32_t)pos;
-                    if constexpr (PAIRS) sv[slot] = vals[pos];
-                }
-            }
-            woff += (uint32_t)__popcll(m[q]);
-        }
-        running += total;
-        __syncthreads();
+        const uint64_t next = (x - 1) * TP;  // tile x - 1 holds the next element
+        sc.pos = next > sc.pos ? next : (t + 1) * TP;
     }
-    return running;
 }
 
-// One workgroup per chunk: exchange the chunk's misplaced elements.
+// Classify one subtile of kPartSub positions starting at sc.pos (wave-striped:
+// wave w covers 16 x 64 consecutive positions, lane-interleaved) and record
+// the positions of the misplaced ones in `slots` in position order.
+template <class O, int PASS>
+__device__ __forceinline__ void classify_subtile(const uint32_t *keys, uint32_t p, bool right,
+                                                 SideScan &sc, uint32_t *slots, uint32_t cap,
+                                                 uint32_t *wtot) {
+    const int lane = lane_id(), wave = wave_id();
+    const uint64_t base = sc.pos;
+    uint64_t m[kPartItems];
+    uint32_t kv[kPartItems];
+    uint32_t wcount = 0;
+#pragma unroll
+    for (int q = 0; q < kPartItems; ++q) {
+        const uint64_t pos = base + (uint64_t)wave * (kPartItems * kWave) + (uint64_t)q * kWave + lane;
+        kv[q] = ldg(keys + (pos < sc.end ? pos : sc.end - 1));
+    }
+#pragma unroll
+    for (int q = 0; q < kPartItems; ++q) {
+        const uint64_t pos = base + (uint64_t)wave * (kPartItems * kWave) + (uint64_t)q * kWave + lane;
+        const bool bl = belongs_left<PASS>(O::ord(kv[q]), p);
+        const bool f = pos < sc.end && (right ? bl : !bl);
+        m[q] = __ballot(f);
+        wcount += (uint32_t)__popcll(m[q]);
+    }
+    if (lane == 0) wtot[wave] = wcount;
+    __syncthreads();
+    uint32_t woff = sc.found, total = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        if (w < wave) woff += wtot[w];
+        total += wtot[w];
+    }
+    __syncthreads();  // wtot is reused by the next call
+#pragma unroll
+    for (int q = 0; q < kPartItems; ++q) {
+        if ((m[q] >> lane) & 1ull) {
+            const uint32_t slot = woff + (uint32_t)__popcll(m[q] & lanemask_lt());
+            if (slot < cap)  // always true with consistent counts
+                slots[slot] = (uint32_t)(base + (uint64_t)wave * (kPartItems * kWave) +
+                                         (uint64_t)q * kWave + lane);
+        }
+        woff += (uint32_t)__popcll(m[q]);
+    }
+    sc.found += total;
+    sc.pos = base + kPartSub;
+}
+
+// One workgroup per chunk: find the positions of the chunk's misplaced
+// elements on both sides (the two ranges are scanned in the same steps, so
+// their loads overlap), then exchange the k-th of the left with the k-th of
+// the right.  Only positions are kept in LDS; the values are read again at
+// the exchange, from cache.
 template <class O, bool PAIRS, int PASS>
 __global__ __launch_bounds__(kBlock) void k_part_swap(TaskRef<PartSeg> tasks, uint32_t TP,
                                                       const uint32_t *preL_all,
@@ -493,8 +507,7 @@ __global__ __launch_bounds__(kBlock) void k_part_swap(TaskRef<PartSeg> tasks, ui
                                                       const uint32_t *spR_all,
                                                       uint32_t *eqmv_all,
                                                       const uint64_t *meta_all) {
-    __shared__ uint32_t kL[kRankChunk], kR[kRankChunk], pL[kRankChunk], pR[kRankChunk];
-    __shared__ uint32_t vL[PAIRS ? kRankChunk : 1], vR[PAIRS ? kRankChunk : 1];
+    __shared__ uint32_t pL[kRankChunk], pR[kRankChunk];
     __shared__ uint32_t wtot[kWaves];
     uint32_t j, a;
     const PartSeg g = task_of(tasks, blockIdx.x, &j, &a);
@@ -510,30 +523,38 @@ __global__ __launch_bounds__(kBlock) void k_part_swap(TaskRef<PartSeg> tasks, ui
     const uint32_t r0 = j * rc;
     uint32_t cnt = X - r0 < rc ? X - r0 : rc;
     const uint32_t *spL = spL_all + g.chunk_off, *spR = spR_all + g.chunk_off;
-    const uint32_t *preL = preL_all + g.tile_off + g.slot;
-    const uint32_t *preR = preR_all + g.tile_off + g.slot;
     // position ranges of this chunk, clamped to the pass's regions
     const PassGeom geo = pass_geom<PASS>(meta, g.s);
-    const uint64_t la = spL[j] > geo.l0 ? spL[j] : geo.l0;
-    const uint64_t lb = spL[j + 1] < geo.l1 ? spL[j + 1] : geo.l1;
-    const uint64_t ra = spR[j] > geo.r0 ? spR[j] : geo.r0;
-    const uint64_t rb = spR[j + 1] < geo.r1 ? spR[j + 1] : geo.r1;
-    const uint32_t nl = collect_misplaced<O, PAIRS, PASS>(keys, vals, la, lb, p, false, preL, TP,
-                                                          g.nt, kRankChunk, kL, vL, pL, wtot);
-    const uint32_t nr = collect_misplaced<O, PAIRS, PASS>(keys, vals, ra, rb, p, true, preR, TP,
-                                                          g.nt, kRankChunk, kR, vR, pR, wtot);
-    // equal by construction; the minimum keeps every write inside the filled slots
-    cnt = min(cnt, min(nl, nr));
+    SideScan L{spL[j] > geo.l0 ? spL[j] : geo.l0, spL[j + 1] < geo.l1 ? spL[j + 1] : geo.l1,
+               preL_all + g.tile_off + g.slot, 0};
+    SideScan R{spR[j] > geo.r0 ? spR[j] : geo.r0, spR[j + 1] < geo.r1 ? spR[j + 1] : geo.r1,
+               preR_all + g.tile_off + g.slot, 0};
+    // look for empty tiles only where the misplaced elements are sparse
+    const bool sparse_l = L.end > L.pos && L.end - L.pos > 8ull * kPartSub + 8ull * cnt;
+    const bool sparse_r = R.end > R.pos && R.end - R.pos > 8ull * kPartSub + 8ull * cnt;
+    for (;;) {
+        if (sparse_l) skip_empty_tiles(L, TP, g.nt);
+        if (sparse_r) skip_empty_tiles(R, TP, g.nt);
+        const bool more_l = L.pos < L.end, more_r = R.pos < R.end;
+        if (!more_l && !more_r) break;
+        if (more_l) classify_subtile<O, PASS>(keys, p, false, L, pL, kRankChunk, wtot);
+        if (more_r) classify_subtile<O, PASS>(keys, p, true, R, pR, kRankChunk, wtot);
+    }
+    __syncthreads();
+    // equal by construction; the minimum keeps every access inside the filled slots
+    cnt = min(cnt, min(L.found, R.found));
     uint32_t *eqmv = eqmv_all + g.tile_off;
     for (uint32_t k = threadIdx.x; k < cnt; k += kBlock) {
-        const uint32_t x = kL[k], y = kR[k];
-        keys[pL[k]] = y;
-        keys[pR[k]] = x;
+        const uint32_t il = pL[k], ir = pR[k];
+        const uint32_t x = ldg(keys + il), y = ldg(keys + ir);
+        stg(keys + il, y);
+        stg(keys + ir, x);
         if constexpr (PAIRS) {
-            vals[pL[k]] = vR[k];
-            vals[pR[k]] = vL[k];
+            const uint32_t vx = ldg(vals + il), vy = ldg(vals + ir);
+            stg(vals + il, vy);
+            stg(vals + ir, vx);
         }
-        if (PASS == 0 && O::ord(x) == p) atomicAdd(&eqmv[pR[k] / TP], 1u);
+        if (PASS == 0 && O::ord(x) == p) atomicAdd(&eqmv[ir / TP], 1u);
     }
 }
 
