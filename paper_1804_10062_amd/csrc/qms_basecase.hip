@@ -140,9 +140,19 @@ __device__ __forceinline__ void tile_sort_block(uint32_t *sk, uint32_t *sv, uint
         }
     }
 
-    // 4. merge stages
+    // 4. merge stages.  During merge stage k a thread's keys are held
+    //    complemented when its k-block sorts descending (complementing
+    //    reverses the unsigned order), so every compare-exchange below is an
+    //    ascending one; the representation changes only between stages.  At
+    //    the last stage every block ascends and the keys are plain again.
+    E cur_mask = E(0);
     for (uint32_t k = 2 * ITEMS; k <= T; k <<= 1) {
-        const bool asc = (base & k) == 0;
+        const E mask = (base & k) == 0 ? E(0) : ~E(0);
+        const E flip = mask ^ cur_mask;
+        cur_mask = mask;
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) r[i] ^= flip;
+        const bool asc = true;
         uint32_t j = k >> 1;
         // partners in other waves: exchange through LDS
         for (; j >= (uint32_t)kWave * ITEMS; j >>= 1) {

@@ -16,12 +16,16 @@ constexpr int kWaves = kBlock / kWave;
 #ifndef QMS_MERGE_ITEMS
 #define QMS_MERGE_ITEMS 8
 #endif
+#ifndef QMS_SPLIT_LANES
+#define QMS_SPLIT_LANES 4
+#endif
 
 constexpr int kSortThreads = 512;      // threads of the base-case workgroup
 constexpr uint32_t kBaseTileKeys = 16384;  // base-case tile, keys only
 constexpr uint32_t kBaseTilePairs = 8192;  // base-case tile, key/payload pairs
 constexpr int kMergePerThread = QMS_MERGE_ITEMS;       // outputs per thread
 constexpr int kMergeTile = kBlock * kMergePerThread;   // outputs per workgroup
+constexpr uint32_t kSplitLanes = QMS_SPLIT_LANES;      // lanes per merge-path split
 constexpr int kPartSub = 4096;         // elements a workgroup classifies per step
 constexpr int kPartItems = kPartSub / kBlock;          // 16
 constexpr int kRankChunk = 4096;       // misplaced pairs exchanged per workgroup

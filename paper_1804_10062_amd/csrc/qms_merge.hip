@@ -70,23 +70,63 @@ __device__ __forceinline__ uint64_t merge_path_thread(const uint32_t *A, uint64_
     return lo;
 }
 
-// One thread per merge tile: the split at the tile's first output.  A plain
-// binary search touches about 2 log2(W) cache lines per split; a wave-wide
-// 64-way search would touch over ten times more, which costs more than the
-// lower latency saves once there are thousands of splits.
+// The same split searched by kSplitLanes lanes together: each step the lanes
+// probe kSplitLanes evenly spaced candidates and a ballot narrows the range
+// kSplitLanes-fold.  Fewer dependent steps than the binary search (the split
+// kernel is latency-bound) for a few more probes.
+template <class O>
+__device__ __forceinline__ uint64_t merge_path_group(const uint32_t *A, uint64_t lenA,
+                                                     const uint32_t *B, uint64_t lenB, uint64_t d,
+                                                     bool active) {
+    constexpr uint32_t G = kSplitLanes;
+    const uint32_t sub = lane_id() % G;
+    const uint32_t gshift = (lane_id() / G) * G;
+    uint64_t lo = d > lenB ? d - lenB : 0;
+    uint64_t hi = d < lenA ? d : lenA;
+    if (!active) lo = hi = 0;
+    // every lane of the wave loops while any group still searches
+    while (__ballot(hi > lo) != 0) {
+        const uint64_t step = hi > lo ? (hi - lo + G - 1) / G : 1;
+        const uint64_t i = lo + (uint64_t)sub * step;
+        bool pred = false;
+        if (i < hi) pred = O::ord(ldg(A + i)) <= O::ord(ldg(B + d - 1 - i));
+        const uint64_t bits = (__ballot(pred) >> gshift) & ((1ull << G) - 1);
+        const int c = __popcll(bits);
+        if (hi > lo) {
+            const uint64_t nlo = c > 0 ? lo + (uint64_t)(c - 1) * step + 1 : lo;
+            const uint64_t cand = lo + (uint64_t)c * step;
+            hi = cand < hi ? cand : hi;
+            lo = nlo;
+        }
+    }
+    return lo;
+}
+
+// kSplitLanes lanes per merge tile: the split at the tile's first output.  A
+// wave-wide 64-way search would touch over ten times more cache lines than a
+// binary search, which costs more than its lower latency saves once there are
+// thousands of splits; a few lanes per split sit in between.
 template <class O>
 __global__ __launch_bounds__(kBlock) void k_merge_split(TaskRef<SortSeg> tasks, uint32_t level,
                                                         uint32_t total, uint32_t *splits) {
-    const uint32_t w = blockIdx.x * kBlock + threadIdx.x;
-    if (w >= total) return;
-    uint32_t tile, a;
-    const SortSeg g = task_of(tasks, w, &tile, &a);
+    const uint32_t gid = blockIdx.x * kBlock + threadIdx.x;
+    const uint32_t w = gid / kSplitLanes;
+    const bool active = w < total;
+    uint32_t tile = 0, a = 0;
+    const SortSeg g = task_of(tasks, active ? w : total - 1, &tile, &a);
     uint32_t src, dst;
     level_regions(g, level, &src, &dst);
     const uint64_t W = (uint64_t)g.w0 << level;
     const MergeTileGeom geo = merge_geom(g.m, W, tile);
     const uint32_t *A = g.keys + src + geo.pb;
-    splits[g.split_off + tile] = (uint32_t)merge_path_thread<O>(A, geo.lenA, A + W, geo.lenB, geo.d0);
+    uint64_t i;
+    if constexpr (kSplitLanes == 1) {
+        if (!active) return;
+        i = merge_path_thread<O>(A, geo.lenA, A + W, geo.lenB, geo.d0);
+    } else {
+        i = merge_path_group<O>(A, geo.lenA, A + W, geo.lenB, geo.d0, active);
+    }
+    if (active && gid % kSplitLanes == 0) splits[g.split_off + tile] = (uint32_t)i;
 }
 
 template <class O, bool PAIRS>
@@ -215,8 +255,9 @@ static hipError_t merge_t(const TaskRef<SortSeg> &tasks, uint32_t level, uint32_
     if (tiles == 0) return hipSuccess;
     {
         ProfScope prof(st, K_MERGE_SPLIT, 0.0);
-        hipLaunchKernelGGL((k_merge_split<O>), dim3((tiles + kBlock - 1) / kBlock), dim3(kBlock),
-                           0, st, tasks, level, tiles, splits);
+        const uint64_t threads = (uint64_t)tiles * kSplitLanes;
+        hipLaunchKernelGGL((k_merge_split<O>), dim3((uint32_t)((threads + kBlock - 1) / kBlock)),
+                           dim3(kBlock), 0, st, tasks, level, tiles, splits);
     }
     {
         // per element: read the run cell and the window cell, write both
