@@ -37,7 +37,7 @@ static std::mutex g_ws_mutex;
 static std::map<std::pair<int, hipStream_t>, Workspace *> g_ws;
 
 static size_t ws_words() {
-    return 3ull * kCapTiles + 2ull * (kCapTiles + kCapSegs) + 2ull * kCapChunks + kCapSplits +
+    return 3ull * kCapTiles + 2ull * (kCapTiles + kCapSegs) + 2ull * kCapChunks + 3ull * kCapSplits +
            4ull * kCapSegs;
 }
 
@@ -93,6 +93,10 @@ int get_workspace(int device, hipStream_t stream, Workspace **out) {
     ws->spR = w;
     w += kCapChunks;
     ws->splits = w;
+    w += kCapSplits;
+    ws->samples[0] = w;
+    w += kCapSplits;
+    ws->samples[1] = w;
     w += kCapSplits;
     ws->res = w;
     g_ws[key] = ws;

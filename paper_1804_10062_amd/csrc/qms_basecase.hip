@@ -55,6 +55,19 @@ __device__ __forceinline__ void cmpx(E &a, E &b, bool asc) {
     b = asc ? hi : lo;
 }
 
+// One side of a compare-exchange whose partner value is y: the smaller of the
+// two if keep_min, else the larger.  `bound` is 0 when keep_min and all ones
+// otherwise; for 32-bit elements the median of (x, y, bound) is then exactly
+// the kept value, a single v_med3_u32.
+__device__ __forceinline__ uint32_t keep_side(uint32_t x, uint32_t y, bool, uint32_t bound) {
+    return median3(x, y, bound);
+}
+__device__ __forceinline__ uint64_t keep_side(uint64_t x, uint64_t y, bool keep_min, uint64_t) {
+    const uint64_t mn = x < y ? x : y;
+    const uint64_t mx = x < y ? y : x;
+    return keep_min ? mn : mx;
+}
+
 // Padded LDS index of element e of the tile in natural order: one spare slot
 // every ITEMS slots, so that thread t reading its ITEMS consecutive elements
 // and lanes reading consecutive elements both avoid bank conflicts.
@@ -67,7 +80,8 @@ __device__ __forceinline__ uint32_t nat_idx(uint32_t e) {
 // the destination region (equal in place); len <= the tile size.
 template <class O, bool PAIRS>
 __device__ __forceinline__ void tile_sort_block(uint32_t *sk, uint32_t *sv, uint32_t *dk,
-                                                uint32_t *dv, uint32_t len, bool swap) {
+                                                uint32_t *dv, uint32_t len, bool swap,
+                                                uint32_t *samples) {
     using TE = TileElem<PAIRS>;
     using E = typename TE::E;
     constexpr int ITEMS = TE::ITEMS;
@@ -127,9 +141,10 @@ __device__ __forceinline__ void tile_sort_block(uint32_t *sk, uint32_t *sv, uint
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) r[i] = s[nat_idx<ITEMS>(base + i)];
 
-    // 3. runs of ITEMS in registers, alternating direction
+    // 3. runs of ITEMS / 2 in registers, alternating direction (fixed per
+    //    register, since base is a multiple of ITEMS)
 #pragma unroll
-    for (int k = 2; k <= ITEMS; k <<= 1) {
+    for (int k = 2; k < ITEMS; k <<= 1) {
 #pragma unroll
         for (int j = k >> 1; j >= 1; j >>= 1) {
 #pragma unroll
@@ -140,13 +155,14 @@ __device__ __forceinline__ void tile_sort_block(uint32_t *sk, uint32_t *sv, uint
         }
     }
 
-    // 4. merge stages.  During merge stage k a thread's keys are held
-    //    complemented when its k-block sorts descending (complementing
+    // 4. merge stages from k = ITEMS on, where the direction of a block
+    //    depends on the thread.  During merge stage k a thread's keys are
+    //    held complemented when its k-block sorts descending (complementing
     //    reverses the unsigned order), so every compare-exchange below is an
     //    ascending one; the representation changes only between stages.  At
     //    the last stage every block ascends and the keys are plain again.
     E cur_mask = E(0);
-    for (uint32_t k = 2 * ITEMS; k <= T; k <<= 1) {
+    for (uint32_t k = ITEMS; k <= T; k <<= 1) {
         const E mask = (base & k) == 0 ? E(0) : ~E(0);
         const E flip = mask ^ cur_mask;
         cur_mask = mask;
@@ -163,29 +179,23 @@ __device__ __forceinline__ void tile_sort_block(uint32_t *sk, uint32_t *sv, uint
             const uint32_t pt = tid ^ (j / ITEMS);
             const bool lower = (tid & (j / ITEMS)) == 0;
             const bool keep_min = asc == lower;
+            const E bound = keep_min ? E(0) : ~E(0);
 #pragma unroll
-            for (int i = 0; i < ITEMS; ++i) {
-                const E y = s[(uint32_t)i * NT + pt];
-                const E mn = r[i] < y ? r[i] : y;
-                const E mx = r[i] < y ? y : r[i];
-                r[i] = keep_min ? mn : mx;
-            }
+            for (int i = 0; i < ITEMS; ++i)
+                r[i] = keep_side(r[i], s[(uint32_t)i * NT + pt], keep_min, bound);
         }
         // partners in other lanes of the wave: exchange with shuffles
         for (; j >= (uint32_t)ITEMS; j >>= 1) {
             const uint32_t lm = j / ITEMS;
             const bool lower = (lane & lm) == 0;
             const bool keep_min = asc == lower;
+            const E bound = keep_min ? E(0) : ~E(0);
             // all exchanges of the stage first, so that they overlap
             E y[ITEMS];
 #pragma unroll
             for (int i = 0; i < ITEMS; ++i) y[i] = __shfl_xor(r[i], (int)lm, kWave);
 #pragma unroll
-            for (int i = 0; i < ITEMS; ++i) {
-                const E mn = r[i] < y[i] ? r[i] : y[i];
-                const E mx = r[i] < y[i] ? y[i] : r[i];
-                r[i] = keep_min ? mn : mx;
-            }
+            for (int i = 0; i < ITEMS; ++i) r[i] = keep_side(r[i], y[i], keep_min, bound);
         }
         // partners in the thread's own registers
 #pragma unroll
@@ -198,11 +208,14 @@ __device__ __forceinline__ void tile_sort_block(uint32_t *sk, uint32_t *sv, uint
         }
     }
 
-    // 5. back to natural order in LDS, coalesced stores
+    // 5. back to natural order in LDS, coalesced stores; every kMergeTile-th
+    //    key (order-mapped) is the sample the first merge level searches
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) s[nat_idx<ITEMS>(base + i)] = r[i];
     __syncthreads();
+    if (tid * (uint32_t)kMergeTile < len)
+        stg(samples + tid, TE::key(s[nat_idx<ITEMS>(tid * (uint32_t)kMergeTile)]));
 #pragma unroll 8
     for (int q = 0; q < ITEMS; ++q) {
         const uint32_t e = (uint32_t)q * NT + tid;
@@ -215,8 +228,11 @@ __device__ __forceinline__ void tile_sort_block(uint32_t *sk, uint32_t *sv, uint
 }
 
 // One workgroup per base tile of every Mergesort task in the table.
+// Samples: one word per kMergeTile keys of each task, at the task's merge
+// split offset (the base tile is a multiple of kMergeTile).
 template <class O, bool PAIRS>
-__global__ __launch_bounds__(kSortThreads) void k_tile_sort(TaskRef<SortSeg> tasks) {
+__global__ __launch_bounds__(kSortThreads) void k_tile_sort(TaskRef<SortSeg> tasks,
+                                                            uint32_t *samples) {
     constexpr uint32_t T = PAIRS ? kBaseTilePairs : kBaseTileKeys;
     uint32_t t, a;
     const SortSeg g = task_of(tasks, blockIdx.x, &t, &a);
@@ -226,25 +242,27 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_sort(TaskRef<SortSeg> tas
     const bool swap = (g.L & 1u) != 0;
     const uint32_t src = g.D + t0, dst = (swap ? g.Bf : g.D) + t0;
     tile_sort_block<O, PAIRS>(g.keys + src, PAIRS ? g.vals + src : nullptr, g.keys + dst,
-                              PAIRS ? g.vals + dst : nullptr, len, swap);
+                              PAIRS ? g.vals + dst : nullptr, len, swap,
+                              samples + g.split_off + t0 / kMergeTile);
 }
 
 template <class O, bool PAIRS>
 static hipError_t tile_sort_t(const TaskRef<SortSeg> &tasks, uint32_t tiles, double bytes,
-                              hipStream_t st) {
+                              const Workspace &ws, hipStream_t st) {
     if (tiles == 0) return hipSuccess;
     ProfScope prof(st, K_TILE_SORT, bytes);
-    hipLaunchKernelGGL((k_tile_sort<O, PAIRS>), dim3(tiles), dim3(kSortThreads), 0, st, tasks);
+    hipLaunchKernelGGL((k_tile_sort<O, PAIRS>), dim3(tiles), dim3(kSortThreads), 0, st, tasks,
+                       ws.samples[0]);
     return hipGetLastError();
 }
 
 hipError_t launch_tile_sort(int dt, bool pairs, const TaskRef<SortSeg> &tasks, uint32_t tiles,
-                            double bytes, hipStream_t st) {
+                            double bytes, const Workspace &ws, hipStream_t st) {
     if (dt == 1)
-        return pairs ? tile_sort_t<OrdF32, true>(tasks, tiles, bytes, st)
-                     : tile_sort_t<OrdF32, false>(tasks, tiles, bytes, st);
-    return pairs ? tile_sort_t<OrdU32, true>(tasks, tiles, bytes, st)
-                 : tile_sort_t<OrdU32, false>(tasks, tiles, bytes, st);
+        return pairs ? tile_sort_t<OrdF32, true>(tasks, tiles, bytes, ws, st)
+                     : tile_sort_t<OrdF32, false>(tasks, tiles, bytes, ws, st);
+    return pairs ? tile_sort_t<OrdU32, true>(tasks, tiles, bytes, ws, st)
+                 : tile_sort_t<OrdU32, false>(tasks, tiles, bytes, ws, st);
 }
 
 }  // namespace qms

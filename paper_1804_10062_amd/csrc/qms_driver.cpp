@@ -293,7 +293,7 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
         R.one = stab[0];
         R.tab = ar.dev<SortSeg>(o_st);
         R.pre = ar.dev<uint32_t>(o_pt);
-        hipError_t e = launch_tile_sort(dt, pairs, R, ptile[T], base_bytes, st);
+        hipError_t e = launch_tile_sort(dt, pairs, R, ptile[T], base_bytes, ws, st);
         if (e != hipSuccess) return hip_error(e, "base case");
         R.pre = ar.dev<uint32_t>(o_pm);
         for (uint32_t l = 0; l < maxL; ++l) {
@@ -305,7 +305,7 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
             }
             TaskRef<SortSeg> Rl = R;
             Rl.A = Al;
-            e = launch_merge_level(dt, pairs, Rl, l, pmerge[Al], mb, ws.splits, st);
+            e = launch_merge_level(dt, pairs, Rl, l, pmerge[Al], mb, ws, st);
             if (e != hipSuccess) return hip_error(e, "merge level");
         }
     }

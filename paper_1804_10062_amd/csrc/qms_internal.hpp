@@ -35,6 +35,7 @@ struct Workspace {
     uint32_t *spL = nullptr;     // [kCapChunks]
     uint32_t *spR = nullptr;     // [kCapChunks]
     uint32_t *splits = nullptr;  // [kCapSplits]
+    uint32_t *samples[2] = {nullptr, nullptr};  // [kCapSplits] each: run samples, by level parity
     uint64_t *meta = nullptr;    // [kCapSegs * M_COUNT]
     uint32_t *res = nullptr;     // [4 * kCapSegs] per-segment partition results
     // task tables: device copies of the host arena below
@@ -68,8 +69,8 @@ struct PartitionLaunch {
 
 hipError_t launch_partition_phase(int dt, bool pairs, const PartitionLaunch &L, hipStream_t st);
 hipError_t launch_tile_sort(int dt, bool pairs, const TaskRef<SortSeg> &tasks, uint32_t tiles,
-                            double bytes, hipStream_t st);
+                            double bytes, const Workspace &ws, hipStream_t st);
 hipError_t launch_merge_level(int dt, bool pairs, const TaskRef<SortSeg> &tasks, uint32_t level,
-                              uint32_t tiles, double bytes, uint32_t *splits, hipStream_t st);
+                              uint32_t tiles, double bytes, const Workspace &ws, hipStream_t st);
 
 }  // namespace qms

@@ -53,44 +53,23 @@ __device__ __forceinline__ void level_regions(const SortSeg &g, uint32_t level, 
     *dst = (level & 1u) ? r0 : r1;
 }
 
-// Merge-path split of diagonal d by binary search (one thread): the number
-// of elements of run A among the first d outputs of the stable merge of A
-// and B (ties taken from A first).
-template <class O>
-__device__ __forceinline__ uint64_t merge_path_thread(const uint32_t *A, uint64_t lenA,
-                                                      const uint32_t *B, uint64_t lenB,
-                                                      uint64_t d) {
-    uint64_t lo = d > lenB ? d - lenB : 0;
-    uint64_t hi = d < lenA ? d : lenA;
-    while (lo < hi) {
-        const uint64_t mid = (lo + hi) >> 1;
-        if (O::ord(ldg(A + mid)) <= O::ord(ldg(B + d - 1 - mid))) lo = mid + 1;
-        else hi = mid;
-    }
-    return lo;
-}
-
-// The same split searched by kSplitLanes lanes together: each step the lanes
-// probe kSplitLanes evenly spaced candidates and a ballot narrows the range
-// kSplitLanes-fold.  Fewer dependent steps than the binary search (the split
-// kernel is latency-bound) for a few more probes.
-template <class O>
-__device__ __forceinline__ uint64_t merge_path_group(const uint32_t *A, uint64_t lenA,
-                                                     const uint32_t *B, uint64_t lenB, uint64_t d,
-                                                     bool active) {
+// First index in [lo, hi) where the prefix-true predicate pred fails (hi if
+// it holds everywhere), searched by kSplitLanes lanes together: each step the
+// lanes probe kSplitLanes evenly spaced candidates and a ballot narrows the
+// range kSplitLanes-fold.  Fewer dependent steps than a binary search for a
+// few more probes.  Every lane of the wave calls it; inactive groups pass an
+// empty range.
+template <class F>
+__device__ __forceinline__ uint64_t group_first_false(uint64_t lo, uint64_t hi, F pred) {
     constexpr uint32_t G = kSplitLanes;
     const uint32_t sub = lane_id() % G;
     const uint32_t gshift = (lane_id() / G) * G;
-    uint64_t lo = d > lenB ? d - lenB : 0;
-    uint64_t hi = d < lenA ? d : lenA;
-    if (!active) lo = hi = 0;
     // every lane of the wave loops while any group still searches
     while (__ballot(hi > lo) != 0) {
         const uint64_t step = hi > lo ? (hi - lo + G - 1) / G : 1;
         const uint64_t i = lo + (uint64_t)sub * step;
-        bool pred = false;
-        if (i < hi) pred = O::ord(ldg(A + i)) <= O::ord(ldg(B + d - 1 - i));
-        const uint64_t bits = (__ballot(pred) >> gshift) & ((1ull << G) - 1);
+        const bool t = i < hi && pred(i);
+        const uint64_t bits = (__ballot(t) >> gshift) & ((1ull << G) - 1);
         const int c = __popcll(bits);
         if (hi > lo) {
             const uint64_t nlo = c > 0 ? lo + (uint64_t)(c - 1) * step + 1 : lo;
@@ -102,13 +81,24 @@ __device__ __forceinline__ uint64_t merge_path_group(const uint32_t *A, uint64_t
     return lo;
 }
 
-// kSplitLanes lanes per merge tile: the split at the tile's first output.  A
-// wave-wide 64-way search would touch over ten times more cache lines than a
-// binary search, which costs more than its lower latency saves once there are
-// thousands of splits; a few lanes per split sit in between.
+// kSplitLanes lanes per merge tile: the merge-path split at the tile's first
+// output d, i.e. the number c of elements of run A among the first d outputs
+// (c = the first i with A[i] > B[d - 1 - i], within the diagonal's range
+// [lo, hi]).  The search runs in two stages:
+//   coarse  on the samples of the runs (every kMergeTile-th element, written
+//           by the previous level or the base case; a small array that stays
+//           in cache): with S = kMergeTile and d a multiple of S, the test
+//           Q(u): uS <= hi and (d - uS >= |B| or A[(u-1)S] <= B[d - uS])
+//           only reads samples, holds whenever c >= uS, and is prefix-true;
+//           for the last u1 with Q(u1), (u1 - 1) S < c < (u1 + 1) S;
+//   fine    on the runs, inside that window of fewer than 2S candidates.
+// The 4-lane searches beat both a one-lane binary search (latency) and a
+// wave-wide one (cache lines touched) once there are thousands of splits.
 template <class O>
 __global__ __launch_bounds__(kBlock) void k_merge_split(TaskRef<SortSeg> tasks, uint32_t level,
-                                                        uint32_t total, uint32_t *splits) {
+                                                        uint32_t total, uint32_t *splits,
+                                                        const uint32_t *samples) {
+    constexpr uint64_t S = kMergeTile;
     const uint32_t gid = blockIdx.x * kBlock + threadIdx.x;
     const uint32_t w = gid / kSplitLanes;
     const bool active = w < total;
@@ -119,20 +109,32 @@ __global__ __launch_bounds__(kBlock) void k_merge_split(TaskRef<SortSeg> tasks, 
     const uint64_t W = (uint64_t)g.w0 << level;
     const MergeTileGeom geo = merge_geom(g.m, W, tile);
     const uint32_t *A = g.keys + src + geo.pb;
-    uint64_t i;
-    if constexpr (kSplitLanes == 1) {
-        if (!active) return;
-        i = merge_path_thread<O>(A, geo.lenA, A + W, geo.lenB, geo.d0);
-    } else {
-        i = merge_path_group<O>(A, geo.lenA, A + W, geo.lenB, geo.d0, active);
-    }
-    if (active && gid % kSplitLanes == 0) splits[g.split_off + tile] = (uint32_t)i;
+    const uint32_t *B = A + W;
+    const uint32_t *As = samples + g.split_off + geo.pb / S;
+    const uint32_t *Bs = As + W / S;
+    const uint64_t d = geo.d0, nA = geo.lenA, nB = geo.lenB;
+    uint64_t lo = d > nB ? d - nB : 0;
+    uint64_t hi = d < nA ? d : nA;
+    if (!active) lo = hi = 0;
+    // coarse: first u in [1, hi / S] without Q(u)
+    const uint64_t f = group_first_false(1, active ? hi / S + 1 : 1, [&](uint64_t u) {
+        return d - u * S >= nB || ldg(As + u - 1) <= ldg(Bs + (d - u * S) / S);
+    });
+    const uint64_t u1 = f - 1;
+    const uint64_t wl = u1 >= 1 ? max(lo, (u1 - 1) * S + 1) : lo;
+    const uint64_t wh = min(hi, (u1 + 1) * S - 1);
+    // fine: the first i in [wl, wh) with A[i] > B[d - 1 - i], else wh
+    const uint64_t c = group_first_false(wl, wh, [&](uint64_t i) {
+        return O::ord(ldg(A + i)) <= O::ord(ldg(B + d - 1 - i));
+    });
+    if (active && gid % kSplitLanes == 0) splits[g.split_off + tile] = (uint32_t)c;
 }
 
 template <class O, bool PAIRS>
 __device__ __forceinline__ void merge_block(uint32_t *S, uint32_t *SV, uint32_t *D,
                                             uint32_t *DV, uint64_t m, uint64_t W,
-                                            uint64_t tile, const uint32_t *splits) {
+                                            uint64_t tile, const uint32_t *splits,
+                                            uint32_t *samples_out) {
     __shared__ uint32_t sk[kMergeTile];
     __shared__ uint32_t sv[PAIRS ? kMergeTile : 1];
     const uint32_t tid = threadIdx.x;
@@ -223,6 +225,8 @@ __device__ __forceinline__ void merge_block(uint32_t *S, uint32_t *SV, uint32_t 
         }
     }
     __syncthreads();
+    // the tile's first output is the sample the next level's split search uses
+    if (tid == 0) stg(samples_out + tile, sk[0]);
 #pragma unroll
     for (int q = 0; q < kMergePerThread; ++q) {
         const uint32_t e = q * kBlock + tid;
@@ -238,7 +242,8 @@ __device__ __forceinline__ void merge_block(uint32_t *S, uint32_t *SV, uint32_t 
 
 template <class O, bool PAIRS>
 __global__ __launch_bounds__(kBlock) void k_merge(TaskRef<SortSeg> tasks, uint32_t level,
-                                                  const uint32_t *splits) {
+                                                  const uint32_t *splits,
+                                                  uint32_t *samples_out) {
     uint32_t tile, a;
     const SortSeg g = task_of(tasks, blockIdx.x, &tile, &a);
     if (tile * (uint64_t)kMergeTile >= g.m) return;
@@ -246,35 +251,39 @@ __global__ __launch_bounds__(kBlock) void k_merge(TaskRef<SortSeg> tasks, uint32
     level_regions(g, level, &src, &dst);
     merge_block<O, PAIRS>(g.keys + src, PAIRS ? g.vals + src : nullptr, g.keys + dst,
                           PAIRS ? g.vals + dst : nullptr, g.m, (uint64_t)g.w0 << level,
-                          tile, splits + g.split_off);
+                          tile, splits + g.split_off, samples_out + g.split_off);
 }
 
 template <class O, bool PAIRS>
 static hipError_t merge_t(const TaskRef<SortSeg> &tasks, uint32_t level, uint32_t tiles,
-                          double bytes, uint32_t *splits, hipStream_t st) {
+                          double bytes, const Workspace &ws, hipStream_t st) {
     if (tiles == 0) return hipSuccess;
+    // level l searches the samples written by level l - 1 (or the base case)
+    // and writes the other array
+    const uint32_t *smp_in = ws.samples[level & 1];
+    uint32_t *smp_out = ws.samples[(level + 1) & 1];
     {
         ProfScope prof(st, K_MERGE_SPLIT, 0.0);
         const uint64_t threads = (uint64_t)tiles * kSplitLanes;
         hipLaunchKernelGGL((k_merge_split<O>), dim3((uint32_t)((threads + kBlock - 1) / kBlock)),
-                           dim3(kBlock), 0, st, tasks, level, tiles, splits);
+                           dim3(kBlock), 0, st, tasks, level, tiles, ws.splits, smp_in);
     }
     {
         // per element: read the run cell and the window cell, write both
         ProfScope prof(st, K_MERGE, bytes);
         hipLaunchKernelGGL((k_merge<O, PAIRS>), dim3(tiles), dim3(kBlock), 0, st, tasks, level,
-                           (const uint32_t *)splits);
+                           (const uint32_t *)ws.splits, smp_out);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_merge_level(int dt, bool pairs, const TaskRef<SortSeg> &tasks, uint32_t level,
-                              uint32_t tiles, double bytes, uint32_t *splits, hipStream_t st) {
+                              uint32_t tiles, double bytes, const Workspace &ws, hipStream_t st) {
     if (dt == 1)
-        return pairs ? merge_t<OrdF32, true>(tasks, level, tiles, bytes, splits, st)
-                     : merge_t<OrdF32, false>(tasks, level, tiles, bytes, splits, st);
-    return pairs ? merge_t<OrdU32, true>(tasks, level, tiles, bytes, splits, st)
-                 : merge_t<OrdU32, false>(tasks, level, tiles, bytes, splits, st);
+        return pairs ? merge_t<OrdF32, true>(tasks, level, tiles, bytes, ws, st)
+                     : merge_t<OrdF32, false>(tasks, level, tiles, bytes, ws, st);
+    return pairs ? merge_t<OrdU32, true>(tasks, level, tiles, bytes, ws, st)
+                 : merge_t<OrdU32, false>(tasks, level, tiles, bytes, ws, st);
 }
 
 }  // namespace qms

@@ -21,9 +21,10 @@
 //   count   one workgroup per tile: #(< p) and #(== p) of the tile;
 //   scan    one workgroup: totals, boundary, per-tile misplaced counts and
 //           their exclusive prefix sums (ranks of each tile's first misplaced
-//           element on either side);
+//           element on either side), and for every chunk boundary (rank
+//           j * rc) the tile that holds it;
 //   split   one wave per chunk boundary and side: the exact position of the
-//           misplaced element of rank j * kRankChunk;
+//           misplaced element of rank j * rc inside that tile;
 //   swap    one workgroup per chunk: reads exactly the position ranges of its
 //           ranks on both sides (coalesced, wave-striped), compacts the
 //           misplaced elements with ballot + prefix counts into LDS, and
@@ -125,68 +126,164 @@ __global__ __launch_bounds__(kBlock) void k_part_count(TaskRef<PartSeg> tasks, u
     }
 }
 
-// count keys with ord(k) < p and == p in [a, b) with the whole block
+// count keys with ord(k) < p and == p in [a, b) (a < b) with the whole
+// block, four clamped loads per thread in flight
 template <class O>
 __device__ __forceinline__ void block_count_range(const uint32_t *keys, uint64_t a, uint64_t b,
                                                   uint32_t p, uint32_t *lt_out,
                                                   uint32_t *eq_out, uint32_t *tmp) {
     uint32_t lt = 0, eq = 0;
-    for (uint64_t pos = a + threadIdx.x; pos < b; pos += blockDim.x) {
-        const uint32_t k = O::ord(keys[pos]);
-        lt += k < p;
-        eq += k == p;
+    const uint64_t nth = blockDim.x;
+    for (uint64_t base = a; base < b; base += 4 * nth) {
+        uint32_t k[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint64_t pos = base + q * nth + threadIdx.x;
+            k[q] = ldg(keys + (pos < b ? pos : b - 1));
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint64_t pos = base + q * nth + threadIdx.x;
+            const uint32_t x = O::ord(k[q]);
+            lt += pos < b && x < p;
+            eq += pos < b && x == p;
+        }
     }
     *lt_out = block_sum(lt, tmp);
     *eq_out = block_sum(eq, tmp);
 }
 
-// Exclusive prefix sums of the per-tile misplaced counts of both sides, the
-// tiles split among the block's threads in contiguous runs.  mis(t, &l, &r)
-// gives tile t's counts.  Returns the total of the left side.
-template <class F>
-__device__ __forceinline__ uint32_t scan_misplaced(uint32_t nt, F mis, uint32_t *preL,
-                                                   uint32_t *preR, uint32_t *tmp) {
-    const uint32_t per = (nt + blockDim.x - 1) / blockDim.x;
-    const uint32_t t0 = threadIdx.x * per;
-    const uint32_t t1 = t0 + per < nt ? t0 + per : nt;
-    uint32_t sl = 0, sr = 0;
-    for (uint32_t t = t0; t < t1; ++t) {
-        uint32_t l, r;
-        mis(t, &l, &r);
-        sl += l;
-        sr += r;
+// Exclusive prefix sums of the per-tile misplaced counts of both sides.  The
+// per-tile words are staged through LDS in chunks of NTH * kScanPer tiles
+// (coalesced loads, all in flight); each thread then scans kScanPer
+// consecutive tiles of the chunk.  ld(t) gives tile t's words, mis(t, w, &l,
+// &r) its counts from them.  Returns the left side's total.
+constexpr int kScanPer = 8;
+template <int NTH>
+struct ScanStage {
+    uint2 w[NTH * kScanPer + NTH];  // one spare slot every kScanPer (bank spread)
+};
+template <int NTH, class LD, class MIS>
+__device__ __forceinline__ uint32_t scan_misplaced(uint32_t nt, LD ld, MIS mis, uint32_t *preL,
+                                                   uint32_t *preR, ScanStage<NTH> &stage,
+                                                   uint32_t *tmp) {
+    constexpr uint32_t C = (uint32_t)NTH * kScanPer;
+    const uint32_t tid = threadIdx.x;
+    uint32_t carryL = 0, carryR = 0;
+    for (uint32_t c0 = 0; c0 < nt; c0 += C) {
+        uint2 v[kScanPer];
+#pragma unroll
+        for (int q = 0; q < kScanPer; ++q) {
+            const uint32_t t = c0 + (uint32_t)q * NTH + tid;
+            v[q] = ld(t < nt ? t : nt - 1);
+        }
+#pragma unroll
+        for (int q = 0; q < kScanPer; ++q) {
+            const uint32_t e = (uint32_t)q * NTH + tid;
+            stage.w[e + e / kScanPer] = v[q];
+        }
+        __syncthreads();
+        uint32_t l[kScanPer], r[kScanPer], sl = 0, sr = 0;
+#pragma unroll
+        for (int i = 0; i < kScanPer; ++i) {
+            const uint32_t e = tid * kScanPer + (uint32_t)i;
+            l[i] = r[i] = 0;
+            if (c0 + e < nt) mis(c0 + e, stage.w[e + e / kScanPer], &l[i], &r[i]);
+            sl += l[i];
+            sr += r[i];
+        }
+        // the scans end with a barrier, after which the stage may be refilled
+        uint32_t totL, totR;
+        uint32_t offL = carryL + block_exclusive_scan(sl, tmp, &totL);
+        uint32_t offR = carryR + block_exclusive_scan(sr, tmp, &totR);
+#pragma unroll
+        for (int i = 0; i < kScanPer; ++i) {
+            const uint32_t t = c0 + tid * kScanPer + (uint32_t)i;
+            if (t < nt) {
+                stg(preL + t, offL);
+                stg(preR + t, offR);
+            }
+            offL += l[i];
+            offR += r[i];
+        }
+        carryL += totL;
+        carryR += totR;
     }
-    uint32_t totL, totR;
-    uint32_t offL = block_exclusive_scan(sl, tmp, &totL);
-    uint32_t offR = block_exclusive_scan(sr, tmp, &totR);
-    for (uint32_t t = t0; t < t1; ++t) {
-        uint32_t l, r;
-        mis(t, &l, &r);
-        preL[t] = offL;
-        preR[t] = offR;
-        offL += l;
-        offR += r;
+    if (tid == 0) {
+        stg(preL + nt, carryL);
+        stg(preR + nt, carryR);
     }
-    if (threadIdx.x == 0) {
-        preL[nt] = totL;
-        preR[nt] = totR;
+    return carryL;
+}
+
+// Chunk boundaries j = 1 .. nch - 1 lie at the misplaced elements of rank
+// j * rc of each side.  For every tile, record for each boundary whose rank
+// falls in the tile the tile and the boundary's rank inside it, encoded as
+// t * TP + k (< the range size); k_part_split turns it into a position.
+// Reads the prefixes the block has just written.
+template <int NTH>
+__device__ __forceinline__ void mark_chunk_tiles(uint32_t nt, uint32_t TP, uint32_t rc,
+                                                 uint32_t nch, const uint32_t *preL,
+                                                 const uint32_t *preR, uint32_t *spL,
+                                                 uint32_t *spR) {
+    __syncthreads();  // prefixes written by other threads of the block
+    if (nch <= 1) return;
+    auto mark = [&](uint32_t *sp, uint32_t a, uint32_t b, uint32_t t) {
+        uint64_t j = ((uint64_t)a + rc - 1) / rc;
+        if (j == 0) j = 1;
+        for (; j < nch && j * rc < b; ++j) stg(sp + j, (uint32_t)((uint64_t)t * TP + (j * rc - a)));
+    };
+    constexpr uint32_t C = (uint32_t)NTH * 4;
+    for (uint32_t c0 = 0; c0 < nt; c0 += C) {
+        uint32_t l0[4], l1[4], r0[4], r1[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            uint32_t t = c0 + (uint32_t)q * NTH + threadIdx.x;
+            t = t < nt ? t : nt - 1;
+            l0[q] = ldg(preL + t);
+            l1[q] = ldg(preL + t + 1);
+            r0[q] = ldg(preR + t);
+            r1[q] = ldg(preR + t + 1);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t t = c0 + (uint32_t)q * NTH + threadIdx.x;
+            if (t < nt) {
+                if (l1[q] > l0[q]) mark(spL, l0[q], l1[q], t);
+                if (r1[q] > r0[q]) mark(spR, r0[q], r1[q], t);
+            }
+        }
     }
-    return totL;
 }
 
 // ---- scan of pass A ----------------------------------------------------------
-// One workgroup per segment.  res[4 a + 0..2] = (#<p, #==p, pass-A pairs) for
-// the host.
-template <class O>
-__global__ void k_part_scan_a(TaskRef<PartSeg> tasks, uint32_t TP, const uint32_t *cnt_lt_all,
-                              const uint32_t *cnt_eq_all, uint32_t *preL_all,
-                              uint32_t *preR_all, uint32_t *eqmv_all, uint32_t *spL_all,
-                              uint32_t *spR_all, uint64_t *meta_all, uint32_t *res) {
-    __shared__ uint32_t tmp[kScanThreads / kWave + 1];
-    __shared__ uint64_t tmp64[kScanThreads / kWave + 1];
+// One workgroup of NTH threads per segment, two passes over the tiles.
+//   1. P[t] = #(< p) in tiles before t (exclusive prefix, written over
+//      cnt_lt, which nothing reads later), the totals c_lt and c_eq; eqmv
+//      is cleared for pass A.
+//   2. With B1 = c_lt in tile tb and lt_part = #(< p) in [tb TP, B1), every
+//      tile left of tb is full and wholly left of B1, so the misplaced
+//      ranks have closed forms:
+//        preL[t] = t TP - P[t]                (t <= tb),  X  (t > tb)
+//        preR[t] = 0                          (t <= tb),  P[t] - P[tb] - lt_part  (t > tb)
+//      with X = c_lt - P[tb] - lt_part pairs.  The pass writes them and
+//      records the tile of every chunk boundary.
+// res[4 a + 0..2] = (#<p, #==p, pass-A pairs) for the host.
+template <class O, int NTH>
+__global__ __launch_bounds__(NTH) void k_part_scan_a(TaskRef<PartSeg> tasks, uint32_t TP,
+                                                     uint32_t *cnt_lt_all,
+                                                     const uint32_t *cnt_eq_all,
+                                                     uint32_t *preL_all, uint32_t *preR_all,
+                                                     uint32_t *eqmv_all, uint32_t *spL_all,
+                                                     uint32_t *spR_all, uint64_t *meta_all,
+                                                     uint32_t *res) {
+    constexpr int PER = kScanPer;
+    constexpr uint32_t C = (uint32_t)NTH * PER;
+    __shared__ uint32_t tmp[NTH / kWave + 1];
+    __shared__ ScanStage<NTH> stage;
     const PartSeg g = seg_by_index(tasks, blockIdx.x);
     const uint32_t *keys = g.keys + g.lo;
-    const uint32_t *cnt_lt = cnt_lt_all + g.tile_off;
+    uint32_t *P = cnt_lt_all + g.tile_off;
     const uint32_t *cnt_eq = cnt_eq_all + g.tile_off;
     uint32_t *preL = preL_all + g.tile_off + g.slot;
     uint32_t *preR = preR_all + g.tile_off + g.slot;
@@ -194,16 +291,47 @@ __global__ void k_part_scan_a(TaskRef<PartSeg> tasks, uint32_t TP, const uint32_
     uint64_t *meta = meta_all + (uint64_t)g.slot * M_COUNT;
     const uint32_t nt = g.nt;
     const uint64_t s = g.s;
+    const uint32_t tid = threadIdx.x;
     const uint32_t p = (g.flags & kPivotFromSample) ? (uint32_t)meta[M_PIVOT]
                                                     : pivot_of<O>(keys, 0, s);
-    uint64_t slt = 0, seq = 0;
-    for (uint32_t t = threadIdx.x; t < nt; t += blockDim.x) {
-        slt += cnt_lt[t];
-        seq += cnt_eq[t];
-        eqmv[t] = 0;
+    // pass 1
+    uint32_t carry = 0, seq = 0;
+    for (uint32_t c0 = 0; c0 < nt; c0 += C) {
+        uint2 v[PER];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const uint32_t t = c0 + (uint32_t)q * NTH + tid;
+            const uint32_t tc = t < nt ? t : nt - 1;
+            v[q] = make_uint2(ldg(P + tc), ldg(cnt_eq + tc));
+        }
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const uint32_t e = (uint32_t)q * NTH + tid;
+            stage.w[e + e / PER] = v[q];
+            if (c0 + e < nt) stg(eqmv + c0 + e, 0u);
+        }
+        __syncthreads();
+        uint32_t lt[PER], sl = 0;
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const uint32_t e = tid * PER + (uint32_t)i;
+            const uint2 w = c0 + e < nt ? stage.w[e + e / PER] : make_uint2(0u, 0u);
+            lt[i] = w.x;
+            sl += w.x;
+            seq += w.y;
+        }
+        uint32_t tot;
+        uint32_t off = carry + block_exclusive_scan(sl, tmp, &tot);  // ends with a barrier
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const uint32_t t = c0 + tid * PER + (uint32_t)i;
+            if (t < nt) stg(P + t, off);
+            off += lt[i];
+        }
+        carry += tot;
     }
-    const uint64_t c_lt = block_sum(slt, tmp64);
-    const uint64_t c_eq_all = block_sum(seq, tmp64);
+    const uint64_t c_lt = carry;
+    const uint64_t c_eq_all = block_sum(seq, tmp);
     // Keys equal to the pivot get a block of their own (pass B) only when
     // there are many of them, or when nothing is smaller than the pivot (then
     // excluding them is what makes the round progress).  Otherwise they stay
@@ -211,28 +339,54 @@ __global__ void k_part_scan_a(TaskRef<PartSeg> tasks, uint32_t TP, const uint32_
     // round still removes at least one key from the range (the "< p" side).
     const bool eq_block = c_lt == 0 || c_eq_all > kEqBlockMin + s / 4096;
     const uint64_t c_eq = eq_block ? c_eq_all : 0;
-    const uint64_t tb = c_lt / TP;  // tile holding B1 (tb < nt since c_lt < s)
+    const uint32_t tb = (uint32_t)(c_lt / TP);  // tile holding B1 (tb < nt since c_lt < s)
     uint32_t lt_part = 0, eq_part = 0;
-    if (c_lt % TP != 0) block_count_range<O>(keys, tb * TP, c_lt, p, &lt_part, &eq_part, tmp);
-    auto mis = [&](uint32_t t, uint32_t *l, uint32_t *r) {
-        const uint64_t ts = (uint64_t)t * TP;
-        const uint32_t sz = (uint32_t)((ts + TP < s ? ts + TP : s) - ts);
-        if (t < tb) {
-            *l = sz - cnt_lt[t];
-            *r = 0;
-        } else if (t == tb) {
-            *l = (uint32_t)(c_lt - ts) - lt_part;
-            *r = cnt_lt[t] - lt_part;
-        } else {
-            *l = 0;
-            *r = cnt_lt[t];
-        }
+    if (c_lt % TP != 0) block_count_range<O>(keys, (uint64_t)tb * TP, c_lt, p, &lt_part, &eq_part, tmp);
+    __syncthreads();  // P written by other threads of the block
+    const uint32_t Ptb = ldg(P + tb);
+    const uint32_t X = (uint32_t)c_lt - Ptb - lt_part;
+    const uint32_t rc = rank_chunk(X, s);
+    const uint32_t nch = (uint32_t)chunk_count(X, s);
+    uint32_t *spL = spL_all + g.chunk_off, *spR = spR_all + g.chunk_off;
+    // pass 2
+    auto prefix_at = [&](uint32_t t, uint32_t Pt, uint32_t *l, uint32_t *r) {
+        *l = t <= tb ? t * TP - Pt : X;
+        *r = t <= tb ? 0u : Pt - Ptb - lt_part;
     };
-    const uint32_t X = scan_misplaced(nt, mis, preL, preR, tmp);
-    if (threadIdx.x == 0) {
-        const uint32_t nch = (uint32_t)chunk_count(X, s);
-        uint32_t *spL = spL_all + g.chunk_off, *spR = spR_all + g.chunk_off;
-        meta[M_RCA] = rank_chunk(X, s);
+    auto mark = [&](uint32_t *sp, uint32_t a, uint32_t b, uint32_t t) {
+        uint64_t j = ((uint64_t)a + rc - 1) / rc;
+        if (j == 0) j = 1;
+        for (; j < nch && j * rc < b; ++j) stg(sp + j, (uint32_t)((uint64_t)t * TP + (j * rc - a)));
+    };
+    for (uint32_t c0 = 0; c0 < nt; c0 += C) {
+        uint32_t p0[PER], p1[PER];
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const uint32_t t = c0 + (uint32_t)q * NTH + tid;
+            const uint32_t tc = t < nt ? t : nt - 1;
+            p0[q] = ldg(P + tc);
+            p1[q] = tc + 1 < nt ? ldg(P + tc + 1) : (uint32_t)c_lt;
+        }
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const uint32_t t = c0 + (uint32_t)q * NTH + tid;
+            if (t < nt) {
+                uint32_t l0, r0, l1, r1;
+                prefix_at(t, p0[q], &l0, &r0);
+                prefix_at(t + 1, p1[q], &l1, &r1);
+                stg(preL + t, l0);
+                stg(preR + t, r0);
+                if (t == nt - 1) {
+                    stg(preL + nt, l1);
+                    stg(preR + nt, r1);
+                }
+                if (nch > 1 && l1 > l0) mark(spL, l0, l1, t);
+                if (nch > 1 && r1 > r0) mark(spR, r0, r1, t);
+            }
+        }
+    }
+    if (tid == 0) {
+        meta[M_RCA] = rc;
         meta[M_PIVOT] = p;
         meta[M_CLT] = c_lt;
         meta[M_CEQ] = c_eq;
@@ -257,11 +411,15 @@ __global__ void k_part_scan_a(TaskRef<PartSeg> tasks, uint32_t TP, const uint32_
 // right of B1 are the ones it held before (they did not move) plus the ones
 // pass A moved in (eqmv).  One workgroup per segment; segments without
 // possible pass-B pairs return at once.
-template <class O>
-__global__ void k_part_scan_b(TaskRef<PartSeg> tasks, uint32_t TP, const uint32_t *cnt_eq_all,
-                              const uint32_t *eqmv_all, uint32_t *preL_all, uint32_t *preR_all,
-                              uint32_t *spL_all, uint32_t *spR_all, uint64_t *meta_all) {
-    __shared__ uint32_t tmp[kScanThreads / kWave + 1];
+template <class O, int NTH>
+__global__ __launch_bounds__(NTH) void k_part_scan_b(TaskRef<PartSeg> tasks, uint32_t TP,
+                                                     const uint32_t *cnt_eq_all,
+                                                     const uint32_t *eqmv_all,
+                                                     uint32_t *preL_all, uint32_t *preR_all,
+                                                     uint32_t *spL_all, uint32_t *spR_all,
+                                                     uint64_t *meta_all) {
+    __shared__ uint32_t tmp[NTH / kWave + 1];
+    __shared__ ScanStage<NTH> stage;
     const PartSeg g = seg_by_index(tasks, blockIdx.x);
     uint64_t *meta = meta_all + (uint64_t)g.slot * M_COUNT;
     const uint64_t s = g.s;
@@ -286,7 +444,8 @@ __global__ void k_part_scan_b(TaskRef<PartSeg> tasks, uint32_t TP, const uint32_
         const uint64_t a = tb2 * TP > b1 ? tb2 * TP : b1;
         block_count_range<O>(keys, a, b2, p, &dummy, &eq_part2, tmp);
     }
-    auto mis = [&](uint32_t t, uint32_t *l, uint32_t *r) {
+    auto ld = [&](uint32_t t) { return make_uint2(ldg(cnt_eq + t), ldg(eqmv + t)); };
+    auto mis = [&](uint32_t t, uint2 w, uint32_t *l, uint32_t *r) {
         if (t < tb) {
             *l = 0;
             *r = 0;
@@ -295,7 +454,7 @@ __global__ void k_part_scan_b(TaskRef<PartSeg> tasks, uint32_t TP, const uint32_
         const uint64_t ts = (uint64_t)t * TP;
         const uint64_t te = ts + TP < s ? ts + TP : s;
         const uint64_t a0 = ts > b1 ? ts : b1;
-        const uint32_t le = (t == tb ? cnt_eq[t] - eq_part : cnt_eq[t]) + eqmv[t];
+        const uint32_t le = (t == tb ? w.x - eq_part : w.x) + w.y;
         const uint64_t aend = te < b2 ? te : b2;
         const uint32_t szA = aend > a0 ? (uint32_t)(aend - a0) : 0;
         const bool hasB = te > (ts > b2 ? ts : b2);
@@ -303,11 +462,13 @@ __global__ void k_part_scan_b(TaskRef<PartSeg> tasks, uint32_t TP, const uint32_
         *l = szA - leA;
         *r = le - leA;
     };
-    const uint32_t X = scan_misplaced(nt, mis, preL, preR, tmp);
+    const uint32_t X = scan_misplaced<NTH>(nt, ld, mis, preL, preR, stage, tmp);
+    const uint32_t rc = rank_chunk(X, s);
+    const uint32_t nch = (uint32_t)chunk_count(X, s);
+    uint32_t *spL = spL_all + g.chunk_off, *spR = spR_all + g.chunk_off;
+    mark_chunk_tiles<NTH>(nt, TP, rc, nch, preL, preR, spL, spR);
     if (threadIdx.x == 0) {
-        const uint32_t nch = (uint32_t)chunk_count(X, s);
-        uint32_t *spL = spL_all + g.chunk_off, *spR = spR_all + g.chunk_off;
-        meta[M_RCB] = rank_chunk(X, s);
+        meta[M_RCB] = rc;
         meta[M_XB] = X;
         spL[0] = (uint32_t)b1;
         spL[nch] = (uint32_t)b2;
@@ -346,13 +507,15 @@ __device__ __forceinline__ bool belongs_left(uint32_t k, uint32_t p) {
 }
 
 // ---- split: position of the first misplaced element of every chunk ----------
-// One wave per (chunk boundary j >= 1, side).  The host gives each segment an
-// upper bound of 2 (chunks - 1) waves; surplus waves return.
+// One wave per (chunk boundary j >= 1, side).  The scan recorded the tile
+// holding the boundary and its rank k inside the tile; the wave finds the k-th
+// misplaced element of the tile's part of the region and replaces the record
+// with its position.  The host gives each segment an upper bound of
+// 2 (chunks - 1) waves; surplus waves return.
 template <class O, int PASS>
 __global__ __launch_bounds__(kBlock) void k_part_split(TaskRef<PartSeg> tasks, uint32_t TP,
-                                                       uint32_t total, const uint32_t *preL_all,
-                                                       const uint32_t *preR_all,
-                                                       uint32_t *spL_all, uint32_t *spR_all,
+                                                       uint32_t total, uint32_t *spL_all,
+                                                       uint32_t *spR_all,
                                                        const uint64_t *meta_all) {
     const uint32_t gw = blockIdx.x * kWaves + wave_id();
     if (gw >= total) return;
@@ -367,54 +530,47 @@ __global__ __launch_bounds__(kBlock) void k_part_split(TaskRef<PartSeg> tasks, u
     const int side = (int)(w & 1);
     if (j >= nch) return;
     const uint32_t *keys = g.keys + g.lo;
-    const uint32_t nt = g.nt;
     const uint32_t p = (uint32_t)meta[M_PIVOT];
     const uint64_t s = g.s;
     const PassGeom geo = pass_geom<PASS>(meta, s);
-    const uint32_t *pre = (side ? preR_all : preL_all) + g.tile_off + g.slot;
-    const uint32_t r = (uint32_t)(j * rc);
-    // largest t with pre[t] <= r (pre[0] = 0 <= r < pre[nt] = X)
-    uint32_t lo = 0, hi = nt;
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (pre[mid] <= r) lo = mid;
-        else hi = mid;
-    }
-    const uint32_t t = lo;
-    uint32_t k = r - pre[t];
+    uint32_t *sp = (side ? spR_all : spL_all) + g.chunk_off;
+    const uint32_t rec = sp[j];
+    const uint32_t t = rec / TP;
+    uint32_t k = rec - t * TP;
     const uint64_t ts = (uint64_t)t * TP;
     const uint64_t te = ts + TP < s ? ts + TP : s;
     const uint64_t reg0 = side ? geo.r0 : geo.l0, reg1 = side ? geo.r1 : geo.l1;
     const uint64_t x0 = ts > reg0 ? ts : reg0;
     const uint64_t x1 = te < reg1 ? te : reg1;
     const int lane = lane_id();
-    uint32_t *sp = (side ? spR_all : spL_all) + g.chunk_off;
-    // the wave walks the tile 1024 elements a step, 16 consecutive per lane
-    constexpr int kPer = 16;
-    for (uint64_t base = x0; base < x1; base += kWave * kPer) {
-        const uint64_t lb = base + (uint64_t)lane * kPer;
-        uint32_t kv[kPer];
+    // the wave walks the part 1024 positions a step, lane-interleaved
+    // (coalesced loads, all in flight), and counts misplaced elements with
+    // ballots
+    constexpr int kQ = 16;
+    for (uint64_t base = x0; base < x1; base += kWave * kQ) {
+        uint32_t kv[kQ];
 #pragma unroll
-        for (int q = 0; q < kPer; ++q) kv[q] = ldg(keys + (lb + q < x1 ? lb + q : x1 - 1));
-        uint32_t flags = 0;
+        for (int q = 0; q < kQ; ++q) {
+            const uint64_t pos = base + (uint64_t)q * kWave + lane;
+            kv[q] = ldg(keys + (pos < x1 ? pos : x1 - 1));
+        }
+        uint64_t m[kQ];
 #pragma unroll
-        for (int q = 0; q < kPer; ++q) {
+        for (int q = 0; q < kQ; ++q) {
+            const uint64_t pos = base + (uint64_t)q * kWave + lane;
             const bool bl = belongs_left<PASS>(O::ord(kv[q]), p);
-            flags |= (uint32_t)(lb + q < x1 && (side ? bl : !bl)) << q;
+            m[q] = __ballot(pos < x1 && (side ? bl : !bl));
         }
-        const uint32_t c = (uint32_t)__popc(flags);
-        const uint32_t incl = wave_inclusive_scan(c);
-        const uint32_t total = __shfl(incl, kWave - 1, kWave);
-        if (k < total) {
-            const uint32_t excl = incl - c;
-            if (excl <= k && k < incl) {
-                uint32_t f = flags;
-                for (uint32_t r = k - excl; r > 0; --r) f &= f - 1;  // drop lower set bits
-                sp[j] = (uint32_t)(lb + (uint32_t)__ffs(f) - 1);
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) {
+            const uint32_t c = (uint32_t)__popcll(m[q]);
+            if (k < c) {  // the k-th set bit of m[q]
+                if (((m[q] >> lane) & 1ull) && (uint32_t)__popcll(m[q] & lanemask_lt()) == k)
+                    sp[j] = (uint32_t)(base + (uint64_t)q * kWave + lane);
+                return;
             }
-            return;
+            k -= c;
         }
-        k -= total;
     }
 }
 
@@ -446,52 +602,55 @@ __device__ __forceinline__ void skip_empty_tiles(SideScan &sc, uint32_t TP, uint
     }
 }
 
-// Classify one subtile of kPartSub positions starting at sc.pos (wave-striped:
-// wave w covers 16 x 64 consecutive positions, lane-interleaved) and record
-// the positions of the misplaced ones in `slots` in position order.
+// Load one subtile of kPartSub positions starting at sc.pos (wave-striped:
+// wave w covers 16 x 64 consecutive positions, lane-interleaved; clamped
+// loads, all in flight) and ballot its misplaced elements.
 template <class O, int PASS>
-__device__ __forceinline__ void classify_subtile(const uint32_t *keys, uint32_t p, bool right,
-                                                 SideScan &sc, uint32_t *slots, uint32_t cap,
-                                                 uint32_t *wtot) {
+__device__ __forceinline__ uint32_t ballot_subtile(const uint32_t *keys, uint32_t p, bool right,
+                                                   const SideScan &sc, uint64_t m[kPartItems]) {
     const int lane = lane_id(), wave = wave_id();
-    const uint64_t base = sc.pos;
-    uint64_t m[kPartItems];
+    const uint64_t base = sc.pos + (uint64_t)wave * (kPartItems * kWave) + lane;
     uint32_t kv[kPartItems];
+#pragma unroll
+    for (int q = 0; q < kPartItems; ++q) {
+        const uint64_t pos = base + (uint64_t)q * kWave;
+        kv[q] = ldg(keys + (pos < sc.end ? pos : sc.end - 1));
+    }
     uint32_t wcount = 0;
 #pragma unroll
     for (int q = 0; q < kPartItems; ++q) {
-        const uint64_t pos = base + (uint64_t)wave * (kPartItems * kWave) + (uint64_t)q * kWave + lane;
-        kv[q] = ldg(keys + (pos < sc.end ? pos : sc.end - 1));
-    }
-#pragma unroll
-    for (int q = 0; q < kPartItems; ++q) {
-        const uint64_t pos = base + (uint64_t)wave * (kPartItems * kWave) + (uint64_t)q * kWave + lane;
+        const uint64_t pos = base + (uint64_t)q * kWave;
         const bool bl = belongs_left<PASS>(O::ord(kv[q]), p);
-        const bool f = pos < sc.end && (right ? bl : !bl);
-        m[q] = __ballot(f);
+        m[q] = __ballot(pos < sc.end && (right ? bl : !bl));
         wcount += (uint32_t)__popcll(m[q]);
     }
-    if (lane == 0) wtot[wave] = wcount;
-    __syncthreads();
+    return wcount;
+}
+
+// Record the positions of a subtile's misplaced elements in `slots`, in
+// position order, after the waves' counts are known (wtot: one per wave).
+__device__ __forceinline__ void record_subtile(SideScan &sc, const uint64_t m[kPartItems],
+                                               const uint32_t *wtot, uint32_t *slots,
+                                               uint32_t cap) {
+    const int lane = lane_id(), wave = wave_id();
     uint32_t woff = sc.found, total = 0;
 #pragma unroll
     for (int w = 0; w < kWaves; ++w) {
         if (w < wave) woff += wtot[w];
         total += wtot[w];
     }
-    __syncthreads();  // wtot is reused by the next call
+    const uint64_t base = sc.pos + (uint64_t)wave * (kPartItems * kWave) + lane;
 #pragma unroll
     for (int q = 0; q < kPartItems; ++q) {
         if ((m[q] >> lane) & 1ull) {
             const uint32_t slot = woff + (uint32_t)__popcll(m[q] & lanemask_lt());
             if (slot < cap)  // always true with consistent counts
-                slots[slot] = (uint32_t)(base + (uint64_t)wave * (kPartItems * kWave) +
-                                         (uint64_t)q * kWave + lane);
+                slots[slot] = (uint32_t)(base + (uint64_t)q * kWave);
         }
         woff += (uint32_t)__popcll(m[q]);
     }
     sc.found += total;
-    sc.pos = base + kPartSub;
+    sc.pos += kPartSub;
 }
 
 // One workgroup per chunk: find the positions of the chunk's misplaced
@@ -508,7 +667,7 @@ __global__ __launch_bounds__(kBlock) void k_part_swap(TaskRef<PartSeg> tasks, ui
                                                       uint32_t *eqmv_all,
                                                       const uint64_t *meta_all) {
     __shared__ uint32_t pL[kRankChunk], pR[kRankChunk];
-    __shared__ uint32_t wtot[kWaves];
+    __shared__ uint32_t wtot[2][kWaves];
     uint32_t j, a;
     const PartSeg g = task_of(tasks, blockIdx.x, &j, &a);
     const uint64_t *meta = meta_all + (uint64_t)g.slot * M_COUNT;
@@ -537,24 +696,64 @@ __global__ __launch_bounds__(kBlock) void k_part_swap(TaskRef<PartSeg> tasks, ui
         if (sparse_r) skip_empty_tiles(R, TP, g.nt);
         const bool more_l = L.pos < L.end, more_r = R.pos < R.end;
         if (!more_l && !more_r) break;
-        if (more_l) classify_subtile<O, PASS>(keys, p, false, L, pL, kRankChunk, wtot);
-        if (more_r) classify_subtile<O, PASS>(keys, p, true, R, pR, kRankChunk, wtot);
+        // both sides' loads in flight together, one pair of barriers
+        uint64_t mL[kPartItems], mR[kPartItems];
+        uint32_t cl = 0, cr = 0;
+        if (more_l) cl = ballot_subtile<O, PASS>(keys, p, false, L, mL);
+        if (more_r) cr = ballot_subtile<O, PASS>(keys, p, true, R, mR);
+        if (lane_id() == 0) {
+            wtot[0][wave_id()] = cl;
+            wtot[1][wave_id()] = cr;
+        }
+        __syncthreads();
+        if (more_l) record_subtile(L, mL, wtot[0], pL, kRankChunk);
+        if (more_r) record_subtile(R, mR, wtot[1], pR, kRankChunk);
+        __syncthreads();  // wtot is rewritten by the next step
     }
     __syncthreads();
     // equal by construction; the minimum keeps every access inside the filled slots
     cnt = min(cnt, min(L.found, R.found));
+    if (cnt == 0) return;
     uint32_t *eqmv = eqmv_all + g.tile_off;
-    for (uint32_t k = threadIdx.x; k < cnt; k += kBlock) {
-        const uint32_t il = pL[k], ir = pR[k];
-        const uint32_t x = ldg(keys + il), y = ldg(keys + ir);
-        stg(keys + il, y);
-        stg(keys + ir, x);
-        if constexpr (PAIRS) {
-            const uint32_t vx = ldg(vals + il), vy = ldg(vals + ir);
-            stg(vals + il, vy);
-            stg(vals + ir, vx);
+    // every thread exchanges up to kXItems pairs; all loads are issued before
+    // the first store (clamped slots load a valid pair and store nothing)
+    constexpr int kXItems = kRankChunk / kBlock;
+    uint32_t il[kXItems], ir[kXItems], x[kXItems], y[kXItems];
+#pragma unroll
+    for (int q = 0; q < kXItems; ++q) {
+        const uint32_t k = (uint32_t)q * kBlock + threadIdx.x;
+        const uint32_t kk = k < cnt ? k : cnt - 1;
+        il[q] = pL[kk];
+        ir[q] = pR[kk];
+    }
+#pragma unroll
+    for (int q = 0; q < kXItems; ++q) {
+        x[q] = ldg(keys + il[q]);
+        y[q] = ldg(keys + ir[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < kXItems; ++q) {
+        const uint32_t k = (uint32_t)q * kBlock + threadIdx.x;
+        if (k < cnt) {
+            stg(keys + il[q], y[q]);
+            stg(keys + ir[q], x[q]);
+            if (PASS == 0 && O::ord(x[q]) == p) atomicAdd(&eqmv[ir[q] / TP], 1u);
         }
-        if (PASS == 0 && O::ord(x) == p) atomicAdd(&eqmv[ir / TP], 1u);
+    }
+    if constexpr (PAIRS) {
+#pragma unroll
+        for (int q = 0; q < kXItems; ++q) {
+            x[q] = ldg(vals + il[q]);
+            y[q] = ldg(vals + ir[q]);
+        }
+#pragma unroll
+        for (int q = 0; q < kXItems; ++q) {
+            const uint32_t k = (uint32_t)q * kBlock + threadIdx.x;
+            if (k < cnt) {
+                stg(vals + il[q], y[q]);
+                stg(vals + ir[q], x[q]);
+            }
+        }
     }
 }
 
@@ -576,9 +775,14 @@ static hipError_t partition_t(const PartitionLaunch &L, hipStream_t st) {
         }
         {
             ProfScope prof(st, K_PART_SCAN, 0.0);
-            hipLaunchKernelGGL((k_part_scan_a<O>), dim3(L.tasks.A), dim3(L.scan_threads), 0, st,
-                               L.tasks, L.TP, ws.cnt_lt, ws.cnt_eq, ws.preL, ws.preR, ws.eqmv,
-                               ws.spL, ws.spR, ws.meta, ws.res);
+            if (L.scan_threads == kScanThreads)
+                hipLaunchKernelGGL((k_part_scan_a<O, kScanThreads>), dim3(L.tasks.A),
+                                   dim3(kScanThreads), 0, st, L.tasks, L.TP, ws.cnt_lt, ws.cnt_eq,
+                                   ws.preL, ws.preR, ws.eqmv, ws.spL, ws.spR, ws.meta, ws.res);
+            else
+                hipLaunchKernelGGL((k_part_scan_a<O, kBlock>), dim3(L.tasks.A), dim3(kBlock), 0,
+                                   st, L.tasks, L.TP, ws.cnt_lt, ws.cnt_eq, ws.preL, ws.preR,
+                                   ws.eqmv, ws.spL, ws.spR, ws.meta, ws.res);
         }
         break;
     }
@@ -588,12 +792,12 @@ static hipError_t partition_t(const PartitionLaunch &L, hipStream_t st) {
         ProfScope prof(st, K_PART_SPLIT, 0.0);
         if (L.phase == 1)
             hipLaunchKernelGGL((k_part_split<O, 0>), dim3((L.work + kWaves - 1) / kWaves),
-                               dim3(kBlock), 0, st, L.tasks, L.TP, L.work, ws.preL, ws.preR,
-                               ws.spL, ws.spR, ws.meta);
+                               dim3(kBlock), 0, st, L.tasks, L.TP, L.work, ws.spL, ws.spR,
+                               ws.meta);
         else
             hipLaunchKernelGGL((k_part_split<O, 1>), dim3((L.work + kWaves - 1) / kWaves),
-                               dim3(kBlock), 0, st, L.tasks, L.TP, L.work, ws.preL, ws.preR,
-                               ws.spL, ws.spR, ws.meta);
+                               dim3(kBlock), 0, st, L.tasks, L.TP, L.work, ws.spL, ws.spR,
+                               ws.meta);
         break;
     }
     case 2: {  // swap of pass A
@@ -605,9 +809,14 @@ static hipError_t partition_t(const PartitionLaunch &L, hipStream_t st) {
     }
     case 4: {  // scan B
         ProfScope prof(st, K_PART_SCAN, 0.0);
-        hipLaunchKernelGGL((k_part_scan_b<O>), dim3(L.tasks.A), dim3(L.scan_threads), 0, st,
-                           L.tasks, L.TP, ws.cnt_eq, ws.eqmv, ws.preL, ws.preR, ws.spL, ws.spR,
-                           ws.meta);
+        if (L.scan_threads == kScanThreads)
+            hipLaunchKernelGGL((k_part_scan_b<O, kScanThreads>), dim3(L.tasks.A),
+                               dim3(kScanThreads), 0, st, L.tasks, L.TP, ws.cnt_eq, ws.eqmv,
+                               ws.preL, ws.preR, ws.spL, ws.spR, ws.meta);
+        else
+            hipLaunchKernelGGL((k_part_scan_b<O, kBlock>), dim3(L.tasks.A), dim3(kBlock), 0, st,
+                               L.tasks, L.TP, ws.cnt_eq, ws.eqmv, ws.preL, ws.preR, ws.spL,
+                               ws.spR, ws.meta);
         break;
     }
     case 5: {  // swap of pass B
