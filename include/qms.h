@@ -156,11 +156,32 @@ int qms_release_workspaces(void);
 /*
  * Round log of the last single-array sort on the calling thread: for each
  * partition round, the range size s, the sizes of the sides (<, ==, >
- * pivot) and the number of merge levels run on the mergesorted side.
- * Writes up to max_rounds records of 5 uint64 each into out; returns the
- * number of rounds of that sort (which may exceed max_rounds).
+ * pivot; == is 0 when the few pivot-equal keys stayed with the > side), the
+ * number of merge levels run on the mergesorted side, and the pivot rule of
+ * the round (0 median-of-3, 1 median of the medians of three, taken after a
+ * round whose smaller side held less than 1/16 of its range: Sec.
+ * "Worst-Case Efficient QuickMergeSort", HybridQuickMergesort with
+ * delta = 1/16).  Writes up to max_rounds records of QMS_SCHEDULE_WORDS
+ * uint64 each into out; returns the number of rounds of that sort (which
+ * may exceed max_rounds).
  */
+#define QMS_SCHEDULE_WORDS 6
 uint64_t qms_last_schedule(uint64_t *out, uint64_t max_rounds);
+
+/*
+ * The worst-case pivot of Sec. "Worst-Case Efficient QuickMergeSort"
+ * (MoMQuickMergesort): the lower median of the floor(n/3) medians of the
+ * triples (d_keys[3i], d_keys[3i+1], d_keys[3i+2]), keys compared as in
+ * qms_sort (dt).  At least 2 floor(n/6) keys are <= it and as many >= it.
+ * The same kernels pick the pivot inside a sort after an unbalanced round;
+ * this entry point runs them on a whole array, for tests and callers that
+ * want the pivot alone.  d_keys: n 32-bit words on the current device
+ * (read only); *pivot_out (host) gets the pivot's bits.  Synchronises
+ * `stream`.  Errors: QMS_ERR_INVALID for NULL pointers or n < 3,
+ * QMS_ERR_UNSUPPORTED for n >= 2^32 or an unknown dt, QMS_ERR_HIP.
+ */
+int qms_mom_pivot(const void *d_keys, uint64_t n, int dt, uint32_t *pivot_out,
+                  hipStream_t stream);
 
 /*
  * Per-kernel-class timing of the sorts issued by the calling thread between

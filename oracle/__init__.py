@@ -14,6 +14,8 @@ module loads it with ctypes and offers numpy-level helpers:
 * ``sort_segments`` -- the same, independently per segment.
 * ``partition``, ``out``, ``msort``, ``merge`` -- the individual routines of
   Fig. 2, for pinning them one by one.
+* ``mom_pivot(keys)`` -- the worst-case pivot of the paper's
+  MoMQuickMergesort: the lower median of the medians of the triples.
 * ``order_statistic_ok(x, k, v)`` -- whether ``v`` is the element of rank
   ``k`` of ``x`` by the plain counting definition (for checking sampled
   outputs at sizes where a full oracle sort is too slow).
@@ -92,6 +94,8 @@ def _load():
     lib.qmso_msort.restype = None
     lib.qmso_merge.argtypes = [u32p, u32p, sz, sz, sz, sz, cp]
     lib.qmso_merge.restype = None
+    lib.qmso_mom_pivot.argtypes = [u32p, sz, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    lib.qmso_mom_pivot.restype = ctypes.c_uint32
     _lib = lib
     return lib
 
@@ -199,6 +203,24 @@ def merge(keys, begin1: int, end1: int, target: int, endtarget: int, vals=None):
     lib.qmso_merge(_ptr(k), _ptr(v), begin1, end1, target, endtarget,
                    ctypes.byref(c))
     return k, v, Counts(int(c.comparisons), int(c.moves))
+
+
+def mom_pivot(keys: np.ndarray) -> int:
+    """Median of the floor(n/3) medians of (keys[3i], keys[3i+1], keys[3i+2])
+    (Sec. "Worst-Case Efficient QuickMergeSort", reading R7), as the 32-bit
+    pattern of the pivot; float32 keys are compared by the total order."""
+    x = np.ascontiguousarray(keys)
+    if x.size < 3:
+        raise ValueError("the pivot needs n >= 3")
+    is_f32 = x.dtype == np.float32
+    xb = x.view(np.uint32) if is_f32 else x.astype(np.uint32, copy=False)
+    lib = _load()
+    ok = ctypes.c_int()
+    p = lib.qmso_mom_pivot(xb.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), xb.size,
+                           int(is_f32), ctypes.byref(ok))
+    if not ok.value:
+        raise MemoryError("oracle mom_pivot")
+    return int(p)
 
 
 def order_statistic_ok(x: np.ndarray, k: int, value) -> bool:

@@ -43,6 +43,13 @@
  *       flipping the bits of negative values and the sign bit of the others;
  *       with plain '<' the two zeros would tie and the output bits would
  *       depend on the algorithm.
+ *   R7  the worst-case pivot of Sec. "Worst-Case Efficient QuickMergeSort"
+ *       (qmso_mom_pivot) is the median of n/3 medians of three; the paper
+ *       fixes neither the groups nor which middle element of an even count
+ *       it means.  Read as the triples (3i, 3i+1, 3i+2), i < floor(n/3), and
+ *       the lower median (0-based rank floor((c-1)/2) of the c medians).  The
+ *       paper selects it with the median-of-medians algorithm; any exact
+ *       selection yields the same value, here a library sort of the medians.
  *
  * Counters (Experiments section): one comparison per key comparison; one
  * move per element assignment, a swap counting as three moves.  The counting
@@ -55,6 +62,7 @@
  */
 #include <stddef.h>
 #include <stdint.h>
+#include <stdlib.h>
 
 #ifndef QMSO_COUNTING
 #define QMSO_COUNTING 1
@@ -288,6 +296,42 @@ void QMSO_FN(sort_segments)(uint32_t *keys, uint32_t *vals,
 }
 
 #if QMSO_COUNTING
+static int cmp_u32(const void *x, const void *y)
+{
+    uint32_t a = *(const uint32_t *)x, b = *(const uint32_t *)y;
+    return (a > b) - (a < b);
+}
+
+/* R7: the median of the floor(n/3) medians of three (MoMQuickMergesort's
+ * pivot, Sec. "Worst-Case Efficient QuickMergeSort"), as the key bits of the
+ * input (is_f32: compared by R6).  n >= 3.  Returns 0 and sets *ok = 0 if
+ * memory runs out. */
+uint32_t qmso_mom_pivot(const uint32_t *keys, size_t n, int is_f32, int *ok)
+{
+    size_t c = n / 3;
+    uint32_t *med = malloc((c ? c : 1) * sizeof(uint32_t));
+    *ok = med != NULL && c > 0;
+    if (!*ok) {
+        free(med);
+        return 0;
+    }
+    for (size_t i = 0; i < c; i++) {
+        uint32_t x = keys[3 * i], y = keys[3 * i + 1], z = keys[3 * i + 2];
+        if (is_f32) {
+            x = f32_bits_to_key(x);
+            y = f32_bits_to_key(y);
+            z = f32_bits_to_key(z);
+        }
+        /* median of three: the one that is neither the smallest nor the largest */
+        uint32_t lo = x < y ? x : y, hi = x < y ? y : x;
+        med[i] = z < lo ? lo : (z > hi ? hi : z);
+    }
+    qsort(med, c, sizeof(uint32_t), cmp_u32);
+    uint32_t p = med[(c - 1) / 2];
+    free(med);
+    return is_f32 ? key_to_f32_bits(p) : p;
+}
+
 /* The pieces below are exported only from the counting build, for tests
  * that pin the individual routines of Fig. 2.  Keys are plain u32. */
 

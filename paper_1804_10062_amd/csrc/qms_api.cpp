@@ -38,7 +38,7 @@ static std::map<std::pair<int, hipStream_t>, Workspace *> g_ws;
 
 static size_t ws_words() {
     return 3ull * kCapTiles + 2ull * (kCapTiles + kCapSegs) + 2ull * kCapChunks + 3ull * kCapSplits +
-           4ull * kCapSegs;
+           4ull * kCapSegs + 256ull * kCapMoM;
 }
 
 int get_workspace(int device, hipStream_t stream, Workspace **out) {
@@ -99,6 +99,8 @@ int get_workspace(int device, hipStream_t stream, Workspace **out) {
     ws->samples[1] = w;
     w += kCapSplits;
     ws->res = w;
+    w += 4ull * kCapSegs;
+    ws->hist = w;
     g_ws[key] = ws;
     *out = ws;
     return QMS_OK;
@@ -216,14 +218,41 @@ int qms_release_workspaces(void) {
     }
 }
 
+static_assert(kScheduleWords == QMS_SCHEDULE_WORDS, "schedule record size");
+
 uint64_t qms_last_schedule(uint64_t *out, uint64_t max_rounds) {
     const auto &sched = last_schedule();
     const uint64_t n = sched.size();
     if (out) {
         for (uint64_t i = 0; i < n && i < max_rounds; ++i)
-            for (int j = 0; j < 5; ++j) out[i * 5 + j] = sched[i][j];
+            for (int j = 0; j < kScheduleWords; ++j) out[i * kScheduleWords + j] = sched[i][j];
     }
     return n;
+}
+
+int qms_mom_pivot(const void *d_keys, uint64_t n, int dt, uint32_t *pivot_out,
+                  hipStream_t stream) {
+    try {
+        if (!d_keys || !pivot_out) return set_error(QMS_ERR_INVALID, "NULL keys or output");
+        if (dt != QMS_U32 && dt != QMS_F32) return set_error(QMS_ERR_UNSUPPORTED, "unknown dtype");
+        if (n < 3) return set_error(QMS_ERR_INVALID, "the pivot needs n >= 3");
+        if (n >= (1ull << 32)) return set_error(QMS_ERR_UNSUPPORTED, "n must be below 2^32");
+        int dev = -1;
+        int rc = check_device_ptr(d_keys, "keys", &dev);
+        if (rc != QMS_OK) return rc;
+        DeviceScope scope(dev);
+        Workspace *ws = nullptr;
+        rc = get_workspace(dev, stream, &ws);
+        if (rc != QMS_OK) return rc;
+        uint32_t p = 0;
+        rc = mom_pivot_of(dt, (const uint32_t *)d_keys, n, *ws, stream, &p);
+        if (rc != QMS_OK) return rc;
+        // order-mapped key back to the caller's bits
+        *pivot_out = dt == QMS_F32 ? (p ^ ((uint32_t)((int32_t)(~p) >> 31) | 0x80000000u)) : p;
+        return QMS_OK;
+    } catch (...) {
+        return set_error(QMS_ERR_NOMEM, "host exception in qms_mom_pivot");
+    }
 }
 
 void qms_get_tiles(uint32_t *base_tile, uint32_t *merge_tile, uint32_t *partition_tile) {

@@ -48,6 +48,8 @@ enum MetaSlot : int {
     M_XB = 7,      // misplaced pairs of pass B (== pivot vs > pivot)
     M_RCA = 8,     // misplaced pairs per chunk, pass A
     M_RCB = 9,     // misplaced pairs per chunk, pass B
+    M_MOM_PREFIX = 10,  // median-of-medians pivot: digits chosen so far
+    M_MOM_RANK = 11,    // median-of-medians pivot: rank inside the prefix
     M_COUNT = 16
 };
 
@@ -85,11 +87,10 @@ struct PartSeg {
     uint32_t nt;         // partition tiles of the range
     uint32_t chunk_off;  // first entry in the chunk-boundary arrays
     uint32_t slot;       // index of the segment's round-state words
-    uint32_t flags;      // kPivotFromSample: pivot precomputed by k_part_pivot
-    uint32_t pad;
+    uint32_t flags;      // kPivotMoM: pivot precomputed by the median-of-medians select
+    uint32_t pad;        // histogram slot of that select
 };
-constexpr uint32_t kPivotFromSample = 1;
-constexpr int kPivotSample = 1023;  // sample of the fallback pivot
+constexpr uint32_t kPivotMoM = 1;
 
 // One Mergesort of a round: m keys at D, swap space at Bf (offsets from keys),
 // L merge levels over runs of w0 << level keys; the base case (tiles of w0

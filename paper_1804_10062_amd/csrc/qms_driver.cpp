@@ -66,7 +66,42 @@ int upload(Arena &ar, size_t from, hipStream_t st) {
     return e == hipSuccess ? QMS_OK : hip_error(e, "task table upload");
 }
 
-thread_local std::vector<std::array<uint64_t, 5>> g_schedule;
+thread_local std::vector<std::array<uint64_t, kScheduleWords>> g_schedule;
+
+// The median-of-medians pivots of the flagged segments of a round, in groups
+// of at most kCapMoM (one histogram each).
+int mom_pivots(int dt, const PartSeg *pt, uint32_t A, Arena &ar, Workspace &ws, hipStream_t st) {
+    std::vector<uint32_t> idx;
+    for (uint32_t a = 0; a < A; ++a)
+        if (pt[a].flags & kPivotMoM) idx.push_back(a);
+    for (size_t g0 = 0; g0 < idx.size(); g0 += kCapMoM) {
+        const uint32_t n = (uint32_t)std::min<size_t>(kCapMoM, idx.size() - g0);
+        const size_t mark = ar.used;
+        size_t o_tab, o_pre;
+        PartSeg *tab = ar.take<PartSeg>(n, &o_tab);
+        uint32_t *pre = ar.take<uint32_t>(n + 1, &o_pre);
+        if (!tab || !pre) return set_error(QMS_ERR_NOMEM, "task table arena too small");
+        pre[0] = 0;
+        for (uint32_t i = 0; i < n; ++i) {
+            tab[i] = pt[idx[g0 + i]];
+            tab[i].pad = i;
+            pre[i + 1] = pre[i] + mom_tiles(tab[i].s);
+        }
+        if (n > 1) {
+            int rc = upload(ar, mark, st);
+            if (rc != QMS_OK) return rc;
+        }
+        TaskRef<PartSeg> R;
+        R.A = n;
+        R.one = tab[0];
+        R.tab = ar.dev<PartSeg>(o_tab);
+        R.pre = ar.dev<uint32_t>(o_pre);
+        hipError_t e = launch_mom_pivot(dt, R, pre[n], ws, st);
+        if (e != hipSuccess) return hip_error(e, "median-of-medians pivot");
+    }
+    return QMS_OK;
+}
+
 
 }  // namespace
 
@@ -76,7 +111,7 @@ size_t tab_arena_bytes() {
     return per * kCapSegs + 64 * 1024;
 }
 
-const std::vector<std::array<uint64_t, 5>> &last_schedule() { return g_schedule; }
+const std::vector<std::array<uint64_t, kScheduleWords>> &last_schedule() { return g_schedule; }
 
 // Sort a group of segments (count <= kCapSegs, total keys < 2^32).
 static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
@@ -117,14 +152,14 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
             uint32_t *pc = ar.take<uint32_t>(A + 1, &o_pre);
             if (!pt || !pc) return set_error(QMS_ERR_NOMEM, "task table arena too small");
             uint32_t toff = 0, coff = 0, max_nt = 0;
-            bool any_sample = false;
+            bool any_mom = false;
             pc[0] = 0;
             for (uint32_t a = 0; a < A; ++a) {
                 const Seg &g = segs[active[a]];
                 const uint32_t s = g.hi - g.lo;
                 const uint32_t nt = (s + TP - 1) / TP;
-                const uint32_t fl = g.bad_split ? kPivotFromSample : 0u;
-                any_sample |= g.bad_split;
+                const uint32_t fl = g.bad_split ? kPivotMoM : 0u;
+                any_mom |= g.bad_split;
                 pt[a] = PartSeg{g.keys, g.vals, g.lo, s, toff, nt, coff, a, fl, 0};
                 toff += nt;
                 coff += (s + 4095) / 4096 + 2;
@@ -136,6 +171,10 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
                 int rc = upload(ar, 0, st);
                 if (rc != QMS_OK) return rc;
             }
+            if (any_mom) {
+                int rc = mom_pivots(dt, pt, A, ar, ws, st);
+                if (rc != QMS_OK) return rc;
+            }
             PartitionLaunch L{};
             L.tasks.A = A;
             L.tasks.one = pt[0];
@@ -144,7 +183,6 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
             L.TP = TP;
             L.scan_threads = max_nt > 4 * kBlock ? kScanThreads : kBlock;
             L.keys_total = (double)sum_s;
-            L.sample_pivots = any_sample;
             L.ws = &ws;
             L.phase = 0;
             L.work = toff;
@@ -245,10 +283,15 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
                 }
                 t.L = t.m > T0 ? ceil_log2((t.m + T0 - 1) / T0) : 0;
                 // HybridQuickMergesort's rule with delta = 1/16: a split outside
-                // [s/16, 15 s/16] makes the next pivot of this array a sample median
+                // [s/16, 15 s/16] makes the next pivot of this array the
+                // median of the medians of three; the one after returns to
+                // median-of-3
+                const bool mom = (pt[a].flags & kPivotMoM) != 0;
                 g.bad_split = (uint64_t)std::min(mL, mR) * 16 < s;
                 if (t.m > 1) tasks.push_back(t);
-                if (log) g_schedule.push_back({s, c_lt, c_eq, (uint64_t)(s - c_lt - c_eq), t.L});
+                if (log)
+                    g_schedule.push_back(
+                        {s, c_lt, c_eq, (uint64_t)(s - c_lt - c_eq), t.L, mom ? 1ull : 0ull});
                 const uint32_t s2 = g.hi - g.lo;
                 if (s2 > T0) next.push_back(active[a]);
                 else if (s2 > 1) next_finals.push_back(SortSeg{g.keys, g.vals, g.lo, 0, s2, 0, 0, T0});
@@ -309,6 +352,21 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
             if (e != hipSuccess) return hip_error(e, "merge level");
         }
     }
+    return QMS_OK;
+}
+
+int mom_pivot_of(int dt, const uint32_t *keys, uint64_t n, Workspace &ws, hipStream_t st,
+                 uint32_t *pivot) {
+    Arena ar{(char *)ws.htab[ws.rounds & 1], (char *)ws.dtab, ws.tab_bytes};
+    ++ws.rounds;
+    PartSeg seg{(uint32_t *)keys, nullptr, 0, (uint32_t)n, 0, 0, 0, 0, kPivotMoM, 0};
+    int rc = mom_pivots(dt, &seg, 1, ar, ws, st);
+    if (rc != QMS_OK) return rc;
+    uint64_t p = 0;
+    hipError_t e = hipMemcpyAsync(&p, ws.meta + M_PIVOT, sizeof(p), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_error(e, "median-of-medians pivot readback");
+    *pivot = (uint32_t)p;
     return QMS_OK;
 }
 

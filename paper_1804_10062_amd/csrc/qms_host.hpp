@@ -12,6 +12,9 @@
 
 namespace qms {
 
+// Words per round of the schedule log (QMS_SCHEDULE_WORDS in qms.h).
+constexpr int kScheduleWords = 6;
+
 int set_error(int code, const std::string &msg);
 int hip_error(hipError_t e, const char *where);
 int check_device_ptr(const void *p, const char *what, int *device);
@@ -31,7 +34,10 @@ struct HostSeg {
 int sort_segments(int dt, bool pairs, const HostSeg *segs, size_t count, Workspace &ws,
                   hipStream_t st, bool log);
 size_t tab_arena_bytes();
-const std::vector<std::array<uint64_t, 5>> &last_schedule();
+const std::vector<std::array<uint64_t, kScheduleWords>> &last_schedule();
+// The median-of-medians pivot of one array (order-mapped key into *pivot).
+int mom_pivot_of(int dt, const uint32_t *keys, uint64_t n, Workspace &ws, hipStream_t st,
+                 uint32_t *pivot);
 
 // Makes `dev` current for the lifetime of the object.
 class DeviceScope {

@@ -18,6 +18,8 @@ constexpr uint64_t kCapTiles = 1ull << 20;
 constexpr uint64_t kCapChunks = (1ull << 20) + 2ull * kCapSegs + 16;
 // Merge splits of one level: ceil(m / kMergeTile) per task, m < 2^31.
 constexpr uint64_t kCapSplits = (1ull << 31) / kMergeTile + kCapSegs + 16;
+// Segments whose median-of-medians pivot one launch group selects.
+constexpr uint32_t kCapMoM = 2048;
 // Merge levels a task can need: ceil(log2(2^31 / 8192)).
 constexpr int kMaxLevels = 18;
 
@@ -38,6 +40,7 @@ struct Workspace {
     uint32_t *samples[2] = {nullptr, nullptr};  // [kCapSplits] each: run samples, by level parity
     uint64_t *meta = nullptr;    // [kCapSegs * M_COUNT]
     uint32_t *res = nullptr;     // [4 * kCapSegs] per-segment partition results
+    uint32_t *hist = nullptr;    // [256 * kCapMoM] median-of-medians select histograms
     // task tables: device copies of the host arena below
     void *dtab = nullptr;        // [tab_bytes]
     void *htab[2] = {nullptr, nullptr};  // pinned host arenas (alternating rounds)
@@ -61,13 +64,18 @@ struct PartitionLaunch {
     uint32_t work;             // work items (workgroups, or waves for splits)
     uint32_t TP;               // partition tile
     uint32_t scan_threads;     // block size of the scans
-    bool sample_pivots;        // some segment takes its pivot from a sample
     double keys_total;         // keys in all ranges (byte figures)
     double bytes;              // algorithmic bytes of the launch (swap A)
     const Workspace *ws;
 };
 
 hipError_t launch_partition_phase(int dt, bool pairs, const PartitionLaunch &L, hipStream_t st);
+// Median-of-medians pivots (into meta[M_PIVOT]) of the segments listed in
+// `tasks` (PartSeg.pad = histogram slot < kCapMoM); `tiles` = total of
+// mom_tiles(s) over them, the exclusive prefix of which is tasks.pre.
+uint32_t mom_tiles(uint64_t s);
+hipError_t launch_mom_pivot(int dt, const TaskRef<PartSeg> &tasks, uint32_t tiles,
+                            const Workspace &ws, hipStream_t st);
 hipError_t launch_tile_sort(int dt, bool pairs, const TaskRef<SortSeg> &tasks, uint32_t tiles,
                             double bytes, const Workspace &ws, hipStream_t st);
 hipError_t launch_merge_level(int dt, bool pairs, const TaskRef<SortSeg> &tasks, uint32_t level,

@@ -47,42 +47,6 @@ __device__ __forceinline__ const PartSeg &seg_by_index(const TaskRef<PartSeg> &r
     return r.A == 1 ? r.one : r.tab[a];
 }
 
-// ---- fallback pivot -----------------------------------------------------------
-// After a round whose smaller side held less than s/16 keys, the next pivot of
-// the segment is the median of kPivotSample keys at evenly spaced positions
-// (the median-of-a-larger-sample pivot of Sec. "QuickXsort and QuickMergesort"
-// and Theorem 3, used in the spirit of Sec. "Worst-Case Efficient
-// QuickMergeSort": median-of-3 as long as the splits stay within
-// [s/16, 15 s/16], a stronger pivot for the round after one that did not).
-// One workgroup per segment; segments without the flag return at once.
-template <class O>
-__global__ __launch_bounds__(1024) void k_part_pivot(TaskRef<PartSeg> tasks, uint64_t *meta_all) {
-    __shared__ uint32_t smp[1024];
-    const PartSeg g = seg_by_index(tasks, blockIdx.x);
-    if (!(g.flags & kPivotFromSample)) return;
-    const uint32_t *keys = g.keys + g.lo;
-    const uint32_t tid = threadIdx.x;
-    const uint32_t S = g.s < (uint32_t)kPivotSample ? g.s : (uint32_t)kPivotSample;
-    smp[tid] = tid < S ? O::ord(keys[(uint64_t)(2 * tid + 1) * g.s / (2 * S)]) : 0xFFFFFFFFu;
-    // bitonic sort of the 1024 sampled keys in LDS
-    for (uint32_t k = 2; k <= 1024; k <<= 1) {
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            __syncthreads();
-            const uint32_t l = tid ^ j;
-            if (l > tid) {
-                const uint32_t a = smp[tid], b = smp[l];
-                const bool asc = (tid & k) == 0;
-                if ((a > b) == asc) {
-                    smp[tid] = b;
-                    smp[l] = a;
-                }
-            }
-        }
-    }
-    __syncthreads();
-    if (tid == 0) meta_all[(uint64_t)g.slot * M_COUNT + M_PIVOT] = smp[S / 2];
-}
-
 // ---- count -------------------------------------------------------------------
 // One workgroup per tile: #(< p) and #(== p).  Tile 0 of a segment also
 // records the segment's pivot.
@@ -94,7 +58,7 @@ __global__ __launch_bounds__(kBlock) void k_part_count(TaskRef<PartSeg> tasks, u
     uint32_t t, a;
     const PartSeg g = task_of(tasks, blockIdx.x, &t, &a);
     const uint32_t *keys = g.keys + g.lo;
-    const uint32_t p = (g.flags & kPivotFromSample)
+    const uint32_t p = (g.flags & kPivotMoM)
                            ? (uint32_t)meta[(uint64_t)g.slot * M_COUNT + M_PIVOT]
                            : pivot_of<O>(keys, 0, g.s);
     const uint64_t ts = (uint64_t)t * TP;
@@ -292,7 +256,7 @@ __global__ __launch_bounds__(NTH) void k_part_scan_a(TaskRef<PartSeg> tasks, uin
     const uint32_t nt = g.nt;
     const uint64_t s = g.s;
     const uint32_t tid = threadIdx.x;
-    const uint32_t p = (g.flags & kPivotFromSample) ? (uint32_t)meta[M_PIVOT]
+    const uint32_t p = (g.flags & kPivotMoM) ? (uint32_t)meta[M_PIVOT]
                                                     : pivot_of<O>(keys, 0, s);
     // pass 1
     uint32_t carry = 0, seq = 0;
@@ -762,12 +726,7 @@ template <class O, bool PAIRS>
 static hipError_t partition_t(const PartitionLaunch &L, hipStream_t st) {
     const Workspace &ws = *L.ws;
     switch (L.phase) {
-    case 0: {  // [fallback pivot +] count + scan A
-        if (L.sample_pivots) {
-            ProfScope prof(st, K_PART_SCAN, 0.0);
-            hipLaunchKernelGGL((k_part_pivot<O>), dim3(L.tasks.A), dim3(1024), 0, st, L.tasks,
-                               ws.meta);
-        }
+    case 0: {  // count + scan A
         {
             ProfScope prof(st, K_PART_COUNT, 4.0 * (double)L.keys_total);
             hipLaunchKernelGGL((k_part_count<O>), dim3(L.work), dim3(kBlock), 0, st, L.tasks,

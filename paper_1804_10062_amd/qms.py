@@ -34,8 +34,10 @@ EXPORTS = (
     "qms_server_create", "qms_server_submit", "qms_server_poll",
     "qms_server_get_stats", "qms_server_destroy",
     "qms_last_error", "qms_release_workspaces", "qms_last_schedule",
-    "qms_get_tiles", "qms_profile_begin", "qms_profile_end",
+    "qms_get_tiles", "qms_profile_begin", "qms_profile_end", "qms_mom_pivot",
 )
+
+QMS_SCHEDULE_WORDS = 6
 
 
 class QmsError(RuntimeError):
@@ -104,6 +106,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.qms_profile_begin.restype = i32
     lib.qms_profile_end.argtypes = [ctypes.POINTER(KernelStat), i32, ctypes.POINTER(i32)]
     lib.qms_profile_end.restype = i32
+    lib.qms_mom_pivot.argtypes = [vp, u64, i32, u32p, vp]
+    lib.qms_mom_pivot.restype = i32
     _lib = lib
     return lib
 
@@ -189,12 +193,25 @@ def qms_sort_batch(keys, offsets, vals=None, host_offsets=None, stream=None,
 
 
 def qms_last_schedule(max_rounds: int = 4096):
-    """Per-round log of the last single-array sort on this thread:
-    a list of (s, n_less, n_equal, n_greater, merge_levels)."""
+    """Per-round log of the last single-array sort on this thread: a list of
+    (s, n_less, n_equal, n_greater, merge_levels, pivot_rule) with
+    pivot_rule 0 = median-of-3, 1 = median of the medians of three."""
     lib = load_library()
-    buf = (ctypes.c_uint64 * (5 * max_rounds))()
+    w = QMS_SCHEDULE_WORDS
+    buf = (ctypes.c_uint64 * (w * max_rounds))()
     n = lib.qms_last_schedule(buf, max_rounds)
-    return [tuple(buf[5 * i:5 * i + 5]) for i in range(min(n, max_rounds))]
+    return [tuple(buf[w * i:w * i + w]) for i in range(min(n, max_rounds))]
+
+
+def qms_mom_pivot(keys, stream=None) -> int:
+    """Median of the medians of the triples of `keys` (1-D device tensor,
+    uint32/int32 bits or float32), as the 32-bit pattern of the pivot."""
+    _check_tensor(keys, "keys")
+    out = ctypes.c_uint32()
+    _check(load_library().qms_mom_pivot(keys.data_ptr(), keys.numel(), _dtype_code(keys),
+                                        ctypes.byref(out), _stream_handle(stream)),
+           "qms_mom_pivot")
+    return out.value
 
 
 def qms_get_tiles():

@@ -123,7 +123,7 @@ def test_sort_on_side_stream_and_schedule_log():
     sched = qms.qms_last_schedule()
     assert len(sched) > 0
     lo_hi = 1 << 18
-    for (s_, lt, eq, gt, levels) in sched:
+    for (s_, lt, eq, gt, levels, rule) in sched:
         # eq == 0: the pivot-equal keys stayed in the ">= p" side (then lt > 0)
         assert s_ == lo_hi and lt + eq + gt == s_ and (eq >= 1 or lt >= 1)
         lo_hi = max(lt, gt)

@@ -32,6 +32,15 @@ MUTANTS = {
     "total_order_positive_bit": (
         "return (u & 0x80000000u) ? ~u : (u | 0x80000000u);",
         "return (u & 0x80000000u) ? ~u : u;"),
+    "mom_upper_median": (
+        "uint32_t p = med[(c - 1) / 2];",
+        "uint32_t p = med[c / 2];"),
+    "mom_triples_overlap": (
+        "uint32_t x = keys[3 * i], y = keys[3 * i + 1], z = keys[3 * i + 2];",
+        "uint32_t x = keys[2 * i], y = keys[2 * i + 1], z = keys[2 * i + 2];"),
+    "mom_median_of_three_wrong": (
+        "med[i] = z < lo ? lo : (z > hi ? hi : z);",
+        "med[i] = z < lo ? z : (z > hi ? hi : z);"),
     "partition_scan_skips_element": (
         "        swap_ij(a, i, j);\n        i++;\n        j--;",
         "        swap_ij(a, i, j);\n        i += 2;\n        j--;"),
@@ -73,6 +82,13 @@ CHECK = textwrap.dedent(r"""
     want = np.array([-3.0, -1.0, -0.0, 0.0, 1.0, 2.5], dtype=np.float32)
     if s.view(np.uint32).tolist() != want.view(np.uint32).tolist():
         failures.append(("f32",))
+    from tests.test_oracle_pins import _mom_pivot_by_counting
+    r = np.random.default_rng(7)
+    for n in (4, 9, 10, 31):
+        for _ in range(40):
+            x = r.integers(0, 20, n).astype(np.uint32)
+            if oracle.mom_pivot(x) != _mom_pivot_by_counting(x):
+                failures.append(("mom", n)); break
     print("FAILURES", failures)
     sys.exit(1 if failures else 0)
 """)

@@ -371,3 +371,67 @@ def test_order_statistic_definition():
     for k in (0, 2500, 4999):
         assert oracle.order_statistic_ok(f, k, sf[k])
         assert not oracle.order_statistic_ok(f, k, np.nextafter(sf[k], np.float32(np.inf)))
+
+
+# ---- the worst-case pivot (Sec. Worst-Case Efficient QuickMergeSort) -------------
+
+def _mom_pivot_by_counting(x):
+    """The pivot by order-statistic counting only: the median of each triple
+    is its element of rank 1, the pivot the element of rank (c - 1) // 2 of
+    the medians (lower median); no sorting involved."""
+    c = len(x) // 3
+    meds = []
+    for i in range(c):
+        t = [int(v) for v in x[3 * i:3 * i + 3]]
+        meds.append(next(v for v in t if sum(u < v for u in t) <= 1 < sum(u <= v for u in t)))
+    k = (c - 1) // 2
+    return next(v for v in meds if sum(u < v for u in meds) <= k < sum(u <= v for u in meds))
+
+
+def test_mom_pivot_golden_example():
+    with open(os.path.join(os.path.dirname(__file__), "golden", "mom_pivot_example.json")) as f:
+        g = json.load(f)
+    x = np.array(g["input"], dtype=np.uint32)
+    assert oracle.mom_pivot(x) == g["pivot"]
+
+
+def test_mom_pivot_brute_force_small_words():
+    # every word over {0,1,2,3} of length 3..7 (and a few longer random ones)
+    for n in range(3, 8):
+        for w in itertools.product(range(4), repeat=n):
+            x = np.array(w, dtype=np.uint32)
+            assert oracle.mom_pivot(x) == _mom_pivot_by_counting(x), w
+    rng = np.random.default_rng(5)
+    for n in (8, 9, 10, 31, 100):
+        for _ in range(50):
+            x = rng.integers(0, 50, n).astype(np.uint32)
+            assert oracle.mom_pivot(x) == _mom_pivot_by_counting(x)
+
+
+@pytest.mark.parametrize("kind", ["uniform", "sorted", "reverse", "equal", "zipf", "organ",
+                                  "triples_low_high"])
+@pytest.mark.parametrize("n", [3, 4, 5, 17, 1000, 65537])
+def test_mom_pivot_guarantee(kind, n):
+    """At least 2 floor(n/6) keys are <= the pivot and at least as many >= it
+    (the guarantee the section derives from the median-of-medians idea)."""
+    rng = np.random.default_rng(n)
+    i = np.arange(n)
+    if kind == "organ":
+        x = np.minimum(i, n - 1 - i).astype(np.uint32)
+    elif kind == "triples_low_high":
+        # every triple is (small, small, large): medians are all small
+        x = np.where(i % 3 == 2, 10**6 + i, i).astype(np.uint32)
+    else:
+        x = inputs.make_keys(kind, n, seed=3)
+    p = np.uint32(oracle.mom_pivot(x))
+    bound = 2 * (n // 6)
+    assert np.count_nonzero(x <= p) >= bound and np.count_nonzero(x >= p) >= bound
+
+
+def test_mom_pivot_f32_total_order():
+    f = np.array([-1.0, 2.0, -0.0, 0.0, 3.0, -5.0, 1.0, 1.0, 1.0], dtype=np.float32)
+    # medians -0, +0, 1 under the total order; lower median +0
+    assert oracle.mom_pivot(f) == np.float32(0.0).view(np.uint32)
+    x = inputs.normal_f32(3001, seed=2)
+    p = np.array([oracle.mom_pivot(x)], dtype=np.uint32).view(np.float32)[0]
+    assert np.count_nonzero(x <= p) >= 2 * (3001 // 6) and np.count_nonzero(x >= p) >= 2 * (3001 // 6)
