@@ -68,6 +68,55 @@ __device__ __forceinline__ uint64_t keep_side(uint64_t x, uint64_t y, bool keep_
     return keep_min ? mn : mx;
 }
 
+// Cross-lane compare-exchange steps of 32-bit elements without the LDS pipe
+// (the ds_bpermute of a generic shuffle occupies it, and it is what limits
+// the base case): lane masks 1, 2 and 8 are single DPP row moves (quad_perm
+// [1,0,3,2], quad_perm [2,3,0,1], row_ror:8 -- a rotation by half a row of 16
+// is the xor-8 partner), mask 4 takes row_ror:4 (lane i - 4) or row_ror:12
+// (lane i + 4) by the lane's bit 2.  Masks 16 and 32 use the CDNA4 permlane
+// swaps on register pairs: v_permlane16_swap / v_permlane32_swap exchange
+// rows (halves) between two registers so that both elements of each pair of
+// either register sit in one lane, one min/max settles them, and a second
+// swap restores the layout.  Every block is ascending here (complemented
+// representation), so the lower lane keeps the smaller element.
+template <int LM>
+__device__ __forceinline__ uint32_t dpp_partner(uint32_t v, uint32_t lane) {
+    if constexpr (LM == 1) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);
+    } else if constexpr (LM == 2) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);
+    } else if constexpr (LM == 8) {
+        return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x128, 0xF, 0xF, false);
+    } else {
+        static_assert(LM == 4, "lane mask");
+        const uint32_t from_below = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x124, 0xF, 0xF, false);
+        const uint32_t from_above = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x12C, 0xF, 0xF, false);
+        return (lane & 4) ? from_below : from_above;
+    }
+}
+
+template <int LM, int ITEMS>
+__device__ __forceinline__ void lane_step_u32(uint32_t (&r)[ITEMS], uint32_t lane) {
+    if constexpr (LM <= 8) {
+        const uint32_t bound = (lane & LM) ? ~0u : 0u;
+#pragma unroll
+        for (int i = 0; i < ITEMS; ++i) r[i] = median3(r[i], dpp_partner<LM>(r[i], lane), bound);
+    } else {
+        static_assert(ITEMS % 2 == 0, "register pairs");
+#pragma unroll
+        for (int i = 0; i < ITEMS; i += 2) {
+            const auto t = LM == 32 ? __builtin_amdgcn_permlane32_swap(r[i], r[i + 1], false, false)
+                                    : __builtin_amdgcn_permlane16_swap(r[i], r[i + 1], false, false);
+            const uint32_t a = t[0], b = t[1];
+            const auto u = LM == 32
+                               ? __builtin_amdgcn_permlane32_swap(min(a, b), max(a, b), false, false)
+                               : __builtin_amdgcn_permlane16_swap(min(a, b), max(a, b), false, false);
+            r[i] = u[0];
+            r[i + 1] = u[1];
+        }
+    }
+}
+
 // Padded LDS index of element e of the tile in natural order: one spare slot
 // every ITEMS slots, so that thread t reading its ITEMS consecutive elements
 // and lanes reading consecutive elements both avoid bank conflicts.
@@ -184,7 +233,32 @@ __device__ __forceinline__ void tile_sort_block(uint32_t *sk, uint32_t *sv, uint
             for (int i = 0; i < ITEMS; ++i)
                 r[i] = keep_side(r[i], s[(uint32_t)i * NT + pt], keep_min, bound);
         }
-        // partners in other lanes of the wave: exchange with shuffles
+        // partners in other lanes of the wave
+        if constexpr (!PAIRS) {
+            switch (j / ITEMS) {  // lane masks j / ITEMS down to 1
+            case 32:
+                lane_step_u32<32>(r, lane);
+                [[fallthrough]];
+            case 16:
+                lane_step_u32<16>(r, lane);
+                [[fallthrough]];
+            case 8:
+                lane_step_u32<8>(r, lane);
+                [[fallthrough]];
+            case 4:
+                lane_step_u32<4>(r, lane);
+                [[fallthrough]];
+            case 2:
+                lane_step_u32<2>(r, lane);
+                [[fallthrough]];
+            case 1:
+                lane_step_u32<1>(r, lane);
+                [[fallthrough]];
+            default:
+                break;
+            }
+            j = ITEMS / 2;
+        }
         for (; j >= (uint32_t)ITEMS; j >>= 1) {
             const uint32_t lm = j / ITEMS;
             const bool lower = (lane & lm) == 0;
