@@ -104,11 +104,32 @@ struct SortSeg {
     uint32_t w0;         // base-case tile (run width of level 0)
 };
 
+// Merge passes of a Mergesort task with L binary levels (runs of w0 << l
+// keys after level l).  Key-only tasks merge four runs per pass: a 2-way pass
+// first when L is odd, then 4-way passes, ceil(L / 2) passes in all.
+// Key/payload tasks run L 2-way passes.  The pass that starts at binary level
+// `level` has index pass_index(); passes alternate between the two regions,
+// and the base case writes into the buffer exactly when the pass count is
+// odd, so that the last pass ends in the data region.
+// (QMS_MERGE_WAYS = 2 builds the binary schedule for every task, for
+// comparisons.)
+#ifndef QMS_MERGE_WAYS
+#define QMS_MERGE_WAYS 4
+#endif
+__host__ __device__ inline bool two_way_only(bool pairs) { return pairs || QMS_MERGE_WAYS == 2; }
+__host__ __device__ inline uint32_t merge_passes(uint32_t L, bool pairs) {
+    return two_way_only(pairs) ? L : (L + 1) / 2;
+}
+__host__ __device__ inline uint32_t pass_index(uint32_t L, uint32_t level, bool pairs) {
+    return two_way_only(pairs) ? level : ((L & 1u) ? (level + 1) / 2 : level / 2);
+}
+
 template <class T>
 struct TaskRef {
-    const T *tab;        // device table (A > 1)
-    const uint32_t *pre; // device prefix of work items, A + 1 entries (A > 1)
-    uint32_t A;          // segments
+    const T *tab = nullptr;        // device table (A > 1)
+    const uint32_t *pre = nullptr; // device prefix of work items, A + 1 entries (A > 1)
+    uint32_t A = 0;                // segments
+    uint32_t base = 0;             // pre[0] (a sub-range of a longer table; A > 1)
     T one;               // the segment itself when A == 1
 };
 
@@ -131,6 +152,7 @@ __device__ __forceinline__ T task_of(const TaskRef<T> &r, uint32_t g, uint32_t *
         *index = 0;
         return r.one;
     }
+    g += r.base;
     const uint32_t a = find_task(r.pre, r.A, g);
     *local = g - r.pre[a];
     *index = a;

@@ -91,7 +91,7 @@ int mom_pivots(int dt, const PartSeg *pt, uint32_t A, Arena &ar, Workspace &ws, 
             int rc = upload(ar, mark, st);
             if (rc != QMS_OK) return rc;
         }
-        TaskRef<PartSeg> R;
+        TaskRef<PartSeg> R{};
         R.A = n;
         R.one = tab[0];
         R.tab = ar.dev<PartSeg>(o_tab);
@@ -304,9 +304,17 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
         ready_finals.swap(next_finals);
         next_finals.clear();
         if (tasks.empty()) continue;
-        // order by merge levels, descending: the tasks of level l are a prefix
-        std::stable_sort(tasks.begin(), tasks.end(),
-                         [](const SortSeg &x, const SortSeg &y) { return x.L > y.L; });
+        // order: tasks with an even level count first, then odd, each by
+        // level count descending.  The passes that start at binary level l
+        // then cover a contiguous range: for key-only tasks the 4-way passes
+        // at l belong to the tasks with L > l and L = l (mod 2), the 2-way
+        // first passes (l = 0) to the odd ones; for key/payload tasks every
+        // task with L > l runs a 2-way pass at l
+        const bool by_parity = !two_way_only(pairs);
+        std::stable_sort(tasks.begin(), tasks.end(), [&](const SortSeg &x, const SortSeg &y) {
+            if (by_parity && (x.L & 1u) != (y.L & 1u)) return (x.L & 1u) < (y.L & 1u);
+            return x.L > y.L;
+        });
         const uint32_t T = (uint32_t)tasks.size();
         const size_t mark = ar.used;
         size_t o_st, o_pt, o_pm;
@@ -316,40 +324,64 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
         if (!stab || !ptile || !pmerge) return set_error(QMS_ERR_NOMEM, "task table arena too small");
         ptile[0] = pmerge[0] = 0;
         double base_bytes = 0;
-        uint32_t maxL = 0;
+        uint32_t maxL = 0, E = 0;
         for (uint32_t a = 0; a < T; ++a) {
             SortSeg t = tasks[a];
             t.split_off = pmerge[a];
             stab[a] = t;
             ptile[a + 1] = ptile[a] + (t.m + T0 - 1) / T0;
             pmerge[a + 1] = pmerge[a] + (t.m + kMergeTile - 1) / kMergeTile;
-            base_bytes += ((t.L & 1) ? 16.0 : 8.0) * w * (double)t.m;
+            base_bytes += ((merge_passes(t.L, pairs) & 1) ? 16.0 : 8.0) * w * (double)t.m;
             maxL = std::max(maxL, t.L);
+            if (!by_parity || (t.L & 1u) == 0) E = a + 1;
         }
         if (pmerge[T] > kCapSplits) return set_error(QMS_ERR_UNSUPPORTED, "too many merge tiles");
         if (T > 1) {
             int rc = upload(ar, mark, st);
             if (rc != QMS_OK) return rc;
         }
-        TaskRef<SortSeg> R;
+        TaskRef<SortSeg> R{};
         R.A = T;
         R.one = stab[0];
         R.tab = ar.dev<SortSeg>(o_st);
         R.pre = ar.dev<uint32_t>(o_pt);
         hipError_t e = launch_tile_sort(dt, pairs, R, ptile[T], base_bytes, ws, st);
         if (e != hipSuccess) return hip_error(e, "base case");
-        R.pre = ar.dev<uint32_t>(o_pm);
-        for (uint32_t l = 0; l < maxL; ++l) {
-            uint32_t Al = 0;
+        // one launch group per (binary level, pass kind) over a contiguous
+        // range [a0, a1) of the table
+        auto run = [&](uint32_t a0, uint32_t a1, uint32_t l, bool four) -> hipError_t {
+            if (a1 <= a0) return hipSuccess;
+            TaskRef<SortSeg> Rl{};
+            Rl.A = a1 - a0;
+            Rl.one = stab[a0];
+            Rl.tab = ar.dev<SortSeg>(o_st) + a0;
+            Rl.pre = ar.dev<uint32_t>(o_pm) + a0;
+            Rl.base = pmerge[a0];
             double mb = 0;
-            while (Al < T && stab[Al].L > l) {
-                mb += 16.0 * w * (double)stab[Al].m;
-                ++Al;
+            for (uint32_t a = a0; a < a1; ++a) mb += 16.0 * w * (double)stab[a].m;
+            const uint32_t pass = pass_index(stab[a0].L, l, pairs);
+            return launch_merge_pass(dt, pairs, Rl, l, pass, four, pmerge[a1] - pmerge[a0], mb, ws,
+                                     st);
+        };
+        for (uint32_t l = 0; l < maxL; ++l) {
+            if (!by_parity) {
+                uint32_t a1 = 0;
+                while (a1 < T && stab[a1].L > l) ++a1;
+                e = run(0, a1, l, false);
+            } else {
+                // the class whose passes start at l: even L at even l, odd L at odd l
+                const uint32_t c0 = (l & 1u) ? E : 0, c_end = (l & 1u) ? T : E;
+                uint32_t a1 = c0;
+                while (a1 < c_end && stab[a1].L > l) ++a1;
+                e = run(c0, a1, l, true);
+                if (e == hipSuccess && l == 0) {
+                    // 2-way first passes of the odd tasks
+                    uint32_t b1 = E;
+                    while (b1 < T && stab[b1].L > 0) ++b1;
+                    e = run(E, b1, 0, false);
+                }
             }
-            TaskRef<SortSeg> Rl = R;
-            Rl.A = Al;
-            e = launch_merge_level(dt, pairs, Rl, l, pmerge[Al], mb, ws, st);
-            if (e != hipSuccess) return hip_error(e, "merge level");
+            if (e != hipSuccess) return hip_error(e, "merge pass");
         }
     }
     return QMS_OK;

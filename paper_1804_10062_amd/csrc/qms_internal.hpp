@@ -37,7 +37,10 @@ struct Workspace {
     uint32_t *spL = nullptr;     // [kCapChunks]
     uint32_t *spR = nullptr;     // [kCapChunks]
     uint32_t *splits = nullptr;  // [kCapSplits]
-    uint32_t *samples[2] = {nullptr, nullptr};  // [kCapSplits] each: run samples, by level parity
+    uint32_t *samples[2] = {nullptr, nullptr};  // [kCapSplits] each: run samples, by pass parity
+    uint32_t *pair_samples = nullptr;  // [kCapSplits] 4-way pass: element at each pair split
+    uint32_t *bounds = nullptr;        // [4 * kCapSplits] 4-way pass: tile starts
+    uint32_t *ends = nullptr;          // [4 * kCapSplits] 4-way pass: tile ends
     uint64_t *meta = nullptr;    // [kCapSegs * M_COUNT]
     uint32_t *res = nullptr;     // [4 * kCapSegs] per-segment partition results
     uint32_t *hist = nullptr;    // [256 * kCapMoM] median-of-medians select histograms
@@ -78,7 +81,10 @@ hipError_t launch_mom_pivot(int dt, const TaskRef<PartSeg> &tasks, uint32_t tile
                             const Workspace &ws, hipStream_t st);
 hipError_t launch_tile_sort(int dt, bool pairs, const TaskRef<SortSeg> &tasks, uint32_t tiles,
                             double bytes, const Workspace &ws, hipStream_t st);
-hipError_t launch_merge_level(int dt, bool pairs, const TaskRef<SortSeg> &tasks, uint32_t level,
-                              uint32_t tiles, double bytes, const Workspace &ws, hipStream_t st);
+// One merge pass (2-way or 4-way) of the tasks listed, all starting at binary
+// level `level` with the same pass index `pass`.
+hipError_t launch_merge_pass(int dt, bool pairs, const TaskRef<SortSeg> &tasks, uint32_t level,
+                             uint32_t pass, bool four_way, uint32_t tiles, double bytes,
+                             const Workspace &ws, hipStream_t st);
 
 }  // namespace qms

@@ -1,24 +1,37 @@
-// qms_merge.hip -- one level of the swap-merge on gfx950.
+// qms_merge.hip -- the swap-merge passes of the Mergesort on gfx950.
 //
 // Fig. 2's merge takes two sorted runs and writes their merge into a target
 // area, moving the elements found in the target into the cells the runs
 // vacate (Sec. "QuickXsort and QuickMergesort": an element Mergesort would
 // move to extra space is swapped with the element occupying that cell).
 //
-// Here a level merges consecutive pairs of runs of width W of a source
-// region S into the destination region D of the same length (S and D are the
+// 2-way pass: consecutive pairs of runs of width W of a source region S are
+// merged into the destination region D of the same length (S and D are the
 // data side and the buffer side of the current partition round, in either
 // order).  The output of each pair is cut into tiles of kMergeTile elements;
 // the merge-path split (the diagonal search of Odeh et al.'s Merge Path) gives
 // every tile its own slice of each run, disjoint from every other tile's
-// slices.  A workgroup therefore reads its two run slices and its output
-// window of D, writes the merged keys into the window and the displaced
-// window contents into the run-slice cells it just read.  No workgroup
-// touches another's cells.  The splits are found by a separate kernel before
-// the level starts: a search inside the merge kernel would probe run cells
-// that neighbouring workgroups are already overwriting with buffer elements.
-// The split array (one word per tile) is part of the fixed-size workspace.
-// Ties go to the left run.
+// slices.  A workgroup reads its two run slices and its output window of D,
+// writes the merged keys into the window and the displaced window contents
+// into the run-slice cells it just read.  No workgroup touches another's
+// cells.  The splits are found by a separate kernel before the pass starts: a
+// search inside the merge kernel would probe run cells that neighbouring
+// workgroups are already overwriting with buffer elements.
+//
+// 4-way pass (key-only sorts; the multi-way merging the paper's conclusion
+// proposes): groups of four runs A, B, C, D are merged at once, so a pass
+// moves every element once for two levels of the binary Mergesort.  Its
+// tiles are bounded by exact boundaries that need no multi-way search: the
+// pair splits of (A, B) and (C, D) at every kMergeTile-th element give the
+// elements x = AB[k kMergeTile] and y = CD[j kMergeTile] with their places
+// in their pair, and the place of x among C and D is #(C < x) + #(D < x)
+// (ties go to A, then B, then C, then D), of y among A and B #(A <= y) +
+// #(B <= y): two plain searches each.  A tile runs from one boundary to the
+// next in merge order; it holds at most kMergeTile elements of each pair.
+// The workgroup merges A with B and C with D in LDS, then the two results.
+//
+// Ties go to the earlier run.  The split arrays (one word per tile) and the
+// run samples the searches start from are part of the fixed-size workspace.
 #include "qms_device.hpp"
 #include "qms_internal.hpp"
 #include "qms_prof.hpp"
@@ -42,15 +55,17 @@ __device__ __forceinline__ MergeTileGeom merge_geom(uint64_t m, uint64_t W, uint
     return g;
 }
 
-// Regions of a merge level: the base case leaves the runs in R0 (the buffer
-// when the level count is odd, the data region otherwise); level l reads
-// R(l mod 2) and writes the other region, so the last level ends in D.
+// Regions of a merge pass: the base case leaves the runs in R0 (the buffer
+// when the pass count is odd, the data region otherwise); pass p reads
+// R(p mod 2) and writes the other region, so the last pass ends in D.
+template <bool PAIRS>
 __device__ __forceinline__ void level_regions(const SortSeg &g, uint32_t level, uint32_t *src,
                                               uint32_t *dst) {
-    const bool odd = (g.L & 1u) != 0;
+    const bool odd = (merge_passes(g.L, PAIRS) & 1u) != 0;
     const uint32_t r0 = odd ? g.Bf : g.D, r1 = odd ? g.D : g.Bf;
-    *src = (level & 1u) ? r1 : r0;
-    *dst = (level & 1u) ? r0 : r1;
+    const uint32_t p = pass_index(g.L, level, PAIRS);
+    *src = (p & 1u) ? r1 : r0;
+    *dst = (p & 1u) ? r0 : r1;
 }
 
 // First index in [lo, hi) where the prefix-true predicate pred fails (hi if
@@ -94,10 +109,13 @@ __device__ __forceinline__ uint64_t group_first_false(uint64_t lo, uint64_t hi, 
 //   fine    on the runs, inside that window of fewer than 2S candidates.
 // The 4-lane searches beat both a one-lane binary search (latency) and a
 // wave-wide one (cache lines touched) once there are thousands of splits.
-template <class O>
+// With PSAMP (the first step of a 4-way pass) the kernel also records the
+// element at the split, x = AB[d] (order-mapped), for the boundary kernel.
+template <class O, bool PAIRS, bool PSAMP>
 __global__ __launch_bounds__(kBlock) void k_merge_split(TaskRef<SortSeg> tasks, uint32_t level,
                                                         uint32_t total, uint32_t *splits,
-                                                        const uint32_t *samples) {
+                                                        const uint32_t *samples,
+                                                        uint32_t *pair_samples) {
     constexpr uint64_t S = kMergeTile;
     const uint32_t gid = blockIdx.x * kBlock + threadIdx.x;
     const uint32_t w = gid / kSplitLanes;
@@ -105,7 +123,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_split(TaskRef<SortSeg> tasks, 
     uint32_t tile = 0, a = 0;
     const SortSeg g = task_of(tasks, active ? w : total - 1, &tile, &a);
     uint32_t src, dst;
-    level_regions(g, level, &src, &dst);
+    level_regions<PAIRS>(g, level, &src, &dst);
     const uint64_t W = (uint64_t)g.w0 << level;
     const MergeTileGeom geo = merge_geom(g.m, W, tile);
     const uint32_t *A = g.keys + src + geo.pb;
@@ -127,7 +145,292 @@ __global__ __launch_bounds__(kBlock) void k_merge_split(TaskRef<SortSeg> tasks, 
     const uint64_t c = group_first_false(wl, wh, [&](uint64_t i) {
         return O::ord(ldg(A + i)) <= O::ord(ldg(B + d - 1 - i));
     });
-    if (active && gid % kSplitLanes == 0) splits[g.split_off + tile] = (uint32_t)c;
+    if (active && gid % kSplitLanes == 0) {
+        splits[g.split_off + tile] = (uint32_t)c;
+        if constexpr (PSAMP) {
+            // the element at output d of the pair (d < nA + nB for a tile)
+            const bool fromA =
+                c < nA && (d - c >= nB || O::ord(ldg(A + c)) <= O::ord(ldg(B + (d - c))));
+            pair_samples[g.split_off + tile] = O::ord(ldg(fromA ? A + c : B + (d - c)));
+        }
+    }
+}
+
+// ---- 4-way pass ----------------------------------------------------------------
+// Geometry of pair tile `tile` in a 4-way pass over runs of width W: the group
+// base gb (a multiple of 4W), which pair (0: A,B; 1: C,D), the tile's index k
+// within its pair, and the four run lengths.
+struct Merge4Geom {
+    uint64_t gb;
+    uint32_t which, k;
+    uint32_t n[4];
+};
+__device__ __forceinline__ Merge4Geom merge4_geom(uint64_t m, uint64_t W, uint64_t tile) {
+    Merge4Geom g;
+    const uint64_t start = tile * kMergeTile;
+    g.gb = (start / (4 * W)) * (4 * W);
+    g.which = (uint32_t)((start - g.gb) / (2 * W));
+    g.k = (uint32_t)((start - g.gb - g.which * 2 * W) / kMergeTile);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const uint64_t b = g.gb + r * W;
+        g.n[r] = b >= m ? 0u : (uint32_t)(m - b < W ? m - b : W);
+    }
+    return g;
+}
+
+// Boundaries of a 4-way pass: for every pair tile, the place of its boundary
+// element in each of the four runs (4 words per tile).  Two groups of
+// kSplitLanes lanes per tile, one per run of the other pair; each counts
+// #(Y < x) (x from A, B: C, D come later on ties) or #(Y <= y) (y from C, D),
+// first on Y's samples (every kMergeTile-th element, in cache), then inside
+// the window of one sample gap.  The group of the first run also copies the
+// boundary's own pair split.
+template <class O>
+__global__ __launch_bounds__(kBlock) void k_merge4_bounds(TaskRef<SortSeg> tasks, uint32_t level,
+                                                          uint32_t total, const uint32_t *splits,
+                                                          const uint32_t *pair_samples,
+                                                          const uint32_t *samples,
+                                                          uint32_t *bounds) {
+    constexpr uint64_t S = kMergeTile;
+    const uint32_t gid = blockIdx.x * kBlock + threadIdx.x;
+    const uint32_t w = gid / (2 * kSplitLanes);
+    const uint32_t side = (gid / kSplitLanes) & 1u;
+    const bool active = w < total;
+    uint32_t tile = 0, a = 0;
+    const SortSeg g = task_of(tasks, active ? w : total - 1, &tile, &a);
+    uint32_t src, dst;
+    level_regions<false>(g, level, &src, &dst);
+    const uint64_t W = (uint64_t)g.w0 << level;
+    const Merge4Geom geo = merge4_geom(g.m, W, tile);
+    const uint32_t x = pair_samples[g.split_off + tile];
+    // the run searched: C or D for a boundary of (A, B), A or B for one of (C, D)
+    const uint32_t r = geo.which == 0 ? 2 + side : side;
+    const bool strict = geo.which == 0;
+    const uint32_t *Y = g.keys + src + geo.gb + r * W;
+    const uint32_t *Ys = samples + g.split_off + (geo.gb + r * W) / S;
+    const uint64_t nY = geo.n[r];
+    const uint64_t nS = active ? (nY + S - 1) / S : 0;
+    auto before = [&](uint32_t v) { return strict ? v < x : v <= x; };
+    // coarse: u samples precede x, so the count lies in [(u-1) S + 1, u S]
+    const uint64_t u = group_first_false(0, nS, [&](uint64_t i) { return before(ldg(Ys + i)); });
+    const uint64_t lo = u == 0 ? 0 : (u - 1) * S + 1;
+    const uint64_t hi = u == 0 ? 0 : min(u * S, nY);
+    const uint64_t cnt = group_first_false(lo, hi, [&](uint64_t i) { return before(O::ord(ldg(Y + i))); });
+    if (active && gid % kSplitLanes == 0) {
+        uint32_t *bd = bounds + 4 * ((uint64_t)g.split_off + tile);
+        bd[r] = (uint32_t)cnt;
+        if (side == 0) {
+            const uint32_t own = splits[g.split_off + tile];
+            const uint32_t o = geo.which == 0 ? 0 : 2;
+            bd[o] = own;
+            bd[o + 1] = geo.k * (uint32_t)S - own;
+        }
+    }
+}
+
+// End of every 4-way tile: the next boundary in merge order, i.e. the next
+// boundary of its own pair or the first boundary of the other pair placed
+// after it, whichever comes first (4 words per tile, from the start vectors).
+// One thread per tile.
+__global__ __launch_bounds__(kBlock) void k_merge4_ends(TaskRef<SortSeg> tasks, uint32_t level,
+                                                        uint32_t total, const uint32_t *bounds,
+                                                        uint32_t *ends) {
+    constexpr uint32_t S = kMergeTile;
+    const uint32_t w = blockIdx.x * kBlock + threadIdx.x;
+    if (w >= total) return;
+    uint32_t tile, a;
+    const SortSeg g = task_of(tasks, w, &tile, &a);
+    const uint64_t W = (uint64_t)g.w0 << level;
+    const Merge4Geom geo = merge4_geom(g.m, W, tile);
+    const uint32_t *bd = bounds + 4 * (uint64_t)g.split_off;
+    uint32_t s[4], e[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        s[r] = bd[4 * tile + r];
+        e[r] = geo.n[r];
+    }
+    const uint32_t nP[2] = {geo.n[0] + geo.n[1], geo.n[2] + geo.n[3]};
+    const uint64_t first[2] = {geo.gb / S, (geo.gb + 2 * W) / S};  // first tile of each pair
+    uint64_t best = ~0ull;
+    auto consider = [&](uint64_t c) {
+        uint32_t v[4];
+        uint64_t pos = 0;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            v[r] = bd[4 * c + r];
+            pos += v[r];
+        }
+        if (pos < best) {
+            best = pos;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) e[r] = v[r];
+        }
+    };
+    if ((geo.k + 1) * S < nP[geo.which]) consider(tile + 1);
+    const uint32_t other = 1 - geo.which;
+    const uint32_t placed = other == 0 ? s[0] + s[1] : s[2] + s[3];
+    const uint32_t j = (placed + S - 1) / S;
+    if ((uint64_t)j * S < nP[other]) consider(first[other] + j);
+    uint32_t *out = ends + 4 * ((uint64_t)g.split_off + tile);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) out[r] = e[r];
+}
+
+// LDS index with one spare word every 32: the strided accesses of the merge
+// (thread t at 8 t or 16 t) then fall into different banks.
+__device__ __forceinline__ uint32_t pad32(uint32_t e) { return e + (e >> 5); }
+
+// Outputs [d, d + N) of the stable merge of X[x0, x0 + nx) and Y[y0, y0 + ny)
+// (padded LDS indices; X first on ties) into out[]; d < nx + ny.
+template <int N>
+__device__ __forceinline__ void merge_lds(const uint32_t *sk, uint32_t x0, uint32_t nx,
+                                          uint32_t y0, uint32_t ny, uint32_t d,
+                                          uint32_t (&out)[N]) {
+    uint32_t lo = d > ny ? d - ny : 0, hi = d < nx ? d : nx;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (sk[pad32(x0 + mid)] <= sk[pad32(y0 + d - 1 - mid)]) lo = mid + 1;
+        else hi = mid;
+    }
+    uint32_t i = lo, j = d - lo;
+    uint32_t kx = i < nx ? sk[pad32(x0 + i)] : 0u;
+    uint32_t ky = j < ny ? sk[pad32(y0 + j)] : 0u;
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+        const bool takeX = j >= ny || (i < nx && kx <= ky);
+        out[q] = takeX ? kx : ky;
+        if (takeX) {
+            ++i;
+            kx = i < nx ? sk[pad32(x0 + i)] : 0u;
+        } else {
+            ++j;
+            ky = j < ny ? sk[pad32(y0 + j)] : 0u;
+        }
+    }
+}
+
+// One workgroup per boundary: the tile from its start vector to its end
+// vector.  The slices A|B|C|D are staged in LDS; A with B and C with D are
+// merged into registers and written back over their own slices, then the two
+// halves are merged the same way; 16 KB of LDS and few registers, so that
+// eight workgroups (as many elements in flight as the 2-way pass) stay
+// resident per CU.
+constexpr int kMerge4Threads = 256;
+#ifndef QMS_MERGE4_WPE
+#define QMS_MERGE4_WPE 8
+#endif
+#ifndef QMS_MERGE4_BATCH
+#define QMS_MERGE4_BATCH 8
+#endif
+template <class O>
+__global__ __launch_bounds__(kMerge4Threads)
+__attribute__((amdgpu_waves_per_eu(QMS_MERGE4_WPE, QMS_MERGE4_WPE))) void k_merge4(
+    TaskRef<SortSeg> tasks, uint32_t level,
+                                                           const uint32_t *bounds,
+                                                           const uint32_t *ends,
+                                                           uint32_t *samples_out) {
+    constexpr uint32_t S = kMergeTile;
+    constexpr int NT = kMerge4Threads;
+    constexpr int PER = 2 * S / NT;  // elements per thread at most
+    constexpr int PER2 = S / NT;     // outputs per thread and pair
+    __shared__ uint32_t sk[2 * S + 2 * S / 32];
+    uint32_t tile, a;
+    const SortSeg g = task_of(tasks, blockIdx.x, &tile, &a);
+    if (tile * (uint64_t)S >= g.m) return;
+    uint32_t src, dst;
+    level_regions<false>(g, level, &src, &dst);
+    const uint64_t W = (uint64_t)g.w0 << level;
+    const Merge4Geom geo = merge4_geom(g.m, W, tile);
+    const uint64_t at = 4 * ((uint64_t)g.split_off + tile);
+    uint32_t s[4], len[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        // clamped to the runs and the LDS tile (a no-op for consistent bounds)
+        s[r] = min(bounds[at + r], geo.n[r]);
+        len[r] = min(max(ends[at + r], s[r]), geo.n[r]) - s[r];
+    }
+    len[1] = min(len[1], S - min(len[0], S));
+    len[0] = min(len[0], S);
+    len[3] = min(len[3], S - min(len[2], S));
+    len[2] = min(len[2], S);
+    const uint32_t c1 = len[0], c2 = c1 + len[1], c3 = c2 + len[2], cnt = c3 + len[3];
+    if (cnt == 0) return;
+    const uint64_t ps = (uint64_t)s[0] + s[1] + s[2] + s[3];
+    uint32_t *S_ = g.keys + src + geo.gb;
+    uint32_t *T_ = g.keys + dst + geo.gb + ps;
+    const uint32_t tid = threadIdx.x;
+    // source cell of tile element el (runs A, B, C, D in order), as an
+    // offset from the group base (< 4 W <= m < 2^32)
+    const uint32_t W32 = (uint32_t)W;
+    const uint32_t off1 = W32 + s[1] - c1, off2 = 2 * W32 + s[2] - c2, off3 = 3 * W32 + s[3] - c3;
+    // (steps between the runs' offsets, added by comparison: a select chain
+    // here is turned into a table in scratch memory)
+    const uint32_t off0 = s[0], d1 = off1 - off0, d2 = off2 - off1, d3 = off3 - off2;
+    auto cell = [=](uint32_t el) -> uint32_t {
+        return off0 + el + (uint32_t)(el >= c1) * d1 + (uint32_t)(el >= c2) * d2 +
+               (uint32_t)(el >= c3) * d3;
+    };
+    {
+        // the window's buffer elements go to the run cells as soon as both
+        // are loaded (each cell is read and written by the same thread), so
+        // that no registers hold them through the merge
+        constexpr int B = QMS_MERGE4_BATCH;
+#pragma unroll
+        for (int q0 = 0; q0 < PER; q0 += B) {
+            uint32_t oldk[B], nk[B];
+#pragma unroll
+            for (int q = 0; q < B; ++q) {
+                const uint32_t el = min((uint32_t)((q0 + q) * NT + tid), cnt - 1);
+                oldk[q] = ldg(T_ + el);
+                nk[q] = ldg(S_ + cell(el));
+            }
+#pragma unroll
+            for (int q = 0; q < B; ++q) {
+                const uint32_t el = (q0 + q) * NT + tid;
+                if (el < cnt) {
+                    sk[pad32(el)] = O::ord(nk[q]);
+                    stg(S_ + cell(el), oldk[q]);
+                }
+            }
+        }
+    }
+    __syncthreads();
+    {
+        // A with B over [0, c2), C with D over [c2, cnt)
+        uint32_t ab[PER2], cd[PER2];
+        const uint32_t d = tid * PER2;
+        if (d < c2) merge_lds<PER2>(sk, 0, c1, c1, c2 - c1, d, ab);
+        if (d < cnt - c2) merge_lds<PER2>(sk, c2, c3 - c2, c3, cnt - c3, d, cd);
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < PER2; ++q) {
+            if (d + q < c2) sk[pad32(d + q)] = ab[q];
+            if (d + q < cnt - c2) sk[pad32(c2 + d + q)] = cd[q];
+        }
+    }
+    __syncthreads();
+    {
+        uint32_t o[PER];
+        const uint32_t d = tid * PER;
+        if (d < cnt) merge_lds<PER>(sk, 0, c2, c2, cnt - c2, d, o);
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < PER; ++q)
+            if (d + q < cnt) sk[pad32(d + q)] = o[q];
+    }
+    __syncthreads();
+    // samples of the output runs: every kMergeTile-th position of the group
+    {
+        const uint32_t first = (uint32_t)((S - ps % S) % S);
+        const uint32_t el = first + tid * S;
+        if (el < cnt) stg(samples_out + g.split_off + (geo.gb + ps + el) / S, sk[pad32(el)]);
+    }
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const uint32_t el = q * NT + tid;
+        if (el < cnt) stg(T_ + el, O::unord(sk[pad32(el)]));
+    }
 }
 
 template <class O, bool PAIRS>
@@ -248,42 +551,66 @@ __global__ __launch_bounds__(kBlock) void k_merge(TaskRef<SortSeg> tasks, uint32
     const SortSeg g = task_of(tasks, blockIdx.x, &tile, &a);
     if (tile * (uint64_t)kMergeTile >= g.m) return;
     uint32_t src, dst;
-    level_regions(g, level, &src, &dst);
+    level_regions<PAIRS>(g, level, &src, &dst);
     merge_block<O, PAIRS>(g.keys + src, PAIRS ? g.vals + src : nullptr, g.keys + dst,
                           PAIRS ? g.vals + dst : nullptr, g.m, (uint64_t)g.w0 << level,
                           tile, splits + g.split_off, samples_out + g.split_off);
 }
 
 template <class O, bool PAIRS>
-static hipError_t merge_t(const TaskRef<SortSeg> &tasks, uint32_t level, uint32_t tiles,
-                          double bytes, const Workspace &ws, hipStream_t st) {
+static hipError_t merge_t(const TaskRef<SortSeg> &tasks, uint32_t level, uint32_t pass,
+                          bool four_way, uint32_t tiles, double bytes, const Workspace &ws,
+                          hipStream_t st) {
     if (tiles == 0) return hipSuccess;
-    // level l searches the samples written by level l - 1 (or the base case)
+    // pass p searches the samples written by pass p - 1 (or the base case)
     // and writes the other array
-    const uint32_t *smp_in = ws.samples[level & 1];
-    uint32_t *smp_out = ws.samples[(level + 1) & 1];
-    {
-        ProfScope prof(st, K_MERGE_SPLIT, 0.0);
-        const uint64_t threads = (uint64_t)tiles * kSplitLanes;
-        hipLaunchKernelGGL((k_merge_split<O>), dim3((uint32_t)((threads + kBlock - 1) / kBlock)),
-                           dim3(kBlock), 0, st, tasks, level, tiles, ws.splits, smp_in);
+    const uint32_t *smp_in = ws.samples[pass & 1];
+    uint32_t *smp_out = ws.samples[(pass + 1) & 1];
+    const uint32_t sgrid = (uint32_t)(((uint64_t)tiles * kSplitLanes + kBlock - 1) / kBlock);
+    if (!four_way) {
+        {
+            ProfScope prof(st, K_MERGE_SPLIT, 0.0);
+            hipLaunchKernelGGL((k_merge_split<O, PAIRS, false>), dim3(sgrid), dim3(kBlock), 0, st,
+                               tasks, level, tiles, ws.splits, smp_in, (uint32_t *)nullptr);
+        }
+        {
+            // per element: read the run cell and the window cell, write both
+            ProfScope prof(st, K_MERGE, bytes);
+            hipLaunchKernelGGL((k_merge<O, PAIRS>), dim3(tiles), dim3(kBlock), 0, st, tasks,
+                               level, (const uint32_t *)ws.splits, smp_out);
+        }
+        return hipGetLastError();
     }
-    {
-        // per element: read the run cell and the window cell, write both
-        ProfScope prof(st, K_MERGE, bytes);
-        hipLaunchKernelGGL((k_merge<O, PAIRS>), dim3(tiles), dim3(kBlock), 0, st, tasks, level,
-                           (const uint32_t *)ws.splits, smp_out);
+    if constexpr (!PAIRS) {
+        {
+            ProfScope prof(st, K_MERGE_SPLIT, 0.0);
+            hipLaunchKernelGGL((k_merge_split<O, false, true>), dim3(sgrid), dim3(kBlock), 0, st,
+                               tasks, level, tiles, ws.splits, smp_in, ws.pair_samples);
+            hipLaunchKernelGGL((k_merge4_bounds<O>), dim3(2 * sgrid), dim3(kBlock), 0, st, tasks,
+                               level, tiles, (const uint32_t *)ws.splits,
+                               (const uint32_t *)ws.pair_samples, smp_in, ws.bounds);
+            hipLaunchKernelGGL(k_merge4_ends, dim3((tiles + kBlock - 1) / kBlock), dim3(kBlock),
+                               0, st, tasks, level, tiles, (const uint32_t *)ws.bounds, ws.ends);
+        }
+        {
+            // the same 16 bytes per element as a 2-way pass, for two levels
+            ProfScope prof(st, K_MERGE, bytes);
+            hipLaunchKernelGGL((k_merge4<O>), dim3(tiles), dim3(kMerge4Threads), 0, st, tasks, level,
+                               (const uint32_t *)ws.bounds, (const uint32_t *)ws.ends, smp_out);
+        }
+        return hipGetLastError();
     }
-    return hipGetLastError();
+    return hipErrorInvalidValue;
 }
 
-hipError_t launch_merge_level(int dt, bool pairs, const TaskRef<SortSeg> &tasks, uint32_t level,
-                              uint32_t tiles, double bytes, const Workspace &ws, hipStream_t st) {
+hipError_t launch_merge_pass(int dt, bool pairs, const TaskRef<SortSeg> &tasks, uint32_t level,
+                             uint32_t pass, bool four_way, uint32_t tiles, double bytes,
+                             const Workspace &ws, hipStream_t st) {
     if (dt == 1)
-        return pairs ? merge_t<OrdF32, true>(tasks, level, tiles, bytes, ws, st)
-                     : merge_t<OrdF32, false>(tasks, level, tiles, bytes, ws, st);
-    return pairs ? merge_t<OrdU32, true>(tasks, level, tiles, bytes, ws, st)
-                 : merge_t<OrdU32, false>(tasks, level, tiles, bytes, ws, st);
+        return pairs ? merge_t<OrdF32, true>(tasks, level, pass, four_way, tiles, bytes, ws, st)
+                     : merge_t<OrdF32, false>(tasks, level, pass, four_way, tiles, bytes, ws, st);
+    return pairs ? merge_t<OrdU32, true>(tasks, level, pass, four_way, tiles, bytes, ws, st)
+                 : merge_t<OrdU32, false>(tasks, level, pass, four_way, tiles, bytes, ws, st);
 }
 
 }  // namespace qms
