@@ -25,7 +25,7 @@ COMMON = [
     "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
     f"--offload-arch={ARCH}",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+    "-I", os.path.join(ROOT, "include"),
 ]
 
 
@@ -38,18 +38,20 @@ def _hipcc() -> str:
 
 def _compile(src: str, extra=(), build_dir: str = BUILD) -> str:
     obj = os.path.join(build_dir, os.path.basename(src) + ".o")
-    cmd = [_hipcc()] + COMMON + list(extra) + ["-c", src, "-o", obj]
+    cmd = [_hipcc()] + COMMON + ["-I", os.path.dirname(src)] + list(extra) + ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")
     return obj
 
 
-def build(verbose: bool = False, defines=(), out: str = LIB, build_dir: str = BUILD) -> str:
+def build(verbose: bool = False, defines=(), out: str = LIB, build_dir: str = BUILD,
+          csrc: str = CSRC) -> str:
     """Compile and link; `defines` (e.g. ["QMS_MERGE_ITEMS=16"]) override
-    build-time tunables, `out` names the library written."""
+    build-time tunables, `out` names the library written, `csrc` the source
+    directory."""
     os.makedirs(build_dir, exist_ok=True)
-    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
+    srcs = sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.cpp")))
     extra = [f"-D{d}" for d in defines]
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(lambda s: _compile(s, extra, build_dir), srcs))

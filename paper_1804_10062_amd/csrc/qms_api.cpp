@@ -37,7 +37,7 @@ static std::mutex g_ws_mutex;
 static std::map<std::pair<int, hipStream_t>, Workspace *> g_ws;
 
 static size_t ws_words() {
-    return 3ull * kCapTiles + 2ull * (kCapTiles + kCapSegs) + 2ull * kCapChunks + 12ull * kCapSplits +
+    return 3ull * kCapTiles + 2ull * (kCapTiles + kCapSegs) + 2ull * kCapChunks + 16ull * kCapSplits +
            4ull * kCapSegs + 256ull * kCapMoM;
 }
 
@@ -103,7 +103,7 @@ int get_workspace(int device, hipStream_t stream, Workspace **out) {
     ws->bounds = w;
     w += 4ull * kCapSplits;
     ws->ends = w;
-    w += 4ull * kCapSplits;
+    w += 8ull * kCapSplits;
     ws->res = w;
     w += 4ull * kCapSegs;
     ws->hist = w;

@@ -231,8 +231,10 @@ __global__ __launch_bounds__(kBlock) void k_merge4_bounds(TaskRef<SortSeg> tasks
 
 // End of every 4-way tile: the next boundary in merge order, i.e. the next
 // boundary of its own pair or the first boundary of the other pair placed
-// after it, whichever comes first (4 words per tile, from the start vectors).
-// One thread per tile.
+// after it, whichever comes first.  The tile's start and end are stored at the
+// tile's index, 8 words per tile (running the merge workgroups in output
+// order instead was measured slower: the concurrent workgroups then crowd a
+// narrow address range).  One thread per tile.
 __global__ __launch_bounds__(kBlock) void k_merge4_ends(TaskRef<SortSeg> tasks, uint32_t level,
                                                         uint32_t total, const uint32_t *bounds,
                                                         uint32_t *ends) {
@@ -272,69 +274,94 @@ __global__ __launch_bounds__(kBlock) void k_merge4_ends(TaskRef<SortSeg> tasks, 
     const uint32_t placed = other == 0 ? s[0] + s[1] : s[2] + s[3];
     const uint32_t j = (placed + S - 1) / S;
     if ((uint64_t)j * S < nP[other]) consider(first[other] + j);
-    uint32_t *out = ends + 4 * ((uint64_t)g.split_off + tile);
+    uint32_t *out = ends + 8 * ((uint64_t)g.split_off + tile);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) out[r] = e[r];
+    for (int r = 0; r < 4; ++r) {
+        out[r] = s[r];
+        out[4 + r] = e[r];
+    }
 }
 
-// LDS index with one spare word every 32: the strided accesses of the merge
-// (thread t at 8 t or 16 t) then fall into different banks.
-__device__ __forceinline__ uint32_t pad32(uint32_t e) { return e + (e >> 5); }
-
-// Outputs [d, d + N) of the stable merge of X[x0, x0 + nx) and Y[y0, y0 + ny)
-// (padded LDS indices; X first on ties) into out[]; d < nx + ny.
+// Outputs [d, d + N) of the stable merge of X = sk[x0, x0 + nx) and
+// Y = sk[y0, y0 + ny) into out[] (X first on ties); d < nx + ny.
 template <int N>
 __device__ __forceinline__ void merge_lds(const uint32_t *sk, uint32_t x0, uint32_t nx,
                                           uint32_t y0, uint32_t ny, uint32_t d,
                                           uint32_t (&out)[N]) {
+    const uint32_t *X = sk + x0, *Y = sk + y0;
     uint32_t lo = d > ny ? d - ny : 0, hi = d < nx ? d : nx;
     while (lo < hi) {
         const uint32_t mid = (lo + hi) >> 1;
-        if (sk[pad32(x0 + mid)] <= sk[pad32(y0 + d - 1 - mid)]) lo = mid + 1;
+        if (X[mid] <= Y[d - 1 - mid]) lo = mid + 1;
         else hi = mid;
     }
+    // branch-free: reads are clamped into the arrays (a value read past an
+    // end is never taken; an empty array reads the word at its start, which
+    // the caller's LDS array holds)
+    const uint32_t xl = nx ? nx - 1 : 0, yl = ny ? ny - 1 : 0;
     uint32_t i = lo, j = d - lo;
-    uint32_t kx = i < nx ? sk[pad32(x0 + i)] : 0u;
-    uint32_t ky = j < ny ? sk[pad32(y0 + j)] : 0u;
+    uint32_t kx = X[min(i, xl)], ky = Y[min(j, yl)];
 #pragma unroll
     for (int q = 0; q < N; ++q) {
         const bool takeX = j >= ny || (i < nx && kx <= ky);
         out[q] = takeX ? kx : ky;
-        if (takeX) {
-            ++i;
-            kx = i < nx ? sk[pad32(x0 + i)] : 0u;
-        } else {
-            ++j;
-            ky = j < ny ? sk[pad32(y0 + j)] : 0u;
-        }
+        i += takeX;
+        j += !takeX;
+        const uint32_t nkx = X[min(i, xl)], nky = Y[min(j, yl)];
+        kx = takeX ? nkx : kx;
+        ky = takeX ? ky : nky;
     }
+}
+
+// The two pair merges of a 4-way tile in place: A with B over [0, c2) by the
+// first half of the threads, C with D over [c2, cnt) by the second half, N
+// outputs per thread.
+template <int N, int NT>
+__device__ __forceinline__ void merge4_halves(uint32_t *sk, uint32_t c1, uint32_t c2, uint32_t c3,
+                                              uint32_t cnt, uint32_t tid) {
+    const bool cd = tid >= NT / 2;
+    const uint32_t d = (cd ? tid - NT / 2 : tid) * N;
+    const uint32_t base = cd ? c2 : 0, nx = cd ? c3 - c2 : c1, n = cd ? cnt - c2 : c2;
+    uint32_t o[N];
+    if (d < n) merge_lds<N>(sk, base, nx, base + nx, n - nx, d, o);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < N; ++q)
+        if (d + q < n) sk[base + d + q] = o[q];
+    __syncthreads();
+}
+// The two halves [0, c2) and [c2, cnt) merged in place, N outputs per thread.
+template <int N>
+__device__ __forceinline__ void merge4_final(uint32_t *sk, uint32_t c2, uint32_t cnt,
+                                             uint32_t tid) {
+    uint32_t o[N];
+    const uint32_t d = tid * N;
+    if (d < cnt) merge_lds<N>(sk, 0, c2, c2, cnt - c2, d, o);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < N; ++q)
+        if (d + q < cnt) sk[d + q] = o[q];
+    __syncthreads();
 }
 
 // One workgroup per boundary: the tile from its start vector to its end
 // vector.  The slices A|B|C|D are staged in LDS; A with B and C with D are
-// merged into registers and written back over their own slices, then the two
-// halves are merged the same way; 16 KB of LDS and few registers, so that
-// eight workgroups (as many elements in flight as the 2-way pass) stay
-// resident per CU.
-constexpr int kMerge4Threads = 256;
+// merged and written back over their own slices, then the two halves are
+// merged the same way; 16 KB of LDS and few registers, so that eight
+// workgroups (as many elements in flight as the 2-way pass) stay resident
+// per CU.
 #ifndef QMS_MERGE4_WPE
 #define QMS_MERGE4_WPE 8
 #endif
-#ifndef QMS_MERGE4_BATCH
-#define QMS_MERGE4_BATCH 8
-#endif
+constexpr int kMerge4Threads = 256;
 template <class O>
 __global__ __launch_bounds__(kMerge4Threads)
 __attribute__((amdgpu_waves_per_eu(QMS_MERGE4_WPE, QMS_MERGE4_WPE))) void k_merge4(
-    TaskRef<SortSeg> tasks, uint32_t level,
-                                                           const uint32_t *bounds,
-                                                           const uint32_t *ends,
-                                                           uint32_t *samples_out) {
+    TaskRef<SortSeg> tasks, uint32_t level, const uint32_t *bounds, const uint32_t *ends,
+    uint32_t *samples_out) {
     constexpr uint32_t S = kMergeTile;
     constexpr int NT = kMerge4Threads;
-    constexpr int PER = 2 * S / NT;  // elements per thread at most
-    constexpr int PER2 = S / NT;     // outputs per thread and pair
-    __shared__ uint32_t sk[2 * S + 2 * S / 32];
+    __shared__ uint32_t sk[2 * S + 1];  // + 1: see merge_lds
     uint32_t tile, a;
     const SortSeg g = task_of(tasks, blockIdx.x, &tile, &a);
     if (tile * (uint64_t)S >= g.m) return;
@@ -342,13 +369,14 @@ __attribute__((amdgpu_waves_per_eu(QMS_MERGE4_WPE, QMS_MERGE4_WPE))) void k_merg
     level_regions<false>(g, level, &src, &dst);
     const uint64_t W = (uint64_t)g.w0 << level;
     const Merge4Geom geo = merge4_geom(g.m, W, tile);
-    const uint64_t at = 4 * ((uint64_t)g.split_off + tile);
+    // the tile's start and end vectors
+    const uint64_t at = 8 * ((uint64_t)g.split_off + tile);
     uint32_t s[4], len[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         // clamped to the runs and the LDS tile (a no-op for consistent bounds)
-        s[r] = min(bounds[at + r], geo.n[r]);
-        len[r] = min(max(ends[at + r], s[r]), geo.n[r]) - s[r];
+        s[r] = min(ends[at + r], geo.n[r]);
+        len[r] = min(max(ends[at + 4 + r], s[r]), geo.n[r]) - s[r];
     }
     len[1] = min(len[1], S - min(len[0], S));
     len[0] = min(len[0], S);
@@ -358,78 +386,64 @@ __attribute__((amdgpu_waves_per_eu(QMS_MERGE4_WPE, QMS_MERGE4_WPE))) void k_merg
     if (cnt == 0) return;
     const uint64_t ps = (uint64_t)s[0] + s[1] + s[2] + s[3];
     uint32_t *S_ = g.keys + src + geo.gb;
-    uint32_t *T_ = g.keys + dst + geo.gb + ps;
+    const uint32_t *T_ = g.keys + dst + geo.gb + ps;
     const uint32_t tid = threadIdx.x;
-    // source cell of tile element el (runs A, B, C, D in order), as an
-    // offset from the group base (< 4 W <= m < 2^32)
+    // tile element el sits in run r at offset cell(el) from the group base
+    // (< 4 W <= m < 2^32); the steps between the runs' offsets are added by
+    // comparison (a select chain here is turned into a table in scratch)
     const uint32_t W32 = (uint32_t)W;
-    const uint32_t off1 = W32 + s[1] - c1, off2 = 2 * W32 + s[2] - c2, off3 = 3 * W32 + s[3] - c3;
-    // (steps between the runs' offsets, added by comparison: a select chain
-    // here is turned into a table in scratch memory)
-    const uint32_t off0 = s[0], d1 = off1 - off0, d2 = off2 - off1, d3 = off3 - off2;
+    const uint32_t off0 = s[0], d1 = W32 + s[1] - c1 - off0, d2 = W32 + s[2] - (c2 - c1) - s[1],
+                   d3 = W32 + s[3] - (c3 - c2) - s[2];
     auto cell = [=](uint32_t el) -> uint32_t {
         return off0 + el + (uint32_t)(el >= c1) * d1 + (uint32_t)(el >= c2) * d2 +
                (uint32_t)(el >= c3) * d3;
     };
     {
-        // the window's buffer elements go to the run cells as soon as both
-        // are loaded (each cell is read and written by the same thread), so
-        // that no registers hold them through the merge
-        constexpr int B = QMS_MERGE4_BATCH;
+        // every load of the tile in flight together (up to 2 S / NT per
+        // thread, as many as the tile needs); the window's buffer element
+        // takes its run cell at once (each cell is read and written by the
+        // same thread), so no registers hold buffer elements through the merge
+        constexpr int Q = 2 * S / NT;
+        uint32_t v[Q], old[Q];
 #pragma unroll
-        for (int q0 = 0; q0 < PER; q0 += B) {
-            uint32_t oldk[B], nk[B];
-#pragma unroll
-            for (int q = 0; q < B; ++q) {
-                const uint32_t el = min((uint32_t)((q0 + q) * NT + tid), cnt - 1);
-                oldk[q] = ldg(T_ + el);
-                nk[q] = ldg(S_ + cell(el));
+        for (int q = 0; q < Q; ++q) {
+            if ((uint32_t)q * NT < cnt) {
+                const uint32_t el = min((uint32_t)q * NT + tid, cnt - 1);
+                v[q] = ldg(S_ + cell(el));
+                old[q] = ldg(T_ + el);
             }
+        }
 #pragma unroll
-            for (int q = 0; q < B; ++q) {
-                const uint32_t el = (q0 + q) * NT + tid;
-                if (el < cnt) {
-                    sk[pad32(el)] = O::ord(nk[q]);
-                    stg(S_ + cell(el), oldk[q]);
-                }
+        for (int q = 0; q < Q; ++q) {
+            const uint32_t el = (uint32_t)q * NT + tid;
+            if (el < cnt) {
+                sk[el] = O::ord(v[q]);
+                stg(S_ + cell(el), old[q]);
             }
         }
     }
     __syncthreads();
-    {
-        // A with B over [0, c2), C with D over [c2, cnt)
-        uint32_t ab[PER2], cd[PER2];
-        const uint32_t d = tid * PER2;
-        if (d < c2) merge_lds<PER2>(sk, 0, c1, c1, c2 - c1, d, ab);
-        if (d < cnt - c2) merge_lds<PER2>(sk, c2, c3 - c2, c3, cnt - c3, d, cd);
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < PER2; ++q) {
-            if (d + q < c2) sk[pad32(d + q)] = ab[q];
-            if (d + q < cnt - c2) sk[pad32(c2 + d + q)] = cd[q];
-        }
-    }
-    __syncthreads();
-    {
-        uint32_t o[PER];
-        const uint32_t d = tid * PER;
-        if (d < cnt) merge_lds<PER>(sk, 0, c2, c2, cnt - c2, d, o);
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < PER; ++q)
-            if (d + q < cnt) sk[pad32(d + q)] = o[q];
-    }
-    __syncthreads();
+    // the merges, with as many outputs per thread as the tile needs (a
+    // typical tile holds kMergeTile elements, half the maximum)
+    if (c2 <= S / 2 && cnt - c2 <= S / 2)
+        merge4_halves<2 * S / NT / 2, NT>(sk, c1, c2, c3, cnt, tid);
+    else
+        merge4_halves<2 * S / NT, NT>(sk, c1, c2, c3, cnt, tid);
+    if (cnt <= S)
+        merge4_final<S / NT>(sk, c2, cnt, tid);
+    else
+        merge4_final<2 * S / NT>(sk, c2, cnt, tid);
     // samples of the output runs: every kMergeTile-th position of the group
     {
         const uint32_t first = (uint32_t)((S - ps % S) % S);
         const uint32_t el = first + tid * S;
-        if (el < cnt) stg(samples_out + g.split_off + (geo.gb + ps + el) / S, sk[pad32(el)]);
+        if (el < cnt) stg(samples_out + g.split_off + (geo.gb + ps + el) / S, sk[el]);
     }
+    uint32_t *Tw = g.keys + dst + geo.gb + ps;
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
+    for (int q = 0; q < 2 * S / NT; ++q) {
         const uint32_t el = q * NT + tid;
-        if (el < cnt) stg(T_ + el, O::unord(sk[pad32(el)]));
+        if (el < cnt) stg(Tw + el, O::unord(sk[el]));
     }
 }
 
@@ -496,25 +510,21 @@ __device__ __forceinline__ void merge_block(uint32_t *S, uint32_t *SV, uint32_t 
             if (sk[mid] <= sk[na + diag - 1 - mid]) lo = mid + 1;
             else hi = mid;
         }
+        // branch-free: reads are clamped into the runs (a value read past
+        // an end is never taken; cnt >= 1 so one of the runs is not empty)
+        const uint32_t al = na ? na - 1 : 0, bl = nb ? na + nb - 1 : al;
         uint32_t ia = lo, ib = diag - lo;
-        uint32_t ka = ia < na ? sk[ia] : 0u;
-        uint32_t kb = ib < nb ? sk[na + ib] : 0u;
+        uint32_t ka = sk[min(ia, al)], kb = sk[min(na + ib, bl)];
 #pragma unroll
         for (int q = 0; q < kMergePerThread; ++q) {
-            if (diag + q < cnt) {
-                const bool takeA = ib >= nb || (ia < na && ka <= kb);
-                if (takeA) {
-                    ok[q] = ka;
-                    if constexpr (PAIRS) ov[q] = sv[ia];
-                    ++ia;
-                    ka = ia < na ? sk[ia] : 0u;
-                } else {
-                    ok[q] = kb;
-                    if constexpr (PAIRS) ov[q] = sv[na + ib];
-                    ++ib;
-                    kb = ib < nb ? sk[na + ib] : 0u;
-                }
-            }
+            const bool takeA = ib >= nb || (ia < na && ka <= kb);
+            ok[q] = takeA ? ka : kb;
+            if constexpr (PAIRS) ov[q] = sv[takeA ? min(ia, al) : min(na + ib, bl)];
+            ia += takeA;
+            ib += !takeA;
+            const uint32_t nka = sk[min(ia, al)], nkb = sk[min(na + ib, bl)];
+            ka = takeA ? nka : ka;
+            kb = takeA ? kb : nkb;
         }
     }
     __syncthreads();
