@@ -10,7 +10,8 @@ nearly-sorted (1% random transpositions, seed 3) and reverse-sorted inputs
 are timed the same way and reported beside it.
 
 One JSON line goes to stdout with, besides the contract fields:
-  roofline      for the dominant kernel (the swap-merge level, k_merge):
+  roofline      for the dominant kernel (the swap-merge pass: k_merge4 for
+                the 4-way passes, k_merge for a first 2-way pass):
                 algorithmic bytes per launch (16 B per element of the merged
                 side) over its mean launch duration, timed with HIP events on
                 the sorting stream in a second pass of K sorts right after the
@@ -72,8 +73,9 @@ def merge_source_hash() -> str:
 
 
 def measured_traffic():
-    """HBM bytes per k_merge launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source."""
+    """HBM bytes per merge-pass launch (k_merge and k_merge4 together) from
+    the committed rocprofv3 counter summary, if it was taken on the current
+    kernel source."""
     try:
         d = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
@@ -286,7 +288,7 @@ def main():
     achieved = (mk["bytes"] / 1e9) / (mk["total_ms"] / 1e3)
     traffic = measured_traffic()
     roofline = {
-        "kernel": "k_merge (swap-merge level)",
+        "kernel": "swap-merge pass (k_merge4, k_merge)",
         "bound": "hbm",
         "achieved": round(achieved, 1),
         "peak": HBM_PEAK_GBS,

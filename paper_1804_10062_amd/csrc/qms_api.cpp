@@ -37,7 +37,7 @@ static std::mutex g_ws_mutex;
 static std::map<std::pair<int, hipStream_t>, Workspace *> g_ws;
 
 static size_t ws_words() {
-    return 3ull * kCapTiles + 2ull * (kCapTiles + kCapSegs) + 2ull * kCapChunks + 16ull * kCapSplits +
+    return 3ull * kCapTiles + 2ull * (kCapTiles + kCapSegs) + 2ull * kCapChunks + 15ull * kCapSplits +
            4ull * kCapSegs + 256ull * kCapMoM;
 }
 
@@ -97,8 +97,6 @@ int get_workspace(int device, hipStream_t stream, Workspace **out) {
     ws->samples[0] = w;
     w += kCapSplits;
     ws->samples[1] = w;
-    w += kCapSplits;
-    ws->pair_samples = w;
     w += kCapSplits;
     ws->bounds = w;
     w += 4ull * kCapSplits;

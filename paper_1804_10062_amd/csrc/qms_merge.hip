@@ -109,16 +109,61 @@ __device__ __forceinline__ uint64_t group_first_false(uint64_t lo, uint64_t hi, 
 //   fine    on the runs, inside that window of fewer than 2S candidates.
 // The 4-lane searches beat both a one-lane binary search (latency) and a
 // wave-wide one (cache lines touched) once there are thousands of splits.
-// With PSAMP (the first step of a 4-way pass) the kernel also records the
-// element at the split, x = AB[d] (order-mapped), for the boundary kernel.
-template <class O, bool PAIRS, bool PSAMP>
+// Geometry of pair tile `tile` in a 4-way pass over runs of width W: the group
+// base gb (a multiple of 4W), which pair (0: A,B; 1: C,D), the tile's index k
+// within its pair, and the four run lengths.
+struct Merge4Geom {
+    uint64_t gb;
+    uint32_t which, k;
+    uint32_t n[4];
+};
+__device__ __forceinline__ Merge4Geom merge4_geom(uint64_t m, uint64_t W, uint64_t tile) {
+    Merge4Geom g;
+    const uint64_t start = tile * kMergeTile;
+    g.gb = (start / (4 * W)) * (4 * W);
+    g.which = (uint32_t)((start - g.gb) / (2 * W));
+    g.k = (uint32_t)((start - g.gb - g.which * 2 * W) / kMergeTile);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const uint64_t b = g.gb + r * W;
+        g.n[r] = b >= m ? 0u : (uint32_t)(m - b < W ? m - b : W);
+    }
+    return g;
+}
+
+// Number of elements of the sorted run Y (nY elements, samples Ys of every
+// kMergeTile-th one) that precede x: #(Y < x) if strict, else #(Y <= x).
+// First on the samples (u of them precede x, so the count lies in
+// [(u-1) S + 1, u S]), then inside that gap.  A group collective (every
+// lane of the wave calls it; inactive groups pass nY = 0).
+template <class O>
+__device__ __forceinline__ uint64_t group_count_before(const uint32_t *Y, const uint32_t *Ys,
+                                                       uint64_t nY, uint32_t x, bool strict) {
+    constexpr uint64_t S = kMergeTile;
+    auto before = [&](uint32_t v) { return strict ? v < x : v <= x; };
+    const uint64_t u =
+        group_first_false(0, (nY + S - 1) / S, [&](uint64_t i) { return before(ldg(Ys + i)); });
+    const uint64_t lo = u == 0 ? 0 : (u - 1) * S + 1;
+    const uint64_t hi = u == 0 ? 0 : min(u * S, nY);
+    return group_first_false(lo, hi, [&](uint64_t i) { return before(O::ord(ldg(Y + i))); });
+}
+
+// With BOUNDS (the first step of a 4-way pass over runs A, B, C, D) each tile
+// has two groups; both find the split (the same result, found in parallel),
+// take the element at it, x = AB[d] (or CD[d]), and each counts its
+// predecessors in one run of the other pair: #(C < x) and #(D < x) for a
+// boundary of (A, B) (ties go to A, B first), #(A <= x) and #(B <= x) for
+// one of (C, D).  The tile's start vector (4 words) goes to bounds.
+template <class O, bool PAIRS, bool BOUNDS>
 __global__ __launch_bounds__(kBlock) void k_merge_split(TaskRef<SortSeg> tasks, uint32_t level,
                                                         uint32_t total, uint32_t *splits,
                                                         const uint32_t *samples,
-                                                        uint32_t *pair_samples) {
+                                                        uint32_t *bounds) {
     constexpr uint64_t S = kMergeTile;
+    constexpr uint32_t GPT = BOUNDS ? 2 : 1;  // lane groups per tile
     const uint32_t gid = blockIdx.x * kBlock + threadIdx.x;
-    const uint32_t w = gid / kSplitLanes;
+    const uint32_t w = gid / (GPT * kSplitLanes);
+    const uint32_t half = (gid / kSplitLanes) % GPT;
     const bool active = w < total;
     uint32_t tile = 0, a = 0;
     const SortSeg g = task_of(tasks, active ? w : total - 1, &tile, &a);
@@ -145,90 +190,35 @@ __global__ __launch_bounds__(kBlock) void k_merge_split(TaskRef<SortSeg> tasks, 
     const uint64_t c = group_first_false(wl, wh, [&](uint64_t i) {
         return O::ord(ldg(A + i)) <= O::ord(ldg(B + d - 1 - i));
     });
-    if (active && gid % kSplitLanes == 0) {
-        splits[g.split_off + tile] = (uint32_t)c;
-        if constexpr (PSAMP) {
-            // the element at output d of the pair (d < nA + nB for a tile)
+    if (active && gid % kSplitLanes == 0 && half == 0) splits[g.split_off + tile] = (uint32_t)c;
+    if constexpr (BOUNDS) {
+        // the element at output d of the pair (d < nA + nB for a tile)
+        uint32_t x = 0;
+        if (active) {
             const bool fromA =
                 c < nA && (d - c >= nB || O::ord(ldg(A + c)) <= O::ord(ldg(B + (d - c))));
-            pair_samples[g.split_off + tile] = O::ord(ldg(fromA ? A + c : B + (d - c)));
+            x = O::ord(ldg(fromA ? A + c : B + (d - c)));
+        }
+        const Merge4Geom g4 = merge4_geom(g.m, W, tile);
+        // this group's run of the other pair
+        const uint32_t r = (g4.which == 0 ? 2 : 0) + half;
+        const uint64_t off = g4.gb + r * W;
+        const uint64_t cnt = group_count_before<O>(g.keys + src + off,
+                                                   samples + g.split_off + off / S,
+                                                   active ? g4.n[r] : 0, x, g4.which == 0);
+        if (active && gid % kSplitLanes == 0) {
+            uint32_t *bd = bounds + 4 * ((uint64_t)g.split_off + tile);
+            bd[r] = (uint32_t)cnt;
+            if (half == 0) {
+                const uint32_t o = g4.which == 0 ? 0 : 2;
+                bd[o] = (uint32_t)c;
+                bd[o + 1] = (uint32_t)(d - c);
+            }
         }
     }
 }
 
 // ---- 4-way pass ----------------------------------------------------------------
-// Geometry of pair tile `tile` in a 4-way pass over runs of width W: the group
-// base gb (a multiple of 4W), which pair (0: A,B; 1: C,D), the tile's index k
-// within its pair, and the four run lengths.
-struct Merge4Geom {
-    uint64_t gb;
-    uint32_t which, k;
-    uint32_t n[4];
-};
-__device__ __forceinline__ Merge4Geom merge4_geom(uint64_t m, uint64_t W, uint64_t tile) {
-    Merge4Geom g;
-    const uint64_t start = tile * kMergeTile;
-    g.gb = (start / (4 * W)) * (4 * W);
-    g.which = (uint32_t)((start - g.gb) / (2 * W));
-    g.k = (uint32_t)((start - g.gb - g.which * 2 * W) / kMergeTile);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const uint64_t b = g.gb + r * W;
-        g.n[r] = b >= m ? 0u : (uint32_t)(m - b < W ? m - b : W);
-    }
-    return g;
-}
-
-// Boundaries of a 4-way pass: for every pair tile, the place of its boundary
-// element in each of the four runs (4 words per tile).  Two groups of
-// kSplitLanes lanes per tile, one per run of the other pair; each counts
-// #(Y < x) (x from A, B: C, D come later on ties) or #(Y <= y) (y from C, D),
-// first on Y's samples (every kMergeTile-th element, in cache), then inside
-// the window of one sample gap.  The group of the first run also copies the
-// boundary's own pair split.
-template <class O>
-__global__ __launch_bounds__(kBlock) void k_merge4_bounds(TaskRef<SortSeg> tasks, uint32_t level,
-                                                          uint32_t total, const uint32_t *splits,
-                                                          const uint32_t *pair_samples,
-                                                          const uint32_t *samples,
-                                                          uint32_t *bounds) {
-    constexpr uint64_t S = kMergeTile;
-    const uint32_t gid = blockIdx.x * kBlock + threadIdx.x;
-    const uint32_t w = gid / (2 * kSplitLanes);
-    const uint32_t side = (gid / kSplitLanes) & 1u;
-    const bool active = w < total;
-    uint32_t tile = 0, a = 0;
-    const SortSeg g = task_of(tasks, active ? w : total - 1, &tile, &a);
-    uint32_t src, dst;
-    level_regions<false>(g, level, &src, &dst);
-    const uint64_t W = (uint64_t)g.w0 << level;
-    const Merge4Geom geo = merge4_geom(g.m, W, tile);
-    const uint32_t x = pair_samples[g.split_off + tile];
-    // the run searched: C or D for a boundary of (A, B), A or B for one of (C, D)
-    const uint32_t r = geo.which == 0 ? 2 + side : side;
-    const bool strict = geo.which == 0;
-    const uint32_t *Y = g.keys + src + geo.gb + r * W;
-    const uint32_t *Ys = samples + g.split_off + (geo.gb + r * W) / S;
-    const uint64_t nY = geo.n[r];
-    const uint64_t nS = active ? (nY + S - 1) / S : 0;
-    auto before = [&](uint32_t v) { return strict ? v < x : v <= x; };
-    // coarse: u samples precede x, so the count lies in [(u-1) S + 1, u S]
-    const uint64_t u = group_first_false(0, nS, [&](uint64_t i) { return before(ldg(Ys + i)); });
-    const uint64_t lo = u == 0 ? 0 : (u - 1) * S + 1;
-    const uint64_t hi = u == 0 ? 0 : min(u * S, nY);
-    const uint64_t cnt = group_first_false(lo, hi, [&](uint64_t i) { return before(O::ord(ldg(Y + i))); });
-    if (active && gid % kSplitLanes == 0) {
-        uint32_t *bd = bounds + 4 * ((uint64_t)g.split_off + tile);
-        bd[r] = (uint32_t)cnt;
-        if (side == 0) {
-            const uint32_t own = splits[g.split_off + tile];
-            const uint32_t o = geo.which == 0 ? 0 : 2;
-            bd[o] = own;
-            bd[o + 1] = geo.k * (uint32_t)S - own;
-        }
-    }
-}
-
 // End of every 4-way tile: the next boundary in merge order, i.e. the next
 // boundary of its own pair or the first boundary of the other pair placed
 // after it, whichever comes first.  The tile's start and end are stored at the
@@ -594,11 +584,8 @@ static hipError_t merge_t(const TaskRef<SortSeg> &tasks, uint32_t level, uint32_
     if constexpr (!PAIRS) {
         {
             ProfScope prof(st, K_MERGE_SPLIT, 0.0);
-            hipLaunchKernelGGL((k_merge_split<O, false, true>), dim3(sgrid), dim3(kBlock), 0, st,
-                               tasks, level, tiles, ws.splits, smp_in, ws.pair_samples);
-            hipLaunchKernelGGL((k_merge4_bounds<O>), dim3(2 * sgrid), dim3(kBlock), 0, st, tasks,
-                               level, tiles, (const uint32_t *)ws.splits,
-                               (const uint32_t *)ws.pair_samples, smp_in, ws.bounds);
+            hipLaunchKernelGGL((k_merge_split<O, false, true>), dim3(2 * sgrid), dim3(kBlock), 0,
+                               st, tasks, level, tiles, ws.splits, smp_in, ws.bounds);
             hipLaunchKernelGGL(k_merge4_ends, dim3((tiles + kBlock - 1) / kBlock), dim3(kBlock),
                                0, st, tasks, level, tiles, (const uint32_t *)ws.bounds, ws.ends);
         }
