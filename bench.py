@@ -20,6 +20,9 @@ One JSON line goes to stdout with, besides the contract fields:
                 HBM traffic per launch measured by rocprofv3 counters
                 (profiles/k_merge_traffic.json) while the kernel source is
                 unchanged since that measurement, else null;
+  whole_sort    every algorithmic byte of the executed schedule (base case,
+                merge passes, counting, exchange) over the time per sort,
+                against the same peak;
   cpu_baseline  the CPU oracle (single thread) on a bounded sample of the
                 same workload (the first 2^26 keys), in Gkeys/s;
   kernels       per-kernel-class launches, time and achieved GB/s;
@@ -113,6 +116,16 @@ def bench_batched(qms, torch, np, inputs, per_array_stride: int, reps: int = 3):
     src = torch.randn(n, generator=g, device="cuda", dtype=torch.float32)
     src[src == 0] = 0.0
     ot = torch.from_numpy(off.view(np.int64)).cuda()
+    # tiles and merge arity picked by the autotuner on a sample of the batch
+    # (every 20th array, about 5% of the keys), outside the timed region
+    from paper_1804_10062_amd import autotune
+    sidx = list(range(0, lens.size, 20))
+    slens = lens[sidx]
+    soff = inputs.offsets_from_lengths(slens)
+    sample = torch.cat([src[int(off[j]):int(off[j + 1])] for j in sidx])
+    sot = torch.from_numpy(soff.view(np.int64)).cuda()
+    tune = autotune.autotune_batch(sample, sot, host_offsets=soff)
+    del sample
     work = src.clone()
     times = []
     for _ in range(reps + 1):
@@ -147,6 +160,9 @@ def bench_batched(qms, torch, np, inputs, per_array_stride: int, reps: int = 3):
         "per_array_sample": f"every {per_array_stride}th array ({len(idx)} arrays, "
                             f"{keys_sub} keys), one qms_sort call each",
         "speedup": round(batched / per_array, 2),
+        "tuning": tune["best"],
+        "autotune_trials_ms": {f"{t['merge_ways']}way/{t['partition_tile']}/{t['chunk_span']}":
+                               t["ms"] for t in tune["trials"]},
     }
 
 
@@ -299,6 +315,14 @@ def main():
         "mean_launch_us": mk["total_ms"] / mk["launches"] * 1e3,
         "launches": mk["launches"],
     }
+    # the whole sort against the same peak: all algorithmic bytes of the
+    # executed schedule (base case, merge passes, counting, pass-A exchange)
+    # over the headline time per sort
+    sort_gb = sum(d["bytes"] for d in prof.values()) / K / 1e9
+    whole_sort = {"algorithmic_GB_per_sort": round(sort_gb, 3),
+                  "GB_s": round(sort_gb / (ms / 1e3), 1),
+                  "frac": round(sort_gb / (ms / 1e3) / HBM_PEAK_GBS, 4),
+                  "B_per_key": round(sort_gb * 1e9 / N_KEYS, 1)}
 
     dists = {"uniform": round(value, 3)}
     if not args.only_uniform:
@@ -361,6 +385,7 @@ def main():
                                "seed 2; in-place QuickMergesort",
                    "n": N_KEYS, "rounds": len(sched)},
         "roofline": roofline,
+        "whole_sort": whole_sort,
         "cpu_baseline": cpu,
         "distributions_Gkeys_per_s": dists,
         "batched": batched,

@@ -204,6 +204,30 @@ typedef struct {
 int qms_profile_begin(void);
 int qms_profile_end(qms_kernel_stat *out, int max_entries, int *n_out);
 
+/*
+ * Run-time tunables, process-wide, read at the start of every sort (the
+ * server's worker included); defaults {4, 4096, 16384}.  They change speed,
+ * never results.
+ *   merge_ways      2 or 4: key-only sorts merge four runs per pass (the
+ *                   multi-way merging proposed in the paper's Conclusion) or
+ *                   two; key/payload sorts always merge two.
+ *   partition_tile  keys per counting tile of the partition (a power of two
+ *                   in [4096, 65536]); a round with more than 2^20 tiles
+ *                   doubles it.
+ *   chunk_span      target positions per exchange chunk of the partition, in
+ *                   [4096, 2^20] (smaller: more, shorter chunks).
+ * qms_set_tuning returns QMS_ERR_INVALID for values out of range (nothing is
+ * changed then).  The package's autotuner (paper_1804_10062_amd/autotune.py)
+ * picks them for a workload by timing sorts of a sample.
+ */
+typedef struct {
+    uint32_t merge_ways;
+    uint32_t partition_tile;
+    uint32_t chunk_span;
+} qms_tuning;
+int qms_set_tuning(const qms_tuning *t);
+int qms_get_tuning(qms_tuning *t);
+
 /* Tunables as used by the kernels: base-case tile, merge tile, partition
  * tile (elements).  Read-only; for reports and tests. */
 void qms_get_tiles(uint32_t *base_tile, uint32_t *merge_tile,

@@ -1,0 +1,75 @@
+"""Autotuner for the run-time tunables of libqms (qms_set_tuning).
+
+The batched solves pick their partition and merge parameters by measurement:
+each candidate tuning sorts fresh copies of a sample of the workload (a
+device-resident batch the caller provides), timed with events on the sorting
+stream, and the fastest is kept and set.  Tunings change speed, never
+results.  torch provides the copies and the events; all sorting runs in
+libqms.
+
+    from paper_1804_10062_amd import autotune
+    report = autotune.autotune_batch(sample_keys, sample_offsets)
+"""
+from __future__ import annotations
+
+import itertools
+from typing import Iterable, Optional, Sequence, Tuple
+
+from . import qms
+
+# (merge_ways, partition_tile, chunk_span)
+CANDIDATES: Tuple[Tuple[int, int, int], ...] = tuple(
+    itertools.product((4, 2), (4096, 8192), (16384, 32768)))
+
+
+def _time_batch(keys, offsets, vals, ref_keys, ref_vals, reps: int, stream,
+                host_offsets) -> float:
+    import torch
+    best = float("inf")
+    for _ in range(reps):
+        keys.copy_(ref_keys)
+        if vals is not None:
+            vals.copy_(ref_vals)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        qms.qms_sort_batch(keys, offsets, vals=vals, host_offsets=host_offsets, stream=stream)
+        e1.record(stream)
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1))
+    return best
+
+
+def autotune_batch(keys, offsets, vals=None, host_offsets=None,
+                   candidates: Iterable[Sequence[int]] = CANDIDATES,
+                   reps: int = 2, stream=None) -> dict:
+    """Time every candidate tuning on the batch (keys, offsets[, vals];
+    host_offsets: an optional numpy copy of offsets) and set the fastest.
+    The inputs are left as they were (each trial sorts a copy).
+    Returns {"best": {...}, "trials": [{..., "ms": t}, ...]}."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    work_k = torch.empty_like(keys)
+    work_v = None if vals is None else torch.empty_like(vals)
+    before = qms.qms_get_tuning()
+    trials = []
+    try:
+        with torch.cuda.stream(stream):
+            for ways, ptile, span in candidates:
+                qms.qms_set_tuning(ways, ptile, span)
+                ms = _time_batch(work_k, offsets, work_v, keys, vals, reps, stream, host_offsets)
+                trials.append({"merge_ways": ways, "partition_tile": ptile,
+                               "chunk_span": span, "ms": round(ms, 4)})
+    except Exception:
+        qms.qms_set_tuning(before["merge_ways"], before["partition_tile"], before["chunk_span"])
+        raise
+    best = min(trials, key=lambda t: t["ms"])
+    qms.qms_set_tuning(best["merge_ways"], best["partition_tile"], best["chunk_span"])
+    return {"best": {k: best[k] for k in ("merge_ways", "partition_tile", "chunk_span")},
+            "trials": trials}
+
+
+def reset_tuning() -> None:
+    """Back to the library defaults."""
+    qms.qms_set_tuning(4, 4096, 16384)

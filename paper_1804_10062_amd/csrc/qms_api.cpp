@@ -32,6 +32,15 @@ int hip_error(hipError_t e, const char *where) {
     return set_error(QMS_ERR_HIP, std::string(where) + ": " + hipGetErrorString(e));
 }
 
+// ---- run-time tuning -------------------------------------------------------------------
+static std::mutex g_tuning_mutex;
+static Tuning g_tuning;
+
+Tuning current_tuning() {
+    std::lock_guard<std::mutex> lock(g_tuning_mutex);
+    return g_tuning;
+}
+
 // ---- workspaces ----------------------------------------------------------------------
 static std::mutex g_ws_mutex;
 static std::map<std::pair<int, hipStream_t>, Workspace *> g_ws;
@@ -223,6 +232,31 @@ int qms_release_workspaces(void) {
 }
 
 static_assert(kScheduleWords == QMS_SCHEDULE_WORDS, "schedule record size");
+
+int qms_set_tuning(const qms_tuning *t) {
+    if (!t) return set_error(QMS_ERR_INVALID, "NULL tuning");
+    if (t->merge_ways != 2 && t->merge_ways != 4)
+        return set_error(QMS_ERR_INVALID, "merge_ways must be 2 or 4");
+    const uint32_t pt = t->partition_tile;
+    if (pt < (uint32_t)kPartSub || pt > 16u * kPartSub || (pt & (pt - 1)) != 0)
+        return set_error(QMS_ERR_INVALID, "partition_tile must be a power of two in [4096, 65536]");
+    if (t->chunk_span < (uint32_t)kPartSub || t->chunk_span > (1u << 20))
+        return set_error(QMS_ERR_INVALID, "chunk_span must lie in [4096, 2^20]");
+    std::lock_guard<std::mutex> lock(g_tuning_mutex);
+    g_tuning.merge_ways = t->merge_ways;
+    g_tuning.partition_tile = pt;
+    g_tuning.chunk_span = t->chunk_span;
+    return QMS_OK;
+}
+
+int qms_get_tuning(qms_tuning *t) {
+    if (!t) return set_error(QMS_ERR_INVALID, "NULL tuning");
+    const Tuning c = current_tuning();
+    t->merge_ways = c.merge_ways;
+    t->partition_tile = c.partition_tile;
+    t->chunk_span = c.chunk_span;
+    return QMS_OK;
+}
 
 uint64_t qms_last_schedule(uint64_t *out, uint64_t max_rounds) {
     const auto &sched = last_schedule();

@@ -313,7 +313,7 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_sort(TaskRef<SortSeg> tas
     const uint32_t t0 = t * T;
     if (t0 >= g.m) return;
     const uint32_t len = min(T, g.m - t0);
-    const bool swap = (merge_passes(g.L, PAIRS) & 1u) != 0;
+    const bool swap = (merge_passes(g.L, g.two_way != 0) & 1u) != 0;
     const uint32_t src = g.D + t0, dst = (swap ? g.Bf : g.D) + t0;
     tile_sort_block<O, PAIRS>(g.keys + src, PAIRS ? g.vals + src : nullptr, g.keys + dst,
                               PAIRS ? g.vals + dst : nullptr, len, swap,

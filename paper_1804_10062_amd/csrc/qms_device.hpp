@@ -55,18 +55,19 @@ enum MetaSlot : int {
 
 // Misplaced pairs per swap chunk for a pass with X pairs over a range of s
 // keys: at most kRankChunk (the LDS slots of a workgroup), and small enough
-// that there are about s / (4 kPartSub) chunks, so that sparse misplacement
-// (nearly sorted input) still spreads the range scans over many workgroups.
-constexpr uint64_t kChunkSpan = 4 * kPartSub;  // target positions per chunk
-__host__ __device__ inline uint32_t rank_chunk(uint64_t X, uint64_t s) {
-    const uint64_t target = (s + kChunkSpan - 1) / kChunkSpan;
+// that there are about s / span chunks (span >= kPartSub, a tunable; default
+// kChunkSpan), so that sparse misplacement (nearly sorted input) still
+// spreads the range scans over many workgroups.
+constexpr uint64_t kChunkSpan = 4 * kPartSub;  // default target positions per chunk
+__host__ __device__ inline uint32_t rank_chunk(uint64_t X, uint64_t s, uint64_t span) {
+    const uint64_t target = (s + span - 1) / span;
     uint64_t rc = (X + target - 1) / target;
     if (rc < 1) rc = 1;
     if (rc > (uint64_t)kRankChunk) rc = kRankChunk;
     return (uint32_t)rc;
 }
-__host__ __device__ inline uint64_t chunk_count(uint64_t X, uint64_t s) {
-    const uint32_t rc = rank_chunk(X, s);
+__host__ __device__ inline uint64_t chunk_count(uint64_t X, uint64_t s, uint64_t span) {
+    const uint32_t rc = rank_chunk(X, s, span);
     return (X + rc - 1) / rc;
 }
 
@@ -102,6 +103,8 @@ struct SortSeg {
     uint32_t L;          // merge levels
     uint32_t split_off;  // first entry in the merge split array
     uint32_t w0;         // base-case tile (run width of level 0)
+    uint32_t two_way;    // 1: 2-way passes only (key/payload sorts, or by tuning)
+    uint32_t pad;
 };
 
 // Merge passes of a Mergesort task with L binary levels (runs of w0 << l
@@ -111,17 +114,13 @@ struct SortSeg {
 // `level` has index pass_index(); passes alternate between the two regions,
 // and the base case writes into the buffer exactly when the pass count is
 // odd, so that the last pass ends in the data region.
-// (QMS_MERGE_WAYS = 2 builds the binary schedule for every task, for
-// comparisons.)
-#ifndef QMS_MERGE_WAYS
-#define QMS_MERGE_WAYS 4
-#endif
-__host__ __device__ inline bool two_way_only(bool pairs) { return pairs || QMS_MERGE_WAYS == 2; }
-__host__ __device__ inline uint32_t merge_passes(uint32_t L, bool pairs) {
-    return two_way_only(pairs) ? L : (L + 1) / 2;
+// `two` selects the 2-way schedule (key/payload tasks always; key-only
+// tasks by tuning).
+__host__ __device__ inline uint32_t merge_passes(uint32_t L, bool two) {
+    return two ? L : (L + 1) / 2;
 }
-__host__ __device__ inline uint32_t pass_index(uint32_t L, uint32_t level, bool pairs) {
-    return two_way_only(pairs) ? level : ((L & 1u) ? (level + 1) / 2 : level / 2);
+__host__ __device__ inline uint32_t pass_index(uint32_t L, uint32_t level, bool two) {
+    return two ? level : ((L & 1u) ? (level + 1) / 2 : level / 2);
 }
 
 template <class T>

@@ -115,7 +115,7 @@ const std::vector<std::array<uint64_t, kScheduleWords>> &last_schedule() { retur
 
 // Sort a group of segments (count <= kCapSegs, total keys < 2^32).
 static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
-                      hipStream_t st, bool log) {
+                      hipStream_t st, bool log, const Tuning &tune) {
     const double w = pairs ? 2.0 : 1.0;
     const uint32_t T0 = pairs ? kBaseTilePairs : kBaseTileKeys;  // base-case tile
     std::vector<uint32_t> active, next;
@@ -140,7 +140,7 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
             // ---- partition: count + scan A, then read three counters back ----
             uint64_t sum_s = 0;
             for (uint32_t i : active) sum_s += segs[i].hi - segs[i].lo;
-            uint32_t TP = kPartSub;
+            uint32_t TP = tune.partition_tile;
             for (;;) {
                 uint64_t tot = 0;
                 for (uint32_t i : active) tot += (segs[i].hi - segs[i].lo + TP - 1) / TP;
@@ -181,6 +181,7 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
             L.tasks.tab = ar.dev<PartSeg>(o_tab);
             L.tasks.pre = ar.dev<uint32_t>(o_pre);
             L.TP = TP;
+            L.chunk_span = tune.chunk_span;
             L.scan_threads = max_nt > 4 * kBlock ? kScanThreads : kBlock;
             L.keys_total = (double)sum_s;
             L.ws = &ws;
@@ -209,7 +210,7 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
                 // then the "< p" side is not empty
                 if ((c_eq == 0 && c_lt == 0) || c_lt + c_eq > s)
                     return set_error(QMS_ERR_HIP, "partition returned inconsistent counts");
-                const uint64_t nch = chunk_count(X, s);
+                const uint64_t nch = chunk_count(X, s, tune.chunk_span);
                 ca[a + 1] = ca[a] + (uint32_t)nch;
                 wa[a + 1] = wa[a] + (uint32_t)(nch > 1 ? 2 * (nch - 1) : 0);
                 if (X > 0) swap_bytes += 4.0 * (double)s + 2.0 * 4.0 * w * (double)X;
@@ -219,7 +220,7 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
                 uint64_t nb = 0;
                 if (xb > 0) {
                     const uint64_t full = (xb + kRankChunk - 1) / kRankChunk;
-                    const uint64_t target = (s + kChunkSpan - 1) / kChunkSpan;
+                    const uint64_t target = (s + tune.chunk_span - 1) / tune.chunk_span;
                     nb = std::min(xb, std::max(full, target));
                     any_b = true;
                 }
@@ -310,7 +311,8 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
         // at l belong to the tasks with L > l and L = l (mod 2), the 2-way
         // first passes (l = 0) to the odd ones; for key/payload tasks every
         // task with L > l runs a 2-way pass at l
-        const bool by_parity = !two_way_only(pairs);
+        const bool two = pairs || tune.merge_ways == 2;
+        const bool by_parity = !two;
         std::stable_sort(tasks.begin(), tasks.end(), [&](const SortSeg &x, const SortSeg &y) {
             if (by_parity && (x.L & 1u) != (y.L & 1u)) return (x.L & 1u) < (y.L & 1u);
             return x.L > y.L;
@@ -328,10 +330,11 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
         for (uint32_t a = 0; a < T; ++a) {
             SortSeg t = tasks[a];
             t.split_off = pmerge[a];
+            t.two_way = two ? 1u : 0u;
             stab[a] = t;
             ptile[a + 1] = ptile[a] + (t.m + T0 - 1) / T0;
             pmerge[a + 1] = pmerge[a] + (t.m + kMergeTile - 1) / kMergeTile;
-            base_bytes += ((merge_passes(t.L, pairs) & 1) ? 16.0 : 8.0) * w * (double)t.m;
+            base_bytes += ((merge_passes(t.L, two) & 1) ? 16.0 : 8.0) * w * (double)t.m;
             maxL = std::max(maxL, t.L);
             if (!by_parity || (t.L & 1u) == 0) E = a + 1;
         }
@@ -359,7 +362,7 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
             Rl.base = pmerge[a0];
             double mb = 0;
             for (uint32_t a = a0; a < a1; ++a) mb += 16.0 * w * (double)stab[a].m;
-            const uint32_t pass = pass_index(stab[a0].L, l, pairs);
+            const uint32_t pass = pass_index(stab[a0].L, l, two);
             return launch_merge_pass(dt, pairs, Rl, l, pass, four, pmerge[a1] - pmerge[a0], mb, ws,
                                      st);
         };
@@ -405,11 +408,12 @@ int mom_pivot_of(int dt, const uint32_t *keys, uint64_t n, Workspace &ws, hipStr
 int sort_segments(int dt, bool pairs, const HostSeg *segs, size_t count, Workspace &ws,
                   hipStream_t st, bool log) {
     if (log) g_schedule.clear();
+    const Tuning tune = current_tuning();
     std::vector<Seg> group;
     uint64_t group_keys = 0;
     auto flush = [&]() -> int {
         if (group.empty()) return QMS_OK;
-        int rc = sort_group(dt, pairs, group, ws, st, log);
+        int rc = sort_group(dt, pairs, group, ws, st, log, tune);
         group.clear();
         group_keys = 0;
         return rc;

@@ -15,6 +15,15 @@ namespace qms {
 // Words per round of the schedule log (QMS_SCHEDULE_WORDS in qms.h).
 constexpr int kScheduleWords = 6;
 
+// Run-time tunables (qms_set_tuning): merge arity of key-only sorts, the
+// first partition counting tile, the target positions per exchange chunk.
+struct Tuning {
+    uint32_t merge_ways = 4;
+    uint32_t partition_tile = kPartSub;
+    uint32_t chunk_span = (uint32_t)kChunkSpan;
+};
+Tuning current_tuning();
+
 int set_error(int code, const std::string &msg);
 int hip_error(hipError_t e, const char *where);
 int check_device_ptr(const void *p, const char *what, int *device);

@@ -65,6 +65,7 @@ struct PartitionLaunch {
     TaskRef<PartSeg> tasks;    // table + work prefix of the phase
     uint32_t work;             // work items (workgroups, or waves for splits)
     uint32_t TP;               // partition tile
+    uint32_t chunk_span;       // target positions per exchange chunk
     uint32_t scan_threads;     // block size of the scans
     double keys_total;         // keys in all ranges (byte figures)
     double bytes;              // algorithmic bytes of the launch (swap A)

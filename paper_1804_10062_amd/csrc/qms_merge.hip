@@ -58,12 +58,11 @@ __device__ __forceinline__ MergeTileGeom merge_geom(uint64_t m, uint64_t W, uint
 // Regions of a merge pass: the base case leaves the runs in R0 (the buffer
 // when the pass count is odd, the data region otherwise); pass p reads
 // R(p mod 2) and writes the other region, so the last pass ends in D.
-template <bool PAIRS>
 __device__ __forceinline__ void level_regions(const SortSeg &g, uint32_t level, uint32_t *src,
                                               uint32_t *dst) {
-    const bool odd = (merge_passes(g.L, PAIRS) & 1u) != 0;
+    const bool odd = (merge_passes(g.L, g.two_way != 0) & 1u) != 0;
     const uint32_t r0 = odd ? g.Bf : g.D, r1 = odd ? g.D : g.Bf;
-    const uint32_t p = pass_index(g.L, level, PAIRS);
+    const uint32_t p = pass_index(g.L, level, g.two_way != 0);
     *src = (p & 1u) ? r1 : r0;
     *dst = (p & 1u) ? r0 : r1;
 }
@@ -168,7 +167,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_split(TaskRef<SortSeg> tasks, 
     uint32_t tile = 0, a = 0;
     const SortSeg g = task_of(tasks, active ? w : total - 1, &tile, &a);
     uint32_t src, dst;
-    level_regions<PAIRS>(g, level, &src, &dst);
+    level_regions(g, level, &src, &dst);
     const uint64_t W = (uint64_t)g.w0 << level;
     const MergeTileGeom geo = merge_geom(g.m, W, tile);
     const uint32_t *A = g.keys + src + geo.pb;
@@ -356,7 +355,7 @@ __attribute__((amdgpu_waves_per_eu(QMS_MERGE4_WPE, QMS_MERGE4_WPE))) void k_merg
     const SortSeg g = task_of(tasks, blockIdx.x, &tile, &a);
     if (tile * (uint64_t)S >= g.m) return;
     uint32_t src, dst;
-    level_regions<false>(g, level, &src, &dst);
+    level_regions(g, level, &src, &dst);
     const uint64_t W = (uint64_t)g.w0 << level;
     const Merge4Geom geo = merge4_geom(g.m, W, tile);
     // the tile's start and end vectors
@@ -551,7 +550,7 @@ __global__ __launch_bounds__(kBlock) void k_merge(TaskRef<SortSeg> tasks, uint32
     const SortSeg g = task_of(tasks, blockIdx.x, &tile, &a);
     if (tile * (uint64_t)kMergeTile >= g.m) return;
     uint32_t src, dst;
-    level_regions<PAIRS>(g, level, &src, &dst);
+    level_regions(g, level, &src, &dst);
     merge_block<O, PAIRS>(g.keys + src, PAIRS ? g.vals + src : nullptr, g.keys + dst,
                           PAIRS ? g.vals + dst : nullptr, g.m, (uint64_t)g.w0 << level,
                           tile, splits + g.split_off, samples_out + g.split_off);

@@ -235,6 +235,7 @@ __device__ __forceinline__ void mark_chunk_tiles(uint32_t nt, uint32_t TP, uint3
 // res[4 a + 0..2] = (#<p, #==p, pass-A pairs) for the host.
 template <class O, int NTH>
 __global__ __launch_bounds__(NTH) void k_part_scan_a(TaskRef<PartSeg> tasks, uint32_t TP,
+                                                     uint32_t span,
                                                      uint32_t *cnt_lt_all,
                                                      const uint32_t *cnt_eq_all,
                                                      uint32_t *preL_all, uint32_t *preR_all,
@@ -309,8 +310,8 @@ __global__ __launch_bounds__(NTH) void k_part_scan_a(TaskRef<PartSeg> tasks, uin
     __syncthreads();  // P written by other threads of the block
     const uint32_t Ptb = ldg(P + tb);
     const uint32_t X = (uint32_t)c_lt - Ptb - lt_part;
-    const uint32_t rc = rank_chunk(X, s);
-    const uint32_t nch = (uint32_t)chunk_count(X, s);
+    const uint32_t rc = rank_chunk(X, s, span);
+    const uint32_t nch = (uint32_t)chunk_count(X, s, span);
     uint32_t *spL = spL_all + g.chunk_off, *spR = spR_all + g.chunk_off;
     // pass 2
     auto prefix_at = [&](uint32_t t, uint32_t Pt, uint32_t *l, uint32_t *r) {
@@ -377,6 +378,7 @@ __global__ __launch_bounds__(NTH) void k_part_scan_a(TaskRef<PartSeg> tasks, uin
 // possible pass-B pairs return at once.
 template <class O, int NTH>
 __global__ __launch_bounds__(NTH) void k_part_scan_b(TaskRef<PartSeg> tasks, uint32_t TP,
+                                                     uint32_t span,
                                                      const uint32_t *cnt_eq_all,
                                                      const uint32_t *eqmv_all,
                                                      uint32_t *preL_all, uint32_t *preR_all,
@@ -427,8 +429,8 @@ __global__ __launch_bounds__(NTH) void k_part_scan_b(TaskRef<PartSeg> tasks, uin
         *r = le - leA;
     };
     const uint32_t X = scan_misplaced<NTH>(nt, ld, mis, preL, preR, stage, tmp);
-    const uint32_t rc = rank_chunk(X, s);
-    const uint32_t nch = (uint32_t)chunk_count(X, s);
+    const uint32_t rc = rank_chunk(X, s, span);
+    const uint32_t nch = (uint32_t)chunk_count(X, s, span);
     uint32_t *spL = spL_all + g.chunk_off, *spR = spR_all + g.chunk_off;
     mark_chunk_tiles<NTH>(nt, TP, rc, nch, preL, preR, spL, spR);
     if (threadIdx.x == 0) {
@@ -736,11 +738,13 @@ static hipError_t partition_t(const PartitionLaunch &L, hipStream_t st) {
             ProfScope prof(st, K_PART_SCAN, 0.0);
             if (L.scan_threads == kScanThreads)
                 hipLaunchKernelGGL((k_part_scan_a<O, kScanThreads>), dim3(L.tasks.A),
-                                   dim3(kScanThreads), 0, st, L.tasks, L.TP, ws.cnt_lt, ws.cnt_eq,
+                                   dim3(kScanThreads), 0, st, L.tasks, L.TP, L.chunk_span,
+                                   ws.cnt_lt, ws.cnt_eq,
                                    ws.preL, ws.preR, ws.eqmv, ws.spL, ws.spR, ws.meta, ws.res);
             else
                 hipLaunchKernelGGL((k_part_scan_a<O, kBlock>), dim3(L.tasks.A), dim3(kBlock), 0,
-                                   st, L.tasks, L.TP, ws.cnt_lt, ws.cnt_eq, ws.preL, ws.preR,
+                                   st, L.tasks, L.TP, L.chunk_span, ws.cnt_lt, ws.cnt_eq,
+                                   ws.preL, ws.preR,
                                    ws.eqmv, ws.spL, ws.spR, ws.meta, ws.res);
         }
         break;
@@ -770,11 +774,13 @@ static hipError_t partition_t(const PartitionLaunch &L, hipStream_t st) {
         ProfScope prof(st, K_PART_SCAN, 0.0);
         if (L.scan_threads == kScanThreads)
             hipLaunchKernelGGL((k_part_scan_b<O, kScanThreads>), dim3(L.tasks.A),
-                               dim3(kScanThreads), 0, st, L.tasks, L.TP, ws.cnt_eq, ws.eqmv,
+                               dim3(kScanThreads), 0, st, L.tasks, L.TP, L.chunk_span,
+                               ws.cnt_eq, ws.eqmv,
                                ws.preL, ws.preR, ws.spL, ws.spR, ws.meta);
         else
             hipLaunchKernelGGL((k_part_scan_b<O, kBlock>), dim3(L.tasks.A), dim3(kBlock), 0, st,
-                               L.tasks, L.TP, ws.cnt_eq, ws.eqmv, ws.preL, ws.preR, ws.spL,
+                               L.tasks, L.TP, L.chunk_span, ws.cnt_eq, ws.eqmv, ws.preL,
+                               ws.preR, ws.spL,
                                ws.spR, ws.meta);
         break;
     }

@@ -35,6 +35,7 @@ EXPORTS = (
     "qms_server_get_stats", "qms_server_destroy",
     "qms_last_error", "qms_release_workspaces", "qms_last_schedule",
     "qms_get_tiles", "qms_profile_begin", "qms_profile_end", "qms_mom_pivot",
+    "qms_set_tuning", "qms_get_tuning",
 )
 
 QMS_SCHEDULE_WORDS = 6
@@ -55,6 +56,14 @@ class ServerStats(ctypes.Structure):
     _fields_ = [("completed", ctypes.c_uint64), ("completed_keys", ctypes.c_uint64),
                 ("peak_admitted_bytes", ctypes.c_uint64),
                 ("waited_for_budget", ctypes.c_uint64), ("batches", ctypes.c_uint64)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("merge_ways", ctypes.c_uint32), ("partition_tile", ctypes.c_uint32),
+                ("chunk_span", ctypes.c_uint32)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class KernelStat(ctypes.Structure):
@@ -108,6 +117,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.qms_profile_end.restype = i32
     lib.qms_mom_pivot.argtypes = [vp, u64, i32, u32p, vp]
     lib.qms_mom_pivot.restype = i32
+    lib.qms_set_tuning.argtypes = [ctypes.POINTER(Tuning)]
+    lib.qms_set_tuning.restype = i32
+    lib.qms_get_tuning.argtypes = [ctypes.POINTER(Tuning)]
+    lib.qms_get_tuning.restype = i32
     _lib = lib
     return lib
 
@@ -212,6 +225,17 @@ def qms_mom_pivot(keys, stream=None) -> int:
                                         ctypes.byref(out), _stream_handle(stream)),
            "qms_mom_pivot")
     return out.value
+
+
+def qms_set_tuning(merge_ways: int, partition_tile: int, chunk_span: int) -> None:
+    t = Tuning(merge_ways, partition_tile, chunk_span)
+    _check(load_library().qms_set_tuning(ctypes.byref(t)), "qms_set_tuning")
+
+
+def qms_get_tuning() -> dict:
+    t = Tuning()
+    _check(load_library().qms_get_tuning(ctypes.byref(t)), "qms_get_tuning")
+    return t.as_dict()
 
 
 def qms_get_tiles():
