@@ -24,6 +24,15 @@
 #include "qms_internal.hpp"
 #include "qms_prof.hpp"
 
+// Cross-lane exchanges for lane masks 4 and 16 by ds_swizzle (1) or by
+// VALU row moves / permlane swaps (0); build-time switches for measurements.
+#ifndef QMS_SWIZZLE_4
+#define QMS_SWIZZLE_4 1
+#endif
+#ifndef QMS_SWIZZLE_16
+#define QMS_SWIZZLE_16 1
+#endif
+
 namespace qms {
 
 template <bool PAIRS>
@@ -87,6 +96,11 @@ __device__ __forceinline__ uint32_t dpp_partner(uint32_t v, uint32_t lane) {
         return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);
     } else if constexpr (LM == 8) {
         return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x128, 0xF, 0xF, false);
+    } else if constexpr (LM == 4 && QMS_SWIZZLE_4) {
+        // ds_swizzle in bit mode, xor mask 4 (one LDS-pipe op, no memory)
+        return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x101F);
+    } else if constexpr (LM == 16) {
+        return (uint32_t)__builtin_amdgcn_ds_swizzle((int)v, 0x401F);  // xor mask 16
     } else {
         static_assert(LM == 4, "lane mask");
         const uint32_t from_below = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x124, 0xF, 0xF, false);
@@ -97,7 +111,7 @@ __device__ __forceinline__ uint32_t dpp_partner(uint32_t v, uint32_t lane) {
 
 template <int LM, int ITEMS>
 __device__ __forceinline__ void lane_step_u32(uint32_t (&r)[ITEMS], uint32_t lane) {
-    if constexpr (LM <= 8) {
+    if constexpr (LM <= 8 || (LM == 16 && QMS_SWIZZLE_16)) {
         const uint32_t bound = (lane & LM) ? ~0u : 0u;
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) r[i] = median3(r[i], dpp_partner<LM>(r[i], lane), bound);
