@@ -26,7 +26,8 @@ One JSON line goes to stdout with, besides the contract fields:
   cpu_baseline  the CPU oracle (single thread) on a bounded sample of the
                 same workload (the first 2^26 keys), in Gkeys/s;
   kernels       per-kernel-class launches, time and achieved GB/s;
-  distributions Gkeys/s of the three inputs;
+  distributions Gkeys/s of the three inputs, and of 2^26 key/payload pairs
+                (Zipf(1.1) keys over [0, 2^10), payload = index);
   batched       20,000 float32 arrays in one qms_sort_batch call against one
                 qms_sort call per array (a 1-in-10 sample of the arrays);
   serving       open-loop Poisson request streams at 2k/10k/50k requests/s
@@ -340,6 +341,27 @@ def main():
             dists[name] = round(N_KEYS / (sec2 / args.dist_steps) / 1e9, 3)
             dists[name + "_rounds"] = len(qms.qms_last_schedule())
             del cps, s2
+        # key/payload pairs: 2^26 Zipf(1.1) keys over [0, 2^10), payload = index
+        print("[bench] pairs", file=sys.stderr, flush=True)
+        npairs = 1 << 26
+        hk = inputs.zipf_u32(npairs, seed=4)
+        k0 = torch.from_numpy(hk.view(np.int32)).to(dev)
+        v0 = torch.arange(npairs, dtype=torch.int32, device=dev)
+        ks = [k0.clone() for _ in range(args.dist_steps + 1)]
+        vs = [v0.clone() for _ in range(args.dist_steps + 1)]
+        torch.cuda.synchronize()
+        qms.qms_sort_pairs(ks[0], vs[0])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for kt, vt in zip(ks[1:], vs[1:]):
+            qms.qms_sort_pairs(kt, vt)
+        torch.cuda.synchronize()
+        sec2 = time.perf_counter() - t0
+        if not is_sorted(ks[-1]):
+            print("bench.py: pairs output not sorted", file=sys.stderr)
+            sys.exit(1)
+        dists["pairs_zipf_2e26"] = round(npairs / (sec2 / args.dist_steps) / 1e9, 3)
+        del ks, vs, k0, v0
 
     batched = None
     if not args.no_batched:

@@ -72,9 +72,8 @@ __device__ __forceinline__ uint32_t keep_side(uint32_t x, uint32_t y, bool, uint
     return median3(x, y, bound);
 }
 __device__ __forceinline__ uint64_t keep_side(uint64_t x, uint64_t y, bool keep_min, uint64_t) {
-    const uint64_t mn = x < y ? x : y;
-    const uint64_t mx = x < y ? y : x;
-    return keep_min ? mn : mx;
+    // x stays when it is on the kept side of y (ties keep either: equal values)
+    return (x < y) == keep_min ? x : y;
 }
 
 // Cross-lane compare-exchange steps of 32-bit elements without the LDS pipe
@@ -128,6 +127,33 @@ __device__ __forceinline__ void lane_step_u32(uint32_t (&r)[ITEMS], uint32_t lan
             r[i] = u[0];
             r[i + 1] = u[1];
         }
+    }
+}
+
+// The partner value of a 32-bit register at lane mask LM, for any mask: DPP
+// and swizzles as above, and for mask 32 one permlane32 swap of the register
+// with itself (it returns both halves broadcast: the lower half takes the
+// copy of the upper half and vice versa).
+template <int LM>
+__device__ __forceinline__ uint32_t lane_partner(uint32_t v, uint32_t lane) {
+    if constexpr (LM == 32) {
+        const auto t = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+        return (lane & 32) ? (uint32_t)t[0] : (uint32_t)t[1];
+    } else {
+        return dpp_partner<LM>(v, lane);
+    }
+}
+
+// Key/payload elements (64 bits: key, then index): both halves travel to the
+// partner lane, and one 64-bit comparison picks the kept element.
+template <int LM, int ITEMS>
+__device__ __forceinline__ void lane_step_u64(uint64_t (&r)[ITEMS], uint32_t lane) {
+    const bool keep_min = (lane & LM) == 0;
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        const uint32_t lo = lane_partner<LM>((uint32_t)r[i], lane);
+        const uint32_t hi = lane_partner<LM>((uint32_t)(r[i] >> 32), lane);
+        r[i] = keep_side(r[i], ((uint64_t)hi << 32) | lo, keep_min, 0);
     }
 }
 
@@ -267,6 +293,30 @@ __device__ __forceinline__ void tile_sort_block(uint32_t *sk, uint32_t *sv, uint
                 [[fallthrough]];
             case 1:
                 lane_step_u32<1>(r, lane);
+                [[fallthrough]];
+            default:
+                break;
+            }
+            j = ITEMS / 2;
+        } else {
+            switch (j / ITEMS) {
+            case 32:
+                lane_step_u64<32>(r, lane);
+                [[fallthrough]];
+            case 16:
+                lane_step_u64<16>(r, lane);
+                [[fallthrough]];
+            case 8:
+                lane_step_u64<8>(r, lane);
+                [[fallthrough]];
+            case 4:
+                lane_step_u64<4>(r, lane);
+                [[fallthrough]];
+            case 2:
+                lane_step_u64<2>(r, lane);
+                [[fallthrough]];
+            case 1:
+                lane_step_u64<1>(r, lane);
                 [[fallthrough]];
             default:
                 break;

@@ -28,7 +28,10 @@ constexpr int kMergeTile = kBlock * kMergePerThread;   // outputs per workgroup
 constexpr uint32_t kSplitLanes = QMS_SPLIT_LANES;      // lanes per merge-path split
 constexpr int kPartSub = 4096;         // elements a workgroup classifies per step
 constexpr int kPartItems = kPartSub / kBlock;          // 16
-constexpr int kRankChunk = 4096;       // misplaced pairs exchanged per workgroup
+#ifndef QMS_RANK_CHUNK
+#define QMS_RANK_CHUNK 4096
+#endif
+constexpr int kRankChunk = QMS_RANK_CHUNK;  // misplaced pairs exchanged per workgroup
 constexpr uint32_t kMaxTiles = 65536;  // fixed bound on partition tiles
 constexpr int kScanThreads = 1024;     // single-workgroup scan kernels
 constexpr uint64_t kEqBlockMin = 64;   // pivot-equal keys that always get their own block
