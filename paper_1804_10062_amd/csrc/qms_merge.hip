@@ -272,7 +272,13 @@ __global__ __launch_bounds__(kBlock) void k_merge4_ends(TaskRef<SortSeg> tasks, 
 }
 
 // Outputs [d, d + N) of the stable merge of X = sk[x0, x0 + nx) and
-// Y = sk[y0, y0 + ny) into out[] (X first on ties); d < nx + ny.
+// Y = sk[y0, y0 + ny) into out[] (X first on ties), d < nx + ny.  The word
+// after Y, sk[y0 + ny], holds the largest key 0xffffffff: once Y is used up
+// every X element compares <= it, so a step tests only for the end of X
+// (X[nx] is read, never taken).  Outputs past nx + ny are garbage (the
+// caller stores none of them) and read at most N - 1 words past the
+// sentinel.  A step is two LDS reads at addresses one add from i, a compare
+// and a select.
 template <int N>
 __device__ __forceinline__ void merge_lds(const uint32_t *sk, uint32_t x0, uint32_t nx,
                                           uint32_t y0, uint32_t ny, uint32_t d,
@@ -284,33 +290,39 @@ __device__ __forceinline__ void merge_lds(const uint32_t *sk, uint32_t x0, uint3
         if (X[mid] <= Y[d - 1 - mid]) lo = mid + 1;
         else hi = mid;
     }
-    // branch-free: reads are clamped into the arrays (a value read past an
-    // end is never taken; an empty array reads the word at its start, which
-    // the caller's LDS array holds)
-    const uint32_t xl = nx ? nx - 1 : 0, yl = ny ? ny - 1 : 0;
-    uint32_t i = lo, j = d - lo;
-    uint32_t kx = X[min(i, xl)], ky = Y[min(j, yl)];
+    uint32_t i = lo;
+    const uint32_t *Yd = Y + d;  // Y[j] for j = d + q - i
 #pragma unroll
     for (int q = 0; q < N; ++q) {
-        const bool takeX = j >= ny || (i < nx && kx <= ky);
+        const uint32_t kx = X[i], ky = Yd[q - (int)i];
+        const bool takeX = i < nx && kx <= ky;
         out[q] = takeX ? kx : ky;
         i += takeX;
-        j += !takeX;
-        const uint32_t nkx = X[min(i, xl)], nky = Y[min(j, yl)];
-        kx = takeX ? nkx : kx;
-        ky = takeX ? ky : nky;
     }
 }
 
-// The two pair merges of a 4-way tile in place: A with B over [0, c2) by the
-// first half of the threads, C with D over [c2, cnt) by the second half, N
-// outputs per thread.
+// LDS layout of a 4-way tile: A | B | max | C | D | max, i.e. tile element el
+// at sk[el + (el >= c2)], with the sentinels merge_lds needs after B (at c2)
+// and after D (at cnt + 1); kMerge4Slack words past them absorb the reads of
+// threads whose outputs run past the end.
+//
+// Outputs per thread of the pair merges and of the final merge: odd counts
+// (one more than the power of two that covers the tile) put the lanes'
+// diagonals on distinct LDS banks; even ones stack them on a few.
+#ifndef QMS_MERGE_ODD
+#define QMS_MERGE_ODD 1
+#endif
+constexpr int kMergeOdd = QMS_MERGE_ODD;
+constexpr int kMerge4Slack = 16 + kMergeOdd;
+
+// The two pair merges of a 4-way tile in place: A with B by the first half of
+// the threads, C with D by the second half, N outputs per thread.
 template <int N, int NT>
 __device__ __forceinline__ void merge4_halves(uint32_t *sk, uint32_t c1, uint32_t c2, uint32_t c3,
                                               uint32_t cnt, uint32_t tid) {
     const bool cd = tid >= NT / 2;
     const uint32_t d = (cd ? tid - NT / 2 : tid) * N;
-    const uint32_t base = cd ? c2 : 0, nx = cd ? c3 - c2 : c1, n = cd ? cnt - c2 : c2;
+    const uint32_t base = cd ? c2 + 1 : 0, nx = cd ? c3 - c2 : c1, n = cd ? cnt - c2 : c2;
     uint32_t o[N];
     if (d < n) merge_lds<N>(sk, base, nx, base + nx, n - nx, d, o);
     __syncthreads();
@@ -319,13 +331,14 @@ __device__ __forceinline__ void merge4_halves(uint32_t *sk, uint32_t c1, uint32_
         if (d + q < n) sk[base + d + q] = o[q];
     __syncthreads();
 }
-// The two halves [0, c2) and [c2, cnt) merged in place, N outputs per thread.
+// The merged pairs sk[0, c2) and sk[c2 + 1, cnt + 1) merged into sk[0, cnt),
+// N outputs per thread.
 template <int N>
 __device__ __forceinline__ void merge4_final(uint32_t *sk, uint32_t c2, uint32_t cnt,
                                              uint32_t tid) {
     uint32_t o[N];
     const uint32_t d = tid * N;
-    if (d < cnt) merge_lds<N>(sk, 0, c2, c2, cnt - c2, d, o);
+    if (d < cnt) merge_lds<N>(sk, 0, c2, c2 + 1, cnt - c2, d, o);
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < N; ++q)
@@ -350,7 +363,7 @@ __attribute__((amdgpu_waves_per_eu(QMS_MERGE4_WPE, QMS_MERGE4_WPE))) void k_merg
     uint32_t *samples_out) {
     constexpr uint32_t S = kMergeTile;
     constexpr int NT = kMerge4Threads;
-    __shared__ uint32_t sk[2 * S + 1];  // + 1: see merge_lds
+    __shared__ uint32_t sk[2 * S + 2 + kMerge4Slack];
     uint32_t tile, a;
     const SortSeg g = task_of(tasks, blockIdx.x, &tile, &a);
     if (tile * (uint64_t)S >= g.m) return;
@@ -406,22 +419,26 @@ __attribute__((amdgpu_waves_per_eu(QMS_MERGE4_WPE, QMS_MERGE4_WPE))) void k_merg
         for (int q = 0; q < Q; ++q) {
             const uint32_t el = (uint32_t)q * NT + tid;
             if (el < cnt) {
-                sk[el] = O::ord(v[q]);
+                sk[el + (el >= c2)] = O::ord(v[q]);
                 stg(S_ + cell(el), old[q]);
             }
+        }
+        if (tid == 0) {
+            sk[c2] = 0xffffffffu;
+            sk[cnt + 1] = 0xffffffffu;
         }
     }
     __syncthreads();
     // the merges, with as many outputs per thread as the tile needs (a
     // typical tile holds kMergeTile elements, half the maximum)
     if (c2 <= S / 2 && cnt - c2 <= S / 2)
-        merge4_halves<2 * S / NT / 2, NT>(sk, c1, c2, c3, cnt, tid);
+        merge4_halves<2 * S / NT / 2 + kMergeOdd, NT>(sk, c1, c2, c3, cnt, tid);
     else
-        merge4_halves<2 * S / NT, NT>(sk, c1, c2, c3, cnt, tid);
+        merge4_halves<2 * S / NT + kMergeOdd, NT>(sk, c1, c2, c3, cnt, tid);
     if (cnt <= S)
-        merge4_final<S / NT>(sk, c2, cnt, tid);
+        merge4_final<S / NT + kMergeOdd>(sk, c2, cnt, tid);
     else
-        merge4_final<2 * S / NT>(sk, c2, cnt, tid);
+        merge4_final<2 * S / NT + kMergeOdd>(sk, c2, cnt, tid);
     // samples of the output runs: every kMergeTile-th position of the group
     {
         const uint32_t first = (uint32_t)((S - ps % S) % S);
@@ -441,8 +458,10 @@ __device__ __forceinline__ void merge_block(uint32_t *S, uint32_t *SV, uint32_t 
                                             uint32_t *DV, uint64_t m, uint64_t W,
                                             uint64_t tile, const uint32_t *splits,
                                             uint32_t *samples_out) {
-    __shared__ uint32_t sk[kMergeTile];
-    __shared__ uint32_t sv[PAIRS ? kMergeTile : 1];
+    // padded tiles (index i at lpad(i)): the merge reads at lane strides of
+    // kMergePerThread words
+    __shared__ uint32_t sk[lds_words(kMergeTile)];
+    __shared__ uint32_t sv[PAIRS ? lds_words(kMergeTile) : 1];
     const uint32_t tid = threadIdx.x;
 
     const MergeTileGeom g = merge_geom(m, W, tile);
@@ -481,8 +500,8 @@ __device__ __forceinline__ void merge_block(uint32_t *S, uint32_t *SV, uint32_t 
     for (int q = 0; q < kMergePerThread; ++q) {
         const uint32_t e = q * kBlock + tid;
         if (e < cnt) {
-            sk[e] = O::ord(nk[q]);
-            if constexpr (PAIRS) sv[e] = nv[q];
+            sk[lpad(e)] = O::ord(nk[q]);
+            if constexpr (PAIRS) sv[lpad(e)] = nv[q];
         }
     }
     __syncthreads();
@@ -496,22 +515,22 @@ __device__ __forceinline__ void merge_block(uint32_t *S, uint32_t *SV, uint32_t 
         uint32_t hi = diag < na ? diag : na;
         while (lo < hi) {
             const uint32_t mid = (lo + hi) >> 1;
-            if (sk[mid] <= sk[na + diag - 1 - mid]) lo = mid + 1;
+            if (sk[lpad(mid)] <= sk[lpad(na + diag - 1 - mid)]) lo = mid + 1;
             else hi = mid;
         }
         // branch-free: reads are clamped into the runs (a value read past
         // an end is never taken; cnt >= 1 so one of the runs is not empty)
         const uint32_t al = na ? na - 1 : 0, bl = nb ? na + nb - 1 : al;
         uint32_t ia = lo, ib = diag - lo;
-        uint32_t ka = sk[min(ia, al)], kb = sk[min(na + ib, bl)];
+        uint32_t ka = sk[lpad(min(ia, al))], kb = sk[lpad(min(na + ib, bl))];
 #pragma unroll
         for (int q = 0; q < kMergePerThread; ++q) {
             const bool takeA = ib >= nb || (ia < na && ka <= kb);
             ok[q] = takeA ? ka : kb;
-            if constexpr (PAIRS) ov[q] = sv[takeA ? min(ia, al) : min(na + ib, bl)];
+            if constexpr (PAIRS) ov[q] = sv[lpad(takeA ? min(ia, al) : min(na + ib, bl))];
             ia += takeA;
             ib += !takeA;
-            const uint32_t nka = sk[min(ia, al)], nkb = sk[min(na + ib, bl)];
+            const uint32_t nka = sk[lpad(min(ia, al))], nkb = sk[lpad(min(na + ib, bl))];
             ka = takeA ? nka : ka;
             kb = takeA ? kb : nkb;
         }
@@ -521,20 +540,20 @@ __device__ __forceinline__ void merge_block(uint32_t *S, uint32_t *SV, uint32_t 
 #pragma unroll
         for (int q = 0; q < kMergePerThread; ++q) {
             if (diag + q < cnt) {
-                sk[diag + q] = ok[q];
-                if constexpr (PAIRS) sv[diag + q] = ov[q];
+                sk[lpad(diag + q)] = ok[q];
+                if constexpr (PAIRS) sv[lpad(diag + q)] = ov[q];
             }
         }
     }
     __syncthreads();
     // the tile's first output is the sample the next level's split search uses
-    if (tid == 0) stg(samples_out + tile, sk[0]);
+    if (tid == 0) stg(samples_out + tile, sk[lpad(0)]);
 #pragma unroll
     for (int q = 0; q < kMergePerThread; ++q) {
         const uint32_t e = q * kBlock + tid;
         if (e < cnt) {
-            stg(D + pb + d0 + e, O::unord(sk[e]));
-            if constexpr (PAIRS) stg(DV + pb + d0 + e, sv[e]);
+            stg(D + pb + d0 + e, O::unord(sk[lpad(e)]));
+            if constexpr (PAIRS) stg(DV + pb + d0 + e, sv[lpad(e)]);
             const uint64_t pos = e < na ? pb + i0 + e : pb + W + j0 + (e - na);
             stg(S + pos, oldk[q]);
             if constexpr (PAIRS) stg(SV + pos, oldv[q]);
