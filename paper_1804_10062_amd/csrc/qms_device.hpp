@@ -242,13 +242,6 @@ __device__ __forceinline__ T block_sum(T v, T *tmp) {
     return total;
 }
 
-// LDS tiles that lanes read at power-of-two strides (merge-path diagonals
-// tid * N words apart) get one pad word after every 32, which spreads such
-// strides over all 32 banks instead of a few.  lpad maps a tile index to its
-// LDS word; lds_words(n) words hold indices 0 .. n - 1.
-__device__ __forceinline__ uint32_t lpad(uint32_t i) { return i + (i >> 5); }
-constexpr uint32_t lds_words(uint32_t n) { return n + (n >> 5); }
-
 __device__ __forceinline__ uint32_t median3(uint32_t a, uint32_t b, uint32_t c) {
     return max(min(a, b), min(max(a, b), c));
 }

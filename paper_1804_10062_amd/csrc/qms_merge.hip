@@ -279,10 +279,12 @@ __global__ __launch_bounds__(kBlock) void k_merge4_ends(TaskRef<SortSeg> tasks, 
 // caller stores none of them) and read at most N - 1 words past the
 // sentinel.  A step is two LDS reads at addresses one add from i, a compare
 // and a select.
-template <int N>
+// With `from`, also the LDS index each output was read from (to carry
+// payloads along).
+template <int N, bool FROM = false>
 __device__ __forceinline__ void merge_lds(const uint32_t *sk, uint32_t x0, uint32_t nx,
                                           uint32_t y0, uint32_t ny, uint32_t d,
-                                          uint32_t (&out)[N]) {
+                                          uint32_t (&out)[N], uint32_t *from = nullptr) {
     const uint32_t *X = sk + x0, *Y = sk + y0;
     uint32_t lo = d > ny ? d - ny : 0, hi = d < nx ? d : nx;
     while (lo < hi) {
@@ -297,6 +299,7 @@ __device__ __forceinline__ void merge_lds(const uint32_t *sk, uint32_t x0, uint3
         const uint32_t kx = X[i], ky = Yd[q - (int)i];
         const bool takeX = i < nx && kx <= ky;
         out[q] = takeX ? kx : ky;
+        if constexpr (FROM) from[q] = takeX ? x0 + i : y0 + d + q - i;
         i += takeX;
     }
 }
@@ -458,10 +461,10 @@ __device__ __forceinline__ void merge_block(uint32_t *S, uint32_t *SV, uint32_t 
                                             uint32_t *DV, uint64_t m, uint64_t W,
                                             uint64_t tile, const uint32_t *splits,
                                             uint32_t *samples_out) {
-    // padded tiles (index i at lpad(i)): the merge reads at lane strides of
-    // kMergePerThread words
-    __shared__ uint32_t sk[lds_words(kMergeTile)];
-    __shared__ uint32_t sv[PAIRS ? lds_words(kMergeTile) : 1];
+    // the two run slices back to back, then the sentinel merge_lds needs
+    // (at cnt) and slack for the reads of threads whose outputs run past cnt
+    __shared__ uint32_t sk[kMergeTile + 1 + kMerge4Slack];
+    __shared__ uint32_t sv[PAIRS ? kMergeTile : 1];
     const uint32_t tid = threadIdx.x;
 
     const MergeTileGeom g = merge_geom(m, W, tile);
@@ -500,60 +503,47 @@ __device__ __forceinline__ void merge_block(uint32_t *S, uint32_t *SV, uint32_t 
     for (int q = 0; q < kMergePerThread; ++q) {
         const uint32_t e = q * kBlock + tid;
         if (e < cnt) {
-            sk[lpad(e)] = O::ord(nk[q]);
-            if constexpr (PAIRS) sv[lpad(e)] = nv[q];
+            sk[e] = O::ord(nk[q]);
+            if constexpr (PAIRS) sv[e] = nv[q];
         }
     }
+    if (tid == 0) sk[cnt] = 0xffffffffu;
     __syncthreads();
 
-    // each thread merges kMergePerThread consecutive outputs of the tile
-    uint32_t ok[kMergePerThread];
-    uint32_t ov[PAIRS ? kMergePerThread : 1];
-    const uint32_t diag = tid * kMergePerThread;
+    // each thread merges NM consecutive outputs of the tile (one more than
+    // the tile needs: an odd count keeps the lanes' diagonals on distinct
+    // LDS banks)
+    constexpr int NM = kMergePerThread + kMergeOdd;
+    uint32_t ok[NM];
+    uint32_t from[PAIRS ? NM : 1];
+    uint32_t ov[PAIRS ? NM : 1];
+    const uint32_t diag = tid * NM;
     if (diag < cnt) {
-        uint32_t lo = diag > nb ? diag - nb : 0;
-        uint32_t hi = diag < na ? diag : na;
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (sk[lpad(mid)] <= sk[lpad(na + diag - 1 - mid)]) lo = mid + 1;
-            else hi = mid;
-        }
-        // branch-free: reads are clamped into the runs (a value read past
-        // an end is never taken; cnt >= 1 so one of the runs is not empty)
-        const uint32_t al = na ? na - 1 : 0, bl = nb ? na + nb - 1 : al;
-        uint32_t ia = lo, ib = diag - lo;
-        uint32_t ka = sk[lpad(min(ia, al))], kb = sk[lpad(min(na + ib, bl))];
+        merge_lds<NM, PAIRS>(sk, 0, na, na, nb, diag, ok, from);
+        if constexpr (PAIRS) {
 #pragma unroll
-        for (int q = 0; q < kMergePerThread; ++q) {
-            const bool takeA = ib >= nb || (ia < na && ka <= kb);
-            ok[q] = takeA ? ka : kb;
-            if constexpr (PAIRS) ov[q] = sv[lpad(takeA ? min(ia, al) : min(na + ib, bl))];
-            ia += takeA;
-            ib += !takeA;
-            const uint32_t nka = sk[lpad(min(ia, al))], nkb = sk[lpad(min(na + ib, bl))];
-            ka = takeA ? nka : ka;
-            kb = takeA ? kb : nkb;
+            for (int q = 0; q < NM; ++q) ov[q] = sv[min(from[q], cnt - 1)];
         }
     }
     __syncthreads();
     if (diag < cnt) {
 #pragma unroll
-        for (int q = 0; q < kMergePerThread; ++q) {
+        for (int q = 0; q < NM; ++q) {
             if (diag + q < cnt) {
-                sk[lpad(diag + q)] = ok[q];
-                if constexpr (PAIRS) sv[lpad(diag + q)] = ov[q];
+                sk[diag + q] = ok[q];
+                if constexpr (PAIRS) sv[diag + q] = ov[q];
             }
         }
     }
     __syncthreads();
     // the tile's first output is the sample the next level's split search uses
-    if (tid == 0) stg(samples_out + tile, sk[lpad(0)]);
+    if (tid == 0) stg(samples_out + tile, sk[0]);
 #pragma unroll
     for (int q = 0; q < kMergePerThread; ++q) {
         const uint32_t e = q * kBlock + tid;
         if (e < cnt) {
-            stg(D + pb + d0 + e, O::unord(sk[lpad(e)]));
-            if constexpr (PAIRS) stg(DV + pb + d0 + e, sv[lpad(e)]);
+            stg(D + pb + d0 + e, O::unord(sk[e]));
+            if constexpr (PAIRS) stg(DV + pb + d0 + e, sv[e]);
             const uint64_t pos = e < na ? pb + i0 + e : pb + W + j0 + (e - na);
             stg(S + pos, oldk[q]);
             if constexpr (PAIRS) stg(SV + pos, oldv[q]);
