@@ -29,7 +29,7 @@ constexpr uint32_t kSplitLanes = QMS_SPLIT_LANES;      // lanes per merge-path s
 constexpr int kPartSub = 4096;         // elements a workgroup classifies per step
 constexpr int kPartItems = kPartSub / kBlock;          // 16
 #ifndef QMS_RANK_CHUNK
-#define QMS_RANK_CHUNK 4096
+#define QMS_RANK_CHUNK 2048
 #endif
 constexpr int kRankChunk = QMS_RANK_CHUNK;  // misplaced pairs exchanged per workgroup
 constexpr uint32_t kMaxTiles = 65536;  // fixed bound on partition tiles

@@ -15,7 +15,7 @@ constexpr uint32_t kCapSegs = 32768;
 // Partition tiles of one round (the tile grows beyond kPartSub if needed).
 constexpr uint64_t kCapTiles = 1ull << 20;
 // Chunk boundaries of one round: each segment reserves ceil(s / 4096) + 2.
-constexpr uint64_t kCapChunks = (1ull << 20) + 2ull * kCapSegs + 16;
+constexpr uint64_t kCapChunks = (1ull << 21) + 2ull * kCapSegs + 16;
 // Merge splits of one level: ceil(m / kMergeTile) per task, m < 2^31.
 constexpr uint64_t kCapSplits = (1ull << 31) / kMergeTile + kCapSegs + 16;
 // Segments whose median-of-medians pivot one launch group selects.

@@ -570,13 +570,14 @@ __device__ __forceinline__ void skip_empty_tiles(SideScan &sc, uint32_t TP, uint
 
 // Load one subtile of kPartSub positions starting at sc.pos (wave-striped:
 // wave w covers 16 x 64 consecutive positions, lane-interleaved; clamped
-// loads, all in flight) and ballot its misplaced elements.
+// loads, all in flight) and ballot its misplaced elements; the keys stay in
+// kv for the exchange.
 template <class O, int PASS>
 __device__ __forceinline__ uint32_t ballot_subtile(const uint32_t *keys, uint32_t p, bool right,
-                                                   const SideScan &sc, uint64_t m[kPartItems]) {
+                                                   const SideScan &sc, uint64_t m[kPartItems],
+                                                   uint32_t kv[kPartItems]) {
     const int lane = lane_id(), wave = wave_id();
     const uint64_t base = sc.pos + (uint64_t)wave * (kPartItems * kWave) + lane;
-    uint32_t kv[kPartItems];
 #pragma unroll
     for (int q = 0; q < kPartItems; ++q) {
         const uint64_t pos = base + (uint64_t)q * kWave;
@@ -593,11 +594,13 @@ __device__ __forceinline__ uint32_t ballot_subtile(const uint32_t *keys, uint32_
     return wcount;
 }
 
-// Record the positions of a subtile's misplaced elements in `slots`, in
-// position order, after the waves' counts are known (wtot: one per wave).
+// Record the positions of a subtile's misplaced elements in `slots` and
+// their keys in `vslots`, in position order, after the waves' counts are
+// known (wtot: one per wave).
 __device__ __forceinline__ void record_subtile(SideScan &sc, const uint64_t m[kPartItems],
+                                               const uint32_t kv[kPartItems],
                                                const uint32_t *wtot, uint32_t *slots,
-                                               uint32_t cap) {
+                                               uint32_t *vslots, uint32_t cap) {
     const int lane = lane_id(), wave = wave_id();
     uint32_t woff = sc.found, total = 0;
 #pragma unroll
@@ -610,8 +613,10 @@ __device__ __forceinline__ void record_subtile(SideScan &sc, const uint64_t m[kP
     for (int q = 0; q < kPartItems; ++q) {
         if ((m[q] >> lane) & 1ull) {
             const uint32_t slot = woff + (uint32_t)__popcll(m[q] & lanemask_lt());
-            if (slot < cap)  // always true with consistent counts
+            if (slot < cap) {  // always true with consistent counts
                 slots[slot] = (uint32_t)(base + (uint64_t)q * kWave);
+                vslots[slot] = kv[q];
+            }
         }
         woff += (uint32_t)__popcll(m[q]);
     }
@@ -622,8 +627,10 @@ __device__ __forceinline__ void record_subtile(SideScan &sc, const uint64_t m[kP
 // One workgroup per chunk: find the positions of the chunk's misplaced
 // elements on both sides (the two ranges are scanned in the same steps, so
 // their loads overlap), then exchange the k-th of the left with the k-th of
-// the right.  Only positions are kept in LDS; the values are read again at
-// the exchange, from cache.
+// the right.  Positions and keys are kept in LDS, so the exchange only
+// stores (reading the keys again would fetch nearly every line of the range
+// a second time: misplaced elements are dense when the pivot is central);
+// payloads of key/payload sorts are gathered at the exchange.
 template <class O, bool PAIRS, int PASS>
 __global__ __launch_bounds__(kBlock) void k_part_swap(TaskRef<PartSeg> tasks, uint32_t TP,
                                                       const uint32_t *preL_all,
@@ -632,7 +639,7 @@ __global__ __launch_bounds__(kBlock) void k_part_swap(TaskRef<PartSeg> tasks, ui
                                                       const uint32_t *spR_all,
                                                       uint32_t *eqmv_all,
                                                       const uint64_t *meta_all) {
-    __shared__ uint32_t pL[kRankChunk], pR[kRankChunk];
+    __shared__ uint32_t pL[kRankChunk], pR[kRankChunk], vL[kRankChunk], vR[kRankChunk];
     __shared__ uint32_t wtot[2][kWaves];
     uint32_t j, a;
     const PartSeg g = task_of(tasks, blockIdx.x, &j, &a);
@@ -664,16 +671,17 @@ __global__ __launch_bounds__(kBlock) void k_part_swap(TaskRef<PartSeg> tasks, ui
         if (!more_l && !more_r) break;
         // both sides' loads in flight together, one pair of barriers
         uint64_t mL[kPartItems], mR[kPartItems];
+        uint32_t kL[kPartItems], kR[kPartItems];
         uint32_t cl = 0, cr = 0;
-        if (more_l) cl = ballot_subtile<O, PASS>(keys, p, false, L, mL);
-        if (more_r) cr = ballot_subtile<O, PASS>(keys, p, true, R, mR);
+        if (more_l) cl = ballot_subtile<O, PASS>(keys, p, false, L, mL, kL);
+        if (more_r) cr = ballot_subtile<O, PASS>(keys, p, true, R, mR, kR);
         if (lane_id() == 0) {
             wtot[0][wave_id()] = cl;
             wtot[1][wave_id()] = cr;
         }
         __syncthreads();
-        if (more_l) record_subtile(L, mL, wtot[0], pL, kRankChunk);
-        if (more_r) record_subtile(R, mR, wtot[1], pR, kRankChunk);
+        if (more_l) record_subtile(L, mL, kL, wtot[0], pL, vL, kRankChunk);
+        if (more_r) record_subtile(R, mR, kR, wtot[1], pR, vR, kRankChunk);
         __syncthreads();  // wtot is rewritten by the next step
     }
     __syncthreads();
@@ -681,9 +689,9 @@ __global__ __launch_bounds__(kBlock) void k_part_swap(TaskRef<PartSeg> tasks, ui
     cnt = min(cnt, min(L.found, R.found));
     if (cnt == 0) return;
     uint32_t *eqmv = eqmv_all + g.tile_off;
-    // every thread exchanges up to kXItems pairs; all loads are issued before
-    // the first store (clamped slots load a valid pair and store nothing)
-    constexpr int kXItems = kRankChunk / kBlock;
+    // every thread exchanges up to kXItems pairs (clamped slots read a
+    // valid pair and store nothing)
+    constexpr int kXItems = (kRankChunk + kBlock - 1) / kBlock;
     uint32_t il[kXItems], ir[kXItems], x[kXItems], y[kXItems];
 #pragma unroll
     for (int q = 0; q < kXItems; ++q) {
@@ -691,11 +699,8 @@ __global__ __launch_bounds__(kBlock) void k_part_swap(TaskRef<PartSeg> tasks, ui
         const uint32_t kk = k < cnt ? k : cnt - 1;
         il[q] = pL[kk];
         ir[q] = pR[kk];
-    }
-#pragma unroll
-    for (int q = 0; q < kXItems; ++q) {
-        x[q] = ldg(keys + il[q]);
-        y[q] = ldg(keys + ir[q]);
+        x[q] = vL[kk];
+        y[q] = vR[kk];
     }
 #pragma unroll
     for (int q = 0; q < kXItems; ++q) {
