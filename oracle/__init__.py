@@ -12,8 +12,12 @@ module loads it with ctypes and offers numpy-level helpers:
   paper, median-of-3, X_THRESH = 2) on copies of the inputs; returns the
   sorted arrays and the (comparisons, moves) counters.
 * ``sort_segments`` -- the same, independently per segment.
+* ``sort_x(keys, x_thresh=None)`` -- QuickMergeXsort: msort hands ranges
+  shorter than ``x_thresh`` (default ceil(sqrt(n))) to X = CleverQuicksort
+  (Sec. "QuickMergeXsort"); ``x_thresh = 2`` is QuickMergesort.
+* ``clever_quicksort(keys)`` -- X alone, median-of-3 Quicksort.
 * ``partition``, ``out``, ``msort``, ``merge`` -- the individual routines of
-  Fig. 2, for pinning them one by one.
+  Fig. 2, for pinning them one by one; ``msort_x`` is msort with X.
 * ``mom_pivot(keys)`` -- the worst-case pivot of the paper's
   MoMQuickMergesort: the lower median of the medians of the triples.
 * ``order_statistic_ok(x, k, v)`` -- whether ``v`` is the element of rank
@@ -82,6 +86,14 @@ def _load():
         f = getattr(lib, name)
         f.argtypes = [u32p, u32p, sz, ctypes.c_int, cp]
         f.restype = None
+    for name in ("qmso_sort_x", "qmso_fast_sort_x"):
+        f = getattr(lib, name)
+        f.argtypes = [u32p, u32p, sz, ctypes.c_int, sz, cp]
+        f.restype = None
+    for name in ("qmso_clever_quicksort", "qmso_fast_clever_quicksort"):
+        f = getattr(lib, name)
+        f.argtypes = [u32p, u32p, sz, ctypes.c_int, cp]
+        f.restype = None
     for name in ("qmso_sort_segments", "qmso_fast_sort_segments"):
         f = getattr(lib, name)
         f.argtypes = [u32p, u32p, u64p, sz, ctypes.c_int, cp]
@@ -92,6 +104,8 @@ def _load():
     lib.qmso_out.restype = None
     lib.qmso_msort.argtypes = [u32p, u32p, sz, sz, sz, cp]
     lib.qmso_msort.restype = None
+    lib.qmso_msort_x.argtypes = [u32p, u32p, sz, sz, sz, sz, cp]
+    lib.qmso_msort_x.restype = None
     lib.qmso_merge.argtypes = [u32p, u32p, sz, sz, sz, sz, cp]
     lib.qmso_merge.restype = None
     lib.qmso_mom_pivot.argtypes = [u32p, sz, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
@@ -125,6 +139,47 @@ def sort(keys, vals=None, counted: bool = True):
         raise ValueError("keys and vals differ in length")
     c = _Counters()
     fn = lib.qmso_sort if counted else lib.qmso_fast_sort
+    fn(_ptr(words), _ptr(v), words.size, is_f32, ctypes.byref(c))
+    out = words.view(np.float32) if is_f32 else words
+    return out, v, Counts(int(c.comparisons), int(c.moves))
+
+
+def sqrt_threshold(n: int) -> int:
+    """ceil(sqrt(n)): the X_THRESH of QuickMergeXsort's sqrt(n) configuration."""
+    r = int(np.floor(np.sqrt(float(n))))
+    while r * r < n:
+        r += 1
+    while r > 0 and (r - 1) * (r - 1) >= n:
+        r -= 1
+    return max(r, 2)
+
+
+def sort_x(keys, vals=None, x_thresh: int | None = None, counted: bool = True):
+    """QuickMergeXsort copies of the inputs with X = CleverQuicksort called on
+    msort ranges shorter than ``x_thresh`` (default ceil(sqrt(n))); returns
+    (keys, vals, Counts)."""
+    lib = _load()
+    words, is_f32 = _as_words(keys)
+    v = None if vals is None else np.ascontiguousarray(vals, dtype=np.uint32).copy()
+    if v is not None and v.shape != words.shape:
+        raise ValueError("keys and vals differ in length")
+    xt = sqrt_threshold(words.size) if x_thresh is None else int(x_thresh)
+    if xt < 2:
+        raise ValueError("x_thresh must be at least 2")
+    c = _Counters()
+    fn = lib.qmso_sort_x if counted else lib.qmso_fast_sort_x
+    fn(_ptr(words), _ptr(v), words.size, is_f32, xt, ctypes.byref(c))
+    out = words.view(np.float32) if is_f32 else words
+    return out, v, Counts(int(c.comparisons), int(c.moves))
+
+
+def clever_quicksort(keys, vals=None, counted: bool = True):
+    """X alone: median-of-3 Quicksort of copies; returns (keys, vals, Counts)."""
+    lib = _load()
+    words, is_f32 = _as_words(keys)
+    v = None if vals is None else np.ascontiguousarray(vals, dtype=np.uint32).copy()
+    c = _Counters()
+    fn = lib.qmso_clever_quicksort if counted else lib.qmso_fast_clever_quicksort
     fn(_ptr(words), _ptr(v), words.size, is_f32, ctypes.byref(c))
     out = words.view(np.float32) if is_f32 else words
     return out, v, Counts(int(c.comparisons), int(c.moves))
@@ -189,6 +244,20 @@ def msort(keys, begin: int, end: int, target: int, vals=None):
         raise ValueError("msort: ranges out of the array")
     c = _Counters()
     lib.qmso_msort(_ptr(k), _ptr(v), begin, end, target, ctypes.byref(c))
+    return k, v, Counts(int(c.comparisons), int(c.moves))
+
+
+def msort_x(keys, begin: int, end: int, target: int, x_thresh: int, vals=None):
+    """QuickMergeXsort's msort on a copy: X below ``x_thresh``."""
+    lib = _load()
+    k = np.ascontiguousarray(keys, dtype=np.uint32).copy()
+    v = None if vals is None else np.ascontiguousarray(vals, dtype=np.uint32).copy()
+    n = end - begin
+    if not (0 <= begin <= end <= k.size and 0 <= target and target + n <= k.size):
+        raise ValueError("msort: ranges out of the array")
+    c = _Counters()
+    lib.qmso_msort_x(_ptr(k), _ptr(v), begin, end, target, max(2, int(x_thresh)),
+                     ctypes.byref(c))
     return k, v, Counts(int(c.comparisons), int(c.moves))
 
 

@@ -19,7 +19,13 @@
  *     figure, both listed below;
  *   - median-of-3 pivot ("CleverQuickMergesort", Theorem 1 / Corollary 2):
  *     3 comparisons for the sample, one comparison per remaining element
- *     during partitioning (proof of Theorem 1).
+ *     during partitioning (proof of Theorem 1);
+ *   - QuickMergeXsort (Sec. "QuickMergeXsort", Theorem "Average-Case
+ *     QuickMergeXsort"): msort hands ranges shorter than X_THRESH to a
+ *     sorting algorithm X and then exchanges the sorted block with its target
+ *     cells (the joint movement of Fig. 2).  X = CleverQuicksort, Quicksort
+ *     with the median-of-3 partition below (Introduction: its average is
+ *     (12/7) ln 2 n lg n + O(n) comparisons).  X_THRESH = 2 is QuickMergesort.
  *
  * Readings of the paper taken here (the paper is silent or its figure does
  * not run as printed):
@@ -50,6 +56,13 @@
  *       the lower median (0-based rank floor((c-1)/2) of the c medians).  The
  *       paper selects it with the median-of-medians algorithm; any exact
  *       selection yields the same value, here a library sort of the medians.
+ *   R8  QuickMergeXsort's threshold X_THRESH is one constant for the whole
+ *       sort, as in Fig. 2 (msort tests n < X_THRESH); the configuration the
+ *       paper analyses, X called at about sqrt(n) elements, takes
+ *       X_THRESH = ceil(sqrt(n)) of the whole input (the caller's choice).
+ *       CleverQuicksort recurses on the smaller side and loops on the larger
+ *       (same comparisons, logarithmic depth) and finishes ranges of two
+ *       elements with one compare-exchange (R5).
  *
  * Counters (Experiments section): one comparison per key comparison; one
  * move per element assignment, a swap counting as three moves.  The counting
@@ -85,6 +98,7 @@ typedef struct {
     uint32_t *k;
     uint32_t *v;
     qmso_counters *c;
+    size_t xt; /* X_THRESH of msort (2: pure Mergesort) */
 } arr_t;
 
 #if QMSO_COUNTING
@@ -159,15 +173,19 @@ static void merge(arr_t *a, size_t begin1, size_t end1, size_t target,
     COUNT_MOV(a, 1);
 }
 
+static void clever_quicksort(arr_t *a, size_t lo, size_t hi);
+
 /*
  * msort (Fig. 2): sort [begin, end) into [target, target + n); the buffer
- * elements found at the target end up in [begin, end).  X_THRESH = 2: a
- * single element is its own sorted run and is swapped into place.
+ * elements found at the target end up in [begin, end).  Below X_THRESH the
+ * range is sorted by X in place and then swapped into the target cells (the
+ * joint movement); with X_THRESH = 2 a single element is its own sorted run.
  */
 static void msort(arr_t *a, size_t begin, size_t end, size_t target)
 {
     size_t n = end - begin;
-    if (n < 2) {
+    if (n < a->xt) {
+        clever_quicksort(a, begin, end);
         for (size_t i = 0; i < n; i++) swap_ij(a, begin + i, target + i);
         return;
     }
@@ -229,6 +247,28 @@ static size_t partition(arr_t *a, size_t lo, size_t hi)
     return b;
 }
 
+/*
+ * X = CleverQuicksort: Quicksort with the median-of-3 partition above on
+ * [lo, hi); the smaller side recursively, the larger one by the loop (R8).
+ */
+static void clever_quicksort(arr_t *a, size_t lo, size_t hi)
+{
+    while (hi - lo > 1) {
+        if (hi - lo == 2) {
+            cmp_exchange(a, lo, lo + 1);
+            return;
+        }
+        size_t b = partition(a, lo, hi);
+        if (b - lo < hi - (b + 1)) {
+            clever_quicksort(a, lo, b);
+            lo = b + 1;
+        } else {
+            clever_quicksort(a, b + 1, hi);
+            hi = b;
+        }
+    }
+}
+
 /* sort (Fig. 2): the QuickMergesort loop on [lo, hi). */
 static void qms_loop(arr_t *a, size_t lo, size_t hi)
 {
@@ -275,10 +315,37 @@ void QMSO_FN(sort)(uint32_t *keys, uint32_t *vals, size_t n, int is_f32,
                    qmso_counters *counters)
 {
     qmso_counters scratch;
-    arr_t a = {keys, vals, counters_or_scratch(counters, &scratch)};
+    arr_t a = {keys, vals, counters_or_scratch(counters, &scratch), 2};
     if (is_f32)
         for (size_t i = 0; i < n; i++) keys[i] = f32_bits_to_key(keys[i]);
     qms_loop(&a, 0, n);
+    if (is_f32)
+        for (size_t i = 0; i < n; i++) keys[i] = key_to_f32_bits(keys[i]);
+}
+
+/* QuickMergeXsort with X = CleverQuicksort below x_thresh (>= 2; R8). */
+void QMSO_FN(sort_x)(uint32_t *keys, uint32_t *vals, size_t n, int is_f32,
+                     size_t x_thresh, qmso_counters *counters)
+{
+    qmso_counters scratch;
+    arr_t a = {keys, vals, counters_or_scratch(counters, &scratch),
+               x_thresh < 2 ? 2 : x_thresh};
+    if (is_f32)
+        for (size_t i = 0; i < n; i++) keys[i] = f32_bits_to_key(keys[i]);
+    qms_loop(&a, 0, n);
+    if (is_f32)
+        for (size_t i = 0; i < n; i++) keys[i] = key_to_f32_bits(keys[i]);
+}
+
+/* X alone: CleverQuicksort of the whole input. */
+void QMSO_FN(clever_quicksort)(uint32_t *keys, uint32_t *vals, size_t n,
+                               int is_f32, qmso_counters *counters)
+{
+    qmso_counters scratch;
+    arr_t a = {keys, vals, counters_or_scratch(counters, &scratch), 2};
+    if (is_f32)
+        for (size_t i = 0; i < n; i++) keys[i] = f32_bits_to_key(keys[i]);
+    clever_quicksort(&a, 0, n);
     if (is_f32)
         for (size_t i = 0; i < n; i++) keys[i] = key_to_f32_bits(keys[i]);
 }
@@ -339,7 +406,7 @@ size_t qmso_partition(uint32_t *keys, uint32_t *vals, size_t lo, size_t hi,
                       qmso_counters *counters)
 {
     qmso_counters scratch;
-    arr_t a = {keys, vals, counters_or_scratch(counters, &scratch)};
+    arr_t a = {keys, vals, counters_or_scratch(counters, &scratch), 2};
     return partition(&a, lo, hi);
 }
 
@@ -347,7 +414,7 @@ void qmso_out(uint32_t *keys, uint32_t *vals, size_t begin, size_t end,
               size_t temp, qmso_counters *counters)
 {
     qmso_counters scratch;
-    arr_t a = {keys, vals, counters_or_scratch(counters, &scratch)};
+    arr_t a = {keys, vals, counters_or_scratch(counters, &scratch), 2};
     out(&a, begin, end, temp);
 }
 
@@ -355,7 +422,17 @@ void qmso_msort(uint32_t *keys, uint32_t *vals, size_t begin, size_t end,
                 size_t target, qmso_counters *counters)
 {
     qmso_counters scratch;
-    arr_t a = {keys, vals, counters_or_scratch(counters, &scratch)};
+    arr_t a = {keys, vals, counters_or_scratch(counters, &scratch), 2};
+    msort(&a, begin, end, target);
+}
+
+/* msort with X = CleverQuicksort below x_thresh (QuickMergeXsort's msort) */
+void qmso_msort_x(uint32_t *keys, uint32_t *vals, size_t begin, size_t end,
+                  size_t target, size_t x_thresh, qmso_counters *counters)
+{
+    qmso_counters scratch;
+    arr_t a = {keys, vals, counters_or_scratch(counters, &scratch),
+               x_thresh < 2 ? 2 : x_thresh};
     msort(&a, begin, end, target);
 }
 
@@ -363,7 +440,7 @@ void qmso_merge(uint32_t *keys, uint32_t *vals, size_t begin1, size_t end1,
                 size_t target, size_t endtarget, qmso_counters *counters)
 {
     qmso_counters scratch;
-    arr_t a = {keys, vals, counters_or_scratch(counters, &scratch)};
+    arr_t a = {keys, vals, counters_or_scratch(counters, &scratch), 2};
     merge(&a, begin1, end1, target, endtarget);
 }
 #endif

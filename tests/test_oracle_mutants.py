@@ -41,6 +41,15 @@ MUTANTS = {
     "mom_median_of_three_wrong": (
         "med[i] = z < lo ? lo : (z > hi ? hi : z);",
         "med[i] = z < lo ? z : (z > hi ? hi : z);"),
+    "x_never_called": (
+        "    if (n < a->xt) {",
+        "    if (n < 2) {"),
+    "x_recursion_includes_pivot": (
+        "            clever_quicksort(a, lo, b);\n            lo = b + 1;",
+        "            clever_quicksort(a, lo, b + 1);\n            lo = b + 1;"),
+    "x_joint_movement_short": (
+        "        for (size_t i = 0; i < n; i++) swap_ij(a, begin + i, target + i);\n        return;\n    }\n    size_t q",
+        "        for (size_t i = 0; i + 1 < n; i++) swap_ij(a, begin + i, target + i);\n        return;\n    }\n    size_t q"),
     "partition_scan_skips_element": (
         "        swap_ij(a, i, j);\n        i++;\n        j--;",
         "        swap_ij(a, i, j);\n        i += 2;\n        j--;"),
@@ -89,6 +98,31 @@ CHECK = textwrap.dedent(r"""
             x = r.integers(0, 20, n).astype(np.uint32)
             if oracle.mom_pivot(x) != _mom_pivot_by_counting(x):
                 failures.append(("mom", n)); break
+    from tests.test_oracle_xsort import cqs_recurrence, msort_x_avg
+    Q = cqs_recurrence(16)
+    for n in range(2, 8):
+        tot = cnt = 0
+        for p in itertools.permutations(range(n)):
+            s, _, c = oracle.clever_quicksort(np.array(p, dtype=np.uint32))
+            if s.tolist() != list(range(n)):
+                failures.append(("cqs perm", n)); break
+            tot += c.comparisons; cnt += 1
+        if abs(tot / cnt - Q[n]) > 1e-9:
+            failures.append(("cqs avg", n))
+    for xt in (5, 8):
+        tot = cnt = 0
+        buf = np.arange(50, 57, dtype=np.uint32)
+        for p in itertools.permutations(range(7)):
+            k, _, c = oracle.msort_x(np.concatenate([np.array(p, dtype=np.uint32), buf]), 0, 7, 7, xt)
+            if k[7:].tolist() != list(range(7)):
+                failures.append(("msort_x perm", xt)); break
+            tot += c.comparisons; cnt += 1
+        if abs(tot / cnt - msort_x_avg(7, xt, Q, {})) > 1e-9:
+            failures.append(("msort_x avg", xt))
+    for xt in (3, 17, None):
+        x = rng.permutation(3000).astype(np.uint32)
+        if oracle.sort_x(x, x_thresh=xt)[0].tolist() != list(range(3000)):
+            failures.append(("sort_x", xt))
     print("FAILURES", failures)
     sys.exit(1 if failures else 0)
 """)
