@@ -64,6 +64,7 @@ def parse():
     ap.add_argument("--only-uniform", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-threshold-sweep", action="store_true")
     ap.add_argument("--per-array-stride", type=int, default=10)
     ap.add_argument("--serving-requests", type=int, default=3000)
     ap.add_argument("--pmc-run", action="store_true",
@@ -363,6 +364,35 @@ def main():
         dists["pairs_zipf_2e26"] = round(npairs / (sec2 / args.dist_steps) / 1e9, 3)
         del ks, vs, k0, v0
 
+    # QuickMergeXsort's threshold (Sec. "QuickMergeXsort"): the same uniform
+    # workload with the Mergesort stopping at runs of base_tile keys; the
+    # bitonic base case spends lg(t)(lg(t)+1)/4 compare-exchanges per key,
+    # every merge level one pass over the data
+    xthresh = None
+    if not args.only_uniform and not args.no_threshold_sweep:
+        from paper_1804_10062_amd import autotune
+        xthresh = {}
+        try:
+            for t0 in (16384, 8192, 4096, 2048):
+                print(f"[bench] X_THRESH {t0}", file=sys.stderr, flush=True)
+                qms.qms_set_tuning(4, 4096, 16384, t0)
+                cps = [src.clone() for _ in range(args.dist_steps + 1)]
+                time_sorts(cps[:1], qms, torch, profile=False)
+                sec2, _ = time_sorts(cps[1:], qms, torch, profile=False)
+                if not is_sorted(cps[-1]):
+                    print(f"bench.py: X_THRESH {t0} output not sorted", file=sys.stderr)
+                    sys.exit(1)
+                lg = int(t0).bit_length() - 1
+                first = qms.qms_last_schedule()[0]
+                xthresh[str(t0)] = {
+                    "Gkeys_per_s": round(N_KEYS / (sec2 / args.dist_steps) / 1e9, 3),
+                    "ms_per_sort": round(sec2 / args.dist_steps * 1e3, 3),
+                    "network_compare_exchanges_per_key": lg * (lg + 1) / 4,
+                    "first_round_merge_levels": int(first[4])}
+                del cps
+        finally:
+            autotune.reset_tuning()
+
     batched = None
     if not args.no_batched:
         print("[bench] batched vs per-array", file=sys.stderr, flush=True)
@@ -410,6 +440,7 @@ def main():
         "whole_sort": whole_sort,
         "cpu_baseline": cpu,
         "distributions_Gkeys_per_s": dists,
+        "x_thresh_tradeoff": xthresh,
         "batched": batched,
         "serving": serving,
         "kernels": kernels,

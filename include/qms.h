@@ -206,8 +206,8 @@ int qms_profile_end(qms_kernel_stat *out, int max_entries, int *n_out);
 
 /*
  * Run-time tunables, process-wide, read at the start of every sort (the
- * server's worker included); defaults {4, 4096, 16384}.  They change speed,
- * never results.
+ * server's worker included); defaults {4, 4096, 16384, 16384}.  They change
+ * speed, never results.
  *   merge_ways      2 or 4: key-only sorts merge four runs per pass (the
  *                   multi-way merging proposed in the paper's Conclusion) or
  *                   two; key/payload sorts always merge two.
@@ -216,6 +216,13 @@ int qms_profile_end(qms_kernel_stat *out, int max_entries, int *n_out);
  *                   doubles it.
  *   chunk_span      target positions per exchange chunk of the partition, in
  *                   [4096, 2^20] (smaller: more, shorter chunks).
+ *   base_tile       X_THRESH of QuickMergeXsort (Sec. "QuickMergeXsort"): the
+ *                   Mergesort of each round stops at runs of this many keys,
+ *                   which the base case X (a bitonic network in LDS) sorts;
+ *                   a power of two in [2048, 16384].  Smaller: fewer network
+ *                   comparisons, more merge levels.  Key/payload sorts use at
+ *                   most 8192.  16384 = sqrt(2^28), the paper's sqrt(n) rule
+ *                   for the 2^28-key workload.
  * qms_set_tuning returns QMS_ERR_INVALID for values out of range (nothing is
  * changed then).  The package's autotuner (paper_1804_10062_amd/autotune.py)
  * picks them for a workload by timing sorts of a sample.
@@ -224,12 +231,14 @@ typedef struct {
     uint32_t merge_ways;
     uint32_t partition_tile;
     uint32_t chunk_span;
+    uint32_t base_tile;
 } qms_tuning;
 int qms_set_tuning(const qms_tuning *t);
 int qms_get_tuning(qms_tuning *t);
 
-/* Tunables as used by the kernels: base-case tile, merge tile, partition
- * tile (elements).  Read-only; for reports and tests. */
+/* Build-time tiles of the kernels: base-case workgroup tile (keys; the
+ * largest base_tile), merge tile, partition tile (elements).  Read-only; for
+ * reports and tests. */
 void qms_get_tiles(uint32_t *base_tile, uint32_t *merge_tile,
                    uint32_t *partition_tile);
 

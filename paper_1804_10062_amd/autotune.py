@@ -17,9 +17,12 @@ from typing import Iterable, Optional, Sequence, Tuple
 
 from . import qms
 
-# (merge_ways, partition_tile, chunk_span)
-CANDIDATES: Tuple[Tuple[int, int, int], ...] = tuple(
-    itertools.product((4, 2), (4096, 8192), (16384, 32768)))
+FIELDS = ("merge_ways", "partition_tile", "chunk_span", "base_tile")
+# (merge_ways, partition_tile, chunk_span, base_tile); base_tile is
+# QuickMergeXsort's X_THRESH, the run width at which the Mergesort calls the
+# base case
+CANDIDATES: Tuple[Tuple[int, int, int, int], ...] = tuple(
+    itertools.product((4, 2), (4096, 8192), (16384, 32768), (16384, 8192, 4096)))
 
 
 def _time_batch(keys, offsets, vals, ref_keys, ref_vals, reps: int, stream,
@@ -56,20 +59,18 @@ def autotune_batch(keys, offsets, vals=None, host_offsets=None,
     trials = []
     try:
         with torch.cuda.stream(stream):
-            for ways, ptile, span in candidates:
-                qms.qms_set_tuning(ways, ptile, span)
+            for cand in candidates:
+                qms.qms_set_tuning(*cand)
                 ms = _time_batch(work_k, offsets, work_v, keys, vals, reps, stream, host_offsets)
-                trials.append({"merge_ways": ways, "partition_tile": ptile,
-                               "chunk_span": span, "ms": round(ms, 4)})
+                trials.append(dict(zip(FIELDS, qms.qms_get_tuning().values()), ms=round(ms, 4)))
     except Exception:
-        qms.qms_set_tuning(before["merge_ways"], before["partition_tile"], before["chunk_span"])
+        qms.qms_set_tuning(*(before[f] for f in FIELDS))
         raise
     best = min(trials, key=lambda t: t["ms"])
-    qms.qms_set_tuning(best["merge_ways"], best["partition_tile"], best["chunk_span"])
-    return {"best": {k: best[k] for k in ("merge_ways", "partition_tile", "chunk_span")},
-            "trials": trials}
+    qms.qms_set_tuning(*(best[f] for f in FIELDS))
+    return {"best": {f: best[f] for f in FIELDS}, "trials": trials}
 
 
 def reset_tuning() -> None:
     """Back to the library defaults."""
-    qms.qms_set_tuning(4, 4096, 16384)
+    qms.qms_set_tuning(4, 4096, 16384, 16384)

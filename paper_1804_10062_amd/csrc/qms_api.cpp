@@ -242,10 +242,14 @@ int qms_set_tuning(const qms_tuning *t) {
         return set_error(QMS_ERR_INVALID, "partition_tile must be a power of two in [4096, 65536]");
     if (t->chunk_span < (uint32_t)kPartSub || t->chunk_span > (1u << 20))
         return set_error(QMS_ERR_INVALID, "chunk_span must lie in [4096, 2^20]");
+    const uint32_t bt = t->base_tile;
+    if (bt < (uint32_t)kMergeTile || bt > kBaseTileKeys || (bt & (bt - 1)) != 0)
+        return set_error(QMS_ERR_INVALID, "base_tile must be a power of two in [2048, 16384]");
     std::lock_guard<std::mutex> lock(g_tuning_mutex);
     g_tuning.merge_ways = t->merge_ways;
     g_tuning.partition_tile = pt;
     g_tuning.chunk_span = t->chunk_span;
+    g_tuning.base_tile = bt;
     return QMS_OK;
 }
 
@@ -255,6 +259,7 @@ int qms_get_tuning(qms_tuning *t) {
     t->merge_ways = c.merge_ways;
     t->partition_tile = c.partition_tile;
     t->chunk_span = c.chunk_span;
+    t->base_tile = c.base_tile;
     return QMS_OK;
 }
 

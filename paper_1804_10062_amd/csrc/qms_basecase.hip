@@ -169,8 +169,8 @@ __device__ __forceinline__ uint32_t nat_idx(uint32_t e) {
 // the destination region (equal in place); len <= the tile size.
 template <class O, bool PAIRS>
 __device__ __forceinline__ void tile_sort_block(uint32_t *sk, uint32_t *sv, uint32_t *dk,
-                                                uint32_t *dv, uint32_t len, bool swap,
-                                                uint32_t *samples) {
+                                                uint32_t *dv, uint32_t len, uint32_t run,
+                                                bool swap, uint32_t *samples) {
     using TE = TileElem<PAIRS>;
     using E = typename TE::E;
     constexpr int ITEMS = TE::ITEMS;
@@ -244,15 +244,17 @@ __device__ __forceinline__ void tile_sort_block(uint32_t *sk, uint32_t *sv, uint
         }
     }
 
-    // 4. merge stages from k = ITEMS on, where the direction of a block
-    //    depends on the thread.  During merge stage k a thread's keys are
-    //    held complemented when its k-block sorts descending (complementing
-    //    reverses the unsigned order), so every compare-exchange below is an
-    //    ascending one; the representation changes only between stages.  At
-    //    the last stage every block ascends and the keys are plain again.
+    // 4. merge stages from k = ITEMS up to the run width (the whole tile, or
+    //    QuickMergeXsort's X_THRESH when the Mergesort stops earlier), where
+    //    the direction of a block depends on the thread.  During merge stage
+    //    k a thread's keys are held complemented when its k-block sorts
+    //    descending (complementing reverses the unsigned order), so every
+    //    compare-exchange below is an ascending one; the representation
+    //    changes only between stages.  At the last stage every block ascends
+    //    and the keys are plain again: the tile holds T / run sorted runs.
     E cur_mask = E(0);
-    for (uint32_t k = ITEMS; k <= T; k <<= 1) {
-        const E mask = (base & k) == 0 ? E(0) : ~E(0);
+    for (uint32_t k = ITEMS; k <= run; k <<= 1) {
+        const E mask = (k == run || (base & k) == 0) ? E(0) : ~E(0);
         const E flip = mask ^ cur_mask;
         cur_mask = mask;
 #pragma unroll
@@ -379,8 +381,11 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_sort(TaskRef<SortSeg> tas
     const uint32_t len = min(T, g.m - t0);
     const bool swap = (merge_passes(g.L, g.two_way != 0) & 1u) != 0;
     const uint32_t src = g.D + t0, dst = (swap ? g.Bf : g.D) + t0;
+    // runs of g.w0 keys (a power of two in [kMergeTile, T]; clamped so that
+    // a malformed task still runs a valid network)
+    const uint32_t run = g.w0 >= T ? T : (g.w0 <= (uint32_t)kMergeTile ? (uint32_t)kMergeTile : g.w0);
     tile_sort_block<O, PAIRS>(g.keys + src, PAIRS ? g.vals + src : nullptr, g.keys + dst,
-                              PAIRS ? g.vals + dst : nullptr, len, swap,
+                              PAIRS ? g.vals + dst : nullptr, len, run, swap,
                               samples + g.split_off + t0 / kMergeTile);
 }
 

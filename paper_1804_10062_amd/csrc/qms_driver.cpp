@@ -117,7 +117,12 @@ const std::vector<std::array<uint64_t, kScheduleWords>> &last_schedule() { retur
 static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
                       hipStream_t st, bool log, const Tuning &tune) {
     const double w = pairs ? 2.0 : 1.0;
-    const uint32_t T0 = pairs ? kBaseTilePairs : kBaseTileKeys;  // base-case tile
+    // T0: the base case's workgroup tile; ranges of at most T0 keys are
+    // finished in place by one workgroup.  R0: the run width at which each
+    // round's Mergesort stops and calls the base case X (QuickMergeXsort's
+    // X_THRESH, a tunable), so that a workgroup tile holds T0 / R0 runs.
+    const uint32_t T0 = pairs ? kBaseTilePairs : kBaseTileKeys;
+    const uint32_t R0 = std::min(T0, tune.base_tile);
     std::vector<uint32_t> active, next;
     // ranges of at most T0 keys, sorted in place by the base case.  A
     // range that becomes small in a round still holds that round's swap
@@ -270,7 +275,7 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
                 const uint32_t c_lt = ws.h_res[4 * a], c_eq = ws.h_res[4 * a + 1];
                 const uint32_t b1 = g.lo + c_lt, b2 = b1 + c_eq;
                 const uint32_t mL = c_lt, mR = g.hi - b2;
-                SortSeg t{g.keys, g.vals, 0, 0, 0, 0, 0, T0};
+                SortSeg t{g.keys, g.vals, 0, 0, 0, 0, 0, R0};
                 if (mL <= mR) {
                     t.D = g.lo;
                     t.Bf = b2;
@@ -282,7 +287,7 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
                     t.m = mR;
                     g.hi = b1;
                 }
-                t.L = t.m > T0 ? ceil_log2((t.m + T0 - 1) / T0) : 0;
+                t.L = t.m > R0 ? ceil_log2((t.m + R0 - 1) / R0) : 0;
                 // HybridQuickMergesort's rule with delta = 1/16: a split outside
                 // [s/16, 15 s/16] makes the next pivot of this array the
                 // median of the medians of three; the one after returns to

@@ -16,11 +16,13 @@ namespace qms {
 constexpr int kScheduleWords = 6;
 
 // Run-time tunables (qms_set_tuning): merge arity of key-only sorts, the
-// first partition counting tile, the target positions per exchange chunk.
+// first partition counting tile, the target positions per exchange chunk,
+// the Mergesort's base-case run width (QuickMergeXsort's X_THRESH).
 struct Tuning {
     uint32_t merge_ways = 4;
     uint32_t partition_tile = kPartSub;
     uint32_t chunk_span = (uint32_t)kChunkSpan;
+    uint32_t base_tile = kBaseTileKeys;
 };
 Tuning current_tuning();
 

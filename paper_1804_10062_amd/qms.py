@@ -60,7 +60,7 @@ class ServerStats(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("merge_ways", ctypes.c_uint32), ("partition_tile", ctypes.c_uint32),
-                ("chunk_span", ctypes.c_uint32)]
+                ("chunk_span", ctypes.c_uint32), ("base_tile", ctypes.c_uint32)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -227,8 +227,9 @@ def qms_mom_pivot(keys, stream=None) -> int:
     return out.value
 
 
-def qms_set_tuning(merge_ways: int, partition_tile: int, chunk_span: int) -> None:
-    t = Tuning(merge_ways, partition_tile, chunk_span)
+def qms_set_tuning(merge_ways: int, partition_tile: int, chunk_span: int,
+                   base_tile: int = 16384) -> None:
+    t = Tuning(merge_ways, partition_tile, chunk_span, base_tile)
     _check(load_library().qms_set_tuning(ctypes.byref(t)), "qms_set_tuning")
 
 

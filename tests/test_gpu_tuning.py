@@ -12,8 +12,11 @@ from tests.gpu_helpers import to_device, to_host  # noqa: E402
 pytestmark = pytest.mark.gpu
 needs_gpu = pytest.mark.skipif(not torch.cuda.is_available(), reason="no GPU")
 
-TUNINGS = [(4, 4096, 16384), (2, 4096, 16384), (4, 8192, 32768), (2, 16384, 4096),
-           (4, 65536, 1 << 20)]
+# (merge_ways, partition_tile, chunk_span, base_tile)
+TUNINGS = [(4, 4096, 16384, 16384), (2, 4096, 16384, 16384), (4, 8192, 32768, 8192),
+           (2, 16384, 4096, 4096), (4, 65536, 1 << 20, 2048), (4, 4096, 16384, 4096),
+           (2, 8192, 16384, 2048)]
+FIELDS = ("merge_ways", "partition_tile", "chunk_span", "base_tile")
 
 
 @pytest.fixture(autouse=True)
@@ -29,7 +32,7 @@ def _restore_defaults():
                                     ("zipf", 200003), ("reverse", 1 << 18)])
 def test_tuned_sort_matches_oracle(tuning, kind, n):
     qms.qms_set_tuning(*tuning)
-    assert qms.qms_get_tuning() == dict(zip(("merge_ways", "partition_tile", "chunk_span"), tuning))
+    assert qms.qms_get_tuning() == dict(zip(FIELDS, tuning))
     x = inputs.make_keys(kind, n, seed=11)
     t = to_device(x)
     qms.qms_sort(t)
@@ -39,7 +42,7 @@ def test_tuned_sort_matches_oracle(tuning, kind, n):
 
 
 @needs_gpu
-@pytest.mark.parametrize("tuning", TUNINGS[:3])
+@pytest.mark.parametrize("tuning", TUNINGS[:5])
 def test_tuned_pairs_and_f32(tuning):
     qms.qms_set_tuning(*tuning)
     x = inputs.normal_f32(123457, seed=3)
@@ -62,7 +65,8 @@ def test_tuned_pairs_and_f32(tuning):
 def test_invalid_tuning_rejected_and_unchanged():
     before = qms.qms_get_tuning()
     for bad in [(3, 4096, 16384), (4, 4095, 16384), (4, 6144, 16384), (4, 4096, 100),
-                (4, 1 << 17, 16384), (4, 4096, (1 << 20) + 1)]:
+                (4, 1 << 17, 16384), (4, 4096, (1 << 20) + 1),
+                (4, 4096, 16384, 1024), (4, 4096, 16384, 3072), (4, 4096, 16384, 32768)]:
         with pytest.raises(qms.QmsError):
             qms.qms_set_tuning(*bad)
     assert qms.qms_get_tuning() == before
