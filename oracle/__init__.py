@@ -45,13 +45,15 @@ def build(force: bool = True) -> str:
         return _LIB_PATH
     os.makedirs(_BUILD, exist_ok=True)
     objs = []
-    for counting in (1, 0):
-        obj = os.path.join(_BUILD, f"qms_oracle_{counting}.o")
-        subprocess.check_call([
-            "gcc", "-std=c11", "-O2", "-fPIC", "-Wall", "-Wextra",
-            f"-DQMSO_COUNTING={counting}", "-c", _SRC, "-o", obj,
-        ])
-        objs.append(obj)
+    for bits in (32, 64):
+        for counting in (1, 0):
+            obj = os.path.join(_BUILD, f"qms_oracle_{bits}_{counting}.o")
+            subprocess.check_call([
+                "gcc", "-std=c11", "-O2", "-fPIC", "-Wall", "-Wextra",
+                f"-DQMSO_COUNTING={counting}", f"-DQMSO_KEY_BITS={bits}", "-c", _SRC,
+                "-o", obj,
+            ])
+            objs.append(obj)
     tmp = _LIB_PATH + ".tmp"
     subprocess.check_call(["gcc", "-shared", "-o", tmp] + objs)
     os.replace(tmp, _LIB_PATH)
@@ -86,6 +88,20 @@ def _load():
         f = getattr(lib, name)
         f.argtypes = [u32p, u32p, sz, ctypes.c_int, cp]
         f.restype = None
+    # 64-bit keys: the same routines compiled for uint64 keys
+    for name in ("qmso64_sort", "qmso64_fast_sort", "qmso64_clever_quicksort",
+                 "qmso64_fast_clever_quicksort"):
+        f = getattr(lib, name)
+        f.argtypes = [u64p, u32p, sz, ctypes.c_int, cp]
+        f.restype = None
+    for name in ("qmso64_sort_x", "qmso64_fast_sort_x"):
+        f = getattr(lib, name)
+        f.argtypes = [u64p, u32p, sz, ctypes.c_int, sz, cp]
+        f.restype = None
+    for name in ("qmso64_sort_segments", "qmso64_fast_sort_segments"):
+        f = getattr(lib, name)
+        f.argtypes = [u64p, u32p, u64p, sz, ctypes.c_int, cp]
+        f.restype = None
     for name in ("qmso_sort_x", "qmso_fast_sort_x"):
         f = getattr(lib, name)
         f.argtypes = [u32p, u32p, sz, ctypes.c_int, sz, cp]
@@ -115,19 +131,36 @@ def _load():
 
 
 def _as_words(a: np.ndarray) -> tuple[np.ndarray, int]:
-    """Return a contiguous uint32 copy of the 32-bit words and the f32 flag."""
+    """Return a contiguous unsigned copy of the key words (32 or 64 bits) and
+    the float flag."""
     a = np.asarray(a)
     if a.dtype == np.float32:
         return np.ascontiguousarray(a).view(np.uint32).copy(), 1
     if a.dtype == np.uint32:
         return np.ascontiguousarray(a).copy(), 0
-    raise TypeError(f"oracle sorts uint32 or float32 keys, got {a.dtype}")
+    if a.dtype == np.float64:
+        return np.ascontiguousarray(a).view(np.uint64).copy(), 1
+    if a.dtype == np.uint64:
+        return np.ascontiguousarray(a).copy(), 0
+    raise TypeError(f"oracle sorts uint32/uint64 or float32/float64 keys, got {a.dtype}")
 
 
 def _ptr(a):
     if a is None:
         return None
+    if a.dtype == np.uint64:
+        return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+
+
+def _wide(words: np.ndarray) -> bool:
+    return words.dtype == np.uint64
+
+
+def _floats(words: np.ndarray, is_f: int) -> np.ndarray:
+    if not is_f:
+        return words
+    return words.view(np.float64 if _wide(words) else np.float32)
 
 
 def sort(keys, vals=None, counted: bool = True):
@@ -138,10 +171,10 @@ def sort(keys, vals=None, counted: bool = True):
     if v is not None and v.shape != words.shape:
         raise ValueError("keys and vals differ in length")
     c = _Counters()
-    fn = lib.qmso_sort if counted else lib.qmso_fast_sort
+    pre = "qmso64_" if _wide(words) else "qmso_"
+    fn = getattr(lib, pre + ("sort" if counted else "fast_sort"))
     fn(_ptr(words), _ptr(v), words.size, is_f32, ctypes.byref(c))
-    out = words.view(np.float32) if is_f32 else words
-    return out, v, Counts(int(c.comparisons), int(c.moves))
+    return _floats(words, is_f32), v, Counts(int(c.comparisons), int(c.moves))
 
 
 def sqrt_threshold(n: int) -> int:
@@ -167,10 +200,10 @@ def sort_x(keys, vals=None, x_thresh: int | None = None, counted: bool = True):
     if xt < 2:
         raise ValueError("x_thresh must be at least 2")
     c = _Counters()
-    fn = lib.qmso_sort_x if counted else lib.qmso_fast_sort_x
+    pre = "qmso64_" if _wide(words) else "qmso_"
+    fn = getattr(lib, pre + ("sort_x" if counted else "fast_sort_x"))
     fn(_ptr(words), _ptr(v), words.size, is_f32, xt, ctypes.byref(c))
-    out = words.view(np.float32) if is_f32 else words
-    return out, v, Counts(int(c.comparisons), int(c.moves))
+    return _floats(words, is_f32), v, Counts(int(c.comparisons), int(c.moves))
 
 
 def clever_quicksort(keys, vals=None, counted: bool = True):
@@ -179,10 +212,10 @@ def clever_quicksort(keys, vals=None, counted: bool = True):
     words, is_f32 = _as_words(keys)
     v = None if vals is None else np.ascontiguousarray(vals, dtype=np.uint32).copy()
     c = _Counters()
-    fn = lib.qmso_clever_quicksort if counted else lib.qmso_fast_clever_quicksort
+    pre = "qmso64_" if _wide(words) else "qmso_"
+    fn = getattr(lib, pre + ("clever_quicksort" if counted else "fast_clever_quicksort"))
     fn(_ptr(words), _ptr(v), words.size, is_f32, ctypes.byref(c))
-    out = words.view(np.float32) if is_f32 else words
-    return out, v, Counts(int(c.comparisons), int(c.moves))
+    return _floats(words, is_f32), v, Counts(int(c.comparisons), int(c.moves))
 
 
 def sort_segments(keys, offsets, vals=None, counted: bool = False):
@@ -192,11 +225,11 @@ def sort_segments(keys, offsets, vals=None, counted: bool = False):
     off = np.ascontiguousarray(offsets, dtype=np.uint64)
     v = None if vals is None else np.ascontiguousarray(vals, dtype=np.uint32).copy()
     c = _Counters()
-    fn = lib.qmso_sort_segments if counted else lib.qmso_fast_sort_segments
+    pre = "qmso64_" if _wide(words) else "qmso_"
+    fn = getattr(lib, pre + ("sort_segments" if counted else "fast_sort_segments"))
     fn(_ptr(words), _ptr(v), off.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
        off.size - 1, is_f32, ctypes.byref(c))
-    out = words.view(np.float32) if is_f32 else words
-    return out, v, Counts(int(c.comparisons), int(c.moves))
+    return _floats(words, is_f32), v, Counts(int(c.comparisons), int(c.moves))
 
 
 def sort_inplace_fast(words: np.ndarray, is_f32: bool) -> None:

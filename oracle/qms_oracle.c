@@ -72,6 +72,12 @@
  *
  * Elements are (key, payload) when a payload array is given, keys only
  * otherwise; every assignment moves both, every comparison reads keys only.
+ *
+ * Key width: the file is compiled once with 32-bit keys (entry points
+ * qmso_*, qmso_fast_*) and once with 64-bit keys (QMSO_KEY_BITS = 64: the
+ * wide records of the Experiments section; qmso64_*, qmso64_fast_*, sort
+ * entry points only), the float flag then meaning IEEE-754 binary64 under
+ * the same total order (R6).
  */
 #include <stddef.h>
 #include <stdint.h>
@@ -81,10 +87,26 @@
 #define QMSO_COUNTING 1
 #endif
 
+#ifndef QMSO_KEY_BITS
+#define QMSO_KEY_BITS 32
+#endif
+
+#if QMSO_KEY_BITS == 64
+typedef uint64_t qkey_t;
+#define KEY_SIGN 0x8000000000000000ull
+#if QMSO_COUNTING
+#define QMSO_FN(name) qmso64_##name
+#else
+#define QMSO_FN(name) qmso64_fast_##name
+#endif
+#else
+typedef uint32_t qkey_t;
+#define KEY_SIGN 0x80000000u
 #if QMSO_COUNTING
 #define QMSO_FN(name) qmso_##name
 #else
 #define QMSO_FN(name) qmso_fast_##name
+#endif
 #endif
 
 typedef struct {
@@ -92,10 +114,10 @@ typedef struct {
     uint64_t moves;
 } qmso_counters;
 
-/* The array under sort: keys (already in comparable u32 form), optional
- * payloads, and the counters.  Positions are plain indices. */
+/* The array under sort: keys (already in comparable unsigned form),
+ * optional payloads, and the counters.  Positions are plain indices. */
 typedef struct {
-    uint32_t *k;
+    qkey_t *k;
     uint32_t *v;
     qmso_counters *c;
     size_t xt; /* X_THRESH of msort (2: pure Mergesort) */
@@ -128,7 +150,7 @@ static inline void assign(arr_t *a, size_t dst, size_t src)
 static inline void swap_ij(arr_t *a, size_t i, size_t j)
 {
     COUNT_MOV(a, 3);
-    uint32_t t = a->k[i];
+    qkey_t t = a->k[i];
     a->k[i] = a->k[j];
     a->k[j] = t;
     if (a->v) {
@@ -151,7 +173,7 @@ static void merge(arr_t *a, size_t begin1, size_t end1, size_t target,
                   size_t endtarget)
 {
     size_t i1 = begin1, i2 = target + (end1 - begin1), ires = target;
-    uint32_t temp_k = a->k[target];
+    qkey_t temp_k = a->k[target];
     uint32_t temp_v = a->v ? a->v[target] : 0;
     COUNT_MOV(a, 1);
     while (i1 != end1 && i2 != endtarget) {
@@ -288,14 +310,15 @@ static void qms_loop(arr_t *a, size_t lo, size_t hi)
     }
 }
 
-/* R6: IEEE-754 total order as an unsigned key, and its inverse */
-static inline uint32_t f32_bits_to_key(uint32_t u)
+/* R6: IEEE-754 total order as an unsigned key, and its inverse (binary32
+ * or binary64 by the key width) */
+static inline qkey_t f32_bits_to_key(qkey_t u)
 {
-    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+    return (u & KEY_SIGN) ? ~u : (u | KEY_SIGN);
 }
-static inline uint32_t key_to_f32_bits(uint32_t k)
+static inline qkey_t key_to_f32_bits(qkey_t k)
 {
-    return (k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k;
+    return (k & KEY_SIGN) ? (k & ~KEY_SIGN) : ~k;
 }
 
 static qmso_counters *counters_or_scratch(qmso_counters *c,
@@ -311,7 +334,7 @@ static qmso_counters *counters_or_scratch(qmso_counters *c,
 /* Sort keys (and payloads, if vals != NULL) in place.  is_f32 != 0: the
  * 32-bit words are IEEE-754 binary32 values ordered by R6.  counters may be
  * NULL; otherwise they are accumulated (not reset). */
-void QMSO_FN(sort)(uint32_t *keys, uint32_t *vals, size_t n, int is_f32,
+void QMSO_FN(sort)(qkey_t *keys, uint32_t *vals, size_t n, int is_f32,
                    qmso_counters *counters)
 {
     qmso_counters scratch;
@@ -324,7 +347,7 @@ void QMSO_FN(sort)(uint32_t *keys, uint32_t *vals, size_t n, int is_f32,
 }
 
 /* QuickMergeXsort with X = CleverQuicksort below x_thresh (>= 2; R8). */
-void QMSO_FN(sort_x)(uint32_t *keys, uint32_t *vals, size_t n, int is_f32,
+void QMSO_FN(sort_x)(qkey_t *keys, uint32_t *vals, size_t n, int is_f32,
                      size_t x_thresh, qmso_counters *counters)
 {
     qmso_counters scratch;
@@ -338,7 +361,7 @@ void QMSO_FN(sort_x)(uint32_t *keys, uint32_t *vals, size_t n, int is_f32,
 }
 
 /* X alone: CleverQuicksort of the whole input. */
-void QMSO_FN(clever_quicksort)(uint32_t *keys, uint32_t *vals, size_t n,
+void QMSO_FN(clever_quicksort)(qkey_t *keys, uint32_t *vals, size_t n,
                                int is_f32, qmso_counters *counters)
 {
     qmso_counters scratch;
@@ -351,7 +374,7 @@ void QMSO_FN(clever_quicksort)(uint32_t *keys, uint32_t *vals, size_t n,
 }
 
 /* Sort each segment [offsets[j], offsets[j+1]) independently. */
-void QMSO_FN(sort_segments)(uint32_t *keys, uint32_t *vals,
+void QMSO_FN(sort_segments)(qkey_t *keys, uint32_t *vals,
                             const uint64_t *offsets, size_t num_segments,
                             int is_f32, qmso_counters *counters)
 {
@@ -362,7 +385,7 @@ void QMSO_FN(sort_segments)(uint32_t *keys, uint32_t *vals,
     }
 }
 
-#if QMSO_COUNTING
+#if QMSO_COUNTING && QMSO_KEY_BITS == 32
 static int cmp_u32(const void *x, const void *y)
 {
     uint32_t a = *(const uint32_t *)x, b = *(const uint32_t *)y;
