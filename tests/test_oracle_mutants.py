@@ -30,8 +30,8 @@ MUTANTS = {
         "        ires++;\n        assign(a, from, ires); /* next target cell into the vacated cell */",
         "        assign(a, from, ires); /* next target cell into the vacated cell */\n        ires++;"),
     "total_order_positive_bit": (
-        "return (u & 0x80000000u) ? ~u : (u | 0x80000000u);",
-        "return (u & 0x80000000u) ? ~u : u;"),
+        "return (u & KEY_SIGN) ? ~u : (u | KEY_SIGN);",
+        "return (u & KEY_SIGN) ? ~u : u;"),
     "mom_upper_median": (
         "uint32_t p = med[(c - 1) / 2];",
         "uint32_t p = med[c / 2];"),
@@ -136,12 +136,13 @@ def test_mutant_is_caught(name, tmp_path):
     mutant_c = tmp_path / "mutant.c"
     mutant_c.write_text(src.replace(old, new))
     objs = []
-    for counting in (1, 0):
-        o = tmp_path / f"m{counting}.o"
-        subprocess.check_call(["gcc", "-std=c11", "-O1", "-fPIC", "-w",
-                               f"-DQMSO_COUNTING={counting}", "-c", str(mutant_c),
-                               "-o", str(o)])
-        objs.append(str(o))
+    for bits in (32, 64):
+        for counting in (1, 0):
+            o = tmp_path / f"m{bits}_{counting}.o"
+            subprocess.check_call(["gcc", "-std=c11", "-O1", "-fPIC", "-w",
+                                   f"-DQMSO_COUNTING={counting}", f"-DQMSO_KEY_BITS={bits}",
+                                   "-c", str(mutant_c), "-o", str(o)])
+            objs.append(str(o))
     lib = tmp_path / "libmutant.so"
     subprocess.check_call(["gcc", "-shared", "-o", str(lib)] + objs)
     script = f"ROOT = {ROOT!r}\nLIB = {str(lib)!r}\n" + CHECK
