@@ -16,6 +16,9 @@
  *   - Keys are 32-bit words: QMS_U32 compares them as unsigned integers;
  *     QMS_F32 compares IEEE-754 binary32 values by the IEEE total order
  *     (negative NaNs < -inf < ... < -0 < +0 < ... < +inf < positive NaNs).
+ *     qms_sort and qms_sort_batch also take 64-bit keys (the wide records of
+ *     the paper's Experiments section): QMS_U64 unsigned, QMS_F64 IEEE-754
+ *     binary64 by the same total order; 8-byte aligned, without payloads.
  *   - Payloads (qms_sort_pairs, qms_sort_batch with vals) are uint32 words in
  *     a separate array (structure of arrays); every move of a key moves its
  *     payload.  The sort is not stable: payload order among equal keys is
@@ -41,7 +44,7 @@
 extern "C" {
 #endif
 
-typedef enum { QMS_U32 = 0, QMS_F32 = 1 } qms_dtype;
+typedef enum { QMS_U32 = 0, QMS_F32 = 1, QMS_U64 = 2, QMS_F64 = 3 } qms_dtype;
 
 typedef enum {
     QMS_OK = 0,
@@ -58,9 +61,9 @@ typedef enum {
  * qms_sort -- sort n keys in place (Fig. 2 sort(); Sec. "QuickXsort and
  * QuickMergesort"; pivot rule of Theorem 1: median of the keys at lo,
  * lo + (hi-lo)/2 and hi-1).
- *   d_keys  device pointer to n 32-bit keys of type dt.
+ *   d_keys  device pointer to n keys of type dt (4 or 8 bytes each).
  *   n       number of keys; 0 and 1 are no-ops returning QMS_OK.
- *   dt      QMS_U32 or QMS_F32.
+ *   dt      QMS_U32, QMS_F32, QMS_U64 or QMS_F64.
  *   stream  HIP stream to run on.
  * Errors: QMS_ERR_INVALID for NULL with n > 0 or a pointer that is not
  * device memory; QMS_ERR_ALIGN; QMS_ERR_UNSUPPORTED for an unknown dt;
@@ -72,6 +75,7 @@ int qms_sort(void *d_keys, uint64_t n, int dt, hipStream_t stream);
  * qms_sort_pairs -- as qms_sort, carrying a uint32 payload per key (the
  * QuickXsort section's element moves apply to whole elements).
  *   d_vals  device pointer to n uint32 payloads, permuted with the keys.
+ *   dt      QMS_U32 or QMS_F32 (QMS_ERR_UNSUPPORTED for 64-bit keys).
  * Result: keys sorted; the multiset of (key, payload) pairs preserved.
  */
 int qms_sort_pairs(void *d_keys, uint32_t *d_vals, uint64_t n, int dt,
@@ -84,7 +88,8 @@ int qms_sort_pairs(void *d_keys, uint32_t *d_vals, uint64_t n, int dt,
  * partition / base-case / merge phases (one set of launches per phase for
  * the whole batch rather than per segment).
  *   d_keys       device keys of all segments.
- *   d_vals       device payloads, or NULL for keys only.
+ *   d_vals       device payloads, or NULL for keys only (64-bit keys:
+ *                NULL only).
  *   d_offsets    DEVICE array of num_segments + 1 uint64 offsets, non-
  *                decreasing, offsets[0] = 0 (empty segments allowed).
  *   h_offsets    optional HOST copy of the same offsets (NULL: the library
@@ -115,9 +120,10 @@ typedef struct qms_server qms_server;
 int qms_server_create(const qms_server_config *cfg, qms_server **out);
 
 /*
- * Submit one request: sort n keys of dtype dt at d_keys (device memory of
- * the server's device), in place.  *ticket_out receives a ticket.  Returns
- * QMS_ERR_BUDGET if n * 4 bytes alone exceed the budget (never admissible).
+ * Submit one request: sort n keys of dtype dt (QMS_U32 or QMS_F32) at d_keys
+ * (device memory of the server's device), in place.  *ticket_out receives a
+ * ticket.  Returns QMS_ERR_BUDGET if n * 4 bytes alone exceed the budget
+ * (never admissible), QMS_ERR_UNSUPPORTED for other dtypes.
  */
 int qms_server_submit(qms_server *srv, void *d_keys, uint64_t n, int dt,
                       uint64_t *ticket_out);
@@ -178,7 +184,8 @@ uint64_t qms_last_schedule(uint64_t *out, uint64_t max_rounds);
  * want the pivot alone.  d_keys: n 32-bit words on the current device
  * (read only); *pivot_out (host) gets the pivot's bits.  Synchronises
  * `stream`.  Errors: QMS_ERR_INVALID for NULL pointers or n < 3,
- * QMS_ERR_UNSUPPORTED for n >= 2^32 or an unknown dt, QMS_ERR_HIP.
+ * QMS_ERR_UNSUPPORTED for n >= 2^32 or a dt other than QMS_U32 / QMS_F32,
+ * QMS_ERR_HIP.
  */
 int qms_mom_pivot(const void *d_keys, uint64_t n, int dt, uint32_t *pivot_out,
                   hipStream_t stream);

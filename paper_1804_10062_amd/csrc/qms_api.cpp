@@ -46,7 +46,7 @@ static std::mutex g_ws_mutex;
 static std::map<std::pair<int, hipStream_t>, Workspace *> g_ws;
 
 static size_t ws_words() {
-    return 3ull * kCapTiles + 2ull * (kCapTiles + kCapSegs) + 2ull * kCapChunks + 15ull * kCapSplits +
+    return 3ull * kCapTiles + 2ull * (kCapTiles + kCapSegs) + 2ull * kCapChunks + 17ull * kCapSplits +
            4ull * kCapSegs + 256ull * kCapMoM;
 }
 
@@ -103,10 +103,12 @@ int get_workspace(int device, hipStream_t stream, Workspace **out) {
     w += kCapChunks;
     ws->splits = w;
     w += kCapSplits;
+    // run samples hold keys of either width: 2 words per entry (the offsets
+    // before them are even, so these arrays are 8-byte aligned)
     ws->samples[0] = w;
-    w += kCapSplits;
+    w += 2ull * kCapSplits;
     ws->samples[1] = w;
-    w += kCapSplits;
+    w += 2ull * kCapSplits;
     ws->bounds = w;
     w += 4ull * kCapSplits;
     ws->ends = w;
@@ -150,9 +152,10 @@ int release_workspaces() {
 }
 
 // ---- argument checks ---------------------------------------------------------------
-int check_device_ptr(const void *p, const char *what, int *device) {
-    if (((uintptr_t)p & 3u) != 0)
-        return set_error(QMS_ERR_ALIGN, std::string(what) + " is not 4-byte aligned");
+int check_device_ptr(const void *p, const char *what, int *device, uintptr_t align) {
+    if (((uintptr_t)p & (align - 1)) != 0)
+        return set_error(QMS_ERR_ALIGN, std::string(what) + " is not " + std::to_string(align) +
+                                            "-byte aligned");
     hipPointerAttribute_t a;
     std::memset(&a, 0, sizeof(a));
     hipError_t e = hipPointerGetAttributes(&a, p);
@@ -177,14 +180,16 @@ DeviceScope::~DeviceScope() {
 
 static int sort_entry(void *d_keys, uint32_t *d_vals, uint64_t n, int dt, hipStream_t stream,
                       bool pairs) {
-    if (dt != QMS_U32 && dt != QMS_F32) return set_error(QMS_ERR_UNSUPPORTED, "unknown dtype");
+    if (!dtype_known(dt)) return set_error(QMS_ERR_UNSUPPORTED, "unknown dtype");
+    if (pairs && dtype_wide(dt))
+        return set_error(QMS_ERR_UNSUPPORTED, "payloads are supported for 32-bit keys only");
     if (n <= 1) return QMS_OK;
     if (d_keys == nullptr || (pairs && d_vals == nullptr))
         return set_error(QMS_ERR_INVALID, "NULL pointer with n > 1");
     if (n >= (1ull << 32))
         return set_error(QMS_ERR_UNSUPPORTED, "n must be below 2^32");
     int dev = 0, dev2 = 0;
-    int rc = check_device_ptr(d_keys, "keys", &dev);
+    int rc = check_device_ptr(d_keys, "keys", &dev, dtype_wide(dt) ? 8 : 4);
     if (rc != QMS_OK) return rc;
     if (pairs) {
         rc = check_device_ptr(d_vals, "vals", &dev2);
@@ -277,7 +282,7 @@ int qms_mom_pivot(const void *d_keys, uint64_t n, int dt, uint32_t *pivot_out,
                   hipStream_t stream) {
     try {
         if (!d_keys || !pivot_out) return set_error(QMS_ERR_INVALID, "NULL keys or output");
-        if (dt != QMS_U32 && dt != QMS_F32) return set_error(QMS_ERR_UNSUPPORTED, "unknown dtype");
+        if (dt != QMS_U32 && dt != QMS_F32) return set_error(QMS_ERR_UNSUPPORTED, "the pivot entry point takes 32-bit keys (QMS_U32, QMS_F32)");
         if (n < 3) return set_error(QMS_ERR_INVALID, "the pivot needs n >= 3");
         if (n >= (1ull << 32)) return set_error(QMS_ERR_UNSUPPORTED, "n must be below 2^32");
         int dev = -1;

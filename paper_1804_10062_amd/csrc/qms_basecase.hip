@@ -35,10 +35,10 @@
 
 namespace qms {
 
-template <bool PAIRS>
+template <bool PAIRS, class K>
 struct TileElem;
 template <>
-struct TileElem<false> {
+struct TileElem<false, uint32_t> {
     using E = uint32_t;
     static constexpr int ITEMS = kBaseTileKeys / kSortThreads;  // 32
     __device__ static E make(uint32_t k, uint32_t) { return k; }
@@ -47,13 +47,23 @@ struct TileElem<false> {
     __device__ static uint32_t index(E) { return 0; }
 };
 template <>
-struct TileElem<true> {
+struct TileElem<true, uint32_t> {
     using E = uint64_t;
     static constexpr int ITEMS = kBaseTilePairs / kSortThreads;  // 16
     __device__ static E make(uint32_t k, uint32_t i) { return ((uint64_t)k << 32) | i; }
     __device__ static E pad(uint32_t i) { return (0xFFFFFFFFull << 32) | i; }
     __device__ static uint32_t key(E x) { return (uint32_t)(x >> 32); }
     __device__ static uint32_t index(E x) { return (uint32_t)x; }
+};
+// 64-bit keys without payload: the element is the order-mapped key itself.
+template <>
+struct TileElem<false, uint64_t> {
+    using E = uint64_t;
+    static constexpr int ITEMS = kBaseTilePairs / kSortThreads;  // 16
+    __device__ static E make(uint64_t k, uint32_t) { return k; }
+    __device__ static E pad(uint32_t) { return ~0ull; }
+    __device__ static uint64_t key(E x) { return x; }
+    __device__ static uint32_t index(E) { return 0; }
 };
 
 template <class E>
@@ -168,10 +178,12 @@ __device__ __forceinline__ uint32_t nat_idx(uint32_t e) {
 // Sort one tile.  sk/sv: the tile's cells in the source region, dk/dv: in
 // the destination region (equal in place); len <= the tile size.
 template <class O, bool PAIRS>
-__device__ __forceinline__ void tile_sort_block(uint32_t *sk, uint32_t *sv, uint32_t *dk,
-                                                uint32_t *dv, uint32_t len, uint32_t run,
-                                                bool swap, uint32_t *samples) {
-    using TE = TileElem<PAIRS>;
+__device__ __forceinline__ void tile_sort_block(typename O::K *sk, uint32_t *sv,
+                                                typename O::K *dk, uint32_t *dv, uint32_t len,
+                                                uint32_t run, bool swap,
+                                                typename O::K *samples) {
+    using K = typename O::K;
+    using TE = TileElem<PAIRS, K>;
     using E = typename TE::E;
     constexpr int ITEMS = TE::ITEMS;
     constexpr int NT = kSortThreads;
@@ -185,7 +197,7 @@ __device__ __forceinline__ void tile_sort_block(uint32_t *sk, uint32_t *sv, uint
     //    each thread then moves the buffer elements of exactly the source
     //    cells it has read into those cells
     {
-        uint32_t kv[ITEMS];
+        K kv[ITEMS];
 #pragma unroll
         for (int r = 0; r < ITEMS; ++r) kv[r] = ldg(sk + min((uint32_t)r * NT + tid, len - 1));
 #pragma unroll
@@ -199,7 +211,7 @@ __device__ __forceinline__ void tile_sort_block(uint32_t *sk, uint32_t *sv, uint
 #pragma unroll
             for (int r = 0; r < ITEMS; ++r) {
                 const uint32_t e = (uint32_t)r * NT + tid;
-                if (e < len) sp[e] = kv[r];
+                if (e < len) sp[e] = (uint32_t)kv[r];
             }
         }
         if (swap) {
@@ -217,7 +229,7 @@ __device__ __forceinline__ void tile_sort_block(uint32_t *sk, uint32_t *sv, uint
 #pragma unroll
                 for (int r = 0; r < ITEMS; ++r) {
                     const uint32_t e = (uint32_t)r * NT + tid;
-                    if (e < len) stg(sv + e, kv[r]);
+                    if (e < len) stg(sv + e, (uint32_t)kv[r]);
                 }
             }
         }
@@ -276,7 +288,7 @@ __device__ __forceinline__ void tile_sort_block(uint32_t *sk, uint32_t *sv, uint
                 r[i] = keep_side(r[i], s[(uint32_t)i * NT + pt], keep_min, bound);
         }
         // partners in other lanes of the wave
-        if constexpr (!PAIRS) {
+        if constexpr (sizeof(E) == 4) {
             switch (j / ITEMS) {  // lane masks j / ITEMS down to 1
             case 32:
                 lane_step_u32<32>(r, lane);
@@ -368,12 +380,14 @@ __device__ __forceinline__ void tile_sort_block(uint32_t *sk, uint32_t *sv, uint
 }
 
 // One workgroup per base tile of every Mergesort task in the table.
-// Samples: one word per kMergeTile keys of each task, at the task's merge
-// split offset (the base tile is a multiple of kMergeTile).
+// Samples: one key per kMergeTile keys of each task, at the task's merge
+// split offset (the base tile is a multiple of kMergeTile).  64-bit keys use
+// the 8,192-element tile of key/payload pairs.
 template <class O, bool PAIRS>
 __global__ __launch_bounds__(kSortThreads) void k_tile_sort(TaskRef<SortSeg> tasks,
-                                                            uint32_t *samples) {
-    constexpr uint32_t T = PAIRS ? kBaseTilePairs : kBaseTileKeys;
+                                                            typename O::K *samples) {
+    using K = typename O::K;
+    constexpr uint32_t T = (PAIRS || sizeof(K) == 8) ? kBaseTilePairs : kBaseTileKeys;
     uint32_t t, a;
     const SortSeg g = task_of(tasks, blockIdx.x, &t, &a);
     const uint32_t t0 = t * T;
@@ -384,7 +398,8 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_sort(TaskRef<SortSeg> tas
     // runs of g.w0 keys (a power of two in [kMergeTile, T]; clamped so that
     // a malformed task still runs a valid network)
     const uint32_t run = g.w0 >= T ? T : (g.w0 <= (uint32_t)kMergeTile ? (uint32_t)kMergeTile : g.w0);
-    tile_sort_block<O, PAIRS>(g.keys + src, PAIRS ? g.vals + src : nullptr, g.keys + dst,
+    K *keys = (K *)g.keys;
+    tile_sort_block<O, PAIRS>(keys + src, PAIRS ? g.vals + src : nullptr, keys + dst,
                               PAIRS ? g.vals + dst : nullptr, len, run, swap,
                               samples + g.split_off + t0 / kMergeTile);
 }
@@ -395,17 +410,26 @@ static hipError_t tile_sort_t(const TaskRef<SortSeg> &tasks, uint32_t tiles, dou
     if (tiles == 0) return hipSuccess;
     ProfScope prof(st, K_TILE_SORT, bytes);
     hipLaunchKernelGGL((k_tile_sort<O, PAIRS>), dim3(tiles), dim3(kSortThreads), 0, st, tasks,
-                       ws.samples[0]);
+                       (typename O::K *)ws.samples[0]);
     return hipGetLastError();
 }
 
 hipError_t launch_tile_sort(int dt, bool pairs, const TaskRef<SortSeg> &tasks, uint32_t tiles,
                             double bytes, const Workspace &ws, hipStream_t st) {
-    if (dt == 1)
+    switch (dt) {
+    case 0:
+        return pairs ? tile_sort_t<OrdU32, true>(tasks, tiles, bytes, ws, st)
+                     : tile_sort_t<OrdU32, false>(tasks, tiles, bytes, ws, st);
+    case 1:
         return pairs ? tile_sort_t<OrdF32, true>(tasks, tiles, bytes, ws, st)
                      : tile_sort_t<OrdF32, false>(tasks, tiles, bytes, ws, st);
-    return pairs ? tile_sort_t<OrdU32, true>(tasks, tiles, bytes, ws, st)
-                 : tile_sort_t<OrdU32, false>(tasks, tiles, bytes, ws, st);
+    case 2:
+        return pairs ? hipErrorInvalidValue : tile_sort_t<OrdU64, false>(tasks, tiles, bytes, ws, st);
+    case 3:
+        return pairs ? hipErrorInvalidValue : tile_sort_t<OrdF64, false>(tasks, tiles, bytes, ws, st);
+    default:
+        return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace qms

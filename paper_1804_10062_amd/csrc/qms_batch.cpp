@@ -13,12 +13,14 @@ extern "C" int qms_sort_batch(void *d_keys, uint32_t *d_vals, const uint64_t *d_
                               const uint64_t *h_offsets, uint32_t num_segments, int dt,
                               hipStream_t stream) {
     try {
-        if (dt != QMS_U32 && dt != QMS_F32) return set_error(QMS_ERR_UNSUPPORTED, "unknown dtype");
+        if (!dtype_known(dt)) return set_error(QMS_ERR_UNSUPPORTED, "unknown dtype");
+        if (d_vals && dtype_wide(dt))
+            return set_error(QMS_ERR_UNSUPPORTED, "payloads are supported for 32-bit keys only");
         if (num_segments == 0) return QMS_OK;
         if (d_keys == nullptr || d_offsets == nullptr)
             return set_error(QMS_ERR_INVALID, "NULL keys or offsets");
         int dev = 0, dev2 = 0;
-        int rc = check_device_ptr(d_keys, "keys", &dev);
+        int rc = check_device_ptr(d_keys, "keys", &dev, dtype_wide(dt) ? 8 : 4);
         if (rc != QMS_OK) return rc;
         rc = check_device_ptr(d_offsets, "offsets", &dev2);
         if (rc != QMS_OK) return rc;
@@ -42,13 +44,16 @@ extern "C" int qms_sort_batch(void *d_keys, uint32_t *d_vals, const uint64_t *d_
         Workspace *ws = nullptr;
         rc = get_workspace(dev, stream, &ws);
         if (rc != QMS_OK) return rc;
-        uint32_t *keys = (uint32_t *)d_keys;
+        // segment j starts off[j] keys in, keys of 4 or 8 bytes
+        const size_t kb = dtype_wide(dt) ? 8 : 4;
+        char *keys = (char *)d_keys;
         std::vector<HostSeg> segs;
         segs.reserve(num_segments);
         for (uint32_t j = 0; j < num_segments; ++j) {
             const uint64_t n = off[j + 1] - off[j];
             if (n <= 1) continue;
-            segs.push_back(HostSeg{keys + off[j], d_vals ? d_vals + off[j] : nullptr, n});
+            segs.push_back(HostSeg{(uint32_t *)(keys + kb * off[j]),
+                                   d_vals ? d_vals + off[j] : nullptr, n});
         }
         return sort_segments(dt, d_vals != nullptr, segs.data(), segs.size(), *ws, stream, false);
     } catch (...) {

@@ -162,9 +162,12 @@ __device__ __forceinline__ T task_of(const TaskRef<T> &r, uint32_t g, uint32_t *
 }
 
 // ---- key order ----------------------------------------------------------------
-// Keys are compared as unsigned 32-bit integers after an order map applied in
-// registers on load (and undone on store).
+// Keys are compared as unsigned integers of their own width (K: 32 or 64
+// bits) after an order map applied in registers on load (and undone on
+// store).  The policy carries the key type, so kernels templated on it read
+// and write keys of the right width.
 struct OrdU32 {
+    using K = uint32_t;
     __device__ __forceinline__ static uint32_t ord(uint32_t x) { return x; }
     __device__ __forceinline__ static uint32_t unord(uint32_t x) { return x; }
 };
@@ -172,6 +175,7 @@ struct OrdU32 {
 // non-negative values get the sign bit set; unsigned order of the result is
 // the total order (-NaN < -inf < ... < -0 < +0 < ... < +inf < +NaN).
 struct OrdF32 {
+    using K = uint32_t;
     __device__ __forceinline__ static uint32_t ord(uint32_t u) {
         return u ^ ((uint32_t)((int32_t)u >> 31) | 0x80000000u);
     }
@@ -179,13 +183,34 @@ struct OrdF32 {
         return k ^ ((uint32_t)((int32_t)(~k) >> 31) | 0x80000000u);
     }
 };
+// 64-bit keys: unsigned, and IEEE-754 binary64 by the same total order.
+struct OrdU64 {
+    using K = uint64_t;
+    __device__ __forceinline__ static uint64_t ord(uint64_t x) { return x; }
+    __device__ __forceinline__ static uint64_t unord(uint64_t x) { return x; }
+};
+struct OrdF64 {
+    using K = uint64_t;
+    __device__ __forceinline__ static uint64_t ord(uint64_t u) {
+        return u ^ ((uint64_t)((int64_t)u >> 63) | 0x8000000000000000ull);
+    }
+    __device__ __forceinline__ static uint64_t unord(uint64_t k) {
+        return k ^ ((uint64_t)((int64_t)(~k) >> 63) | 0x8000000000000000ull);
+    }
+};
+// The largest key of a width (the merge sentinel, the base case's padding).
+template <class K>
+__device__ __forceinline__ constexpr K key_max() { return ~K(0); }
 
 // ---- global memory access -------------------------------------------------------
 // Pointers taken from task tables are generic; accessing them through the
 // global address space lets the compiler emit global_load/store (not flat).
 typedef __attribute__((address_space(1))) uint32_t g_u32;
+typedef __attribute__((address_space(1))) uint64_t g_u64;
 __device__ __forceinline__ uint32_t ldg(const uint32_t *p) { return *(const g_u32 *)p; }
 __device__ __forceinline__ void stg(uint32_t *p, uint32_t v) { *(g_u32 *)p = v; }
+__device__ __forceinline__ uint64_t ldg(const uint64_t *p) { return *(const g_u64 *)p; }
+__device__ __forceinline__ void stg(uint64_t *p, uint64_t v) { *(g_u64 *)p = v; }
 
 // ---- wave and block primitives -------------------------------------------------
 __device__ __forceinline__ int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
@@ -245,11 +270,16 @@ __device__ __forceinline__ T block_sum(T v, T *tmp) {
 __device__ __forceinline__ uint32_t median3(uint32_t a, uint32_t b, uint32_t c) {
     return max(min(a, b), min(max(a, b), c));
 }
+__device__ __forceinline__ uint64_t median3(uint64_t a, uint64_t b, uint64_t c) {
+    const uint64_t lo = a < b ? a : b, hi = a < b ? b : a;
+    const uint64_t m = hi < c ? hi : c;
+    return lo > m ? lo : m;
+}
 
 // Pivot of the range [lo, hi): median of the keys at lo, lo + s/2 and hi - 1.
 template <class O>
-__device__ __forceinline__ uint32_t pivot_of(const uint32_t *keys, uint64_t lo,
-                                             uint64_t hi) {
+__device__ __forceinline__ typename O::K pivot_of(const typename O::K *keys, uint64_t lo,
+                                                  uint64_t hi) {
     const uint64_t s = hi - lo;
     return median3(O::ord(keys[lo]), O::ord(keys[lo + s / 2]),
                    O::ord(keys[hi - 1]));

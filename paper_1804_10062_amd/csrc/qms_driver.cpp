@@ -116,12 +116,15 @@ const std::vector<std::array<uint64_t, kScheduleWords>> &last_schedule() { retur
 // Sort a group of segments (count <= kCapSegs, total keys < 2^32).
 static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
                       hipStream_t st, bool log, const Tuning &tune) {
-    const double w = pairs ? 2.0 : 1.0;
+    // 64-bit keys: twice the bytes per element, the 8,192-element base tile
+    // of key/payload pairs and 2-way merge passes, as for pairs
+    const bool wide = dtype_wide(dt);
+    const double w = (pairs || wide) ? 2.0 : 1.0;
     // T0: the base case's workgroup tile; ranges of at most T0 keys are
     // finished in place by one workgroup.  R0: the run width at which each
     // round's Mergesort stops and calls the base case X (QuickMergeXsort's
     // X_THRESH, a tunable), so that a workgroup tile holds T0 / R0 runs.
-    const uint32_t T0 = pairs ? kBaseTilePairs : kBaseTileKeys;
+    const uint32_t T0 = (pairs || wide) ? kBaseTilePairs : kBaseTileKeys;
     const uint32_t R0 = std::min(T0, tune.base_tile);
     std::vector<uint32_t> active, next;
     // ranges of at most T0 keys, sorted in place by the base case.  A
@@ -218,7 +221,7 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
                 const uint64_t nch = chunk_count(X, s, tune.chunk_span);
                 ca[a + 1] = ca[a] + (uint32_t)nch;
                 wa[a + 1] = wa[a] + (uint32_t)(nch > 1 ? 2 * (nch - 1) : 0);
-                if (X > 0) swap_bytes += 4.0 * (double)s + 2.0 * 4.0 * w * (double)X;
+                if (X > 0) swap_bytes += (wide ? 8.0 : 4.0) * (double)s + 2.0 * 4.0 * w * (double)X;
                 // pass B pairs are at most min(#==, #>); size its grids for that
                 const uint64_t gt = s - c_lt - c_eq;
                 const uint64_t xb = std::min(c_eq, gt);
@@ -316,7 +319,7 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
         // at l belong to the tasks with L > l and L = l (mod 2), the 2-way
         // first passes (l = 0) to the odd ones; for key/payload tasks every
         // task with L > l runs a 2-way pass at l
-        const bool two = pairs || tune.merge_ways == 2;
+        const bool two = pairs || wide || tune.merge_ways == 2;
         const bool by_parity = !two;
         std::stable_sort(tasks.begin(), tasks.end(), [&](const SortSeg &x, const SortSeg &y) {
             if (by_parity && (x.L & 1u) != (y.L & 1u)) return (x.L & 1u) < (y.L & 1u);

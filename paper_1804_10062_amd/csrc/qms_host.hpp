@@ -28,7 +28,10 @@ Tuning current_tuning();
 
 int set_error(int code, const std::string &msg);
 int hip_error(hipError_t e, const char *where);
-int check_device_ptr(const void *p, const char *what, int *device);
+int check_device_ptr(const void *p, const char *what, int *device, uintptr_t align = 4);
+// dtype codes of qms.h: 32-bit (QMS_U32, QMS_F32) or 64-bit (QMS_U64, QMS_F64)
+inline bool dtype_known(int dt) { return dt >= 0 && dt <= 3; }
+inline bool dtype_wide(int dt) { return dt == 2 || dt == 3; }
 int get_workspace(int device, hipStream_t stream, Workspace **out);
 int release_workspaces();
 int release_workspace(int device, hipStream_t stream);

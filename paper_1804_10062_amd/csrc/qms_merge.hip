@@ -156,8 +156,9 @@ __device__ __forceinline__ uint64_t group_count_before(const uint32_t *Y, const 
 template <class O, bool PAIRS, bool BOUNDS>
 __global__ __launch_bounds__(kBlock) void k_merge_split(TaskRef<SortSeg> tasks, uint32_t level,
                                                         uint32_t total, uint32_t *splits,
-                                                        const uint32_t *samples,
+                                                        const typename O::K *samples,
                                                         uint32_t *bounds) {
+    using K = typename O::K;
     constexpr uint64_t S = kMergeTile;
     constexpr uint32_t GPT = BOUNDS ? 2 : 1;  // lane groups per tile
     const uint32_t gid = blockIdx.x * kBlock + threadIdx.x;
@@ -170,10 +171,10 @@ __global__ __launch_bounds__(kBlock) void k_merge_split(TaskRef<SortSeg> tasks, 
     level_regions(g, level, &src, &dst);
     const uint64_t W = (uint64_t)g.w0 << level;
     const MergeTileGeom geo = merge_geom(g.m, W, tile);
-    const uint32_t *A = g.keys + src + geo.pb;
-    const uint32_t *B = A + W;
-    const uint32_t *As = samples + g.split_off + geo.pb / S;
-    const uint32_t *Bs = As + W / S;
+    const K *A = (const K *)g.keys + src + geo.pb;
+    const K *B = A + W;
+    const K *As = samples + g.split_off + geo.pb / S;
+    const K *Bs = As + W / S;
     const uint64_t d = geo.d0, nA = geo.lenA, nB = geo.lenB;
     uint64_t lo = d > nB ? d - nB : 0;
     uint64_t hi = d < nA ? d : nA;
@@ -192,7 +193,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_split(TaskRef<SortSeg> tasks, 
     if (active && gid % kSplitLanes == 0 && half == 0) splits[g.split_off + tile] = (uint32_t)c;
     if constexpr (BOUNDS) {
         // the element at output d of the pair (d < nA + nB for a tile)
-        uint32_t x = 0;
+        K x = 0;
         if (active) {
             const bool fromA =
                 c < nA && (d - c >= nB || O::ord(ldg(A + c)) <= O::ord(ldg(B + (d - c))));
@@ -281,11 +282,11 @@ __global__ __launch_bounds__(kBlock) void k_merge4_ends(TaskRef<SortSeg> tasks, 
 // and a select.
 // With `from`, also the LDS index each output was read from (to carry
 // payloads along).
-template <int N, bool FROM = false>
-__device__ __forceinline__ void merge_lds(const uint32_t *sk, uint32_t x0, uint32_t nx,
-                                          uint32_t y0, uint32_t ny, uint32_t d,
-                                          uint32_t (&out)[N], uint32_t *from = nullptr) {
-    const uint32_t *X = sk + x0, *Y = sk + y0;
+template <int N, bool FROM = false, class T = uint32_t>
+__device__ __forceinline__ void merge_lds(const T *sk, uint32_t x0, uint32_t nx, uint32_t y0,
+                                          uint32_t ny, uint32_t d, T (&out)[N],
+                                          uint32_t *from = nullptr) {
+    const T *X = sk + x0, *Y = sk + y0;
     uint32_t lo = d > ny ? d - ny : 0, hi = d < nx ? d : nx;
     while (lo < hi) {
         const uint32_t mid = (lo + hi) >> 1;
@@ -293,10 +294,10 @@ __device__ __forceinline__ void merge_lds(const uint32_t *sk, uint32_t x0, uint3
         else hi = mid;
     }
     uint32_t i = lo;
-    const uint32_t *Yd = Y + d;  // Y[j] for j = d + q - i
+    const T *Yd = Y + d;  // Y[j] for j = d + q - i
 #pragma unroll
     for (int q = 0; q < N; ++q) {
-        const uint32_t kx = X[i], ky = Yd[q - (int)i];
+        const T kx = X[i], ky = Yd[q - (int)i];
         const bool takeX = i < nx && kx <= ky;
         out[q] = takeX ? kx : ky;
         if constexpr (FROM) from[q] = takeX ? x0 + i : y0 + d + q - i;
@@ -457,13 +458,14 @@ __attribute__((amdgpu_waves_per_eu(QMS_MERGE4_WPE, QMS_MERGE4_WPE))) void k_merg
 }
 
 template <class O, bool PAIRS>
-__device__ __forceinline__ void merge_block(uint32_t *S, uint32_t *SV, uint32_t *D,
+__device__ __forceinline__ void merge_block(typename O::K *S, uint32_t *SV, typename O::K *D,
                                             uint32_t *DV, uint64_t m, uint64_t W,
                                             uint64_t tile, const uint32_t *splits,
-                                            uint32_t *samples_out) {
+                                            typename O::K *samples_out) {
+    using K = typename O::K;
     // the two run slices back to back, then the sentinel merge_lds needs
     // (at cnt) and slack for the reads of threads whose outputs run past cnt
-    __shared__ uint32_t sk[kMergeTile + 1 + kMerge4Slack];
+    __shared__ K sk[kMergeTile + 1 + kMerge4Slack];
     __shared__ uint32_t sv[PAIRS ? kMergeTile : 1];
     const uint32_t tid = threadIdx.x;
 
@@ -479,7 +481,7 @@ __device__ __forceinline__ void merge_block(uint32_t *S, uint32_t *SV, uint32_t 
 
     // the destination window's current contents (buffer elements)
     // clamped, unconditional loads so that all of them are in flight together
-    uint32_t oldk[kMergePerThread];
+    K oldk[kMergePerThread];
     uint32_t oldv[PAIRS ? kMergePerThread : 1];
 #pragma unroll
     for (int q = 0; q < kMergePerThread; ++q) {
@@ -490,7 +492,7 @@ __device__ __forceinline__ void merge_block(uint32_t *S, uint32_t *SV, uint32_t 
     const uint64_t j0 = d0 - i0, j1 = d1 - i1;
     const uint32_t na = (uint32_t)(i1 - i0);
     const uint32_t nb = (uint32_t)(j1 - j0);
-    uint32_t nk[kMergePerThread];
+    K nk[kMergePerThread];
     uint32_t nv[PAIRS ? kMergePerThread : 1];
 #pragma unroll
     for (int q = 0; q < kMergePerThread; ++q) {
@@ -507,19 +509,19 @@ __device__ __forceinline__ void merge_block(uint32_t *S, uint32_t *SV, uint32_t 
             if constexpr (PAIRS) sv[e] = nv[q];
         }
     }
-    if (tid == 0) sk[cnt] = 0xffffffffu;
+    if (tid == 0) sk[cnt] = key_max<K>();
     __syncthreads();
 
     // each thread merges NM consecutive outputs of the tile (one more than
     // the tile needs: an odd count keeps the lanes' diagonals on distinct
     // LDS banks)
     constexpr int NM = kMergePerThread + kMergeOdd;
-    uint32_t ok[NM];
+    K ok[NM];
     uint32_t from[PAIRS ? NM : 1];
     uint32_t ov[PAIRS ? NM : 1];
     const uint32_t diag = tid * NM;
     if (diag < cnt) {
-        merge_lds<NM, PAIRS>(sk, 0, na, na, nb, diag, ok, from);
+        merge_lds<NM, PAIRS, K>(sk, 0, na, na, nb, diag, ok, from);
         if constexpr (PAIRS) {
 #pragma unroll
             for (int q = 0; q < NM; ++q) ov[q] = sv[min(from[q], cnt - 1)];
@@ -554,13 +556,15 @@ __device__ __forceinline__ void merge_block(uint32_t *S, uint32_t *SV, uint32_t 
 template <class O, bool PAIRS>
 __global__ __launch_bounds__(kBlock) void k_merge(TaskRef<SortSeg> tasks, uint32_t level,
                                                   const uint32_t *splits,
-                                                  uint32_t *samples_out) {
+                                                  typename O::K *samples_out) {
+    using K = typename O::K;
     uint32_t tile, a;
     const SortSeg g = task_of(tasks, blockIdx.x, &tile, &a);
     if (tile * (uint64_t)kMergeTile >= g.m) return;
     uint32_t src, dst;
     level_regions(g, level, &src, &dst);
-    merge_block<O, PAIRS>(g.keys + src, PAIRS ? g.vals + src : nullptr, g.keys + dst,
+    K *keys = (K *)g.keys;
+    merge_block<O, PAIRS>(keys + src, PAIRS ? g.vals + src : nullptr, keys + dst,
                           PAIRS ? g.vals + dst : nullptr, g.m, (uint64_t)g.w0 << level,
                           tile, splits + g.split_off, samples_out + g.split_off);
 }
@@ -569,11 +573,12 @@ template <class O, bool PAIRS>
 static hipError_t merge_t(const TaskRef<SortSeg> &tasks, uint32_t level, uint32_t pass,
                           bool four_way, uint32_t tiles, double bytes, const Workspace &ws,
                           hipStream_t st) {
+    using K = typename O::K;
     if (tiles == 0) return hipSuccess;
     // pass p searches the samples written by pass p - 1 (or the base case)
     // and writes the other array
-    const uint32_t *smp_in = ws.samples[pass & 1];
-    uint32_t *smp_out = ws.samples[(pass + 1) & 1];
+    const K *smp_in = (const K *)ws.samples[pass & 1];
+    K *smp_out = (K *)ws.samples[(pass + 1) & 1];
     const uint32_t sgrid = (uint32_t)(((uint64_t)tiles * kSplitLanes + kBlock - 1) / kBlock);
     if (!four_way) {
         {
@@ -589,7 +594,7 @@ static hipError_t merge_t(const TaskRef<SortSeg> &tasks, uint32_t level, uint32_
         }
         return hipGetLastError();
     }
-    if constexpr (!PAIRS) {
+    if constexpr (!PAIRS && sizeof(K) == 4) {  // 4-way passes: 32-bit keys only
         {
             ProfScope prof(st, K_MERGE_SPLIT, 0.0);
             hipLaunchKernelGGL((k_merge_split<O, false, true>), dim3(2 * sgrid), dim3(kBlock), 0,
@@ -611,11 +616,22 @@ static hipError_t merge_t(const TaskRef<SortSeg> &tasks, uint32_t level, uint32_
 hipError_t launch_merge_pass(int dt, bool pairs, const TaskRef<SortSeg> &tasks, uint32_t level,
                              uint32_t pass, bool four_way, uint32_t tiles, double bytes,
                              const Workspace &ws, hipStream_t st) {
-    if (dt == 1)
+    switch (dt) {
+    case 0:
+        return pairs ? merge_t<OrdU32, true>(tasks, level, pass, four_way, tiles, bytes, ws, st)
+                     : merge_t<OrdU32, false>(tasks, level, pass, four_way, tiles, bytes, ws, st);
+    case 1:
         return pairs ? merge_t<OrdF32, true>(tasks, level, pass, four_way, tiles, bytes, ws, st)
                      : merge_t<OrdF32, false>(tasks, level, pass, four_way, tiles, bytes, ws, st);
-    return pairs ? merge_t<OrdU32, true>(tasks, level, pass, four_way, tiles, bytes, ws, st)
-                 : merge_t<OrdU32, false>(tasks, level, pass, four_way, tiles, bytes, ws, st);
+    case 2:  // 64-bit keys: key-only, 2-way passes
+        return pairs ? hipErrorInvalidValue
+                     : merge_t<OrdU64, false>(tasks, level, pass, four_way, tiles, bytes, ws, st);
+    case 3:
+        return pairs ? hipErrorInvalidValue
+                     : merge_t<OrdF64, false>(tasks, level, pass, four_way, tiles, bytes, ws, st);
+    default:
+        return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace qms

@@ -54,20 +54,20 @@ template <class O>
 __global__ __launch_bounds__(kBlock) void k_part_count(TaskRef<PartSeg> tasks, uint32_t TP,
                                                        uint32_t *cnt_lt, uint32_t *cnt_eq,
                                                        uint64_t *meta) {
+    using K = typename O::K;
     __shared__ uint32_t tmp[kWaves + 1];
     uint32_t t, a;
     const PartSeg g = task_of(tasks, blockIdx.x, &t, &a);
-    const uint32_t *keys = g.keys + g.lo;
-    const uint32_t p = (g.flags & kPivotMoM)
-                           ? (uint32_t)meta[(uint64_t)g.slot * M_COUNT + M_PIVOT]
-                           : pivot_of<O>(keys, 0, g.s);
+    const K *keys = (const K *)g.keys + g.lo;
+    const K p = (g.flags & kPivotMoM) ? (K)meta[(uint64_t)g.slot * M_COUNT + M_PIVOT]
+                                      : pivot_of<O>(keys, 0, g.s);
     const uint64_t ts = (uint64_t)t * TP;
     const uint64_t te = ts + TP < g.s ? ts + TP : g.s;
     uint32_t lt = 0, eq = 0;
     for (uint64_t b = ts; b < te; b += kPartSub) {
         // clamped, unconditional loads (all in flight together); the tail
         // positions are masked out of the counts
-        uint32_t k[kPartItems];
+        K k[kPartItems];
 #pragma unroll
         for (int q = 0; q < kPartItems; ++q) {
             const uint64_t pos = b + (uint64_t)q * kBlock + threadIdx.x;
@@ -76,7 +76,7 @@ __global__ __launch_bounds__(kBlock) void k_part_count(TaskRef<PartSeg> tasks, u
 #pragma unroll
         for (int q = 0; q < kPartItems; ++q) {
             const uint64_t pos = b + (uint64_t)q * kBlock + threadIdx.x;
-            const uint32_t x = O::ord(k[q]);
+            const K x = O::ord(k[q]);
             const bool in = pos < te;
             lt += in && x < p;
             eq += in && x == p;
@@ -93,13 +93,14 @@ __global__ __launch_bounds__(kBlock) void k_part_count(TaskRef<PartSeg> tasks, u
 // count keys with ord(k) < p and == p in [a, b) (a < b) with the whole
 // block, four clamped loads per thread in flight
 template <class O>
-__device__ __forceinline__ void block_count_range(const uint32_t *keys, uint64_t a, uint64_t b,
-                                                  uint32_t p, uint32_t *lt_out,
+__device__ __forceinline__ void block_count_range(const typename O::K *keys, uint64_t a,
+                                                  uint64_t b, typename O::K p, uint32_t *lt_out,
                                                   uint32_t *eq_out, uint32_t *tmp) {
+    using K = typename O::K;
     uint32_t lt = 0, eq = 0;
     const uint64_t nth = blockDim.x;
     for (uint64_t base = a; base < b; base += 4 * nth) {
-        uint32_t k[4];
+        K k[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const uint64_t pos = base + q * nth + threadIdx.x;
@@ -108,7 +109,7 @@ __device__ __forceinline__ void block_count_range(const uint32_t *keys, uint64_t
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             const uint64_t pos = base + q * nth + threadIdx.x;
-            const uint32_t x = O::ord(k[q]);
+            const K x = O::ord(k[q]);
             lt += pos < b && x < p;
             eq += pos < b && x == p;
         }
@@ -246,8 +247,9 @@ __global__ __launch_bounds__(NTH) void k_part_scan_a(TaskRef<PartSeg> tasks, uin
     constexpr uint32_t C = (uint32_t)NTH * PER;
     __shared__ uint32_t tmp[NTH / kWave + 1];
     __shared__ ScanStage<NTH> stage;
+    using K = typename O::K;
     const PartSeg g = seg_by_index(tasks, blockIdx.x);
-    const uint32_t *keys = g.keys + g.lo;
+    const K *keys = (const K *)g.keys + g.lo;
     uint32_t *P = cnt_lt_all + g.tile_off;
     const uint32_t *cnt_eq = cnt_eq_all + g.tile_off;
     uint32_t *preL = preL_all + g.tile_off + g.slot;
@@ -257,8 +259,7 @@ __global__ __launch_bounds__(NTH) void k_part_scan_a(TaskRef<PartSeg> tasks, uin
     const uint32_t nt = g.nt;
     const uint64_t s = g.s;
     const uint32_t tid = threadIdx.x;
-    const uint32_t p = (g.flags & kPivotMoM) ? (uint32_t)meta[M_PIVOT]
-                                                    : pivot_of<O>(keys, 0, s);
+    const K p = (g.flags & kPivotMoM) ? (K)meta[M_PIVOT] : pivot_of<O>(keys, 0, s);
     // pass 1
     uint32_t carry = 0, seq = 0;
     for (uint32_t c0 = 0; c0 < nt; c0 += C) {
@@ -395,13 +396,14 @@ __global__ __launch_bounds__(NTH) void k_part_scan_b(TaskRef<PartSeg> tasks, uin
         if (threadIdx.x == 0) meta[M_XB] = 0;
         return;
     }
-    const uint32_t *keys = g.keys + g.lo;
+    using K = typename O::K;
+    const K *keys = (const K *)g.keys + g.lo;
     const uint32_t *cnt_eq = cnt_eq_all + g.tile_off;
     const uint32_t *eqmv = eqmv_all + g.tile_off;
     uint32_t *preL = preL_all + g.tile_off + g.slot;
     uint32_t *preR = preR_all + g.tile_off + g.slot;
     const uint32_t nt = g.nt;
-    const uint32_t p = (uint32_t)meta[M_PIVOT];
+    const K p = (K)meta[M_PIVOT];
     const uint64_t tb = meta[M_TB];
     const uint32_t eq_part = (uint32_t)meta[M_EQPART];
     const uint64_t tb2 = b2 / TP;
@@ -467,8 +469,8 @@ __device__ __forceinline__ PassGeom pass_geom(const uint64_t *meta, uint64_t s) 
     }
     return g;
 }
-template <int PASS>
-__device__ __forceinline__ bool belongs_left(uint32_t k, uint32_t p) {
+template <int PASS, class K>
+__device__ __forceinline__ bool belongs_left(K k, K p) {
     return PASS == 0 ? k < p : k <= p;
 }
 
@@ -495,8 +497,9 @@ __global__ __launch_bounds__(kBlock) void k_part_split(TaskRef<PartSeg> tasks, u
     const uint64_t j = 1 + w / 2;
     const int side = (int)(w & 1);
     if (j >= nch) return;
-    const uint32_t *keys = g.keys + g.lo;
-    const uint32_t p = (uint32_t)meta[M_PIVOT];
+    using K = typename O::K;
+    const K *keys = (const K *)g.keys + g.lo;
+    const K p = (K)meta[M_PIVOT];
     const uint64_t s = g.s;
     const PassGeom geo = pass_geom<PASS>(meta, s);
     uint32_t *sp = (side ? spR_all : spL_all) + g.chunk_off;
@@ -514,7 +517,7 @@ __global__ __launch_bounds__(kBlock) void k_part_split(TaskRef<PartSeg> tasks, u
     // ballots
     constexpr int kQ = 16;
     for (uint64_t base = x0; base < x1; base += kWave * kQ) {
-        uint32_t kv[kQ];
+        K kv[kQ];
 #pragma unroll
         for (int q = 0; q < kQ; ++q) {
             const uint64_t pos = base + (uint64_t)q * kWave + lane;
@@ -573,9 +576,10 @@ __device__ __forceinline__ void skip_empty_tiles(SideScan &sc, uint32_t TP, uint
 // loads, all in flight) and ballot its misplaced elements; the keys stay in
 // kv for the exchange.
 template <class O, int PASS>
-__device__ __forceinline__ uint32_t ballot_subtile(const uint32_t *keys, uint32_t p, bool right,
-                                                   const SideScan &sc, uint64_t m[kPartItems],
-                                                   uint32_t kv[kPartItems]) {
+__device__ __forceinline__ uint32_t ballot_subtile(const typename O::K *keys, typename O::K p,
+                                                   bool right, const SideScan &sc,
+                                                   uint64_t m[kPartItems],
+                                                   typename O::K kv[kPartItems]) {
     const int lane = lane_id(), wave = wave_id();
     const uint64_t base = sc.pos + (uint64_t)wave * (kPartItems * kWave) + lane;
 #pragma unroll
@@ -597,10 +601,11 @@ __device__ __forceinline__ uint32_t ballot_subtile(const uint32_t *keys, uint32_
 // Record the positions of a subtile's misplaced elements in `slots` and
 // their keys in `vslots`, in position order, after the waves' counts are
 // known (wtot: one per wave).
+template <class K>
 __device__ __forceinline__ void record_subtile(SideScan &sc, const uint64_t m[kPartItems],
-                                               const uint32_t kv[kPartItems],
+                                               const K kv[kPartItems],
                                                const uint32_t *wtot, uint32_t *slots,
-                                               uint32_t *vslots, uint32_t cap) {
+                                               K *vslots, uint32_t cap) {
     const int lane = lane_id(), wave = wave_id();
     uint32_t woff = sc.found, total = 0;
 #pragma unroll
@@ -639,7 +644,9 @@ __global__ __launch_bounds__(kBlock) void k_part_swap(TaskRef<PartSeg> tasks, ui
                                                       const uint32_t *spR_all,
                                                       uint32_t *eqmv_all,
                                                       const uint64_t *meta_all) {
-    __shared__ uint32_t pL[kRankChunk], pR[kRankChunk], vL[kRankChunk], vR[kRankChunk];
+    using K = typename O::K;
+    __shared__ uint32_t pL[kRankChunk], pR[kRankChunk];
+    __shared__ K vL[kRankChunk], vR[kRankChunk];
     __shared__ uint32_t wtot[2][kWaves];
     uint32_t j, a;
     const PartSeg g = task_of(tasks, blockIdx.x, &j, &a);
@@ -649,9 +656,9 @@ __global__ __launch_bounds__(kBlock) void k_part_swap(TaskRef<PartSeg> tasks, ui
     if (X == 0) return;
     const uint32_t nch = (X + rc - 1) / rc;
     if (j >= nch) return;
-    uint32_t *keys = g.keys + g.lo;
+    K *keys = (K *)g.keys + g.lo;
     uint32_t *vals = PAIRS ? g.vals + g.lo : nullptr;
-    const uint32_t p = (uint32_t)meta[M_PIVOT];
+    const K p = (K)meta[M_PIVOT];
     const uint32_t r0 = j * rc;
     uint32_t cnt = X - r0 < rc ? X - r0 : rc;
     const uint32_t *spL = spL_all + g.chunk_off, *spR = spR_all + g.chunk_off;
@@ -671,7 +678,7 @@ __global__ __launch_bounds__(kBlock) void k_part_swap(TaskRef<PartSeg> tasks, ui
         if (!more_l && !more_r) break;
         // both sides' loads in flight together, one pair of barriers
         uint64_t mL[kPartItems], mR[kPartItems];
-        uint32_t kL[kPartItems], kR[kPartItems];
+        K kL[kPartItems], kR[kPartItems];
         uint32_t cl = 0, cr = 0;
         if (more_l) cl = ballot_subtile<O, PASS>(keys, p, false, L, mL, kL);
         if (more_r) cr = ballot_subtile<O, PASS>(keys, p, true, R, mR, kR);
@@ -692,7 +699,8 @@ __global__ __launch_bounds__(kBlock) void k_part_swap(TaskRef<PartSeg> tasks, ui
     // every thread exchanges up to kXItems pairs (clamped slots read a
     // valid pair and store nothing)
     constexpr int kXItems = (kRankChunk + kBlock - 1) / kBlock;
-    uint32_t il[kXItems], ir[kXItems], x[kXItems], y[kXItems];
+    uint32_t il[kXItems], ir[kXItems];
+    K x[kXItems], y[kXItems];
 #pragma unroll
     for (int q = 0; q < kXItems; ++q) {
         const uint32_t k = (uint32_t)q * kBlock + threadIdx.x;
@@ -712,17 +720,18 @@ __global__ __launch_bounds__(kBlock) void k_part_swap(TaskRef<PartSeg> tasks, ui
         }
     }
     if constexpr (PAIRS) {
+        uint32_t xv[kXItems], yv[kXItems];
 #pragma unroll
         for (int q = 0; q < kXItems; ++q) {
-            x[q] = ldg(vals + il[q]);
-            y[q] = ldg(vals + ir[q]);
+            xv[q] = ldg(vals + il[q]);
+            yv[q] = ldg(vals + ir[q]);
         }
 #pragma unroll
         for (int q = 0; q < kXItems; ++q) {
             const uint32_t k = (uint32_t)q * kBlock + threadIdx.x;
             if (k < cnt) {
-                stg(vals + il[q], y[q]);
-                stg(vals + ir[q], x[q]);
+                stg(vals + il[q], yv[q]);
+                stg(vals + ir[q], xv[q]);
             }
         }
     }
@@ -735,7 +744,7 @@ static hipError_t partition_t(const PartitionLaunch &L, hipStream_t st) {
     switch (L.phase) {
     case 0: {  // count + scan A
         {
-            ProfScope prof(st, K_PART_COUNT, 4.0 * (double)L.keys_total);
+            ProfScope prof(st, K_PART_COUNT, (double)sizeof(typename O::K) * L.keys_total);
             hipLaunchKernelGGL((k_part_count<O>), dim3(L.work), dim3(kBlock), 0, st, L.tasks,
                                L.TP, ws.cnt_lt, ws.cnt_eq, ws.meta);
         }
@@ -804,9 +813,18 @@ static hipError_t partition_t(const PartitionLaunch &L, hipStream_t st) {
 }
 
 hipError_t launch_partition_phase(int dt, bool pairs, const PartitionLaunch &L, hipStream_t st) {
-    if (dt == 1)
+    switch (dt) {
+    case 0:
+        return pairs ? partition_t<OrdU32, true>(L, st) : partition_t<OrdU32, false>(L, st);
+    case 1:
         return pairs ? partition_t<OrdF32, true>(L, st) : partition_t<OrdF32, false>(L, st);
-    return pairs ? partition_t<OrdU32, true>(L, st) : partition_t<OrdU32, false>(L, st);
+    case 2:  // 64-bit keys carry no payload
+        return pairs ? hipErrorInvalidValue : partition_t<OrdU64, false>(L, st);
+    case 3:
+        return pairs ? hipErrorInvalidValue : partition_t<OrdF64, false>(L, st);
+    default:
+        return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace qms

@@ -152,7 +152,7 @@ int qms_server_create(const qms_server_config *cfg, qms_server **out) {
 int qms_server_submit(qms_server *s, void *d_keys, uint64_t n, int dt, uint64_t *ticket_out) {
     try {
         if (!s || !ticket_out) return set_error(QMS_ERR_INVALID, "NULL server or ticket");
-        if (dt != QMS_U32 && dt != QMS_F32) return set_error(QMS_ERR_UNSUPPORTED, "unknown dtype");
+        if (dt != QMS_U32 && dt != QMS_F32) return set_error(QMS_ERR_UNSUPPORTED, "the server takes 32-bit keys (QMS_U32, QMS_F32)");
         if (n >= (1ull << 32)) return set_error(QMS_ERR_UNSUPPORTED, "n must be below 2^32");
         if (n * 4 > s->cfg.hbm_budget_bytes)
             return set_error(QMS_ERR_BUDGET, "request larger than the HBM budget");

@@ -18,6 +18,8 @@ LIB_PATH = os.environ.get("QMS_LIBRARY") or os.path.join(PKG, "libqms.so")
 
 QMS_U32 = 0
 QMS_F32 = 1
+QMS_U64 = 2
+QMS_F64 = 3
 
 QMS_OK = 0
 QMS_PENDING = 1
@@ -148,7 +150,12 @@ def _dtype_code(t) -> int:
         return QMS_F32
     if t.dtype in (torch.int32, torch.uint32):
         return QMS_U32
-    raise TypeError(f"keys must be float32, uint32 or int32 (bit pattern of uint32), got {t.dtype}")
+    if t.dtype == torch.float64:
+        return QMS_F64
+    if t.dtype in (torch.int64, torch.uint64):
+        return QMS_U64
+    raise TypeError("keys must be float32/float64 or 32/64-bit integers (bit patterns of "
+                    f"unsigned keys), got {t.dtype}")
 
 
 def _check_tensor(t, name):
@@ -159,11 +166,11 @@ def _check_tensor(t, name):
 
 
 def qms_sort(keys, stream=None, dtype: Optional[int] = None) -> None:
-    """Sort a 1-D device tensor of 32-bit keys in place.
+    """Sort a 1-D device tensor of 32- or 64-bit keys in place.
 
-    uint32/int32 tensors are sorted as unsigned 32-bit integers (an int32
-    tensor is taken as the bit pattern of uint32 keys); float32 tensors by
-    the IEEE-754 total order."""
+    uint32/int32 (uint64/int64) tensors are sorted as unsigned integers of
+    their width (a signed tensor is taken as the bit pattern of unsigned
+    keys); float32 and float64 tensors by the IEEE-754 total order."""
     _check_tensor(keys, "keys")
     lib = load_library()
     dt = _dtype_code(keys) if dtype is None else dtype
