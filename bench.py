@@ -363,6 +363,25 @@ def main():
             sys.exit(1)
         dists["pairs_zipf_2e26"] = round(npairs / (sec2 / args.dist_steps) / 1e9, 3)
         del ks, vs, k0, v0
+        # 64-bit keys (wide records): 2^27 uniform uint64 keys, the same 1 GiB
+        print("[bench] u64", file=sys.stderr, flush=True)
+        n64 = 1 << 27
+        g64 = torch.Generator(device=dev)
+        g64.manual_seed(6)
+        w0 = torch.randint(-2 ** 63, 2 ** 63 - 1, (n64,), dtype=torch.int64, device=dev,
+                           generator=g64)
+        ws64 = [w0.clone() for _ in range(args.dist_steps + 1)]
+        del w0
+        time_sorts(ws64[:1], qms, torch, profile=False)
+        sec2, _ = time_sorts(ws64[1:], qms, torch, profile=False)
+        last = ws64[-1]
+        hi, lo = (last >> 32) & 0xFFFFFFFF, last & 0xFFFFFFFF
+        if not bool(((hi[:-1] < hi[1:]) | ((hi[:-1] == hi[1:]) & (lo[:-1] <= lo[1:]))).all()):
+            print("bench.py: u64 output not sorted", file=sys.stderr)
+            sys.exit(1)
+        dists["u64_2e27"] = round(n64 / (sec2 / args.dist_steps) / 1e9, 3)
+        dists["u64_2e27_GB_per_s_keys"] = round(8 * n64 / (sec2 / args.dist_steps) / 1e9, 1)
+        del ws64, last, hi, lo
 
     # QuickMergeXsort's threshold (Sec. "QuickMergeXsort"): the same uniform
     # workload with the Mergesort stopping at runs of base_tile keys; the
