@@ -392,7 +392,7 @@ def main():
         from paper_1804_10062_amd import autotune
         xthresh = {}
         try:
-            for t0 in (16384, 8192, 4096, 2048):
+            for t0 in (0, 16384, 8192, 4096, 2048):
                 print(f"[bench] X_THRESH {t0}", file=sys.stderr, flush=True)
                 qms.qms_set_tuning(4, 4096, 16384, t0)
                 cps = [src.clone() for _ in range(args.dist_steps + 1)]
@@ -401,9 +401,9 @@ def main():
                 if not is_sorted(cps[-1]):
                     print(f"bench.py: X_THRESH {t0} output not sorted", file=sys.stderr)
                     sys.exit(1)
-                lg = int(t0).bit_length() - 1
+                lg = int(t0 or 16384).bit_length() - 1
                 first = qms.qms_last_schedule()[0]
-                xthresh[str(t0)] = {
+                xthresh["auto" if t0 == 0 else str(t0)] = {
                     "Gkeys_per_s": round(N_KEYS / (sec2 / args.dist_steps) / 1e9, 3),
                     "ms_per_sort": round(sec2 / args.dist_steps * 1e3, 3),
                     "network_compare_exchanges_per_key": lg * (lg + 1) / 4,

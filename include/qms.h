@@ -213,7 +213,7 @@ int qms_profile_end(qms_kernel_stat *out, int max_entries, int *n_out);
 
 /*
  * Run-time tunables, process-wide, read at the start of every sort (the
- * server's worker included); defaults {4, 4096, 16384, 16384}.  They change
+ * server's worker included); defaults {4, 4096, 16384, 0}.  They change
  * speed, never results.
  *   merge_ways      2 or 4: key-only sorts merge four runs per pass (the
  *                   multi-way merging proposed in the paper's Conclusion) or
@@ -227,9 +227,13 @@ int qms_profile_end(qms_kernel_stat *out, int max_entries, int *n_out);
  *                   Mergesort of each round stops at runs of this many keys,
  *                   which the base case X (a bitonic network in LDS) sorts;
  *                   a power of two in [2048, 16384].  Smaller: fewer network
- *                   comparisons, more merge levels.  Key/payload sorts use at
- *                   most 8192.  16384 = sqrt(2^28), the paper's sqrt(n) rule
- *                   for the 2^28-key workload.
+ *                   comparisons, more merge levels.  Key/payload sorts and
+ *                   64-bit keys use at most 8192.  16384 = sqrt(2^28), the
+ *                   paper's sqrt(n) rule for the 2^28-key workload.  0
+ *                   (automatic): 16384 (8192 for pairs and 64-bit keys),
+ *                   except that a key-only sort merging four runs per pass
+ *                   takes 8192 for a Mergesort whose level count would
+ *                   otherwise be odd.
  * qms_set_tuning returns QMS_ERR_INVALID for values out of range (nothing is
  * changed then).  The package's autotuner (paper_1804_10062_amd/autotune.py)
  * picks them for a workload by timing sorts of a sample.

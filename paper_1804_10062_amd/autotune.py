@@ -20,9 +20,9 @@ from . import qms
 FIELDS = ("merge_ways", "partition_tile", "chunk_span", "base_tile")
 # (merge_ways, partition_tile, chunk_span, base_tile); base_tile is
 # QuickMergeXsort's X_THRESH, the run width at which the Mergesort calls the
-# base case
+# base case (0: automatic)
 CANDIDATES: Tuple[Tuple[int, int, int, int], ...] = tuple(
-    itertools.product((4, 2), (4096, 8192), (16384, 32768), (16384, 8192, 4096)))
+    itertools.product((4, 2), (4096, 8192), (16384, 32768), (0, 16384, 8192, 4096)))
 
 
 def _time_batch(keys, offsets, vals, ref_keys, ref_vals, reps: int, stream,
@@ -73,4 +73,4 @@ def autotune_batch(keys, offsets, vals=None, host_offsets=None,
 
 def reset_tuning() -> None:
     """Back to the library defaults."""
-    qms.qms_set_tuning(4, 4096, 16384, 16384)
+    qms.qms_set_tuning(4, 4096, 16384, 0)

@@ -248,8 +248,8 @@ int qms_set_tuning(const qms_tuning *t) {
     if (t->chunk_span < (uint32_t)kPartSub || t->chunk_span > (1u << 20))
         return set_error(QMS_ERR_INVALID, "chunk_span must lie in [4096, 2^20]");
     const uint32_t bt = t->base_tile;
-    if (bt < (uint32_t)kMergeTile || bt > kBaseTileKeys || (bt & (bt - 1)) != 0)
-        return set_error(QMS_ERR_INVALID, "base_tile must be a power of two in [2048, 16384]");
+    if (bt != 0 && (bt < (uint32_t)kMergeTile || bt > kBaseTileKeys || (bt & (bt - 1)) != 0))
+        return set_error(QMS_ERR_INVALID, "base_tile must be 0 or a power of two in [2048, 16384]");
     std::lock_guard<std::mutex> lock(g_tuning_mutex);
     g_tuning.merge_ways = t->merge_ways;
     g_tuning.partition_tile = pt;

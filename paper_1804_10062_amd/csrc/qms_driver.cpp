@@ -125,7 +125,15 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
     // round's Mergesort stops and calls the base case X (QuickMergeXsort's
     // X_THRESH, a tunable), so that a workgroup tile holds T0 / R0 runs.
     const uint32_t T0 = (pairs || wide) ? kBaseTilePairs : kBaseTileKeys;
-    const uint32_t R0 = std::min(T0, tune.base_tile);
+    // base_tile 0 (automatic): the whole workgroup tile, except that 4-way
+    // key-only sorts take half of it when that makes the level count even,
+    // so that every pass merges four runs (no 2-way first pass)
+    const bool auto_r0 = tune.base_tile == 0;
+    const bool four_way_sort = !pairs && !wide && tune.merge_ways == 4;
+    const uint32_t R0 = auto_r0 ? T0 : std::min(T0, tune.base_tile);
+    auto levels = [](uint64_t m, uint32_t r) -> uint32_t {
+        return m > r ? ceil_log2((m + r - 1) / r) : 0;
+    };
     std::vector<uint32_t> active, next;
     // ranges of at most T0 keys, sorted in place by the base case.  A
     // range that becomes small in a round still holds that round's swap
@@ -290,7 +298,11 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
                     t.m = mR;
                     g.hi = b1;
                 }
-                t.L = t.m > R0 ? ceil_log2((t.m + R0 - 1) / R0) : 0;
+                t.L = levels(t.m, R0);
+                if (auto_r0 && four_way_sort && (t.L & 1u)) {
+                    t.w0 = R0 / 2;
+                    t.L = levels(t.m, t.w0);
+                }
                 // HybridQuickMergesort's rule with delta = 1/16: a split outside
                 // [s/16, 15 s/16] makes the next pivot of this array the
                 // median of the medians of three; the one after returns to

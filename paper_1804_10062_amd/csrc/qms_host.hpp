@@ -22,7 +22,7 @@ struct Tuning {
     uint32_t merge_ways = 4;
     uint32_t partition_tile = kPartSub;
     uint32_t chunk_span = (uint32_t)kChunkSpan;
-    uint32_t base_tile = kBaseTileKeys;
+    uint32_t base_tile = 0;  // automatic
 };
 Tuning current_tuning();
 

@@ -235,7 +235,7 @@ def qms_mom_pivot(keys, stream=None) -> int:
 
 
 def qms_set_tuning(merge_ways: int, partition_tile: int, chunk_span: int,
-                   base_tile: int = 16384) -> None:
+                   base_tile: int = 0) -> None:
     t = Tuning(merge_ways, partition_tile, chunk_span, base_tile)
     _check(load_library().qms_set_tuning(ctypes.byref(t)), "qms_set_tuning")
 

@@ -13,7 +13,8 @@ pytestmark = pytest.mark.gpu
 needs_gpu = pytest.mark.skipif(not torch.cuda.is_available(), reason="no GPU")
 
 # (merge_ways, partition_tile, chunk_span, base_tile)
-TUNINGS = [(4, 4096, 16384, 16384), (2, 4096, 16384, 16384), (4, 8192, 32768, 8192),
+TUNINGS = [(4, 4096, 16384, 0), (4, 4096, 16384, 16384), (2, 4096, 16384, 16384),
+           (4, 8192, 32768, 8192),
            (2, 16384, 4096, 4096), (4, 65536, 1 << 20, 2048), (4, 4096, 16384, 4096),
            (2, 8192, 16384, 2048)]
 FIELDS = ("merge_ways", "partition_tile", "chunk_span", "base_tile")

@@ -50,6 +50,29 @@ def test_threshold_sort_matches_oracle(t0, ways, n):
 
 
 @needs_gpu
+@pytest.mark.parametrize("ways", [4, 2])
+@pytest.mark.parametrize("n", [16385, 100003, 1 << 20, 3000017])
+def test_automatic_threshold(ways, n):
+    """base_tile 0: runs of 16,384 keys, or of 8,192 when a 4-way sort's
+    level count would otherwise be odd (every pass then merges four runs)."""
+    qms.qms_set_tuning(ways, 4096, 16384, 0)
+    assert qms.qms_get_tuning()["base_tile"] == 0
+    x = inputs.uniform_u32(n, seed=n % 89)
+    t = to_device(x)
+    qms.qms_sort(t)
+    torch.cuda.synchronize()
+    want, _, _ = oracle.sort(x, counted=False)
+    np.testing.assert_array_equal(to_host(t), want)
+    for s, c_lt, c_eq, c_gt, L, _ in qms.qms_last_schedule():
+        m = min(c_lt, c_gt)
+        l16 = _levels(m, 16384)
+        expect = _levels(m, 8192) if (ways == 4 and l16 % 2 == 1) else l16
+        assert L == expect, (m, L, expect)
+        if ways == 4:
+            assert L % 2 == 0
+
+
+@needs_gpu
 @pytest.mark.parametrize("t0", THRESHOLDS)
 @pytest.mark.parametrize("kind", ["sorted", "reverse", "sorted_swaps", "zipf", "equal"])
 def test_threshold_structured_inputs(t0, kind):
