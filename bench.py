@@ -412,6 +412,32 @@ def main():
         finally:
             autotune.reset_tuning()
 
+    # QuickXsort's other threshold: ranges of at most final_tile keys leave
+    # the loop for one Mergesort into the fixed scratch buffer (8192: the
+    # loop runs down to the base tile)
+    final_sweep = None
+    if not args.only_uniform and not args.no_threshold_sweep:
+        from paper_1804_10062_amd import autotune
+        final_sweep = {}
+        try:
+            for ft in (8192, 1 << 18, 1 << 20, 1 << 22, 1 << 24):
+                print(f"[bench] final_tile {ft}", file=sys.stderr, flush=True)
+                d = autotune.DEFAULTS
+                qms.qms_set_tuning(d[0], d[1], d[2], d[3], ft)
+                cps = [src.clone() for _ in range(args.dist_steps + 1)]
+                time_sorts(cps[:1], qms, torch, profile=False)
+                sec2, _ = time_sorts(cps[1:], qms, torch, profile=False)
+                if not is_sorted(cps[-1]):
+                    print(f"bench.py: final_tile {ft} output not sorted", file=sys.stderr)
+                    sys.exit(1)
+                final_sweep[str(ft)] = {
+                    "Gkeys_per_s": round(N_KEYS / (sec2 / args.dist_steps) / 1e9, 3),
+                    "ms_per_sort": round(sec2 / args.dist_steps * 1e3, 3),
+                    "partition_rounds": len(qms.qms_last_schedule())}
+                del cps
+        finally:
+            autotune.reset_tuning()
+
     batched = None
     if not args.no_batched:
         print("[bench] batched vs per-array", file=sys.stderr, flush=True)
@@ -460,6 +486,7 @@ def main():
         "cpu_baseline": cpu,
         "distributions_Gkeys_per_s": dists,
         "x_thresh_tradeoff": xthresh,
+        "final_tile_tradeoff": final_sweep,
         "batched": batched,
         "serving": serving,
         "kernels": kernels,

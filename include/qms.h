@@ -28,8 +28,9 @@
  *     results back to the host once per partition round, so they return
  *     only after the sort has completed on the stream.
  *   - Extra device memory: a library-owned workspace per (device, stream)
- *     of fixed size (tile counters and round state; no buffer proportional
- *     to n), allocated on first use and kept until qms_release_workspaces().
+ *     of fixed size (tile counters, round state and a 128 MiB scratch buffer
+ *     for the last, small ranges; nothing proportional to n), allocated on
+ *     first use and kept until qms_release_workspaces().
  *   - Return values are qms_status codes; no C++ exception crosses this
  *     interface.  The message of the last failure on the calling thread is
  *     available from qms_last_error().
@@ -213,8 +214,8 @@ int qms_profile_end(qms_kernel_stat *out, int max_entries, int *n_out);
 
 /*
  * Run-time tunables, process-wide, read at the start of every sort (the
- * server's worker included); defaults {4, 4096, 16384, 0}.  They change
- * speed, never results.
+ * server's worker included); defaults {4, 4096, 16384, 0, 2^22}.  They
+ * change speed, never results.
  *   merge_ways      2 or 4: key-only sorts merge four runs per pass (the
  *                   multi-way merging proposed in the paper's Conclusion) or
  *                   two; key/payload sorts always merge two.
@@ -234,6 +235,14 @@ int qms_profile_end(qms_kernel_stat *out, int max_entries, int *n_out);
  *                   except that a key-only sort merging four runs per pass
  *                   takes 8192 for a Mergesort whose level count would
  *                   otherwise be odd.
+ *   final_tile      ranges of at most this many keys leave the QuickMergesort
+ *                   loop (QuickXsort hands small arrays to X): one Mergesort
+ *                   finishes each, its swap space taken from a fixed 128 MiB
+ *                   scratch buffer of the workspace (2^24 elements, whatever
+ *                   n is; a round runs as many as fit); ranges of at most the
+ *                   base tile are sorted in place by the base case.  A power
+ *                   of two in [8192, 2^24]; 8192 keeps every range in the
+ *                   loop down to the base tile.
  * qms_set_tuning returns QMS_ERR_INVALID for values out of range (nothing is
  * changed then).  The package's autotuner (paper_1804_10062_amd/autotune.py)
  * picks them for a workload by timing sorts of a sample.
@@ -243,6 +252,7 @@ typedef struct {
     uint32_t partition_tile;
     uint32_t chunk_span;
     uint32_t base_tile;
+    uint32_t final_tile;
 } qms_tuning;
 int qms_set_tuning(const qms_tuning *t);
 int qms_get_tuning(qms_tuning *t);

@@ -17,12 +17,14 @@ from typing import Iterable, Optional, Sequence, Tuple
 
 from . import qms
 
-FIELDS = ("merge_ways", "partition_tile", "chunk_span", "base_tile")
-# (merge_ways, partition_tile, chunk_span, base_tile); base_tile is
-# QuickMergeXsort's X_THRESH, the run width at which the Mergesort calls the
-# base case (0: automatic)
-CANDIDATES: Tuple[Tuple[int, int, int, int], ...] = tuple(
-    itertools.product((4, 2), (4096, 8192), (16384, 32768), (0, 16384, 8192, 4096)))
+FIELDS = ("merge_ways", "partition_tile", "chunk_span", "base_tile", "final_tile")
+# (merge_ways, partition_tile, chunk_span, base_tile, final_tile); base_tile
+# is QuickMergeXsort's X_THRESH, the run width at which the Mergesort calls
+# the base case (0: automatic); final_tile the range size at which a range
+# leaves the loop for one buffered Mergesort
+CANDIDATES: Tuple[Tuple[int, int, int, int, int], ...] = tuple(
+    itertools.product((4, 2), (4096, 8192), (16384, 32768), (0, 8192),
+                      (8192, 1 << 18, 1 << 22)))
 
 
 def _time_batch(keys, offsets, vals, ref_keys, ref_vals, reps: int, stream,
@@ -71,6 +73,9 @@ def autotune_batch(keys, offsets, vals=None, host_offsets=None,
     return {"best": {f: best[f] for f in FIELDS}, "trials": trials}
 
 
+DEFAULTS = (4, 4096, 16384, 0, 1 << 22)
+
+
 def reset_tuning() -> None:
     """Back to the library defaults."""
-    qms.qms_set_tuning(4, 4096, 16384, 0)
+    qms.qms_set_tuning(*DEFAULTS)

@@ -63,7 +63,9 @@ int get_workspace(int device, hipStream_t stream, Workspace **out) {
     ws->stream = stream;
     ws->tab_bytes = tab_arena_bytes();
     const size_t meta_bytes = (size_t)kCapSegs * M_COUNT * sizeof(uint64_t);
-    const size_t bytes = meta_bytes + ws_words() * sizeof(uint32_t) + ws->tab_bytes + 4096;
+    const size_t fbuf_bytes = 2 * kFinalCap * sizeof(uint32_t);
+    const size_t bytes = meta_bytes + fbuf_bytes + ws_words() * sizeof(uint32_t) + ws->tab_bytes +
+                         4096;
     hipError_t e = hipMalloc(&ws->block, bytes);
     if (e != hipSuccess) {
         delete ws;
@@ -78,12 +80,26 @@ int get_workspace(int device, hipStream_t stream, Workspace **out) {
         (void)hipGetLastError();
         return set_error(QMS_ERR_NOMEM, std::string("pinned host allocation: ") + hipGetErrorString(e));
     }
+    for (hipEvent_t &ev : ws->arena_done) {
+        e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            for (hipEvent_t &x : ws->arena_done)
+                if (x) (void)hipEventDestroy(x);
+            (void)hipHostFree(h);
+            (void)hipFree(ws->block);
+            delete ws;
+            (void)hipGetLastError();
+            return set_error(QMS_ERR_NOMEM, std::string("event creation: ") + hipGetErrorString(e));
+        }
+    }
     ws->htab[0] = h;
     ws->htab[1] = (char *)h + ws->tab_bytes;
     ws->h_res = (uint32_t *)((char *)h + 2 * ws->tab_bytes);
     char *b = (char *)ws->block;
     ws->meta = (uint64_t *)b;
     b += meta_bytes;
+    ws->fbuf = (uint32_t *)b;  // 8-byte aligned (meta_bytes is a multiple of 8)
+    b += fbuf_bytes;
     ws->dtab = b;
     b += (ws->tab_bytes + 255) & ~(size_t)255;
     uint32_t *w = (uint32_t *)b;
@@ -124,6 +140,8 @@ int get_workspace(int device, hipStream_t stream, Workspace **out) {
 static void free_workspace(Workspace *ws) {
     (void)hipSetDevice(ws->device);
     (void)hipStreamSynchronize(ws->stream);
+    for (hipEvent_t &e : ws->arena_done)
+        if (e) (void)hipEventDestroy(e);
     (void)hipFree(ws->block);
     (void)hipHostFree(ws->htab[0]);
     delete ws;
@@ -250,7 +268,11 @@ int qms_set_tuning(const qms_tuning *t) {
     const uint32_t bt = t->base_tile;
     if (bt != 0 && (bt < (uint32_t)kMergeTile || bt > kBaseTileKeys || (bt & (bt - 1)) != 0))
         return set_error(QMS_ERR_INVALID, "base_tile must be 0 or a power of two in [2048, 16384]");
+    const uint32_t ft = t->final_tile;
+    if (ft < kBaseTilePairs || ft > kFinalCap || (ft & (ft - 1)) != 0)
+        return set_error(QMS_ERR_INVALID, "final_tile must be a power of two in [8192, 2^24]");
     std::lock_guard<std::mutex> lock(g_tuning_mutex);
+    g_tuning.final_tile = ft;
     g_tuning.merge_ways = t->merge_ways;
     g_tuning.partition_tile = pt;
     g_tuning.chunk_span = t->chunk_span;
@@ -265,6 +287,7 @@ int qms_get_tuning(qms_tuning *t) {
     t->partition_tile = c.partition_tile;
     t->chunk_span = c.chunk_span;
     t->base_tile = c.base_tile;
+    t->final_tile = c.final_tile;
     return QMS_OK;
 }
 

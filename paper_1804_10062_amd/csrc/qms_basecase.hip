@@ -394,13 +394,14 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_sort(TaskRef<SortSeg> tas
     if (t0 >= g.m) return;
     const uint32_t len = min(T, g.m - t0);
     const bool swap = (merge_passes(g.L, g.two_way != 0) & 1u) != 0;
-    const uint32_t src = g.D + t0, dst = (swap ? g.Bf : g.D) + t0;
     // runs of g.w0 keys (a power of two in [kMergeTile, T]; clamped so that
     // a malformed task still runs a valid network)
     const uint32_t run = g.w0 >= T ? T : (g.w0 <= (uint32_t)kMergeTile ? (uint32_t)kMergeTile : g.w0);
-    K *keys = (K *)g.keys;
-    tile_sort_block<O, PAIRS>(keys + src, PAIRS ? g.vals + src : nullptr, keys + dst,
-                              PAIRS ? g.vals + dst : nullptr, len, run, swap,
+    K *sk = (K *)g.keys + t0;
+    K *dk = (K *)(swap ? g.bkeys : g.keys) + t0;
+    uint32_t *sv = PAIRS ? g.vals + t0 : nullptr;
+    uint32_t *dv = PAIRS ? (swap ? g.bvals : g.vals) + t0 : nullptr;
+    tile_sort_block<O, PAIRS>(sk, sv, dk, dv, len, run, swap,
                               samples + g.split_off + t0 / kMergeTile);
 }
 

@@ -96,13 +96,17 @@ struct PartSeg {
 };
 constexpr uint32_t kPivotMoM = 1;
 
-// One Mergesort of a round: m keys at D, swap space at Bf (offsets from keys),
-// L merge levels over runs of w0 << level keys; the base case (tiles of w0
-// keys) swaps into Bf when L is odd.
+// One Mergesort of a round: m keys in the data region D, m cells of swap
+// space in the buffer region Bf (the other side of the partition, or the
+// library's scratch buffer for a final range), L merge levels over runs of
+// w0 << level keys; the base case swaps into Bf when the pass count is odd.
+// The pointers address element 0 of each region (keys of the sort's width).
 struct SortSeg {
-    uint32_t *keys;
-    uint32_t *vals;
-    uint32_t D, Bf, m;
+    uint32_t *keys;      // D
+    uint32_t *vals;      // payloads of D (nullptr for keys only)
+    uint32_t *bkeys;     // Bf (unused when L == 0)
+    uint32_t *bvals;     // payloads of Bf
+    uint32_t m;
     uint32_t L;          // merge levels
     uint32_t split_off;  // first entry in the merge split array
     uint32_t w0;         // base-case tile (run width of level 0)

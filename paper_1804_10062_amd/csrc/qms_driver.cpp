@@ -58,6 +58,37 @@ struct Seg {
     bool bad_split;  // the last round's smaller side held less than 1/16 of its range
 };
 
+// The host arenas alternate between rounds.  An arena's contents go to the
+// device by asynchronous copies, so before the host writes it again those
+// copies must have run: a round that reads counters back synchronises the
+// stream, but a round without a partition does not, so every round records
+// an event when it is done with its arena (ArenaUse's destructor, on every
+// exit path) and the round that takes the arena next waits for it.
+struct ArenaUse {
+    Workspace &ws;
+    hipStream_t st;
+    int slot;
+    Arena ar;
+    ArenaUse(Workspace &w, hipStream_t s) : ws(w), st(s), slot((int)(w.rounds & 1)) {
+        if (ws.arena_busy[slot]) {
+            (void)hipEventSynchronize(ws.arena_done[slot]);
+            ws.arena_busy[slot] = false;
+        }
+        ++ws.rounds;
+        ar = Arena{(char *)ws.htab[slot], (char *)ws.dtab, ws.tab_bytes};
+    }
+    ~ArenaUse() {
+        if (hipEventRecord(ws.arena_done[slot], st) == hipSuccess) {
+            ws.arena_busy[slot] = true;
+        } else {
+            (void)hipGetLastError();
+            (void)hipStreamSynchronize(st);
+        }
+    }
+    ArenaUse(const ArenaUse &) = delete;
+    ArenaUse &operator=(const ArenaUse &) = delete;
+};
+
 // One round's tables.
 int upload(Arena &ar, size_t from, hipStream_t st) {
     if (ar.used <= from) return QMS_OK;
@@ -134,22 +165,43 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
     auto levels = [](uint64_t m, uint32_t r) -> uint32_t {
         return m > r ? ceil_log2((m + r - 1) / r) : 0;
     };
+    // run width and level count of a Mergesort of m keys
+    auto set_levels = [&](SortSeg &t) {
+        t.w0 = R0;
+        t.L = levels(t.m, R0);
+        if (auto_r0 && four_way_sort && (t.L & 1u)) {
+            t.w0 = R0 / 2;
+            t.L = levels(t.m, t.w0);
+        }
+    };
+    // region pointers: keys are ew 32-bit words wide
+    const uint64_t ew = wide ? 2 : 1;
+    auto kptr = [&](const Seg &g, uint64_t off) { return g.keys + ew * off; };
+    auto vptr = [&](const Seg &g, uint64_t off) { return g.vals ? g.vals + off : nullptr; };
+    // TF: ranges of at most TF keys leave the loop (QuickXsort hands small
+    // arrays to X): up to T0 keys the base case sorts them in place; above,
+    // one Mergesort with the library's fixed scratch buffer as swap space
+    // (kFinalCap elements per workspace, whatever n is).  A round runs as
+    // many of them as the buffer holds; the others wait for the next round.
+    const uint64_t TF = std::max<uint64_t>(T0, std::min<uint64_t>(tune.final_tile, kFinalCap));
+    auto final_task = [&](const Seg &g, uint32_t lo, uint32_t s) {
+        SortSeg f{kptr(g, lo), vptr(g, lo), nullptr, nullptr, s, 0, 0, T0, 0, 0};
+        if (s > T0) set_levels(f);
+        return f;
+    };
     std::vector<uint32_t> active, next;
-    // ranges of at most T0 keys, sorted in place by the base case.  A
-    // range that becomes small in a round still holds that round's swap
+    // A range that becomes small in a round still holds that round's swap
     // buffer, so it runs one round later (next_finals -> ready_finals).
-    std::vector<SortSeg> ready_finals, next_finals, tasks;
+    std::vector<SortSeg> ready_finals, next_finals, tasks, deferred;
     for (uint32_t i = 0; i < segs.size(); ++i) {
         const Seg &g = segs[i];
         const uint32_t s = g.hi - g.lo;
-        if (s > T0) active.push_back(i);
-        else if (s > 1) ready_finals.push_back(SortSeg{g.keys, g.vals, g.lo, 0, s, 0, 0, T0});
+        if (s > TF) active.push_back(i);
+        else if (s > 1) ready_finals.push_back(final_task(g, g.lo, s));
     }
     while (!active.empty() || !ready_finals.empty()) {
-        // alternate arenas: the one used two rounds ago has no copy in flight
-        // (the previous round's readback synchronised the stream after them)
-        Arena ar{(char *)ws.htab[ws.rounds & 1], (char *)ws.dtab, ws.tab_bytes};
-        ++ws.rounds;
+        ArenaUse use(ws, st);
+        Arena &ar = use.ar;
         tasks.clear();
         const uint32_t A = (uint32_t)active.size();
         if (A > 0) {
@@ -286,23 +338,23 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
                 const uint32_t c_lt = ws.h_res[4 * a], c_eq = ws.h_res[4 * a + 1];
                 const uint32_t b1 = g.lo + c_lt, b2 = b1 + c_eq;
                 const uint32_t mL = c_lt, mR = g.hi - b2;
-                SortSeg t{g.keys, g.vals, 0, 0, 0, 0, 0, R0};
+                SortSeg t{};
                 if (mL <= mR) {
-                    t.D = g.lo;
-                    t.Bf = b2;
+                    t.keys = kptr(g, g.lo);
+                    t.vals = vptr(g, g.lo);
+                    t.bkeys = kptr(g, b2);
+                    t.bvals = vptr(g, b2);
                     t.m = mL;
                     g.lo = b2;
                 } else {
-                    t.D = b2;
-                    t.Bf = b1 - mR;
+                    t.keys = kptr(g, b2);
+                    t.vals = vptr(g, b2);
+                    t.bkeys = kptr(g, b1 - mR);
+                    t.bvals = vptr(g, b1 - mR);
                     t.m = mR;
                     g.hi = b1;
                 }
-                t.L = levels(t.m, R0);
-                if (auto_r0 && four_way_sort && (t.L & 1u)) {
-                    t.w0 = R0 / 2;
-                    t.L = levels(t.m, t.w0);
-                }
+                set_levels(t);
                 // HybridQuickMergesort's rule with delta = 1/16: a split outside
                 // [s/16, 15 s/16] makes the next pivot of this array the
                 // median of the medians of three; the one after returns to
@@ -314,15 +366,31 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
                     g_schedule.push_back(
                         {s, c_lt, c_eq, (uint64_t)(s - c_lt - c_eq), t.L, mom ? 1ull : 0ull});
                 const uint32_t s2 = g.hi - g.lo;
-                if (s2 > T0) next.push_back(active[a]);
-                else if (s2 > 1) next_finals.push_back(SortSeg{g.keys, g.vals, g.lo, 0, s2, 0, 0, T0});
+                if (s2 > TF) next.push_back(active[a]);
+                else if (s2 > 1) next_finals.push_back(final_task(g, g.lo, s2));
             }
             active.swap(next);
         }
 
         // ---- Mergesort tasks of this round and the finals that may run ----
-        for (const SortSeg &f : ready_finals) tasks.push_back(f);
-        ready_finals.swap(next_finals);
+        // (finals above T0 take their swap space from the scratch buffer
+        // while it lasts; the rest wait for the next round)
+        uint64_t fused = 0;
+        deferred.clear();
+        for (SortSeg f : ready_finals) {
+            if (f.m > T0) {
+                if (fused + f.m > kFinalCap) {
+                    deferred.push_back(f);
+                    continue;
+                }
+                f.bkeys = ws.fbuf + ew * fused;
+                f.bvals = pairs ? ws.fbuf + kFinalCap + fused : nullptr;
+                fused += f.m;
+            }
+            tasks.push_back(f);
+        }
+        ready_finals.swap(deferred);
+        for (const SortSeg &f : next_finals) ready_finals.push_back(f);
         next_finals.clear();
         if (tasks.empty()) continue;
         // order: tasks with an even level count first, then odd, each by
@@ -412,8 +480,8 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
 
 int mom_pivot_of(int dt, const uint32_t *keys, uint64_t n, Workspace &ws, hipStream_t st,
                  uint32_t *pivot) {
-    Arena ar{(char *)ws.htab[ws.rounds & 1], (char *)ws.dtab, ws.tab_bytes};
-    ++ws.rounds;
+    ArenaUse use(ws, st);
+    Arena &ar = use.ar;
     PartSeg seg{(uint32_t *)keys, nullptr, 0, (uint32_t)n, 0, 0, 0, 0, kPivotMoM, 0};
     int rc = mom_pivots(dt, &seg, 1, ar, ws, st);
     if (rc != QMS_OK) return rc;

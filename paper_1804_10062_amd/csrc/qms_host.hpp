@@ -17,12 +17,14 @@ constexpr int kScheduleWords = 6;
 
 // Run-time tunables (qms_set_tuning): merge arity of key-only sorts, the
 // first partition counting tile, the target positions per exchange chunk,
-// the Mergesort's base-case run width (QuickMergeXsort's X_THRESH).
+// the Mergesort's base-case run width (QuickMergeXsort's X_THRESH), the
+// size below which a range leaves the loop for one buffered Mergesort.
 struct Tuning {
     uint32_t merge_ways = 4;
     uint32_t partition_tile = kPartSub;
     uint32_t chunk_span = (uint32_t)kChunkSpan;
     uint32_t base_tile = 0;  // automatic
+    uint32_t final_tile = 1u << 22;
 };
 Tuning current_tuning();
 

@@ -22,6 +22,9 @@ constexpr uint64_t kCapSplits = (1ull << 31) / kMergeTile + kCapSegs + 16;
 constexpr uint32_t kCapMoM = 2048;
 // Merge levels a task can need: ceil(log2(2^31 / 8192)).
 constexpr int kMaxLevels = 18;
+// Elements of the scratch buffer that final ranges use as swap space (keys
+// of up to 8 bytes, or 4-byte keys with 4-byte payloads): 128 MiB.
+constexpr uint64_t kFinalCap = 1ull << 24;
 
 // Library-owned scratch of one (device, stream): counters, round state and
 // task tables.  Its size does not depend on the number of keys sorted.
@@ -44,9 +47,14 @@ struct Workspace {
     uint64_t *meta = nullptr;    // [kCapSegs * M_COUNT]
     uint32_t *res = nullptr;     // [4 * kCapSegs] per-segment partition results
     uint32_t *hist = nullptr;    // [256 * kCapMoM] median-of-medians select histograms
+    uint32_t *fbuf = nullptr;    // [2 * kFinalCap] swap space of final ranges
     // task tables: device copies of the host arena below
     void *dtab = nullptr;        // [tab_bytes]
     void *htab[2] = {nullptr, nullptr};  // pinned host arenas (alternating rounds)
+    // recorded on the stream after the last round that used each host arena:
+    // its asynchronous uploads have run once the event has
+    hipEvent_t arena_done[2] = {nullptr, nullptr};
+    bool arena_busy[2] = {false, false};
     size_t tab_bytes = 0;
     uint32_t *h_res = nullptr;   // pinned host mirror of res
     uint64_t rounds = 0;         // rounds run with this workspace (arena parity)

@@ -58,13 +58,21 @@ __device__ __forceinline__ MergeTileGeom merge_geom(uint64_t m, uint64_t W, uint
 // Regions of a merge pass: the base case leaves the runs in R0 (the buffer
 // when the pass count is odd, the data region otherwise); pass p reads
 // R(p mod 2) and writes the other region, so the last pass ends in D.
-__device__ __forceinline__ void level_regions(const SortSeg &g, uint32_t level, uint32_t *src,
-                                              uint32_t *dst) {
+struct Regions {
+    uint32_t *sk, *sv;  // source keys, payloads
+    uint32_t *dk, *dv;  // destination keys, payloads
+};
+__device__ __forceinline__ Regions level_regions(const SortSeg &g, uint32_t level) {
     const bool odd = (merge_passes(g.L, g.two_way != 0) & 1u) != 0;
-    const uint32_t r0 = odd ? g.Bf : g.D, r1 = odd ? g.D : g.Bf;
-    const uint32_t p = pass_index(g.L, level, g.two_way != 0);
-    *src = (p & 1u) ? r1 : r0;
-    *dst = (p & 1u) ? r0 : r1;
+    const bool p1 = (pass_index(g.L, level, g.two_way != 0) & 1u) != 0;
+    // the region holding the runs at this pass: R0 on even passes
+    const bool from_buffer = odd != p1;
+    Regions r;
+    r.sk = from_buffer ? g.bkeys : g.keys;
+    r.sv = from_buffer ? g.bvals : g.vals;
+    r.dk = from_buffer ? g.keys : g.bkeys;
+    r.dv = from_buffer ? g.vals : g.bvals;
+    return r;
 }
 
 // First index in [lo, hi) where the prefix-true predicate pred fails (hi if
@@ -167,11 +175,10 @@ __global__ __launch_bounds__(kBlock) void k_merge_split(TaskRef<SortSeg> tasks, 
     const bool active = w < total;
     uint32_t tile = 0, a = 0;
     const SortSeg g = task_of(tasks, active ? w : total - 1, &tile, &a);
-    uint32_t src, dst;
-    level_regions(g, level, &src, &dst);
+    const Regions rg = level_regions(g, level);
     const uint64_t W = (uint64_t)g.w0 << level;
     const MergeTileGeom geo = merge_geom(g.m, W, tile);
-    const K *A = (const K *)g.keys + src + geo.pb;
+    const K *A = (const K *)rg.sk + geo.pb;
     const K *B = A + W;
     const K *As = samples + g.split_off + geo.pb / S;
     const K *Bs = As + W / S;
@@ -203,7 +210,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_split(TaskRef<SortSeg> tasks, 
         // this group's run of the other pair
         const uint32_t r = (g4.which == 0 ? 2 : 0) + half;
         const uint64_t off = g4.gb + r * W;
-        const uint64_t cnt = group_count_before<O>(g.keys + src + off,
+        const uint64_t cnt = group_count_before<O>((const K *)rg.sk + off,
                                                    samples + g.split_off + off / S,
                                                    active ? g4.n[r] : 0, x, g4.which == 0);
         if (active && gid % kSplitLanes == 0) {
@@ -371,8 +378,7 @@ __attribute__((amdgpu_waves_per_eu(QMS_MERGE4_WPE, QMS_MERGE4_WPE))) void k_merg
     uint32_t tile, a;
     const SortSeg g = task_of(tasks, blockIdx.x, &tile, &a);
     if (tile * (uint64_t)S >= g.m) return;
-    uint32_t src, dst;
-    level_regions(g, level, &src, &dst);
+    const Regions rg = level_regions(g, level);
     const uint64_t W = (uint64_t)g.w0 << level;
     const Merge4Geom geo = merge4_geom(g.m, W, tile);
     // the tile's start and end vectors
@@ -391,8 +397,8 @@ __attribute__((amdgpu_waves_per_eu(QMS_MERGE4_WPE, QMS_MERGE4_WPE))) void k_merg
     const uint32_t c1 = len[0], c2 = c1 + len[1], c3 = c2 + len[2], cnt = c3 + len[3];
     if (cnt == 0) return;
     const uint64_t ps = (uint64_t)s[0] + s[1] + s[2] + s[3];
-    uint32_t *S_ = g.keys + src + geo.gb;
-    const uint32_t *T_ = g.keys + dst + geo.gb + ps;
+    uint32_t *S_ = rg.sk + geo.gb;
+    const uint32_t *T_ = rg.dk + geo.gb + ps;
     const uint32_t tid = threadIdx.x;
     // tile element el sits in run r at offset cell(el) from the group base
     // (< 4 W <= m < 2^32); the steps between the runs' offsets are added by
@@ -449,7 +455,7 @@ __attribute__((amdgpu_waves_per_eu(QMS_MERGE4_WPE, QMS_MERGE4_WPE))) void k_merg
         const uint32_t el = first + tid * S;
         if (el < cnt) stg(samples_out + g.split_off + (geo.gb + ps + el) / S, sk[el]);
     }
-    uint32_t *Tw = g.keys + dst + geo.gb + ps;
+    uint32_t *Tw = rg.dk + geo.gb + ps;
 #pragma unroll
     for (int q = 0; q < 2 * S / NT; ++q) {
         const uint32_t el = q * NT + tid;
@@ -561,11 +567,9 @@ __global__ __launch_bounds__(kBlock) void k_merge(TaskRef<SortSeg> tasks, uint32
     uint32_t tile, a;
     const SortSeg g = task_of(tasks, blockIdx.x, &tile, &a);
     if (tile * (uint64_t)kMergeTile >= g.m) return;
-    uint32_t src, dst;
-    level_regions(g, level, &src, &dst);
-    K *keys = (K *)g.keys;
-    merge_block<O, PAIRS>(keys + src, PAIRS ? g.vals + src : nullptr, keys + dst,
-                          PAIRS ? g.vals + dst : nullptr, g.m, (uint64_t)g.w0 << level,
+    const Regions rg = level_regions(g, level);
+    merge_block<O, PAIRS>((K *)rg.sk, PAIRS ? rg.sv : nullptr, (K *)rg.dk,
+                          PAIRS ? rg.dv : nullptr, g.m, (uint64_t)g.w0 << level,
                           tile, splits + g.split_off, samples_out + g.split_off);
 }
 

@@ -62,7 +62,8 @@ class ServerStats(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("merge_ways", ctypes.c_uint32), ("partition_tile", ctypes.c_uint32),
-                ("chunk_span", ctypes.c_uint32), ("base_tile", ctypes.c_uint32)]
+                ("chunk_span", ctypes.c_uint32), ("base_tile", ctypes.c_uint32),
+                ("final_tile", ctypes.c_uint32)]
 
     def as_dict(self) -> dict:
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -235,8 +236,14 @@ def qms_mom_pivot(keys, stream=None) -> int:
 
 
 def qms_set_tuning(merge_ways: int, partition_tile: int, chunk_span: int,
-                   base_tile: int = 0) -> None:
-    t = Tuning(merge_ways, partition_tile, chunk_span, base_tile)
+                   base_tile: Optional[int] = None, final_tile: Optional[int] = None) -> None:
+    """Set the run-time tunables (qms.h); base_tile / final_tile left as
+    None keep their current values."""
+    if base_tile is None or final_tile is None:
+        cur = qms_get_tuning()
+        base_tile = cur["base_tile"] if base_tile is None else base_tile
+        final_tile = cur["final_tile"] if final_tile is None else final_tile
+    t = Tuning(merge_ways, partition_tile, chunk_span, base_tile, final_tile)
     _check(load_library().qms_set_tuning(ctypes.byref(t)), "qms_set_tuning")
 
 

@@ -1,0 +1,163 @@
+"""The buffered final Mergesort: ranges of at most final_tile keys leave the
+QuickMergesort loop and are finished by one Mergesort whose swap space is
+the library's fixed scratch buffer (QuickXsort hands small arrays to X).
+Results must be the oracle's bit for bit, whatever path a range takes."""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from paper_1804_10062_amd import autotune, inputs, qms  # noqa: E402
+from tests.gpu_helpers import check_pairs_exact, to_device, to_host  # noqa: E402
+
+pytestmark = [pytest.mark.gpu, pytest.mark.final_path]
+needs_gpu = pytest.mark.skipif(not torch.cuda.is_available(), reason="no GPU")
+FINAL_CAP = 1 << 24  # elements of the scratch buffer
+
+
+@pytest.fixture(autouse=True)
+def _defaults():
+    if torch.cuda.is_available():
+        autotune.reset_tuning()
+    yield
+    if torch.cuda.is_available():
+        autotune.reset_tuning()
+
+
+def _check_rounds(n: int, tf: int):
+    """The loop runs only while the range exceeds final_tile."""
+    sched = qms.qms_last_schedule()
+    if n <= tf:
+        assert sched == [], sched[:2]
+    else:
+        assert len(sched) >= 1
+        for s, *_ in sched:
+            assert s > tf
+
+
+@needs_gpu
+@pytest.mark.parametrize("ways", [4, 2])
+@pytest.mark.parametrize("tf", [1 << 16, 1 << 20, 1 << 22])
+@pytest.mark.parametrize("n", [8193, 16385, 100003, 1 << 20, (1 << 22) + 1])
+def test_final_sort_matches_oracle(ways, tf, n):
+    qms.qms_set_tuning(ways, 4096, 16384, 0, tf)
+    x = inputs.uniform_u32(n, seed=n % 71 + tf % 13)
+    t = to_device(x)
+    qms.qms_sort(t)
+    torch.cuda.synchronize()
+    want, _, _ = oracle.sort(x, counted=False)
+    np.testing.assert_array_equal(to_host(t), want)
+    _check_rounds(n, tf)
+
+
+@needs_gpu
+@pytest.mark.parametrize("kind", ["sorted", "reverse", "sorted_swaps", "zipf", "equal"])
+def test_final_structured(kind):
+    x = inputs.make_keys(kind, 700001, seed=6)
+    t = to_device(x)
+    qms.qms_sort(t)
+    torch.cuda.synchronize()
+    want, _, _ = oracle.sort(x, counted=False)
+    np.testing.assert_array_equal(to_host(t), want)
+
+
+@needs_gpu
+@pytest.mark.parametrize("base_tile", [0, 16384, 4096])
+def test_final_f32_and_pairs(base_tile):
+    qms.qms_set_tuning(4, 4096, 16384, base_tile, 1 << 20)
+    x = inputs.normal_f32(300007, seed=base_tile)
+    x[:4] = np.array([0.0, -0.0, np.inf, -np.nan], dtype=np.float32)
+    t = to_device(x)
+    qms.qms_sort(t)
+    torch.cuda.synchronize()
+    want, _, _ = oracle.sort(x, counted=False)
+    np.testing.assert_array_equal(to_host(t).view(np.uint32), want.view(np.uint32))
+    k = inputs.make_keys("zipf", 600011, seed=base_tile + 1)
+    kt = to_device(k)
+    k_in = kt.clone()
+    vt = torch.arange(k.size, dtype=torch.int32, device="cuda")
+    qms.qms_sort_pairs(kt, vt)
+    torch.cuda.synchronize()
+    want, _, _ = oracle.sort(k, counted=False)
+    np.testing.assert_array_equal(to_host(kt), want)
+    check_pairs_exact(k_in, kt, vt)
+
+
+@needs_gpu
+@pytest.mark.parametrize("n", [9000, 1 << 20, (1 << 21) + 3])
+def test_final_64_bit(n):
+    qms.qms_set_tuning(4, 4096, 16384, 0, 1 << 20)
+    x = np.random.default_rng(n).integers(0, 2 ** 64, n, dtype=np.uint64)
+    t = torch.from_numpy(x.view(np.int64)).cuda()
+    qms.qms_sort(t)
+    torch.cuda.synchronize()
+    want, _, _ = oracle.sort(x, counted=False)
+    np.testing.assert_array_equal(t.cpu().numpy().view(np.uint64), want)
+    f = np.random.default_rng(n + 1).standard_normal(n)
+    tf = torch.from_numpy(f).cuda()
+    qms.qms_sort(tf)
+    torch.cuda.synchronize()
+    want, _, _ = oracle.sort(f, counted=False)
+    np.testing.assert_array_equal(tf.cpu().numpy().view(np.uint64), want.view(np.uint64))
+
+
+@needs_gpu
+def test_final_batch_beyond_the_buffer():
+    """More final keys than the scratch buffer holds: the finals that do not
+    fit wait for later rounds.  Segments of every size class (in place,
+    buffered, through the loop) in one batch."""
+    qms.qms_set_tuning(4, 4096, 16384, 0, 1 << 22)
+    lens = np.concatenate([
+        np.full(5, (1 << 22) - 7, dtype=np.int64),          # buffered finals, 5 x 4M > 2^24
+        np.array([0, 1, 2, 8192, 16384, 16385, (1 << 22) + 9], dtype=np.int64),
+        inputs.log_uniform_lengths(200, seed=4, lo_exp=6, hi_exp=18).astype(np.int64)])
+    off = inputs.offsets_from_lengths(lens)
+    x = inputs.uniform_u32(int(off[-1]), seed=8)
+    assert int(lens[:5].sum()) > FINAL_CAP
+    t = to_device(x)
+    ot = torch.from_numpy(off.view(np.int64)).cuda()
+    qms.qms_sort_batch(t, ot, host_offsets=off)
+    torch.cuda.synchronize()
+    want, _, _ = oracle.sort_segments(x, off)
+    np.testing.assert_array_equal(to_host(t), want)
+
+
+@needs_gpu
+def test_final_path_is_the_default_and_large_sorts_use_both():
+    """Defaults: a range of 2^24 + 1 keys is partitioned until it fits the
+    final threshold, then finished by the buffered Mergesort."""
+    tf = qms.qms_get_tuning()["final_tile"]
+    n = (1 << 24) + 1
+    x = inputs.uniform_u32(n, seed=3)
+    t = to_device(x)
+    qms.qms_sort(t)
+    torch.cuda.synchronize()
+    want, _, _ = oracle.sort(x, counted=False)
+    np.testing.assert_array_equal(to_host(t), want)
+    sched = qms.qms_last_schedule()
+    assert len(sched) >= 1
+    assert all(s > tf for s, *_ in sched)
+
+
+@needs_gpu
+def test_final_only_rounds_back_to_back():
+    """Twelve buffered finals of almost 2^22 keys fill the scratch buffer
+    four at a time: three rounds in a row without a partition (and so
+    without a readback that synchronises the stream) must each see their own
+    task tables."""
+    qms.qms_set_tuning(4, 4096, 16384, 0, 1 << 22)
+    lens = np.concatenate([np.full(12, (1 << 22) - 5, dtype=np.int64),
+                           np.array([3, 9000, 20000], dtype=np.int64)])
+    off = inputs.offsets_from_lengths(lens)
+    x = inputs.uniform_u32(int(off[-1]), seed=21)
+    t = to_device(x)
+    ot = torch.from_numpy(off.view(np.int64)).cuda()
+    for _ in range(2):  # twice: the second call reuses the arenas of the first
+        t.copy_(to_device(x))
+        qms.qms_sort_batch(t, ot, host_offsets=off)
+        torch.cuda.synchronize()
+    want, _, _ = oracle.sort_segments(x, off)
+    np.testing.assert_array_equal(to_host(t), want)

@@ -17,7 +17,7 @@ TUNINGS = [(4, 4096, 16384, 0), (4, 4096, 16384, 16384), (2, 4096, 16384, 16384)
            (4, 8192, 32768, 8192),
            (2, 16384, 4096, 4096), (4, 65536, 1 << 20, 2048), (4, 4096, 16384, 4096),
            (2, 8192, 16384, 2048)]
-FIELDS = ("merge_ways", "partition_tile", "chunk_span", "base_tile")
+FIELDS = ("merge_ways", "partition_tile", "chunk_span", "base_tile", "final_tile")
 
 
 @pytest.fixture(autouse=True)
@@ -33,7 +33,8 @@ def _restore_defaults():
                                     ("zipf", 200003), ("reverse", 1 << 18)])
 def test_tuned_sort_matches_oracle(tuning, kind, n):
     qms.qms_set_tuning(*tuning)
-    assert qms.qms_get_tuning() == dict(zip(FIELDS, tuning))
+    got = qms.qms_get_tuning()
+    assert {f: got[f] for f in FIELDS[:len(tuning)]} == dict(zip(FIELDS, tuning))
     x = inputs.make_keys(kind, n, seed=11)
     t = to_device(x)
     qms.qms_sort(t)
@@ -67,7 +68,9 @@ def test_invalid_tuning_rejected_and_unchanged():
     before = qms.qms_get_tuning()
     for bad in [(3, 4096, 16384), (4, 4095, 16384), (4, 6144, 16384), (4, 4096, 100),
                 (4, 1 << 17, 16384), (4, 4096, (1 << 20) + 1),
-                (4, 4096, 16384, 1024), (4, 4096, 16384, 3072), (4, 4096, 16384, 32768)]:
+                (4, 4096, 16384, 1024), (4, 4096, 16384, 3072), (4, 4096, 16384, 32768),
+                (4, 4096, 16384, 0, 4096), (4, 4096, 16384, 0, 3 << 20),
+                (4, 4096, 16384, 0, 1 << 25)]:
         with pytest.raises(qms.QmsError):
             qms.qms_set_tuning(*bad)
     assert qms.qms_get_tuning() == before
