@@ -226,51 +226,102 @@ __global__ __launch_bounds__(kBlock) void k_merge_split(TaskRef<SortSeg> tasks, 
 }
 
 // ---- 4-way pass ----------------------------------------------------------------
-// End of every 4-way tile: the next boundary in merge order, i.e. the next
-// boundary of its own pair or the first boundary of the other pair placed
-// after it, whichever comes first.  The tile's start and end are stored at the
-// tile's index, 8 words per tile (running the merge workgroups in output
-// order instead was measured slower: the concurrent workgroups then crowd a
-// narrow address range).  One thread per tile.
+// Tiles of a 4-way pass run from one boundary to the next in merge order
+// (boundaries of both pairs together).  Boundaries of one pair lie at least
+// kMergeTile apart in merge order, so two boundaries of different pairs can
+// fall close together and leave a tiny tile between them; a workgroup for a
+// tile of a hundred elements costs as long as a full one in everything but
+// bandwidth.  A tiny tile (fewer than kMerge4Absorb outputs, not the first
+// of its group, not the last) is absorbed by the tile before it, which
+// cannot be tiny itself (three boundaries within 2 kMerge4Absorb <
+// kMergeTile would put two of one pair closer than kMergeTile); a tile then
+// holds at most kMergeTile + kMerge4Absorb elements of each pair.
+constexpr uint32_t kMerge4Absorb = 256;
+
+// The boundary after the one at tile t (start vector v): the next boundary
+// of its own pair or the first boundary of the other pair placed at or after
+// it, whichever comes first in merge order; tile = -1 for the end of the
+// group (then vec holds the run lengths).
+struct Merge4Bnd {
+    uint32_t vec[4];
+    uint64_t pos;
+    int64_t tile;
+};
+__device__ __forceinline__ Merge4Bnd next_boundary(const uint32_t *bd, uint64_t m, uint64_t W,
+                                                   uint64_t t, const uint32_t (&v)[4]) {
+    constexpr uint32_t S = kMergeTile;
+    const Merge4Geom geo = merge4_geom(m, W, t);
+    Merge4Bnd r;
+    r.tile = -1;
+    r.pos = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        r.vec[q] = geo.n[q];
+        r.pos += geo.n[q];
+    }
+    const uint32_t nP[2] = {geo.n[0] + geo.n[1], geo.n[2] + geo.n[3]};
+    const uint64_t first[2] = {geo.gb / S, (geo.gb + 2 * W) / S};  // first tile of each pair
+    auto consider = [&](uint64_t c) {
+        uint32_t u[4];
+        uint64_t pos = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            u[q] = bd[4 * c + q];
+            pos += u[q];
+        }
+        if (pos < r.pos) {
+            r.pos = pos;
+            r.tile = (int64_t)c;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) r.vec[q] = u[q];
+        }
+    };
+    if ((geo.k + 1) * S < nP[geo.which]) consider(t + 1);
+    const uint32_t other = 1 - geo.which;
+    const uint32_t placed = other == 0 ? v[0] + v[1] : v[2] + v[3];
+    const uint32_t j = (placed + S - 1) / S;
+    if ((uint64_t)j * S < nP[other]) consider(first[other] + j);
+    return r;
+}
+
+// Start and end vector of every 4-way tile, 8 words at the tile's index
+// (running the merge workgroups in output order instead was measured slower:
+// the concurrent workgroups then crowd a narrow address range).  An absorbed
+// tile gets an empty range.  One thread per tile.
 __global__ __launch_bounds__(kBlock) void k_merge4_ends(TaskRef<SortSeg> tasks, uint32_t level,
                                                         uint32_t total, const uint32_t *bounds,
                                                         uint32_t *ends) {
-    constexpr uint32_t S = kMergeTile;
     const uint32_t w = blockIdx.x * kBlock + threadIdx.x;
     if (w >= total) return;
     uint32_t tile, a;
     const SortSeg g = task_of(tasks, w, &tile, &a);
     const uint64_t W = (uint64_t)g.w0 << level;
-    const Merge4Geom geo = merge4_geom(g.m, W, tile);
     const uint32_t *bd = bounds + 4 * (uint64_t)g.split_off;
-    uint32_t s[4], e[4];
+    uint32_t s[4];
+    uint64_t pos = 0;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         s[r] = bd[4 * tile + r];
-        e[r] = geo.n[r];
+        pos += s[r];
     }
-    const uint32_t nP[2] = {geo.n[0] + geo.n[1], geo.n[2] + geo.n[3]};
-    const uint64_t first[2] = {geo.gb / S, (geo.gb + 2 * W) / S};  // first tile of each pair
-    uint64_t best = ~0ull;
-    auto consider = [&](uint64_t c) {
-        uint32_t v[4];
-        uint64_t pos = 0;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            v[r] = bd[4 * c + r];
-            pos += v[r];
-        }
-        if (pos < best) {
-            best = pos;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) e[r] = v[r];
-        }
+    // tiny tiles with a real boundary after them and a tile before them
+    auto tiny = [&](uint64_t p0, const Merge4Bnd &nx) {
+        return p0 > 0 && nx.tile >= 0 && nx.pos - p0 < kMerge4Absorb;
     };
-    if ((geo.k + 1) * S < nP[geo.which]) consider(tile + 1);
-    const uint32_t other = 1 - geo.which;
-    const uint32_t placed = other == 0 ? s[0] + s[1] : s[2] + s[3];
-    const uint32_t j = (placed + S - 1) / S;
-    if ((uint64_t)j * S < nP[other]) consider(first[other] + j);
+    const Merge4Bnd n1 = next_boundary(bd, g.m, W, tile, s);
+    uint32_t e[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) e[r] = n1.vec[r];
+    if (tiny(pos, n1)) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) e[r] = s[r];  // absorbed by the tile before
+    } else if (n1.tile >= 0) {
+        const Merge4Bnd n2 = next_boundary(bd, g.m, W, (uint64_t)n1.tile, n1.vec);
+        if (tiny(n1.pos, n2)) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) e[r] = n2.vec[r];  // absorbs the tiny tile after
+        }
+    }
     uint32_t *out = ends + 8 * ((uint64_t)g.split_off + tile);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -314,7 +365,7 @@ __device__ __forceinline__ void merge_lds(const T *sk, uint32_t x0, uint32_t nx,
 
 // LDS layout of a 4-way tile: A | B | max | C | D | max, i.e. tile element el
 // at sk[el + (el >= c2)], with the sentinels merge_lds needs after B (at c2)
-// and after D (at cnt + 1); kMerge4Slack words past them absorb the reads of
+// and after D (at cnt + 1); kMerge4Slack words past them take the reads of
 // threads whose outputs run past the end.
 //
 // Outputs per thread of the pair merges and of the final merge: odd counts
@@ -324,7 +375,12 @@ __device__ __forceinline__ void merge_lds(const T *sk, uint32_t x0, uint32_t nx,
 #define QMS_MERGE_ODD 1
 #endif
 constexpr int kMergeOdd = QMS_MERGE_ODD;
-constexpr int kMerge4Slack = 16 + kMergeOdd;
+// elements of one pair in a 4-way tile (with an absorbed tiny tile), and the
+// outputs per thread that cover them: the pair merges run on half the
+// workgroup, the final merge on all of it (odd, see above)
+constexpr uint32_t kMerge4Pair = kMergeTile + kMerge4Absorb;
+constexpr int kMerge4NBig = (int)((kMerge4Pair + 127) / 128) | kMergeOdd;
+constexpr int kMerge4Slack = kMerge4NBig + 1;
 
 // The two pair merges of a 4-way tile in place: A with B by the first half of
 // the threads, C with D by the second half, N outputs per thread.
@@ -373,8 +429,9 @@ __attribute__((amdgpu_waves_per_eu(QMS_MERGE4_WPE, QMS_MERGE4_WPE))) void k_merg
     TaskRef<SortSeg> tasks, uint32_t level, const uint32_t *bounds, const uint32_t *ends,
     uint32_t *samples_out) {
     constexpr uint32_t S = kMergeTile;
+    constexpr uint32_t SP = kMerge4Pair;  // elements of one pair at most
     constexpr int NT = kMerge4Threads;
-    __shared__ uint32_t sk[2 * S + 2 + kMerge4Slack];
+    __shared__ uint32_t sk[2 * SP + 2 + kMerge4Slack];
     uint32_t tile, a;
     const SortSeg g = task_of(tasks, blockIdx.x, &tile, &a);
     if (tile * (uint64_t)S >= g.m) return;
@@ -390,10 +447,10 @@ __attribute__((amdgpu_waves_per_eu(QMS_MERGE4_WPE, QMS_MERGE4_WPE))) void k_merg
         s[r] = min(ends[at + r], geo.n[r]);
         len[r] = min(max(ends[at + 4 + r], s[r]), geo.n[r]) - s[r];
     }
-    len[1] = min(len[1], S - min(len[0], S));
-    len[0] = min(len[0], S);
-    len[3] = min(len[3], S - min(len[2], S));
-    len[2] = min(len[2], S);
+    len[1] = min(len[1], SP - min(len[0], SP));
+    len[0] = min(len[0], SP);
+    len[3] = min(len[3], SP - min(len[2], SP));
+    len[2] = min(len[2], SP);
     const uint32_t c1 = len[0], c2 = c1 + len[1], c3 = c2 + len[2], cnt = c3 + len[3];
     if (cnt == 0) return;
     const uint64_t ps = (uint64_t)s[0] + s[1] + s[2] + s[3];
@@ -411,11 +468,11 @@ __attribute__((amdgpu_waves_per_eu(QMS_MERGE4_WPE, QMS_MERGE4_WPE))) void k_merg
                (uint32_t)(el >= c3) * d3;
     };
     {
-        // every load of the tile in flight together (up to 2 S / NT per
+        // every load of the tile in flight together (up to 2 SP / NT per
         // thread, as many as the tile needs); the window's buffer element
         // takes its run cell at once (each cell is read and written by the
         // same thread), so no registers hold buffer elements through the merge
-        constexpr int Q = 2 * S / NT;
+        constexpr int Q = (2 * SP + NT - 1) / NT;
         uint32_t v[Q], old[Q];
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
@@ -440,15 +497,17 @@ __attribute__((amdgpu_waves_per_eu(QMS_MERGE4_WPE, QMS_MERGE4_WPE))) void k_merg
     }
     __syncthreads();
     // the merges, with as many outputs per thread as the tile needs (a
-    // typical tile holds kMergeTile elements, half the maximum)
+    // typical tile holds kMergeTile elements, under half the maximum)
+    static_assert((uint32_t)kMerge4NBig * (NT / 2) >= SP && (uint32_t)kMerge4NBig * NT >= 2 * SP,
+                  "outputs per thread cover the largest tile");
     if (c2 <= S / 2 && cnt - c2 <= S / 2)
         merge4_halves<2 * S / NT / 2 + kMergeOdd, NT>(sk, c1, c2, c3, cnt, tid);
     else
-        merge4_halves<2 * S / NT + kMergeOdd, NT>(sk, c1, c2, c3, cnt, tid);
+        merge4_halves<kMerge4NBig, NT>(sk, c1, c2, c3, cnt, tid);
     if (cnt <= S)
         merge4_final<S / NT + kMergeOdd>(sk, c2, cnt, tid);
     else
-        merge4_final<2 * S / NT + kMergeOdd>(sk, c2, cnt, tid);
+        merge4_final<kMerge4NBig>(sk, c2, cnt, tid);
     // samples of the output runs: every kMergeTile-th position of the group
     {
         const uint32_t first = (uint32_t)((S - ps % S) % S);
@@ -457,7 +516,7 @@ __attribute__((amdgpu_waves_per_eu(QMS_MERGE4_WPE, QMS_MERGE4_WPE))) void k_merg
     }
     uint32_t *Tw = rg.dk + geo.gb + ps;
 #pragma unroll
-    for (int q = 0; q < 2 * S / NT; ++q) {
+    for (int q = 0; q < (int)((2 * SP + NT - 1) / NT); ++q) {
         const uint32_t el = q * NT + tid;
         if (el < cnt) stg(Tw + el, O::unord(sk[el]));
     }
