@@ -3,8 +3,10 @@
 // Sec. "QuickMergeXsort": below a size threshold Mergesort hands a block to a
 // sorting algorithm X and then moves the sorted block to the place Mergesort
 // expects it.  Here X is a bitonic sorting network run by one 512-thread
-// workgroup on a tile of kBaseTileKeys keys (kBaseTilePairs key/payload
-// pairs).  Each thread owns ITEMS consecutive elements in registers:
+// workgroup on a tile of kBaseTileKeys 32-bit keys (kBaseTilePairs key/payload
+// pairs or 64-bit keys); the network stops at runs of the Mergesort's run
+// width (X_THRESH) when that is smaller than the tile.  Each thread owns
+// ITEMS consecutive elements in registers:
 //   stride <  ITEMS            compare-exchange inside the thread's registers;
 //   stride <  64 * ITEMS       partner in another lane of the same wave,
 //                              exchanged with a wave shuffle (no barrier);

@@ -27,10 +27,11 @@
 // in their pair, and the place of x among C and D is #(C < x) + #(D < x)
 // (ties go to A, then B, then C, then D), of y among A and B #(A <= y) +
 // #(B <= y): two plain searches each.  A tile runs from one boundary to the
-// next in merge order; it holds at most kMergeTile elements of each pair.
+// next in merge order; it holds at most kMergeTile elements of each pair
+// (kMergeTile + kMerge4Absorb when it absorbs a tiny tile, see below).
 // The workgroup merges A with B and C with D in LDS, then the two results.
 //
-// Ties go to the earlier run.  The split arrays (one word per tile) and the
+// Ties go to the earlier run.  The split arrays (one entry per tile) and the
 // run samples the searches start from are part of the fixed-size workspace.
 #include "qms_device.hpp"
 #include "qms_internal.hpp"
@@ -414,11 +415,11 @@ __device__ __forceinline__ void merge4_final(uint32_t *sk, uint32_t c2, uint32_t
 }
 
 // One workgroup per boundary: the tile from its start vector to its end
-// vector.  The slices A|B|C|D are staged in LDS; A with B and C with D are
-// merged and written back over their own slices, then the two halves are
-// merged the same way; 16 KB of LDS and few registers, so that eight
-// workgroups (as many elements in flight as the 2-way pass) stay resident
-// per CU.
+// vector (empty for an absorbed tile).  The slices A|B|C|D are staged in
+// LDS; A with B and C with D are merged and written back over their own
+// slices, then the two halves are merged the same way; about 18 KB of LDS
+// and few registers, so that eight workgroups (as many elements in flight
+// as the 2-way pass) stay resident per CU.
 #ifndef QMS_MERGE4_WPE
 #define QMS_MERGE4_WPE 8
 #endif
