@@ -47,7 +47,7 @@ static std::map<std::pair<int, hipStream_t>, Workspace *> g_ws;
 
 static size_t ws_words() {
     return 3ull * kCapTiles + 2ull * (kCapTiles + kCapSegs) + 2ull * kCapChunks + 17ull * kCapSplits +
-           4ull * kCapSegs + 256ull * kCapMoM;
+           4ull * kCapSegs + 256ull * kCapMoM + kCapGroups / 4;
 }
 
 int get_workspace(int device, hipStream_t stream, Workspace **out) {
@@ -132,6 +132,8 @@ int get_workspace(int device, hipStream_t stream, Workspace **out) {
     ws->res = w;
     w += 4ull * kCapSegs;
     ws->hist = w;
+    w += 256ull * kCapMoM;
+    ws->gcnt = (uint8_t *)w;
     g_ws[key] = ws;
     *out = ws;
     return QMS_OK;

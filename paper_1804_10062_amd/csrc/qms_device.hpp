@@ -33,7 +33,9 @@ constexpr int kPartItems = kPartSub / kBlock;          // 16
 #endif
 constexpr int kRankChunk = QMS_RANK_CHUNK;  // misplaced pairs exchanged per workgroup
 constexpr uint32_t kMaxTiles = 65536;  // fixed bound on partition tiles
-constexpr int kScanThreads = 1024;     // single-workgroup scan kernels
+constexpr int kScanThreads = 1024;     // block size of the scans of large ranges
+constexpr int kScanPer = 8;            // tiles per thread and step of a scan
+constexpr uint32_t kScanGroups = 16;   // workgroups per segment of the pass-A scan
 constexpr uint64_t kEqBlockMin = 64;   // pivot-equal keys that always get their own block
 
 static_assert(kBaseTileKeys % kMergeTile == 0 && kBaseTilePairs % kMergeTile == 0,
@@ -285,8 +287,8 @@ template <class O>
 __device__ __forceinline__ typename O::K pivot_of(const typename O::K *keys, uint64_t lo,
                                                   uint64_t hi) {
     const uint64_t s = hi - lo;
-    return median3(O::ord(keys[lo]), O::ord(keys[lo + s / 2]),
-                   O::ord(keys[hi - 1]));
+    return median3(O::ord(ldg(keys + lo)), O::ord(ldg(keys + lo + s / 2)),
+                   O::ord(ldg(keys + hi - 1)));
 }
 
 }  // namespace qms

@@ -251,6 +251,11 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
             L.TP = TP;
             L.chunk_span = tune.chunk_span;
             L.scan_threads = max_nt > 4 * kBlock ? kScanThreads : kBlock;
+            {
+                const uint32_t C = L.scan_threads * (uint32_t)kScanPer;
+                L.scan_groups = std::min<uint32_t>((max_nt + C - 1) / C, kScanGroups);
+            }
+            L.groups = (uint64_t)toff * (TP / kWave) <= kCapGroups;
             L.keys_total = (double)sum_s;
             L.ws = &ws;
             L.phase = 0;

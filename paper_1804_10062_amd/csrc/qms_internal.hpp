@@ -16,6 +16,10 @@ constexpr uint32_t kCapSegs = 32768;
 constexpr uint64_t kCapTiles = 1ull << 20;
 // Chunk boundaries of one round: each segment reserves ceil(s / 4096) + 2.
 constexpr uint64_t kCapChunks = (1ull << 21) + 2ull * kCapSegs + 16;
+// Per-wave counts of the partition count (#(< p) in each 64 positions, one
+// byte each) for rounds of at most this many positions (2^31 keys); larger
+// rounds locate their chunk boundaries by walking whole tiles.
+constexpr uint64_t kCapGroups = 1ull << 25;
 // Merge splits of one level: ceil(m / kMergeTile) per task, m < 2^31.
 constexpr uint64_t kCapSplits = (1ull << 31) / kMergeTile + kCapSegs + 16;
 // Segments whose median-of-medians pivot one launch group selects.
@@ -47,6 +51,7 @@ struct Workspace {
     uint64_t *meta = nullptr;    // [kCapSegs * M_COUNT]
     uint32_t *res = nullptr;     // [4 * kCapSegs] per-segment partition results
     uint32_t *hist = nullptr;    // [256 * kCapMoM] median-of-medians select histograms
+    uint8_t *gcnt = nullptr;     // [kCapGroups] #(< p) per 64 positions of a partition
     uint32_t *fbuf = nullptr;    // [2 * kFinalCap] swap space of final ranges
     // task tables: device copies of the host arena below
     void *dtab = nullptr;        // [tab_bytes]
@@ -74,8 +79,10 @@ struct PartitionLaunch {
     TaskRef<PartSeg> tasks;    // table + work prefix of the phase
     uint32_t work;             // work items (workgroups, or waves for splits)
     uint32_t TP;               // partition tile
+    bool groups;               // count A records per-64-position counts (gcnt)
     uint32_t chunk_span;       // target positions per exchange chunk
     uint32_t scan_threads;     // block size of the scans
+    uint32_t scan_groups;      // workgroups per segment of the pass-A scan
     double keys_total;         // keys in all ranges (byte figures)
     double bytes;              // algorithmic bytes of the launch (swap A)
     const Workspace *ws;

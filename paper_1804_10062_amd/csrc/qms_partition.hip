@@ -48,22 +48,23 @@ __device__ __forceinline__ const PartSeg &seg_by_index(const TaskRef<PartSeg> &r
 }
 
 // ---- count -------------------------------------------------------------------
-// One workgroup per tile: #(< p) and #(== p).  Tile 0 of a segment also
-// records the segment's pivot.
+// One workgroup per tile: #(< p) and #(== p).  With `gcnt`, also #(< p) in
+// each 64 positions of the tile (one wave's ballot; a byte per group, TP / 64
+// per tile), from which the split finds a chunk boundary's 64 positions
+// without walking the tile.
 template <class O>
 __global__ __launch_bounds__(kBlock) void k_part_count(TaskRef<PartSeg> tasks, uint32_t TP,
                                                        uint32_t *cnt_lt, uint32_t *cnt_eq,
-                                                       uint64_t *meta) {
+                                                       uint8_t *gcnt, uint64_t *meta) {
     using K = typename O::K;
     __shared__ uint32_t tmp[kWaves + 1];
     uint32_t t, a;
     const PartSeg g = task_of(tasks, blockIdx.x, &t, &a);
     const K *keys = (const K *)g.keys + g.lo;
-    const K p = (g.flags & kPivotMoM) ? (K)meta[(uint64_t)g.slot * M_COUNT + M_PIVOT]
-                                      : pivot_of<O>(keys, 0, g.s);
     const uint64_t ts = (uint64_t)t * TP;
     const uint64_t te = ts + TP < g.s ? ts + TP : g.s;
     uint32_t lt = 0, eq = 0;
+    K p = 0;
     for (uint64_t b = ts; b < te; b += kPartSub) {
         // clamped, unconditional loads (all in flight together); the tail
         // positions are masked out of the counts
@@ -73,13 +74,30 @@ __global__ __launch_bounds__(kBlock) void k_part_count(TaskRef<PartSeg> tasks, u
             const uint64_t pos = b + (uint64_t)q * kBlock + threadIdx.x;
             k[q] = ldg(keys + (pos < te ? pos : te - 1));
         }
+        // the pivot's loads go out behind the tile's (before them, their wait
+        // held the tile's loads back: two memory latencies per workgroup)
+        if (b == ts)
+            p = (g.flags & kPivotMoM) ? (K)ldg(meta + (uint64_t)g.slot * M_COUNT + M_PIVOT)
+                                      : pivot_of<O>(keys, 0, g.s);
+        uint32_t mine = 0;  // lane q: this wave's count in slice q
 #pragma unroll
         for (int q = 0; q < kPartItems; ++q) {
             const uint64_t pos = b + (uint64_t)q * kBlock + threadIdx.x;
             const K x = O::ord(k[q]);
             const bool in = pos < te;
-            lt += in && x < p;
+            const bool less = in && x < p;
+            lt += less;
             eq += in && x == p;
+            if (gcnt) {
+                const uint32_t c = (uint32_t)__popcll(__ballot(less));
+                mine = lane_id() == q ? c : mine;
+            }
+        }
+        if (gcnt && lane_id() < kPartItems) {
+            // the wave's 64 positions of slice `lane`
+            const uint64_t g0 = b + (uint64_t)lane_id() * kBlock + (uint64_t)wave_id() * kWave;
+            if (g0 < te)
+                gcnt[((uint64_t)g.tile_off + t) * (TP / kWave) + (g0 - ts) / kWave] = (uint8_t)mine;
         }
     }
     lt = block_sum(lt, tmp);
@@ -123,7 +141,6 @@ __device__ __forceinline__ void block_count_range(const typename O::K *keys, uin
 // (coalesced loads, all in flight); each thread then scans kScanPer
 // consecutive tiles of the chunk.  ld(t) gives tile t's words, mis(t, w, &l,
 // &r) its counts from them.  Returns the left side's total.
-constexpr int kScanPer = 8;
 template <int NTH>
 struct ScanStage {
     uint2 w[NTH * kScanPer + NTH];  // one spare slot every kScanPer (bank spread)
@@ -185,7 +202,19 @@ __device__ __forceinline__ uint32_t scan_misplaced(uint32_t nt, LD ld, MIS mis, 
 // j * rc of each side.  For every tile, record for each boundary whose rank
 // falls in the tile the tile and the boundary's rank inside it, encoded as
 // t * TP + k (< the range size); k_part_split turns it into a position.
-// Reads the prefixes the block has just written.
+// mark_boundaries does it for the ranks [a, b) of tile t on one side (a
+// 32-bit division: a 64-bit one cost the one-workgroup scans a hundred
+// instructions per tile).
+__device__ __forceinline__ void mark_boundaries(uint32_t *sp, uint32_t a, uint32_t b, uint32_t t,
+                                                uint32_t TP, uint32_t rc, uint32_t nch) {
+    uint32_t j = a / rc;
+    if ((uint64_t)j * rc < a) ++j;
+    if (j == 0) j = 1;
+    for (; j < nch && (uint64_t)j * rc < b; ++j)
+        stg(sp + j, (uint32_t)((uint64_t)t * TP + ((uint64_t)j * rc - a)));
+}
+// The same for every tile of pass B, from the prefixes the block has just
+// written.
 template <int NTH>
 __device__ __forceinline__ void mark_chunk_tiles(uint32_t nt, uint32_t TP, uint32_t rc,
                                                  uint32_t nch, const uint32_t *preL,
@@ -193,11 +222,6 @@ __device__ __forceinline__ void mark_chunk_tiles(uint32_t nt, uint32_t TP, uint3
                                                  uint32_t *spR) {
     __syncthreads();  // prefixes written by other threads of the block
     if (nch <= 1) return;
-    auto mark = [&](uint32_t *sp, uint32_t a, uint32_t b, uint32_t t) {
-        uint64_t j = ((uint64_t)a + rc - 1) / rc;
-        if (j == 0) j = 1;
-        for (; j < nch && j * rc < b; ++j) stg(sp + j, (uint32_t)((uint64_t)t * TP + (j * rc - a)));
-    };
     constexpr uint32_t C = (uint32_t)NTH * 4;
     for (uint32_t c0 = 0; c0 < nt; c0 += C) {
         uint32_t l0[4], l1[4], r0[4], r1[4];
@@ -214,30 +238,37 @@ __device__ __forceinline__ void mark_chunk_tiles(uint32_t nt, uint32_t TP, uint3
         for (int q = 0; q < 4; ++q) {
             const uint32_t t = c0 + (uint32_t)q * NTH + threadIdx.x;
             if (t < nt) {
-                if (l1[q] > l0[q]) mark(spL, l0[q], l1[q], t);
-                if (r1[q] > r0[q]) mark(spR, r0[q], r1[q], t);
+                if (l1[q] > l0[q]) mark_boundaries(spL, l0[q], l1[q], t, TP, rc, nch);
+                if (r1[q] > r0[q]) mark_boundaries(spR, r0[q], r1[q], t, TP, rc, nch);
             }
         }
     }
 }
 
 // ---- scan of pass A ----------------------------------------------------------
-// One workgroup of NTH threads per segment, two passes over the tiles.
-//   1. P[t] = #(< p) in tiles before t (exclusive prefix, written over
-//      cnt_lt, which nothing reads later), the totals c_lt and c_eq; eqmv
-//      is cleared for pass A.
-//   2. With B1 = c_lt in tile tb and lt_part = #(< p) in [tb TP, B1), every
-//      tile left of tb is full and wholly left of B1, so the misplaced
-//      ranks have closed forms:
+// The tiles of a segment are cut into chunks of C = NTH * kScanPer; up to
+// kScanGroups workgroups serve the segment, each owning a run of
+// consecutive chunks.  Every workgroup
+//   1. sums the counts of all tiles (loads and adds only: with no stores in
+//      the loop, the next chunk's loads stay in flight while a chunk is
+//      added up): #(< p) per chunk, whose exclusive prefix is each chunk's
+//      carry, and the totals c_lt and c_eq;
+//   2. with B1 = c_lt in tile tb, lt_part = #(< p) in [tb TP, B1) and
+//      P[t] = #(< p) in tiles before t, every tile left of tb is full and
+//      wholly left of B1, so the misplaced ranks have closed forms:
 //        preL[t] = t TP - P[t]                (t <= tb),  X  (t > tb)
 //        preR[t] = 0                          (t <= tb),  P[t] - P[tb] - lt_part  (t > tb)
-//      with X = c_lt - P[tb] - lt_part pairs.  The pass writes them and
-//      records the tile of every chunk boundary.
-// res[4 a + 0..2] = (#<p, #==p, pass-A pairs) for the host.
+//      with X = c_lt - P[tb] - lt_part pairs.  For its own chunks it writes
+//      them, records the tile of every chunk boundary and clears eqmv.
+// Workgroup 0 writes the round state and res[4 a + 0..2] = (#<p, #==p,
+// pass-A pairs) for the host.  (One workgroup walking all chunks in turn
+// waited at each chunk for the previous chunk's stores to drain, since a
+// load's wait also covers the stores issued before it: about 5 us per
+// 8,192 tiles on the largest ranges.)
 template <class O, int NTH>
 __global__ __launch_bounds__(NTH) void k_part_scan_a(TaskRef<PartSeg> tasks, uint32_t TP,
                                                      uint32_t span,
-                                                     uint32_t *cnt_lt_all,
+                                                     const uint32_t *cnt_lt_all,
                                                      const uint32_t *cnt_eq_all,
                                                      uint32_t *preL_all, uint32_t *preR_all,
                                                      uint32_t *eqmv_all, uint32_t *spL_all,
@@ -245,13 +276,18 @@ __global__ __launch_bounds__(NTH) void k_part_scan_a(TaskRef<PartSeg> tasks, uin
                                                      uint32_t *res) {
     constexpr int PER = kScanPer;
     constexpr uint32_t C = (uint32_t)NTH * PER;
+    constexpr uint32_t kMaxChunks = (uint32_t)(kCapTiles / C) + 1;
+    static_assert(kCapTiles / ((uint64_t)kScanThreads * kScanPer) < kScanThreads,
+                  "one thread per chunk carries the chunks' prefix");
     __shared__ uint32_t tmp[NTH / kWave + 1];
-    __shared__ ScanStage<NTH> stage;
+    __shared__ uint32_t csum[kMaxChunks];  // #(< p) per chunk, then its carry
+    __shared__ uint32_t stage[C + NTH + 1];  // one spare slot every PER (bank spread)
     using K = typename O::K;
-    const PartSeg g = seg_by_index(tasks, blockIdx.x);
+    const uint32_t a = blockIdx.y;
+    const PartSeg g = seg_by_index(tasks, a);
     const K *keys = (const K *)g.keys + g.lo;
-    uint32_t *P = cnt_lt_all + g.tile_off;
-    const uint32_t *cnt_eq = cnt_eq_all + g.tile_off;
+    const uint32_t *LT = cnt_lt_all + g.tile_off;
+    const uint32_t *EQ = cnt_eq_all + g.tile_off;
     uint32_t *preL = preL_all + g.tile_off + g.slot;
     uint32_t *preR = preR_all + g.tile_off + g.slot;
     uint32_t *eqmv = eqmv_all + g.tile_off;
@@ -259,45 +295,48 @@ __global__ __launch_bounds__(NTH) void k_part_scan_a(TaskRef<PartSeg> tasks, uin
     const uint32_t nt = g.nt;
     const uint64_t s = g.s;
     const uint32_t tid = threadIdx.x;
-    const K p = (g.flags & kPivotMoM) ? (K)meta[M_PIVOT] : pivot_of<O>(keys, 0, s);
+    const uint32_t nch_t = (nt + C - 1) / C;  // chunks of tiles
+    const uint32_t G = nch_t < kScanGroups ? nch_t : kScanGroups;
+    if (blockIdx.x >= G) return;
+    const uint32_t k0 = (uint32_t)((uint64_t)blockIdx.x * nch_t / G);
+    const uint32_t k1 = (uint32_t)((uint64_t)(blockIdx.x + 1) * nch_t / G);
+    for (uint32_t k = tid; k < nch_t; k += NTH) csum[k] = 0;
+    const K p = (g.flags & kPivotMoM) ? (K)ldg(meta + M_PIVOT) : pivot_of<O>(keys, 0, s);
+    __syncthreads();
     // pass 1
-    uint32_t carry = 0, seq = 0;
-    for (uint32_t c0 = 0; c0 < nt; c0 += C) {
-        uint2 v[PER];
+    auto load_counts = [&](uint32_t c0, uint2(&v)[PER]) {
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const uint32_t t = c0 + (uint32_t)q * NTH + tid;
-            const uint32_t tc = t < nt ? t : nt - 1;
-            v[q] = make_uint2(ldg(P + tc), ldg(cnt_eq + tc));
+            v[q] = t < nt ? make_uint2(ldg(LT + t), ldg(EQ + t)) : make_uint2(0u, 0u);
         }
+    };
+    uint32_t seq = 0;
+    {
+        uint2 v[PER];
+        load_counts(0, v);
+        for (uint32_t k = 0; k < nch_t; ++k) {
+            uint32_t sl = 0;
 #pragma unroll
-        for (int q = 0; q < PER; ++q) {
-            const uint32_t e = (uint32_t)q * NTH + tid;
-            stage.w[e + e / PER] = v[q];
-            if (c0 + e < nt) stg(eqmv + c0 + e, 0u);
+            for (int q = 0; q < PER; ++q) {
+                sl += v[q].x;
+                seq += v[q].y;
+            }
+            if (k + 1 < nch_t) load_counts((k + 1) * C, v);
+            sl = wave_inclusive_scan(sl);
+            if (lane_id() == kWave - 1) atomicAdd(&csum[k], sl);
         }
-        __syncthreads();
-        uint32_t lt[PER], sl = 0;
-#pragma unroll
-        for (int i = 0; i < PER; ++i) {
-            const uint32_t e = tid * PER + (uint32_t)i;
-            const uint2 w = c0 + e < nt ? stage.w[e + e / PER] : make_uint2(0u, 0u);
-            lt[i] = w.x;
-            sl += w.x;
-            seq += w.y;
-        }
-        uint32_t tot;
-        uint32_t off = carry + block_exclusive_scan(sl, tmp, &tot);  // ends with a barrier
-#pragma unroll
-        for (int i = 0; i < PER; ++i) {
-            const uint32_t t = c0 + tid * PER + (uint32_t)i;
-            if (t < nt) stg(P + t, off);
-            off += lt[i];
-        }
-        carry += tot;
     }
-    const uint64_t c_lt = carry;
-    const uint64_t c_eq_all = block_sum(seq, tmp);
+    __syncthreads();
+    uint64_t c_lt;
+    {
+        const uint32_t mine = tid < nch_t ? csum[tid] : 0u;
+        uint32_t tot;
+        const uint32_t carry = block_exclusive_scan(mine, tmp, &tot);  // ends with a barrier
+        if (tid < nch_t) csum[tid] = carry;
+        c_lt = tot;
+    }
+    const uint64_t c_eq_all = block_sum(seq, tmp);  // (its barriers publish csum)
     // Keys equal to the pivot get a block of their own (pass B) only when
     // there are many of them, or when nothing is smaller than the pivot (then
     // excluding them is what makes the round progress).  Otherwise they stay
@@ -308,50 +347,89 @@ __global__ __launch_bounds__(NTH) void k_part_scan_a(TaskRef<PartSeg> tasks, uin
     const uint32_t tb = (uint32_t)(c_lt / TP);  // tile holding B1 (tb < nt since c_lt < s)
     uint32_t lt_part = 0, eq_part = 0;
     if (c_lt % TP != 0) block_count_range<O>(keys, (uint64_t)tb * TP, c_lt, p, &lt_part, &eq_part, tmp);
-    __syncthreads();  // P written by other threads of the block
-    const uint32_t Ptb = ldg(P + tb);
+    // P[tb]: the carry of tb's chunk and the tiles before tb in it
+    uint32_t Ptb;
+    {
+        const uint32_t kb = tb / C;
+        uint32_t part = 0;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const uint32_t t = kb * C + (uint32_t)q * NTH + tid;
+            part += t < tb ? ldg(LT + t) : 0u;
+        }
+        Ptb = csum[kb] + block_sum(part, tmp);
+    }
     const uint32_t X = (uint32_t)c_lt - Ptb - lt_part;
     const uint32_t rc = rank_chunk(X, s, span);
     const uint32_t nch = (uint32_t)chunk_count(X, s, span);
     uint32_t *spL = spL_all + g.chunk_off, *spR = spR_all + g.chunk_off;
-    // pass 2
+    // pass 2, over this workgroup's chunks
     auto prefix_at = [&](uint32_t t, uint32_t Pt, uint32_t *l, uint32_t *r) {
         *l = t <= tb ? t * TP - Pt : X;
         *r = t <= tb ? 0u : Pt - Ptb - lt_part;
     };
-    auto mark = [&](uint32_t *sp, uint32_t a, uint32_t b, uint32_t t) {
-        uint64_t j = ((uint64_t)a + rc - 1) / rc;
-        if (j == 0) j = 1;
-        for (; j < nch && j * rc < b; ++j) stg(sp + j, (uint32_t)((uint64_t)t * TP + (j * rc - a)));
-    };
-    for (uint32_t c0 = 0; c0 < nt; c0 += C) {
-        uint32_t p0[PER], p1[PER];
+    for (uint32_t k = k0; k < k1; ++k) {
+        const uint32_t c0 = k * C;
+        // #(< p) per tile, coalesced, into LDS; each thread then takes PER
+        // consecutive tiles, and the block scan turns them into P
+        uint32_t v[PER];
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
             const uint32_t t = c0 + (uint32_t)q * NTH + tid;
-            const uint32_t tc = t < nt ? t : nt - 1;
-            p0[q] = ldg(P + tc);
-            p1[q] = tc + 1 < nt ? ldg(P + tc + 1) : (uint32_t)c_lt;
+            v[q] = t < nt ? ldg(LT + t) : 0u;
         }
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
-            const uint32_t t = c0 + (uint32_t)q * NTH + tid;
+            const uint32_t e = (uint32_t)q * NTH + tid;
+            stage[e + e / PER] = v[q];
+        }
+        __syncthreads();
+        uint32_t mine[PER], sl = 0;
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const uint32_t e = tid * PER + (uint32_t)i;
+            mine[i] = stage[e + e / PER];
+            sl += mine[i];
+        }
+        uint32_t tot;
+        uint32_t off = csum[k] + block_exclusive_scan(sl, tmp, &tot);  // ends with a barrier
+#pragma unroll
+        for (int i = 0; i < PER; ++i) {
+            const uint32_t e = tid * PER + (uint32_t)i;
+            stage[e + e / PER] = off;  // P[c0 + e]
+            off += mine[i];
+        }
+        if (tid == NTH - 1) stage[C + C / PER] = off;  // P at the chunk's end
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const uint32_t e = (uint32_t)q * NTH + tid;
+            const uint32_t t = c0 + e;
             if (t < nt) {
+                // P[nt] = c_lt: tiles past nt count zero
+                const uint32_t Pt = stage[e + e / PER], Pt1 = stage[e + 1 + (e + 1) / PER];
                 uint32_t l0, r0, l1, r1;
-                prefix_at(t, p0[q], &l0, &r0);
-                prefix_at(t + 1, p1[q], &l1, &r1);
+                prefix_at(t, Pt, &l0, &r0);
+                prefix_at(t + 1, Pt1, &l1, &r1);
                 stg(preL + t, l0);
                 stg(preR + t, r0);
+                stg(eqmv + t, 0u);
                 if (t == nt - 1) {
                     stg(preL + nt, l1);
                     stg(preR + nt, r1);
                 }
-                if (nch > 1 && l1 > l0) mark(spL, l0, l1, t);
-                if (nch > 1 && r1 > r0) mark(spR, r0, r1, t);
+                if (nch > 1) {
+                    // left of tb only left ranks, right of it only right ones
+                    const bool right = t > tb;
+                    const uint32_t ra = right ? r0 : l0, rb = right ? r1 : l1;
+                    if (rb > ra) mark_boundaries(right ? spR : spL, ra, rb, t, TP, rc, nch);
+                    if (t == tb && r1 > r0) mark_boundaries(spR, r0, r1, t, TP, rc, nch);
+                }
             }
         }
+        __syncthreads();  // the stage is reused by the next chunk
     }
-    if (tid == 0) {
+    if (blockIdx.x == 0 && tid == 0) {
         meta[M_RCA] = rc;
         meta[M_PIVOT] = p;
         meta[M_CLT] = c_lt;
@@ -365,10 +443,10 @@ __global__ __launch_bounds__(NTH) void k_part_scan_a(TaskRef<PartSeg> tasks, uin
         spL[nch] = (uint32_t)c_lt;
         spR[0] = (uint32_t)c_lt;
         spR[nch] = (uint32_t)s;
-        res[4 * blockIdx.x + 0] = (uint32_t)c_lt;
-        res[4 * blockIdx.x + 1] = (uint32_t)c_eq;
-        res[4 * blockIdx.x + 2] = X;
-        res[4 * blockIdx.x + 3] = 0;
+        res[4 * a + 0] = (uint32_t)c_lt;
+        res[4 * a + 1] = (uint32_t)c_eq;
+        res[4 * a + 2] = X;
+        res[4 * a + 3] = 0;
     }
 }
 
@@ -479,11 +557,15 @@ __device__ __forceinline__ bool belongs_left(K k, K p) {
 // holding the boundary and its rank k inside the tile; the wave finds the k-th
 // misplaced element of the tile's part of the region and replaces the record
 // with its position.  The host gives each segment an upper bound of
-// 2 (chunks - 1) waves; surplus waves return.
+// 2 (chunks - 1) waves; surplus waves return.  In pass A, with the count's
+// per-64 counts (`gcnt`) and a tile wholly inside the region, a wave scan
+// over those counts picks the 64 positions that hold the element and one
+// ballot over them finishes; otherwise the wave walks the tile.
 template <class O, int PASS>
 __global__ __launch_bounds__(kBlock) void k_part_split(TaskRef<PartSeg> tasks, uint32_t TP,
                                                        uint32_t total, uint32_t *spL_all,
                                                        uint32_t *spR_all,
+                                                       const uint8_t *gcnt,
                                                        const uint64_t *meta_all) {
     const uint32_t gw = blockIdx.x * kWaves + wave_id();
     if (gw >= total) return;
@@ -509,9 +591,40 @@ __global__ __launch_bounds__(kBlock) void k_part_split(TaskRef<PartSeg> tasks, u
     const uint64_t ts = (uint64_t)t * TP;
     const uint64_t te = ts + TP < s ? ts + TP : s;
     const uint64_t reg0 = side ? geo.r0 : geo.l0, reg1 = side ? geo.r1 : geo.l1;
-    const uint64_t x0 = ts > reg0 ? ts : reg0;
-    const uint64_t x1 = te < reg1 ? te : reg1;
+    uint64_t x0 = ts > reg0 ? ts : reg0;
+    uint64_t x1 = te < reg1 ? te : reg1;
     const int lane = lane_id();
+    if (PASS == 0 && gcnt != nullptr && x0 == ts && x1 == te) {
+        // misplaced elements per 64 positions: #(< p) on the right side,
+        // the rest on the left
+        const uint8_t *gc = gcnt + ((uint64_t)g.tile_off + t) * (TP / kWave);
+        const uint32_t ng = (uint32_t)((te - ts + kWave - 1) / kWave);
+        for (uint32_t g0 = 0; g0 < ng; g0 += kWave) {
+            const uint32_t gi = g0 + (uint32_t)lane;
+            uint32_t c = 0;
+            if (gi < ng) {
+                const uint32_t less = gc[gi];
+                const uint64_t len = te - ts - (uint64_t)gi * kWave;
+                c = side ? less : (uint32_t)(len < kWave ? len : kWave) - less;
+            }
+            const uint32_t inc = wave_inclusive_scan(c);
+            const uint32_t tot = (uint32_t)__shfl((int)inc, kWave - 1);
+            if (k < tot) {
+                const int hit = __ffsll((unsigned long long)__ballot(inc > k)) - 1;
+                k -= (uint32_t)__shfl((int)(inc - c), hit);
+                const uint64_t a0 = ts + (uint64_t)(g0 + (uint32_t)hit) * kWave;
+                const uint64_t pos = a0 + (uint64_t)lane;
+                const bool in = pos < te;
+                const bool bl = belongs_left<PASS>(O::ord(ldg(keys + (in ? pos : te - 1))), p);
+                const uint64_t m = __ballot(in && (side ? bl : !bl));
+                if (((m >> lane) & 1ull) && (uint32_t)__popcll(m & lanemask_lt()) == k)
+                    sp[j] = (uint32_t)pos;
+                return;
+            }
+            k -= tot;
+        }
+        return;  // not reached: the tile holds more than k misplaced elements
+    }
     // the wave walks the part 1024 positions a step, lane-interleaved
     // (coalesced loads, all in flight), and counts misplaced elements with
     // ballots
@@ -746,17 +859,18 @@ static hipError_t partition_t(const PartitionLaunch &L, hipStream_t st) {
         {
             ProfScope prof(st, K_PART_COUNT, (double)sizeof(typename O::K) * L.keys_total);
             hipLaunchKernelGGL((k_part_count<O>), dim3(L.work), dim3(kBlock), 0, st, L.tasks,
-                               L.TP, ws.cnt_lt, ws.cnt_eq, ws.meta);
+                               L.TP, ws.cnt_lt, ws.cnt_eq, L.groups ? ws.gcnt : nullptr,
+                               ws.meta);
         }
         {
             ProfScope prof(st, K_PART_SCAN, 0.0);
             if (L.scan_threads == kScanThreads)
-                hipLaunchKernelGGL((k_part_scan_a<O, kScanThreads>), dim3(L.tasks.A),
+                hipLaunchKernelGGL((k_part_scan_a<O, kScanThreads>), dim3(L.scan_groups, L.tasks.A),
                                    dim3(kScanThreads), 0, st, L.tasks, L.TP, L.chunk_span,
                                    ws.cnt_lt, ws.cnt_eq,
                                    ws.preL, ws.preR, ws.eqmv, ws.spL, ws.spR, ws.meta, ws.res);
             else
-                hipLaunchKernelGGL((k_part_scan_a<O, kBlock>), dim3(L.tasks.A), dim3(kBlock), 0,
+                hipLaunchKernelGGL((k_part_scan_a<O, kBlock>), dim3(L.scan_groups, L.tasks.A), dim3(kBlock), 0,
                                    st, L.tasks, L.TP, L.chunk_span, ws.cnt_lt, ws.cnt_eq,
                                    ws.preL, ws.preR,
                                    ws.eqmv, ws.spL, ws.spR, ws.meta, ws.res);
@@ -770,11 +884,11 @@ static hipError_t partition_t(const PartitionLaunch &L, hipStream_t st) {
         if (L.phase == 1)
             hipLaunchKernelGGL((k_part_split<O, 0>), dim3((L.work + kWaves - 1) / kWaves),
                                dim3(kBlock), 0, st, L.tasks, L.TP, L.work, ws.spL, ws.spR,
-                               ws.meta);
+                               L.groups ? ws.gcnt : nullptr, ws.meta);
         else
             hipLaunchKernelGGL((k_part_split<O, 1>), dim3((L.work + kWaves - 1) / kWaves),
                                dim3(kBlock), 0, st, L.tasks, L.TP, L.work, ws.spL, ws.spR,
-                               ws.meta);
+                               nullptr, ws.meta);
         break;
     }
     case 2: {  // swap of pass A

@@ -100,3 +100,34 @@ def test_batch_config3_20000_arrays_f32():
         got = kt[int(off[j]):int(off[j + 1])].cpu().numpy()
         want, _, _ = oracle.sort(before[j], counted=False)
         np.testing.assert_array_equal(got.view(np.uint32), want.view(np.uint32))
+
+
+@needs_gpu
+def test_batch_segments_with_several_scan_chunks():
+    """Segments above 8,192 partition tiles (2^25 keys at the default tile)
+    are scanned by several workgroups, one row of the scan grid per segment;
+    small segments beside them by one.  Big segments: sorted, same multiset,
+    sampled ranks against the oracle's rank test; small ones: exact."""
+    lens = np.array([(1 << 25) + 4097, 4097, 70_000_001, 1, 300_000, 0, 9], dtype=np.int64)
+    n = int(lens.sum())
+    x = inputs.uniform_u32(n, seed=21)
+    off = inputs.offsets_from_lengths(lens)
+    kt = to_device(x)
+    ot = torch.from_numpy(off.view(np.int64)).cuda()
+    seg = segment_ids(ot, n)
+    h_in = segment_multiset_hash(kt, seg)
+    qms.qms_sort_batch(kt, ot, host_offsets=off)
+    torch.cuda.synchronize()
+    assert segments_sorted(kt, ot)
+    assert segment_multiset_hash(kt, seg) == h_in
+    got = to_host(kt)
+    rng = np.random.default_rng(5)
+    for j, L in enumerate(lens):
+        a, b = int(off[j]), int(off[j + 1])
+        if L > (1 << 25):
+            ks = sorted(set([0, int(L) - 1, int(L) // 2] + rng.integers(0, int(L), 5).tolist()))
+            for k in ks:
+                assert oracle.order_statistic_ok(x[a:b], k, got[a + k]), (j, k)
+        else:
+            want, _, _ = oracle.sort(x[a:b], counted=False)
+            np.testing.assert_array_equal(got[a:b], want)
