@@ -46,7 +46,7 @@ static std::mutex g_ws_mutex;
 static std::map<std::pair<int, hipStream_t>, Workspace *> g_ws;
 
 static size_t ws_words() {
-    return 3ull * kCapTiles + 2ull * (kCapTiles + kCapSegs) + 2ull * kCapChunks + 17ull * kCapSplits +
+    return 3ull * kCapTiles + 2ull * (kCapTiles + kCapSegs) + 2ull * kCapChunks + (13ull + 4ull * kSamplesPerTile) * kCapSplits +
            4ull * kCapSegs + 256ull * kCapMoM + kCapGroups / 4;
 }
 
@@ -122,9 +122,9 @@ int get_workspace(int device, hipStream_t stream, Workspace **out) {
     // run samples hold keys of either width: 2 words per entry (the offsets
     // before them are even, so these arrays are 8-byte aligned)
     ws->samples[0] = w;
-    w += 2ull * kCapSplits;
+    w += 2ull * kSamplesPerTile * kCapSplits;
     ws->samples[1] = w;
-    w += 2ull * kCapSplits;
+    w += 2ull * kSamplesPerTile * kCapSplits;
     ws->bounds = w;
     w += 4ull * kCapSplits;
     ws->ends = w;

@@ -362,14 +362,16 @@ __device__ __forceinline__ void tile_sort_block(typename O::K *sk, uint32_t *sv,
         }
     }
 
-    // 5. back to natural order in LDS, coalesced stores; every kMergeTile-th
-    //    key (order-mapped) is the sample the first merge level searches
+    // 5. back to natural order in LDS, coalesced stores; every
+    //    kSampleStride-th key (order-mapped) is a sample the first merge
+    //    level searches
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) s[nat_idx<ITEMS>(base + i)] = r[i];
     __syncthreads();
-    if (tid * (uint32_t)kMergeTile < len)
-        stg(samples + tid, TE::key(s[nat_idx<ITEMS>(tid * (uint32_t)kMergeTile)]));
+    static_assert((uint32_t)(NT * ITEMS) / kSampleStride <= (uint32_t)NT, "one sample per thread");
+    if (tid * kSampleStride < len)
+        stg(samples + tid, TE::key(s[nat_idx<ITEMS>(tid * kSampleStride)]));
 #pragma unroll 8
     for (int q = 0; q < ITEMS; ++q) {
         const uint32_t e = (uint32_t)q * NT + tid;
@@ -382,8 +384,9 @@ __device__ __forceinline__ void tile_sort_block(typename O::K *sk, uint32_t *sv,
 }
 
 // One workgroup per base tile of every Mergesort task in the table.
-// Samples: one key per kMergeTile keys of each task, at the task's merge
-// split offset (the base tile is a multiple of kMergeTile).  64-bit keys use
+// Samples: one key per kSampleStride keys of each task, kSamplesPerTile
+// entries per merge split tile of the task (the base tile is a multiple of
+// kMergeTile).  64-bit keys use
 // the 8,192-element tile of key/payload pairs.
 template <class O, bool PAIRS>
 __global__ __launch_bounds__(kSortThreads) void k_tile_sort(TaskRef<SortSeg> tasks,
@@ -404,7 +407,8 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_sort(TaskRef<SortSeg> tas
     uint32_t *sv = PAIRS ? g.vals + t0 : nullptr;
     uint32_t *dv = PAIRS ? (swap ? g.bvals : g.vals) + t0 : nullptr;
     tile_sort_block<O, PAIRS>(sk, sv, dk, dv, len, run, swap,
-                              samples + g.split_off + t0 / kMergeTile);
+                              samples + (uint64_t)g.split_off * kSamplesPerTile +
+                                  t0 / kSampleStride);
 }
 
 template <class O, bool PAIRS>

@@ -25,6 +25,17 @@ constexpr uint32_t kBaseTileKeys = 16384;  // base-case tile, keys only
 constexpr uint32_t kBaseTilePairs = 8192;  // base-case tile, key/payload pairs
 constexpr int kMergePerThread = QMS_MERGE_ITEMS;       // outputs per thread
 constexpr int kMergeTile = kBlock * kMergePerThread;   // outputs per workgroup
+// Run samples: every kSampleStride-th element of every sorted run, written by
+// the pass that produced the run; the next pass's split searches start on
+// them and finish inside one sample gap of the runs (a smaller stride leaves
+// fewer cache lines of the runs to touch there).
+#ifndef QMS_SAMPLE_STRIDE
+#define QMS_SAMPLE_STRIDE 256
+#endif
+constexpr uint32_t kSampleStride = QMS_SAMPLE_STRIDE;
+constexpr uint32_t kSamplesPerTile = (uint32_t)kMergeTile / kSampleStride;
+static_assert((uint32_t)kMergeTile % kSampleStride == 0 && kSampleStride >= 64,
+              "samples at a divisor of the merge tile");
 constexpr uint32_t kSplitLanes = QMS_SPLIT_LANES;      // lanes per merge-path split
 constexpr int kPartSub = 4096;         // elements a workgroup classifies per step
 constexpr int kPartItems = kPartSub / kBlock;          // 16

@@ -44,8 +44,9 @@ struct Workspace {
     uint32_t *spL = nullptr;     // [kCapChunks]
     uint32_t *spR = nullptr;     // [kCapChunks]
     uint32_t *splits = nullptr;  // [kCapSplits]
-    uint32_t *samples[2] = {nullptr, nullptr};  // [2 kCapSplits] each: run samples (keys of
-                                                // either width), by pass parity
+    // [2 kSamplesPerTile kCapSplits] each: run samples (keys of either
+    // width), by pass parity
+    uint32_t *samples[2] = {nullptr, nullptr};
     uint32_t *bounds = nullptr;        // [4 * kCapSplits] 4-way pass: tile starts
     uint32_t *ends = nullptr;          // [8 * kCapSplits] 4-way pass: tiles in merge order
     uint64_t *meta = nullptr;    // [kCapSegs * M_COUNT]

@@ -108,9 +108,10 @@ __device__ __forceinline__ uint64_t group_first_false(uint64_t lo, uint64_t hi, 
 // output d, i.e. the number c of elements of run A among the first d outputs
 // (c = the first i with A[i] > B[d - 1 - i], within the diagonal's range
 // [lo, hi]).  The search runs in two stages:
-//   coarse  on the samples of the runs (every kMergeTile-th element, written
-//           by the previous level or the base case; a small array that stays
-//           in cache): with S = kMergeTile and d a multiple of S, the test
+//   coarse  on the samples of the runs (every kSampleStride-th element,
+//           written by the previous level or the base case; a small array
+//           that stays in cache): with S = kSampleStride and d a multiple of
+//           S (d is a multiple of kMergeTile), the test
 //           Q(u): uS <= hi and (d - uS >= |B| or A[(u-1)S] <= B[d - uS])
 //           only reads samples, holds whenever c >= uS, and is prefix-true;
 //           for the last u1 with Q(u1), (u1 - 1) S < c < (u1 + 1) S;
@@ -140,14 +141,14 @@ __device__ __forceinline__ Merge4Geom merge4_geom(uint64_t m, uint64_t W, uint64
 }
 
 // Number of elements of the sorted run Y (nY elements, samples Ys of every
-// kMergeTile-th one) that precede x: #(Y < x) if strict, else #(Y <= x).
+// kSampleStride-th one) that precede x: #(Y < x) if strict, else #(Y <= x).
 // First on the samples (u of them precede x, so the count lies in
 // [(u-1) S + 1, u S]), then inside that gap.  A group collective (every
 // lane of the wave calls it; inactive groups pass nY = 0).
 template <class O>
 __device__ __forceinline__ uint64_t group_count_before(const uint32_t *Y, const uint32_t *Ys,
                                                        uint64_t nY, uint32_t x, bool strict) {
-    constexpr uint64_t S = kMergeTile;
+    constexpr uint64_t S = kSampleStride;
     auto before = [&](uint32_t v) { return strict ? v < x : v <= x; };
     const uint64_t u =
         group_first_false(0, (nY + S - 1) / S, [&](uint64_t i) { return before(ldg(Ys + i)); });
@@ -168,7 +169,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_split(TaskRef<SortSeg> tasks, 
                                                         const typename O::K *samples,
                                                         uint32_t *bounds) {
     using K = typename O::K;
-    constexpr uint64_t S = kMergeTile;
+    constexpr uint64_t S = kSampleStride;
     constexpr uint32_t GPT = BOUNDS ? 2 : 1;  // lane groups per tile
     const uint32_t gid = blockIdx.x * kBlock + threadIdx.x;
     const uint32_t w = gid / (GPT * kSplitLanes);
@@ -181,7 +182,9 @@ __global__ __launch_bounds__(kBlock) void k_merge_split(TaskRef<SortSeg> tasks, 
     const MergeTileGeom geo = merge_geom(g.m, W, tile);
     const K *A = (const K *)rg.sk + geo.pb;
     const K *B = A + W;
-    const K *As = samples + g.split_off + geo.pb / S;
+    // the task's samples start at kSamplesPerTile entries per split tile
+    const K *smp = samples + (uint64_t)g.split_off * kSamplesPerTile;
+    const K *As = smp + geo.pb / S;
     const K *Bs = As + W / S;
     const uint64_t d = geo.d0, nA = geo.lenA, nB = geo.lenB;
     uint64_t lo = d > nB ? d - nB : 0;
@@ -212,7 +215,7 @@ __global__ __launch_bounds__(kBlock) void k_merge_split(TaskRef<SortSeg> tasks, 
         const uint32_t r = (g4.which == 0 ? 2 : 0) + half;
         const uint64_t off = g4.gb + r * W;
         const uint64_t cnt = group_count_before<O>((const K *)rg.sk + off,
-                                                   samples + g.split_off + off / S,
+                                                   smp + off / S,
                                                    active ? g4.n[r] : 0, x, g4.which == 0);
         if (active && gid % kSplitLanes == 0) {
             uint32_t *bd = bounds + 4 * ((uint64_t)g.split_off + tile);
@@ -509,11 +512,15 @@ __attribute__((amdgpu_waves_per_eu(QMS_MERGE4_WPE, QMS_MERGE4_WPE))) void k_merg
         merge4_final<S / NT + kMergeOdd>(sk, c2, cnt, tid);
     else
         merge4_final<kMerge4NBig>(sk, c2, cnt, tid);
-    // samples of the output runs: every kMergeTile-th position of the group
+    // samples of the output runs: every kSampleStride-th position of the group
     {
-        const uint32_t first = (uint32_t)((S - ps % S) % S);
-        const uint32_t el = first + tid * S;
-        if (el < cnt) stg(samples_out + g.split_off + (geo.gb + ps + el) / S, sk[el]);
+        constexpr uint32_t SS = kSampleStride;
+        static_assert((2 * SP + SS - 1) / SS + 1 <= (uint32_t)NT, "one sample per thread");
+        const uint32_t first = (uint32_t)((SS - ps % SS) % SS);
+        const uint32_t el = first + tid * SS;
+        if (el < cnt)
+            stg(samples_out + (uint64_t)g.split_off * kSamplesPerTile + (geo.gb + ps + el) / SS,
+                sk[el]);
     }
     uint32_t *Tw = rg.dk + geo.gb + ps;
 #pragma unroll
@@ -604,8 +611,9 @@ __device__ __forceinline__ void merge_block(typename O::K *S, uint32_t *SV, type
         }
     }
     __syncthreads();
-    // the tile's first output is the sample the next level's split search uses
-    if (tid == 0) stg(samples_out + tile, sk[0]);
+    // the tile's samples for the next level's split search
+    if (tid < kSamplesPerTile && tid * kSampleStride < cnt)
+        stg(samples_out + tile * kSamplesPerTile + tid, sk[tid * kSampleStride]);
 #pragma unroll
     for (int q = 0; q < kMergePerThread; ++q) {
         const uint32_t e = q * kBlock + tid;
@@ -630,7 +638,8 @@ __global__ __launch_bounds__(kBlock) void k_merge(TaskRef<SortSeg> tasks, uint32
     const Regions rg = level_regions(g, level);
     merge_block<O, PAIRS>((K *)rg.sk, PAIRS ? rg.sv : nullptr, (K *)rg.dk,
                           PAIRS ? rg.dv : nullptr, g.m, (uint64_t)g.w0 << level,
-                          tile, splits + g.split_off, samples_out + g.split_off);
+                          tile, splits + g.split_off,
+                          samples_out + (uint64_t)g.split_off * kSamplesPerTile);
 }
 
 template <class O, bool PAIRS>
