@@ -28,9 +28,10 @@
  *     results back to the host once per partition round, so they return
  *     only after the sort has completed on the stream.
  *   - Extra device memory: a library-owned workspace per (device, stream)
- *     of fixed size (tile counters, round state and a 128 MiB scratch buffer
- *     for the last, small ranges; nothing proportional to n), allocated on
- *     first use and kept until qms_release_workspaces().
+ *     of fixed size, about 400 MB (tile counters, run samples, round state
+ *     and a 128 MiB scratch buffer for the last, small ranges; nothing
+ *     proportional to n), allocated on first use and kept until
+ *     qms_release_workspaces().
  *   - Return values are qms_status codes; no C++ exception crosses this
  *     interface.  The message of the last failure on the calling thread is
  *     available from qms_last_error().
