@@ -412,9 +412,10 @@ def main():
         finally:
             autotune.reset_tuning()
 
-    # QuickXsort's other threshold: ranges of at most final_tile keys leave
-    # the loop for one Mergesort into the fixed scratch buffer (8192: the
-    # loop runs down to the base tile)
+    # the recursion stopper: a range a partition round leaves with at most
+    # final_tile keys leaves the loop for one Mergesort into the fixed
+    # scratch buffer (8192: the loop runs down to the base tile, as in the
+    # paper)
     final_sweep = None
     if not args.only_uniform and not args.no_threshold_sweep:
         from paper_1804_10062_amd import autotune

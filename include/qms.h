@@ -236,14 +236,17 @@ int qms_profile_end(qms_kernel_stat *out, int max_entries, int *n_out);
  *                   except that a key-only sort merging four runs per pass
  *                   takes 8192 for a Mergesort whose level count would
  *                   otherwise be odd.
- *   final_tile      ranges of at most this many keys leave the QuickMergesort
- *                   loop (QuickXsort hands small arrays to X): one Mergesort
- *                   finishes each, its swap space taken from a fixed 128 MiB
- *                   scratch buffer of the workspace (2^24 elements, whatever
- *                   n is; a round runs as many as fit); ranges of at most the
- *                   base tile are sorted in place by the base case.  A power
- *                   of two in [8192, 2^24]; 8192 keeps every range in the
- *                   loop down to the base tile.
+ *   final_tile      a range that a partition round leaves with at most this
+ *                   many keys leaves the QuickMergesort loop (a recursion
+ *                   stopper; the paper's loop continues to the base tile):
+ *                   one Mergesort finishes it, its swap space taken from a
+ *                   fixed 128 MiB scratch buffer of the workspace (2^24
+ *                   elements, whatever n is; a round runs as many as fit).
+ *                   Every input array above the base tile is partitioned at
+ *                   least once; arrays of at most the base tile are sorted
+ *                   in place by the base case.  A power of two in
+ *                   [8192, 2^24]; 8192 keeps every range in the loop down to
+ *                   the base tile, as in the paper.
  * qms_set_tuning returns QMS_ERR_INVALID for values out of range (nothing is
  * changed then).  The package's autotuner (paper_1804_10062_amd/autotune.py)
  * picks them for a workload by timing sorts of a sample.

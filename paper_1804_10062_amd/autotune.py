@@ -20,8 +20,8 @@ from . import qms
 FIELDS = ("merge_ways", "partition_tile", "chunk_span", "base_tile", "final_tile")
 # (merge_ways, partition_tile, chunk_span, base_tile, final_tile); base_tile
 # is QuickMergeXsort's X_THRESH, the run width at which the Mergesort calls
-# the base case (0: automatic); final_tile the range size at which a range
-# leaves the loop for one buffered Mergesort
+# the base case (0: automatic); final_tile the range size at or below which
+# a partitioned range leaves the loop for one buffered Mergesort
 CANDIDATES: Tuple[Tuple[int, int, int, int, int], ...] = tuple(
     itertools.product((4, 2), (4096, 8192), (16384, 32768), (0, 8192),
                       (8192, 1 << 18, 1 << 22)))

@@ -178,11 +178,15 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
     const uint64_t ew = wide ? 2 : 1;
     auto kptr = [&](const Seg &g, uint64_t off) { return g.keys + ew * off; };
     auto vptr = [&](const Seg &g, uint64_t off) { return g.vals ? g.vals + off : nullptr; };
-    // TF: ranges of at most TF keys leave the loop (QuickXsort hands small
-    // arrays to X): up to T0 keys the base case sorts them in place; above,
-    // one Mergesort with the library's fixed scratch buffer as swap space
-    // (kFinalCap elements per workspace, whatever n is).  A round runs as
-    // many of them as the buffer holds; the others wait for the next round.
+    // TF: a range that a partition round leaves with at most TF keys leaves
+    // the loop (a recursion stopper; the paper's recursion would continue
+    // down to T0): one Mergesort finishes it with the library's fixed scratch
+    // buffer as swap space (kFinalCap elements per workspace, whatever n is).
+    // A round runs as many of them as the buffer holds; the others wait for
+    // the next round.  An input array of at most T0 keys goes to the base
+    // case in place; every larger one is partitioned at least once, so its
+    // top level is always QuickMergesort's (partition, Mergesort of one side
+    // with the other side as its buffer).
     const uint64_t TF = std::max<uint64_t>(T0, std::min<uint64_t>(tune.final_tile, kFinalCap));
     auto final_task = [&](const Seg &g, uint32_t lo, uint32_t s) {
         SortSeg f{kptr(g, lo), vptr(g, lo), nullptr, nullptr, s, 0, 0, T0, 0, 0};
@@ -196,7 +200,7 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
     for (uint32_t i = 0; i < segs.size(); ++i) {
         const Seg &g = segs[i];
         const uint32_t s = g.hi - g.lo;
-        if (s > TF) active.push_back(i);
+        if (s > T0) active.push_back(i);
         else if (s > 1) ready_finals.push_back(final_task(g, g.lo, s));
     }
     while (!active.empty() || !ready_finals.empty()) {

@@ -1,6 +1,8 @@
-"""The buffered final Mergesort: ranges of at most final_tile keys leave the
-QuickMergesort loop and are finished by one Mergesort whose swap space is
-the library's fixed scratch buffer (QuickXsort hands small arrays to X).
+"""The buffered final Mergesort: a range that a partition round leaves with
+at most final_tile keys leaves the QuickMergesort loop and is finished by
+one Mergesort whose swap space is the library's fixed scratch buffer (a
+recursion stopper; final_tile 8192 runs the paper's loop to the base tile).
+Every input array above the base tile is partitioned at least once.
 Results must be the oracle's bit for bit, whatever path a range takes."""
 import math
 
@@ -28,14 +30,15 @@ def _defaults():
 
 
 def _check_rounds(n: int, tf: int):
-    """The loop runs only while the range exceeds final_tile."""
+    """The first round partitions the whole array (above the base tile);
+    later rounds run only while the range exceeds final_tile."""
     sched = qms.qms_last_schedule()
-    if n <= tf:
+    if n <= qms.qms_get_tiles()["base_tile"]:
         assert sched == [], sched[:2]
-    else:
-        assert len(sched) >= 1
-        for s, *_ in sched:
-            assert s > tf
+        return
+    assert len(sched) >= 1 and sched[0][0] == n
+    for s, *_ in sched[1:]:
+        assert s > tf
 
 
 @needs_gpu
@@ -111,12 +114,14 @@ def test_final_batch_beyond_the_buffer():
     buffered, through the loop) in one batch."""
     qms.qms_set_tuning(4, 4096, 16384, 0, 1 << 22)
     lens = np.concatenate([
-        np.full(5, (1 << 22) - 7, dtype=np.int64),          # buffered finals, 5 x 4M > 2^24
+        # after their first partition the larger sides (at least half of
+        # each) are buffered finals: 9 x 2M > 2^24
+        np.full(9, (1 << 22) - 7, dtype=np.int64),
         np.array([0, 1, 2, 8192, 16384, 16385, (1 << 22) + 9], dtype=np.int64),
         inputs.log_uniform_lengths(200, seed=4, lo_exp=6, hi_exp=18).astype(np.int64)])
     off = inputs.offsets_from_lengths(lens)
     x = inputs.uniform_u32(int(off[-1]), seed=8)
-    assert int(lens[:5].sum()) > FINAL_CAP
+    assert int(lens[:9].sum()) // 2 > FINAL_CAP
     t = to_device(x)
     ot = torch.from_numpy(off.view(np.int64)).cuda()
     qms.qms_sort_batch(t, ot, host_offsets=off)
@@ -144,10 +149,11 @@ def test_final_path_is_the_default_and_large_sorts_use_both():
 
 @needs_gpu
 def test_final_only_rounds_back_to_back():
-    """Twelve buffered finals of almost 2^22 keys fill the scratch buffer
-    four at a time: three rounds in a row without a partition (and so
-    without a readback that synchronises the stream) must each see their own
-    task tables."""
+    """Twelve arrays of almost 2^22 keys: one partition round, then their
+    larger sides (at least 2^21 keys each, 2.4 * 10^7 or more in all) fill
+    the scratch buffer several times: rounds in a row without a partition
+    (and so without a readback that synchronises the stream) must each see
+    their own task tables."""
     qms.qms_set_tuning(4, 4096, 16384, 0, 1 << 22)
     lens = np.concatenate([np.full(12, (1 << 22) - 5, dtype=np.int64),
                            np.array([3, 9000, 20000], dtype=np.int64)])
