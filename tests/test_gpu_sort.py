@@ -213,3 +213,42 @@ def test_reverse_rounds(n):
     x = inputs.reverse_u32(n)
     _sort_and_compare(x)
     assert len(qms.qms_last_schedule()) <= 40
+
+
+def _sliced(t: torch.Tensor, step: int = 1 << 28):
+    return [t[a:a + step] for a in range(0, t.numel(), step)]
+
+
+def _sliced_hash(t: torch.Tensor) -> tuple:
+    """multiset_hash summed over slices (its terms are sums mod 2^64)."""
+    acc = [0, 0]
+    for part in _sliced(t):
+        for q, v in enumerate(multiset_hash(part)):
+            acc[q] = (acc[q] + v) % (1 << 64)
+    return tuple(acc)
+
+
+def _sliced_sorted(t: torch.Tensor, step: int = 1 << 28) -> bool:
+    parts = _sliced(t, step)
+    if not all(is_sorted(p) for p in parts):
+        return False
+    return all(int(as_u64(parts[i][-1:]).item()) <= int(as_u64(parts[i + 1][:1]).item())
+               for i in range(len(parts) - 1))
+
+
+@needs_gpu
+def test_array_above_2_31_keys():
+    """2^31 + 2^20 + 7 uint32 keys (8.6 GB) from the device's seeded
+    generator.  The first partition round holds more keys than the per-64
+    counts cover (its chunk boundaries are found by walking whole tiles), and
+    its scan gives each of its workgroups several chunks of tiles.  Checks
+    that hold at any size: sorted, same multiset (both computed in slices)."""
+    n = (1 << 31) + (1 << 20) + 7
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(31)
+    t = torch.randint(-(1 << 31), 1 << 31, (n,), dtype=torch.int32, device="cuda", generator=gen)
+    h_in = _sliced_hash(t)
+    qms.qms_sort(t)
+    torch.cuda.synchronize()
+    assert _sliced_sorted(t)
+    assert _sliced_hash(t) == h_in
