@@ -18,13 +18,15 @@
 // perfect matching, so every element moves at most once per pass.
 //
 // Kernels, per pass:
-//   count   one workgroup per tile: #(< p) and #(== p) of the tile;
-//   scan    one workgroup: totals, boundary, per-tile misplaced counts and
-//           their exclusive prefix sums (ranks of each tile's first misplaced
-//           element on either side), and for every chunk boundary (rank
-//           j * rc) the tile that holds it;
+//   count   one workgroup per tile: #(< p) and #(== p) of the tile, and
+//           #(< p) of every 64 positions (pass A);
+//   scan    up to kScanGroups workgroups per segment: totals, boundary,
+//           per-tile misplaced counts and their exclusive prefix sums (ranks
+//           of each tile's first misplaced element on either side), and for
+//           every chunk boundary (rank j * rc) the tile that holds it;
 //   split   one wave per chunk boundary and side: the exact position of the
-//           misplaced element of rank j * rc inside that tile;
+//           misplaced element of rank j * rc inside that tile (from the
+//           per-64 counts and one ballot, or by walking the tile);
 //   swap    one workgroup per chunk: reads exactly the position ranges of its
 //           ranks on both sides (coalesced, wave-striped), compacts the
 //           misplaced elements with ballot + prefix counts into LDS, and

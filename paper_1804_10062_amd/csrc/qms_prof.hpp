@@ -11,7 +11,7 @@ enum KernelClass : int {
     K_MERGE_SPLIT,    // merge-path splits of a level
     K_MERGE,          // swap-merge of a level
     K_PART_COUNT,     // partition: per-tile class counts
-    K_PART_SCAN,      // partition: single-workgroup scans
+    K_PART_SCAN,      // partition: scans (pass A, and pass B when it runs)
     K_PART_SPLIT,     // partition: chunk boundary positions
     K_PART_SWAP,      // partition: rank-matched exchange
     K_NUM_CLASSES
