@@ -152,8 +152,11 @@ def bench_batched(qms, torch, np, inputs, per_array_stride: int, reps: int = 3):
     t_per = time.perf_counter() - t0
     batched = n / t_batch / 1e9
     per_array = keys_sub / t_per / 1e9
+    # the per-array sample's input keys, kept on the host for the CPU leg
+    host_sample = [src[int(off[j]):int(off[j + 1])].cpu().numpy().view(np.uint32).copy()
+                   for j in idx]
     del work, src
-    return {
+    return host_sample, {
         "workload": "20,000 float32 arrays, lengths log-uniform in [2^6, 2^20] (seed 5), "
                     f"N(0,1) keys; {n} keys in all",
         "batched_Gkeys_per_s": round(batched, 3),
@@ -439,10 +442,10 @@ def main():
         finally:
             autotune.reset_tuning()
 
-    batched = None
+    batched, batched_host = None, None
     if not args.no_batched:
         print("[bench] batched vs per-array", file=sys.stderr, flush=True)
-        batched = bench_batched(qms, torch, np, inputs, args.per_array_stride)
+        batched_host, batched = bench_batched(qms, torch, np, inputs, args.per_array_stride)
     serving = None
     if not args.no_serving:
         print("[bench] serving", file=sys.stderr, flush=True)
@@ -464,6 +467,26 @@ def main():
                "sample": f"first 2^{args.cpu_sample_log2} keys of the uniform 2^28 workload "
                          "(seed 2), single-threaded C oracle (QuickMergesort of Fig. 2, "
                          "counters compiled out)"}
+        if batched_host is not None:
+            # the batched workload on every host core the box gives one GPU
+            # (at most 16): the per-array sample's arrays, one oracle call
+            # each (ctypes releases the GIL during the call)
+            from concurrent.futures import ThreadPoolExecutor
+            workers = max(1, min(16, os.cpu_count() or 1))
+            keys = int(sum(a.size for a in batched_host))
+            print(f"[bench] cpu oracle on the batched sample, {workers} threads",
+                  file=sys.stderr, flush=True)
+            t0 = time.perf_counter()
+            with ThreadPoolExecutor(max_workers=workers) as ex:
+                list(ex.map(lambda a: oracle.sort_inplace_fast(a, True), batched_host))
+            dt = time.perf_counter() - t0
+            batched["cpu_baseline"] = {
+                "value": round(keys / dt / 1e9, 5), "unit": "Gkeys/s", "cores": workers,
+                "kind": "oracle", "seconds": round(dt, 2),
+                "sample": f"the per-array sample of the batched workload ({len(batched_host)} "
+                          f"float32 arrays, {keys} keys), one C oracle call per array on a "
+                          f"pool of {workers} threads"}
+            del batched_host
 
     out = {
         "metric": "Gkeys/s (uint32, n=2^28) + HBM roofline %; batched vs per-array; p99 latency",
