@@ -182,8 +182,10 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
     // the loop (a recursion stopper; the paper's recursion would continue
     // down to T0): one Mergesort finishes it with the library's fixed scratch
     // buffer as swap space (kFinalCap elements per workspace, whatever n is).
-    // A round runs as many of them as the buffer holds; the others wait for
-    // the next round.  An input array of at most T0 keys goes to the base
+    // A range is handed over only while the next round's buffer has room for
+    // it; otherwise it stays in the loop, so many arrays of a batch do not
+    // queue for the buffer round after round.  An input array of at most T0
+    // keys goes to the base
     // case in place; every larger one is partitioned at least once, so its
     // top level is always QuickMergesort's (partition, Mergesort of one side
     // with the other side as its buffer).
@@ -207,6 +209,25 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
         ArenaUse use(ws, st);
         Arena &ar = use.ar;
         tasks.clear();
+        // ---- the finals that run this round: those above T0 take their swap
+        // space from the scratch buffer while it lasts, the rest wait for the
+        // next round, whose scratch room is what they leave ----
+        uint64_t fused = 0, deferred_keys = 0;
+        deferred.clear();
+        for (SortSeg f : ready_finals) {
+            if (f.m > T0) {
+                if (fused + f.m > kFinalCap) {
+                    deferred.push_back(f);
+                    deferred_keys += f.m;
+                    continue;
+                }
+                f.bkeys = ws.fbuf + ew * fused;
+                f.bvals = pairs ? ws.fbuf + kFinalCap + fused : nullptr;
+                fused += f.m;
+            }
+            tasks.push_back(f);
+        }
+        uint64_t next_room = kFinalCap - std::min<uint64_t>(deferred_keys, kFinalCap);
         const uint32_t A = (uint32_t)active.size();
         if (A > 0) {
             // ---- partition: count + scan A, then read three counters back ----
@@ -374,30 +395,24 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
                 if (log)
                     g_schedule.push_back(
                         {s, c_lt, c_eq, (uint64_t)(s - c_lt - c_eq), t.L, mom ? 1ull : 0ull});
+                // the larger side goes on in the loop unless it is small
+                // enough for the stopper and the next round's scratch has
+                // room for it (without room it is partitioned again, which
+                // needs none: no round waits for the buffer)
                 const uint32_t s2 = g.hi - g.lo;
-                if (s2 > TF) next.push_back(active[a]);
-                else if (s2 > 1) next_finals.push_back(final_task(g, g.lo, s2));
+                if (s2 <= T0) {
+                    if (s2 > 1) next_finals.push_back(final_task(g, g.lo, s2));
+                } else if (s2 <= TF && s2 <= next_room) {
+                    next_finals.push_back(final_task(g, g.lo, s2));
+                    next_room -= s2;
+                } else {
+                    next.push_back(active[a]);
+                }
             }
             active.swap(next);
         }
 
-        // ---- Mergesort tasks of this round and the finals that may run ----
-        // (finals above T0 take their swap space from the scratch buffer
-        // while it lasts; the rest wait for the next round)
-        uint64_t fused = 0;
-        deferred.clear();
-        for (SortSeg f : ready_finals) {
-            if (f.m > T0) {
-                if (fused + f.m > kFinalCap) {
-                    deferred.push_back(f);
-                    continue;
-                }
-                f.bkeys = ws.fbuf + ew * fused;
-                f.bvals = pairs ? ws.fbuf + kFinalCap + fused : nullptr;
-                fused += f.m;
-            }
-            tasks.push_back(f);
-        }
+        // ---- Mergesort tasks of this round (smaller sides and finals) ----
         ready_finals.swap(deferred);
         for (const SortSeg &f : next_finals) ready_finals.push_back(f);
         next_finals.clear();

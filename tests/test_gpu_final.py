@@ -109,9 +109,9 @@ def test_final_64_bit(n):
 
 @needs_gpu
 def test_final_batch_beyond_the_buffer():
-    """More final keys than the scratch buffer holds: the finals that do not
-    fit wait for later rounds.  Segments of every size class (in place,
-    buffered, through the loop) in one batch."""
+    """More small ranges than the scratch buffer holds: those it has no room
+    for stay in the loop (partitioned again) until it has.  Segments of
+    every size class (in place, buffered, through the loop) in one batch."""
     qms.qms_set_tuning(4, 4096, 16384, 0, 1 << 22)
     lens = np.concatenate([
         # after their first partition the larger sides (at least half of
@@ -149,11 +149,11 @@ def test_final_path_is_the_default_and_large_sorts_use_both():
 
 @needs_gpu
 def test_final_only_rounds_back_to_back():
-    """Twelve arrays of almost 2^22 keys: one partition round, then their
-    larger sides (at least 2^21 keys each, 2.4 * 10^7 or more in all) fill
-    the scratch buffer several times: rounds in a row without a partition
-    (and so without a readback that synchronises the stream) must each see
-    their own task tables."""
+    """Twelve arrays of almost 2^22 keys: their larger sides (at least 2^21
+    keys each, 2.4 * 10^7 or more in all) fill the scratch buffer more than
+    once, so some stay in the loop; rounds that end without a partition (no
+    readback that synchronises the stream) must each see their own task
+    tables, and a second call reuses the arenas of the first."""
     qms.qms_set_tuning(4, 4096, 16384, 0, 1 << 22)
     lens = np.concatenate([np.full(12, (1 << 22) - 5, dtype=np.int64),
                            np.array([3, 9000, 20000], dtype=np.int64)])
