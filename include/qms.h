@@ -217,9 +217,10 @@ int qms_profile_end(qms_kernel_stat *out, int max_entries, int *n_out);
  * Run-time tunables, process-wide, read at the start of every sort (the
  * server's worker included); defaults {4, 4096, 16384, 0, 2^22}.  They
  * change speed, never results.
- *   merge_ways      2 or 4: key-only sorts merge four runs per pass (the
- *                   multi-way merging proposed in the paper's Conclusion) or
- *                   two; key/payload sorts always merge two.
+ *   merge_ways      2 or 4: sorts of 32-bit keys (with or without payloads)
+ *                   merge four runs per pass (the multi-way merging proposed
+ *                   in the paper's Conclusion) or two; 64-bit keys always
+ *                   merge two.
  *   partition_tile  keys per counting tile of the partition (a power of two
  *                   in [4096, 65536]); a round with more than 2^20 tiles
  *                   doubles it.
@@ -233,8 +234,8 @@ int qms_profile_end(qms_kernel_stat *out, int max_entries, int *n_out);
  *                   64-bit keys use at most 8192.  16384 = sqrt(2^28), the
  *                   paper's sqrt(n) rule for the 2^28-key workload.  0
  *                   (automatic): 16384 (8192 for pairs and 64-bit keys),
- *                   except that a key-only sort merging four runs per pass
- *                   takes 8192 for a Mergesort whose level count would
+ *                   except that a sort merging four runs per pass takes
+ *                   half of that for a Mergesort whose level count would
  *                   otherwise be odd.
  *   final_tile      a range that a partition round leaves with at most this
  *                   many keys leaves the QuickMergesort loop (a recursion

@@ -18,8 +18,8 @@
 // search inside the merge kernel would probe run cells that neighbouring
 // workgroups are already overwriting with buffer elements.
 //
-// 4-way pass (key-only sorts; the multi-way merging the paper's conclusion
-// proposes): groups of four runs A, B, C, D are merged at once, so a pass
+// 4-way pass (32-bit keys, with or without payloads; the multi-way merging
+// the paper's conclusion proposes): groups of four runs A, B, C, D are merged at once, so a pass
 // moves every element once for two levels of the binary Mergesort.  Its
 // tiles are bounded by exact boundaries that need no multi-way search: the
 // pair splits of (A, B) and (C, D) at every kMergeTile-th element give the
@@ -387,33 +387,56 @@ constexpr int kMerge4NBig = (int)((kMerge4Pair + 127) / 128) | kMergeOdd;
 constexpr int kMerge4Slack = kMerge4NBig + 1;
 
 // The two pair merges of a 4-way tile in place: A with B by the first half of
-// the threads, C with D by the second half, N outputs per thread.
-template <int N, int NT>
-__device__ __forceinline__ void merge4_halves(uint32_t *sk, uint32_t c1, uint32_t c2, uint32_t c3,
-                                              uint32_t cnt, uint32_t tid) {
+// the threads, C with D by the second half, N outputs per thread.  With
+// PAIRS the payloads (sv, same layout) follow their keys: each output's
+// source index in LDS picks its payload.
+constexpr uint32_t kMerge4Lds = 2 * kMerge4Pair + 2 + kMerge4Slack;  // words per LDS array
+template <int N, int NT, bool PAIRS>
+__device__ __forceinline__ void merge4_halves(uint32_t *sk, uint32_t *sv, uint32_t c1, uint32_t c2,
+                                              uint32_t c3, uint32_t cnt, uint32_t tid) {
     const bool cd = tid >= NT / 2;
     const uint32_t d = (cd ? tid - NT / 2 : tid) * N;
     const uint32_t base = cd ? c2 + 1 : 0, nx = cd ? c3 - c2 : c1, n = cd ? cnt - c2 : c2;
     uint32_t o[N];
-    if (d < n) merge_lds<N>(sk, base, nx, base + nx, n - nx, d, o);
+    uint32_t from[PAIRS ? N : 1], ov[PAIRS ? N : 1];
+    if (d < n) {
+        merge_lds<N, PAIRS>(sk, base, nx, base + nx, n - nx, d, o, from);
+        if constexpr (PAIRS) {
+#pragma unroll
+            for (int q = 0; q < N; ++q) ov[q] = sv[min(from[q], kMerge4Lds - 1)];
+        }
+    }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < N; ++q)
-        if (d + q < n) sk[base + d + q] = o[q];
+        if (d + q < n) {
+            sk[base + d + q] = o[q];
+            if constexpr (PAIRS) sv[base + d + q] = ov[q];
+        }
     __syncthreads();
 }
 // The merged pairs sk[0, c2) and sk[c2 + 1, cnt + 1) merged into sk[0, cnt),
 // N outputs per thread.
-template <int N>
-__device__ __forceinline__ void merge4_final(uint32_t *sk, uint32_t c2, uint32_t cnt,
+template <int N, bool PAIRS>
+__device__ __forceinline__ void merge4_final(uint32_t *sk, uint32_t *sv, uint32_t c2, uint32_t cnt,
                                              uint32_t tid) {
     uint32_t o[N];
+    uint32_t from[PAIRS ? N : 1], ov[PAIRS ? N : 1];
     const uint32_t d = tid * N;
-    if (d < cnt) merge_lds<N>(sk, 0, c2, c2 + 1, cnt - c2, d, o);
+    if (d < cnt) {
+        merge_lds<N, PAIRS>(sk, 0, c2, c2 + 1, cnt - c2, d, o, from);
+        if constexpr (PAIRS) {
+#pragma unroll
+            for (int q = 0; q < N; ++q) ov[q] = sv[min(from[q], kMerge4Lds - 1)];
+        }
+    }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < N; ++q)
-        if (d + q < cnt) sk[d + q] = o[q];
+        if (d + q < cnt) {
+            sk[d + q] = o[q];
+            if constexpr (PAIRS) sv[d + q] = ov[q];
+        }
     __syncthreads();
 }
 
@@ -422,20 +445,22 @@ __device__ __forceinline__ void merge4_final(uint32_t *sk, uint32_t c2, uint32_t
 // LDS; A with B and C with D are merged and written back over their own
 // slices, then the two halves are merged the same way; about 18 KB of LDS
 // and few registers, so that eight workgroups (as many elements in flight
-// as the 2-way pass) stay resident per CU.
+// as the 2-way pass) stay resident per CU.  Key/payload pairs take a second
+// LDS array for the payloads (four workgroups per CU).
 #ifndef QMS_MERGE4_WPE
 #define QMS_MERGE4_WPE 8
 #endif
 constexpr int kMerge4Threads = 256;
-template <class O>
+template <class O, bool PAIRS>
 __global__ __launch_bounds__(kMerge4Threads)
-__attribute__((amdgpu_waves_per_eu(QMS_MERGE4_WPE, QMS_MERGE4_WPE))) void k_merge4(
-    TaskRef<SortSeg> tasks, uint32_t level, const uint32_t *bounds, const uint32_t *ends,
-    uint32_t *samples_out) {
+__attribute__((amdgpu_waves_per_eu(PAIRS ? 4 : QMS_MERGE4_WPE, PAIRS ? 4 : QMS_MERGE4_WPE)))
+void k_merge4(TaskRef<SortSeg> tasks, uint32_t level, const uint32_t *bounds,
+              const uint32_t *ends, uint32_t *samples_out) {
     constexpr uint32_t S = kMergeTile;
     constexpr uint32_t SP = kMerge4Pair;  // elements of one pair at most
     constexpr int NT = kMerge4Threads;
-    __shared__ uint32_t sk[2 * SP + 2 + kMerge4Slack];
+    __shared__ uint32_t sk[kMerge4Lds];
+    __shared__ uint32_t sv[PAIRS ? kMerge4Lds : 1];
     uint32_t tile, a;
     const SortSeg g = task_of(tasks, blockIdx.x, &tile, &a);
     if (tile * (uint64_t)S >= g.m) return;
@@ -460,6 +485,8 @@ __attribute__((amdgpu_waves_per_eu(QMS_MERGE4_WPE, QMS_MERGE4_WPE))) void k_merg
     const uint64_t ps = (uint64_t)s[0] + s[1] + s[2] + s[3];
     uint32_t *S_ = rg.sk + geo.gb;
     const uint32_t *T_ = rg.dk + geo.gb + ps;
+    uint32_t *SV_ = PAIRS ? rg.sv + geo.gb : nullptr;
+    const uint32_t *TV_ = PAIRS ? rg.dv + geo.gb + ps : nullptr;
     const uint32_t tid = threadIdx.x;
     // tile element el sits in run r at offset cell(el) from the group base
     // (< 4 W <= m < 2^32); the steps between the runs' offsets are added by
@@ -478,12 +505,17 @@ __attribute__((amdgpu_waves_per_eu(QMS_MERGE4_WPE, QMS_MERGE4_WPE))) void k_merg
         // same thread), so no registers hold buffer elements through the merge
         constexpr int Q = (2 * SP + NT - 1) / NT;
         uint32_t v[Q], old[Q];
+        uint32_t pv[PAIRS ? Q : 1], pold[PAIRS ? Q : 1];
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             if ((uint32_t)q * NT < cnt) {
                 const uint32_t el = min((uint32_t)q * NT + tid, cnt - 1);
                 v[q] = ldg(S_ + cell(el));
                 old[q] = ldg(T_ + el);
+                if constexpr (PAIRS) {
+                    pv[q] = ldg(SV_ + cell(el));
+                    pold[q] = ldg(TV_ + el);
+                }
             }
         }
 #pragma unroll
@@ -492,6 +524,10 @@ __attribute__((amdgpu_waves_per_eu(QMS_MERGE4_WPE, QMS_MERGE4_WPE))) void k_merg
             if (el < cnt) {
                 sk[el + (el >= c2)] = O::ord(v[q]);
                 stg(S_ + cell(el), old[q]);
+                if constexpr (PAIRS) {
+                    sv[el + (el >= c2)] = pv[q];
+                    stg(SV_ + cell(el), pold[q]);
+                }
             }
         }
         if (tid == 0) {
@@ -505,13 +541,13 @@ __attribute__((amdgpu_waves_per_eu(QMS_MERGE4_WPE, QMS_MERGE4_WPE))) void k_merg
     static_assert((uint32_t)kMerge4NBig * (NT / 2) >= SP && (uint32_t)kMerge4NBig * NT >= 2 * SP,
                   "outputs per thread cover the largest tile");
     if (c2 <= S / 2 && cnt - c2 <= S / 2)
-        merge4_halves<2 * S / NT / 2 + kMergeOdd, NT>(sk, c1, c2, c3, cnt, tid);
+        merge4_halves<2 * S / NT / 2 + kMergeOdd, NT, PAIRS>(sk, sv, c1, c2, c3, cnt, tid);
     else
-        merge4_halves<kMerge4NBig, NT>(sk, c1, c2, c3, cnt, tid);
+        merge4_halves<kMerge4NBig, NT, PAIRS>(sk, sv, c1, c2, c3, cnt, tid);
     if (cnt <= S)
-        merge4_final<S / NT + kMergeOdd>(sk, c2, cnt, tid);
+        merge4_final<S / NT + kMergeOdd, PAIRS>(sk, sv, c2, cnt, tid);
     else
-        merge4_final<kMerge4NBig>(sk, c2, cnt, tid);
+        merge4_final<kMerge4NBig, PAIRS>(sk, sv, c2, cnt, tid);
     // samples of the output runs: every kSampleStride-th position of the group
     {
         constexpr uint32_t SS = kSampleStride;
@@ -523,10 +559,14 @@ __attribute__((amdgpu_waves_per_eu(QMS_MERGE4_WPE, QMS_MERGE4_WPE))) void k_merg
                 sk[el]);
     }
     uint32_t *Tw = rg.dk + geo.gb + ps;
+    uint32_t *TVw = PAIRS ? rg.dv + geo.gb + ps : nullptr;
 #pragma unroll
     for (int q = 0; q < (int)((2 * SP + NT - 1) / NT); ++q) {
         const uint32_t el = q * NT + tid;
-        if (el < cnt) stg(Tw + el, O::unord(sk[el]));
+        if (el < cnt) {
+            stg(Tw + el, O::unord(sk[el]));
+            if constexpr (PAIRS) stg(TVw + el, sv[el]);
+        }
     }
 }
 
@@ -667,7 +707,7 @@ static hipError_t merge_t(const TaskRef<SortSeg> &tasks, uint32_t level, uint32_
         }
         return hipGetLastError();
     }
-    if constexpr (!PAIRS && sizeof(K) == 4) {  // 4-way passes: 32-bit keys only
+    if constexpr (sizeof(K) == 4) {  // 4-way passes: 32-bit keys (with or without payloads)
         {
             ProfScope prof(st, K_MERGE_SPLIT, 0.0);
             hipLaunchKernelGGL((k_merge_split<O, false, true>), dim3(2 * sgrid), dim3(kBlock), 0,
@@ -678,8 +718,9 @@ static hipError_t merge_t(const TaskRef<SortSeg> &tasks, uint32_t level, uint32_
         {
             // the same 16 bytes per element as a 2-way pass, for two levels
             ProfScope prof(st, K_MERGE, bytes);
-            hipLaunchKernelGGL((k_merge4<O>), dim3(tiles), dim3(kMerge4Threads), 0, st, tasks, level,
-                               (const uint32_t *)ws.bounds, (const uint32_t *)ws.ends, smp_out);
+            hipLaunchKernelGGL((k_merge4<O, PAIRS>), dim3(tiles), dim3(kMerge4Threads), 0, st, tasks,
+                               level, (const uint32_t *)ws.bounds, (const uint32_t *)ws.ends,
+                               smp_out);
         }
         return hipGetLastError();
     }
