@@ -217,10 +217,9 @@ int qms_profile_end(qms_kernel_stat *out, int max_entries, int *n_out);
  * Run-time tunables, process-wide, read at the start of every sort (the
  * server's worker included); defaults {4, 4096, 16384, 0, 2^22}.  They
  * change speed, never results.
- *   merge_ways      2 or 4: sorts of 32-bit keys (with or without payloads)
- *                   merge four runs per pass (the multi-way merging proposed
- *                   in the paper's Conclusion) or two; 64-bit keys always
- *                   merge two.
+ *   merge_ways      2 or 4: every sort merges four runs per pass (the
+ *                   multi-way merging proposed in the paper's Conclusion) or
+ *                   two.
  *   partition_tile  keys per counting tile of the partition (a power of two
  *                   in [4096, 65536]); a round with more than 2^20 tiles
  *                   doubles it.

@@ -147,8 +147,8 @@ const std::vector<std::array<uint64_t, kScheduleWords>> &last_schedule() { retur
 // Sort a group of segments (count <= kCapSegs, total keys < 2^32).
 static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
                       hipStream_t st, bool log, const Tuning &tune) {
-    // 64-bit keys: twice the bytes per element, the 8,192-element base tile
-    // of key/payload pairs, and 2-way merge passes
+    // 64-bit keys: twice the bytes per element and the 8,192-element base
+    // tile of key/payload pairs
     const bool wide = dtype_wide(dt);
     const double w = (pairs || wide) ? 2.0 : 1.0;
     // T0: the base case's workgroup tile; ranges of at most T0 keys are
@@ -160,7 +160,7 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
     // sorts take half of it when that makes the level count even, so that
     // every pass merges four runs (no 2-way first pass)
     const bool auto_r0 = tune.base_tile == 0;
-    const bool four_way_sort = !wide && tune.merge_ways == 4;
+    const bool four_way_sort = tune.merge_ways == 4;
     const uint32_t R0 = auto_r0 ? T0 : std::min(T0, tune.base_tile);
     auto levels = [](uint64_t m, uint32_t r) -> uint32_t {
         return m > r ? ceil_log2((m + r - 1) / r) : 0;
@@ -419,12 +419,11 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
         if (tasks.empty()) continue;
         // order: tasks with an even level count first, then odd, each by
         // level count descending.  The passes that start at binary level l
-        // then cover a contiguous range: with 4-way passes (32-bit keys,
-        // with or without payloads) the passes at l belong to the tasks with
-        // L > l and L = l (mod 2), the 2-way first passes (l = 0) to the odd
-        // ones; with 2-way passes only (64-bit keys, or merge_ways 2) every
-        // task with L > l runs a 2-way pass at l
-        const bool two = wide || tune.merge_ways == 2;
+        // then cover a contiguous range: with 4-way passes the passes at l
+        // belong to the tasks with L > l and L = l (mod 2), the 2-way first
+        // passes (l = 0) to the odd ones; with 2-way passes only
+        // (merge_ways 2) every task with L > l runs a 2-way pass at l
+        const bool two = tune.merge_ways == 2;
         const bool by_parity = !two;
         std::stable_sort(tasks.begin(), tasks.end(), [&](const SortSeg &x, const SortSeg &y) {
             if (by_parity && (x.L & 1u) != (y.L & 1u)) return (x.L & 1u) < (y.L & 1u);

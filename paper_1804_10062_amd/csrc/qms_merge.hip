@@ -18,8 +18,7 @@
 // search inside the merge kernel would probe run cells that neighbouring
 // workgroups are already overwriting with buffer elements.
 //
-// 4-way pass (32-bit keys, with or without payloads; the multi-way merging
-// the paper's conclusion proposes): groups of four runs A, B, C, D are merged at once, so a pass
+// 4-way pass (the multi-way merging the paper's conclusion proposes): groups of four runs A, B, C, D are merged at once, so a pass
 // moves every element once for two levels of the binary Mergesort.  Its
 // tiles are bounded by exact boundaries that need no multi-way search: the
 // pair splits of (A, B) and (C, D) at every kMergeTile-th element give the
@@ -146,10 +145,12 @@ __device__ __forceinline__ Merge4Geom merge4_geom(uint64_t m, uint64_t W, uint64
 // [(u-1) S + 1, u S]), then inside that gap.  A group collective (every
 // lane of the wave calls it; inactive groups pass nY = 0).
 template <class O>
-__device__ __forceinline__ uint64_t group_count_before(const uint32_t *Y, const uint32_t *Ys,
-                                                       uint64_t nY, uint32_t x, bool strict) {
+__device__ __forceinline__ uint64_t group_count_before(const typename O::K *Y,
+                                                       const typename O::K *Ys, uint64_t nY,
+                                                       typename O::K x, bool strict) {
+    using K = typename O::K;
     constexpr uint64_t S = kSampleStride;
-    auto before = [&](uint32_t v) { return strict ? v < x : v <= x; };
+    auto before = [&](K v) { return strict ? v < x : v <= x; };
     const uint64_t u =
         group_first_false(0, (nY + S - 1) / S, [&](uint64_t i) { return before(ldg(Ys + i)); });
     const uint64_t lo = u == 0 ? 0 : (u - 1) * S + 1;
@@ -391,16 +392,16 @@ constexpr int kMerge4Slack = kMerge4NBig + 1;
 // PAIRS the payloads (sv, same layout) follow their keys: each output's
 // source index in LDS picks its payload.
 constexpr uint32_t kMerge4Lds = 2 * kMerge4Pair + 2 + kMerge4Slack;  // words per LDS array
-template <int N, int NT, bool PAIRS>
-__device__ __forceinline__ void merge4_halves(uint32_t *sk, uint32_t *sv, uint32_t c1, uint32_t c2,
+template <int N, int NT, bool PAIRS, class K>
+__device__ __forceinline__ void merge4_halves(K *sk, uint32_t *sv, uint32_t c1, uint32_t c2,
                                               uint32_t c3, uint32_t cnt, uint32_t tid) {
     const bool cd = tid >= NT / 2;
     const uint32_t d = (cd ? tid - NT / 2 : tid) * N;
     const uint32_t base = cd ? c2 + 1 : 0, nx = cd ? c3 - c2 : c1, n = cd ? cnt - c2 : c2;
-    uint32_t o[N];
+    K o[N];
     uint32_t from[PAIRS ? N : 1], ov[PAIRS ? N : 1];
     if (d < n) {
-        merge_lds<N, PAIRS>(sk, base, nx, base + nx, n - nx, d, o, from);
+        merge_lds<N, PAIRS, K>(sk, base, nx, base + nx, n - nx, d, o, from);
         if constexpr (PAIRS) {
 #pragma unroll
             for (int q = 0; q < N; ++q) ov[q] = sv[min(from[q], kMerge4Lds - 1)];
@@ -417,14 +418,14 @@ __device__ __forceinline__ void merge4_halves(uint32_t *sk, uint32_t *sv, uint32
 }
 // The merged pairs sk[0, c2) and sk[c2 + 1, cnt + 1) merged into sk[0, cnt),
 // N outputs per thread.
-template <int N, bool PAIRS>
-__device__ __forceinline__ void merge4_final(uint32_t *sk, uint32_t *sv, uint32_t c2, uint32_t cnt,
+template <int N, bool PAIRS, class K>
+__device__ __forceinline__ void merge4_final(K *sk, uint32_t *sv, uint32_t c2, uint32_t cnt,
                                              uint32_t tid) {
-    uint32_t o[N];
+    K o[N];
     uint32_t from[PAIRS ? N : 1], ov[PAIRS ? N : 1];
     const uint32_t d = tid * N;
     if (d < cnt) {
-        merge_lds<N, PAIRS>(sk, 0, c2, c2 + 1, cnt - c2, d, o, from);
+        merge_lds<N, PAIRS, K>(sk, 0, c2, c2 + 1, cnt - c2, d, o, from);
         if constexpr (PAIRS) {
 #pragma unroll
             for (int q = 0; q < N; ++q) ov[q] = sv[min(from[q], kMerge4Lds - 1)];
@@ -446,20 +447,23 @@ __device__ __forceinline__ void merge4_final(uint32_t *sk, uint32_t *sv, uint32_
 // slices, then the two halves are merged the same way; about 18 KB of LDS
 // and few registers, so that eight workgroups (as many elements in flight
 // as the 2-way pass) stay resident per CU.  Key/payload pairs take a second
-// LDS array for the payloads (four workgroups per CU).
+// LDS array for the payloads, 64-bit keys twice the words (four workgroups
+// per CU).
 #ifndef QMS_MERGE4_WPE
 #define QMS_MERGE4_WPE 8
 #endif
 constexpr int kMerge4Threads = 256;
 template <class O, bool PAIRS>
 __global__ __launch_bounds__(kMerge4Threads)
-__attribute__((amdgpu_waves_per_eu(PAIRS ? 4 : QMS_MERGE4_WPE, PAIRS ? 4 : QMS_MERGE4_WPE)))
+__attribute__((amdgpu_waves_per_eu((PAIRS || sizeof(typename O::K) == 8) ? 4 : QMS_MERGE4_WPE,
+                                   (PAIRS || sizeof(typename O::K) == 8) ? 4 : QMS_MERGE4_WPE)))
 void k_merge4(TaskRef<SortSeg> tasks, uint32_t level, const uint32_t *bounds,
-              const uint32_t *ends, uint32_t *samples_out) {
+              const uint32_t *ends, typename O::K *samples_out) {
+    using K = typename O::K;
     constexpr uint32_t S = kMergeTile;
     constexpr uint32_t SP = kMerge4Pair;  // elements of one pair at most
     constexpr int NT = kMerge4Threads;
-    __shared__ uint32_t sk[kMerge4Lds];
+    __shared__ K sk[kMerge4Lds];
     __shared__ uint32_t sv[PAIRS ? kMerge4Lds : 1];
     uint32_t tile, a;
     const SortSeg g = task_of(tasks, blockIdx.x, &tile, &a);
@@ -483,8 +487,8 @@ void k_merge4(TaskRef<SortSeg> tasks, uint32_t level, const uint32_t *bounds,
     const uint32_t c1 = len[0], c2 = c1 + len[1], c3 = c2 + len[2], cnt = c3 + len[3];
     if (cnt == 0) return;
     const uint64_t ps = (uint64_t)s[0] + s[1] + s[2] + s[3];
-    uint32_t *S_ = rg.sk + geo.gb;
-    const uint32_t *T_ = rg.dk + geo.gb + ps;
+    K *S_ = (K *)rg.sk + geo.gb;
+    const K *T_ = (const K *)rg.dk + geo.gb + ps;
     uint32_t *SV_ = PAIRS ? rg.sv + geo.gb : nullptr;
     const uint32_t *TV_ = PAIRS ? rg.dv + geo.gb + ps : nullptr;
     const uint32_t tid = threadIdx.x;
@@ -504,7 +508,7 @@ void k_merge4(TaskRef<SortSeg> tasks, uint32_t level, const uint32_t *bounds,
         // takes its run cell at once (each cell is read and written by the
         // same thread), so no registers hold buffer elements through the merge
         constexpr int Q = (2 * SP + NT - 1) / NT;
-        uint32_t v[Q], old[Q];
+        K v[Q], old[Q];
         uint32_t pv[PAIRS ? Q : 1], pold[PAIRS ? Q : 1];
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
@@ -531,8 +535,8 @@ void k_merge4(TaskRef<SortSeg> tasks, uint32_t level, const uint32_t *bounds,
             }
         }
         if (tid == 0) {
-            sk[c2] = 0xffffffffu;
-            sk[cnt + 1] = 0xffffffffu;
+            sk[c2] = key_max<K>();
+            sk[cnt + 1] = key_max<K>();
         }
     }
     __syncthreads();
@@ -558,7 +562,7 @@ void k_merge4(TaskRef<SortSeg> tasks, uint32_t level, const uint32_t *bounds,
             stg(samples_out + (uint64_t)g.split_off * kSamplesPerTile + (geo.gb + ps + el) / SS,
                 sk[el]);
     }
-    uint32_t *Tw = rg.dk + geo.gb + ps;
+    K *Tw = (K *)rg.dk + geo.gb + ps;
     uint32_t *TVw = PAIRS ? rg.dv + geo.gb + ps : nullptr;
 #pragma unroll
     for (int q = 0; q < (int)((2 * SP + NT - 1) / NT); ++q) {
@@ -707,7 +711,7 @@ static hipError_t merge_t(const TaskRef<SortSeg> &tasks, uint32_t level, uint32_
         }
         return hipGetLastError();
     }
-    if constexpr (sizeof(K) == 4) {  // 4-way passes: 32-bit keys (with or without payloads)
+    if constexpr (!PAIRS || sizeof(K) == 4) {  // 4-way passes (payloads with 32-bit keys only)
         {
             ProfScope prof(st, K_MERGE_SPLIT, 0.0);
             hipLaunchKernelGGL((k_merge_split<O, false, true>), dim3(2 * sgrid), dim3(kBlock), 0,
@@ -737,7 +741,7 @@ hipError_t launch_merge_pass(int dt, bool pairs, const TaskRef<SortSeg> &tasks, 
     case 1:
         return pairs ? merge_t<OrdF32, true>(tasks, level, pass, four_way, tiles, bytes, ws, st)
                      : merge_t<OrdF32, false>(tasks, level, pass, four_way, tiles, bytes, ws, st);
-    case 2:  // 64-bit keys: key-only, 2-way passes
+    case 2:  // 64-bit keys: key-only
         return pairs ? hipErrorInvalidValue
                      : merge_t<OrdU64, false>(tasks, level, pass, four_way, tiles, bytes, ws, st);
     case 3:

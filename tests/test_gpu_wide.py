@@ -80,8 +80,8 @@ def test_f64_total_order(n):
 @pytest.mark.parametrize("tuning", [(4, 4096, 16384, 16384), (2, 8192, 32768, 2048),
                                     (4, 4096, 16384, 4096)])
 def test_u64_tunings(tuning):
-    """64-bit sorts run 2-way passes on runs of at most 8,192 keys whatever
-    the tuning says."""
+    """64-bit sorts run on runs of at most 8,192 keys whatever base_tile the
+    tuning names (2-way or 4-way passes as merge_ways says)."""
     qms.qms_set_tuning(*tuning)
     x = u64_keys(400009, seed=3)
     t = dev64(x)
