@@ -232,10 +232,11 @@ int qms_profile_end(qms_kernel_stat *out, int max_entries, int *n_out);
  *                   comparisons, more merge levels.  Key/payload sorts and
  *                   64-bit keys use at most 8192.  16384 = sqrt(2^28), the
  *                   paper's sqrt(n) rule for the 2^28-key workload.  0
- *                   (automatic): 16384 (8192 for pairs and 64-bit keys),
- *                   except that a sort merging four runs per pass takes
- *                   half of that for a Mergesort whose level count would
- *                   otherwise be odd.
+ *                   (automatic): 16384 (8192 for pairs), except that a sort
+ *                   merging four runs per pass takes half of that for a
+ *                   Mergesort whose level count would otherwise be odd;
+ *                   2048 for 64-bit keys, whose network costs more per
+ *                   level than a merge level.
  *   final_tile      a range that a partition round leaves with at most this
  *                   many keys leaves the QuickMergesort loop (a recursion
  *                   stopper; the paper's loop continues to the base tile):

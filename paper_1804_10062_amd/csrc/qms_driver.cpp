@@ -158,10 +158,12 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
     const uint32_t T0 = (pairs || wide) ? kBaseTilePairs : kBaseTileKeys;
     // base_tile 0 (automatic): the whole workgroup tile, except that 4-way
     // sorts take half of it when that makes the level count even, so that
-    // every pass merges four runs (no 2-way first pass)
+    // every pass merges four runs (no 2-way first pass); 64-bit keys take
+    // runs of kMergeTile keys, since their 64-bit network costs more per
+    // level than a merge level (2^27 uint64: 11.0 against 10.6 Gkeys/s)
     const bool auto_r0 = tune.base_tile == 0;
     const bool four_way_sort = tune.merge_ways == 4;
-    const uint32_t R0 = auto_r0 ? T0 : std::min(T0, tune.base_tile);
+    const uint32_t R0 = auto_r0 ? (wide ? (uint32_t)kMergeTile : T0) : std::min(T0, tune.base_tile);
     auto levels = [](uint64_t m, uint32_t r) -> uint32_t {
         return m > r ? ceil_log2((m + r - 1) / r) : 0;
     };
@@ -169,7 +171,7 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
     auto set_levels = [&](SortSeg &t) {
         t.w0 = R0;
         t.L = levels(t.m, R0);
-        if (auto_r0 && four_way_sort && (t.L & 1u)) {
+        if (auto_r0 && four_way_sort && !wide && (t.L & 1u)) {
             t.w0 = R0 / 2;
             t.L = levels(t.m, t.w0);
         }
