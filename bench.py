@@ -241,7 +241,7 @@ def bench_serving(qms, torch, np, inputs, loads, count: int, budget: int = 64 <<
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: qms sorts on one GPU; --gpus {args.gpus} is not supported "
               "(the sort of one array is not sharded across GPUs here)", file=sys.stderr)
         sys.exit(2)
     import numpy as np
