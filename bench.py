@@ -468,9 +468,9 @@ def main():
                          "(seed 2), single-threaded C oracle (QuickMergesort of Fig. 2, "
                          "counters compiled out)"}
         if batched_host is not None:
-            # the batched workload on every host core the box gives one GPU
-            # (at most 16): the per-array sample's arrays, one oracle call
-            # each (ctypes releases the GIL during the call)
+            # the batched workload on the host's cores (at most 16, the
+            # share of one GPU): the per-array sample's arrays, one oracle
+            # call each (ctypes releases the GIL during the call)
             from concurrent.futures import ThreadPoolExecutor
             workers = max(1, min(16, os.cpu_count() or 1))
             keys = int(sum(a.size for a in batched_host))
