@@ -196,3 +196,27 @@ def test_64_bit_rejections():
     lib = qms.load_library()
     rc = lib.qms_sort(buf.data_ptr() + 4, 64, qms.QMS_U64, None)
     assert rc == -2  # QMS_ERR_ALIGN
+
+
+@needs_gpu
+def test_u64_automatic_run_width():
+    """With the automatic X_THRESH, 64-bit keys mergesort from runs of 2,048
+    keys (their network costs more per level than a merge level); keys stay
+    bit-exact with the oracle."""
+    import math
+    defaults = qms.qms_get_tuning()
+    qms.qms_set_tuning(4, 4096, 16384, 0, 8192)
+    try:
+        x = u64_keys(1 << 20, seed=12)
+        t = dev64(x)
+        qms.qms_sort(t)
+        torch.cuda.synchronize()
+        want, _, _ = oracle.sort(x, counted=False)
+        np.testing.assert_array_equal(host64(t), want)
+        sched = qms.qms_last_schedule()
+        assert len(sched) >= 1
+        for s, c_lt, c_eq, c_gt, L, _ in sched:
+            m = min(c_lt, c_gt)
+            assert L == (0 if m <= 2048 else math.ceil(math.log2(math.ceil(m / 2048)))), (s, m, L)
+    finally:
+        qms.qms_set_tuning(*(defaults[f] for f in autotune.FIELDS))
