@@ -18,8 +18,9 @@
 //                cells (the swap-instead-of-move principle of Sec.
 //                "QuickXsort and QuickMergesort"; Fig. 2's msort base case).
 // Short tiles are padded with the largest key; for key/payload pairs each
-// element is (key << 32 | index), so padding sorts after real keys and the
-// payload is gathered through the index at the end.
+// element carries the key above the element's index in the tile, so padding
+// sorts after real keys and the payload is gathered through the index at the
+// end.
 #include <type_traits>
 
 #include "qms_device.hpp"
@@ -37,31 +38,51 @@
 
 namespace qms {
 
+// Element types of the network.  FLIP complements an element's order (the
+// representation of a descending block, see stage 4); F64 marks elements
+// that are positive normal doubles, whose order as doubles is their order as
+// unsigned integers.
 template <bool PAIRS, class K>
 struct TileElem;
 template <>
 struct TileElem<false, uint32_t> {
     using E = uint32_t;
     static constexpr int ITEMS = kBaseTileKeys / kSortThreads;  // 32
+    static constexpr E FLIP = ~0u;
+    static constexpr bool F64 = false;
     __device__ static E make(uint32_t k, uint32_t) { return k; }
     __device__ static E pad(uint32_t) { return 0xFFFFFFFFu; }
     __device__ static uint32_t key(E x) { return x; }
     __device__ static uint32_t index(E) { return 0; }
 };
+// Key/payload pairs: bit 52 (the lowest exponent bit of a double), the key in
+// bits 13..44 and the element's index in the tile in bits 0..12.  Every
+// element is then a positive normal double, so one v_min_f64 and one
+// v_max_f64 settle an in-register compare-exchange (a 64-bit integer compare
+// takes a compare and four selects); complementing bits 0..44 reverses the
+// order and keeps the exponent bit.
 template <>
 struct TileElem<true, uint32_t> {
     using E = uint64_t;
     static constexpr int ITEMS = kBaseTilePairs / kSortThreads;  // 16
-    __device__ static E make(uint32_t k, uint32_t i) { return ((uint64_t)k << 32) | i; }
-    __device__ static E pad(uint32_t i) { return (0xFFFFFFFFull << 32) | i; }
-    __device__ static uint32_t key(E x) { return (uint32_t)(x >> 32); }
-    __device__ static uint32_t index(E x) { return (uint32_t)x; }
+    static constexpr uint32_t IBITS = 13;
+    static constexpr E FLIP = (1ull << (32 + IBITS)) - 1;
+    static constexpr bool F64 = true;
+    __device__ static E make(uint32_t k, uint32_t i) {
+        return (1ull << 52) | ((uint64_t)k << IBITS) | i;
+    }
+    __device__ static E pad(uint32_t i) { return make(0xFFFFFFFFu, i); }
+    __device__ static uint32_t key(E x) { return (uint32_t)(x >> IBITS); }
+    __device__ static uint32_t index(E x) { return (uint32_t)x & ((1u << IBITS) - 1); }
 };
+static_assert(kBaseTilePairs <= (1u << TileElem<true, uint32_t>::IBITS), "tile index bits");
 // 64-bit keys without payload: the element is the order-mapped key itself.
 template <>
 struct TileElem<false, uint64_t> {
     using E = uint64_t;
     static constexpr int ITEMS = kBaseTilePairs / kSortThreads;  // 16
+    static constexpr E FLIP = ~0ull;
+    static constexpr bool F64 = false;
     __device__ static E make(uint64_t k, uint32_t) { return k; }
     __device__ static E pad(uint32_t) { return ~0ull; }
     __device__ static uint64_t key(E x) { return x; }
@@ -74,6 +95,26 @@ __device__ __forceinline__ void cmpx(E &a, E &b, bool asc) {
     const E hi = a < b ? b : a;
     a = asc ? lo : hi;
     b = asc ? hi : lo;
+}
+
+// The same for elements that are positive normal doubles (F64 above): the
+// double min and max of the bit patterns, written as instructions so that
+// no canonicalisation of the operands is added (both return one of the two
+// inputs unchanged for such values).
+__device__ __forceinline__ void cmpx_f64(uint64_t &a, uint64_t &b, bool asc) {
+    uint64_t lo, hi;
+    asm("v_min_f64 %0, %1, %2" : "=v"(lo) : "v"(a), "v"(b));
+    asm("v_max_f64 %0, %1, %2" : "=v"(hi) : "v"(a), "v"(b));
+    a = asc ? lo : hi;
+    b = asc ? hi : lo;
+}
+template <class TE, class E>
+__device__ __forceinline__ void cmpx_elem(E &a, E &b, bool asc) {
+    if constexpr (TE::F64) {
+        cmpx_f64(a, b, asc);
+    } else {
+        cmpx(a, b, asc);
+    }
 }
 
 // One side of a compare-exchange whose partner value is y: the smaller of the
@@ -253,7 +294,7 @@ __device__ __forceinline__ void tile_sort_block(typename O::K *sk, uint32_t *sv,
 #pragma unroll
             for (int i = 0; i < ITEMS; ++i) {
                 const int l = i ^ j;
-                if (l > i) cmpx(r[i], r[l], ((base + i) & k) == 0);
+                if (l > i) cmpx_elem<TE>(r[i], r[l], ((base + i) & k) == 0);
             }
         }
     }
@@ -268,7 +309,7 @@ __device__ __forceinline__ void tile_sort_block(typename O::K *sk, uint32_t *sv,
     //    and the keys are plain again: the tile holds T / run sorted runs.
     E cur_mask = E(0);
     for (uint32_t k = ITEMS; k <= run; k <<= 1) {
-        const E mask = (k == run || (base & k) == 0) ? E(0) : ~E(0);
+        const E mask = (k == run || (base & k) == 0) ? E(0) : TE::FLIP;
         const E flip = mask ^ cur_mask;
         cur_mask = mask;
 #pragma unroll
@@ -357,7 +398,7 @@ __device__ __forceinline__ void tile_sort_block(typename O::K *sk, uint32_t *sv,
 #pragma unroll
             for (int i = 0; i < ITEMS; ++i) {
                 const int l = i ^ jj;
-                if (l > i) cmpx(r[i], r[l], asc);
+                if (l > i) cmpx_elem<TE>(r[i], r[l], asc);
             }
         }
     }
