@@ -32,6 +32,8 @@
 //
 // Ties go to the earlier run.  The split arrays (one entry per tile) and the
 // run samples the searches start from are part of the fixed-size workspace.
+#include <type_traits>
+
 #include "qms_device.hpp"
 #include "qms_internal.hpp"
 #include "qms_prof.hpp"
@@ -344,8 +346,17 @@ __global__ __launch_bounds__(kBlock) void k_merge4_ends(TaskRef<SortSeg> tasks, 
 // sentinel.  A step is two LDS reads at addresses one add from i, a compare
 // and a select.
 // With `from`, also the LDS index each output was read from (to carry
-// payloads along).
-template <int N, bool FROM = false, class T = uint32_t>
+// payloads along).  With HI the elements are 64-bit key/payload words and
+// only their upper halves (the keys) are compared.
+template <bool HI, class T>
+__device__ __forceinline__ bool lds_le(T a, T b) {
+    if constexpr (HI) {
+        return (uint32_t)(a >> 32) <= (uint32_t)(b >> 32);
+    } else {
+        return a <= b;
+    }
+}
+template <int N, bool FROM = false, class T = uint32_t, bool HI = false>
 __device__ __forceinline__ void merge_lds(const T *sk, uint32_t x0, uint32_t nx, uint32_t y0,
                                           uint32_t ny, uint32_t d, T (&out)[N],
                                           uint32_t *from = nullptr) {
@@ -353,7 +364,7 @@ __device__ __forceinline__ void merge_lds(const T *sk, uint32_t x0, uint32_t nx,
     uint32_t lo = d > ny ? d - ny : 0, hi = d < nx ? d : nx;
     while (lo < hi) {
         const uint32_t mid = (lo + hi) >> 1;
-        if (X[mid] <= Y[d - 1 - mid]) lo = mid + 1;
+        if (lds_le<HI>(X[mid], Y[d - 1 - mid])) lo = mid + 1;
         else hi = mid;
     }
     uint32_t i = lo;
@@ -361,7 +372,7 @@ __device__ __forceinline__ void merge_lds(const T *sk, uint32_t x0, uint32_t nx,
 #pragma unroll
     for (int q = 0; q < N; ++q) {
         const T kx = X[i], ky = Yd[q - (int)i];
-        const bool takeX = i < nx && kx <= ky;
+        const bool takeX = i < nx && lds_le<HI>(kx, ky);
         out[q] = takeX ? kx : ky;
         if constexpr (FROM) from[q] = takeX ? x0 + i : y0 + d + q - i;
         i += takeX;
@@ -388,56 +399,35 @@ constexpr int kMerge4NBig = (int)((kMerge4Pair + 127) / 128) | kMergeOdd;
 constexpr int kMerge4Slack = kMerge4NBig + 1;
 
 // The two pair merges of a 4-way tile in place: A with B by the first half of
-// the threads, C with D by the second half, N outputs per thread.  With
-// PAIRS the payloads (sv, same layout) follow their keys: each output's
-// source index in LDS picks its payload.
-constexpr uint32_t kMerge4Lds = 2 * kMerge4Pair + 2 + kMerge4Slack;  // words per LDS array
-template <int N, int NT, bool PAIRS, class K>
-__device__ __forceinline__ void merge4_halves(K *sk, uint32_t *sv, uint32_t c1, uint32_t c2,
-                                              uint32_t c3, uint32_t cnt, uint32_t tid) {
+// the threads, C with D by the second half, N outputs per thread.  LDS
+// elements of type L: the keys, or for key/payload pairs 64-bit words with
+// the key in the upper half (HI), so that a payload moves with its key.
+constexpr uint32_t kMerge4Lds = 2 * kMerge4Pair + 2 + kMerge4Slack;  // elements of the LDS tile
+template <int N, int NT, bool HI, class L>
+__device__ __forceinline__ void merge4_halves(L *sk, uint32_t c1, uint32_t c2, uint32_t c3,
+                                              uint32_t cnt, uint32_t tid) {
     const bool cd = tid >= NT / 2;
     const uint32_t d = (cd ? tid - NT / 2 : tid) * N;
     const uint32_t base = cd ? c2 + 1 : 0, nx = cd ? c3 - c2 : c1, n = cd ? cnt - c2 : c2;
-    K o[N];
-    uint32_t from[PAIRS ? N : 1], ov[PAIRS ? N : 1];
-    if (d < n) {
-        merge_lds<N, PAIRS, K>(sk, base, nx, base + nx, n - nx, d, o, from);
-        if constexpr (PAIRS) {
-#pragma unroll
-            for (int q = 0; q < N; ++q) ov[q] = sv[min(from[q], kMerge4Lds - 1)];
-        }
-    }
+    L o[N];
+    if (d < n) merge_lds<N, false, L, HI>(sk, base, nx, base + nx, n - nx, d, o);
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < N; ++q)
-        if (d + q < n) {
-            sk[base + d + q] = o[q];
-            if constexpr (PAIRS) sv[base + d + q] = ov[q];
-        }
+        if (d + q < n) sk[base + d + q] = o[q];
     __syncthreads();
 }
 // The merged pairs sk[0, c2) and sk[c2 + 1, cnt + 1) merged into sk[0, cnt),
 // N outputs per thread.
-template <int N, bool PAIRS, class K>
-__device__ __forceinline__ void merge4_final(K *sk, uint32_t *sv, uint32_t c2, uint32_t cnt,
-                                             uint32_t tid) {
-    K o[N];
-    uint32_t from[PAIRS ? N : 1], ov[PAIRS ? N : 1];
+template <int N, bool HI, class L>
+__device__ __forceinline__ void merge4_final(L *sk, uint32_t c2, uint32_t cnt, uint32_t tid) {
+    L o[N];
     const uint32_t d = tid * N;
-    if (d < cnt) {
-        merge_lds<N, PAIRS, K>(sk, 0, c2, c2 + 1, cnt - c2, d, o, from);
-        if constexpr (PAIRS) {
-#pragma unroll
-            for (int q = 0; q < N; ++q) ov[q] = sv[min(from[q], kMerge4Lds - 1)];
-        }
-    }
+    if (d < cnt) merge_lds<N, false, L, HI>(sk, 0, c2, c2 + 1, cnt - c2, d, o);
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < N; ++q)
-        if (d + q < cnt) {
-            sk[d + q] = o[q];
-            if constexpr (PAIRS) sv[d + q] = ov[q];
-        }
+        if (d + q < cnt) sk[d + q] = o[q];
     __syncthreads();
 }
 
@@ -446,9 +436,9 @@ __device__ __forceinline__ void merge4_final(K *sk, uint32_t *sv, uint32_t c2, u
 // LDS; A with B and C with D are merged and written back over their own
 // slices, then the two halves are merged the same way; about 18 KB of LDS
 // and few registers, so that eight workgroups (as many elements in flight
-// as the 2-way pass) stay resident per CU.  Key/payload pairs take a second
-// LDS array for the payloads, 64-bit keys twice the words (four workgroups
-// per CU).
+// as the 2-way pass) stay resident per CU.  Key/payload pairs are packed into
+// 64-bit LDS words (key above payload) and 64-bit keys take 64-bit words:
+// twice the LDS, four workgroups per CU.
 #ifndef QMS_MERGE4_WPE
 #define QMS_MERGE4_WPE 8
 #endif
@@ -460,11 +450,20 @@ __attribute__((amdgpu_waves_per_eu((PAIRS || sizeof(typename O::K) == 8) ? 4 : Q
 void k_merge4(TaskRef<SortSeg> tasks, uint32_t level, const uint32_t *bounds,
               const uint32_t *ends, typename O::K *samples_out) {
     using K = typename O::K;
+    static_assert(!PAIRS || sizeof(K) == 4, "pairs carry 32-bit keys");
+    using L = std::conditional_t<PAIRS, uint64_t, K>;  // LDS element
     constexpr uint32_t S = kMergeTile;
     constexpr uint32_t SP = kMerge4Pair;  // elements of one pair at most
     constexpr int NT = kMerge4Threads;
-    __shared__ K sk[kMerge4Lds];
-    __shared__ uint32_t sv[PAIRS ? kMerge4Lds : 1];
+    __shared__ L sk[kMerge4Lds];
+    // the key of an LDS element
+    auto lkey = [](L x) -> K {
+        if constexpr (PAIRS) {
+            return (K)(x >> 32);
+        } else {
+            return x;
+        }
+    };
     uint32_t tile, a;
     const SortSeg g = task_of(tasks, blockIdx.x, &tile, &a);
     if (tile * (uint64_t)S >= g.m) return;
@@ -526,17 +525,18 @@ void k_merge4(TaskRef<SortSeg> tasks, uint32_t level, const uint32_t *bounds,
         for (int q = 0; q < Q; ++q) {
             const uint32_t el = (uint32_t)q * NT + tid;
             if (el < cnt) {
-                sk[el + (el >= c2)] = O::ord(v[q]);
-                stg(S_ + cell(el), old[q]);
                 if constexpr (PAIRS) {
-                    sv[el + (el >= c2)] = pv[q];
+                    sk[el + (el >= c2)] = ((uint64_t)O::ord(v[q]) << 32) | pv[q];
                     stg(SV_ + cell(el), pold[q]);
+                } else {
+                    sk[el + (el >= c2)] = O::ord(v[q]);
                 }
+                stg(S_ + cell(el), old[q]);
             }
         }
-        if (tid == 0) {
-            sk[c2] = key_max<K>();
-            sk[cnt + 1] = key_max<K>();
+        if (tid == 0) {  // the largest key (for pairs in the compared upper half)
+            sk[c2] = PAIRS ? ~L(0) : (L)key_max<K>();
+            sk[cnt + 1] = PAIRS ? ~L(0) : (L)key_max<K>();
         }
     }
     __syncthreads();
@@ -545,13 +545,13 @@ void k_merge4(TaskRef<SortSeg> tasks, uint32_t level, const uint32_t *bounds,
     static_assert((uint32_t)kMerge4NBig * (NT / 2) >= SP && (uint32_t)kMerge4NBig * NT >= 2 * SP,
                   "outputs per thread cover the largest tile");
     if (c2 <= S / 2 && cnt - c2 <= S / 2)
-        merge4_halves<2 * S / NT / 2 + kMergeOdd, NT, PAIRS>(sk, sv, c1, c2, c3, cnt, tid);
+        merge4_halves<2 * S / NT / 2 + kMergeOdd, NT, PAIRS>(sk, c1, c2, c3, cnt, tid);
     else
-        merge4_halves<kMerge4NBig, NT, PAIRS>(sk, sv, c1, c2, c3, cnt, tid);
+        merge4_halves<kMerge4NBig, NT, PAIRS>(sk, c1, c2, c3, cnt, tid);
     if (cnt <= S)
-        merge4_final<S / NT + kMergeOdd, PAIRS>(sk, sv, c2, cnt, tid);
+        merge4_final<S / NT + kMergeOdd, PAIRS>(sk, c2, cnt, tid);
     else
-        merge4_final<kMerge4NBig, PAIRS>(sk, sv, c2, cnt, tid);
+        merge4_final<kMerge4NBig, PAIRS>(sk, c2, cnt, tid);
     // samples of the output runs: every kSampleStride-th position of the group
     {
         constexpr uint32_t SS = kSampleStride;
@@ -560,7 +560,7 @@ void k_merge4(TaskRef<SortSeg> tasks, uint32_t level, const uint32_t *bounds,
         const uint32_t el = first + tid * SS;
         if (el < cnt)
             stg(samples_out + (uint64_t)g.split_off * kSamplesPerTile + (geo.gb + ps + el) / SS,
-                sk[el]);
+                lkey(sk[el]));
     }
     K *Tw = (K *)rg.dk + geo.gb + ps;
     uint32_t *TVw = PAIRS ? rg.dv + geo.gb + ps : nullptr;
@@ -568,8 +568,9 @@ void k_merge4(TaskRef<SortSeg> tasks, uint32_t level, const uint32_t *bounds,
     for (int q = 0; q < (int)((2 * SP + NT - 1) / NT); ++q) {
         const uint32_t el = q * NT + tid;
         if (el < cnt) {
-            stg(Tw + el, O::unord(sk[el]));
-            if constexpr (PAIRS) stg(TVw + el, sv[el]);
+            const L x = sk[el];
+            stg(Tw + el, O::unord(lkey(x)));
+            if constexpr (PAIRS) stg(TVw + el, (uint32_t)x);
         }
     }
 }
