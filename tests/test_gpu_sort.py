@@ -99,7 +99,13 @@ def test_extreme_u32_values():
                                     ("uniform_f32", 123457), ("uniform", 8191),
                                     ("uniform", 8193), ("sorted_swaps", 70001)])
 def test_pairs(kind, n):
-    k = inputs.make_keys(kind, n, seed=4)
+    _pairs_and_compare(inputs.make_keys(kind, n, seed=4))
+
+
+def _pairs_and_compare(k: np.ndarray):
+    """Sort k with payload = index: keys bit-exact with the oracle, payloads
+    a permutation that carries every key to its place."""
+    n = k.size
     kt = to_device(k)
     k_in = kt.clone()
     vt = torch.arange(n, dtype=torch.int32, device="cuda")
@@ -108,6 +114,30 @@ def test_pairs(kind, n):
     check_pairs_exact(k_in, kt, vt)
     want, _, _ = oracle.sort(k, counted=False)
     np.testing.assert_array_equal(to_host(kt).view(np.uint32), want.view(np.uint32))
+
+
+@needs_gpu
+@pytest.mark.parametrize("n", [8191, 8193, 50001])
+def test_pairs_extreme_keys(n):
+    """Pairs whose keys sit at the ends and the middle of the unsigned order
+    (the largest equals the base case's padding key), with ragged tails of
+    the 8,192-pair base tile."""
+    rng = np.random.default_rng(n)
+    vals = np.array([0, 1, 0x7FFFFFFF, 0x80000000, 0xFFFFFFFE, 0xFFFFFFFF], dtype=np.uint32)
+    _pairs_and_compare(rng.choice(vals, n))
+
+
+@needs_gpu
+def test_pairs_f32_special_values():
+    """f32 pairs over zeros of both signs, infinities, denormals, the largest
+    finite values and NaN bit patterns, among normal keys."""
+    specials = np.array([0.0, -0.0, 1.0, -1.0, np.inf, -np.inf, 1e-45, -1e-45,
+                         3.4e38, -3.4e38], dtype=np.float32).view(np.uint32)
+    nan_bits = np.array([0x7FC00000, 0xFFC00000, 0x7F800001, 0xFF800001], dtype=np.uint32)
+    rng = np.random.default_rng(5)
+    x = np.concatenate([np.tile(specials, 900), np.tile(nan_bits, 400),
+                        inputs.normal_f32(7001, seed=6).view(np.uint32)])
+    _pairs_and_compare(x[rng.permutation(x.size)].view(np.float32))
 
 
 @needs_gpu
