@@ -210,6 +210,34 @@ __device__ __forceinline__ void lane_step_u64(uint64_t (&r)[ITEMS], uint32_t lan
     }
 }
 
+// Lane masks 16 and 32 for key/payload elements: as in lane_step_u32, permlane
+// swaps of register pairs (one per 32-bit half) bring both elements of each
+// compare pair into one lane, one ascending compare-exchange settles them
+// (double min/max for the F64 encoding), and the same swaps restore the
+// layout.  Every block is ascending here, so the lower lane keeps the
+// smaller element.
+template <class TE, int LM, int ITEMS>
+__device__ __forceinline__ void lane_step_swap64(uint64_t (&r)[ITEMS]) {
+    static_assert(ITEMS % 2 == 0 && (LM == 16 || LM == 32), "register pairs");
+    auto swap = [](uint32_t x, uint32_t y) {
+        const auto t = LM == 32 ? __builtin_amdgcn_permlane32_swap(x, y, false, false)
+                                : __builtin_amdgcn_permlane16_swap(x, y, false, false);
+        return t;
+    };
+#pragma unroll
+    for (int i = 0; i < ITEMS; i += 2) {
+        const auto tl = swap((uint32_t)r[i], (uint32_t)r[i + 1]);
+        const auto th = swap((uint32_t)(r[i] >> 32), (uint32_t)(r[i + 1] >> 32));
+        uint64_t a = ((uint64_t)(uint32_t)th[0] << 32) | (uint32_t)tl[0];
+        uint64_t b = ((uint64_t)(uint32_t)th[1] << 32) | (uint32_t)tl[1];
+        cmpx_elem<TE>(a, b, true);
+        const auto ul = swap((uint32_t)a, (uint32_t)b);
+        const auto uh = swap((uint32_t)(a >> 32), (uint32_t)(b >> 32));
+        r[i] = ((uint64_t)(uint32_t)uh[0] << 32) | (uint32_t)ul[0];
+        r[i + 1] = ((uint64_t)(uint32_t)uh[1] << 32) | (uint32_t)ul[1];
+    }
+}
+
 // Padded LDS index of element e of the tile in natural order: one spare slot
 // every ITEMS slots, so that thread t reading its ITEMS consecutive elements
 // and lanes reading consecutive elements both avoid bank conflicts.
@@ -356,12 +384,23 @@ __device__ __forceinline__ void tile_sort_block(typename O::K *sk, uint32_t *sv,
             }
             j = ITEMS / 2;
         } else {
+            // pairs take the register-pair swaps at masks 16 and 32; for
+            // 64-bit keys (an integer compare and four selects per pair) the
+            // partner exchange measured slightly faster
             switch (j / ITEMS) {
             case 32:
-                lane_step_u64<32>(r, lane);
+                if constexpr (TE::F64) {
+                    lane_step_swap64<TE, 32>(r);
+                } else {
+                    lane_step_u64<32>(r, lane);
+                }
                 [[fallthrough]];
             case 16:
-                lane_step_u64<16>(r, lane);
+                if constexpr (TE::F64) {
+                    lane_step_swap64<TE, 16>(r);
+                } else {
+                    lane_step_u64<16>(r, lane);
+                }
                 [[fallthrough]];
             case 8:
                 lane_step_u64<8>(r, lane);
