@@ -238,6 +238,30 @@ __device__ __forceinline__ void lane_step_swap64(uint64_t (&r)[ITEMS]) {
     }
 }
 
+// Lane masks 1, 2, 4 and 8 for the F64 encoding: during the step at mask LM
+// the lanes with bit LM set hold their elements negated (sign bit set; sign
+// tracks what a lane's elements carry), so one double min of the own element
+// and the negated partner keeps the smaller element in the lower lane and the
+// negated larger one in the upper lane.  The caller clears the signs after
+// the last step.
+template <int LM, int ITEMS>
+__device__ __forceinline__ void lane_step_neg64(uint64_t (&r)[ITEMS], uint32_t lane,
+                                                uint32_t &sign) {
+    const uint32_t want = (lane & LM) ? 0x80000000u : 0u;
+    const uint64_t flip = (uint64_t)(want ^ sign) << 32;
+    sign = want;
+#pragma unroll
+    for (int i = 0; i < ITEMS; ++i) {
+        r[i] ^= flip;
+        const uint32_t lo = dpp_partner<LM>((uint32_t)r[i], lane);
+        const uint32_t hi = dpp_partner<LM>((uint32_t)(r[i] >> 32), lane);
+        const uint64_t y = ((uint64_t)hi << 32) | lo;
+        uint64_t m;
+        asm("v_min_f64 %0, %1, -%2" : "=v"(m) : "v"(r[i]), "v"(y));
+        r[i] = m;
+    }
+}
+
 // Padded LDS index of element e of the tile in natural order: one spare slot
 // every ITEMS slots, so that thread t reading its ITEMS consecutive elements
 // and lanes reading consecutive elements both avoid bank conflicts.
@@ -384,40 +408,47 @@ __device__ __forceinline__ void tile_sort_block(typename O::K *sk, uint32_t *sv,
             }
             j = ITEMS / 2;
         } else {
-            // pairs take the register-pair swaps at masks 16 and 32; for
-            // 64-bit keys (an integer compare and four selects per pair) the
-            // partner exchange measured slightly faster
-            switch (j / ITEMS) {
-            case 32:
-                if constexpr (TE::F64) {
-                    lane_step_swap64<TE, 32>(r);
-                } else {
+            // pairs take the register-pair swaps at masks 16 and 32 and the
+            // signed minimum below; for 64-bit keys (an integer compare and
+            // four selects per pair) the partner exchange at every mask
+            // measured slightly faster than the swaps
+            if constexpr (TE::F64) {
+                const uint32_t lm0 = j / ITEMS;
+                if (lm0 >= 32) lane_step_swap64<TE, 32>(r);
+                if (lm0 >= 16) lane_step_swap64<TE, 16>(r);
+                uint32_t sign = 0;
+                if (lm0 >= 8) lane_step_neg64<8>(r, lane, sign);
+                if (lm0 >= 4) lane_step_neg64<4>(r, lane, sign);
+                if (lm0 >= 2) lane_step_neg64<2>(r, lane, sign);
+                if (lm0 >= 1) lane_step_neg64<1>(r, lane, sign);
+#pragma unroll
+                for (int i = 0; i < ITEMS; ++i) r[i] ^= (uint64_t)sign << 32;
+                j = ITEMS / 2;
+            } else {
+                switch (j / ITEMS) {
+                case 32:
                     lane_step_u64<32>(r, lane);
-                }
-                [[fallthrough]];
-            case 16:
-                if constexpr (TE::F64) {
-                    lane_step_swap64<TE, 16>(r);
-                } else {
+                    [[fallthrough]];
+                case 16:
                     lane_step_u64<16>(r, lane);
+                    [[fallthrough]];
+                case 8:
+                    lane_step_u64<8>(r, lane);
+                    [[fallthrough]];
+                case 4:
+                    lane_step_u64<4>(r, lane);
+                    [[fallthrough]];
+                case 2:
+                    lane_step_u64<2>(r, lane);
+                    [[fallthrough]];
+                case 1:
+                    lane_step_u64<1>(r, lane);
+                    [[fallthrough]];
+                default:
+                    break;
                 }
-                [[fallthrough]];
-            case 8:
-                lane_step_u64<8>(r, lane);
-                [[fallthrough]];
-            case 4:
-                lane_step_u64<4>(r, lane);
-                [[fallthrough]];
-            case 2:
-                lane_step_u64<2>(r, lane);
-                [[fallthrough]];
-            case 1:
-                lane_step_u64<1>(r, lane);
-                [[fallthrough]];
-            default:
-                break;
+                j = ITEMS / 2;
             }
-            j = ITEMS / 2;
         }
         for (; j >= (uint32_t)ITEMS; j >>= 1) {
             const uint32_t lm = j / ITEMS;
