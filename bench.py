@@ -166,8 +166,10 @@ def bench_batched(qms, torch, np, inputs, per_array_stride: int, reps: int = 3):
                             f"{keys_sub} keys), one qms_sort call each",
         "speedup": round(batched / per_array, 2),
         "tuning": tune["best"],
-        "autotune_trials_ms": {f"{t['merge_ways']}way/{t['partition_tile']}/{t['chunk_span']}":
-                               t["ms"] for t in tune["trials"]},
+        # every candidate the autotuner timed, keyed by all five tunables
+        "autotune_trials_ms": {"/".join(str(t[f]) for f in autotune.FIELDS): t["ms"]
+                               for t in tune["trials"]},
+        "autotune_key": "/".join(autotune.FIELDS),
     }
 
 

@@ -35,6 +35,10 @@
  *   - Return values are qms_status codes; no C++ exception crosses this
  *     interface.  The message of the last failure on the calling thread is
  *     available from qms_last_error().
+ *   - Threads: every entry point may be called from any host thread.  Sorts
+ *     issued on the same (device, stream) share that stream's workspace and
+ *     run one after another (a call waits for another thread's call on the
+ *     same stream to return); sorts on different streams run concurrently.
  */
 #ifndef QMS_H
 #define QMS_H
@@ -122,13 +126,18 @@ typedef struct qms_server qms_server;
 int qms_server_create(const qms_server_config *cfg, qms_server **out);
 
 /*
- * Submit one request: sort n keys of dtype dt (QMS_U32 or QMS_F32) at d_keys
- * (device memory of the server's device), in place.  *ticket_out receives a
- * ticket.  Returns QMS_ERR_BUDGET if n * 4 bytes alone exceed the budget
- * (never admissible), QMS_ERR_UNSUPPORTED for other dtypes.
+ * Submit one request: sort n keys of dtype dt (any qms_dtype; 8-byte aligned
+ * for 64-bit keys) at d_keys (device memory of the server's device), in
+ * place.  `stream` is the stream whose work produced the keys: the server
+ * records an event on it at submit and sorts the request only after the
+ * work enqueued there before the submit has run (0 = the null stream).
+ * *ticket_out receives a ticket.  Returns QMS_ERR_BUDGET if the request's
+ * n * 4 (64-bit keys: n * 8) bytes alone exceed the budget (never
+ * admissible), QMS_ERR_UNSUPPORTED for an unknown dtype, QMS_ERR_HIP if the
+ * event cannot be recorded on `stream`.
  */
 int qms_server_submit(qms_server *srv, void *d_keys, uint64_t n, int dt,
-                      uint64_t *ticket_out);
+                      hipStream_t stream, uint64_t *ticket_out);
 
 /*
  * Poll a ticket: QMS_PENDING while queued or running; QMS_OK once the keys
@@ -158,7 +167,9 @@ int qms_server_destroy(qms_server *srv);
 /* Message of the last failure on the calling thread ("" if none). */
 const char *qms_last_error(void);
 
-/* Free the cached workspaces of all devices and streams. */
+/* Free the cached workspaces of all devices and streams.  A workspace in use
+ * (a sort running on another thread, or a live server's) is kept, and
+ * QMS_ERR_INVALID reports that one was. */
 int qms_release_workspaces(void);
 
 /*

@@ -50,14 +50,40 @@ static size_t ws_words() {
            4ull * kCapSegs + 256ull * kCapMoM + kCapGroups / 4;
 }
 
-int get_workspace(int device, hipStream_t stream, Workspace **out) {
-    std::lock_guard<std::mutex> lock(g_ws_mutex);
-    auto key = std::make_pair(device, stream);
-    auto it = g_ws.find(key);
-    if (it != g_ws.end()) {
-        *out = it->second;
-        return QMS_OK;
+void WorkspaceLease::reset() {
+    if (ws_) {
+        ws_->mu.unlock();
+        ws_->users.fetch_sub(1);
+        ws_ = nullptr;
     }
+}
+
+static int create_workspace(int device, hipStream_t stream, Workspace **out);
+
+int get_workspace(int device, hipStream_t stream, WorkspaceLease *lease) {
+    lease->reset();
+    Workspace *ws = nullptr;
+    {
+        // the user count is raised under the map's lock, so that a release
+        // (which holds that lock) sees every lease taken or waiting
+        std::lock_guard<std::mutex> lock(g_ws_mutex);
+        auto key = std::make_pair(device, stream);
+        auto it = g_ws.find(key);
+        if (it != g_ws.end()) {
+            ws = it->second;
+        } else {
+            int rc = create_workspace(device, stream, &ws);
+            if (rc != QMS_OK) return rc;
+            g_ws[key] = ws;
+        }
+        ws->users.fetch_add(1);
+    }
+    ws->mu.lock();  // waits for another thread's sort on this stream
+    lease->ws_ = ws;
+    return QMS_OK;
+}
+
+static int create_workspace(int device, hipStream_t stream, Workspace **out) {
     Workspace *ws = new Workspace();
     ws->device = device;
     ws->stream = stream;
@@ -134,7 +160,6 @@ int get_workspace(int device, hipStream_t stream, Workspace **out) {
     ws->hist = w;
     w += 256ull * kCapMoM;
     ws->gcnt = (uint8_t *)w;
-    g_ws[key] = ws;
     *out = ws;
     return QMS_OK;
 }
@@ -149,10 +174,14 @@ static void free_workspace(Workspace *ws) {
     delete ws;
 }
 
+// Callers hold g_ws_mutex, so no lease can be taken meanwhile; a workspace
+// with users is in use (or about to be) and stays.
 int release_workspace(int device, hipStream_t stream) {
     std::lock_guard<std::mutex> lock(g_ws_mutex);
     auto it = g_ws.find(std::make_pair(device, stream));
     if (it == g_ws.end()) return QMS_OK;
+    if (it->second->users.load() != 0)
+        return set_error(QMS_ERR_INVALID, "the workspace of this stream is in use");
     int cur = 0;
     (void)hipGetDevice(&cur);
     free_workspace(it->second);
@@ -165,9 +194,18 @@ int release_workspaces() {
     std::lock_guard<std::mutex> lock(g_ws_mutex);
     int cur = 0;
     (void)hipGetDevice(&cur);
-    for (auto &kv : g_ws) free_workspace(kv.second);
-    g_ws.clear();
+    bool busy = false;
+    for (auto it = g_ws.begin(); it != g_ws.end();) {
+        if (it->second->users.load() != 0) {
+            busy = true;
+            ++it;
+            continue;
+        }
+        free_workspace(it->second);
+        it = g_ws.erase(it);
+    }
     (void)hipSetDevice(cur);
+    if (busy) return set_error(QMS_ERR_INVALID, "a workspace in use (a running sort or server) was kept");
     return QMS_OK;
 }
 
@@ -217,7 +255,7 @@ static int sort_entry(void *d_keys, uint32_t *d_vals, uint64_t n, int dt, hipStr
         if (dev2 != dev) return set_error(QMS_ERR_INVALID, "keys and vals on different devices");
     }
     DeviceScope scope(dev);
-    Workspace *ws = nullptr;
+    WorkspaceLease ws;
     rc = get_workspace(dev, stream, &ws);
     if (rc != QMS_OK) return rc;
     HostSeg seg{(uint32_t *)d_keys, pairs ? d_vals : nullptr, n};
@@ -314,7 +352,7 @@ int qms_mom_pivot(const void *d_keys, uint64_t n, int dt, uint32_t *pivot_out,
         int rc = check_device_ptr(d_keys, "keys", &dev);
         if (rc != QMS_OK) return rc;
         DeviceScope scope(dev);
-        Workspace *ws = nullptr;
+        WorkspaceLease ws;
         rc = get_workspace(dev, stream, &ws);
         if (rc != QMS_OK) return rc;
         uint32_t p = 0;

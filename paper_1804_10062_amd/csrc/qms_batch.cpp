@@ -41,7 +41,7 @@ extern "C" int qms_sort_batch(void *d_keys, uint32_t *d_vals, const uint64_t *d_
         if (off[0] != 0) return set_error(QMS_ERR_INVALID, "offsets[0] must be 0");
         for (uint32_t j = 0; j < num_segments; ++j)
             if (off[j + 1] < off[j]) return set_error(QMS_ERR_INVALID, "offsets decrease");
-        Workspace *ws = nullptr;
+        WorkspaceLease ws;
         rc = get_workspace(dev, stream, &ws);
         if (rc != QMS_OK) return rc;
         // segment j starts off[j] keys in, keys of 4 or 8 bytes

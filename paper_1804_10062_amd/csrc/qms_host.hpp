@@ -34,7 +34,25 @@ int check_device_ptr(const void *p, const char *what, int *device, uintptr_t ali
 // dtype codes of qms.h: 32-bit (QMS_U32, QMS_F32) or 64-bit (QMS_U64, QMS_F64)
 inline bool dtype_known(int dt) { return dt >= 0 && dt <= 3; }
 inline bool dtype_wide(int dt) { return dt == 2 || dt == 3; }
-int get_workspace(int device, hipStream_t stream, Workspace **out);
+// Exclusive use of the workspace of (device, stream) for one sort: taking
+// the lease waits for another thread's sort on the same stream to end.
+class WorkspaceLease {
+  public:
+    WorkspaceLease() = default;
+    ~WorkspaceLease() { reset(); }
+    WorkspaceLease(const WorkspaceLease &) = delete;
+    WorkspaceLease &operator=(const WorkspaceLease &) = delete;
+    Workspace *get() const { return ws_; }
+    Workspace &operator*() const { return *ws_; }
+    void reset();
+
+  private:
+    friend int get_workspace(int device, hipStream_t stream, WorkspaceLease *out);
+    Workspace *ws_ = nullptr;
+};
+int get_workspace(int device, hipStream_t stream, WorkspaceLease *out);
+// Frees the cached workspaces that no thread holds (a workspace in use is
+// left alone: QMS_ERR_INVALID names it).
 int release_workspaces();
 int release_workspace(int device, hipStream_t stream);
 

@@ -5,6 +5,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+#include <mutex>
+
 #include "qms_device.hpp"
 
 namespace qms {
@@ -31,10 +34,15 @@ constexpr int kMaxLevels = 18;
 constexpr uint64_t kFinalCap = 1ull << 24;
 
 // Library-owned scratch of one (device, stream): counters, round state and
-// task tables.  Its size does not depend on the number of keys sorted.
+// task tables.  Its size does not depend on the number of keys sorted.  One
+// sort at a time uses it: callers hold `mu` for the whole sort (a
+// WorkspaceLease), and `users` counts the leases taken or waiting, so that
+// qms_release_workspaces never frees a workspace in use.
 struct Workspace {
     int device = -1;
     hipStream_t stream = nullptr;
+    std::mutex mu;
+    std::atomic<int> users{0};
     void *block = nullptr;       // one device allocation holding everything below
     uint32_t *cnt_lt = nullptr;  // [kCapTiles]
     uint32_t *cnt_eq = nullptr;  // [kCapTiles]

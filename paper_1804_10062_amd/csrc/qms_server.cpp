@@ -9,6 +9,10 @@
 // Batching is greedy: whenever the worker is idle it takes every admitted
 // request of the oldest request's dtype (up to max_batch) into one batch, so
 // batches stay small under light load and grow with the queue.
+// Ordering: a submit records an event on the caller's stream; the batch that
+// holds the request waits for it on the server's stream, so keys still being
+// written by work the caller enqueued before the submit are sorted only once
+// that work has run.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -35,15 +39,18 @@ struct Request {
     int dt;
     Clock::time_point t_submit, t_done;
     int status;  // QMS_PENDING, QMS_OK or an error code
+    hipEvent_t ready;  // recorded on the caller's stream at submit
 };
+
+inline uint64_t request_bytes(uint64_t n, int dt) { return n * (dtype_wide(dt) ? 8 : 4); }
 
 }  // namespace
 
 struct qms_server {
     qms_server_config cfg;
     hipStream_t stream = nullptr;
-    Workspace *ws = nullptr;
     std::mutex mu;
+    std::vector<hipEvent_t> free_events;  // recycled submit events
     std::condition_variable cv_work, cv_done;
     std::deque<Request *> waiting;    // submitted, not yet admitted (FIFO)
     std::deque<Request *> admitted;   // admitted, not yet in a batch
@@ -58,7 +65,7 @@ struct qms_server {
     void admit_locked() {
         while (!waiting.empty()) {
             Request *r = waiting.front();
-            const uint64_t b = r->n * 4;
+            const uint64_t b = request_bytes(r->n, r->dt);
             if (admitted_bytes + b > cfg.hbm_budget_bytes) break;
             waiting.pop_front();
             admitted_bytes += b;
@@ -71,6 +78,8 @@ struct qms_server {
         (void)hipSetDevice(cfg.device);
         std::vector<Request *> batch;
         std::vector<HostSeg> segs;
+        // the worker holds its stream's workspace while it runs
+        WorkspaceLease ws;
         for (;;) {
             {
                 std::unique_lock<std::mutex> lock(mu);
@@ -89,12 +98,23 @@ struct qms_server {
                 }
             }
             segs.clear();
-            for (Request *r : batch) segs.push_back(HostSeg{r->keys, nullptr, r->n});
-            int rc = sort_segments(batch.front()->dt, false, segs.data(), segs.size(), *ws, stream,
+            int rc = ws.get() ? QMS_OK : get_workspace(cfg.device, stream, &ws);
+            for (Request *r : batch) {
+                segs.push_back(HostSeg{r->keys, nullptr, r->n});
+                if (rc == QMS_OK) {
+                    hipError_t e = hipStreamWaitEvent(stream, r->ready, 0);
+                    if (e != hipSuccess) rc = hip_error(e, "server: waiting for the submit event");
+                }
+            }
+            if (rc == QMS_OK)
+                rc = sort_segments(batch.front()->dt, false, segs.data(), segs.size(), *ws, stream,
                                    false);
             if (rc == QMS_OK) {
                 hipError_t e = hipStreamSynchronize(stream);
                 if (e != hipSuccess) rc = hip_error(e, "server batch");
+            } else {
+                // the events may still be waited on by enqueued work
+                (void)hipStreamSynchronize(stream);
             }
             const Clock::time_point now = Clock::now();
             {
@@ -102,7 +122,9 @@ struct qms_server {
                 for (Request *r : batch) {
                     r->t_done = now;
                     r->status = rc == QMS_OK ? QMS_OK : rc;
-                    admitted_bytes -= r->n * 4;
+                    free_events.push_back(r->ready);
+                    r->ready = nullptr;
+                    admitted_bytes -= request_bytes(r->n, r->dt);
                     --in_flight;
                     stats.completed += 1;
                     stats.completed_keys += r->n;
@@ -135,11 +157,16 @@ int qms_server_create(const qms_server_config *cfg, qms_server **out) {
             delete s;
             return hip_error(e, "server stream");
         }
-        int rc = get_workspace(cfg->device, s->stream, &s->ws);
-        if (rc != QMS_OK) {
-            (void)hipStreamDestroy(s->stream);
-            delete s;
-            return rc;
+        {
+            // allocate the stream's workspace now, so that a failure is
+            // reported here; the worker takes it when it starts
+            WorkspaceLease lease;
+            int rc = get_workspace(cfg->device, s->stream, &lease);
+            if (rc != QMS_OK) {
+                (void)hipStreamDestroy(s->stream);
+                delete s;
+                return rc;
+            }
         }
         s->worker = std::thread([s] { s->run(); });
         *out = s;
@@ -149,25 +176,47 @@ int qms_server_create(const qms_server_config *cfg, qms_server **out) {
     }
 }
 
-int qms_server_submit(qms_server *s, void *d_keys, uint64_t n, int dt, uint64_t *ticket_out) {
+int qms_server_submit(qms_server *s, void *d_keys, uint64_t n, int dt, hipStream_t stream,
+                      uint64_t *ticket_out) {
     try {
         if (!s || !ticket_out) return set_error(QMS_ERR_INVALID, "NULL server or ticket");
-        if (dt != QMS_U32 && dt != QMS_F32) return set_error(QMS_ERR_UNSUPPORTED, "the server takes 32-bit keys (QMS_U32, QMS_F32)");
+        if (!dtype_known(dt)) return set_error(QMS_ERR_UNSUPPORTED, "unknown dtype");
         if (n >= (1ull << 32)) return set_error(QMS_ERR_UNSUPPORTED, "n must be below 2^32");
-        if (n * 4 > s->cfg.hbm_budget_bytes)
+        if (request_bytes(n, dt) > s->cfg.hbm_budget_bytes)
             return set_error(QMS_ERR_BUDGET, "request larger than the HBM budget");
+        hipEvent_t ev = nullptr;
         if (n > 1) {
             if (!d_keys) return set_error(QMS_ERR_INVALID, "NULL keys with n > 1");
             int dev = -1;
-            int rc = check_device_ptr(d_keys, "keys", &dev);
+            int rc = check_device_ptr(d_keys, "keys", &dev, dtype_wide(dt) ? 8 : 4);
             if (rc != QMS_OK) return rc;
             if (dev != s->cfg.device)
                 return set_error(QMS_ERR_INVALID, "keys not on the server's device");
+            {
+                std::lock_guard<std::mutex> lock(s->mu);
+                if (!s->free_events.empty()) {
+                    ev = s->free_events.back();
+                    s->free_events.pop_back();
+                }
+            }
+            DeviceScope scope(s->cfg.device);
+            hipError_t e = hipSuccess;
+            if (!ev) e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            if (e == hipSuccess) e = hipEventRecord(ev, stream);
+            if (e != hipSuccess) {
+                if (ev) {
+                    std::lock_guard<std::mutex> lock(s->mu);
+                    s->free_events.push_back(ev);
+                }
+                (void)hipGetLastError();
+                return hip_error(e, "server: recording the submit event on the caller's stream");
+            }
         }
-        Request *r = new Request{0, (uint32_t *)d_keys, n, dt, Clock::now(), {}, QMS_PENDING};
+        Request *r = new Request{0, (uint32_t *)d_keys, n, dt, Clock::now(), {}, QMS_PENDING, ev};
         {
             std::lock_guard<std::mutex> lock(s->mu);
             if (s->stop) {
+                if (ev) s->free_events.push_back(ev);
                 delete r;
                 return set_error(QMS_ERR_INVALID, "server is shutting down");
             }
@@ -181,7 +230,7 @@ int qms_server_submit(qms_server *s, void *d_keys, uint64_t n, int dt, uint64_t 
             } else {
                 ++s->in_flight;
                 const bool fits = s->waiting.empty() &&
-                                  s->admitted_bytes + n * 4 <= s->cfg.hbm_budget_bytes;
+                                  s->admitted_bytes + request_bytes(n, dt) <= s->cfg.hbm_budget_bytes;
                 if (!fits) s->stats.waited_for_budget += 1;
                 s->waiting.push_back(r);
                 s->admit_locked();
@@ -235,6 +284,7 @@ int qms_server_destroy(qms_server *s) {
         if (s->worker.joinable()) s->worker.join();
         (void)hipStreamSynchronize(s->stream);
         for (auto &kv : s->by_ticket) delete kv.second;
+        for (hipEvent_t ev : s->free_events) (void)hipEventDestroy(ev);
         // the workspace is keyed by this stream; release it with the stream
         (void)release_workspace(s->cfg.device, s->stream);
         (void)hipStreamDestroy(s->stream);

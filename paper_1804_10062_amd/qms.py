@@ -98,7 +98,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.qms_sort_batch.restype = i32
     lib.qms_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
     lib.qms_server_create.restype = i32
-    lib.qms_server_submit.argtypes = [vp, vp, u64, i32, u64p]
+    lib.qms_server_submit.argtypes = [vp, vp, u64, i32, vp, u64p]
     lib.qms_server_submit.restype = i32
     lib.qms_server_poll.argtypes = [vp, u64, ctypes.POINTER(ctypes.c_double)]
     lib.qms_server_poll.restype = i32
@@ -289,12 +289,15 @@ class Server:
         self._h = h
         self._lib = lib
 
-    def submit(self, keys, dtype: Optional[int] = None) -> int:
+    def submit(self, keys, dtype: Optional[int] = None, stream=None) -> int:
+        """Lend ``keys`` to the server; it sorts them after the work already
+        enqueued on ``stream`` (default: the current stream) has run."""
         _check_tensor(keys, "keys")
         dt = _dtype_code(keys) if dtype is None else dtype
         t = ctypes.c_uint64()
         _check(self._lib.qms_server_submit(self._h, keys.data_ptr(), keys.numel(), dt,
-                                           ctypes.byref(t)), "qms_server_submit")
+                                           _stream_handle(stream), ctypes.byref(t)),
+               "qms_server_submit")
         return t.value
 
     def poll(self, ticket: int):

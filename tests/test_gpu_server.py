@@ -78,7 +78,8 @@ def test_server_budget_admission_fifo():
         assert st["peak_admitted_bytes"] <= budget
         assert st["waited_for_budget"] > 0
     for x, d in zip(reqs, devs):
-        np.testing.assert_array_equal(to_host(d), np.sort(x))
+        want, _, _ = oracle.sort(x, counted=False)
+        np.testing.assert_array_equal(to_host(d), want)
 
 
 @needs_gpu
@@ -102,8 +103,11 @@ def test_server_errors():
     with qms.Server(hbm_budget_bytes=1 << 20, device=0) as srv:
         import ctypes
         tk = ctypes.c_uint64()
-        rc = lib.qms_server_submit(srv._h, host.ctypes.data, 16, qms.QMS_U32, ctypes.byref(tk))
+        rc = lib.qms_server_submit(srv._h, host.ctypes.data, 16, qms.QMS_U32, None,
+                                   ctypes.byref(tk))
         assert rc == qms.QMS_ERR_INVALID
+        rc = lib.qms_server_submit(srv._h, host.ctypes.data, 16, 7, None, ctypes.byref(tk))
+        assert rc == qms.QMS_ERR_UNSUPPORTED
 
 
 @needs_gpu
@@ -118,3 +122,63 @@ def test_server_destroy_drains():
     for x, dv in zip(reqs, devs):
         want, _, _ = oracle.sort(x, counted=False)
         np.testing.assert_array_equal(to_host(dv).view(np.uint32), want.view(np.uint32))
+
+
+@needs_gpu
+def test_server_waits_for_the_producing_stream():
+    """Keys written by work still queued on the caller's stream at submit:
+    the server's batch waits for the event recorded there, so it sorts the
+    written keys, not the zeros the tensor held before."""
+    x = inputs.uniform_u32(1 << 20, seed=21)
+    src = to_device(x)
+    dst = torch.zeros_like(src)
+    side = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    with qms.Server(hbm_budget_bytes=1 << 30, device=0) as srv:
+        with torch.cuda.stream(side):
+            # a few milliseconds of queued work ahead of the copy
+            a = torch.rand(4096, 4096, device="cuda")
+            for _ in range(8):
+                a = a @ a
+                a = a / a.abs().amax().clamp_min(1.0)
+            dst.copy_(src)
+        t = srv.submit(dst, stream=side)
+        _wait_all(srv, [t])
+    torch.cuda.synchronize()
+    want, _, _ = oracle.sort(x, counted=False)
+    np.testing.assert_array_equal(to_host(dst), want)
+
+
+@needs_gpu
+def test_server_64_bit_keys():
+    """uint64 and float64 requests beside 32-bit ones, bit-exact with the
+    oracle's 64-bit build; the budget counts 8 bytes per key."""
+    rng = np.random.default_rng(5)
+    reqs = [rng.integers(0, 2 ** 64, int(n), dtype=np.uint64) for n in (3, 1000, 70001, 1 << 18)]
+    reqs += [rng.standard_normal(int(n)) for n in (2, 5000, 100003)]
+    reqs += [inputs.uniform_u32(50000, seed=3)]
+    devs = []
+    for x in reqs:
+        if x.dtype == np.uint64:
+            devs.append(torch.from_numpy(x.view(np.int64)).cuda())
+        elif x.dtype == np.float64:
+            devs.append(torch.from_numpy(x).cuda())
+        else:
+            devs.append(to_device(x))
+    torch.cuda.synchronize()
+    with qms.Server(hbm_budget_bytes=1 << 30, device=0) as srv:
+        tickets = [srv.submit(d) for d in devs]
+        _wait_all(srv, tickets)
+        assert srv.stats()["completed_keys"] == sum(x.size for x in reqs)
+    with qms.Server(hbm_budget_bytes=8 * 999, device=0) as srv:
+        with pytest.raises(qms.QmsError) as e:
+            srv.submit(devs[1])  # 1000 keys of 8 bytes > 7992 bytes
+        assert e.value.code == qms.QMS_ERR_BUDGET
+    for x, d in zip(reqs, devs):
+        want, _, _ = oracle.sort(x, counted=False)
+        got = d.cpu().numpy()
+        if x.dtype == np.uint64:
+            got = got.view(np.uint64)
+        elif x.dtype == np.uint32:
+            got = got.view(np.uint32)
+        np.testing.assert_array_equal(got, want)
