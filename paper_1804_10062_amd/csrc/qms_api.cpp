@@ -45,9 +45,88 @@ Tuning current_tuning() {
 static std::mutex g_ws_mutex;
 static std::map<std::pair<int, hipStream_t>, Workspace *> g_ws;
 
-static size_t ws_words() {
-    return 3ull * kCapTiles + 2ull * (kCapTiles + kCapSegs) + 2ull * kCapChunks + (13ull + 4ull * kSamplesPerTile) * kCapSplits +
-           4ull * kCapSegs + 256ull * kCapMoM + kCapGroups / 4;
+WsCaps default_caps() {
+    WsCaps c;
+    c.tiles = kCapTiles;
+    c.chunks = kCapChunks;
+    c.splits = kCapSplits;
+    c.groups = kCapGroups;
+    c.final_cap = kFinalCap;
+    c.segs = kCapSegs;
+    c.mom = kCapMoM;
+    c.tab_bytes = tab_arena_bytes(kCapSegs);
+    return c;
+}
+
+WsCaps single_array_caps(uint64_t nmax) {
+    WsCaps c;
+    c.tiles = (nmax + kPartSub - 1) / kPartSub + 1;
+    c.chunks = c.tiles + 2 + 16;
+    c.splits = (nmax + kMergeTile - 1) / kMergeTile + 1 + 16;
+    c.groups = c.tiles * (kPartSub / kWave);
+    c.final_cap = 0;
+    c.segs = 1;
+    c.mom = 1;
+    c.tab_bytes = tab_arena_bytes(1);
+    return c;
+}
+
+static size_t ws_words(const WsCaps &c) {
+    return 3ull * c.tiles + 2ull * (c.tiles + c.segs) + 2ull * c.chunks +
+           (13ull + 4ull * kSamplesPerTile) * c.splits + 4ull * c.segs + 256ull * c.mom +
+           (c.groups + 3) / 4;
+}
+
+size_t workspace_device_bytes(const WsCaps &c) {
+    const size_t meta_bytes = (size_t)c.segs * M_COUNT * sizeof(uint64_t);
+    const size_t fbuf_bytes = 2 * c.final_cap * sizeof(uint32_t);
+    return meta_bytes + fbuf_bytes + ((c.tab_bytes + 255) & ~(size_t)255) +
+           ws_words(c) * sizeof(uint32_t) + 256;
+}
+
+void carve_workspace(Workspace *ws, char *block, const WsCaps &c) {
+    ws->caps = c;
+    ws->tab_bytes = c.tab_bytes;
+    char *b = block;
+    ws->meta = (uint64_t *)b;
+    b += (size_t)c.segs * M_COUNT * sizeof(uint64_t);
+    ws->fbuf = c.final_cap ? (uint32_t *)b : nullptr;  // 8-byte aligned
+    b += 2 * c.final_cap * sizeof(uint32_t);
+    ws->dtab = b;
+    b += (c.tab_bytes + 255) & ~(size_t)255;
+    uint32_t *w = (uint32_t *)b;
+    ws->cnt_lt = w;
+    w += c.tiles;
+    ws->cnt_eq = w;
+    w += c.tiles;
+    ws->eqmv = w;
+    w += c.tiles;
+    ws->preL = w;
+    w += c.tiles + c.segs;
+    ws->preR = w;
+    w += c.tiles + c.segs;
+    ws->spL = w;
+    w += c.chunks;
+    ws->spR = w;
+    w += c.chunks;
+    ws->splits = w;
+    w += c.splits;
+    // run samples hold keys of either width: 2 words per entry (8-byte
+    // aligned: every offset before them is a multiple of 8 bytes)
+    if ((uintptr_t)w & 7) ++w;
+    ws->samples[0] = w;
+    w += 2ull * kSamplesPerTile * c.splits;
+    ws->samples[1] = w;
+    w += 2ull * kSamplesPerTile * c.splits;
+    ws->bounds = w;
+    w += 4ull * c.splits;
+    ws->ends = w;
+    w += 8ull * c.splits;
+    ws->res = w;
+    w += 4ull * c.segs;
+    ws->hist = w;
+    w += 256ull * c.mom;
+    ws->gcnt = (uint8_t *)w;
 }
 
 void WorkspaceLease::reset() {
@@ -87,19 +166,16 @@ static int create_workspace(int device, hipStream_t stream, Workspace **out) {
     Workspace *ws = new Workspace();
     ws->device = device;
     ws->stream = stream;
-    ws->tab_bytes = tab_arena_bytes();
-    const size_t meta_bytes = (size_t)kCapSegs * M_COUNT * sizeof(uint64_t);
-    const size_t fbuf_bytes = 2 * kFinalCap * sizeof(uint32_t);
-    const size_t bytes = meta_bytes + fbuf_bytes + ws_words() * sizeof(uint32_t) + ws->tab_bytes +
-                         4096;
-    hipError_t e = hipMalloc(&ws->block, bytes);
+    const WsCaps caps = default_caps();
+    hipError_t e = hipMalloc(&ws->block, workspace_device_bytes(caps));
     if (e != hipSuccess) {
         delete ws;
         (void)hipGetLastError();
         return set_error(QMS_ERR_NOMEM, std::string("workspace allocation: ") + hipGetErrorString(e));
     }
     void *h = nullptr;
-    e = hipHostMalloc(&h, 2 * ws->tab_bytes + 4 * kCapSegs * sizeof(uint32_t), hipHostMallocDefault);
+    e = hipHostMalloc(&h, 2 * caps.tab_bytes + 4 * (size_t)caps.segs * sizeof(uint32_t),
+                      hipHostMallocDefault);
     if (e != hipSuccess) {
         (void)hipFree(ws->block);
         delete ws;
@@ -119,47 +195,9 @@ static int create_workspace(int device, hipStream_t stream, Workspace **out) {
         }
     }
     ws->htab[0] = h;
-    ws->htab[1] = (char *)h + ws->tab_bytes;
-    ws->h_res = (uint32_t *)((char *)h + 2 * ws->tab_bytes);
-    char *b = (char *)ws->block;
-    ws->meta = (uint64_t *)b;
-    b += meta_bytes;
-    ws->fbuf = (uint32_t *)b;  // 8-byte aligned (meta_bytes is a multiple of 8)
-    b += fbuf_bytes;
-    ws->dtab = b;
-    b += (ws->tab_bytes + 255) & ~(size_t)255;
-    uint32_t *w = (uint32_t *)b;
-    ws->cnt_lt = w;
-    w += kCapTiles;
-    ws->cnt_eq = w;
-    w += kCapTiles;
-    ws->eqmv = w;
-    w += kCapTiles;
-    ws->preL = w;
-    w += kCapTiles + kCapSegs;
-    ws->preR = w;
-    w += kCapTiles + kCapSegs;
-    ws->spL = w;
-    w += kCapChunks;
-    ws->spR = w;
-    w += kCapChunks;
-    ws->splits = w;
-    w += kCapSplits;
-    // run samples hold keys of either width: 2 words per entry (the offsets
-    // before them are even, so these arrays are 8-byte aligned)
-    ws->samples[0] = w;
-    w += 2ull * kSamplesPerTile * kCapSplits;
-    ws->samples[1] = w;
-    w += 2ull * kSamplesPerTile * kCapSplits;
-    ws->bounds = w;
-    w += 4ull * kCapSplits;
-    ws->ends = w;
-    w += 8ull * kCapSplits;
-    ws->res = w;
-    w += 4ull * kCapSegs;
-    ws->hist = w;
-    w += 256ull * kCapMoM;
-    ws->gcnt = (uint8_t *)w;
+    ws->htab[1] = (char *)h + caps.tab_bytes;
+    ws->h_res = (uint32_t *)((char *)h + 2 * caps.tab_bytes);
+    carve_workspace(ws, (char *)ws->block, caps);
     *out = ws;
     return QMS_OK;
 }

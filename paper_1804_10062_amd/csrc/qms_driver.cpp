@@ -78,6 +78,9 @@ struct ArenaUse {
         ar = Arena{(char *)ws.htab[slot], (char *)ws.dtab, ws.tab_bytes};
     }
     ~ArenaUse() {
+        // a workspace without events has pageable arenas, whose copies have
+        // read the host memory by the time they return
+        if (!ws.arena_done[slot]) return;
         if (hipEventRecord(ws.arena_done[slot], st) == hipSuccess) {
             ws.arena_busy[slot] = true;
         } else {
@@ -100,13 +103,13 @@ int upload(Arena &ar, size_t from, hipStream_t st) {
 thread_local std::vector<std::array<uint64_t, kScheduleWords>> g_schedule;
 
 // The median-of-medians pivots of the flagged segments of a round, in groups
-// of at most kCapMoM (one histogram each).
+// of at most caps.mom (one histogram each).
 int mom_pivots(int dt, const PartSeg *pt, uint32_t A, Arena &ar, Workspace &ws, hipStream_t st) {
     std::vector<uint32_t> idx;
     for (uint32_t a = 0; a < A; ++a)
         if (pt[a].flags & kPivotMoM) idx.push_back(a);
-    for (size_t g0 = 0; g0 < idx.size(); g0 += kCapMoM) {
-        const uint32_t n = (uint32_t)std::min<size_t>(kCapMoM, idx.size() - g0);
+    for (size_t g0 = 0; g0 < idx.size(); g0 += ws.caps.mom) {
+        const uint32_t n = (uint32_t)std::min<size_t>(ws.caps.mom, idx.size() - g0);
         const size_t mark = ar.used;
         size_t o_tab, o_pre;
         PartSeg *tab = ar.take<PartSeg>(n, &o_tab);
@@ -136,15 +139,16 @@ int mom_pivots(int dt, const PartSeg *pt, uint32_t A, Arena &ar, Workspace &ws, 
 
 }  // namespace
 
-size_t tab_arena_bytes() {
+size_t tab_arena_bytes(uint32_t segs) {
     // per segment: partition entry, 5 prefixes, up to 2 sort tasks, 2 prefixes
+    // (each table rounded up to 256 bytes by the arena)
     const size_t per = sizeof(PartSeg) + 5 * 4 + 2 * sizeof(SortSeg) + 2 * 2 * 4;
-    return per * kCapSegs + 64 * 1024;
+    return per * segs + 64 * 1024;
 }
 
 const std::vector<std::array<uint64_t, kScheduleWords>> &last_schedule() { return g_schedule; }
 
-// Sort a group of segments (count <= kCapSegs, total keys < 2^32).
+// Sort a group of segments (count <= caps.segs, total keys < 2^32).
 static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
                       hipStream_t st, bool log, const Tuning &tune) {
     // 64-bit keys: twice the bytes per element and the 8,192-element base
@@ -183,7 +187,8 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
     // TF: a range that a partition round leaves with at most TF keys leaves
     // the loop (a recursion stopper; the paper's recursion would continue
     // down to T0): one Mergesort finishes it with the library's fixed scratch
-    // buffer as swap space (kFinalCap elements per workspace, whatever n is).
+    // buffer as swap space (caps.final_cap elements per workspace, whatever n
+    // is; a workspace without that buffer runs the loop down to T0).
     // A range is handed over only while the next round's buffer has room for
     // it; otherwise it stays in the loop, so many arrays of a batch do not
     // queue for the buffer round after round.  An input array of at most T0
@@ -191,7 +196,8 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
     // case in place; every larger one is partitioned at least once, so its
     // top level is always QuickMergesort's (partition, Mergesort of one side
     // with the other side as its buffer).
-    const uint64_t TF = std::max<uint64_t>(T0, std::min<uint64_t>(tune.final_tile, kFinalCap));
+    const uint64_t final_cap = ws.caps.final_cap;
+    const uint64_t TF = std::max<uint64_t>(T0, std::min<uint64_t>(tune.final_tile, final_cap));
     auto final_task = [&](const Seg &g, uint32_t lo, uint32_t s) {
         SortSeg f{kptr(g, lo), vptr(g, lo), nullptr, nullptr, s, 0, 0, T0, 0, 0};
         if (s > T0) set_levels(f);
@@ -218,18 +224,18 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
         deferred.clear();
         for (SortSeg f : ready_finals) {
             if (f.m > T0) {
-                if (fused + f.m > kFinalCap) {
+                if (fused + f.m > final_cap) {
                     deferred.push_back(f);
                     deferred_keys += f.m;
                     continue;
                 }
                 f.bkeys = ws.fbuf + ew * fused;
-                f.bvals = pairs ? ws.fbuf + kFinalCap + fused : nullptr;
+                f.bvals = pairs ? ws.fbuf + final_cap + fused : nullptr;
                 fused += f.m;
             }
             tasks.push_back(f);
         }
-        uint64_t next_room = kFinalCap - std::min<uint64_t>(deferred_keys, kFinalCap);
+        uint64_t next_room = final_cap - std::min<uint64_t>(deferred_keys, final_cap);
         const uint32_t A = (uint32_t)active.size();
         if (A > 0) {
             // ---- partition: count + scan A, then read three counters back ----
@@ -239,7 +245,7 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
             for (;;) {
                 uint64_t tot = 0;
                 for (uint32_t i : active) tot += (segs[i].hi - segs[i].lo + TP - 1) / TP;
-                if (tot <= kCapTiles) break;
+                if (tot <= ws.caps.tiles) break;
                 TP *= 2;
             }
             size_t o_tab, o_pre;
@@ -261,7 +267,8 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
                 pc[a + 1] = toff;
                 max_nt = std::max(max_nt, nt);
             }
-            if (coff > kCapChunks) return set_error(QMS_ERR_UNSUPPORTED, "batch too large for one round");
+            if (coff > ws.caps.chunks)
+                return set_error(QMS_ERR_UNSUPPORTED, "batch too large for one round");
             if (A > 1) {
                 int rc = upload(ar, 0, st);
                 if (rc != QMS_OK) return rc;
@@ -282,7 +289,7 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
                 const uint32_t C = L.scan_threads * (uint32_t)kScanPer;
                 L.scan_groups = std::min<uint32_t>((max_nt + C - 1) / C, kScanGroups);
             }
-            L.groups = (uint64_t)toff * (TP / kWave) <= kCapGroups;
+            L.groups = (uint64_t)toff * (TP / kWave) <= ws.caps.groups;
             L.keys_total = (double)sum_s;
             L.ws = &ws;
             L.phase = 0;
@@ -452,7 +459,7 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
             maxL = std::max(maxL, t.L);
             if (!by_parity || (t.L & 1u) == 0) E = a + 1;
         }
-        if (pmerge[T] > kCapSplits) return set_error(QMS_ERR_UNSUPPORTED, "too many merge tiles");
+        if (pmerge[T] > ws.caps.splits) return set_error(QMS_ERR_UNSUPPORTED, "too many merge tiles");
         if (T > 1) {
             int rc = upload(ar, mark, st);
             if (rc != QMS_OK) return rc;
@@ -536,7 +543,7 @@ int sort_segments(int dt, bool pairs, const HostSeg *segs, size_t count, Workspa
         const HostSeg &h = segs[i];
         if (h.n <= 1) continue;
         if (h.n >= (1ull << 32)) return set_error(QMS_ERR_UNSUPPORTED, "segment of 2^32 keys or more");
-        if (group.size() == kCapSegs || group_keys + h.n >= (1ull << 32)) {
+        if (group.size() == ws.caps.segs || group_keys + h.n >= (1ull << 32)) {
             int rc = flush();
             if (rc != QMS_OK) return rc;
         }

@@ -67,7 +67,8 @@ struct HostSeg {
 // through each phase in one launch.  log: record the per-round schedule.
 int sort_segments(int dt, bool pairs, const HostSeg *segs, size_t count, Workspace &ws,
                   hipStream_t st, bool log);
-size_t tab_arena_bytes();
+// Bytes of one task-table arena for rounds of up to `segs` segments.
+size_t tab_arena_bytes(uint32_t segs);
 const std::vector<std::array<uint64_t, kScheduleWords>> &last_schedule();
 // The median-of-medians pivot of one array (order-mapped key into *pivot).
 int mom_pivot_of(int dt, const uint32_t *keys, uint64_t n, Workspace &ws, hipStream_t st,

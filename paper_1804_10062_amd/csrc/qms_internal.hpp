@@ -33,6 +33,21 @@ constexpr int kMaxLevels = 18;
 // of up to 8 bytes, or 4-byte keys with 4-byte payloads): 128 MiB.
 constexpr uint64_t kFinalCap = 1ull << 24;
 
+// Capacities of a workspace.  The cached workspaces take the constants
+// above; the allocation-free entry point carves a smaller set for one array
+// of bounded size out of a fixed device array.
+struct WsCaps {
+    uint64_t tiles, chunks, splits, groups;
+    uint64_t final_cap;  // elements of the final ranges' scratch (0: none)
+    uint32_t segs, mom;
+    size_t tab_bytes;    // bytes of one task-table arena
+};
+WsCaps default_caps();
+// Caps for one array of at most nmax elements, no scratch buffer.
+WsCaps single_array_caps(uint64_t nmax);
+// Device bytes of a workspace with these caps (one block).
+size_t workspace_device_bytes(const WsCaps &c);
+
 // Library-owned scratch of one (device, stream): counters, round state and
 // task tables.  Its size does not depend on the number of keys sorted.  One
 // sort at a time uses it: callers hold `mu` for the whole sort (a
@@ -72,7 +87,11 @@ struct Workspace {
     size_t tab_bytes = 0;
     uint32_t *h_res = nullptr;   // pinned host mirror of res
     uint64_t rounds = 0;         // rounds run with this workspace (arena parity)
+    WsCaps caps{};
 };
+// Point every device array of `ws` into `block` (workspace_device_bytes(c)
+// bytes, 256-byte aligned) and set its caps.
+void carve_workspace(Workspace *ws, char *block, const WsCaps &c);
 
 // Layout of a task-table arena (offsets in bytes; same on host and device).
 struct TabLayout {
