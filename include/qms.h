@@ -106,6 +106,22 @@ int qms_sort_batch(void *d_keys, uint32_t *d_vals, const uint64_t *d_offsets,
                    const uint64_t *h_offsets, uint32_t num_segments, int dt,
                    hipStream_t stream);
 
+/*
+ * qms_sort_noalloc -- qms_sort for callers that cannot allocate memory: code
+ * under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, result and errors as qms_sort, for at most
+ * 2^28 keys (QMS_ERR_UNSUPPORTED above that).  It allocates nothing: no
+ * hipMalloc or hipFree, no pinned host memory, no events.  The kernels' tile
+ * counters, split vectors and run samples live in a fixed 32 MiB device
+ * array of the library (one per GPU, held until the process ends) instead
+ * of a cached workspace, and the loop always runs down to the base tile
+ * (final_tile is not used).  Calls on one GPU share that array: calls are
+ * serialised on the host, but calls whose GPU work overlaps (other streams
+ * of the same device, not synchronised between the calls) race on it.  Like
+ * qms_sort it reads partition results back once per round.
+ */
+int qms_sort_noalloc(void *d_keys, uint64_t n, int dt, hipStream_t stream);
+
 /* ---- request loop (serving) ---------------------------------------------
  * A server owns a worker thread and a HIP stream on `device`.  Requests are
  * device arrays lent to the server until qms_server_poll returns QMS_OK for

@@ -37,7 +37,7 @@ EXPORTS = (
     "qms_server_get_stats", "qms_server_destroy",
     "qms_last_error", "qms_release_workspaces", "qms_last_schedule",
     "qms_get_tiles", "qms_profile_begin", "qms_profile_end", "qms_mom_pivot",
-    "qms_set_tuning", "qms_get_tuning",
+    "qms_set_tuning", "qms_get_tuning", "qms_sort_noalloc",
 )
 
 QMS_SCHEDULE_WORDS = 6
@@ -92,6 +92,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     u32p = ctypes.POINTER(ctypes.c_uint32)
     lib.qms_sort.argtypes = [vp, u64, i32, vp]
     lib.qms_sort.restype = i32
+    lib.qms_sort_noalloc.argtypes = [vp, u64, i32, vp]
+    lib.qms_sort_noalloc.restype = i32
     lib.qms_sort_pairs.argtypes = [vp, vp, u64, i32, vp]
     lib.qms_sort_pairs.restype = i32
     lib.qms_sort_batch.argtypes = [vp, vp, vp, vp, u32, i32, vp]
@@ -176,6 +178,16 @@ def qms_sort(keys, stream=None, dtype: Optional[int] = None) -> None:
     lib = load_library()
     dt = _dtype_code(keys) if dtype is None else dtype
     _check(lib.qms_sort(keys.data_ptr(), keys.numel(), dt, _stream_handle(stream)), "qms_sort")
+
+
+def qms_sort_noalloc(keys, stream=None, dtype: Optional[int] = None) -> None:
+    """qms_sort without any allocation (at most 2^28 keys; the library's
+    fixed device scratch array instead of a cached workspace)."""
+    _check_tensor(keys, "keys")
+    lib = load_library()
+    dt = _dtype_code(keys) if dtype is None else dtype
+    _check(lib.qms_sort_noalloc(keys.data_ptr(), keys.numel(), dt, _stream_handle(stream)),
+           "qms_sort_noalloc")
 
 
 def qms_sort_pairs(keys, vals, stream=None, dtype: Optional[int] = None) -> None:
