@@ -92,19 +92,39 @@ int qms_sort_pairs(void *d_keys, uint32_t *d_vals, uint64_t n, int dt,
  * (segment j is [offsets[j], offsets[j+1])), each exactly as qms_sort /
  * qms_sort_pairs would, with all segments advancing together through the
  * partition / base-case / merge phases (one set of launches per phase for
- * the whole batch rather than per segment).
+ * the whole batch rather than per segment).  The rounds are planned on the
+ * device: the call enqueues a fixed schedule of launches on `stream` and
+ * returns without waiting for the GPU (no readback, no synchronisation),
+ * so it may be captured into a HIP graph (after one call outside the
+ * capture, which allocates the stream's workspace).  The schedule: rounds
+ * with the paper's pivot rule (median-of-3, after an unbalanced round the
+ * median of the medians of three: Sec. "Worst-Case Efficient
+ * QuickMergeSort"), then rounds in which every range still in the loop takes
+ * the median-of-medians pivot; their number follows from the longest
+ * segment and guarantees that every segment is sorted.  The loop runs down
+ * to the base tile (final_tile is not used).
  *   d_keys       device keys of all segments.
  *   d_vals       device payloads, or NULL for keys only (64-bit keys:
  *                NULL only).
  *   d_offsets    DEVICE array of num_segments + 1 uint64 offsets, non-
  *                decreasing, offsets[0] = 0 (empty segments allowed).
- *   h_offsets    optional HOST copy of the same offsets (NULL: the library
- *                reads them from the device).
- * Errors: as qms_sort; QMS_ERR_INVALID for decreasing offsets.
+ *   h_offsets    HOST copy of the same offsets; NULL makes the library read
+ *                them from the device first (a synchronisation of `stream`).
+ * Errors: as qms_sort; QMS_ERR_INVALID for decreasing offsets;
+ * QMS_ERR_UNSUPPORTED for a segment of 2^32 keys or more.
  */
 int qms_sort_batch(void *d_keys, uint32_t *d_vals, const uint64_t *d_offsets,
                    const uint64_t *h_offsets, uint32_t num_segments, int dt,
                    hipStream_t stream);
+
+/*
+ * qms_batch_check -- wait for `stream` (current device) and report whether
+ * every qms_sort_batch enqueued on it since the last check finished within
+ * its schedule: QMS_OK, or QMS_ERR_HIP with the number of segments left
+ * unsorted in qms_last_error() (the schedule's bound makes this a check of
+ * the library itself; it has no other cause).  Resets the count.
+ */
+int qms_batch_check(hipStream_t stream);
 
 /*
  * qms_sort_noalloc -- qms_sort for callers that cannot allocate memory: code
@@ -228,8 +248,10 @@ int qms_mom_pivot(const void *d_keys, uint64_t n, int dt, uint32_t *pivot_out,
  * summed duration and their summed algorithmic bytes (the bytes the method
  * must move: 16 per key per swap-merge level and per swapping base-case
  * pass, 8 per key for an in-place base-case pass, 4 per key for counting,
- * doubled for key/payload pairs).  Writes up to max_entries records;
- * *n_out gets the number written.
+ * doubled for key/payload pairs), followed by one record per binary level
+ * at which swap-merge passes started ("merge_level_<l>"; a 4-way pass covers
+ * levels l and l + 1).  Writes up to max_entries records; *n_out gets the
+ * number written.
  */
 typedef struct {
     char name[32];

@@ -20,11 +20,12 @@ from . import qms
 FIELDS = ("merge_ways", "partition_tile", "chunk_span", "base_tile", "final_tile")
 # (merge_ways, partition_tile, chunk_span, base_tile, final_tile); base_tile
 # is QuickMergeXsort's X_THRESH, the run width at which the Mergesort calls
-# the base case (0: automatic); final_tile the range size at or below which
-# a partitioned range leaves the loop for one buffered Mergesort
+# the base case (0: automatic).  final_tile (the range size at or below
+# which a single array's range leaves the loop for one buffered Mergesort)
+# does not apply to batches, whose rounds are planned on the device and run
+# down to the base tile, so it stays at its default here.
 CANDIDATES: Tuple[Tuple[int, int, int, int, int], ...] = tuple(
-    itertools.product((4, 2), (4096, 8192), (16384, 32768), (0, 8192),
-                      (8192, 1 << 18, 1 << 22)))
+    c + (1 << 22,) for c in itertools.product((4, 2), (4096, 8192), (16384, 32768), (0, 8192)))
 
 
 def _time_batch(keys, offsets, vals, ref_keys, ref_vals, reps: int, stream,

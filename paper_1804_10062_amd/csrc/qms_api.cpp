@@ -53,7 +53,10 @@ WsCaps default_caps() {
     c.groups = kCapGroups;
     c.final_cap = kFinalCap;
     c.segs = kCapSegs;
-    c.mom = kCapMoM;
+    // one histogram per segment: a device-controlled round may give every
+    // segment of a group the median-of-medians pivot
+    c.mom = kCapSegs;
+    c.rounds = kCapSegs;
     c.tab_bytes = tab_arena_bytes(kCapSegs);
     return c;
 }
@@ -67,6 +70,7 @@ WsCaps single_array_caps(uint64_t nmax) {
     c.final_cap = 0;
     c.segs = 1;
     c.mom = 1;
+    c.rounds = 0;
     c.tab_bytes = tab_arena_bytes(1);
     return c;
 }
@@ -80,7 +84,8 @@ static size_t ws_words(const WsCaps &c) {
 size_t workspace_device_bytes(const WsCaps &c) {
     const size_t meta_bytes = (size_t)c.segs * M_COUNT * sizeof(uint64_t);
     const size_t fbuf_bytes = 2 * c.final_cap * sizeof(uint32_t);
-    return meta_bytes + fbuf_bytes + ((c.tab_bytes + 255) & ~(size_t)255) +
+    const size_t rounds_bytes = c.rounds ? rounds_state_bytes(c.rounds) : 0;
+    return meta_bytes + fbuf_bytes + ((c.tab_bytes + 255) & ~(size_t)255) + rounds_bytes +
            ws_words(c) * sizeof(uint32_t) + 256;
 }
 
@@ -94,6 +99,10 @@ void carve_workspace(Workspace *ws, char *block, const WsCaps &c) {
     b += 2 * c.final_cap * sizeof(uint32_t);
     ws->dtab = b;
     b += (c.tab_bytes + 255) & ~(size_t)255;
+    if (c.rounds) {
+        carve_rounds_state(ws, b, c.rounds);
+        b += rounds_state_bytes(c.rounds);
+    }
     uint32_t *w = (uint32_t *)b;
     ws->cnt_lt = w;
     w += c.tiles;
@@ -198,6 +207,21 @@ static int create_workspace(int device, hipStream_t stream, Workspace **out) {
     ws->htab[1] = (char *)h + caps.tab_bytes;
     ws->h_res = (uint32_t *)((char *)h + 2 * caps.tab_bytes);
     carve_workspace(ws, (char *)ws->block, caps);
+    // the median-of-medians histograms and the round status start at zero
+    // (device-controlled rounds rely on each select leaving its histogram
+    // cleared)
+    e = hipMemsetAsync(ws->hist, 0, 256ull * caps.mom * sizeof(uint32_t), stream);
+    if (e == hipSuccess && ws->r_status)
+        e = hipMemsetAsync(ws->r_status, 0, 4 * sizeof(uint32_t), stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        for (hipEvent_t &x : ws->arena_done) (void)hipEventDestroy(x);
+        (void)hipHostFree(h);
+        (void)hipFree(ws->block);
+        delete ws;
+        return hip_error(e, "workspace initialisation");
+    }
     *out = ws;
     return QMS_OK;
 }

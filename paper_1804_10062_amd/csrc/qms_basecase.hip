@@ -500,12 +500,12 @@ __device__ __forceinline__ void tile_sort_block(typename O::K *sk, uint32_t *sv,
 // kMergeTile).  64-bit keys use
 // the 8,192-element tile of key/payload pairs.
 template <class O, bool PAIRS>
-__global__ __launch_bounds__(kSortThreads) void k_tile_sort(TaskRef<SortSeg> tasks,
-                                                            typename O::K *samples) {
+__device__ __forceinline__ void tile_sort_item(TaskRef<SortSeg> tasks, uint32_t item,
+                                               typename O::K *samples) {
     using K = typename O::K;
     constexpr uint32_t T = (PAIRS || sizeof(K) == 8) ? kBaseTilePairs : kBaseTileKeys;
     uint32_t t, a;
-    const SortSeg g = task_of(tasks, blockIdx.x, &t, &a);
+    const SortSeg g = task_of(tasks, item, &t, &a);
     const uint32_t t0 = t * T;
     if (t0 >= g.m) return;
     const uint32_t len = min(T, g.m - t0);
@@ -521,30 +521,54 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_sort(TaskRef<SortSeg> tas
                               samples + (uint64_t)g.split_off * kSamplesPerTile +
                                   t0 / kSampleStride);
 }
+template <class O, bool PAIRS, bool LOOP>
+__global__ __launch_bounds__(kSortThreads) void k_tile_sort(TaskRef<SortSeg> tasks, uint32_t first,
+                                                            typename O::K *samples) {
+    const uint32_t W = work_total(tasks, first + gridDim.x);
+    if constexpr (!LOOP) {
+        const uint32_t item = first + blockIdx.x;
+        if (item < W) tile_sort_item<O, PAIRS>(tasks, item, samples);
+    } else {
+        for (uint32_t item = first + blockIdx.x; item < W; item += gridDim.x) {
+            tile_sort_item<O, PAIRS>(tasks, item, samples);
+            __syncthreads();  // the LDS is reused by the next item
+        }
+    }
+}
 
+// tiles: one workgroup each (host-sized), or with tasks.dyn the estimate of
+// a device-sized launch, followed by `overflow` looping workgroups for the
+// tiles beyond it.
 template <class O, bool PAIRS>
-static hipError_t tile_sort_t(const TaskRef<SortSeg> &tasks, uint32_t tiles, double bytes,
-                              const Workspace &ws, hipStream_t st) {
+static hipError_t tile_sort_t(const TaskRef<SortSeg> &tasks, uint32_t tiles, uint32_t overflow,
+                              double bytes, const Workspace &ws, hipStream_t st) {
     if (tiles == 0) return hipSuccess;
     ProfScope prof(st, K_TILE_SORT, bytes);
-    hipLaunchKernelGGL((k_tile_sort<O, PAIRS>), dim3(tiles), dim3(kSortThreads), 0, st, tasks,
-                       (typename O::K *)ws.samples[0]);
+    using K = typename O::K;
+    hipLaunchKernelGGL((k_tile_sort<O, PAIRS, false>), dim3(tiles), dim3(kSortThreads), 0, st,
+                       tasks, 0u, (K *)ws.samples[0]);
+    if (overflow)
+        hipLaunchKernelGGL((k_tile_sort<O, PAIRS, true>), dim3(overflow), dim3(kSortThreads), 0,
+                           st, tasks, tiles, (K *)ws.samples[0]);
     return hipGetLastError();
 }
 
 hipError_t launch_tile_sort(int dt, bool pairs, const TaskRef<SortSeg> &tasks, uint32_t tiles,
-                            double bytes, const Workspace &ws, hipStream_t st) {
+                            uint32_t overflow, double bytes, const Workspace &ws,
+                            hipStream_t st) {
     switch (dt) {
     case 0:
-        return pairs ? tile_sort_t<OrdU32, true>(tasks, tiles, bytes, ws, st)
-                     : tile_sort_t<OrdU32, false>(tasks, tiles, bytes, ws, st);
+        return pairs ? tile_sort_t<OrdU32, true>(tasks, tiles, overflow, bytes, ws, st)
+                     : tile_sort_t<OrdU32, false>(tasks, tiles, overflow, bytes, ws, st);
     case 1:
-        return pairs ? tile_sort_t<OrdF32, true>(tasks, tiles, bytes, ws, st)
-                     : tile_sort_t<OrdF32, false>(tasks, tiles, bytes, ws, st);
+        return pairs ? tile_sort_t<OrdF32, true>(tasks, tiles, overflow, bytes, ws, st)
+                     : tile_sort_t<OrdF32, false>(tasks, tiles, overflow, bytes, ws, st);
     case 2:
-        return pairs ? hipErrorInvalidValue : tile_sort_t<OrdU64, false>(tasks, tiles, bytes, ws, st);
+        return pairs ? hipErrorInvalidValue
+                     : tile_sort_t<OrdU64, false>(tasks, tiles, overflow, bytes, ws, st);
     case 3:
-        return pairs ? hipErrorInvalidValue : tile_sort_t<OrdF64, false>(tasks, tiles, bytes, ws, st);
+        return pairs ? hipErrorInvalidValue
+                     : tile_sort_t<OrdF64, false>(tasks, tiles, overflow, bytes, ws, st);
     default:
         return hipErrorInvalidValue;
     }

@@ -2,6 +2,7 @@
 // arrays advance together through the phases of the QuickMergesort loop.
 #include <hip/hip_runtime.h>
 
+#include <string>
 #include <vector>
 
 #include "qms.h"
@@ -41,22 +42,41 @@ extern "C" int qms_sort_batch(void *d_keys, uint32_t *d_vals, const uint64_t *d_
         if (off[0] != 0) return set_error(QMS_ERR_INVALID, "offsets[0] must be 0");
         for (uint32_t j = 0; j < num_segments; ++j)
             if (off[j + 1] < off[j]) return set_error(QMS_ERR_INVALID, "offsets decrease");
+        for (uint32_t j = 0; j < num_segments; ++j)
+            if (off[j + 1] - off[j] >= (1ull << 32))
+                return set_error(QMS_ERR_UNSUPPORTED, "segment of 2^32 keys or more");
         WorkspaceLease ws;
         rc = get_workspace(dev, stream, &ws);
         if (rc != QMS_OK) return rc;
-        // segment j starts off[j] keys in, keys of 4 or 8 bytes
-        const size_t kb = dtype_wide(dt) ? 8 : 4;
-        char *keys = (char *)d_keys;
-        std::vector<HostSeg> segs;
-        segs.reserve(num_segments);
-        for (uint32_t j = 0; j < num_segments; ++j) {
-            const uint64_t n = off[j + 1] - off[j];
-            if (n <= 1) continue;
-            segs.push_back(HostSeg{(uint32_t *)(keys + kb * off[j]),
-                                   d_vals ? d_vals + off[j] : nullptr, n});
-        }
-        return sort_segments(dt, d_vals != nullptr, segs.data(), segs.size(), *ws, stream, false);
+        // every round planned on the device: nothing is read back
+        return sort_batch_device_rounds(dt, d_vals != nullptr, (char *)d_keys, d_vals, d_offsets,
+                                        off.data(), num_segments, *ws, stream);
     } catch (...) {
         return set_error(QMS_ERR_NOMEM, "host exception in qms_sort_batch");
+    }
+}
+
+extern "C" int qms_batch_check(hipStream_t stream) {
+    try {
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e != hipSuccess) return hip_error(e, "hipGetDevice");
+        WorkspaceLease ws;
+        int rc = get_workspace(dev, stream, &ws);
+        if (rc != QMS_OK) return rc;
+        uint32_t st[2] = {0, 0};
+        const uint32_t zero[2] = {0, 0};
+        e = hipMemcpyAsync(st, ws.get()->r_status, sizeof(st), hipMemcpyDeviceToHost, stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(ws.get()->r_status, zero, sizeof(zero), hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return hip_error(e, "reading the batch status");
+        if (st[0] || st[1])
+            return set_error(QMS_ERR_HIP, "a batch left " + std::to_string(st[1]) +
+                                              " segments unsorted (" + std::to_string(st[0]) +
+                                              " plan errors)");
+        return QMS_OK;
+    } catch (...) {
+        return set_error(QMS_ERR_NOMEM, "host exception in qms_batch_check");
     }
 }

@@ -48,6 +48,20 @@ constexpr int kScanThreads = 1024;     // block size of the scans of large range
 constexpr int kScanPer = 8;            // tiles per thread and step of a scan
 constexpr uint32_t kScanGroups = 16;   // workgroups per segment of the pass-A scan
 constexpr uint64_t kEqBlockMin = 64;   // pivot-equal keys that always get their own block
+// Median-of-medians select: triples per histogram workgroup (kBlock threads
+// x kMomPerThread), and the workgroups a range of s keys takes.
+constexpr int kMomPerThread = 32;
+constexpr uint32_t kMomTile = (uint32_t)kBlock * kMomPerThread;
+__host__ __device__ inline uint32_t mom_tiles_of(uint64_t s) {
+    return (uint32_t)((s / 3 + kMomTile - 1) / kMomTile);
+}
+// Workgroups of the pass-A scan of a range of nt tiles, scans of nth threads:
+// one per chunk of nth * kScanPer tiles, at most kScanGroups.
+__host__ __device__ inline uint32_t scan_a_groups(uint32_t nt, uint32_t nth) {
+    const uint32_t C = nth * (uint32_t)kScanPer;
+    const uint32_t chunks = (nt + C - 1) / C;
+    return chunks < kScanGroups ? chunks : kScanGroups;
+}
 
 static_assert(kBaseTileKeys % kMergeTile == 0 && kBaseTilePairs % kMergeTile == 0,
               "runs must tile into merge tiles");
@@ -66,6 +80,7 @@ enum MetaSlot : int {
     M_RCB = 9,     // misplaced pairs per chunk, pass B
     M_MOM_PREFIX = 10,  // median-of-medians pivot: digits chosen so far
     M_MOM_RANK = 11,    // median-of-medians pivot: rank inside the prefix
+    M_MOM_DONE = 12,    // median-of-medians pivot: histogram workgroups done this pass
     M_COUNT = 16
 };
 
@@ -143,14 +158,38 @@ __host__ __device__ inline uint32_t pass_index(uint32_t L, uint32_t level, bool 
     return two ? level : ((L & 1u) ? (level + 1) / 2 : level / 2);
 }
 
+// Two ways to size a launch:
+//   host-sized   the host knows the work items and launches exactly that
+//                many workgroups (dyn == nullptr): workgroup g takes item g;
+//   device-sized the round plan, a kernel, wrote the tables and the number
+//                of work items into device memory (*dyn).  The host
+//                launches a grid from its estimate of the work: workgroup g
+//                takes item g if that is below *dyn, and a second, looping
+//                launch of the same kernel (a few workgroups, taking the
+//                items from the estimate on in grid-stride order) covers
+//                whatever the estimate missed.  The one-item form keeps the
+//                registers of the kernel body as they are (a loop around
+//                these bodies lets the compiler hoist thread-invariant
+//                values out of it and spill).  The prefix then has A + 1
+//                entries with every entry past the plan's last segment
+//                equal to the total, so that the lookup below never lands
+//                on an unused entry.
 template <class T>
 struct TaskRef {
     const T *tab = nullptr;        // device table (A > 1)
     const uint32_t *pre = nullptr; // device prefix of work items, A + 1 entries (A > 1)
-    uint32_t A = 0;                // segments
+    uint32_t A = 0;                // segments (an upper bound when device-sized)
     uint32_t base = 0;             // pre[0] (a sub-range of a longer table; A > 1)
     T one;               // the segment itself when A == 1
+    const uint32_t *dyn = nullptr; // device-sized: the number of work items
 };
+
+// Work items of a launch: the plan's count when device-sized, else the
+// count the host gives (the items its grid covers).
+template <class T>
+__device__ __forceinline__ uint32_t work_total(const TaskRef<T> &r, uint32_t host_total) {
+    return r.dyn ? *r.dyn : host_total;
+}
 
 // Work item g -> segment index (largest a with pre[a] <= g).
 __device__ __forceinline__ uint32_t find_task(const uint32_t *pre, uint32_t A, uint32_t g) {

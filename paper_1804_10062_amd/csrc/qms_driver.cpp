@@ -130,7 +130,7 @@ int mom_pivots(int dt, const PartSeg *pt, uint32_t A, Arena &ar, Workspace &ws, 
         R.one = tab[0];
         R.tab = ar.dev<PartSeg>(o_tab);
         R.pre = ar.dev<uint32_t>(o_pre);
-        hipError_t e = launch_mom_pivot(dt, R, pre[n], ws, st);
+        hipError_t e = launch_mom_pivot(dt, R, pre[n], 0, true, ws, st);
         if (e != hipSuccess) return hip_error(e, "median-of-medians pivot");
     }
     return QMS_OK;
@@ -248,10 +248,11 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
                 if (tot <= ws.caps.tiles) break;
                 TP *= 2;
             }
-            size_t o_tab, o_pre;
+            size_t o_tab, o_pre, o_scan;
             PartSeg *pt = ar.take<PartSeg>(A, &o_tab);
             uint32_t *pc = ar.take<uint32_t>(A + 1, &o_pre);
-            if (!pt || !pc) return set_error(QMS_ERR_NOMEM, "task table arena too small");
+            uint32_t *ps = ar.take<uint32_t>(A + 1, &o_scan);
+            if (!pt || !pc || !ps) return set_error(QMS_ERR_NOMEM, "task table arena too small");
             uint32_t toff = 0, coff = 0, max_nt = 0;
             bool any_mom = false;
             pc[0] = 0;
@@ -269,6 +270,10 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
             }
             if (coff > ws.caps.chunks)
                 return set_error(QMS_ERR_UNSUPPORTED, "batch too large for one round");
+            // scans of large ranges take 1024 threads; workgroups per segment
+            const uint32_t scan_threads = max_nt > 4 * kBlock ? kScanThreads : kBlock;
+            ps[0] = 0;
+            for (uint32_t a = 0; a < A; ++a) ps[a + 1] = ps[a] + scan_a_groups(pt[a].nt, scan_threads);
             if (A > 1) {
                 int rc = upload(ar, 0, st);
                 if (rc != QMS_OK) return rc;
@@ -284,17 +289,19 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
             L.tasks.pre = ar.dev<uint32_t>(o_pre);
             L.TP = TP;
             L.chunk_span = tune.chunk_span;
-            L.scan_threads = max_nt > 4 * kBlock ? kScanThreads : kBlock;
-            {
-                const uint32_t C = L.scan_threads * (uint32_t)kScanPer;
-                L.scan_groups = std::min<uint32_t>((max_nt + C - 1) / C, kScanGroups);
-            }
+            L.scan_threads = scan_threads;
             L.groups = (uint64_t)toff * (TP / kWave) <= ws.caps.groups;
             L.keys_total = (double)sum_s;
             L.ws = &ws;
             L.phase = 0;
-            L.work = toff;
+            L.grid = toff;
             hipError_t e = launch_partition_phase(dt, pairs, L, st);
+            if (e == hipSuccess) {
+                L.phase = 6;
+                L.tasks.pre = ar.dev<uint32_t>(o_scan);
+                L.grid = ps[A];
+                e = launch_partition_phase(dt, pairs, L, st);
+            }
             if (e != hipSuccess) return hip_error(e, "partition count/scan");
             e = hipMemcpyAsync(ws.h_res, ws.res, sizeof(uint32_t) * 4 * A, hipMemcpyDeviceToHost, st);
             if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -342,28 +349,30 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
                 L.phase = 1;
                 L.tasks.pre = ar.dev<uint32_t>(o_wa);
                 L.work = wa[A];
+                L.grid = (wa[A] + kWaves - 1) / kWaves;
                 if ((e = launch_partition_phase(dt, pairs, L, st)) != hipSuccess)
                     return hip_error(e, "split A");
                 L.phase = 2;
                 L.tasks.pre = ar.dev<uint32_t>(o_ca);
-                L.work = ca[A];
+                L.grid = ca[A];
                 L.bytes = swap_bytes;
                 if ((e = launch_partition_phase(dt, pairs, L, st)) != hipSuccess)
                     return hip_error(e, "swap A");
             }
             if (any_b) {
                 L.phase = 4;
-                L.work = A;
+                L.grid = A;
                 if ((e = launch_partition_phase(dt, pairs, L, st)) != hipSuccess)
                     return hip_error(e, "scan B");
                 L.phase = 3;
                 L.tasks.pre = ar.dev<uint32_t>(o_wb);
                 L.work = wb[A];
+                L.grid = (wb[A] + kWaves - 1) / kWaves;
                 if ((e = launch_partition_phase(dt, pairs, L, st)) != hipSuccess)
                     return hip_error(e, "split B");
                 L.phase = 5;
                 L.tasks.pre = ar.dev<uint32_t>(o_cb);
-                L.work = cb[A];
+                L.grid = cb[A];
                 if ((e = launch_partition_phase(dt, pairs, L, st)) != hipSuccess)
                     return hip_error(e, "swap B");
             }
@@ -469,7 +478,7 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
         R.one = stab[0];
         R.tab = ar.dev<SortSeg>(o_st);
         R.pre = ar.dev<uint32_t>(o_pt);
-        hipError_t e = launch_tile_sort(dt, pairs, R, ptile[T], base_bytes, ws, st);
+        hipError_t e = launch_tile_sort(dt, pairs, R, ptile[T], 0, base_bytes, ws, st);
         if (e != hipSuccess) return hip_error(e, "base case");
         // one launch group per (binary level, pass kind) over a contiguous
         // range [a0, a1) of the table
@@ -481,11 +490,13 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
             Rl.tab = ar.dev<SortSeg>(o_st) + a0;
             Rl.pre = ar.dev<uint32_t>(o_pm) + a0;
             Rl.base = pmerge[a0];
-            double mb = 0;
-            for (uint32_t a = a0; a < a1; ++a) mb += 16.0 * w * (double)stab[a].m;
-            const uint32_t pass = pass_index(stab[a0].L, l, two);
-            return launch_merge_pass(dt, pairs, Rl, l, pass, four, pmerge[a1] - pmerge[a0], mb, ws,
-                                     st);
+            MergeLaunch M;
+            M.tasks = Rl;
+            M.level = l;
+            M.four_way = four;
+            M.tiles = pmerge[a1] - pmerge[a0];
+            for (uint32_t a = a0; a < a1; ++a) M.bytes += 16.0 * w * (double)stab[a].m;
+            return launch_merge_pass(dt, pairs, M, ws, st);
         };
         for (uint32_t l = 0; l < maxL; ++l) {
             if (!by_parity) {

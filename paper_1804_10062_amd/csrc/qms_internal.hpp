@@ -40,6 +40,7 @@ struct WsCaps {
     uint64_t tiles, chunks, splits, groups;
     uint64_t final_cap;  // elements of the final ranges' scratch (0: none)
     uint32_t segs, mom;
+    uint32_t rounds;     // segments of a device-controlled batch group (0: none)
     size_t tab_bytes;    // bytes of one task-table arena
 };
 WsCaps default_caps();
@@ -88,7 +89,18 @@ struct Workspace {
     uint32_t *h_res = nullptr;   // pinned host mirror of res
     uint64_t rounds = 0;         // rounds run with this workspace (arena parity)
     WsCaps caps{};
+    // device-side round control (qms_rounds.hip): segment states, task
+    // tables, prefixes, work counters and the schedule status (errors,
+    // unsorted segments), for caps.rounds segments
+    void *r_seg = nullptr;
+    uint32_t *r_aseg = nullptr;
+    void *r_ptab = nullptr, *r_mtab = nullptr, *r_stab = nullptr;
+    uint32_t *r_pre = nullptr, *r_work = nullptr, *r_status = nullptr;
 };
+// Device bytes of the round-control state for `segs` segments, and its
+// arrays carved out of `b`.
+size_t rounds_state_bytes(uint32_t segs);
+void carve_rounds_state(Workspace *ws, char *b, uint32_t segs);
 // Point every device array of `ws` into `block` (workspace_device_bytes(c)
 // bytes, 256-byte aligned) and set its caps.
 void carve_workspace(Workspace *ws, char *block, const WsCaps &c);
@@ -103,14 +115,16 @@ TabLayout tab_layout();
 
 // One partition phase launch.
 struct PartitionLaunch {
-    int phase;                 // 0 count+scanA, 1 splitA, 2 swapA, 3 splitB, 4 scanB, 5 swapB
+    int phase;                 // 0 count, 6 scanA, 1 splitA, 2 swapA, 3 splitB, 4 scanB, 5 swapB
     TaskRef<PartSeg> tasks;    // table + work prefix of the phase
-    uint32_t work;             // work items (workgroups, or waves for splits)
+    uint32_t grid;             // workgroups launched (0: nothing to launch)
+    uint32_t first = 0;        // first item (the overflow launch of a device-sized phase)
+    bool loop = false;         // the workgroups loop over the items from first on
+    uint32_t work;             // waves of a host-sized split launch
     uint32_t TP;               // partition tile
     bool groups;               // count A records per-64-position counts (gcnt)
     uint32_t chunk_span;       // target positions per exchange chunk
     uint32_t scan_threads;     // block size of the scans
-    uint32_t scan_groups;      // workgroups per segment of the pass-A scan
     double keys_total;         // keys in all ranges (byte figures)
     double bytes;              // algorithmic bytes of the launch (swap A)
     const Workspace *ws;
@@ -121,14 +135,25 @@ hipError_t launch_partition_phase(int dt, bool pairs, const PartitionLaunch &L, 
 // `tasks` (PartSeg.pad = histogram slot < kCapMoM); `tiles` = total of
 // mom_tiles(s) over them, the exclusive prefix of which is tasks.pre.
 uint32_t mom_tiles(uint64_t s);
+// (overflow: looping workgroups after each pass of a device-sized launch)
 hipError_t launch_mom_pivot(int dt, const TaskRef<PartSeg> &tasks, uint32_t tiles,
-                            const Workspace &ws, hipStream_t st);
+                            uint32_t overflow, bool init, const Workspace &ws, hipStream_t st);
 hipError_t launch_tile_sort(int dt, bool pairs, const TaskRef<SortSeg> &tasks, uint32_t tiles,
-                            double bytes, const Workspace &ws, hipStream_t st);
-// One merge pass (2-way or 4-way) of the tasks listed, all starting at binary
-// level `level` with the same pass index `pass`.
-hipError_t launch_merge_pass(int dt, bool pairs, const TaskRef<SortSeg> &tasks, uint32_t level,
-                             uint32_t pass, bool four_way, uint32_t tiles, double bytes,
-                             const Workspace &ws, hipStream_t st);
+                            uint32_t overflow, double bytes, const Workspace &ws,
+                            hipStream_t st);
+// One merge pass (2-way or 4-way) of the tasks listed: every task's pass at
+// binary level `level`, or with `step` the step-th pass of every task (its
+// level from its level count).  tiles: merge tiles of the listed tasks
+// (with tasks.dyn holding the count: the launch's estimate of it).
+struct MergeLaunch {
+    TaskRef<SortSeg> tasks;
+    uint32_t level = 0, step = 0;
+    bool four_way = false;
+    uint32_t tiles = 0;     // merge tiles (device-sized: the estimate)
+    uint32_t overflow = 0;  // device-sized: looping workgroups for tiles beyond it
+    double bytes = 0;
+};
+hipError_t launch_merge_pass(int dt, bool pairs, const MergeLaunch &M, const Workspace &ws,
+                             hipStream_t st);
 
 }  // namespace qms

@@ -77,6 +77,26 @@ __device__ __forceinline__ Regions level_regions(const SortSeg &g, uint32_t leve
     return r;
 }
 
+// The binary level a launch works on for task g: `level` itself, or with
+// `step` (device-sized rounds, where one launch runs the k-th pass of every
+// task whatever its level count) the level of the task's k-th pass (k =
+// level): 2k for an even level count, 2k + 1 for an odd one (its first pass,
+// a 2-way one at level 0, runs in a launch of its own), k for 2-way tasks.
+__device__ __forceinline__ uint32_t task_level(const SortSeg &g, uint32_t level, uint32_t step) {
+    if (!step) return level;
+    return g.two_way ? level : 2 * level + (g.L & 1u);
+}
+// Run samples: pass p of a task reads the array of its parity and writes
+// the other one (the base case writes array 0 for pass 0).
+template <class K>
+__device__ __forceinline__ const K *samples_in(const SortSeg &g, uint32_t level, K *s0, K *s1) {
+    return (pass_index(g.L, level, g.two_way != 0) & 1u) ? s1 : s0;
+}
+template <class K>
+__device__ __forceinline__ K *samples_out(const SortSeg &g, uint32_t level, K *s0, K *s1) {
+    return (pass_index(g.L, level, g.two_way != 0) & 1u) ? s0 : s1;
+}
+
 // First index in [lo, hi) where the prefix-true predicate pred fails (hi if
 // it holds everywhere), searched by kSplitLanes lanes together: each step the
 // lanes probe kSplitLanes evenly spaced candidates and a ballot narrows the
@@ -167,19 +187,21 @@ __device__ __forceinline__ uint64_t group_count_before(const typename O::K *Y,
 // boundary of (A, B) (ties go to A, B first), #(A <= x) and #(B <= x) for
 // one of (C, D).  The tile's start vector (4 words) goes to bounds.
 template <class O, bool PAIRS, bool BOUNDS>
-__global__ __launch_bounds__(kBlock) void k_merge_split(TaskRef<SortSeg> tasks, uint32_t level,
-                                                        uint32_t total, uint32_t *splits,
-                                                        const typename O::K *samples,
-                                                        uint32_t *bounds) {
+__device__ __forceinline__ void merge_split_item(TaskRef<SortSeg> tasks, uint32_t gid,
+                                                 uint32_t total, uint32_t level_arg,
+                                                 uint32_t step, uint32_t *splits,
+                                                 typename O::K *samples0,
+                                                 typename O::K *samples1, uint32_t *bounds) {
     using K = typename O::K;
     constexpr uint64_t S = kSampleStride;
     constexpr uint32_t GPT = BOUNDS ? 2 : 1;  // lane groups per tile
-    const uint32_t gid = blockIdx.x * kBlock + threadIdx.x;
     const uint32_t w = gid / (GPT * kSplitLanes);
     const uint32_t half = (gid / kSplitLanes) % GPT;
     const bool active = w < total;
     uint32_t tile = 0, a = 0;
     const SortSeg g = task_of(tasks, active ? w : total - 1, &tile, &a);
+    const uint32_t level = task_level(g, level_arg, step);
+    const K *samples = samples_in<K>(g, level, samples0, samples1);
     const Regions rg = level_regions(g, level);
     const uint64_t W = (uint64_t)g.w0 << level;
     const MergeTileGeom geo = merge_geom(g.m, W, tile);
@@ -231,6 +253,33 @@ __global__ __launch_bounds__(kBlock) void k_merge_split(TaskRef<SortSeg> tasks, 
         }
     }
 }
+// Items: threads, kSplitLanes (two groups for BOUNDS) per tile; `first` is
+// a thread index (a multiple of kBlock).  Every lane of a wave takes part in
+// each search (lanes past the last tile with empty ranges), so the
+// iterations are uniform per workgroup.
+template <class O, bool PAIRS, bool BOUNDS, bool LOOP>
+__global__ __launch_bounds__(kBlock) void k_merge_split(TaskRef<SortSeg> tasks, uint32_t first,
+                                                        uint32_t level, uint32_t step,
+                                                        uint32_t total, uint32_t *splits,
+                                                        typename O::K *samples0,
+                                                        typename O::K *samples1,
+                                                        uint32_t *bounds) {
+    constexpr uint32_t GPT = BOUNDS ? 2 : 1;
+    const uint32_t W = work_total(tasks, total);
+    if (W == 0) return;
+    const uint64_t lanes = (uint64_t)W * GPT * kSplitLanes;
+    uint64_t base = (uint64_t)first + (uint64_t)blockIdx.x * kBlock;
+    if constexpr (!LOOP) {
+        if (base < lanes)
+            merge_split_item<O, PAIRS, BOUNDS>(tasks, (uint32_t)base + threadIdx.x, W, level, step,
+                                               splits, samples0, samples1, bounds);
+    } else {
+        for (; base < lanes; base += (uint64_t)gridDim.x * kBlock)
+            merge_split_item<O, PAIRS, BOUNDS>(tasks, (uint32_t)base + threadIdx.x, W, level, step,
+                                               splits, samples0, samples1, bounds);
+    }
+}
+
 
 // ---- 4-way pass ----------------------------------------------------------------
 // Tiles of a 4-way pass run from one boundary to the next in merge order
@@ -295,13 +344,12 @@ __device__ __forceinline__ Merge4Bnd next_boundary(const uint32_t *bd, uint64_t 
 // (running the merge workgroups in output order instead was measured slower:
 // the concurrent workgroups then crowd a narrow address range).  An absorbed
 // tile gets an empty range.  One thread per tile.
-__global__ __launch_bounds__(kBlock) void k_merge4_ends(TaskRef<SortSeg> tasks, uint32_t level,
-                                                        uint32_t total, const uint32_t *bounds,
-                                                        uint32_t *ends) {
-    const uint32_t w = blockIdx.x * kBlock + threadIdx.x;
-    if (w >= total) return;
+__device__ __forceinline__ void merge4_ends_item(TaskRef<SortSeg> tasks, uint32_t w,
+                                                 uint32_t level_arg, uint32_t step,
+                                                 const uint32_t *bounds, uint32_t *ends) {
     uint32_t tile, a;
     const SortSeg g = task_of(tasks, w, &tile, &a);
+    const uint32_t level = task_level(g, level_arg, step);
     const uint64_t W = (uint64_t)g.w0 << level;
     const uint32_t *bd = bounds + 4 * (uint64_t)g.split_off;
     uint32_t s[4];
@@ -336,6 +384,22 @@ __global__ __launch_bounds__(kBlock) void k_merge4_ends(TaskRef<SortSeg> tasks, 
         out[4 + r] = e[r];
     }
 }
+template <bool LOOP>
+__global__ __launch_bounds__(kBlock) void k_merge4_ends(TaskRef<SortSeg> tasks, uint32_t first,
+                                                        uint32_t level, uint32_t step,
+                                                        uint32_t total, const uint32_t *bounds,
+                                                        uint32_t *ends) {
+    // items: threads (no barriers)
+    const uint32_t W = work_total(tasks, total);
+    const uint32_t w0 = first + blockIdx.x * kBlock + threadIdx.x;
+    if constexpr (!LOOP) {
+        if (w0 < W) merge4_ends_item(tasks, w0, level, step, bounds, ends);
+    } else {
+        for (uint32_t w = w0; w < W; w += gridDim.x * kBlock)
+            merge4_ends_item(tasks, w, level, step, bounds, ends);
+    }
+}
+
 
 // Outputs [d, d + N) of the stable merge of X = sk[x0, x0 + nx) and
 // Y = sk[y0, y0 + ny) into out[] (X first on ties), d < nx + ny.  The word
@@ -444,18 +508,19 @@ __device__ __forceinline__ void merge4_final(L *sk, uint32_t c2, uint32_t cnt, u
 #endif
 constexpr int kMerge4Threads = 256;
 template <class O, bool PAIRS>
-__global__ __launch_bounds__(kMerge4Threads)
-__attribute__((amdgpu_waves_per_eu((PAIRS || sizeof(typename O::K) == 8) ? 4 : QMS_MERGE4_WPE,
-                                   (PAIRS || sizeof(typename O::K) == 8) ? 4 : QMS_MERGE4_WPE)))
-void k_merge4(TaskRef<SortSeg> tasks, uint32_t level, const uint32_t *bounds,
-              const uint32_t *ends, typename O::K *samples_out) {
+using Merge4Elem = std::conditional_t<PAIRS, uint64_t, typename O::K>;  // LDS element
+template <class O, bool PAIRS>
+__device__ __forceinline__ void merge4_item(TaskRef<SortSeg> tasks, uint32_t item,
+                                            uint32_t level_arg, uint32_t step,
+                                            const uint32_t *bounds, const uint32_t *ends,
+                                            typename O::K *samples0, typename O::K *samples1,
+                                            Merge4Elem<O, PAIRS> *sk) {
     using K = typename O::K;
     static_assert(!PAIRS || sizeof(K) == 4, "pairs carry 32-bit keys");
-    using L = std::conditional_t<PAIRS, uint64_t, K>;  // LDS element
+    using L = Merge4Elem<O, PAIRS>;
     constexpr uint32_t S = kMergeTile;
     constexpr uint32_t SP = kMerge4Pair;  // elements of one pair at most
     constexpr int NT = kMerge4Threads;
-    __shared__ L sk[kMerge4Lds];
     // the key of an LDS element
     auto lkey = [](L x) -> K {
         if constexpr (PAIRS) {
@@ -465,8 +530,10 @@ void k_merge4(TaskRef<SortSeg> tasks, uint32_t level, const uint32_t *bounds,
         }
     };
     uint32_t tile, a;
-    const SortSeg g = task_of(tasks, blockIdx.x, &tile, &a);
+    const SortSeg g = task_of(tasks, item, &tile, &a);
     if (tile * (uint64_t)S >= g.m) return;
+    const uint32_t level = task_level(g, level_arg, step);
+    K *smp_out = samples_out<K>(g, level, samples0, samples1);
     const Regions rg = level_regions(g, level);
     const uint64_t W = (uint64_t)g.w0 << level;
     const Merge4Geom geo = merge4_geom(g.m, W, tile);
@@ -559,7 +626,7 @@ void k_merge4(TaskRef<SortSeg> tasks, uint32_t level, const uint32_t *bounds,
         const uint32_t first = (uint32_t)((SS - ps % SS) % SS);
         const uint32_t el = first + tid * SS;
         if (el < cnt)
-            stg(samples_out + (uint64_t)g.split_off * kSamplesPerTile + (geo.gb + ps + el) / SS,
+            stg(smp_out + (uint64_t)g.split_off * kSamplesPerTile + (geo.gb + ps + el) / SS,
                 lkey(sk[el]));
     }
     K *Tw = (K *)rg.dk + geo.gb + ps;
@@ -574,6 +641,27 @@ void k_merge4(TaskRef<SortSeg> tasks, uint32_t level, const uint32_t *bounds,
         }
     }
 }
+template <class O, bool PAIRS, bool LOOP>
+__global__ __launch_bounds__(kMerge4Threads)
+__attribute__((amdgpu_waves_per_eu((PAIRS || sizeof(typename O::K) == 8) ? 4 : QMS_MERGE4_WPE,
+                                   (PAIRS || sizeof(typename O::K) == 8) ? 4 : QMS_MERGE4_WPE)))
+void k_merge4(TaskRef<SortSeg> tasks, uint32_t first, uint32_t level, uint32_t step,
+              const uint32_t *bounds, const uint32_t *ends, typename O::K *samples0,
+              typename O::K *samples1) {
+    __shared__ Merge4Elem<O, PAIRS> sk_mem[kMerge4Lds];
+    Merge4Elem<O, PAIRS> *sk = sk_mem;
+    const uint32_t W = work_total(tasks, first + gridDim.x);
+    if constexpr (!LOOP) {
+        const uint32_t item = first + blockIdx.x;
+        if (item < W) merge4_item<O, PAIRS>(tasks, item, level, step, bounds, ends, samples0, samples1, sk);
+    } else {
+        for (uint32_t item = first + blockIdx.x; item < W; item += gridDim.x) {
+            merge4_item<O, PAIRS>(tasks, item, level, step, bounds, ends, samples0, samples1, sk);
+            __syncthreads();  // the LDS is reused by the next item
+        }
+    }
+}
+
 
 template <class O, bool PAIRS>
 __device__ __forceinline__ void merge_block(typename O::K *S, uint32_t *SV, typename O::K *D,
@@ -673,81 +761,116 @@ __device__ __forceinline__ void merge_block(typename O::K *S, uint32_t *SV, type
 }
 
 template <class O, bool PAIRS>
-__global__ __launch_bounds__(kBlock) void k_merge(TaskRef<SortSeg> tasks, uint32_t level,
-                                                  const uint32_t *splits,
-                                                  typename O::K *samples_out) {
+__device__ __forceinline__ void merge2_item(TaskRef<SortSeg> tasks, uint32_t item,
+                                            uint32_t level_arg, uint32_t step,
+                                            const uint32_t *splits, typename O::K *samples0,
+                                            typename O::K *samples1) {
     using K = typename O::K;
     uint32_t tile, a;
-    const SortSeg g = task_of(tasks, blockIdx.x, &tile, &a);
+    const SortSeg g = task_of(tasks, item, &tile, &a);
     if (tile * (uint64_t)kMergeTile >= g.m) return;
+    const uint32_t level = task_level(g, level_arg, step);
     const Regions rg = level_regions(g, level);
     merge_block<O, PAIRS>((K *)rg.sk, PAIRS ? rg.sv : nullptr, (K *)rg.dk,
-                          PAIRS ? rg.dv : nullptr, g.m, (uint64_t)g.w0 << level,
-                          tile, splits + g.split_off,
-                          samples_out + (uint64_t)g.split_off * kSamplesPerTile);
+                          PAIRS ? rg.dv : nullptr, g.m, (uint64_t)g.w0 << level, tile,
+                          splits + g.split_off,
+                          samples_out<K>(g, level, samples0, samples1) +
+                              (uint64_t)g.split_off * kSamplesPerTile);
+}
+template <class O, bool PAIRS, bool LOOP>
+__global__ __launch_bounds__(kBlock) void k_merge(TaskRef<SortSeg> tasks, uint32_t first,
+                                                  uint32_t level_arg, uint32_t step,
+                                                  const uint32_t *splits, typename O::K *samples0,
+                                                  typename O::K *samples1) {
+    const uint32_t W = work_total(tasks, first + gridDim.x);
+    if constexpr (!LOOP) {
+        const uint32_t item = first + blockIdx.x;
+        if (item < W) merge2_item<O, PAIRS>(tasks, item, level_arg, step, splits, samples0, samples1);
+    } else {
+        for (uint32_t item = first + blockIdx.x; item < W; item += gridDim.x) {
+            merge2_item<O, PAIRS>(tasks, item, level_arg, step, splits, samples0, samples1);
+            __syncthreads();  // the LDS is reused by the next item
+        }
+    }
 }
 
+// One pass: the split search, (4-way) the tile ends, then the merge.
+// Host-sized: one workgroup per item.  Device-sized (M.overflow > 0): grids
+// from the estimate M.tiles, each kernel followed by an overflow launch of
+// M.overflow looping workgroups from where the estimate ends (every split
+// launch before the merge launches, which read the splits of neighbouring
+// tiles).
 template <class O, bool PAIRS>
-static hipError_t merge_t(const TaskRef<SortSeg> &tasks, uint32_t level, uint32_t pass,
-                          bool four_way, uint32_t tiles, double bytes, const Workspace &ws,
-                          hipStream_t st) {
+static hipError_t merge_t(const MergeLaunch &M, const Workspace &ws, hipStream_t st) {
     using K = typename O::K;
-    if (tiles == 0) return hipSuccess;
-    // pass p searches the samples written by pass p - 1 (or the base case)
-    // and writes the other array
-    const K *smp_in = (const K *)ws.samples[pass & 1];
-    K *smp_out = (K *)ws.samples[(pass + 1) & 1];
-    const uint32_t sgrid = (uint32_t)(((uint64_t)tiles * kSplitLanes + kBlock - 1) / kBlock);
-    if (!four_way) {
-        {
-            ProfScope prof(st, K_MERGE_SPLIT, 0.0);
-            hipLaunchKernelGGL((k_merge_split<O, PAIRS, false>), dim3(sgrid), dim3(kBlock), 0, st,
-                               tasks, level, tiles, ws.splits, smp_in, (uint32_t *)nullptr);
+    if (M.tiles == 0) return hipSuccess;
+    constexpr bool kFour = !PAIRS || sizeof(K) == 4;  // 4-way passes: payloads with 32-bit keys
+    if (M.four_way && !kFour) return hipErrorInvalidValue;
+    K *s0 = (K *)ws.samples[0], *s1 = (K *)ws.samples[1];
+    const uint32_t T = M.tiles, OV = M.overflow;
+    const uint32_t GPT = M.four_way ? 2 : 1;
+    const uint32_t sgrid = (uint32_t)(((uint64_t)T * GPT * kSplitLanes + kBlock - 1) / kBlock);
+    const uint32_t s_ov = sgrid * kBlock;  // first thread of the split overflow
+    const uint32_t egrid = (T + kBlock - 1) / kBlock;
+    const uint32_t e_ov = egrid * kBlock;  // first tile of the ends overflow
+    {
+        ProfScope prof(st, K_MERGE_SPLIT, 0.0);
+        if (!M.four_way) {
+            hipLaunchKernelGGL((k_merge_split<O, PAIRS, false, false>), dim3(sgrid), dim3(kBlock),
+                               0, st, M.tasks, 0u, M.level, M.step, T, ws.splits, s0, s1,
+                               (uint32_t *)nullptr);
+            if (OV)
+                hipLaunchKernelGGL((k_merge_split<O, PAIRS, false, true>), dim3(OV), dim3(kBlock),
+                                   0, st, M.tasks, s_ov, M.level, M.step, T, ws.splits, s0, s1,
+                                   (uint32_t *)nullptr);
+        } else if constexpr (kFour) {
+            hipLaunchKernelGGL((k_merge_split<O, false, true, false>), dim3(sgrid), dim3(kBlock), 0,
+                               st, M.tasks, 0u, M.level, M.step, T, ws.splits, s0, s1, ws.bounds);
+            if (OV)
+                hipLaunchKernelGGL((k_merge_split<O, false, true, true>), dim3(OV), dim3(kBlock), 0,
+                                   st, M.tasks, s_ov, M.level, M.step, T, ws.splits, s0, s1,
+                                   ws.bounds);
+            hipLaunchKernelGGL(k_merge4_ends<false>, dim3(egrid), dim3(kBlock), 0, st, M.tasks, 0u,
+                               M.level, M.step, T, (const uint32_t *)ws.bounds, ws.ends);
+            if (OV)
+                hipLaunchKernelGGL(k_merge4_ends<true>, dim3(OV), dim3(kBlock), 0, st, M.tasks,
+                                   e_ov, M.level, M.step, T, (const uint32_t *)ws.bounds, ws.ends);
         }
-        {
-            // per element: read the run cell and the window cell, write both
-            ProfScope prof(st, K_MERGE, bytes);
-            hipLaunchKernelGGL((k_merge<O, PAIRS>), dim3(tiles), dim3(kBlock), 0, st, tasks,
-                               level, (const uint32_t *)ws.splits, smp_out);
-        }
-        return hipGetLastError();
     }
-    if constexpr (!PAIRS || sizeof(K) == 4) {  // 4-way passes (payloads with 32-bit keys only)
-        {
-            ProfScope prof(st, K_MERGE_SPLIT, 0.0);
-            hipLaunchKernelGGL((k_merge_split<O, false, true>), dim3(2 * sgrid), dim3(kBlock), 0,
-                               st, tasks, level, tiles, ws.splits, smp_in, ws.bounds);
-            hipLaunchKernelGGL(k_merge4_ends, dim3((tiles + kBlock - 1) / kBlock), dim3(kBlock),
-                               0, st, tasks, level, tiles, (const uint32_t *)ws.bounds, ws.ends);
+    {
+        // per element: read the run cell and the window cell, write both (a
+        // 4-way pass moves each element once for two levels)
+        ProfScope prof(st, K_MERGE, M.bytes, M.step ? -1 : (int)M.level);
+        if (!M.four_way) {
+            hipLaunchKernelGGL((k_merge<O, PAIRS, false>), dim3(T), dim3(kBlock), 0, st, M.tasks,
+                               0u, M.level, M.step, (const uint32_t *)ws.splits, s0, s1);
+            if (OV)
+                hipLaunchKernelGGL((k_merge<O, PAIRS, true>), dim3(OV), dim3(kBlock), 0, st,
+                                   M.tasks, T, M.level, M.step, (const uint32_t *)ws.splits, s0, s1);
+        } else if constexpr (kFour) {
+            hipLaunchKernelGGL((k_merge4<O, PAIRS, false>), dim3(T), dim3(kMerge4Threads), 0, st,
+                               M.tasks, 0u, M.level, M.step, (const uint32_t *)ws.bounds,
+                               (const uint32_t *)ws.ends, s0, s1);
+            if (OV)
+                hipLaunchKernelGGL((k_merge4<O, PAIRS, true>), dim3(OV), dim3(kMerge4Threads), 0,
+                                   st, M.tasks, T, M.level, M.step, (const uint32_t *)ws.bounds,
+                                   (const uint32_t *)ws.ends, s0, s1);
         }
-        {
-            // the same 16 bytes per element as a 2-way pass, for two levels
-            ProfScope prof(st, K_MERGE, bytes);
-            hipLaunchKernelGGL((k_merge4<O, PAIRS>), dim3(tiles), dim3(kMerge4Threads), 0, st, tasks,
-                               level, (const uint32_t *)ws.bounds, (const uint32_t *)ws.ends,
-                               smp_out);
-        }
-        return hipGetLastError();
     }
-    return hipErrorInvalidValue;
+    return hipGetLastError();
 }
 
-hipError_t launch_merge_pass(int dt, bool pairs, const TaskRef<SortSeg> &tasks, uint32_t level,
-                             uint32_t pass, bool four_way, uint32_t tiles, double bytes,
-                             const Workspace &ws, hipStream_t st) {
+hipError_t launch_merge_pass(int dt, bool pairs, const MergeLaunch &M, const Workspace &ws,
+                             hipStream_t st) {
     switch (dt) {
     case 0:
-        return pairs ? merge_t<OrdU32, true>(tasks, level, pass, four_way, tiles, bytes, ws, st)
-                     : merge_t<OrdU32, false>(tasks, level, pass, four_way, tiles, bytes, ws, st);
+        return pairs ? merge_t<OrdU32, true>(M, ws, st) : merge_t<OrdU32, false>(M, ws, st);
     case 1:
-        return pairs ? merge_t<OrdF32, true>(tasks, level, pass, four_way, tiles, bytes, ws, st)
-                     : merge_t<OrdF32, false>(tasks, level, pass, four_way, tiles, bytes, ws, st);
+        return pairs ? merge_t<OrdF32, true>(M, ws, st) : merge_t<OrdF32, false>(M, ws, st);
     case 2:  // 64-bit keys: key-only
-        return pairs ? hipErrorInvalidValue
-                     : merge_t<OrdU64, false>(tasks, level, pass, four_way, tiles, bytes, ws, st);
+        return pairs ? hipErrorInvalidValue : merge_t<OrdU64, false>(M, ws, st);
     case 3:
-        return pairs ? hipErrorInvalidValue
-                     : merge_t<OrdF64, false>(tasks, level, pass, four_way, tiles, bytes, ws, st);
+        return pairs ? hipErrorInvalidValue : merge_t<OrdF64, false>(M, ws, st);
     default:
         return hipErrorInvalidValue;
     }

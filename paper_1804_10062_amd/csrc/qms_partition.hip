@@ -55,13 +55,13 @@ __device__ __forceinline__ const PartSeg &seg_by_index(const TaskRef<PartSeg> &r
 // per tile), from which the split finds a chunk boundary's 64 positions
 // without walking the tile.
 template <class O>
-__global__ __launch_bounds__(kBlock) void k_part_count(TaskRef<PartSeg> tasks, uint32_t TP,
-                                                       uint32_t *cnt_lt, uint32_t *cnt_eq,
-                                                       uint8_t *gcnt, uint64_t *meta) {
+__device__ __forceinline__ void part_count_item(TaskRef<PartSeg> tasks, uint32_t item,
+                                                uint32_t TP, uint32_t *cnt_lt, uint32_t *cnt_eq,
+                                                uint8_t *gcnt, const uint64_t *meta,
+                                                uint32_t *tmp) {
     using K = typename O::K;
-    __shared__ uint32_t tmp[kWaves + 1];
     uint32_t t, a;
-    const PartSeg g = task_of(tasks, blockIdx.x, &t, &a);
+    const PartSeg g = task_of(tasks, item, &t, &a);
     const K *keys = (const K *)g.keys + g.lo;
     const uint64_t ts = (uint64_t)t * TP;
     const uint64_t te = ts + TP < g.s ? ts + TP : g.s;
@@ -103,10 +103,28 @@ __global__ __launch_bounds__(kBlock) void k_part_count(TaskRef<PartSeg> tasks, u
         }
     }
     lt = block_sum(lt, tmp);
-    eq = block_sum(eq, tmp);
+    eq = block_sum(eq, tmp);  // ends with a barrier: tmp is free again
     if (threadIdx.x == 0) {
         cnt_lt[g.tile_off + t] = lt;
         cnt_eq[g.tile_off + t] = eq;
+    }
+}
+template <class O, bool LOOP>
+__global__ __launch_bounds__(kBlock) void k_part_count(TaskRef<PartSeg> tasks, uint32_t first,
+                                                       uint32_t TP, uint32_t *cnt_lt,
+                                                       uint32_t *cnt_eq, uint8_t *gcnt,
+                                                       const uint64_t *meta) {
+    __shared__ uint32_t tmp_lds[kWaves + 1];
+    uint32_t *tmp = tmp_lds;
+    const uint32_t W = work_total(tasks, first + gridDim.x);
+    if constexpr (!LOOP) {
+        const uint32_t item = first + blockIdx.x;
+        if (item < W) part_count_item<O>(tasks, item, TP, cnt_lt, cnt_eq, gcnt, meta, tmp);
+    } else {
+        for (uint32_t item = first + blockIdx.x; item < W; item += gridDim.x) {
+            part_count_item<O>(tasks, item, TP, cnt_lt, cnt_eq, gcnt, meta, tmp);
+            __syncthreads();  // the LDS is reused by the next item
+        }
     }
 }
 
@@ -267,26 +285,33 @@ __device__ __forceinline__ void mark_chunk_tiles(uint32_t nt, uint32_t TP, uint3
 // waited at each chunk for the previous chunk's stores to drain, since a
 // load's wait also covers the stores issued before it: about 5 us per
 // 8,192 tiles on the largest ranges.)
+// Work items: the task prefix counts each segment's workgroups
+// (min(chunks of tiles, kScanGroups)); item -> (segment a, group kgrp).
+template <int NTH>
+struct ScanALds {
+    static constexpr uint32_t C = (uint32_t)NTH * kScanPer;
+    static constexpr uint32_t kMaxChunks = (uint32_t)(kCapTiles / C) + 1;
+    uint32_t tmp[NTH / kWave + 1];
+    uint32_t csum[kMaxChunks];  // #(< p) per chunk, then its carry
+    uint32_t stage[C + NTH + 1];  // one spare slot every kScanPer (bank spread)
+};
 template <class O, int NTH>
-__global__ __launch_bounds__(NTH) void k_part_scan_a(TaskRef<PartSeg> tasks, uint32_t TP,
-                                                     uint32_t span,
-                                                     const uint32_t *cnt_lt_all,
-                                                     const uint32_t *cnt_eq_all,
-                                                     uint32_t *preL_all, uint32_t *preR_all,
-                                                     uint32_t *eqmv_all, uint32_t *spL_all,
-                                                     uint32_t *spR_all, uint64_t *meta_all,
-                                                     uint32_t *res) {
+__device__ __forceinline__ void part_scan_a_item(TaskRef<PartSeg> tasks, uint32_t item,
+                                                 uint32_t TP, uint32_t span,
+                                                 const uint32_t *cnt_lt_all,
+                                                 const uint32_t *cnt_eq_all, uint32_t *preL_all,
+                                                 uint32_t *preR_all, uint32_t *eqmv_all,
+                                                 uint32_t *spL_all, uint32_t *spR_all,
+                                                 uint64_t *meta_all, uint32_t *res,
+                                                 ScanALds<NTH> &lds) {
     constexpr int PER = kScanPer;
     constexpr uint32_t C = (uint32_t)NTH * PER;
-    constexpr uint32_t kMaxChunks = (uint32_t)(kCapTiles / C) + 1;
     static_assert(kCapTiles / ((uint64_t)kScanThreads * kScanPer) < kScanThreads,
                   "one thread per chunk carries the chunks' prefix");
-    __shared__ uint32_t tmp[NTH / kWave + 1];
-    __shared__ uint32_t csum[kMaxChunks];  // #(< p) per chunk, then its carry
-    __shared__ uint32_t stage[C + NTH + 1];  // one spare slot every PER (bank spread)
+    uint32_t *tmp = lds.tmp, *csum = lds.csum, *stage = lds.stage;
     using K = typename O::K;
-    const uint32_t a = blockIdx.y;
-    const PartSeg g = seg_by_index(tasks, a);
+    uint32_t kgrp, a;
+    const PartSeg g = task_of(tasks, item, &kgrp, &a);
     const K *keys = (const K *)g.keys + g.lo;
     const uint32_t *LT = cnt_lt_all + g.tile_off;
     const uint32_t *EQ = cnt_eq_all + g.tile_off;
@@ -298,10 +323,10 @@ __global__ __launch_bounds__(NTH) void k_part_scan_a(TaskRef<PartSeg> tasks, uin
     const uint64_t s = g.s;
     const uint32_t tid = threadIdx.x;
     const uint32_t nch_t = (nt + C - 1) / C;  // chunks of tiles
-    const uint32_t G = nch_t < kScanGroups ? nch_t : kScanGroups;
-    if (blockIdx.x >= G) return;
-    const uint32_t k0 = (uint32_t)((uint64_t)blockIdx.x * nch_t / G);
-    const uint32_t k1 = (uint32_t)((uint64_t)(blockIdx.x + 1) * nch_t / G);
+    const uint32_t G = scan_a_groups(nt, NTH);
+    if (kgrp >= G) return;
+    const uint32_t k0 = (uint32_t)((uint64_t)kgrp * nch_t / G);
+    const uint32_t k1 = (uint32_t)((uint64_t)(kgrp + 1) * nch_t / G);
     for (uint32_t k = tid; k < nch_t; k += NTH) csum[k] = 0;
     const K p = (g.flags & kPivotMoM) ? (K)ldg(meta + M_PIVOT) : pivot_of<O>(keys, 0, s);
     __syncthreads();
@@ -431,7 +456,7 @@ __global__ __launch_bounds__(NTH) void k_part_scan_a(TaskRef<PartSeg> tasks, uin
         }
         __syncthreads();  // the stage is reused by the next chunk
     }
-    if (blockIdx.x == 0 && tid == 0) {
+    if (kgrp == 0 && tid == 0) {
         meta[M_RCA] = rc;
         meta[M_PIVOT] = p;
         meta[M_CLT] = c_lt;
@@ -451,23 +476,52 @@ __global__ __launch_bounds__(NTH) void k_part_scan_a(TaskRef<PartSeg> tasks, uin
         res[4 * a + 3] = 0;
     }
 }
+template <class O, int NTH, bool LOOP>
+__global__ __launch_bounds__(NTH) void k_part_scan_a(TaskRef<PartSeg> tasks, uint32_t first,
+                                                     uint32_t TP, uint32_t span,
+                                                     const uint32_t *cnt_lt_all,
+                                                     const uint32_t *cnt_eq_all,
+                                                     uint32_t *preL_all, uint32_t *preR_all,
+                                                     uint32_t *eqmv_all, uint32_t *spL_all,
+                                                     uint32_t *spR_all, uint64_t *meta_all,
+                                                     uint32_t *res) {
+    __shared__ ScanALds<NTH> lds_mem;
+    ScanALds<NTH> *lds = &lds_mem;
+    const uint32_t W = work_total(tasks, first + gridDim.x);
+    if constexpr (!LOOP) {
+        const uint32_t item = first + blockIdx.x;
+        if (item < W) part_scan_a_item<O, NTH>(tasks, item, TP, span, cnt_lt_all, cnt_eq_all, preL_all,
+                                     preR_all, eqmv_all, spL_all, spR_all, meta_all, res, *lds);
+    } else {
+        for (uint32_t item = first + blockIdx.x; item < W; item += gridDim.x) {
+            part_scan_a_item<O, NTH>(tasks, item, TP, span, cnt_lt_all, cnt_eq_all, preL_all,
+                                     preR_all, eqmv_all, spL_all, spR_all, meta_all, res, *lds);
+            __syncthreads();  // the LDS is reused by the next item
+        }
+    }
+}
 
 // ---- scan of pass B ----------------------------------------------------------
 // After pass A, [B1, s) holds only keys >= p.  The keys == p of a tile's part
 // right of B1 are the ones it held before (they did not move) plus the ones
 // pass A moved in (eqmv).  One workgroup per segment; segments without
 // possible pass-B pairs return at once.
+template <int NTH>
+struct ScanBLds {
+    uint32_t tmp[NTH / kWave + 1];
+    ScanStage<NTH> stage;
+};
 template <class O, int NTH>
-__global__ __launch_bounds__(NTH) void k_part_scan_b(TaskRef<PartSeg> tasks, uint32_t TP,
-                                                     uint32_t span,
-                                                     const uint32_t *cnt_eq_all,
-                                                     const uint32_t *eqmv_all,
-                                                     uint32_t *preL_all, uint32_t *preR_all,
-                                                     uint32_t *spL_all, uint32_t *spR_all,
-                                                     uint64_t *meta_all) {
-    __shared__ uint32_t tmp[NTH / kWave + 1];
-    __shared__ ScanStage<NTH> stage;
-    const PartSeg g = seg_by_index(tasks, blockIdx.x);
+__device__ __forceinline__ void part_scan_b_item(TaskRef<PartSeg> tasks, uint32_t item,
+                                                 uint32_t TP, uint32_t span,
+                                                 const uint32_t *cnt_eq_all,
+                                                 const uint32_t *eqmv_all, uint32_t *preL_all,
+                                                 uint32_t *preR_all, uint32_t *spL_all,
+                                                 uint32_t *spR_all, uint64_t *meta_all,
+                                                 ScanBLds<NTH> &lds) {
+    uint32_t *tmp = lds.tmp;
+    ScanStage<NTH> &stage = lds.stage;
+    const PartSeg g = seg_by_index(tasks, item);
     uint64_t *meta = meta_all + (uint64_t)g.slot * M_COUNT;
     const uint64_t s = g.s;
     const uint64_t b1 = meta[M_CLT];
@@ -524,6 +578,30 @@ __global__ __launch_bounds__(NTH) void k_part_scan_b(TaskRef<PartSeg> tasks, uin
         spR[nch] = (uint32_t)s;
     }
 }
+// One item per segment of the table.
+template <class O, int NTH, bool LOOP>
+__global__ __launch_bounds__(NTH) void k_part_scan_b(TaskRef<PartSeg> tasks, uint32_t first,
+                                                     uint32_t TP, uint32_t span,
+                                                     const uint32_t *cnt_eq_all,
+                                                     const uint32_t *eqmv_all,
+                                                     uint32_t *preL_all, uint32_t *preR_all,
+                                                     uint32_t *spL_all, uint32_t *spR_all,
+                                                     uint64_t *meta_all) {
+    __shared__ ScanBLds<NTH> lds_mem;
+    ScanBLds<NTH> *lds = &lds_mem;
+    const uint32_t W = work_total(tasks, first + gridDim.x);
+    if constexpr (!LOOP) {
+        const uint32_t item = first + blockIdx.x;
+        if (item < W) part_scan_b_item<O, NTH>(tasks, item, TP, span, cnt_eq_all, eqmv_all, preL_all,
+                                     preR_all, spL_all, spR_all, meta_all, *lds);
+    } else {
+        for (uint32_t item = first + blockIdx.x; item < W; item += gridDim.x) {
+            part_scan_b_item<O, NTH>(tasks, item, TP, span, cnt_eq_all, eqmv_all, preL_all,
+                                     preR_all, spL_all, spR_all, meta_all, *lds);
+            __syncthreads();  // the LDS is reused by the next item
+        }
+    }
+}
 
 // Left region and right region of a pass, as offsets from the range start,
 // and the class test: an element belongs left if ord(k) < p (pass A) or
@@ -564,13 +642,10 @@ __device__ __forceinline__ bool belongs_left(K k, K p) {
 // over those counts picks the 64 positions that hold the element and one
 // ballot over them finishes; otherwise the wave walks the tile.
 template <class O, int PASS>
-__global__ __launch_bounds__(kBlock) void k_part_split(TaskRef<PartSeg> tasks, uint32_t TP,
-                                                       uint32_t total, uint32_t *spL_all,
-                                                       uint32_t *spR_all,
-                                                       const uint8_t *gcnt,
-                                                       const uint64_t *meta_all) {
-    const uint32_t gw = blockIdx.x * kWaves + wave_id();
-    if (gw >= total) return;
+__device__ __forceinline__ void part_split_item(TaskRef<PartSeg> tasks, uint32_t gw,
+                                                uint32_t TP, uint32_t *spL_all,
+                                                uint32_t *spR_all, const uint8_t *gcnt,
+                                                const uint64_t *meta_all) {
     uint32_t w, a;
     const PartSeg g = task_of(tasks, gw, &w, &a);
     const uint64_t *meta = meta_all + (uint64_t)g.slot * M_COUNT;
@@ -657,6 +732,23 @@ __global__ __launch_bounds__(kBlock) void k_part_split(TaskRef<PartSeg> tasks, u
         }
     }
 }
+template <class O, int PASS, bool LOOP>
+__global__ __launch_bounds__(kBlock) void k_part_split(TaskRef<PartSeg> tasks, uint32_t first,
+                                                       uint32_t TP, uint32_t total,
+                                                       uint32_t *spL_all, uint32_t *spR_all,
+                                                       const uint8_t *gcnt,
+                                                       const uint64_t *meta_all) {
+    // items: waves (no barriers)
+    const uint32_t W = work_total(tasks, total);
+    const uint32_t gw0 = first + blockIdx.x * kWaves + wave_id();
+    if constexpr (!LOOP) {
+        if (gw0 < W) part_split_item<O, PASS>(tasks, gw0, TP, spL_all, spR_all, gcnt, meta_all);
+    } else {
+        for (uint32_t gw = gw0; gw < W; gw += gridDim.x * kWaves)
+            part_split_item<O, PASS>(tasks, gw, TP, spL_all, spR_all, gcnt, meta_all);
+    }
+}
+
 
 // ---- swap ------------------------------------------------------------------------
 // Scan state of one side of a chunk: its position range [pos, end) (offsets
@@ -751,20 +843,23 @@ __device__ __forceinline__ void record_subtile(SideScan &sc, const uint64_t m[kP
 // stores (reading the keys again would fetch nearly every line of the range
 // a second time: misplaced elements are dense when the pivot is central);
 // payloads of key/payload sorts are gathered at the exchange.
+struct SwapLds {
+    uint32_t pL[kRankChunk], pR[kRankChunk];
+    uint32_t wtot[2][kWaves];
+};
 template <class O, bool PAIRS, int PASS>
-__global__ __launch_bounds__(kBlock) void k_part_swap(TaskRef<PartSeg> tasks, uint32_t TP,
-                                                      const uint32_t *preL_all,
-                                                      const uint32_t *preR_all,
-                                                      const uint32_t *spL_all,
-                                                      const uint32_t *spR_all,
-                                                      uint32_t *eqmv_all,
-                                                      const uint64_t *meta_all) {
+__device__ __forceinline__ void part_swap_item(TaskRef<PartSeg> tasks, uint32_t item,
+                                               uint32_t TP, const uint32_t *preL_all,
+                                               const uint32_t *preR_all,
+                                               const uint32_t *spL_all,
+                                               const uint32_t *spR_all, uint32_t *eqmv_all,
+                                               const uint64_t *meta_all, SwapLds &lds,
+                                               typename O::K *vL, typename O::K *vR) {
     using K = typename O::K;
-    __shared__ uint32_t pL[kRankChunk], pR[kRankChunk];
-    __shared__ K vL[kRankChunk], vR[kRankChunk];
-    __shared__ uint32_t wtot[2][kWaves];
+    uint32_t *pL = lds.pL, *pR = lds.pR;
+    uint32_t(*wtot)[kWaves] = lds.wtot;
     uint32_t j, a;
-    const PartSeg g = task_of(tasks, blockIdx.x, &j, &a);
+    const PartSeg g = task_of(tasks, item, &j, &a);
     const uint64_t *meta = meta_all + (uint64_t)g.slot * M_COUNT;
     const uint32_t X = (uint32_t)meta[PASS == 0 ? M_XA : M_XB];
     const uint32_t rc = (uint32_t)meta[PASS == 0 ? M_RCA : M_RCB];
@@ -851,81 +946,110 @@ __global__ __launch_bounds__(kBlock) void k_part_swap(TaskRef<PartSeg> tasks, ui
         }
     }
 }
+template <class O, bool PAIRS, int PASS, bool LOOP>
+__global__ __launch_bounds__(kBlock) void k_part_swap(TaskRef<PartSeg> tasks, uint32_t first,
+                                                      uint32_t TP, const uint32_t *preL_all,
+                                                      const uint32_t *preR_all,
+                                                      const uint32_t *spL_all,
+                                                      const uint32_t *spR_all,
+                                                      uint32_t *eqmv_all,
+                                                      const uint64_t *meta_all) {
+    using K = typename O::K;
+    __shared__ SwapLds lds_mem;
+    __shared__ K vL_mem[kRankChunk], vR_mem[kRankChunk];
+    SwapLds *lds = &lds_mem;
+    K *vL = vL_mem, *vR = vR_mem;
+    const uint32_t W = work_total(tasks, first + gridDim.x);
+    if constexpr (!LOOP) {
+        const uint32_t item = first + blockIdx.x;
+        if (item < W) part_swap_item<O, PAIRS, PASS>(tasks, item, TP, preL_all, preR_all, spL_all,
+                                           spR_all, eqmv_all, meta_all, *lds, vL, vR);
+    } else {
+        for (uint32_t item = first + blockIdx.x; item < W; item += gridDim.x) {
+            part_swap_item<O, PAIRS, PASS>(tasks, item, TP, preL_all, preR_all, spL_all,
+                                           spR_all, eqmv_all, meta_all, *lds, vL, vR);
+            __syncthreads();  // the LDS is reused by the next item
+        }
+    }
+}
+
 
 // ---- host side ---------------------------------------------------------------------
-template <class O, bool PAIRS>
-static hipError_t partition_t(const PartitionLaunch &L, hipStream_t st) {
+template <class O, bool PAIRS, bool LOOP>
+static hipError_t partition_phase(const PartitionLaunch &L, hipStream_t st) {
     const Workspace &ws = *L.ws;
+    // L.grid workgroups from item L.first on: exactly the work items of a
+    // host-sized launch; for a device-sized one the estimate (first = 0) or
+    // the overflow (LOOP)
+    if (L.grid == 0) return hipSuccess;
+    const uint32_t f = L.first;
     switch (L.phase) {
-    case 0: {  // count + scan A
-        {
-            ProfScope prof(st, K_PART_COUNT, (double)sizeof(typename O::K) * L.keys_total);
-            hipLaunchKernelGGL((k_part_count<O>), dim3(L.work), dim3(kBlock), 0, st, L.tasks,
-                               L.TP, ws.cnt_lt, ws.cnt_eq, L.groups ? ws.gcnt : nullptr,
-                               ws.meta);
-        }
-        {
-            ProfScope prof(st, K_PART_SCAN, 0.0);
-            if (L.scan_threads == kScanThreads)
-                hipLaunchKernelGGL((k_part_scan_a<O, kScanThreads>), dim3(L.scan_groups, L.tasks.A),
-                                   dim3(kScanThreads), 0, st, L.tasks, L.TP, L.chunk_span,
-                                   ws.cnt_lt, ws.cnt_eq,
-                                   ws.preL, ws.preR, ws.eqmv, ws.spL, ws.spR, ws.meta, ws.res);
-            else
-                hipLaunchKernelGGL((k_part_scan_a<O, kBlock>), dim3(L.scan_groups, L.tasks.A), dim3(kBlock), 0,
-                                   st, L.tasks, L.TP, L.chunk_span, ws.cnt_lt, ws.cnt_eq,
-                                   ws.preL, ws.preR,
-                                   ws.eqmv, ws.spL, ws.spR, ws.meta, ws.res);
-        }
+    case 0: {  // count
+        ProfScope prof(st, K_PART_COUNT, (double)sizeof(typename O::K) * L.keys_total);
+        hipLaunchKernelGGL((k_part_count<O, LOOP>), dim3(L.grid), dim3(kBlock), 0, st, L.tasks, f,
+                           L.TP, ws.cnt_lt, ws.cnt_eq, L.groups ? ws.gcnt : nullptr,
+                           (const uint64_t *)ws.meta);
+        break;
+    }
+    case 6: {  // scan A (tasks.pre counts each segment's scan workgroups)
+        ProfScope prof(st, K_PART_SCAN, 0.0);
+        if (L.scan_threads == kScanThreads)
+            hipLaunchKernelGGL((k_part_scan_a<O, kScanThreads, LOOP>), dim3(L.grid),
+                               dim3(kScanThreads), 0, st, L.tasks, f, L.TP, L.chunk_span,
+                               ws.cnt_lt, ws.cnt_eq, ws.preL, ws.preR, ws.eqmv, ws.spL, ws.spR,
+                               ws.meta, ws.res);
+        else
+            hipLaunchKernelGGL((k_part_scan_a<O, kBlock, LOOP>), dim3(L.grid), dim3(kBlock), 0, st,
+                               L.tasks, f, L.TP, L.chunk_span, ws.cnt_lt, ws.cnt_eq, ws.preL,
+                               ws.preR, ws.eqmv, ws.spL, ws.spR, ws.meta, ws.res);
         break;
     }
     case 1:    // split of pass A
-    case 3: {  // split of pass B
-        if (L.work == 0) break;
+    case 3: {  // split of pass B (items: waves; L.work: waves of a host-sized launch)
         ProfScope prof(st, K_PART_SPLIT, 0.0);
         if (L.phase == 1)
-            hipLaunchKernelGGL((k_part_split<O, 0>), dim3((L.work + kWaves - 1) / kWaves),
-                               dim3(kBlock), 0, st, L.tasks, L.TP, L.work, ws.spL, ws.spR,
-                               L.groups ? ws.gcnt : nullptr, ws.meta);
+            hipLaunchKernelGGL((k_part_split<O, 0, LOOP>), dim3(L.grid), dim3(kBlock), 0, st,
+                               L.tasks, f, L.TP, L.work, ws.spL, ws.spR,
+                               L.groups ? ws.gcnt : nullptr, (const uint64_t *)ws.meta);
         else
-            hipLaunchKernelGGL((k_part_split<O, 1>), dim3((L.work + kWaves - 1) / kWaves),
-                               dim3(kBlock), 0, st, L.tasks, L.TP, L.work, ws.spL, ws.spR,
-                               nullptr, ws.meta);
+            hipLaunchKernelGGL((k_part_split<O, 1, LOOP>), dim3(L.grid), dim3(kBlock), 0, st,
+                               L.tasks, f, L.TP, L.work, ws.spL, ws.spR,
+                               (const uint8_t *)nullptr, (const uint64_t *)ws.meta);
         break;
     }
-    case 2: {  // swap of pass A
-        if (L.work == 0) break;
-        ProfScope prof(st, K_PART_SWAP, L.bytes);
-        hipLaunchKernelGGL((k_part_swap<O, PAIRS, 0>), dim3(L.work), dim3(kBlock), 0, st,
-                           L.tasks, L.TP, ws.preL, ws.preR, ws.spL, ws.spR, ws.eqmv, ws.meta);
+    case 2:    // swap of pass A
+    case 5: {  // swap of pass B (its pair count is known only on the device)
+        ProfScope prof(st, K_PART_SWAP, L.phase == 2 ? L.bytes : 0.0);
+        if (L.phase == 2)
+            hipLaunchKernelGGL((k_part_swap<O, PAIRS, 0, LOOP>), dim3(L.grid), dim3(kBlock), 0, st,
+                               L.tasks, f, L.TP, ws.preL, ws.preR, ws.spL, ws.spR, ws.eqmv,
+                               (const uint64_t *)ws.meta);
+        else
+            hipLaunchKernelGGL((k_part_swap<O, PAIRS, 1, LOOP>), dim3(L.grid), dim3(kBlock), 0, st,
+                               L.tasks, f, L.TP, ws.preL, ws.preR, ws.spL, ws.spR, ws.eqmv,
+                               (const uint64_t *)ws.meta);
         break;
     }
-    case 4: {  // scan B
+    case 4: {  // scan B, one item per segment
         ProfScope prof(st, K_PART_SCAN, 0.0);
         if (L.scan_threads == kScanThreads)
-            hipLaunchKernelGGL((k_part_scan_b<O, kScanThreads>), dim3(L.tasks.A),
-                               dim3(kScanThreads), 0, st, L.tasks, L.TP, L.chunk_span,
-                               ws.cnt_eq, ws.eqmv,
-                               ws.preL, ws.preR, ws.spL, ws.spR, ws.meta);
+            hipLaunchKernelGGL((k_part_scan_b<O, kScanThreads, LOOP>), dim3(L.grid),
+                               dim3(kScanThreads), 0, st, L.tasks, f, L.TP, L.chunk_span,
+                               ws.cnt_eq, ws.eqmv, ws.preL, ws.preR, ws.spL, ws.spR, ws.meta);
         else
-            hipLaunchKernelGGL((k_part_scan_b<O, kBlock>), dim3(L.tasks.A), dim3(kBlock), 0, st,
-                               L.tasks, L.TP, L.chunk_span, ws.cnt_eq, ws.eqmv, ws.preL,
-                               ws.preR, ws.spL,
-                               ws.spR, ws.meta);
-        break;
-    }
-    case 5: {  // swap of pass B
-        if (L.work == 0) break;
-        // pass B's pair count is known only on the device: no byte figure
-        ProfScope prof(st, K_PART_SWAP, 0.0);
-        hipLaunchKernelGGL((k_part_swap<O, PAIRS, 1>), dim3(L.work), dim3(kBlock), 0, st,
-                           L.tasks, L.TP, ws.preL, ws.preR, ws.spL, ws.spR, ws.eqmv, ws.meta);
+            hipLaunchKernelGGL((k_part_scan_b<O, kBlock, LOOP>), dim3(L.grid), dim3(kBlock), 0, st,
+                               L.tasks, f, L.TP, L.chunk_span, ws.cnt_eq, ws.eqmv, ws.preL,
+                               ws.preR, ws.spL, ws.spR, ws.meta);
         break;
     }
     default:
         return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+template <class O, bool PAIRS>
+static hipError_t partition_t(const PartitionLaunch &L, hipStream_t st) {
+    return L.loop ? partition_phase<O, PAIRS, true>(L, st) : partition_phase<O, PAIRS, false>(L, st);
 }
 
 hipError_t launch_partition_phase(int dt, bool pairs, const PartitionLaunch &L, hipStream_t st) {

@@ -1,6 +1,7 @@
 // qms_prof.cpp -- per-kernel-class event timing (see qms_prof.hpp).
 #include "qms_prof.hpp"
 
+#include <cstdio>
 #include <cstring>
 #include <vector>
 
@@ -15,9 +16,11 @@ const char *kNames[K_NUM_CLASSES] = {"tile_sort", "merge_split", "merge", "part_
 
 struct Rec {
     int cls;
+    int level;  // merge passes: the binary level the pass starts at
     double bytes;
     hipEvent_t a, b;
 };
+constexpr int kMaxProfLevels = 32;
 
 struct ProfState {
     bool on = false;
@@ -38,9 +41,10 @@ thread_local ProfState g_prof;
 
 bool prof_on() { return g_prof.on; }
 
-void prof_start(hipStream_t st, int cls) {
+void prof_start(hipStream_t st, int cls, int level) {
     Rec r;
     r.cls = cls;
+    r.level = level;
     r.bytes = 0;
     r.a = g_prof.take();
     r.b = g_prof.take();
@@ -74,9 +78,13 @@ int qms_profile_begin(void) {
 int qms_profile_end(qms_kernel_stat *out, int max_entries, int *n_out) {
     g_prof.on = false;
     qms_kernel_stat acc[K_NUM_CLASSES];
+    qms_kernel_stat lev[kMaxProfLevels];
     std::memset(acc, 0, sizeof(acc));
+    std::memset(lev, 0, sizeof(lev));
     for (int c = 0; c < K_NUM_CLASSES; ++c)
         std::strncpy(acc[c].name, kNames[c], sizeof(acc[c].name) - 1);
+    for (int l = 0; l < kMaxProfLevels; ++l)
+        std::snprintf(lev[l].name, sizeof(lev[l].name), "merge_level_%d", l);
     int rc = QMS_OK;
     for (const Rec &r : g_prof.recs) {
         if (!r.a || !r.b) continue;
@@ -90,12 +98,23 @@ int qms_profile_end(qms_kernel_stat *out, int max_entries, int *n_out) {
         acc[r.cls].launches += 1;
         acc[r.cls].total_ms += ms;
         acc[r.cls].bytes += r.bytes;
+        if (r.cls == K_MERGE && r.level >= 0 && r.level < kMaxProfLevels) {
+            lev[r.level].launches += 1;
+            lev[r.level].total_ms += ms;
+            lev[r.level].bytes += r.bytes;
+        }
     }
     g_prof.recs.clear();
     g_prof.used = 0;
     int n = 0;
     for (int c = 0; c < K_NUM_CLASSES && n < max_entries; ++c) {
         if (out) out[n] = acc[c];
+        ++n;
+    }
+    // then the swap-merge passes by the level they start at
+    for (int l = 0; l < kMaxProfLevels && n < max_entries; ++l) {
+        if (lev[l].launches == 0) continue;
+        if (out) out[n] = lev[l];
         ++n;
     }
     if (n_out) *n_out = n;

@@ -20,8 +20,9 @@ enum KernelClass : int {
 // True while the calling thread has profiling switched on.
 bool prof_on();
 // Record the start / end of one launch of class `cls` on stream `st`;
-// `bytes` (end only) are the launch's algorithmic bytes.
-void prof_start(hipStream_t st, int cls);
+// `bytes` (end only) are the launch's algorithmic bytes; `level` tags a
+// merge pass with the binary level it starts at (-1: none).
+void prof_start(hipStream_t st, int cls, int level);
 void prof_stop(hipStream_t st, int cls, double bytes);
 
 // RAII helper around one launch.
@@ -30,8 +31,9 @@ struct ProfScope {
     int cls;
     double bytes;
     bool on;
-    ProfScope(hipStream_t s, int c, double b) : st(s), cls(c), bytes(b), on(prof_on()) {
-        if (on) prof_start(st, cls);
+    ProfScope(hipStream_t s, int c, double b, int level = -1)
+        : st(s), cls(c), bytes(b), on(prof_on()) {
+        if (on) prof_start(st, cls, level);
     }
     ~ProfScope() {
         if (on) prof_stop(st, cls, bytes);

@@ -1,0 +1,697 @@
+// qms_rounds.hip -- the QuickMergesort loop of a batch with its round
+// control on the device: no host readback, no stream synchronisation, so a
+// whole batch can be enqueued at once (and captured in a HIP graph).
+//
+// The host-driven loop (qms_driver.cpp) reads three counters per segment
+// back after each partition count to size the rest of the round.  Here the
+// segment states (range, pivot rule, whether a range waits for the base
+// case) stay in device memory, and small single-workgroup plan kernels turn
+// them into the task tables of each phase: the partition table and its tile
+// and scan prefixes before the count, the exchange chunks after the scan,
+// the side choice (Fig. 2 sort(): the smaller side is mergesorted with the
+// larger side as swap space, the loop keeps the larger one) and the
+// Mergesort tasks with their tile and pass prefixes.  The phase kernels are
+// the same as the host-driven loop's; they read their work-item counts from
+// device memory and take their items in grid-stride order, so the host only
+// has to launch an upper bound of workgroups.
+//
+// The host enqueues a fixed schedule for the batch: R_main rounds with
+// HybridQuickMergesort's pivot rule (Sec. "Worst-Case Efficient
+// QuickMergeSort": median-of-3, or after a round whose smaller side held
+// less than 1/16 of its range the median of the medians of three), then
+// R_safe rounds in which every remaining range takes the median-of-medians
+// pivot, which leaves at most about 2/3 of it; R_safe is enough for any
+// range to fall to the base tile, so the schedule always finishes.  Rounds
+// in which nothing is left do nothing (every launch reads a zero count).
+// Per-round upper bounds for the launch sizes and the merge passes follow
+// from the same rule: a range shrinks by 1/16 in a round with a balanced
+// split, and after an unbalanced round the median-of-medians round removes
+// a third, so after r >= 1 rounds a range of n keys holds at most
+// n (15/16)^(r-1) keys.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "qms.h"
+#include "qms_device.hpp"
+#include "qms_host.hpp"
+#include "qms_internal.hpp"
+
+namespace qms {
+
+namespace {
+
+constexpr int kPlanThreads = 1024;
+// Segment flags.
+constexpr uint32_t DS_ACTIVE = 1;  // range above the base tile: partitioned this round
+constexpr uint32_t DS_MOM = 2;     // next pivot: median of the medians of three
+constexpr uint32_t DS_FINAL = 4;   // range of at most the base tile: base case next round
+
+// Workspace counters (dwork) of the device-sized launches of a round.
+enum WorkSlot : int {
+    W_ACTIVE = 0,  // segments in the partition table
+    W_TILES,       // partition tiles
+    W_SCAN,        // pass-A scan workgroups
+    W_MOM,         // median-of-medians histogram tiles
+    W_SPLIT_A,     // split waves, pass A
+    W_SWAP_A,      // exchange chunks, pass A
+    W_SPLIT_B,
+    W_SWAP_B,
+    W_SORT_TASKS,  // Mergesort tasks
+    W_BASE,        // base-case tiles
+    W_MERGE2,      // merge tiles of the 2-way first passes
+    W_STEP0,       // merge tiles of 4-way (or 2-way) step k: W_STEP0 + k
+    W_ERRORS = W_STEP0 + kMaxLevels,  // inconsistent counts, passes beyond the schedule
+    W_LEFT,        // segments still in the loop at the end of the schedule
+    W_COUNT_SLOTS
+};
+static_assert(W_COUNT_SLOTS <= 64, "work counters fit their array");
+
+struct DevSeg {
+    uint32_t *keys, *vals;  // segment base
+    uint32_t lo, hi;        // current range, relative to the base
+    uint32_t flags, pad;
+};
+
+// Round constants shared by the plan kernels.
+struct PlanArgs {
+    uint32_t nseg;       // segments of the group
+    uint32_t TP;         // partition tile
+    uint32_t scan_nth;   // threads of the pass-A scan
+    uint32_t span;       // exchange-chunk span
+    uint32_t T0;         // base tile: ranges of at most T0 keys go to the base case
+    uint32_t R0;         // Mergesort run width (X_THRESH)
+    uint32_t auto_r0;    // automatic X_THRESH: halve R0 when that makes L even
+    uint32_t four_way;   // 4-way passes (else 2-way)
+    uint32_t wide;       // 64-bit keys
+    uint32_t ew;         // 32-bit words per key
+    uint32_t force_mom;  // safety rounds: every range takes the worst-case pivot
+    uint32_t partitioned;  // this round ran a partition (else only finals are sorted)
+    uint32_t steps;      // merge steps enqueued this round
+    uint32_t first2;     // a launch for 2-way first passes (odd level counts) is enqueued
+    uint32_t cap_tiles, cap_chunks, cap_splits;
+};
+
+struct PlanPtrs {
+    DevSeg *seg;
+    uint32_t *aseg;                // active index -> segment
+    PartSeg *ptab, *mtab;
+    SortSeg *stab;
+    uint32_t *p_tiles, *p_scan, *p_mom, *p_wa, *p_ca, *p_wb, *p_cb, *p_base, *p_m2;
+    uint32_t *p_step;              // kMaxLevels arrays of (nseg + 2) entries
+    uint32_t *work;
+    uint64_t *meta;
+    const uint32_t *res;
+};
+
+__device__ __forceinline__ uint32_t ceil_log2_dev(uint64_t x) {
+    uint32_t l = 0;
+    while ((1ull << l) < x) ++l;
+    return l;
+}
+
+// Block-wide exclusive scan of one value per thread with a running carry
+// across the chunks of a loop; returns the prefix, adds the chunk's total to
+// *carry (uniform).  Every thread of the block calls it.
+__device__ __forceinline__ uint32_t scan_carry(uint32_t v, uint32_t *tmp, uint32_t *carry) {
+    uint32_t total;
+    const uint32_t pre = block_exclusive_scan(v, tmp, &total) + *carry;
+    *carry += total;
+    return pre;
+}
+
+// Fill the prefix entries from `from` to `upto` (inclusive) with `total`, so
+// that a lookup over an upper bound of segments never lands past the plan.
+__device__ __forceinline__ void pad_prefix(uint32_t *pre, uint32_t from, uint32_t upto,
+                                           uint32_t total) {
+    for (uint32_t i = from + threadIdx.x; i <= upto; i += blockDim.x) pre[i] = total;
+}
+
+// ---- init: segment states from the offsets ------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_rounds_init(DevSeg *seg, const uint64_t *offsets,
+                                                        uint32_t j0, uint32_t nseg,
+                                                        uint32_t *keys_base, uint32_t *vals_base,
+                                                        uint32_t ew, uint32_t T0,
+                                                        uint32_t *work) {
+    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < nseg; i += gridDim.x * kBlock) {
+        const uint64_t a = offsets[j0 + i], b = offsets[j0 + i + 1];
+        const uint64_t n = b - a;
+        DevSeg d;
+        d.keys = keys_base + ew * a;
+        d.vals = vals_base ? vals_base + a : nullptr;
+        d.lo = 0;
+        d.hi = (uint32_t)n;
+        d.flags = n > T0 ? DS_ACTIVE : (n > 1 ? DS_FINAL : 0u);
+        d.pad = 0;
+        seg[i] = d;
+    }
+    if (blockIdx.x == 0)
+        for (uint32_t i = threadIdx.x; i < W_COUNT_SLOTS; i += kBlock) work[i] = 0;
+}
+
+// ---- plan of the partition: table, tile / scan / median-of-medians prefixes ----------
+__global__ __launch_bounds__(kPlanThreads) void k_rounds_plan(PlanArgs A, PlanPtrs P) {
+    __shared__ uint32_t tmp[kPlanThreads / kWave + 1];
+    uint32_t c_act = 0, c_tiles = 0, c_scan = 0, c_mom = 0, c_mom_tiles = 0, c_chunk = 0;
+    for (uint32_t base = 0; base < A.nseg; base += kPlanThreads) {
+        const uint32_t j = base + threadIdx.x;
+        DevSeg d{};
+        bool act = false;
+        if (j < A.nseg) {
+            d = P.seg[j];
+            act = (d.flags & DS_ACTIVE) != 0;
+        }
+        const uint32_t s = act ? d.hi - d.lo : 0;
+        const uint32_t nt = act ? (s + A.TP - 1) / A.TP : 0;
+        const bool mom = act && (A.force_mom || (d.flags & DS_MOM));
+        const uint32_t ia = scan_carry(act ? 1u : 0u, tmp, &c_act);
+        const uint32_t toff = scan_carry(nt, tmp, &c_tiles);
+        const uint32_t soff = scan_carry(act ? scan_a_groups(nt, A.scan_nth) : 0u, tmp, &c_scan);
+        const uint32_t coff = scan_carry(act ? (s + 4095) / 4096 + 2 : 0u, tmp, &c_chunk);
+        const uint32_t im = scan_carry(mom ? 1u : 0u, tmp, &c_mom);
+        const uint32_t moff = scan_carry(mom ? mom_tiles_of(s) : 0u, tmp, &c_mom_tiles);
+        if (act) {
+            const PartSeg g{d.keys, d.vals, d.lo, s, toff, nt, coff, ia,
+                            mom ? kPivotMoM : 0u, im};
+            P.ptab[ia] = g;
+            P.aseg[ia] = j;
+            P.p_tiles[ia] = toff;
+            P.p_scan[ia] = soff;
+            if (mom) {
+                P.mtab[im] = g;
+                P.p_mom[im] = moff;
+                uint64_t *meta = P.meta + (uint64_t)ia * M_COUNT;
+                const uint64_t c = s / 3;
+                meta[M_MOM_RANK] = (c - 1) / 2;
+                meta[M_MOM_PREFIX] = 0;
+                meta[M_MOM_DONE] = 0;
+            }
+        }
+    }
+    // entries past the last segment hold the totals (lookups over the
+    // launch's upper bound of segments stop there)
+    pad_prefix(P.p_tiles, c_act, A.nseg + 1, c_tiles);
+    pad_prefix(P.p_scan, c_act, A.nseg + 1, c_scan);
+    pad_prefix(P.p_mom, c_mom, A.nseg + 1, c_mom_tiles);
+    if (threadIdx.x == 0) {
+        // a padding entry that no item reaches
+        const PartSeg none{nullptr, nullptr, 0, 0, 0, 0, 0, 0, 0, 0};
+        P.ptab[c_act] = none;
+        P.mtab[c_mom] = none;
+        const bool fits = c_tiles <= A.cap_tiles && c_chunk <= A.cap_chunks;
+        P.work[W_ACTIVE] = c_act;
+        P.work[W_TILES] = fits ? c_tiles : 0u;
+        P.work[W_SCAN] = fits ? c_scan : 0u;
+        P.work[W_MOM] = fits ? c_mom_tiles : 0u;
+        if (!fits) atomicAdd(&P.work[W_ERRORS], 1u);
+    }
+}
+
+// ---- plan of the exchanges: chunks of pass A, bounds of pass B ---------------------
+__global__ __launch_bounds__(kPlanThreads) void k_rounds_plan_swap(PlanArgs A, PlanPtrs P) {
+    __shared__ uint32_t tmp[kPlanThreads / kWave + 1];
+    const uint32_t act = P.work[W_ACTIVE];
+    const bool ok = P.work[W_TILES] != 0 || act == 0;
+    uint32_t c_wa = 0, c_ca = 0, c_wb = 0, c_cb = 0;
+    for (uint32_t base = 0; base < act; base += kPlanThreads) {
+        const uint32_t a = base + threadIdx.x;
+        uint32_t wa = 0, ca = 0, wb = 0, cb = 0;
+        if (a < act && ok) {
+            const uint64_t s = P.ptab[a].s;
+            const uint64_t c_lt = P.res[4 * a], c_eq = P.res[4 * a + 1], X = P.res[4 * a + 2];
+            if ((c_eq == 0 && c_lt == 0) || c_lt + c_eq > s) {
+                atomicAdd(&P.work[W_ERRORS], 1u);
+            } else {
+                const uint64_t nch = chunk_count(X, s, A.span);
+                ca = (uint32_t)nch;
+                wa = nch > 1 ? (uint32_t)(2 * (nch - 1)) : 0u;
+                // pass B pairs are at most min(#==, #>)
+                const uint64_t gt = s - c_lt - c_eq;
+                const uint64_t xb = c_eq < gt ? c_eq : gt;
+                if (xb > 0) {
+                    const uint64_t full = (xb + kRankChunk - 1) / kRankChunk;
+                    const uint64_t target = (s + A.span - 1) / A.span;
+                    const uint64_t nb = std::min<uint64_t>(xb, std::max(full, target));
+                    cb = (uint32_t)nb;
+                    wb = nb > 1 ? (uint32_t)(2 * (nb - 1)) : 0u;
+                }
+            }
+        }
+        const uint32_t owa = scan_carry(wa, tmp, &c_wa);
+        const uint32_t oca = scan_carry(ca, tmp, &c_ca);
+        const uint32_t owb = scan_carry(wb, tmp, &c_wb);
+        const uint32_t ocb = scan_carry(cb, tmp, &c_cb);
+        if (a < act) {
+            P.p_wa[a] = owa;
+            P.p_ca[a] = oca;
+            P.p_wb[a] = owb;
+            P.p_cb[a] = ocb;
+        }
+    }
+    pad_prefix(P.p_wa, act, A.nseg + 1, c_wa);
+    pad_prefix(P.p_ca, act, A.nseg + 1, c_ca);
+    pad_prefix(P.p_wb, act, A.nseg + 1, c_wb);
+    pad_prefix(P.p_cb, act, A.nseg + 1, c_cb);
+    if (threadIdx.x == 0) {
+        P.work[W_SPLIT_A] = c_wa;
+        P.work[W_SWAP_A] = c_ca;
+        P.work[W_SPLIT_B] = c_wb;
+        P.work[W_SWAP_B] = c_cb;
+    }
+}
+
+// ---- side choice and the Mergesort tasks -------------------------------------------
+// For every segment partitioned this round: the smaller of the < and > sides
+// is the data region D, m cells of the other side next to the pivot block are
+// its buffer; the loop keeps the larger side (Fig. 2 sort()).  A kept range
+// of at most T0 keys waits for the base case, which runs in the next round's
+// sort launches (it still holds this round's buffer).  Segments whose range
+// waited since the last round get their base-case task now.
+__global__ __launch_bounds__(kPlanThreads) void k_rounds_side(PlanArgs A, PlanPtrs P) {
+    __shared__ uint32_t tmp[kPlanThreads / kWave + 1];
+    // with no partition this round, or one whose plan did not fit, ranges in
+    // the loop stay as they are
+    const bool ok = A.partitioned && (P.work[W_TILES] != 0 || P.work[W_ACTIVE] == 0);
+    uint32_t c_task = 0, c_base = 0, c_split = 0, c_m2 = 0;
+    uint32_t c_step[kMaxLevels];
+    for (uint32_t k = 0; k < A.steps; ++k) c_step[k] = 0;
+    uint32_t bad = 0;
+    for (uint32_t base = 0; base < A.nseg; base += kPlanThreads) {
+        const uint32_t j = base + threadIdx.x;
+        SortSeg t{};
+        bool emit = false;
+        if (j < A.nseg) {
+            DevSeg d = P.seg[j];
+            const uint64_t ew = A.ew;
+            if ((d.flags & DS_ACTIVE) && ok) {
+                // the segment's slot in this round's partition table
+                const uint32_t s = d.hi - d.lo;
+                uint32_t a = 0;
+                {
+                    // aseg is sorted (the plan compacts in segment order)
+                    uint32_t lo = 0, hi = P.work[W_ACTIVE];
+                    while (lo < hi) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        if (P.aseg[mid] < j) lo = mid + 1;
+                        else hi = mid;
+                    }
+                    a = lo;
+                }
+                const uint32_t c_lt = P.res[4 * a], c_eq = P.res[4 * a + 1];
+                const uint32_t b1 = d.lo + c_lt, b2 = b1 + c_eq;
+                const uint32_t mL = c_lt, mR = d.hi - b2;
+                if ((c_eq == 0 && c_lt == 0) || (uint64_t)c_lt + c_eq > s) {
+                    // inconsistent counts (the exchange plan skipped this
+                    // range too): leave the segment, report it
+                    ++bad;
+                    d.flags = 0;
+                    P.seg[j] = d;
+                } else if (mL <= mR) {
+                    t.keys = d.keys + ew * d.lo;
+                    t.vals = d.vals ? d.vals + d.lo : nullptr;
+                    t.bkeys = d.keys + ew * b2;
+                    t.bvals = d.vals ? d.vals + b2 : nullptr;
+                    t.m = mL;
+                    d.lo = b2;
+                } else {
+                    t.keys = d.keys + ew * b2;
+                    t.vals = d.vals ? d.vals + b2 : nullptr;
+                    t.bkeys = d.keys + ew * (b1 - mR);
+                    t.bvals = d.vals ? d.vals + (b1 - mR) : nullptr;
+                    t.m = mR;
+                    d.hi = b1;
+                }
+                // run width and levels (as the host-driven loop sets them)
+                t.w0 = A.R0;
+                t.L = t.m > A.R0 ? ceil_log2_dev((t.m + A.R0 - 1) / A.R0) : 0;
+                if (A.auto_r0 && A.four_way && !A.wide && (t.L & 1u)) {
+                    t.w0 = A.R0 / 2;
+                    t.L = t.m > t.w0 ? ceil_log2_dev((t.m + t.w0 - 1) / t.w0) : 0;
+                }
+                t.two_way = A.four_way ? 0u : 1u;
+                emit = t.m > 1;
+                // HybridQuickMergesort, delta = 1/16: an unbalanced split makes
+                // the next pivot the median of the medians of three
+                const bool unbalanced = (uint64_t)(mL < mR ? mL : mR) * 16 < s;
+                const uint32_t s2 = d.hi - d.lo;
+                d.flags = s2 > A.T0 ? (DS_ACTIVE | (unbalanced ? DS_MOM : 0u))
+                                    : (s2 > 1 ? DS_FINAL : 0u);
+                P.seg[j] = d;
+            } else if (d.flags & DS_FINAL) {
+                // the base case in place on the whole remaining range
+                t.keys = d.keys + ew * d.lo;
+                t.vals = d.vals ? d.vals + d.lo : nullptr;
+                t.m = d.hi - d.lo;
+                t.L = 0;
+                t.w0 = A.T0;
+                emit = true;
+                d.flags = 0;
+                P.seg[j] = d;
+            }
+        }
+        const uint32_t steps_needed = !emit ? 0u
+                                      : t.two_way ? t.L
+                                                  : t.L / 2;  // 4-way passes after the first
+        bad += emit && steps_needed > A.steps;
+        bad += emit && !t.two_way && (t.L & 1u) && !A.first2;
+        const uint32_t idx = scan_carry(emit ? 1u : 0u, tmp, &c_task);
+        const uint32_t obase = scan_carry(emit ? (t.m + A.T0 - 1) / A.T0 : 0u, tmp, &c_base);
+        const uint32_t mt = emit ? (t.m + kMergeTile - 1) / kMergeTile : 0u;
+        const uint32_t osplit = scan_carry(mt, tmp, &c_split);
+        // the 2-way first pass of a 4-way Mergesort with an odd level count
+        const bool first2 = emit && !t.two_way && (t.L & 1u);
+        const uint32_t om2 = scan_carry(first2 ? mt : 0u, tmp, &c_m2);
+        uint32_t ostep[kMaxLevels];
+        for (uint32_t k = 0; k < A.steps; ++k)
+            ostep[k] = scan_carry(emit && k < steps_needed ? mt : 0u, tmp, &c_step[k]);
+        if (emit) {
+            t.split_off = osplit;
+            P.stab[idx] = t;
+            P.p_base[idx] = obase;
+            P.p_m2[idx] = om2;
+            for (uint32_t k = 0; k < A.steps; ++k) P.p_step[k * (A.nseg + 2) + idx] = ostep[k];
+        }
+    }
+    bad = block_sum(bad, tmp);
+    pad_prefix(P.p_base, c_task, A.nseg + 1, c_base);
+    pad_prefix(P.p_m2, c_task, A.nseg + 1, c_m2);
+    for (uint32_t k = 0; k < A.steps; ++k)
+        pad_prefix(P.p_step + k * (A.nseg + 2), c_task, A.nseg + 1, c_step[k]);
+    if (threadIdx.x == 0) {
+        SortSeg none{};
+        P.stab[c_task] = none;
+        const bool fits = c_split <= A.cap_splits;
+        P.work[W_SORT_TASKS] = c_task;
+        P.work[W_BASE] = fits ? c_base : 0u;
+        P.work[W_MERGE2] = fits ? c_m2 : 0u;
+        for (uint32_t k = 0; k < A.steps; ++k) P.work[W_STEP0 + k] = fits ? c_step[k] : 0u;
+        if (!fits || bad) atomicAdd(&P.work[W_ERRORS], 1u);
+        // the next round's plan starts from clean counts
+        P.work[W_TILES] = 0;
+        P.work[W_ACTIVE] = 0;
+    }
+}
+
+// ---- end of the schedule: segments still unsorted, plan errors -------------------
+// status[0] accumulates errors, status[1] unsorted segments, until read.
+__global__ __launch_bounds__(kBlock) void k_rounds_end(const DevSeg *seg, uint32_t nseg,
+                                                       const uint32_t *work, uint32_t *status) {
+    uint32_t left = 0;
+    for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < nseg; i += gridDim.x * kBlock)
+        left += seg[i].flags != 0;
+    if (left) atomicAdd(&status[1], left);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && work[W_ERRORS]) atomicAdd(&status[0], work[W_ERRORS]);
+}
+
+uint32_t ceil_log2_host(uint64_t x) {
+    uint32_t l = 0;
+    while ((1ull << l) < x) ++l;
+    return l;
+}
+
+}  // namespace
+
+// ---- host side ------------------------------------------------------------------
+size_t rounds_state_bytes(uint32_t segs) {
+    const size_t S = segs;
+    return S * sizeof(DevSeg) + S * 4 + 2 * (S + 1) * sizeof(PartSeg) +
+           (S + 1) * sizeof(SortSeg) + (9 + kMaxLevels) * (S + 2) * 4 + 64 * 4 + 16 * 256;
+}
+
+void carve_rounds_state(Workspace *ws, char *b, uint32_t segs) {
+    const size_t S = segs;
+    auto take = [&](size_t bytes) {
+        char *p = b;
+        b += (bytes + 255) & ~(size_t)255;
+        return p;
+    };
+    ws->r_seg = take(S * sizeof(DevSeg));
+    ws->r_aseg = (uint32_t *)take(S * 4);
+    ws->r_ptab = take((S + 1) * sizeof(PartSeg));
+    ws->r_mtab = take((S + 1) * sizeof(PartSeg));
+    ws->r_stab = take((S + 1) * sizeof(SortSeg));
+    ws->r_pre = (uint32_t *)take((9 + kMaxLevels) * (S + 2) * 4);
+    ws->r_work = (uint32_t *)take(64 * 4);
+    ws->r_status = (uint32_t *)take(4 * 4);
+}
+
+// The batch [j0, j0 + count) of the offsets, all segments below 2^32 keys.
+// h_len: the host's copy of their lengths (for the schedule's bounds).
+int sort_batch_device_rounds(int dt, bool pairs, char *keys_base, uint32_t *vals_base,
+                             const uint64_t *d_offsets, const uint64_t *h_off, uint32_t nseg,
+                             Workspace &ws, hipStream_t st) {
+    const Tuning tune = current_tuning();
+    const bool wide = dtype_wide(dt);
+    const uint32_t ew = wide ? 2 : 1;
+    const uint32_t T0 = (pairs || wide) ? kBaseTilePairs : kBaseTileKeys;
+    const bool auto_r0 = tune.base_tile == 0;
+    const bool four_way = tune.merge_ways == 4;
+    const uint32_t R0 = auto_r0 ? (wide ? (uint32_t)kMergeTile : T0) : std::min(T0, tune.base_tile);
+    // the smallest run width a Mergesort can take (automatic: half of R0)
+    const uint32_t R0_min = (auto_r0 && four_way && !wide) ? R0 / 2 : R0;
+    const uint32_t S = ws.caps.segs;
+    hipError_t e = hipSuccess;
+
+    for (uint32_t g0 = 0; g0 < nseg;) {
+        // a group: at most S segments and fewer than 2^32 keys
+        uint32_t g1 = g0;
+        uint64_t keys = 0, nmax = 0;
+        while (g1 < nseg && g1 - g0 < S) {
+            const uint64_t n = h_off[g1 + 1] - h_off[g1];
+            if (g1 > g0 && keys + n >= (1ull << 32)) break;
+            keys += n;
+            nmax = std::max(nmax, n);
+            ++g1;
+        }
+        const uint32_t G = g1 - g0;
+        std::vector<uint64_t> len(G);
+        for (uint32_t i = 0; i < G; ++i) len[i] = h_off[g0 + i + 1] - h_off[g0 + i];
+        // the schedule: main rounds, then worst-case-pivot rounds
+        const double levels = nmax > T0 ? std::log2((double)nmax / T0) : 0.0;
+        const uint32_t R_main = nmax > T0 ? (uint32_t)std::ceil(2.0 * levels) + 2 : 0;
+        const uint32_t R_safe =
+            nmax > T0 ? (uint32_t)std::ceil(std::log((double)nmax / T0) / std::log(1.0 / 0.675)) + 1
+                      : 0;
+        const uint32_t R = R_main + R_safe;
+        // range bound of a segment of n keys after r rounds
+        auto bound = [&](uint64_t n, uint32_t r) -> uint64_t {
+            if (r <= 1) return n;
+            const double b = (double)n * std::pow(15.0 / 16.0, (double)(r - 1)) + 72.0;
+            return std::min<uint64_t>(n, (uint64_t)b);
+        };
+        // partition tile: the first round's tiles fit the workspace
+        uint32_t TP = tune.partition_tile;
+        for (;;) {
+            uint64_t tot = 0;
+            for (uint64_t n : len)
+                if (n > T0) tot += (n + TP - 1) / TP;
+            if (tot <= ws.caps.tiles) break;
+            TP *= 2;
+        }
+        const uint32_t max_nt_all = (uint32_t)((nmax + TP - 1) / TP);
+        const uint32_t scan_nth = max_nt_all > 4 * kBlock ? kScanThreads : kBlock;
+
+        PlanArgs A{};
+        A.nseg = G;
+        A.TP = TP;
+        A.scan_nth = scan_nth;
+        A.span = tune.chunk_span;
+        A.T0 = T0;
+        A.R0 = R0;
+        A.auto_r0 = auto_r0;
+        A.four_way = four_way;
+        A.wide = wide;
+        A.ew = ew;
+        A.cap_tiles = (uint32_t)std::min<uint64_t>(ws.caps.tiles, 0xffffffffu);
+        A.cap_chunks = (uint32_t)std::min<uint64_t>(ws.caps.chunks, 0xffffffffu);
+        A.cap_splits = (uint32_t)std::min<uint64_t>(ws.caps.splits, 0xffffffffu);
+        PlanPtrs P{};
+        P.seg = (DevSeg *)ws.r_seg;
+        P.aseg = ws.r_aseg;
+        P.ptab = (PartSeg *)ws.r_ptab;
+        P.mtab = (PartSeg *)ws.r_mtab;
+        P.stab = (SortSeg *)ws.r_stab;
+        const size_t PS = (size_t)G + 2;
+        uint32_t *pre = ws.r_pre;
+        P.p_tiles = pre;
+        P.p_scan = pre + PS;
+        P.p_mom = pre + 2 * PS;
+        P.p_wa = pre + 3 * PS;
+        P.p_ca = pre + 4 * PS;
+        P.p_wb = pre + 5 * PS;
+        P.p_cb = pre + 6 * PS;
+        P.p_base = pre + 7 * PS;
+        P.p_m2 = pre + 8 * PS;
+        P.p_step = pre + 9 * PS;
+        P.work = ws.r_work;
+        P.meta = ws.meta;
+        P.res = ws.res;
+
+        hipLaunchKernelGGL(k_rounds_init, dim3(std::min<uint32_t>((G + kBlock - 1) / kBlock, 1024)),
+                           dim3(kBlock), 0, st, P.seg, d_offsets, g0, G, (uint32_t *)keys_base,
+                           vals_base, ew, T0, P.work);
+        if ((e = hipGetLastError()) != hipSuccess) return hip_error(e, "round state init");
+
+        // Launch sizes.  Each device-sized phase runs one workgroup per item
+        // for as many items as the host expects (a median-of-3 round leaves
+        // a range about 11/16 of its size on average; the estimate takes
+        // 3/4 and a quarter more work), then a looping launch of kOverflow
+        // workgroups for any items beyond the estimate.
+        constexpr uint32_t kOverflow = 256;
+        constexpr double kShrink = 0.75, kSlack = 1.25;
+        auto est = [](double x) -> uint32_t {
+            return (uint32_t)std::min<double>(std::ceil(x * kSlack) + 16.0, 1u << 30);
+        };
+        auto part_ref = [&](const uint32_t *prefix, uint32_t work_slot, const PartSeg *tab) {
+            TaskRef<PartSeg> r{};
+            r.tab = tab;
+            r.pre = prefix;
+            r.A = G + 1;  // an upper bound (>= 2: never the by-value form)
+            r.dyn = P.work + work_slot;
+            return r;
+        };
+        auto sort_ref = [&](const uint32_t *prefix, uint32_t work_slot) {
+            TaskRef<SortSeg> r{};
+            r.tab = P.stab;
+            r.pre = prefix;
+            r.A = G + 1;
+            r.dyn = P.work + work_slot;
+            return r;
+        };
+
+        std::vector<double> expect(G);  // expected range of each segment
+        for (uint32_t i = 0; i < G; ++i) expect[i] = (double)len[i];
+        for (uint32_t r = 0; r <= R; ++r) {
+            // estimates of this round's work, and the bound on the largest
+            // range (for the number of merge steps, which must not fall short)
+            double tiles_e = 0, scan_e = 0, chunks_e = 0, active_e = 0, mom_e = 0, merge_e = 0;
+            double base_e = 0;
+            uint64_t bmax = 0, tiles_b = 0;
+            for (uint32_t i = 0; i < G; ++i) {
+                const uint64_t n = len[i];
+                if (n <= 1) continue;
+                const double x = expect[i];
+                const double prev = r == 0 ? 0.0 : expect[i] / kShrink;
+                const uint64_t b = bound(n, r);
+                if (r < R && b > T0) {
+                    bmax = std::max(bmax, b);
+                    tiles_b += (b + TP - 1) / TP;
+                }
+                if (x > T0 && r < R) {
+                    const double nt = std::ceil(x / TP);
+                    tiles_e += nt;
+                    scan_e += scan_a_groups((uint32_t)nt, scan_nth);
+                    chunks_e += std::ceil(x / std::max<uint32_t>(tune.chunk_span, 4096)) + 1;
+                    active_e += 1;
+                    mom_e += 0.1 * mom_tiles((uint64_t)x);
+                    merge_e += std::ceil(0.35 * x / kMergeTile);
+                    base_e += std::ceil(0.35 * x / T0);
+                }
+                // the ranges that reach the base tile: base case next round
+                if ((r == 0 && x <= T0) || (r > 0 && x <= T0 && prev > T0)) base_e += 1;
+                expect[i] = x * kShrink;
+            }
+            const uint32_t Lmax = bmax / 2 > R0_min ? ceil_log2_host((bmax / 2 + R0_min - 1) / R0_min) : 0;
+            const uint32_t steps = std::min<uint32_t>(four_way ? Lmax / 2 : Lmax, kMaxLevels);
+            A.force_mom = r >= R_main ? 1u : 0u;
+            A.steps = steps;
+            A.first2 = four_way && (!auto_r0 || wide) && Lmax > 0;
+            A.partitioned = r < R && bmax > 0;
+            if (A.partitioned) {
+                hipLaunchKernelGGL(k_rounds_plan, dim3(1), dim3(kPlanThreads), 0, st, A, P);
+                // pivots of the flagged ranges
+                e = launch_mom_pivot(dt, part_ref(P.p_mom, W_MOM, P.mtab), est(mom_e), kOverflow,
+                                     false, ws, st);
+                if (e != hipSuccess) return hip_error(e, "median-of-medians pivot");
+                PartitionLaunch L{};
+                L.TP = TP;
+                L.chunk_span = tune.chunk_span;
+                L.scan_threads = scan_nth;
+                // per-64 counts while the round's tiles (at most tiles_b) fit
+                L.groups = tiles_b * (TP / kWave) <= ws.caps.groups;
+                L.keys_total = 0;
+                L.bytes = 0;
+                L.ws = &ws;
+                L.work = 0;
+                // the phase with an estimate of `items` workgroups, then the
+                // overflow from where the estimate ends (items per workgroup:
+                // one, or kWaves for the splits)
+                auto phase = [&](int ph, TaskRef<PartSeg> tr, uint32_t items, uint32_t per,
+                                 const char *what) -> int {
+                    L.phase = ph;
+                    L.tasks = tr;
+                    L.grid = (items + per - 1) / per;
+                    L.first = 0;
+                    L.loop = false;
+                    hipError_t e2 = launch_partition_phase(dt, pairs, L, st);
+                    if (e2 == hipSuccess) {
+                        L.first = L.grid * per;
+                        L.grid = kOverflow;
+                        L.loop = true;
+                        e2 = launch_partition_phase(dt, pairs, L, st);
+                    }
+                    return e2 == hipSuccess ? QMS_OK : hip_error(e2, what);
+                };
+                int rc;
+                if ((rc = phase(0, part_ref(P.p_tiles, W_TILES, P.ptab), est(tiles_e), 1,
+                                "partition count")) != QMS_OK)
+                    return rc;
+                if ((rc = phase(6, part_ref(P.p_scan, W_SCAN, P.ptab), est(scan_e), 1,
+                                "partition scan")) != QMS_OK)
+                    return rc;
+                hipLaunchKernelGGL(k_rounds_plan_swap, dim3(1), dim3(kPlanThreads), 0, st, A, P);
+                if ((rc = phase(1, part_ref(P.p_wa, W_SPLIT_A, P.ptab), est(2 * chunks_e), kWaves,
+                                "split A")) != QMS_OK)
+                    return rc;
+                if ((rc = phase(2, part_ref(P.p_ca, W_SWAP_A, P.ptab), est(chunks_e), 1,
+                                "swap A")) != QMS_OK)
+                    return rc;
+                if ((rc = phase(4, part_ref(nullptr, W_ACTIVE, P.ptab), est(active_e), 1,
+                                "scan B")) != QMS_OK)
+                    return rc;
+                if ((rc = phase(3, part_ref(P.p_wb, W_SPLIT_B, P.ptab), 16, kWaves, "split B")) !=
+                    QMS_OK)
+                    return rc;
+                if ((rc = phase(5, part_ref(P.p_cb, W_SWAP_B, P.ptab), 16, 1, "swap B")) != QMS_OK)
+                    return rc;
+            }
+            // side choice (or, after the last round, the finals alone)
+            hipLaunchKernelGGL(k_rounds_side, dim3(1), dim3(kPlanThreads), 0, st, A, P);
+            e = launch_tile_sort(dt, pairs, sort_ref(P.p_base, W_BASE), est(base_e), kOverflow, 0.0,
+                                 ws, st);
+            if (e != hipSuccess) return hip_error(e, "base case");
+            if (steps == 0 && !A.first2) continue;
+            MergeLaunch M;
+            M.overflow = kOverflow;
+            M.tiles = est(merge_e);
+            // the 2-way first passes of odd level counts (never with the
+            // automatic run width, which makes every level count even)
+            if (A.first2) {
+                M.tasks = sort_ref(P.p_m2, W_MERGE2);
+                M.level = 0;
+                M.step = 0;
+                M.four_way = false;
+                if ((e = launch_merge_pass(dt, pairs, M, ws, st)) != hipSuccess)
+                    return hip_error(e, "merge pass");
+            }
+            for (uint32_t k = 0; k < steps; ++k) {
+                M.tasks = sort_ref(P.p_step + (size_t)k * PS, W_STEP0 + k);
+                M.level = k;
+                M.step = 1;
+                M.four_way = four_way;
+                if ((e = launch_merge_pass(dt, pairs, M, ws, st)) != hipSuccess)
+                    return hip_error(e, "merge pass");
+            }
+        }
+        hipLaunchKernelGGL(k_rounds_end, dim3(std::min<uint32_t>((G + kBlock - 1) / kBlock, 1024)),
+                           dim3(kBlock), 0, st, (const DevSeg *)P.seg, G,
+                           (const uint32_t *)P.work, ws.r_status);
+        if ((e = hipGetLastError()) != hipSuccess) return hip_error(e, "round schedule end");
+        g0 = g1;
+    }
+    return QMS_OK;
+}
+
+}  // namespace qms

@@ -18,44 +18,74 @@
 //
 // All segments that need the pivot in a round are served by the same
 // launches (task tables); each has a 256-bin histogram in the workspace.
+// The last histogram workgroup of a segment in a pass (a per-segment count
+// of finished workgroups) picks the bucket, so a pass is one launch.
 #include "qms_device.hpp"
 #include "qms_internal.hpp"
 #include "qms_prof.hpp"
 
 namespace qms {
 
-// Triples per histogram workgroup (kBlock threads x kMomPerThread).
-constexpr int kMomPerThread = 32;
-constexpr uint32_t kMomTile = (uint32_t)kBlock * kMomPerThread;
 
 __device__ __forceinline__ const PartSeg &mom_seg(const TaskRef<PartSeg> &r, uint32_t a) {
     return r.A == 1 ? r.one : r.tab[a];
 }
 
-// One workgroup per segment: clear the histogram, set rank and prefix.
-__global__ __launch_bounds__(kBlock) void k_mom_init(TaskRef<PartSeg> tasks, uint64_t *meta_all,
-                                                     uint32_t *hist_all) {
-    const PartSeg g = mom_seg(tasks, blockIdx.x);
+// Clear the histogram, set rank and prefix, no histogram workgroup done
+// (kBlock threads; also called by the device-side round plan).
+__device__ __forceinline__ void mom_init_segment(const PartSeg &g, uint64_t *meta_all,
+                                                 uint32_t *hist_all) {
     stg(hist_all + (uint64_t)g.pad * 256 + threadIdx.x, 0u);
     if (threadIdx.x == 0) {
         uint64_t *meta = meta_all + (uint64_t)g.slot * M_COUNT;
         const uint64_t c = g.s / 3;
         meta[M_MOM_RANK] = (c - 1) / 2;
         meta[M_MOM_PREFIX] = 0;
+        meta[M_MOM_DONE] = 0;
     }
+}
+// One workgroup per segment.
+__global__ __launch_bounds__(kBlock) void k_mom_init(TaskRef<PartSeg> tasks, uint64_t *meta_all,
+                                                     uint32_t *hist_all) {
+    mom_init_segment(mom_seg(tasks, blockIdx.x), meta_all, hist_all);
+}
+
+// The bucket that holds rank r: the prefix grows by its digit and r becomes
+// the rank inside it; the histogram is cleared for the next pass.  After the
+// last pass the prefix is the pivot.  The histogram was filled by atomics
+// of other workgroups: it is read and cleared with agent-scope atomics.
+__device__ __forceinline__ void mom_pick_segment(const PartSeg &g, uint32_t pass, uint32_t last,
+                                                 uint64_t *meta_all, uint32_t *hist_all,
+                                                 uint32_t *tmp) {
+    uint64_t *meta = meta_all + (uint64_t)g.slot * M_COUNT;
+    uint32_t *hist = hist_all + (uint64_t)g.pad * 256;
+    const uint32_t b = threadIdx.x;
+    const uint32_t v = __hip_atomic_exchange(hist + b, 0u, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t r = (uint32_t)meta[M_MOM_RANK];
+    const uint64_t prefix = meta[M_MOM_PREFIX];
+    uint32_t total;
+    const uint32_t below = block_exclusive_scan(v, tmp, &total);  // ends with a barrier
+    if (below <= r && r < below + v) {
+        const uint64_t np = (prefix << 8) | b;
+        meta[M_MOM_RANK] = r - below;
+        meta[M_MOM_PREFIX] = np;
+        if (pass == last) meta[M_PIVOT] = np;
+    }
+    if (b == 0) meta[M_MOM_DONE] = 0;
 }
 
 // Histogram of digit `pass` (the pass-th byte from the top) of the medians
-// whose higher digits equal the prefix chosen so far.
+// whose higher digits equal the prefix chosen so far; the segment's last
+// workgroup to finish picks the digit.
 template <class O>
-__global__ __launch_bounds__(kBlock) void k_mom_hist(TaskRef<PartSeg> tasks, uint32_t pass,
-                                                     const uint64_t *meta_all,
-                                                     uint32_t *hist_all) {
+__device__ __forceinline__ void mom_hist_item(TaskRef<PartSeg> tasks, uint32_t item,
+                                              uint32_t pass, uint32_t last, uint64_t *meta_all,
+                                              uint32_t *hist_all, uint32_t *h, uint32_t *tmp) {
     using K = typename O::K;
     constexpr uint32_t kBits = 8 * sizeof(K);
-    __shared__ uint32_t h[256];
     uint32_t t, a;
-    const PartSeg g = task_of(tasks, blockIdx.x, &t, &a);
+    const PartSeg g = task_of(tasks, item, &t, &a);
     const K *keys = (const K *)g.keys + g.lo;
     const uint64_t c = g.s / 3;
     const K prefix = (K)meta_all[(uint64_t)g.slot * M_COUNT + M_MOM_PREFIX];
@@ -84,58 +114,73 @@ __global__ __launch_bounds__(kBlock) void k_mom_hist(TaskRef<PartSeg> tasks, uin
     __syncthreads();
     const uint32_t v = h[threadIdx.x];
     if (v != 0) atomicAdd(hist_all + (uint64_t)g.pad * 256 + threadIdx.x, v);
+    // every thread's histogram atomics are done before the count goes up
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint64_t done = atomicAdd(
+            (unsigned long long *)(meta_all + (uint64_t)g.slot * M_COUNT + M_MOM_DONE), 1ull);
+        h[0] = done + 1 == mom_tiles_of(g.s) ? 1u : 0u;
+    }
+    __syncthreads();
+    const bool is_last = h[0] != 0;
+    __syncthreads();  // h is reused by the next item
+    if (is_last) {
+        __threadfence();
+        mom_pick_segment(g, pass, last, meta_all, hist_all, tmp);
+    }
 }
-
-// One workgroup per segment: the bucket that holds rank r; the prefix grows
-// by its digit and r becomes the rank inside it.  The histogram is cleared
-// for the next pass.  After the last pass the prefix is the pivot.
-__global__ __launch_bounds__(kBlock) void k_mom_pick(TaskRef<PartSeg> tasks, uint32_t pass,
-                                                     uint32_t last, uint64_t *meta_all,
-                                                     uint32_t *hist_all) {
-    __shared__ uint32_t tmp[kWaves + 1];
-    const PartSeg g = mom_seg(tasks, blockIdx.x);
-    uint64_t *meta = meta_all + (uint64_t)g.slot * M_COUNT;
-    uint32_t *hist = hist_all + (uint64_t)g.pad * 256;
-    const uint32_t b = threadIdx.x;
-    const uint32_t v = hist[b];
-    const uint32_t r = (uint32_t)meta[M_MOM_RANK];
-    const uint64_t prefix = meta[M_MOM_PREFIX];
-    uint32_t total;
-    const uint32_t below = block_exclusive_scan(v, tmp, &total);
-    stg(hist + b, 0u);
-    if (below <= r && r < below + v) {
-        const uint64_t np = (prefix << 8) | b;
-        meta[M_MOM_RANK] = r - below;
-        meta[M_MOM_PREFIX] = np;
-        if (pass == last) meta[M_PIVOT] = np;
+template <class O, bool LOOP>
+__global__ __launch_bounds__(kBlock) void k_mom_hist(TaskRef<PartSeg> tasks, uint32_t first,
+                                                     uint32_t pass, uint32_t last,
+                                                     uint64_t *meta_all, uint32_t *hist_all) {
+    __shared__ uint32_t h_mem[256];
+    __shared__ uint32_t tmp_mem[kWaves + 1];
+    uint32_t *h = h_mem, *tmp = tmp_mem;
+    const uint32_t W = work_total(tasks, first + gridDim.x);
+    if constexpr (!LOOP) {
+        const uint32_t item = first + blockIdx.x;
+        if (item < W) mom_hist_item<O>(tasks, item, pass, last, meta_all, hist_all, h, tmp);
+    } else {
+        for (uint32_t item = first + blockIdx.x; item < W; item += gridDim.x) {
+            mom_hist_item<O>(tasks, item, pass, last, meta_all, hist_all, h, tmp);
+            __syncthreads();  // the LDS is reused by the next item
+        }
     }
 }
 
+// init: one workgroup per segment, unless `init` is false (the round plan
+// initialised them).  tiles: the histogram workgroups of a host-sized
+// launch; with tasks.dyn the estimate of a device-sized one, followed in
+// each pass by an overflow launch of `overflow` looping workgroups.
 template <class O>
-static hipError_t mom_t(const TaskRef<PartSeg> &tasks, uint32_t tiles, const Workspace &ws,
-                        hipStream_t st) {
+static hipError_t mom_t(const TaskRef<PartSeg> &tasks, uint32_t tiles, uint32_t overflow,
+                        bool init, const Workspace &ws, hipStream_t st) {
     ProfScope prof(st, K_PART_SCAN, 0.0);
     constexpr uint32_t kPasses = sizeof(typename O::K);  // 8-bit digits
-    hipLaunchKernelGGL(k_mom_init, dim3(tasks.A), dim3(kBlock), 0, st, tasks, ws.meta, ws.hist);
+    if (init)
+        hipLaunchKernelGGL(k_mom_init, dim3(tasks.A), dim3(kBlock), 0, st, tasks, ws.meta,
+                           ws.hist);
     for (uint32_t pass = 0; pass < kPasses; ++pass) {
-        hipLaunchKernelGGL((k_mom_hist<O>), dim3(tiles), dim3(kBlock), 0, st, tasks, pass,
-                           (const uint64_t *)ws.meta, ws.hist);
-        hipLaunchKernelGGL(k_mom_pick, dim3(tasks.A), dim3(kBlock), 0, st, tasks, pass,
-                           kPasses - 1, ws.meta, ws.hist);
+        hipLaunchKernelGGL((k_mom_hist<O, false>), dim3(tiles), dim3(kBlock), 0, st, tasks, 0u,
+                           pass, kPasses - 1, ws.meta, ws.hist);
+        if (overflow)
+            hipLaunchKernelGGL((k_mom_hist<O, true>), dim3(overflow), dim3(kBlock), 0, st, tasks,
+                               tiles, pass, kPasses - 1, ws.meta, ws.hist);
     }
     return hipGetLastError();
 }
 
-uint32_t mom_tiles(uint64_t s) { return (uint32_t)((s / 3 + kMomTile - 1) / kMomTile); }
+uint32_t mom_tiles(uint64_t s) { return mom_tiles_of(s); }
 
 hipError_t launch_mom_pivot(int dt, const TaskRef<PartSeg> &tasks, uint32_t tiles,
-                            const Workspace &ws, hipStream_t st) {
+                            uint32_t overflow, bool init, const Workspace &ws, hipStream_t st) {
     if (tasks.A == 0 || tiles == 0) return hipSuccess;
     switch (dt) {
-    case 0: return mom_t<OrdU32>(tasks, tiles, ws, st);
-    case 1: return mom_t<OrdF32>(tasks, tiles, ws, st);
-    case 2: return mom_t<OrdU64>(tasks, tiles, ws, st);
-    case 3: return mom_t<OrdF64>(tasks, tiles, ws, st);
+    case 0: return mom_t<OrdU32>(tasks, tiles, overflow, init, ws, st);
+    case 1: return mom_t<OrdF32>(tasks, tiles, overflow, init, ws, st);
+    case 2: return mom_t<OrdU64>(tasks, tiles, overflow, init, ws, st);
+    case 3: return mom_t<OrdF64>(tasks, tiles, overflow, init, ws, st);
     default: return hipErrorInvalidValue;
     }
 }

@@ -37,7 +37,7 @@ EXPORTS = (
     "qms_server_get_stats", "qms_server_destroy",
     "qms_last_error", "qms_release_workspaces", "qms_last_schedule",
     "qms_get_tiles", "qms_profile_begin", "qms_profile_end", "qms_mom_pivot",
-    "qms_set_tuning", "qms_get_tuning", "qms_sort_noalloc",
+    "qms_set_tuning", "qms_get_tuning", "qms_sort_noalloc", "qms_batch_check",
 )
 
 QMS_SCHEDULE_WORDS = 6
@@ -98,6 +98,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.qms_sort_pairs.restype = i32
     lib.qms_sort_batch.argtypes = [vp, vp, vp, vp, u32, i32, vp]
     lib.qms_sort_batch.restype = i32
+    lib.qms_batch_check.argtypes = [vp]
+    lib.qms_batch_check.restype = i32
     lib.qms_server_create.argtypes = [ctypes.POINTER(ServerConfig), ctypes.POINTER(vp)]
     lib.qms_server_create.restype = i32
     lib.qms_server_submit.argtypes = [vp, vp, u64, i32, vp, u64p]
@@ -225,6 +227,12 @@ def qms_sort_batch(keys, offsets, vals=None, host_offsets=None, stream=None,
            "qms_sort_batch")
 
 
+def qms_batch_check(stream=None) -> None:
+    """Wait for the stream and raise if a batch sorted on it left segments
+    unsorted (a check of the library's device-side schedule)."""
+    _check(load_library().qms_batch_check(_stream_handle(stream)), "qms_batch_check")
+
+
 def qms_last_schedule(max_rounds: int = 4096):
     """Per-round log of the last single-array sort on this thread: a list of
     (s, n_less, n_equal, n_greater, merge_levels, pivot_rule) with
@@ -279,9 +287,9 @@ def qms_profile_begin() -> None:
 def qms_profile_end() -> dict:
     """{class: {"launches", "total_ms", "bytes"}} for the sorts since begin."""
     lib = load_library()
-    buf = (KernelStat * 16)()
+    buf = (KernelStat * 48)()
     n = ctypes.c_int()
-    _check(lib.qms_profile_end(buf, 16, ctypes.byref(n)), "qms_profile_end")
+    _check(lib.qms_profile_end(buf, 48, ctypes.byref(n)), "qms_profile_end")
     return {buf[i].name.decode(): {"launches": buf[i].launches, "total_ms": buf[i].total_ms,
                                    "bytes": buf[i].bytes} for i in range(n.value)}
 
