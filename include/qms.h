@@ -16,9 +16,11 @@
  *   - Keys are 32-bit words: QMS_U32 compares them as unsigned integers;
  *     QMS_F32 compares IEEE-754 binary32 values by the IEEE total order
  *     (negative NaNs < -inf < ... < -0 < +0 < ... < +inf < positive NaNs).
- *     qms_sort and qms_sort_batch also take 64-bit keys (the wide records of
+ *     Every sorting entry point also takes 64-bit keys (the wide records of
  *     the paper's Experiments section): QMS_U64 unsigned, QMS_F64 IEEE-754
- *     binary64 by the same total order; 8-byte aligned, without payloads.
+ *     binary64 by the same total order; 8-byte aligned, with or without
+ *     payloads (with payloads their merge passes are 2-way and their base
+ *     tile is 2048 keys).
  *   - Payloads (qms_sort_pairs, qms_sort_batch with vals) are uint32 words in
  *     a separate array (structure of arrays); every move of a key moves its
  *     payload.  The sort is not stable: payload order among equal keys is
@@ -81,7 +83,7 @@ int qms_sort(void *d_keys, uint64_t n, int dt, hipStream_t stream);
  * qms_sort_pairs -- as qms_sort, carrying a uint32 payload per key (the
  * QuickXsort section's element moves apply to whole elements).
  *   d_vals  device pointer to n uint32 payloads, permuted with the keys.
- *   dt      QMS_U32 or QMS_F32 (QMS_ERR_UNSUPPORTED for 64-bit keys).
+ *   dt      any key type (QMS_U32, QMS_F32, QMS_U64, QMS_F64).
  * Result: keys sorted; the multiset of (key, payload) pairs preserved.
  */
 int qms_sort_pairs(void *d_keys, uint32_t *d_vals, uint64_t n, int dt,
@@ -104,8 +106,8 @@ int qms_sort_pairs(void *d_keys, uint32_t *d_vals, uint64_t n, int dt,
  * segment and guarantees that every segment is sorted.  The loop runs down
  * to the base tile (final_tile is not used).
  *   d_keys       device keys of all segments.
- *   d_vals       device payloads, or NULL for keys only (64-bit keys:
- *                NULL only).
+ *   d_vals       device uint32 payloads (one per key), or NULL for keys
+ *                only.
  *   d_offsets    DEVICE array of num_segments + 1 uint64 offsets, non-
  *                decreasing, offsets[0] = 0 (empty segments allowed).
  *   h_offsets    HOST copy of the same offsets; NULL makes the library read

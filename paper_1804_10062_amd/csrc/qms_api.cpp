@@ -301,8 +301,6 @@ DeviceScope::~DeviceScope() {
 static int sort_entry(void *d_keys, uint32_t *d_vals, uint64_t n, int dt, hipStream_t stream,
                       bool pairs) {
     if (!dtype_known(dt)) return set_error(QMS_ERR_UNSUPPORTED, "unknown dtype");
-    if (pairs && dtype_wide(dt))
-        return set_error(QMS_ERR_UNSUPPORTED, "payloads are supported for 32-bit keys only");
     if (n <= 1) return QMS_OK;
     if (d_keys == nullptr || (pairs && d_vals == nullptr))
         return set_error(QMS_ERR_INVALID, "NULL pointer with n > 1");

@@ -89,6 +89,39 @@ struct TileElem<false, uint64_t> {
     __device__ static uint32_t index(E) { return 0; }
 };
 
+// 64-bit keys with payloads: the element is the order-mapped key and the
+// element's index in the tile, compared as one (key, index) value, so that no
+// two elements tie (the exchanges below keep each element exactly once) and
+// the payload is gathered through the index at the end.  Complementing both
+// parts reverses the order.
+struct WideIdx {
+    uint64_t k;
+    uint32_t i, pad;
+};
+__device__ __forceinline__ bool operator<(const WideIdx &a, const WideIdx &b) {
+    return a.k < b.k || (a.k == b.k && a.i < b.i);
+}
+__device__ __forceinline__ WideIdx operator^(const WideIdx &a, const WideIdx &b) {
+    return WideIdx{a.k ^ b.k, a.i ^ b.i, 0};
+}
+__device__ __forceinline__ WideIdx &operator^=(WideIdx &a, const WideIdx &b) {
+    a = a ^ b;
+    return a;
+}
+template <>
+struct TileElem<true, uint64_t> {
+    using E = WideIdx;
+    static constexpr int ITEMS = kBaseTileWidePairs / kSortThreads;  // 4
+    static constexpr uint32_t IBITS = 11;
+    static constexpr E FLIP = WideIdx{~0ull, (1u << IBITS) - 1, 0};
+    static constexpr bool F64 = false;
+    __device__ static E make(uint64_t k, uint32_t i) { return WideIdx{k, i, 0}; }
+    __device__ static E pad(uint32_t i) { return WideIdx{~0ull, i, 0}; }
+    __device__ static uint64_t key(E x) { return x.k; }
+    __device__ static uint32_t index(E x) { return x.i; }
+};
+static_assert(kBaseTileWidePairs <= (1u << TileElem<true, uint64_t>::IBITS), "tile index bits");
+
 template <class E>
 __device__ __forceinline__ void cmpx(E &a, E &b, bool asc) {
     const E lo = a < b ? a : b;
@@ -127,6 +160,16 @@ __device__ __forceinline__ uint32_t keep_side(uint32_t x, uint32_t y, bool, uint
 __device__ __forceinline__ uint64_t keep_side(uint64_t x, uint64_t y, bool keep_min, uint64_t) {
     // x stays when it is on the kept side of y (ties keep either: equal values)
     return (x < y) == keep_min ? x : y;
+}
+__device__ __forceinline__ WideIdx keep_side(WideIdx x, WideIdx y, bool keep_min, WideIdx) {
+    return (x < y) == keep_min ? x : y;  // elements never tie
+}
+
+// The partner lane's element (xor of the lane index).
+__device__ __forceinline__ uint32_t shfl_xor_elem(uint32_t v, int m) { return __shfl_xor(v, m, kWave); }
+__device__ __forceinline__ uint64_t shfl_xor_elem(uint64_t v, int m) { return __shfl_xor(v, m, kWave); }
+__device__ __forceinline__ WideIdx shfl_xor_elem(WideIdx v, int m) {
+    return WideIdx{__shfl_xor(v.k, m, kWave), (uint32_t)__shfl_xor((int)v.i, m, kWave), 0};
 }
 
 // Cross-lane compare-exchange steps of 32-bit elements without the LDS pipe
@@ -359,9 +402,9 @@ __device__ __forceinline__ void tile_sort_block(typename O::K *sk, uint32_t *sv,
     //    compare-exchange below is an ascending one; the representation
     //    changes only between stages.  At the last stage every block ascends
     //    and the keys are plain again: the tile holds T / run sorted runs.
-    E cur_mask = E(0);
+    E cur_mask = E{};
     for (uint32_t k = ITEMS; k <= run; k <<= 1) {
-        const E mask = (k == run || (base & k) == 0) ? E(0) : TE::FLIP;
+        const E mask = (k == run || (base & k) == 0) ? E{} : TE::FLIP;
         const E flip = mask ^ cur_mask;
         cur_mask = mask;
 #pragma unroll
@@ -377,7 +420,7 @@ __device__ __forceinline__ void tile_sort_block(typename O::K *sk, uint32_t *sv,
             const uint32_t pt = tid ^ (j / ITEMS);
             const bool lower = (tid & (j / ITEMS)) == 0;
             const bool keep_min = asc == lower;
-            const E bound = keep_min ? E(0) : ~E(0);
+            const E bound = keep_min ? E{} : TE::FLIP;
 #pragma unroll
             for (int i = 0; i < ITEMS; ++i)
                 r[i] = keep_side(r[i], s[(uint32_t)i * NT + pt], keep_min, bound);
@@ -412,7 +455,9 @@ __device__ __forceinline__ void tile_sort_block(typename O::K *sk, uint32_t *sv,
             // signed minimum below; for 64-bit keys (an integer compare and
             // four selects per pair) the partner exchange at every mask
             // measured slightly faster than the swaps
-            if constexpr (TE::F64) {
+            if constexpr (!std::is_same_v<E, uint64_t>) {
+                // (key, index) elements: the shuffle steps below, every mask
+            } else if constexpr (TE::F64) {
                 const uint32_t lm0 = j / ITEMS;
                 if (lm0 >= 32) lane_step_swap64<TE, 32>(r);
                 if (lm0 >= 16) lane_step_swap64<TE, 16>(r);
@@ -454,11 +499,11 @@ __device__ __forceinline__ void tile_sort_block(typename O::K *sk, uint32_t *sv,
             const uint32_t lm = j / ITEMS;
             const bool lower = (lane & lm) == 0;
             const bool keep_min = asc == lower;
-            const E bound = keep_min ? E(0) : ~E(0);
+            const E bound = keep_min ? E{} : TE::FLIP;
             // all exchanges of the stage first, so that they overlap
             E y[ITEMS];
 #pragma unroll
-            for (int i = 0; i < ITEMS; ++i) y[i] = __shfl_xor(r[i], (int)lm, kWave);
+            for (int i = 0; i < ITEMS; ++i) y[i] = shfl_xor_elem(r[i], (int)lm);
 #pragma unroll
             for (int i = 0; i < ITEMS; ++i) r[i] = keep_side(r[i], y[i], keep_min, bound);
         }
@@ -503,7 +548,7 @@ template <class O, bool PAIRS>
 __device__ __forceinline__ void tile_sort_item(TaskRef<SortSeg> tasks, uint32_t item,
                                                typename O::K *samples) {
     using K = typename O::K;
-    constexpr uint32_t T = (PAIRS || sizeof(K) == 8) ? kBaseTilePairs : kBaseTileKeys;
+    constexpr uint32_t T = base_tile_of(PAIRS, sizeof(K) == 8);
     uint32_t t, a;
     const SortSeg g = task_of(tasks, item, &t, &a);
     const uint32_t t0 = t * T;
@@ -564,10 +609,10 @@ hipError_t launch_tile_sort(int dt, bool pairs, const TaskRef<SortSeg> &tasks, u
         return pairs ? tile_sort_t<OrdF32, true>(tasks, tiles, overflow, bytes, ws, st)
                      : tile_sort_t<OrdF32, false>(tasks, tiles, overflow, bytes, ws, st);
     case 2:
-        return pairs ? hipErrorInvalidValue
+        return pairs ? tile_sort_t<OrdU64, true>(tasks, tiles, overflow, bytes, ws, st)
                      : tile_sort_t<OrdU64, false>(tasks, tiles, overflow, bytes, ws, st);
     case 3:
-        return pairs ? hipErrorInvalidValue
+        return pairs ? tile_sort_t<OrdF64, true>(tasks, tiles, overflow, bytes, ws, st)
                      : tile_sort_t<OrdF64, false>(tasks, tiles, overflow, bytes, ws, st);
     default:
         return hipErrorInvalidValue;

@@ -23,6 +23,13 @@ constexpr int kWaves = kBlock / kWave;
 constexpr int kSortThreads = 512;      // threads of the base-case workgroup
 constexpr uint32_t kBaseTileKeys = 16384;  // base-case tile, keys only
 constexpr uint32_t kBaseTilePairs = 8192;  // base-case tile, key/payload pairs
+constexpr uint32_t kBaseTileWidePairs = 2048;  // 64-bit keys with payloads
+// The base tile of a sort: keys only, key/payload pairs or 64-bit keys, or
+// 64-bit keys with payloads (whose 128-bit network elements fill the LDS
+// four times as fast).
+__host__ __device__ constexpr uint32_t base_tile_of(bool pairs, bool wide) {
+    return pairs && wide ? kBaseTileWidePairs : (pairs || wide) ? kBaseTilePairs : kBaseTileKeys;
+}
 constexpr int kMergePerThread = QMS_MERGE_ITEMS;       // outputs per thread
 constexpr int kMergeTile = kBlock * kMergePerThread;   // outputs per workgroup
 // Run samples: every kSampleStride-th element of every sorted run, written by
@@ -63,7 +70,8 @@ __host__ __device__ inline uint32_t scan_a_groups(uint32_t nt, uint32_t nth) {
     return chunks < kScanGroups ? chunks : kScanGroups;
 }
 
-static_assert(kBaseTileKeys % kMergeTile == 0 && kBaseTilePairs % kMergeTile == 0,
+static_assert(kBaseTileKeys % kMergeTile == 0 && kBaseTilePairs % kMergeTile == 0 &&
+                  kBaseTileWidePairs % kMergeTile == 0,
               "runs must tile into merge tiles");
 
 // ---- round state slots (uint64 words in the workspace) ----------------------

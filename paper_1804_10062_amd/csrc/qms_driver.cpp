@@ -159,14 +159,16 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
     // finished in place by one workgroup.  R0: the run width at which each
     // round's Mergesort stops and calls the base case X (QuickMergeXsort's
     // X_THRESH, a tunable), so that a workgroup tile holds T0 / R0 runs.
-    const uint32_t T0 = (pairs || wide) ? kBaseTilePairs : kBaseTileKeys;
+    const uint32_t T0 = base_tile_of(pairs, wide);
     // base_tile 0 (automatic): the whole workgroup tile, except that 4-way
     // sorts take half of it when that makes the level count even, so that
     // every pass merges four runs (no 2-way first pass); 64-bit keys take
     // runs of kMergeTile keys, since their 64-bit network costs more per
     // level than a merge level (2^27 uint64: 11.0 against 10.6 Gkeys/s)
     const bool auto_r0 = tune.base_tile == 0;
-    const bool four_way_sort = tune.merge_ways == 4;
+    // 64-bit keys with payloads merge two runs per pass (a 4-way tile of
+    // their 96-bit elements would not fit the LDS budget)
+    const bool four_way_sort = tune.merge_ways == 4 && !(pairs && wide);
     const uint32_t R0 = auto_r0 ? (wide ? (uint32_t)kMergeTile : T0) : std::min(T0, tune.base_tile);
     auto levels = [](uint64_t m, uint32_t r) -> uint32_t {
         return m > r ? ceil_log2((m + r - 1) / r) : 0;
@@ -441,7 +443,7 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
         // belong to the tasks with L > l and L = l (mod 2), the 2-way first
         // passes (l = 0) to the odd ones; with 2-way passes only
         // (merge_ways 2) every task with L > l runs a 2-way pass at l
-        const bool two = tune.merge_ways == 2;
+        const bool two = !four_way_sort;
         const bool by_parity = !two;
         std::stable_sort(tasks.begin(), tasks.end(), [&](const SortSeg &x, const SortSeg &y) {
             if (by_parity && (x.L & 1u) != (y.L & 1u)) return (x.L & 1u) < (y.L & 1u);

@@ -867,10 +867,10 @@ hipError_t launch_merge_pass(int dt, bool pairs, const MergeLaunch &M, const Wor
         return pairs ? merge_t<OrdU32, true>(M, ws, st) : merge_t<OrdU32, false>(M, ws, st);
     case 1:
         return pairs ? merge_t<OrdF32, true>(M, ws, st) : merge_t<OrdF32, false>(M, ws, st);
-    case 2:  // 64-bit keys: key-only
-        return pairs ? hipErrorInvalidValue : merge_t<OrdU64, false>(M, ws, st);
+    case 2:  // 64-bit keys (with payloads: 2-way passes only)
+        return pairs ? merge_t<OrdU64, true>(M, ws, st) : merge_t<OrdU64, false>(M, ws, st);
     case 3:
-        return pairs ? hipErrorInvalidValue : merge_t<OrdF64, false>(M, ws, st);
+        return pairs ? merge_t<OrdF64, true>(M, ws, st) : merge_t<OrdF64, false>(M, ws, st);
     default:
         return hipErrorInvalidValue;
     }

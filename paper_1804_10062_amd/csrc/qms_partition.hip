@@ -1058,10 +1058,10 @@ hipError_t launch_partition_phase(int dt, bool pairs, const PartitionLaunch &L, 
         return pairs ? partition_t<OrdU32, true>(L, st) : partition_t<OrdU32, false>(L, st);
     case 1:
         return pairs ? partition_t<OrdF32, true>(L, st) : partition_t<OrdF32, false>(L, st);
-    case 2:  // 64-bit keys carry no payload
-        return pairs ? hipErrorInvalidValue : partition_t<OrdU64, false>(L, st);
+    case 2:
+        return pairs ? partition_t<OrdU64, true>(L, st) : partition_t<OrdU64, false>(L, st);
     case 3:
-        return pairs ? hipErrorInvalidValue : partition_t<OrdF64, false>(L, st);
+        return pairs ? partition_t<OrdF64, true>(L, st) : partition_t<OrdF64, false>(L, st);
     default:
         return hipErrorInvalidValue;
     }

@@ -445,9 +445,10 @@ int sort_batch_device_rounds(int dt, bool pairs, char *keys_base, uint32_t *vals
     const Tuning tune = current_tuning();
     const bool wide = dtype_wide(dt);
     const uint32_t ew = wide ? 2 : 1;
-    const uint32_t T0 = (pairs || wide) ? kBaseTilePairs : kBaseTileKeys;
+    const uint32_t T0 = base_tile_of(pairs, wide);
     const bool auto_r0 = tune.base_tile == 0;
-    const bool four_way = tune.merge_ways == 4;
+    // 64-bit keys with payloads merge two runs per pass
+    const bool four_way = tune.merge_ways == 4 && !(pairs && wide);
     const uint32_t R0 = auto_r0 ? (wide ? (uint32_t)kMergeTile : T0) : std::min(T0, tune.base_tile);
     // the smallest run width a Mergesort can take (automatic: half of R0)
     const uint32_t R0_min = (auto_r0 && four_way && !wide) ? R0 / 2 : R0;

@@ -9,8 +9,8 @@ torch = pytest.importorskip("torch")
 
 import oracle  # noqa: E402
 from paper_1804_10062_amd import inputs, qms  # noqa: E402
-from tests.gpu_helpers import (check_pairs_exact, segment_ids,  # noqa: E402
-                               segment_multiset_hash, segments_sorted, to_device, to_host)
+from tests.gpu_helpers import (segment_ids, segment_multiset_hash,  # noqa: E402
+                               segments_sorted, to_device, to_host)
 
 pytestmark = pytest.mark.gpu
 needs_gpu = pytest.mark.skipif(not torch.cuda.is_available(), reason="no GPU")
@@ -76,7 +76,6 @@ def test_device_rounds_tunings_and_pairs(merge_ways, base_tile):
     try:
         qms.qms_set_tuning(merge_ways, 4096, 16384, base_tile)
         kt = to_device(x)
-        k_in = kt.clone()
         vt = torch.arange(n, dtype=torch.int32, device="cuda")
         ot = torch.from_numpy(off.view(np.int64)).cuda()
         qms.qms_sort_batch(kt, ot, vals=vt, host_offsets=off)
@@ -84,10 +83,12 @@ def test_device_rounds_tunings_and_pairs(merge_ways, base_tile):
     finally:
         autotune.reset_tuning()
     want, _, _ = oracle.sort_segments(x, off)
-    np.testing.assert_array_equal(to_host(kt), want)
-    check_pairs_exact(k_in, kt, vt)
+    ko = to_host(kt)
+    np.testing.assert_array_equal(ko, want)
     vo = to_host(vt).astype(np.int64)
-    for j in range(lens.size):  # payloads stay inside their segment
+    # payload = original index: each carries its key, and stays in its segment
+    np.testing.assert_array_equal(x[vo], ko)
+    for j in range(lens.size):
         a, b = int(off[j]), int(off[j + 1])
         assert np.array_equal(np.sort(vo[a:b]), np.arange(a, b))
 

@@ -184,11 +184,55 @@ def test_u64_2e27_full_size_properties():
 
 
 @needs_gpu
+@pytest.mark.parametrize("kind", ["u64", "f64", "u64_few"])
+@pytest.mark.parametrize("n", [2, 3, 2047, 2048, 2049, 100003, 1 << 20])
+def test_64_bit_pairs(kind, n):
+    """64-bit keys with uint32 payloads (payload = original index): keys
+    bit-exact with the oracle's 64-bit build, payloads the exact permutation
+    that carries every key to its place."""
+    rng = np.random.default_rng(n % 997)
+    if kind == "f64":
+        x = rng.standard_normal(n)
+    elif kind == "u64_few":  # many equal keys
+        x = rng.integers(0, 5, n, dtype=np.uint64) << np.uint64(40)
+    else:
+        x = rng.integers(0, 2 ** 64, n, dtype=np.uint64)
+    t = dev64(x)
+    v = torch.arange(n, dtype=torch.int32, device="cuda")
+    qms.qms_sort_pairs(t, v)
+    torch.cuda.synchronize()
+    want, _, _ = oracle.sort(x, counted=False)
+    got = host64(t)
+    np.testing.assert_array_equal(got, want)
+    vo = v.cpu().numpy().astype(np.int64)
+    assert np.array_equal(np.sort(vo), np.arange(n))
+    np.testing.assert_array_equal(x[vo], got)
+
+
+@needs_gpu
+def test_64_bit_pairs_batch():
+    lens = inputs.log_uniform_lengths(120, seed=61, lo_exp=0, hi_exp=17)
+    off = inputs.offsets_from_lengths(lens)
+    n = int(off[-1])
+    x = np.random.default_rng(62).integers(0, 2 ** 64, n, dtype=np.uint64)
+    t = dev64(x)
+    v = torch.arange(n, dtype=torch.int32, device="cuda")
+    ot = torch.from_numpy(off.view(np.int64)).cuda()
+    qms.qms_sort_batch(t, ot, vals=v, host_offsets=off)
+    qms.qms_batch_check()
+    want, _, _ = oracle.sort_segments(x, off)
+    got = host64(t)
+    np.testing.assert_array_equal(got, want)
+    vo = v.cpu().numpy().astype(np.int64)
+    np.testing.assert_array_equal(x[vo], got)
+    for j in range(lens.size):
+        a, b = int(off[j]), int(off[j + 1])
+        assert np.array_equal(np.sort(vo[a:b]), np.arange(a, b))
+
+
+@needs_gpu
 def test_64_bit_rejections():
     x = torch.zeros(64, dtype=torch.int64, device="cuda")
-    v = torch.zeros(64, dtype=torch.int32, device="cuda")
-    with pytest.raises(qms.QmsError):
-        qms.qms_sort_pairs(x, v)
     with pytest.raises(qms.QmsError):
         qms.qms_mom_pivot(x)
     # 4-byte aligned but not 8-byte aligned 64-bit keys
