@@ -60,17 +60,49 @@ def parse():
     ap.add_argument("--dist-steps", type=int, default=3,
                     help="timed sorts for the nearly-sorted and reverse inputs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-log2", type=int, default=26)
+    ap.add_argument("--cpu-sample-log2", type=int, default=28)
     ap.add_argument("--only-uniform", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-threshold-sweep", action="store_true")
     ap.add_argument("--per-array-stride", type=int, default=10)
-    ap.add_argument("--serving-requests", type=int, default=3000)
+    ap.add_argument("--serving-requests", type=int, default=20000)
+    ap.add_argument("--serving-warmup", type=int, default=1000)
     ap.add_argument("--pmc-run", action="store_true",
                     help="short run for rocprofv3 counter passes: one 1 GiB device copy "
                          "(calibration kernel of known size) and one sort of the workload")
     return ap.parse_args()
+
+
+def _oracle_child(keys, core, conn):
+    """Child process: pin to `core`, time the oracle's sort of `keys`."""
+    import numpy as np
+    try:
+        os.sched_setaffinity(0, {core})
+    except OSError:
+        pass
+    import oracle
+    t0 = time.perf_counter()
+    oracle.sort_inplace_fast(keys, False)
+    dt = time.perf_counter() - t0
+    conn.send((dt, bool(np.all(keys[1:] >= keys[:-1]))))
+    conn.close()
+
+
+def _oracle_on_one_core(keys):
+    """The C oracle on a copy of `keys` in a forked child pinned to one core
+    (the child touches no GPU state); returns (seconds, core)."""
+    import multiprocessing as mp
+    ctx = mp.get_context("fork")
+    cores = sorted(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else [0]
+    core = cores[-1]
+    a, b = ctx.Pipe(duplex=False)
+    p = ctx.Process(target=_oracle_child, args=(keys.copy(), core, b))
+    p.start()
+    dt, ok = a.recv()
+    p.join()
+    assert ok, "oracle output not sorted"
+    return dt, core
 
 
 def merge_source_hash() -> str:
@@ -108,8 +140,10 @@ def time_sorts(copies, qms, torch, profile: bool):
 def bench_batched(qms, torch, np, inputs, per_array_stride: int, reps: int = 3):
     """20,000 arrays, lengths log-uniform in [2^6, 2^20] (seed 5), float32
     N(0,1) keys drawn on the device: one qms_sort_batch call for all of them
-    against one qms_sort call per array (every `per_array_stride`-th array,
-    same kernels, same stream)."""
+    (rounds planned on the device; the call returns before the GPU has run
+    them), the same call captured once in a HIP graph and replayed, and one
+    qms_sort call per array (every `per_array_stride`-th array, same
+    kernels, same stream)."""
     lens = inputs.log_uniform_lengths(20000, seed=5, lo_exp=6, hi_exp=20)
     off = inputs.offsets_from_lengths(lens)
     n = int(off[-1])
@@ -128,18 +162,45 @@ def bench_batched(qms, torch, np, inputs, per_array_stride: int, reps: int = 3):
     sot = torch.from_numpy(soff.view(np.int64)).cuda()
     tune = autotune.autotune_batch(sample, sot, host_offsets=soff)
     del sample
+    from tests.gpu_helpers import segments_sorted
     work = src.clone()
-    times = []
+    times, calls = [], []
     for _ in range(reps + 1):
         work.copy_(src)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         qms.qms_sort_batch(work, ot, host_offsets=off)
+        t1 = time.perf_counter()
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
-    from tests.gpu_helpers import segments_sorted
+        calls.append(t1 - t0)
+    qms.qms_batch_check()
     assert segments_sorted(work, ot), "batched output not sorted"
     t_batch = min(times[1:])
+    # the whole batch as one HIP graph (captured on its own stream after a
+    # warm-up call there, which creates that stream's workspace)
+    gs = torch.cuda.Stream()
+    with torch.cuda.stream(gs):
+        qms.qms_sort_batch(work, ot, host_offsets=off)
+    gs.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    work.copy_(src)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph, stream=gs):
+        qms.qms_sort_batch(work, ot, host_offsets=off)
+    gtimes = []
+    for _ in range(reps):
+        work.copy_(src)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        graph.replay()
+        torch.cuda.synchronize()
+        gtimes.append(time.perf_counter() - t0)
+        assert segments_sorted(work, ot), "graph replay output not sorted"
+    with torch.cuda.stream(gs):
+        qms.qms_batch_check(stream=gs)
+    t_graph = min(gtimes)
+    del graph
     work.copy_(src)
     idx = list(range(0, lens.size, per_array_stride))
     keys_sub = int(sum(int(lens[j]) for j in idx))
@@ -151,6 +212,7 @@ def bench_batched(qms, torch, np, inputs, per_array_stride: int, reps: int = 3):
     torch.cuda.synchronize()
     t_per = time.perf_counter() - t0
     batched = n / t_batch / 1e9
+    graphed = n / t_graph / 1e9
     per_array = keys_sub / t_per / 1e9
     # the per-array sample's input keys, kept on the host for the CPU leg
     host_sample = [src[int(off[j]):int(off[j + 1])].cpu().numpy().view(np.uint32).copy()
@@ -161,10 +223,14 @@ def bench_batched(qms, torch, np, inputs, per_array_stride: int, reps: int = 3):
                     f"N(0,1) keys; {n} keys in all",
         "batched_Gkeys_per_s": round(batched, 3),
         "batched_ms": round(t_batch * 1e3, 2),
+        "call_returns_after_ms": round(min(calls[1:]) * 1e3, 2),
+        "graph_Gkeys_per_s": round(graphed, 3),
+        "graph_ms": round(t_graph * 1e3, 2),
         "per_array_Gkeys_per_s": round(per_array, 4),
         "per_array_sample": f"every {per_array_stride}th array ({len(idx)} arrays, "
                             f"{keys_sub} keys), one qms_sort call each",
         "speedup": round(batched / per_array, 2),
+        "graph_speedup": round(graphed / per_array, 2),
         "tuning": tune["best"],
         # every candidate the autotuner timed, keyed by all five tunables
         "autotune_trials_ms": {"/".join(str(t[f]) for f in autotune.FIELDS): t["ms"]
@@ -173,70 +239,143 @@ def bench_batched(qms, torch, np, inputs, per_array_stride: int, reps: int = 3):
     }
 
 
-def bench_serving(qms, torch, np, inputs, loads, count: int, budget: int = 64 << 30):
+def _request_hashes(torch, pool, off, ids):
+    """Order-independent hash of each request's 32-bit words (requests
+    `ids`, ranges off[j]..off[j+1] of the pool), summed in int64 chunks."""
+    from tests.gpu_helpers import _C1, _C2
+    out = torch.zeros(len(ids), dtype=torch.int64, device=pool.device)
+    for q, j in enumerate(ids):
+        a, b = int(off[j]), int(off[j + 1])
+        acc = 0
+        for c in range(a, b, 1 << 26):
+            x = pool[c:min(b, c + (1 << 26))].to(torch.int64) & 0xFFFFFFFF
+            h = x * _C1
+            h = h ^ ((h >> 29) & ((1 << 35) - 1))
+            h = h * _C2
+            h = h ^ ((h >> 32) & 0xFFFFFFFF)
+            acc = acc + h.sum()
+        out[q] = acc
+    return out
+
+
+def _requests_sorted(torch, pool, off, is_f, ids):
+    """Per request: keys non-decreasing (unsigned, or IEEE total order for
+    float32 requests)."""
+    ok = torch.ones(len(ids), dtype=torch.bool, device=pool.device)
+    for q, j in enumerate(ids):
+        a, b = int(off[j]), int(off[j + 1])
+        if b - a < 2:
+            continue
+        u = pool[a:b].to(torch.int64) & 0xFFFFFFFF
+        if is_f[j]:
+            u = torch.where(u >= (1 << 31), -(u - (1 << 31)) - 1, u)
+        ok[q] = bool((u[1:] >= u[:-1]).all())
+    return ok
+
+
+def bench_serving(qms, torch, np, inputs, loads, count: int, warmup: int,
+                  budget: int = 64 << 30, oracle_every: int = 100):
     """Open-loop Poisson arrivals of sort requests (sizes floor(2^(10+14u)),
     uint32 or float32 with probability 1/2, uniform values) submitted to the
-    library's server; latency = completion - scheduled arrival."""
-    u = inputs.unit_f64(count, seed=7, stream=11)
+    library's server; latency = completion - scheduled arrival.  Per load:
+    `warmup` requests first (not measured), then `count` measured ones.  All
+    requests' keys are drawn on the device before the load starts; every
+    measured request is checked on the device afterwards (sorted, and the
+    same multiset hash as its input), every `oracle_every`-th one against
+    the oracle."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    total_req = warmup + count
+    u = inputs.unit_f64(total_req, seed=7, stream=11)
     sizes = np.floor(2.0 ** (10 + 14 * u)).astype(np.int64)
-    is_f = (inputs.uniform_u32(count, seed=7, stream=12) & 1).astype(bool)
-    off = np.zeros(count + 1, dtype=np.int64)
+    is_f = (inputs.uniform_u32(total_req, seed=7, stream=12) & 1).astype(bool)
+    off = np.zeros(total_req + 1, dtype=np.int64)
     np.cumsum(sizes, out=off[1:])
     total = int(off[-1])
-    pool_u = torch.empty(total, dtype=torch.int32, device="cuda")
-    pool_f = torch.empty(total, dtype=torch.float32, device="cuda")
-    views = [(pool_f if is_f[j] else pool_u)[int(off[j]):int(off[j + 1])] for j in range(count)]
+    pool = torch.empty(total, dtype=torch.int32, device="cuda")
+    pool_f = pool.view(torch.float32)
+    measured = list(range(warmup, total_req))
+    picks = measured[::oracle_every]
     out = {}
     for rate in loads:
-        pool_u.random_(-(1 << 31), (1 << 31) - 1)
-        pool_f.uniform_(0.0, 1.0)
+        # keys of every request, drawn on the device
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(1000 + int(rate))
+        for c in range(0, total, 1 << 28):
+            m = min(total, c + (1 << 28)) - c
+            pool[c:c + m].random_(-(1 << 31), (1 << 31) - 1, generator=gen)
+        for j in np.nonzero(is_f)[0]:
+            a, b = int(off[j]), int(off[j + 1])
+            pool_f[a:b].uniform_(0.0, 1.0, generator=gen)
+        h_in = _request_hashes(torch, pool, off, measured)
+        before = {j: pool[int(off[j]):int(off[j + 1])].cpu().numpy().copy() for j in picks}
+        views = [(pool_f if is_f[j] else pool)[int(off[j]):int(off[j + 1])]
+                 for j in range(total_req)]
         torch.cuda.synchronize()
-        arr = inputs.poisson_arrivals(count, float(rate), seed=100 + int(rate))
         srv = qms.Server(hbm_budget_bytes=budget, device=0)
+        # warm-up requests, then the measured load
+        wt = [srv.submit(views[j]) for j in range(warmup)]
+        for t in wt:
+            while srv.poll(t)[0] != qms.QMS_OK:
+                time.sleep(0.0002)
+        arr = inputs.poisson_arrivals(count, float(rate), seed=100 + int(rate))
         tickets = []
         late = np.zeros(count)
         t0 = time.perf_counter()
-        for j in range(count):
-            due = t0 + arr[j]
-            while True:
-                now = time.perf_counter()
-                if now >= due:
-                    break
+        for q, j in enumerate(measured):
+            due = t0 + arr[q]
+            while time.perf_counter() < due:
+                pass
             tickets.append(srv.submit(views[j]))
-            late[j] = time.perf_counter() - due
+            late[q] = time.perf_counter() - due
         lat = np.zeros(count)
         pending = dict(enumerate(tickets))
         while pending:
-            for j, t in list(pending.items()):
+            for q, t in list(pending.items()):
                 st, l = srv.poll(t)
                 if st == qms.QMS_OK:
-                    lat[j] = l + late[j]
-                    del pending[j]
+                    lat[q] = l + late[q]
+                    del pending[q]
             if pending:
                 time.sleep(0.0002)
-        t_end = time.perf_counter()
         st = srv.stats()
         srv.close()
-        from tests.gpu_helpers import is_sorted
-        bad = sum(0 if is_sorted(views[j]) else 1 for j in range(0, count, max(1, count // 200)))
-        assert bad == 0, "served output not sorted"
-        wall = t_end - t0
-        # completions end before the last poll; use the latest completion
-        done_at = max(arr[j] + lat[j] for j in range(count))
+        torch.cuda.synchronize()
+        ok_sorted = _requests_sorted(torch, pool, off, is_f, measured)
+        h_out = _request_hashes(torch, pool, off, measured)
+        bad = int((~ok_sorted).sum().item()) + int((h_out != h_in).sum().item())
+        assert bad == 0, f"{bad} served requests not sorted or not a permutation"
+
+        def check(j):
+            want, _, _ = oracle.sort(before[j].view(np.float32) if is_f[j] else
+                                     before[j].view(np.uint32), counted=False)
+            got = pool[int(off[j]):int(off[j + 1])].cpu().numpy()
+            return np.array_equal(got.view(np.uint32), want.view(np.uint32))
+        with ThreadPoolExecutor(max_workers=max(1, min(16, os.cpu_count() or 1))) as ex:
+            oracle_ok = all(ex.map(check, picks))
+        assert oracle_ok, "a served request differs from the oracle"
+        done_at = max(arr[q] + lat[q] for q in range(count))
+        keys = int(sum(int(sizes[j]) for j in measured))
+        p99_by_len = {str(m): round(float(np.percentile(lat[:m], 99)) * 1e3, 3)
+                      for m in (count // 4, count // 2, count)}
         out[f"{rate}_req_per_s"] = {
-            "offered_Gkeys_per_s": round(float(sizes.sum()) / arr[-1] / 1e9, 2),
+            "offered_Gkeys_per_s": round(keys / arr[-1] / 1e9, 2),
             "completed_req_per_s": round(count / done_at, 1),
-            "throughput_Gkeys_per_s": round(total / done_at / 1e9, 3),
+            "throughput_Gkeys_per_s": round(keys / done_at / 1e9, 3),
             "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
             "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3),
+            "p99_ms_over_first_requests": p99_by_len,
             "batches": st["batches"],
             "peak_admitted_GB": round(st["peak_admitted_bytes"] / 1e9, 3),
             "waited_for_budget": st["waited_for_budget"],
             "submit_late_p99_ms": round(float(np.percentile(late, 99)) * 1e3, 3),
+            "verified_on_device": count,
+            "oracle_checked": len(picks),
         }
-        del wall
-    del pool_u, pool_f, views
-    return {"requests_per_load": count, "hbm_budget_GB": budget / 2**30,
+        del views, before
+    del pool, pool_f
+    return {"requests_per_load": count, "warmup_requests": warmup,
+            "hbm_budget_GB": budget / 2**30,
             "sizes": "floor(2^(10 + 14u)) keys, u uniform (seed 7)", "loads": out}
 
 
@@ -291,22 +430,47 @@ def main():
     for i in range(K):
         copies[W + i].copy_(src)
     secs_prof, prof = time_sorts(copies[W:], qms, torch, profile=True)
-    del copies
+    # the box's copy bandwidth in this run: a device copy of 1 GiB (read
+    # 1 GiB, write 1 GiB), best of 5, timed with events
+    cdst = copies[0]
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    copy_ms = []
+    for _ in range(6):
+        ev0.record()
+        cdst.copy_(src)
+        ev1.record()
+        ev1.synchronize()
+        copy_ms.append(ev0.elapsed_time(ev1))
+    copy_gbs = 2.0 * N_KEYS * 4 / (min(copy_ms[1:]) / 1e3) / 1e9
+    del copies, cdst
 
     ms = secs / K * 1e3
     value = N_KEYS / (secs / K) / 1e9
 
-    kernels = {}
-    for name, d in prof.items():
-        if d["launches"] == 0:
-            continue
-        kernels[name] = {
+    def kstat(d):
+        return {
             "launches_per_step": d["launches"] / K,
             "ms_per_step": d["total_ms"] / K,
             "mean_launch_us": d["total_ms"] / d["launches"] * 1e3,
             "algorithmic_GB_per_step": d["bytes"] / K / 1e9,
             "achieved_GBs": (d["bytes"] / 1e9) / (d["total_ms"] / 1e3) if d["bytes"] else None,
         }
+
+    # kernel classes, and the swap-merge passes by the binary level they
+    # start at (a 4-way pass covers that level and the next)
+    kernels, merge_levels = {}, {}
+    for name, d in prof.items():
+        if d["launches"] == 0:
+            continue
+        if name.startswith("merge_level_"):
+            st = kstat(d)
+            st["bytes_per_launch"] = d["bytes"] / d["launches"]
+            st["pct_of_copy"] = (round(100.0 * st["achieved_GBs"] / copy_gbs, 1)
+                                 if st["achieved_GBs"] else None)
+            merge_levels[name[len("merge_level_"):]] = st
+        else:
+            kernels[name] = kstat(d)
+    prof = {k: v for k, v in prof.items() if not k.startswith("merge_level_")}
     mk = prof["merge"]
     achieved = (mk["bytes"] / 1e9) / (mk["total_ms"] / 1e3)
     traffic = measured_traffic()
@@ -321,6 +485,9 @@ def main():
         "algorithmic_bytes_per_launch": mk["bytes"] / mk["launches"],
         "mean_launch_us": mk["total_ms"] / mk["launches"] * 1e3,
         "launches": mk["launches"],
+        # the same against a plain device copy of 1 GiB measured in this run
+        "copy_GBs": round(copy_gbs, 1),
+        "frac_of_copy": round(achieved / copy_gbs, 4),
     }
     # the whole sort against the same peak: all algorithmic bytes of the
     # executed schedule (base case, merge passes, counting, pass-A exchange)
@@ -329,6 +496,7 @@ def main():
     whole_sort = {"algorithmic_GB_per_sort": round(sort_gb, 3),
                   "GB_s": round(sort_gb / (ms / 1e3), 1),
                   "frac": round(sort_gb / (ms / 1e3) / HBM_PEAK_GBS, 4),
+                  "frac_of_copy": round(sort_gb / (ms / 1e3) / copy_gbs, 4),
                   "B_per_key": round(sort_gb * 1e9 / N_KEYS, 1)}
 
     dists = {"uniform": round(value, 3)}
@@ -451,30 +619,30 @@ def main():
     serving = None
     if not args.no_serving:
         print("[bench] serving", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()  # the serving pool takes about 145 GB
         serving = bench_serving(qms, torch, np, inputs, (2000, 10000, 50000),
-                                args.serving_requests)
+                                args.serving_requests, args.serving_warmup)
 
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
         m = 1 << args.cpu_sample_log2
-        sample = host[:m].copy()
-        print(f"[bench] cpu oracle on 2^{args.cpu_sample_log2} keys", file=sys.stderr, flush=True)
-        t0 = time.perf_counter()
-        oracle.sort_inplace_fast(sample, False)
-        dt = time.perf_counter() - t0
-        assert np.all(sample[1:] >= sample[:-1])
+        print(f"[bench] cpu oracle on 2^{args.cpu_sample_log2} keys, one pinned core",
+              file=sys.stderr, flush=True)
+        dt, core = _oracle_on_one_core(host[:m])
         cpu = {"value": round(m / dt / 1e9, 5), "unit": "Gkeys/s", "cores": 1,
-               "kind": "oracle", "seconds": round(dt, 2),
-               "sample": f"first 2^{args.cpu_sample_log2} keys of the uniform 2^28 workload "
-                         "(seed 2), single-threaded C oracle (QuickMergesort of Fig. 2, "
-                         "counters compiled out)"}
+               "kind": "oracle", "seconds": round(dt, 2), "pinned_core": core,
+               "sample": ("the whole" if m == N_KEYS else f"the first 2^{args.cpu_sample_log2} "
+                          "keys of the") + " uniform 2^28 workload (seed 2), single-threaded C "
+                          "oracle (QuickMergesort of Fig. 2, counters compiled out), in a child "
+                          "process pinned to one core"}
         if batched_host is not None:
-            # the batched workload on the host's cores (at most 16, the
-            # share of one GPU): the per-array sample's arrays, one oracle
-            # call each (ctypes releases the GIL during the call)
+            # the batched workload's sample on the host's cores: one oracle
+            # call per array on a pool of threads (ctypes releases the GIL);
+            # at most 16 threads, the host share of one GPU on the box
+            import oracle
             from concurrent.futures import ThreadPoolExecutor
-            workers = max(1, min(16, os.cpu_count() or 1))
+            nproc = os.cpu_count() or 1
+            workers = max(1, min(16, nproc))
             keys = int(sum(a.size for a in batched_host))
             print(f"[bench] cpu oracle on the batched sample, {workers} threads",
                   file=sys.stderr, flush=True)
@@ -484,7 +652,7 @@ def main():
             dt = time.perf_counter() - t0
             batched["cpu_baseline"] = {
                 "value": round(keys / dt / 1e9, 5), "unit": "Gkeys/s", "cores": workers,
-                "kind": "oracle", "seconds": round(dt, 2),
+                "nproc": nproc, "kind": "oracle", "seconds": round(dt, 2),
                 "sample": f"the per-array sample of the batched workload ({len(batched_host)} "
                           f"float32 arrays, {keys} keys), one C oracle call per array on a "
                           f"pool of {workers} threads"}
@@ -516,6 +684,8 @@ def main():
         "batched": batched,
         "serving": serving,
         "kernels": kernels,
+        "merge_levels": merge_levels,
+        "copy_GBs": round(copy_gbs, 1),
     }
     print(json.dumps(out))
 
