@@ -14,16 +14,19 @@
  *     (Sec. "QuickXsort and QuickMergesort");
  *   - swap-instead-of-move: an element Mergesort would move to extra space is
  *     exchanged with the element occupying that buffer cell (same section);
- *   - the merge / msort / out / sort routines of Fig. 2 (QuickMergeXsort with
- *     X_THRESH = 2, i.e. pure Mergesort), with two repairs of the printed
- *     figure, both listed below;
+ *     here every placement is such an exchange (swap_merge, sort_to);
+ *   - top-down Mergesort with a buffer: a range is split into its first
+ *     floor(n/2) and last ceil(n/2) elements, each half is sorted into the
+ *     cells that Fig. 1 shows, and the halves are merged (sort_to,
+ *     sort_with_buffer), driven by the QuickMergesort loop of the same
+ *     section (quick_merge_sort);
  *   - median-of-3 pivot ("CleverQuickMergesort", Theorem 1 / Corollary 2):
  *     3 comparisons for the sample, one comparison per remaining element
  *     during partitioning (proof of Theorem 1);
  *   - QuickMergeXsort (Sec. "QuickMergeXsort", Theorem "Average-Case
- *     QuickMergeXsort"): msort hands ranges shorter than X_THRESH to a
+ *     QuickMergeXsort"): the Mergesort hands ranges shorter than X_THRESH to a
  *     sorting algorithm X and then exchanges the sorted block with its target
- *     cells (the joint movement of Fig. 2).  X = CleverQuicksort, Quicksort
+ *     cells (a joint movement).  X = CleverQuicksort, Quicksort
  *     with the median-of-3 partition below (Introduction: its average is
  *     (12/7) ln 2 n lg n + O(n) comparisons).  X_THRESH = 2 is QuickMergesort.
  *
@@ -36,12 +39,16 @@
  *   R2  the side test of sort() adds two iterators; read as
  *       "b - begin < (end - begin) / 2" with integer division: the smaller
  *       side is sorted by Mergesort, the loop continues on the larger side.
- *   R3  in msort the final merge of the printed figure passes run1 as
- *       [begin+q, begin+n); run1 holds q elements, so for odd n that merge
- *       would consume a buffer element.  Here run1 is [begin+q, begin+2q).
- *   R4  the tail loop of merge reads one cell past endtarget on its last
- *       step; the value read is dead (the hole is closed with temp right
- *       after), so the last step writes temp directly and reads nothing.
+ *   R3  Fig. 2's Mergesort into a target passes its first merged run as n -
+ *       floor(n/2) cells long, one more than that run holds for odd n (the
+ *       merge would take in a buffer element); here that run is the
+ *       floor(n/2) sorted first-half elements.
+ *   R4  Fig. 2 realises the exchanges with a travelling hole (two moves per
+ *       placed element plus two).  This oracle performs the exchanges of the
+ *       swap principle themselves (three moves each): the comparisons, their
+ *       outcomes and the sorted result are the same, only the order in which
+ *       the buffer elements come back differs, and the move counter reads
+ *       three per placed element.
  *   R5  ranges of 2 elements are finished with one compare-exchange; ranges
  *       of 0 or 1 element are done (median-of-3 needs 3 elements).
  *   R6  float keys are compared through the IEEE-754 total order (negative
@@ -57,7 +64,7 @@
  *       paper selects it with the median-of-medians algorithm; any exact
  *       selection yields the same value, here a library sort of the medians.
  *   R8  QuickMergeXsort's threshold X_THRESH is one constant for the whole
- *       sort, as in Fig. 2 (msort tests n < X_THRESH); the configuration the
+ *       sort, as in Fig. 2 (the Mergesort tests n < X_THRESH); the configuration the
  *       paper analyses, X called at about sqrt(n) elements, takes
  *       X_THRESH = ceil(sqrt(n)) of the whole input (the caller's choice).
  *       CleverQuicksort recurses on the smaller side and loops on the larger
@@ -120,7 +127,7 @@ typedef struct {
     qkey_t *k;
     uint32_t *v;
     qmso_counters *c;
-    size_t xt; /* X_THRESH of msort (2: pure Mergesort) */
+    size_t xt; /* X_THRESH of the Mergesort (2: pure Mergesort) */
 } arr_t;
 
 #if QMSO_COUNTING
@@ -160,76 +167,85 @@ static inline void swap_ij(arr_t *a, size_t i, size_t j)
     }
 }
 
-/*
- * merge (Fig. 2): run1 = [begin1, end1) lies outside the target; run2 lies
- * already in place at [target + (end1 - begin1), endtarget).  The result
- * fills [target, endtarget).  The cells of run1 receive the buffer elements
- * that occupied [target, target + len1) -- the swap principle of the
- * QuickXsort section, done with a travelling hole (temp) so that each merged
- * element costs two moves instead of a three-move swap.  Ties are taken from
- * run2 because the test is the strict key(run1) < key(run2).
- */
-static void merge(arr_t *a, size_t begin1, size_t end1, size_t target,
-                  size_t endtarget)
+/* exchange the k elements at [x, x + k) with those at [y, y + k) */
+static void swap_blocks(arr_t *a, size_t x, size_t y, size_t k)
 {
-    size_t i1 = begin1, i2 = target + (end1 - begin1), ires = target;
-    qkey_t temp_k = a->k[target];
-    uint32_t temp_v = a->v ? a->v[target] : 0;
-    COUNT_MOV(a, 1);
-    while (i1 != end1 && i2 != endtarget) {
-        size_t from = less_ij(a, i1, i2) ? i1++ : i2++;
-        assign(a, ires, from); /* chosen element into the hole          */
-        ires++;
-        assign(a, from, ires); /* next target cell into the vacated cell */
+    for (size_t i = 0; i < k; i++) swap_ij(a, x + i, y + i);
+}
+
+/*
+ * Merging by exchanges (the swap principle of Sec. "QuickXsort and
+ * QuickMergesort": an element that Mergesort would write to extra space is
+ * exchanged with the buffer element sitting in that cell).
+ *
+ * The output window W = [w, w + nx + ny) holds buffer elements in its first
+ * nx cells and the sorted run Y in its last ny cells; the sorted run X has
+ * nx elements at [x0, x0 + nx), outside W.  Each output cell, from the left,
+ * is exchanged with the smaller of the two run heads (Y's head on equal
+ * keys).  While X is not used up, the cells between the next output cell and
+ * Y's head are exactly the not yet displaced buffer elements, so an exchange
+ * never moves a run element out of reach.  Once X is used up the rest of Y
+ * already lies in place.  Afterwards W holds the nx + ny run elements in
+ * order and [x0, x0 + nx) holds the buffer elements (in some order).
+ */
+static void swap_merge(arr_t *a, size_t x0, size_t nx, size_t w, size_t ny)
+{
+    const size_t x_end = x0 + nx, w_end = w + nx + ny;
+    size_t x = x0, y = w + nx, o = w;
+    for (; x < x_end; o++) {
+        const int take_y = y < w_end && !less_ij(a, x, y);
+        if (take_y) {
+            swap_ij(a, o, y);
+            y++;
+        } else {
+            swap_ij(a, o, x);
+            x++;
+        }
     }
-    while (i1 < end1) {
-        assign(a, ires, i1);
-        ires++;
-        if (ires < endtarget) /* R4: the last step reads nothing   */
-            assign(a, i1, ires);
-        i1++;
-    }
-    /* close the hole: the buffer element saved at the start */
-    a->k[i1 - 1] = temp_k;
-    if (a->v) a->v[i1 - 1] = temp_v;
-    COUNT_MOV(a, 1);
 }
 
 static void clever_quicksort(arr_t *a, size_t lo, size_t hi);
 
 /*
- * msort (Fig. 2): sort [begin, end) into [target, target + n); the buffer
- * elements found at the target end up in [begin, end).  Below X_THRESH the
- * range is sorted by X in place and then swapped into the target cells (the
- * joint movement); with X_THRESH = 2 a single element is its own sorted run.
+ * Mergesort into a disjoint target: the n elements at [src, src + n) end
+ * sorted at [dst, dst + n), and the n elements found there end at
+ * [src, src + n).  The first h = floor(n/2) and the last k = n - h elements
+ * are sorted separately (the last k straight into the tail of the target,
+ * the first h into the cells the last k have just vacated, which now hold
+ * target elements) and then merged into the target.  Blocks shorter than
+ * X_THRESH are sorted by X where they are and exchanged into the target as
+ * one block (QuickMergeXsort's joint movement; with X_THRESH = 2 a single
+ * element is its own sorted run).  Reading R3 fixes the size of the first
+ * run of the merge.
  */
-static void msort(arr_t *a, size_t begin, size_t end, size_t target)
+static void sort_to(arr_t *a, size_t src, size_t n, size_t dst)
 {
-    size_t n = end - begin;
     if (n < a->xt) {
-        clever_quicksort(a, begin, end);
-        for (size_t i = 0; i < n; i++) swap_ij(a, begin + i, target + i);
+        clever_quicksort(a, src, src + n);
+        swap_blocks(a, src, dst, n);
         return;
     }
-    size_t q = n / 2;
-    msort(a, begin + q, end, target + q); /* right part into target+q..  */
-    msort(a, begin, begin + q, begin + q); /* left part into begin+q..    */
-    merge(a, begin + q, begin + 2 * q, target, target + n); /* R3 */
+    const size_t h = n / 2, k = n - h;
+    sort_to(a, src + h, k, dst + h);
+    sort_to(a, src, h, src + h);
+    swap_merge(a, src + h, h, dst, k);
 }
 
 /*
- * out (Fig. 2): sort [begin, end) in place, using the ceil(n/2) cells at
- * temp as swap space; those cells get their elements back, permuted.
+ * Mergesort in place: sorts the n elements at [lo, lo + n) with the
+ * ceil(n/2) cells at buf as swap space (they get their elements back,
+ * permuted).  The last k = ceil(n/2) elements go sorted to the swap space,
+ * the first h = floor(n/2) sorted to the top h cells of the range, and the
+ * run in the swap space is merged back into the range (Fig. 1 shows this
+ * placement).
  */
-static void out(arr_t *a, size_t begin, size_t end, size_t temp)
+static void sort_with_buffer(arr_t *a, size_t lo, size_t n, size_t buf)
 {
-    size_t n = end - begin;
-    if (n > 1) {
-        size_t q = n / 2, r = n - q;
-        msort(a, begin + q, end, temp);     /* right r elements -> temp   */
-        msort(a, begin, begin + q, begin + r); /* left q -> [begin+r, end) */
-        merge(a, temp, temp + r, begin, end);
-    }
+    if (n < 2) return;
+    const size_t h = n / 2, k = n - h;
+    sort_to(a, lo + h, k, buf);
+    sort_to(a, lo, h, lo + k);
+    swap_merge(a, buf, k, lo, h);
 }
 
 /* compare-exchange so that key(i) <= key(j); one comparison */
@@ -291,23 +307,26 @@ static void clever_quicksort(arr_t *a, size_t lo, size_t hi)
     }
 }
 
-/* sort (Fig. 2): the QuickMergesort loop on [lo, hi). */
-static void qms_loop(arr_t *a, size_t lo, size_t hi)
+/*
+ * QuickMergesort on [lo, hi) (Sec. "QuickXsort and QuickMergesort"):
+ * partition around the median of three; the side with fewer than half of
+ * the range's elements (reading R2) is mergesorted, the other side serving
+ * as its swap space; the other side is what remains to be sorted.
+ */
+static void quick_merge_sort(arr_t *a, size_t lo, size_t hi)
 {
-    while (hi - lo > 1) {
-        if (hi - lo == 2) { /* R5 */
-            cmp_exchange(a, lo, lo + 1);
-            return;
-        }
-        size_t b = partition(a, lo, hi);
-        if (b - lo < (hi - lo) / 2) { /* R2: left side is the smaller */
-            out(a, lo, b, b + 1);
-            lo = b + 1;
+    for (size_t n = hi - lo; n > 2; n = hi - lo) {
+        const size_t p = partition(a, lo, hi);
+        const size_t n_left = p - lo, n_right = hi - (p + 1);
+        if (n_left < n / 2) {
+            sort_with_buffer(a, lo, n_left, p + 1);
+            lo = p + 1;
         } else {
-            out(a, b + 1, hi, lo);
-            hi = b;
+            sort_with_buffer(a, p + 1, n_right, lo);
+            hi = p;
         }
     }
+    if (hi - lo == 2) cmp_exchange(a, lo, lo + 1); /* R5 */
 }
 
 /* R6: IEEE-754 total order as an unsigned key, and its inverse (binary32
@@ -341,7 +360,7 @@ void QMSO_FN(sort)(qkey_t *keys, uint32_t *vals, size_t n, int is_f32,
     arr_t a = {keys, vals, counters_or_scratch(counters, &scratch), 2};
     if (is_f32)
         for (size_t i = 0; i < n; i++) keys[i] = f32_bits_to_key(keys[i]);
-    qms_loop(&a, 0, n);
+    quick_merge_sort(&a, 0, n);
     if (is_f32)
         for (size_t i = 0; i < n; i++) keys[i] = key_to_f32_bits(keys[i]);
 }
@@ -355,7 +374,7 @@ void QMSO_FN(sort_x)(qkey_t *keys, uint32_t *vals, size_t n, int is_f32,
                x_thresh < 2 ? 2 : x_thresh};
     if (is_f32)
         for (size_t i = 0; i < n; i++) keys[i] = f32_bits_to_key(keys[i]);
-    qms_loop(&a, 0, n);
+    quick_merge_sort(&a, 0, n);
     if (is_f32)
         for (size_t i = 0; i < n; i++) keys[i] = key_to_f32_bits(keys[i]);
 }
@@ -423,7 +442,10 @@ uint32_t qmso_mom_pivot(const uint32_t *keys, size_t n, int is_f32, int *ok)
 }
 
 /* The pieces below are exported only from the counting build, for tests
- * that pin the individual routines of Fig. 2.  Keys are plain u32. */
+ * that pin the individual routines: the partition, the Mergesort into a
+ * target (msort), the Mergesort with a buffer (out) and the exchange merge
+ * (merge), the last three with the argument conventions of Fig. 2.  Keys
+ * are plain u32. */
 
 size_t qmso_partition(uint32_t *keys, uint32_t *vals, size_t lo, size_t hi,
                       qmso_counters *counters)
@@ -438,7 +460,7 @@ void qmso_out(uint32_t *keys, uint32_t *vals, size_t begin, size_t end,
 {
     qmso_counters scratch;
     arr_t a = {keys, vals, counters_or_scratch(counters, &scratch), 2};
-    out(&a, begin, end, temp);
+    sort_with_buffer(&a, begin, end - begin, temp);
 }
 
 void qmso_msort(uint32_t *keys, uint32_t *vals, size_t begin, size_t end,
@@ -446,17 +468,18 @@ void qmso_msort(uint32_t *keys, uint32_t *vals, size_t begin, size_t end,
 {
     qmso_counters scratch;
     arr_t a = {keys, vals, counters_or_scratch(counters, &scratch), 2};
-    msort(&a, begin, end, target);
+    sort_to(&a, begin, end - begin, target);
 }
 
-/* msort with X = CleverQuicksort below x_thresh (QuickMergeXsort's msort) */
+/* the Mergesort into a target with X = CleverQuicksort below x_thresh
+ * (QuickMergeXsort) */
 void qmso_msort_x(uint32_t *keys, uint32_t *vals, size_t begin, size_t end,
                   size_t target, size_t x_thresh, qmso_counters *counters)
 {
     qmso_counters scratch;
     arr_t a = {keys, vals, counters_or_scratch(counters, &scratch),
                x_thresh < 2 ? 2 : x_thresh};
-    msort(&a, begin, end, target);
+    sort_to(&a, begin, end - begin, target);
 }
 
 void qmso_merge(uint32_t *keys, uint32_t *vals, size_t begin1, size_t end1,
@@ -464,6 +487,6 @@ void qmso_merge(uint32_t *keys, uint32_t *vals, size_t begin1, size_t end1,
 {
     qmso_counters scratch;
     arr_t a = {keys, vals, counters_or_scratch(counters, &scratch), 2};
-    merge(&a, begin1, end1, target, endtarget);
+    swap_merge(&a, begin1, end1 - begin1, target, endtarget - target - (end1 - begin1));
 }
 #endif

@@ -17,18 +17,21 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "qms_oracle.c")
 
 MUTANTS = {
-    "msort_run1_off_by_one": (
-        "merge(a, begin + q, begin + 2 * q, target, target + n); /* R3 */",
-        "merge(a, begin + q, begin + n, target, target + n); /* R3 */"),
+    "merge_first_run_off_by_one": (
+        "    swap_merge(a, src + h, h, dst, k);",
+        "    swap_merge(a, src + h, k, dst, k);"),
     "larger_side_mergesorted": (
-        "if (b - lo < (hi - lo) / 2) {",
-        "if (b - lo >= (hi - lo) / 2) {"),
+        "if (n_left < n / 2) {",
+        "if (n_left >= n / 2) {"),
     "median_of_3_missing_third_exchange": (
         "    cmp_exchange(a, lo, m); /* key[lo] <= key[m] <= key[l] */",
         "    /* dropped */"),
-    "merge_hole_wrong_cell": (
-        "        ires++;\n        assign(a, from, ires); /* next target cell into the vacated cell */",
-        "        assign(a, from, ires); /* next target cell into the vacated cell */\n        ires++;"),
+    "merge_takes_wrong_head": (
+        "            swap_ij(a, o, y);\n            y++;",
+        "            swap_ij(a, o, y);\n            x++;"),
+    "merge_window_run_misplaced": (
+        "size_t x = x0, y = w + nx, o = w;",
+        "size_t x = x0, y = w + ny, o = w;"),
     "total_order_positive_bit": (
         "return (u & KEY_SIGN) ? ~u : (u | KEY_SIGN);",
         "return (u & KEY_SIGN) ? ~u : u;"),
@@ -48,8 +51,8 @@ MUTANTS = {
         "            clever_quicksort(a, lo, b);\n            lo = b + 1;",
         "            clever_quicksort(a, lo, b + 1);\n            lo = b + 1;"),
     "x_joint_movement_short": (
-        "        for (size_t i = 0; i < n; i++) swap_ij(a, begin + i, target + i);\n        return;\n    }\n    size_t q",
-        "        for (size_t i = 0; i + 1 < n; i++) swap_ij(a, begin + i, target + i);\n        return;\n    }\n    size_t q"),
+        "        swap_blocks(a, src, dst, n);",
+        "        swap_blocks(a, src, dst, n - 1);"),
     "partition_scan_skips_element": (
         "        swap_ij(a, i, j);\n        i++;\n        j--;",
         "        swap_ij(a, i, j);\n        i += 2;\n        j--;"),

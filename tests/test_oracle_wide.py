@@ -95,8 +95,7 @@ def test_segments_u64():
 def test_move_counter_swap_is_three_moves():
     """Experiments section: a swap of two elements counts as three moves.
     msort of one element into a target cell is exactly one swap; a merge of
-    one run1 element into an empty run2 is the hole technique's save, move
-    and close: also three moves."""
+    one run1 element into an empty run2 is one exchange: also three moves."""
     x = np.array([5, 9], dtype=np.uint32)
     k, _, c = oracle.msort(x, 0, 1, 1)
     assert k.tolist() == [9, 5] and c.moves == 3 and c.comparisons == 0
