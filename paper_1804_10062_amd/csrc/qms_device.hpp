@@ -190,6 +190,7 @@ struct TaskRef {
     uint32_t base = 0;             // pre[0] (a sub-range of a longer table; A > 1)
     T one;               // the segment itself when A == 1
     const uint32_t *dyn = nullptr; // device-sized: the number of work items
+    const uint32_t *dyn_A = nullptr;  // device-sized: the number of segments (else A)
 };
 
 // Work items of a launch: the plan's count when device-sized, else the
@@ -219,7 +220,7 @@ __device__ __forceinline__ T task_of(const TaskRef<T> &r, uint32_t g, uint32_t *
         return r.one;
     }
     g += r.base;
-    const uint32_t a = find_task(r.pre, r.A, g);
+    const uint32_t a = find_task(r.pre, r.dyn_A ? *r.dyn_A : r.A, g);
     *local = g - r.pre[a];
     *index = a;
     return r.tab[a];

@@ -94,6 +94,8 @@ struct Workspace {
     // unsorted segments), for caps.rounds segments
     void *r_seg = nullptr;
     uint32_t *r_aseg = nullptr;
+    uint32_t *r_amap = nullptr;    // segment -> partition slot of the round
+    uint32_t *r_live[2] = {nullptr, nullptr};  // live lists of alternate rounds
     void *r_ptab = nullptr, *r_mtab = nullptr, *r_stab = nullptr;
     uint32_t *r_pre = nullptr, *r_work = nullptr, *r_status = nullptr;
 };
@@ -141,6 +143,20 @@ hipError_t launch_mom_pivot(int dt, const TaskRef<PartSeg> &tasks, uint32_t tile
 hipError_t launch_tile_sort(int dt, bool pairs, const TaskRef<SortSeg> &tasks, uint32_t tiles,
                             uint32_t overflow, double bytes, const Workspace &ws,
                             hipStream_t st);
+// One pass of the bitonic network that sorts the loop's last ranges in
+// place (qms_bitonic.hip): the mirror step of stage k, the half-cleaner
+// steps 2^hi .. 2^lo (j >= T), or the steps below T inside each tile.
+// tasks: the ranges (keys, vals, m), tiles already sorted by the base case.
+struct BitonicLaunch {
+    enum Kind : uint32_t { MIRROR = 0, COLUMNS = 1, TILE = 2 };
+    TaskRef<SortSeg> tasks;
+    uint32_t kind = 0, k = 0, lo = 0, hi = 0;
+    uint32_t items = 0;  // workgroups (the sum over the tasks of bitonic_items)
+    double bytes = 0;
+};
+// Workgroups of one range of m keys in pass L (base tile T).
+uint32_t bitonic_items(const BitonicLaunch &L, uint64_t m, uint32_t T);
+hipError_t launch_bitonic_pass(int dt, bool pairs, const BitonicLaunch &L, hipStream_t st);
 // One merge pass (2-way or 4-way) of the tasks listed: every task's pass at
 // binary level `level`, or with `step` the step-th pass of every task (its
 // level from its level count).  tiles: merge tiles of the listed tasks

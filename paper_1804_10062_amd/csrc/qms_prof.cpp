@@ -12,7 +12,7 @@ namespace qms {
 
 namespace {
 const char *kNames[K_NUM_CLASSES] = {"tile_sort", "merge_split", "merge", "part_count",
-                                     "part_scan", "part_split", "part_swap"};
+                                     "part_scan", "part_split", "part_swap", "final_x"};
 
 struct Rec {
     int cls;

@@ -14,6 +14,7 @@ enum KernelClass : int {
     K_PART_SCAN,      // partition: scans (pass A, and pass B when it runs)
     K_PART_SPLIT,     // partition: chunk boundary positions
     K_PART_SWAP,      // partition: rank-matched exchange
+    K_FINAL,          // the bitonic network of the loop's last ranges
     K_NUM_CLASSES
 };
 

@@ -65,6 +65,8 @@ enum WorkSlot : int {
     W_STEP0,       // merge tiles of 4-way (or 2-way) step k: W_STEP0 + k
     W_ERRORS = W_STEP0 + kMaxLevels,  // inconsistent counts, passes beyond the schedule
     W_LEFT,        // segments still in the loop at the end of the schedule
+    W_LIVE,        // entries of the live list the next round reads
+    W_MOM_SEGS,    // segments in the median-of-medians table
     W_COUNT_SLOTS
 };
 static_assert(W_COUNT_SLOTS <= 64, "work counters fit their array");
@@ -97,6 +99,11 @@ struct PlanArgs {
 struct PlanPtrs {
     DevSeg *seg;
     uint32_t *aseg;                // active index -> segment
+    uint32_t *amap;                // segment -> active index (entries of active segments)
+    // the segments still in the loop (active, or waiting for the base case),
+    // compacted by each round's side kernel; nullptr in: every segment
+    const uint32_t *live_in;
+    uint32_t *live_out;
     PartSeg *ptab, *mtab;
     SortSeg *stab;
     uint32_t *p_tiles, *p_scan, *p_mom, *p_wa, *p_ca, *p_wb, *p_cb, *p_base, *p_m2;
@@ -122,13 +129,6 @@ __device__ __forceinline__ uint32_t scan_carry(uint32_t v, uint32_t *tmp, uint32
     return pre;
 }
 
-// Fill the prefix entries from `from` to `upto` (inclusive) with `total`, so
-// that a lookup over an upper bound of segments never lands past the plan.
-__device__ __forceinline__ void pad_prefix(uint32_t *pre, uint32_t from, uint32_t upto,
-                                           uint32_t total) {
-    for (uint32_t i = from + threadIdx.x; i <= upto; i += blockDim.x) pre[i] = total;
-}
-
 // ---- init: segment states from the offsets ------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_rounds_init(DevSeg *seg, const uint64_t *offsets,
                                                         uint32_t j0, uint32_t nseg,
@@ -151,114 +151,222 @@ __global__ __launch_bounds__(kBlock) void k_rounds_init(DevSeg *seg, const uint6
         for (uint32_t i = threadIdx.x; i < W_COUNT_SLOTS; i += kBlock) work[i] = 0;
 }
 
-// ---- plan of the partition: table, tile / scan / median-of-medians prefixes ----------
-__global__ __launch_bounds__(kPlanThreads) void k_rounds_plan(PlanArgs A, PlanPtrs P) {
-    __shared__ uint32_t tmp[kPlanThreads / kWave + 1];
-    uint32_t c_act = 0, c_tiles = 0, c_scan = 0, c_mom = 0, c_mom_tiles = 0, c_chunk = 0;
-    for (uint32_t base = 0; base < A.nseg; base += kPlanThreads) {
-        const uint32_t j = base + threadIdx.x;
-        DevSeg d{};
-        bool act = false;
-        if (j < A.nseg) {
-            d = P.seg[j];
-            act = (d.flags & DS_ACTIVE) != 0;
-        }
-        const uint32_t s = act ? d.hi - d.lo : 0;
-        const uint32_t nt = act ? (s + A.TP - 1) / A.TP : 0;
-        const bool mom = act && (A.force_mom || (d.flags & DS_MOM));
-        const uint32_t ia = scan_carry(act ? 1u : 0u, tmp, &c_act);
-        const uint32_t toff = scan_carry(nt, tmp, &c_tiles);
-        const uint32_t soff = scan_carry(act ? scan_a_groups(nt, A.scan_nth) : 0u, tmp, &c_scan);
-        const uint32_t coff = scan_carry(act ? (s + 4095) / 4096 + 2 : 0u, tmp, &c_chunk);
-        const uint32_t im = scan_carry(mom ? 1u : 0u, tmp, &c_mom);
-        const uint32_t moff = scan_carry(mom ? mom_tiles_of(s) : 0u, tmp, &c_mom_tiles);
-        if (act) {
-            const PartSeg g{d.keys, d.vals, d.lo, s, toff, nt, coff, ia,
-                            mom ? kPivotMoM : 0u, im};
-            P.ptab[ia] = g;
-            P.aseg[ia] = j;
-            P.p_tiles[ia] = toff;
-            P.p_scan[ia] = soff;
-            if (mom) {
-                P.mtab[im] = g;
-                P.p_mom[im] = moff;
-                uint64_t *meta = P.meta + (uint64_t)ia * M_COUNT;
-                const uint64_t c = s / 3;
-                meta[M_MOM_RANK] = (c - 1) / 2;
-                meta[M_MOM_PREFIX] = 0;
-                meta[M_MOM_DONE] = 0;
-            }
+// ---- one-pass scans over per-thread blocks ----------------------------------------
+// The plan kernels run in one workgroup over up to a few ten thousand
+// segments.  Each thread takes a contiguous block of them, sums its counts
+// in a first pass, and all counts are scanned together (one barrier for the
+// wave totals); a second pass over the same block writes the tables from
+// the thread's offsets.  Loads are issued kGroup segments at a time, so a
+// block costs a few memory latencies, not one per segment.
+constexpr int kPlanWaves = kPlanThreads / kWave;
+constexpr uint32_t kGroup = 4;
+
+// Exclusive scan across the block (thread order) of the first n <= N of
+// the N values of every thread; v gets the prefixes, tot the block totals.
+// lds: N * kPlanWaves words.  Every thread of the block calls it.
+template <int N>
+__device__ __forceinline__ void block_scan_n(uint32_t (&v)[N], uint32_t (&tot)[N], uint32_t n,
+                                             uint32_t *lds) {
+    const uint32_t lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+    uint32_t inc[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        inc[i] = 0;
+        if ((uint32_t)i < n) {
+            inc[i] = wave_inclusive_scan(v[i]);
+            if (lane == kWave - 1) lds[i * kPlanWaves + wave] = inc[i];
         }
     }
-    // entries past the last segment hold the totals (lookups over the
-    // launch's upper bound of segments stop there)
-    pad_prefix(P.p_tiles, c_act, A.nseg + 1, c_tiles);
-    pad_prefix(P.p_scan, c_act, A.nseg + 1, c_scan);
-    pad_prefix(P.p_mom, c_mom, A.nseg + 1, c_mom_tiles);
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        uint32_t before = 0, all = 0;
+        if ((uint32_t)i < n) {
+            for (uint32_t w = 0; w < (uint32_t)kPlanWaves; ++w) {
+                const uint32_t t = lds[i * kPlanWaves + w];
+                before += w < wave ? t : 0u;
+                all += t;
+            }
+        }
+        v[i] = (uint32_t)i < n ? before + inc[i] - v[i] : 0u;
+        tot[i] = all;
+    }
+    __syncthreads();  // the LDS may be reused
+}
+
+// The block [*a0, *a1) of entries of a list of `count` entries that this
+// thread owns.
+__device__ __forceinline__ void owned_block(uint32_t count, uint32_t *a0, uint32_t *a1) {
+    const uint32_t per = (count + kPlanThreads - 1) / kPlanThreads;
+    const uint32_t b = threadIdx.x * per;
+    *a0 = b < count ? b : count;
+    *a1 = b + per < count ? b + per : count;
+}
+
+// ---- plan of the partition: table, tile / scan / median-of-medians prefixes ----------
+// Counts of one segment: partition slot, tiles, pass-A scan workgroups,
+// exchange chunks, median-of-medians slot, its histogram tiles.
+enum PlanVal { PV_ACT = 0, PV_TILES, PV_SCAN, PV_CHUNK, PV_MOM, PV_MOM_TILES, PV_N };
+
+__device__ __forceinline__ void plan_counts(const PlanArgs &A, const DevSeg &d,
+                                            uint32_t (&c)[PV_N]) {
+    const bool act = (d.flags & DS_ACTIVE) != 0;
+    const uint32_t s = act ? d.hi - d.lo : 0;
+    const uint32_t nt = act ? (s + A.TP - 1) / A.TP : 0;
+    const bool mom = act && (A.force_mom || (d.flags & DS_MOM));
+    c[PV_ACT] = act ? 1u : 0u;
+    c[PV_TILES] = nt;
+    c[PV_SCAN] = act ? scan_a_groups(nt, A.scan_nth) : 0u;
+    c[PV_CHUNK] = act ? (s + 4095) / 4096 + 2 : 0u;
+    c[PV_MOM] = mom ? 1u : 0u;
+    c[PV_MOM_TILES] = mom ? mom_tiles_of(s) : 0u;
+}
+
+__global__ __launch_bounds__(kPlanThreads) void k_rounds_plan(PlanArgs A, PlanPtrs P) {
+    __shared__ uint32_t lds[PV_N * kPlanWaves];
+    const uint32_t n_live = P.live_in ? P.work[W_LIVE] : A.nseg;
+    uint32_t a0, a1;
+    owned_block(n_live, &a0, &a1);
+    uint32_t off[PV_N] = {}, tot[PV_N];
+    for (uint32_t g = a0; g < a1; g += kGroup) {
+        DevSeg d[kGroup];
+#pragma unroll
+        for (uint32_t u = 0; u < kGroup; ++u)
+            if (g + u < a1) d[u] = P.seg[P.live_in ? P.live_in[g + u] : g + u];
+#pragma unroll
+        for (uint32_t u = 0; u < kGroup; ++u)
+            if (g + u < a1) {
+                uint32_t c[PV_N];
+                plan_counts(A, d[u], c);
+#pragma unroll
+                for (int i = 0; i < PV_N; ++i) off[i] += c[i];
+            }
+    }
+    block_scan_n<PV_N>(off, tot, PV_N, lds);
+    for (uint32_t g = a0; g < a1; g += kGroup) {
+        uint32_t jj[kGroup];
+        DevSeg d[kGroup];
+#pragma unroll
+        for (uint32_t u = 0; u < kGroup; ++u)
+            if (g + u < a1) {
+                jj[u] = P.live_in ? P.live_in[g + u] : g + u;
+                d[u] = P.seg[jj[u]];
+            }
+#pragma unroll
+        for (uint32_t u = 0; u < kGroup; ++u) {
+            if (g + u >= a1) continue;
+            uint32_t c[PV_N];
+            plan_counts(A, d[u], c);
+            if (c[PV_ACT]) {
+                const uint32_t ia = off[PV_ACT], im = off[PV_MOM];
+                const uint32_t s = d[u].hi - d[u].lo;
+                const PartSeg pg{d[u].keys, d[u].vals,         d[u].lo, s,
+                                 off[PV_TILES], c[PV_TILES], off[PV_CHUNK], ia,
+                                 c[PV_MOM] ? kPivotMoM : 0u, im};
+                P.ptab[ia] = pg;
+                P.aseg[ia] = jj[u];
+                P.amap[jj[u]] = ia;
+                P.p_tiles[ia] = off[PV_TILES];
+                P.p_scan[ia] = off[PV_SCAN];
+                if (c[PV_MOM]) {
+                    P.mtab[im] = pg;
+                    P.p_mom[im] = off[PV_MOM_TILES];
+                    uint64_t *meta = P.meta + (uint64_t)ia * M_COUNT;
+                    const uint64_t cm = s / 3;
+                    meta[M_MOM_RANK] = (cm - 1) / 2;
+                    meta[M_MOM_PREFIX] = 0;
+                    meta[M_MOM_DONE] = 0;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < PV_N; ++i) off[i] += c[i];
+        }
+    }
+    const uint32_t c_act = tot[PV_ACT], c_mom = tot[PV_MOM];
     if (threadIdx.x == 0) {
         // a padding entry that no item reaches
         const PartSeg none{nullptr, nullptr, 0, 0, 0, 0, 0, 0, 0, 0};
         P.ptab[c_act] = none;
         P.mtab[c_mom] = none;
-        const bool fits = c_tiles <= A.cap_tiles && c_chunk <= A.cap_chunks;
+        const bool fits = tot[PV_TILES] <= A.cap_tiles && tot[PV_CHUNK] <= A.cap_chunks;
         P.work[W_ACTIVE] = c_act;
-        P.work[W_TILES] = fits ? c_tiles : 0u;
-        P.work[W_SCAN] = fits ? c_scan : 0u;
-        P.work[W_MOM] = fits ? c_mom_tiles : 0u;
+        P.work[W_MOM_SEGS] = c_mom;
+        P.work[W_TILES] = fits ? tot[PV_TILES] : 0u;
+        P.work[W_SCAN] = fits ? tot[PV_SCAN] : 0u;
+        P.work[W_MOM] = fits ? tot[PV_MOM_TILES] : 0u;
         if (!fits) atomicAdd(&P.work[W_ERRORS], 1u);
     }
 }
 
 // ---- plan of the exchanges: chunks of pass A, bounds of pass B ---------------------
+enum SwapVal { SV_WA = 0, SV_CA, SV_WB, SV_CB, SV_BAD, SV_N };
+
+__device__ __forceinline__ void swap_counts(const PlanArgs &A, uint64_t s, uint64_t c_lt,
+                                            uint64_t c_eq, uint64_t X, uint32_t (&c)[SV_N]) {
+#pragma unroll
+    for (int i = 0; i < SV_N; ++i) c[i] = 0;
+    if ((c_eq == 0 && c_lt == 0) || c_lt + c_eq > s) {
+        c[SV_BAD] = 1;
+        return;
+    }
+    const uint64_t nch = chunk_count(X, s, A.span);
+    c[SV_CA] = (uint32_t)nch;
+    c[SV_WA] = nch > 1 ? (uint32_t)(2 * (nch - 1)) : 0u;
+    // pass B pairs are at most min(#==, #>)
+    const uint64_t gt = s - c_lt - c_eq;
+    const uint64_t xb = c_eq < gt ? c_eq : gt;
+    if (xb > 0) {
+        const uint64_t full = (xb + kRankChunk - 1) / kRankChunk;
+        const uint64_t target = (s + A.span - 1) / A.span;
+        const uint64_t nb = std::min<uint64_t>(xb, std::max(full, target));
+        c[SV_CB] = (uint32_t)nb;
+        c[SV_WB] = nb > 1 ? (uint32_t)(2 * (nb - 1)) : 0u;
+    }
+}
+
 __global__ __launch_bounds__(kPlanThreads) void k_rounds_plan_swap(PlanArgs A, PlanPtrs P) {
-    __shared__ uint32_t tmp[kPlanThreads / kWave + 1];
+    __shared__ uint32_t lds[SV_N * kPlanWaves];
     const uint32_t act = P.work[W_ACTIVE];
     const bool ok = P.work[W_TILES] != 0 || act == 0;
-    uint32_t c_wa = 0, c_ca = 0, c_wb = 0, c_cb = 0;
-    for (uint32_t base = 0; base < act; base += kPlanThreads) {
-        const uint32_t a = base + threadIdx.x;
-        uint32_t wa = 0, ca = 0, wb = 0, cb = 0;
-        if (a < act && ok) {
-            const uint64_t s = P.ptab[a].s;
-            const uint64_t c_lt = P.res[4 * a], c_eq = P.res[4 * a + 1], X = P.res[4 * a + 2];
-            if ((c_eq == 0 && c_lt == 0) || c_lt + c_eq > s) {
-                atomicAdd(&P.work[W_ERRORS], 1u);
-            } else {
-                const uint64_t nch = chunk_count(X, s, A.span);
-                ca = (uint32_t)nch;
-                wa = nch > 1 ? (uint32_t)(2 * (nch - 1)) : 0u;
-                // pass B pairs are at most min(#==, #>)
-                const uint64_t gt = s - c_lt - c_eq;
-                const uint64_t xb = c_eq < gt ? c_eq : gt;
-                if (xb > 0) {
-                    const uint64_t full = (xb + kRankChunk - 1) / kRankChunk;
-                    const uint64_t target = (s + A.span - 1) / A.span;
-                    const uint64_t nb = std::min<uint64_t>(xb, std::max(full, target));
-                    cb = (uint32_t)nb;
-                    wb = nb > 1 ? (uint32_t)(2 * (nb - 1)) : 0u;
+    uint32_t a0, a1;
+    owned_block(ok ? act : 0u, &a0, &a1);
+    uint32_t off[SV_N] = {}, tot[SV_N];
+    for (int pass = 0; pass < 2; ++pass) {
+        if (pass == 1) block_scan_n<SV_N>(off, tot, SV_N, lds);
+        for (uint32_t g = a0; g < a1; g += kGroup) {
+            uint64_t s[kGroup], lt[kGroup], eq[kGroup], X[kGroup];
+#pragma unroll
+            for (uint32_t u = 0; u < kGroup; ++u)
+                if (g + u < a1) {
+                    const uint32_t a = g + u;
+                    s[u] = P.ptab[a].s;
+                    lt[u] = P.res[4 * a];
+                    eq[u] = P.res[4 * a + 1];
+                    X[u] = P.res[4 * a + 2];
                 }
+#pragma unroll
+            for (uint32_t u = 0; u < kGroup; ++u) {
+                if (g + u >= a1) continue;
+                uint32_t c[SV_N];
+                swap_counts(A, s[u], lt[u], eq[u], X[u], c);
+                if (pass == 1) {
+                    const uint32_t a = g + u;
+                    P.p_wa[a] = off[SV_WA];
+                    P.p_ca[a] = off[SV_CA];
+                    P.p_wb[a] = off[SV_WB];
+                    P.p_cb[a] = off[SV_CB];
+                }
+#pragma unroll
+                for (int i = 0; i < SV_N; ++i) off[i] += c[i];
             }
         }
-        const uint32_t owa = scan_carry(wa, tmp, &c_wa);
-        const uint32_t oca = scan_carry(ca, tmp, &c_ca);
-        const uint32_t owb = scan_carry(wb, tmp, &c_wb);
-        const uint32_t ocb = scan_carry(cb, tmp, &c_cb);
-        if (a < act) {
-            P.p_wa[a] = owa;
-            P.p_ca[a] = oca;
-            P.p_wb[a] = owb;
-            P.p_cb[a] = ocb;
-        }
     }
-    pad_prefix(P.p_wa, act, A.nseg + 1, c_wa);
-    pad_prefix(P.p_ca, act, A.nseg + 1, c_ca);
-    pad_prefix(P.p_wb, act, A.nseg + 1, c_wb);
-    pad_prefix(P.p_cb, act, A.nseg + 1, c_cb);
     if (threadIdx.x == 0) {
-        P.work[W_SPLIT_A] = c_wa;
-        P.work[W_SWAP_A] = c_ca;
-        P.work[W_SPLIT_B] = c_wb;
-        P.work[W_SWAP_B] = c_cb;
+        P.work[W_SPLIT_A] = tot[SV_WA];
+        P.work[W_SWAP_A] = tot[SV_CA];
+        P.work[W_SPLIT_B] = tot[SV_WB];
+        P.work[W_SWAP_B] = tot[SV_CB];
+        if (tot[SV_BAD]) atomicAdd(&P.work[W_ERRORS], 1u);
     }
 }
 
@@ -268,126 +376,161 @@ __global__ __launch_bounds__(kPlanThreads) void k_rounds_plan_swap(PlanArgs A, P
 // its buffer; the loop keeps the larger side (Fig. 2 sort()).  A kept range
 // of at most T0 keys waits for the base case, which runs in the next round's
 // sort launches (it still holds this round's buffer).  Segments whose range
-// waited since the last round get their base-case task now.
+// waited since the last round get their base-case task now.  The segments
+// left in the loop form the next round's live list.
+enum SideVal { SD_TASK = 0, SD_BASE, SD_SPLIT, SD_M2, SD_LIVE, SD_BAD, SD_STEP0, SD_N = SD_STEP0 + kMaxLevels };
+
+struct SideOut {
+    DevSeg d;     // the segment's new state
+    SortSeg t;    // its Mergesort (or base-case) task, if emit
+    bool emit;
+    bool write;   // d changed
+};
+
+__device__ __forceinline__ SideOut side_of(const PlanArgs &A, const PlanPtrs &P, DevSeg d,
+                                           bool ok, uint32_t lt_eq[2], uint32_t (&c)[SD_N]) {
+    SideOut o{};
+    o.d = d;
+    SortSeg &t = o.t;
+    const uint64_t ew = A.ew;
+    uint32_t bad = 0;
+    if ((d.flags & DS_ACTIVE) && ok) {
+        const uint32_t s = d.hi - d.lo;
+        const uint32_t c_lt = lt_eq[0], c_eq = lt_eq[1];
+        const uint32_t b1 = d.lo + c_lt, b2 = b1 + c_eq;
+        const uint32_t mL = c_lt, mR = d.hi - b2;
+        o.write = true;
+        if ((c_eq == 0 && c_lt == 0) || (uint64_t)c_lt + c_eq > s) {
+            // inconsistent counts (the exchange plan skipped this range
+            // too): leave the segment, report it
+            ++bad;
+            o.d.flags = 0;
+        } else {
+            if (mL <= mR) {
+                t.keys = d.keys + ew * d.lo;
+                t.vals = d.vals ? d.vals + d.lo : nullptr;
+                t.bkeys = d.keys + ew * b2;
+                t.bvals = d.vals ? d.vals + b2 : nullptr;
+                t.m = mL;
+                o.d.lo = b2;
+            } else {
+                t.keys = d.keys + ew * b2;
+                t.vals = d.vals ? d.vals + b2 : nullptr;
+                t.bkeys = d.keys + ew * (b1 - mR);
+                t.bvals = d.vals ? d.vals + (b1 - mR) : nullptr;
+                t.m = mR;
+                o.d.hi = b1;
+            }
+            // run width and levels (as the host-driven loop sets them)
+            t.w0 = A.R0;
+            t.L = t.m > A.R0 ? ceil_log2_dev((t.m + A.R0 - 1) / A.R0) : 0;
+            if (A.auto_r0 && A.four_way && !A.wide && (t.L & 1u)) {
+                t.w0 = A.R0 / 2;
+                t.L = t.m > t.w0 ? ceil_log2_dev((t.m + t.w0 - 1) / t.w0) : 0;
+            }
+            t.two_way = A.four_way ? 0u : 1u;
+            o.emit = t.m > 1;
+            // HybridQuickMergesort, delta = 1/16: an unbalanced split makes
+            // the next pivot the median of the medians of three
+            const bool unbalanced = (uint64_t)(mL < mR ? mL : mR) * 16 < s;
+            const uint32_t s2 = o.d.hi - o.d.lo;
+            o.d.flags = s2 > A.T0 ? (DS_ACTIVE | (unbalanced ? DS_MOM : 0u))
+                                  : (s2 > 1 ? DS_FINAL : 0u);
+        }
+    } else if (d.flags & DS_FINAL) {
+        // the base case in place on the whole remaining range
+        t.keys = d.keys + ew * d.lo;
+        t.vals = d.vals ? d.vals + d.lo : nullptr;
+        t.m = d.hi - d.lo;
+        t.L = 0;
+        t.w0 = A.T0;
+        o.emit = true;
+        o.d.flags = 0;
+        o.write = true;
+    }
+    const uint32_t steps_needed = !o.emit ? 0u : t.two_way ? t.L : t.L / 2;  // 4-way passes after the first
+    bad += o.emit && steps_needed > A.steps;
+    bad += o.emit && !t.two_way && (t.L & 1u) && !A.first2;
+    const uint32_t mt = o.emit ? (t.m + kMergeTile - 1) / kMergeTile : 0u;
+    c[SD_TASK] = o.emit ? 1u : 0u;
+    c[SD_BASE] = o.emit ? (t.m + A.T0 - 1) / A.T0 : 0u;
+    c[SD_SPLIT] = mt;
+    // the 2-way first pass of a 4-way Mergesort with an odd level count
+    c[SD_M2] = o.emit && !t.two_way && (t.L & 1u) ? mt : 0u;
+    c[SD_LIVE] = o.d.flags != 0 ? 1u : 0u;
+    c[SD_BAD] = bad;
+#pragma unroll
+    for (int k = 0; k < kMaxLevels; ++k) c[SD_STEP0 + k] = (uint32_t)k < steps_needed ? mt : 0u;
+    return o;
+}
+
 __global__ __launch_bounds__(kPlanThreads) void k_rounds_side(PlanArgs A, PlanPtrs P) {
-    __shared__ uint32_t tmp[kPlanThreads / kWave + 1];
+    __shared__ uint32_t lds[SD_N * kPlanWaves];
     // with no partition this round, or one whose plan did not fit, ranges in
     // the loop stay as they are
     const bool ok = A.partitioned && (P.work[W_TILES] != 0 || P.work[W_ACTIVE] == 0);
-    uint32_t c_task = 0, c_base = 0, c_split = 0, c_m2 = 0;
-    uint32_t c_step[kMaxLevels];
-    for (uint32_t k = 0; k < A.steps; ++k) c_step[k] = 0;
-    uint32_t bad = 0;
-    for (uint32_t base = 0; base < A.nseg; base += kPlanThreads) {
-        const uint32_t j = base + threadIdx.x;
-        SortSeg t{};
-        bool emit = false;
-        if (j < A.nseg) {
-            DevSeg d = P.seg[j];
-            const uint64_t ew = A.ew;
-            if ((d.flags & DS_ACTIVE) && ok) {
-                // the segment's slot in this round's partition table
-                const uint32_t s = d.hi - d.lo;
-                uint32_t a = 0;
-                {
-                    // aseg is sorted (the plan compacts in segment order)
-                    uint32_t lo = 0, hi = P.work[W_ACTIVE];
-                    while (lo < hi) {
-                        const uint32_t mid = (lo + hi) >> 1;
-                        if (P.aseg[mid] < j) lo = mid + 1;
-                        else hi = mid;
+    const uint32_t n_live = P.live_in ? P.work[W_LIVE] : A.nseg;
+    const uint32_t nv = SD_STEP0 + A.steps;  // values to scan
+    uint32_t a0, a1;
+    owned_block(n_live, &a0, &a1);
+    uint32_t off[SD_N] = {}, tot[SD_N];
+    for (int pass = 0; pass < 2; ++pass) {
+        if (pass == 1) block_scan_n<SD_N>(off, tot, nv, lds);
+        for (uint32_t g = a0; g < a1; g += kGroup) {
+            uint32_t jj[kGroup];
+            DevSeg d[kGroup];
+            uint32_t le[kGroup][2];
+#pragma unroll
+            for (uint32_t u = 0; u < kGroup; ++u)
+                if (g + u < a1) {
+                    jj[u] = P.live_in ? P.live_in[g + u] : g + u;
+                    d[u] = P.seg[jj[u]];
+                }
+#pragma unroll
+            for (uint32_t u = 0; u < kGroup; ++u)
+                if (g + u < a1 && (d[u].flags & DS_ACTIVE) && ok) {
+                    const uint32_t ia = P.amap[jj[u]];
+                    le[u][0] = P.res[4 * ia];
+                    le[u][1] = P.res[4 * ia + 1];
+                }
+#pragma unroll
+            for (uint32_t u = 0; u < kGroup; ++u) {
+                if (g + u >= a1) continue;
+                uint32_t c[SD_N];
+                const SideOut o = side_of(A, P, d[u], ok, le[u], c);
+                if (pass == 1) {
+                    if (o.write) P.seg[jj[u]] = o.d;
+                    if (c[SD_LIVE]) P.live_out[off[SD_LIVE]] = jj[u];
+                    if (o.emit) {
+                        const uint32_t idx = off[SD_TASK];
+                        SortSeg t = o.t;
+                        t.split_off = off[SD_SPLIT];
+                        P.stab[idx] = t;
+                        P.p_base[idx] = off[SD_BASE];
+                        P.p_m2[idx] = off[SD_M2];
+#pragma unroll
+                        for (uint32_t k = 0; k < (uint32_t)kMaxLevels; ++k)
+                            if (k < A.steps) P.p_step[k * (A.nseg + 2) + idx] = off[SD_STEP0 + k];
                     }
-                    a = lo;
                 }
-                const uint32_t c_lt = P.res[4 * a], c_eq = P.res[4 * a + 1];
-                const uint32_t b1 = d.lo + c_lt, b2 = b1 + c_eq;
-                const uint32_t mL = c_lt, mR = d.hi - b2;
-                if ((c_eq == 0 && c_lt == 0) || (uint64_t)c_lt + c_eq > s) {
-                    // inconsistent counts (the exchange plan skipped this
-                    // range too): leave the segment, report it
-                    ++bad;
-                    d.flags = 0;
-                    P.seg[j] = d;
-                } else if (mL <= mR) {
-                    t.keys = d.keys + ew * d.lo;
-                    t.vals = d.vals ? d.vals + d.lo : nullptr;
-                    t.bkeys = d.keys + ew * b2;
-                    t.bvals = d.vals ? d.vals + b2 : nullptr;
-                    t.m = mL;
-                    d.lo = b2;
-                } else {
-                    t.keys = d.keys + ew * b2;
-                    t.vals = d.vals ? d.vals + b2 : nullptr;
-                    t.bkeys = d.keys + ew * (b1 - mR);
-                    t.bvals = d.vals ? d.vals + (b1 - mR) : nullptr;
-                    t.m = mR;
-                    d.hi = b1;
-                }
-                // run width and levels (as the host-driven loop sets them)
-                t.w0 = A.R0;
-                t.L = t.m > A.R0 ? ceil_log2_dev((t.m + A.R0 - 1) / A.R0) : 0;
-                if (A.auto_r0 && A.four_way && !A.wide && (t.L & 1u)) {
-                    t.w0 = A.R0 / 2;
-                    t.L = t.m > t.w0 ? ceil_log2_dev((t.m + t.w0 - 1) / t.w0) : 0;
-                }
-                t.two_way = A.four_way ? 0u : 1u;
-                emit = t.m > 1;
-                // HybridQuickMergesort, delta = 1/16: an unbalanced split makes
-                // the next pivot the median of the medians of three
-                const bool unbalanced = (uint64_t)(mL < mR ? mL : mR) * 16 < s;
-                const uint32_t s2 = d.hi - d.lo;
-                d.flags = s2 > A.T0 ? (DS_ACTIVE | (unbalanced ? DS_MOM : 0u))
-                                    : (s2 > 1 ? DS_FINAL : 0u);
-                P.seg[j] = d;
-            } else if (d.flags & DS_FINAL) {
-                // the base case in place on the whole remaining range
-                t.keys = d.keys + ew * d.lo;
-                t.vals = d.vals ? d.vals + d.lo : nullptr;
-                t.m = d.hi - d.lo;
-                t.L = 0;
-                t.w0 = A.T0;
-                emit = true;
-                d.flags = 0;
-                P.seg[j] = d;
+#pragma unroll
+                for (int i = 0; i < SD_N; ++i) off[i] += c[i];
             }
         }
-        const uint32_t steps_needed = !emit ? 0u
-                                      : t.two_way ? t.L
-                                                  : t.L / 2;  // 4-way passes after the first
-        bad += emit && steps_needed > A.steps;
-        bad += emit && !t.two_way && (t.L & 1u) && !A.first2;
-        const uint32_t idx = scan_carry(emit ? 1u : 0u, tmp, &c_task);
-        const uint32_t obase = scan_carry(emit ? (t.m + A.T0 - 1) / A.T0 : 0u, tmp, &c_base);
-        const uint32_t mt = emit ? (t.m + kMergeTile - 1) / kMergeTile : 0u;
-        const uint32_t osplit = scan_carry(mt, tmp, &c_split);
-        // the 2-way first pass of a 4-way Mergesort with an odd level count
-        const bool first2 = emit && !t.two_way && (t.L & 1u);
-        const uint32_t om2 = scan_carry(first2 ? mt : 0u, tmp, &c_m2);
-        uint32_t ostep[kMaxLevels];
-        for (uint32_t k = 0; k < A.steps; ++k)
-            ostep[k] = scan_carry(emit && k < steps_needed ? mt : 0u, tmp, &c_step[k]);
-        if (emit) {
-            t.split_off = osplit;
-            P.stab[idx] = t;
-            P.p_base[idx] = obase;
-            P.p_m2[idx] = om2;
-            for (uint32_t k = 0; k < A.steps; ++k) P.p_step[k * (A.nseg + 2) + idx] = ostep[k];
-        }
     }
-    bad = block_sum(bad, tmp);
-    pad_prefix(P.p_base, c_task, A.nseg + 1, c_base);
-    pad_prefix(P.p_m2, c_task, A.nseg + 1, c_m2);
-    for (uint32_t k = 0; k < A.steps; ++k)
-        pad_prefix(P.p_step + k * (A.nseg + 2), c_task, A.nseg + 1, c_step[k]);
+    const uint32_t c_task = tot[SD_TASK];
     if (threadIdx.x == 0) {
         SortSeg none{};
         P.stab[c_task] = none;
-        const bool fits = c_split <= A.cap_splits;
+        const bool fits = tot[SD_SPLIT] <= A.cap_splits;
         P.work[W_SORT_TASKS] = c_task;
-        P.work[W_BASE] = fits ? c_base : 0u;
-        P.work[W_MERGE2] = fits ? c_m2 : 0u;
-        for (uint32_t k = 0; k < A.steps; ++k) P.work[W_STEP0 + k] = fits ? c_step[k] : 0u;
-        if (!fits || bad) atomicAdd(&P.work[W_ERRORS], 1u);
+        P.work[W_BASE] = fits ? tot[SD_BASE] : 0u;
+        P.work[W_MERGE2] = fits ? tot[SD_M2] : 0u;
+#pragma unroll
+        for (uint32_t k = 0; k < (uint32_t)kMaxLevels; ++k)
+            if (k < A.steps) P.work[W_STEP0 + k] = fits ? tot[SD_STEP0 + k] : 0u;
+        if (!fits || tot[SD_BAD]) atomicAdd(&P.work[W_ERRORS], 1u);
+        P.work[W_LIVE] = tot[SD_LIVE];
         // the next round's plan starts from clean counts
         P.work[W_TILES] = 0;
         P.work[W_ACTIVE] = 0;
@@ -416,7 +559,7 @@ uint32_t ceil_log2_host(uint64_t x) {
 // ---- host side ------------------------------------------------------------------
 size_t rounds_state_bytes(uint32_t segs) {
     const size_t S = segs;
-    return S * sizeof(DevSeg) + S * 4 + 2 * (S + 1) * sizeof(PartSeg) +
+    return S * sizeof(DevSeg) + 4 * S * 4 + 2 * (S + 1) * sizeof(PartSeg) +
            (S + 1) * sizeof(SortSeg) + (9 + kMaxLevels) * (S + 2) * 4 + 64 * 4 + 16 * 256;
 }
 
@@ -429,6 +572,9 @@ void carve_rounds_state(Workspace *ws, char *b, uint32_t segs) {
     };
     ws->r_seg = take(S * sizeof(DevSeg));
     ws->r_aseg = (uint32_t *)take(S * 4);
+    ws->r_amap = (uint32_t *)take(S * 4);
+    ws->r_live[0] = (uint32_t *)take(S * 4);
+    ws->r_live[1] = (uint32_t *)take(S * 4);
     ws->r_ptab = take((S + 1) * sizeof(PartSeg));
     ws->r_mtab = take((S + 1) * sizeof(PartSeg));
     ws->r_stab = take((S + 1) * sizeof(SortSeg));
@@ -511,6 +657,7 @@ int sort_batch_device_rounds(int dt, bool pairs, char *keys_base, uint32_t *vals
         PlanPtrs P{};
         P.seg = (DevSeg *)ws.r_seg;
         P.aseg = ws.r_aseg;
+        P.amap = ws.r_amap;
         P.ptab = (PartSeg *)ws.r_ptab;
         P.mtab = (PartSeg *)ws.r_mtab;
         P.stab = (SortSeg *)ws.r_stab;
@@ -539,18 +686,24 @@ int sort_batch_device_rounds(int dt, bool pairs, char *keys_base, uint32_t *vals
         // for as many items as the host expects (a median-of-3 round leaves
         // a range about 11/16 of its size on average; the estimate takes
         // 3/4 and a quarter more work), then a looping launch of kOverflow
-        // workgroups for any items beyond the estimate.
-        constexpr uint32_t kOverflow = 256;
+        // workgroups for any items beyond the estimate (as many workgroups
+        // as the chip holds at once, so that an estimate that falls short
+        // still runs on every compute unit).
+        constexpr uint32_t kOverflow = 2048;
         constexpr double kShrink = 0.75, kSlack = 1.25;
         auto est = [](double x) -> uint32_t {
             return (uint32_t)std::min<double>(std::ceil(x * kSlack) + 16.0, 1u << 30);
         };
-        auto part_ref = [&](const uint32_t *prefix, uint32_t work_slot, const PartSeg *tab) {
+        // device-sized task references: the work-item count and the number
+        // of segments in the table are read from the plan's counters
+        auto part_ref = [&](const uint32_t *prefix, uint32_t work_slot, const PartSeg *tab,
+                            uint32_t count_slot = W_ACTIVE) {
             TaskRef<PartSeg> r{};
             r.tab = tab;
             r.pre = prefix;
             r.A = G + 1;  // an upper bound (>= 2: never the by-value form)
             r.dyn = P.work + work_slot;
+            r.dyn_A = P.work + count_slot;
             return r;
         };
         auto sort_ref = [&](const uint32_t *prefix, uint32_t work_slot) {
@@ -559,12 +712,17 @@ int sort_batch_device_rounds(int dt, bool pairs, char *keys_base, uint32_t *vals
             r.pre = prefix;
             r.A = G + 1;
             r.dyn = P.work + work_slot;
+            r.dyn_A = P.work + W_SORT_TASKS;
             return r;
         };
 
         std::vector<double> expect(G);  // expected range of each segment
         for (uint32_t i = 0; i < G; ++i) expect[i] = (double)len[i];
         for (uint32_t r = 0; r <= R; ++r) {
+            // live lists: every segment in the first round, then the list the
+            // previous round's side kernel compacted
+            P.live_in = r == 0 ? nullptr : ws.r_live[(r - 1) & 1];
+            P.live_out = ws.r_live[r & 1];
             // estimates of this round's work, and the bound on the largest
             // range (for the number of merge steps, which must not fall short)
             double tiles_e = 0, scan_e = 0, chunks_e = 0, active_e = 0, mom_e = 0, merge_e = 0;
@@ -584,7 +742,11 @@ int sort_batch_device_rounds(int dt, bool pairs, char *keys_base, uint32_t *vals
                     const double nt = std::ceil(x / TP);
                     tiles_e += nt;
                     scan_e += scan_a_groups((uint32_t)nt, scan_nth);
-                    chunks_e += std::ceil(x / std::max<uint32_t>(tune.chunk_span, 4096)) + 1;
+                    // exchange chunks: about s / span, or X / kRankChunk when
+                    // the X misplaced pairs (about s / 4 for keys in random
+                    // order) fill the chunks first
+                    chunks_e += std::ceil(std::max(x / std::max<uint32_t>(tune.chunk_span, 4096),
+                                                   x / 4 / kRankChunk)) + 1;
                     active_e += 1;
                     mom_e += 0.1 * mom_tiles((uint64_t)x);
                     merge_e += std::ceil(0.35 * x / kMergeTile);
@@ -603,7 +765,7 @@ int sort_batch_device_rounds(int dt, bool pairs, char *keys_base, uint32_t *vals
             if (A.partitioned) {
                 hipLaunchKernelGGL(k_rounds_plan, dim3(1), dim3(kPlanThreads), 0, st, A, P);
                 // pivots of the flagged ranges
-                e = launch_mom_pivot(dt, part_ref(P.p_mom, W_MOM, P.mtab), est(mom_e), kOverflow,
+                e = launch_mom_pivot(dt, part_ref(P.p_mom, W_MOM, P.mtab, W_MOM_SEGS), est(mom_e), kOverflow,
                                      false, ws, st);
                 if (e != hipSuccess) return hip_error(e, "median-of-medians pivot");
                 PartitionLaunch L{};

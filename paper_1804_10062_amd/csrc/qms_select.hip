@@ -72,7 +72,9 @@ __device__ __forceinline__ void mom_pick_segment(const PartSeg &g, uint32_t pass
         meta[M_MOM_PREFIX] = np;
         if (pass == last) meta[M_PIVOT] = np;
     }
-    if (b == 0) meta[M_MOM_DONE] = 0;
+    if (b == 0)
+        __hip_atomic_store(meta + M_MOM_DONE, (uint64_t)0, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Histogram of digit `pass` (the pass-th byte from the top) of the medians
@@ -113,22 +115,29 @@ __device__ __forceinline__ void mom_hist_item(TaskRef<PartSeg> tasks, uint32_t i
     }
     __syncthreads();
     const uint32_t v = h[threadIdx.x];
-    if (v != 0) atomicAdd(hist_all + (uint64_t)g.pad * 256 + threadIdx.x, v);
-    // every thread's histogram atomics are done before the count goes up
-    __threadfence();
+    // The histogram, the count of finished workgroups and the last
+    // workgroup's reads of the histogram are all agent-scope atomics, which
+    // every workgroup performs at the same coherent point; ordering them
+    // needs only that each add has been performed (its result has come back)
+    // before the count goes up.  No fence: an agent-scope fence writes back
+    // and invalidates the whole L2 of the workgroup's XCD, which serialises
+    // across the workgroups of a launch.
+    if (v != 0) {
+        const uint32_t old = __hip_atomic_fetch_add(hist_all + (uint64_t)g.pad * 256 + threadIdx.x,
+                                                    v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        asm volatile("" ::"v"(old));  // wait for the result
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        const uint64_t done = atomicAdd(
-            (unsigned long long *)(meta_all + (uint64_t)g.slot * M_COUNT + M_MOM_DONE), 1ull);
+        const uint64_t done = __hip_atomic_fetch_add(
+            meta_all + (uint64_t)g.slot * M_COUNT + M_MOM_DONE, (uint64_t)1, __ATOMIC_RELAXED,
+            __HIP_MEMORY_SCOPE_AGENT);
         h[0] = done + 1 == mom_tiles_of(g.s) ? 1u : 0u;
     }
     __syncthreads();
     const bool is_last = h[0] != 0;
     __syncthreads();  // h is reused by the next item
-    if (is_last) {
-        __threadfence();
-        mom_pick_segment(g, pass, last, meta_all, hist_all, tmp);
-    }
+    if (is_last) mom_pick_segment(g, pass, last, meta_all, hist_all, tmp);
 }
 template <class O, bool LOOP>
 __global__ __launch_bounds__(kBlock) void k_mom_hist(TaskRef<PartSeg> tasks, uint32_t first,
