@@ -51,7 +51,6 @@ WsCaps default_caps() {
     c.chunks = kCapChunks;
     c.splits = kCapSplits;
     c.groups = kCapGroups;
-    c.final_cap = kFinalCap;
     c.segs = kCapSegs;
     // one histogram per segment: a device-controlled round may give every
     // segment of a group the median-of-medians pivot
@@ -67,7 +66,6 @@ WsCaps single_array_caps(uint64_t nmax) {
     c.chunks = c.tiles + 2 + 16;
     c.splits = (nmax + kMergeTile - 1) / kMergeTile + 1 + 16;
     c.groups = c.tiles * (kPartSub / kWave);
-    c.final_cap = 0;
     c.segs = 1;
     c.mom = 1;
     c.rounds = 0;
@@ -83,9 +81,8 @@ static size_t ws_words(const WsCaps &c) {
 
 size_t workspace_device_bytes(const WsCaps &c) {
     const size_t meta_bytes = (size_t)c.segs * M_COUNT * sizeof(uint64_t);
-    const size_t fbuf_bytes = 2 * c.final_cap * sizeof(uint32_t);
     const size_t rounds_bytes = c.rounds ? rounds_state_bytes(c.rounds) : 0;
-    return meta_bytes + fbuf_bytes + ((c.tab_bytes + 255) & ~(size_t)255) + rounds_bytes +
+    return meta_bytes + ((c.tab_bytes + 255) & ~(size_t)255) + rounds_bytes +
            ws_words(c) * sizeof(uint32_t) + 256;
 }
 
@@ -95,8 +92,6 @@ void carve_workspace(Workspace *ws, char *block, const WsCaps &c) {
     char *b = block;
     ws->meta = (uint64_t *)b;
     b += (size_t)c.segs * M_COUNT * sizeof(uint64_t);
-    ws->fbuf = c.final_cap ? (uint32_t *)b : nullptr;  // 8-byte aligned
-    b += 2 * c.final_cap * sizeof(uint32_t);
     ws->dtab = b;
     b += (c.tab_bytes + 255) & ~(size_t)255;
     if (c.rounds) {
@@ -369,8 +364,8 @@ int qms_set_tuning(const qms_tuning *t) {
     if (bt != 0 && (bt < (uint32_t)kMergeTile || bt > kBaseTileKeys || (bt & (bt - 1)) != 0))
         return set_error(QMS_ERR_INVALID, "base_tile must be 0 or a power of two in [2048, 16384]");
     const uint32_t ft = t->final_tile;
-    if (ft < kBaseTilePairs || ft > kFinalCap || (ft & (ft - 1)) != 0)
-        return set_error(QMS_ERR_INVALID, "final_tile must be a power of two in [8192, 2^24]");
+    if (ft < kBaseTilePairs || ft > kMaxFinalTile || (ft & (ft - 1)) != 0)
+        return set_error(QMS_ERR_INVALID, "final_tile must be a power of two in [8192, 2^30]");
     std::lock_guard<std::mutex> lock(g_tuning_mutex);
     g_tuning.final_tile = ft;
     g_tuning.merge_ways = t->merge_ways;

@@ -315,7 +315,10 @@ __device__ __forceinline__ uint32_t nat_idx(uint32_t e) {
 
 // Sort one tile.  sk/sv: the tile's cells in the source region, dk/dv: in
 // the destination region (equal in place); len <= the tile size.
-template <class O, bool PAIRS>
+// MERGE_ONLY: the tile holds a bitonic sequence (padded past len with the
+// largest key); only the last stage's half-cleaners run (in place, no
+// samples).
+template <class O, bool PAIRS, bool MERGE_ONLY = false>
 __device__ __forceinline__ void tile_sort_block(typename O::K *sk, uint32_t *sv,
                                                 typename O::K *dk, uint32_t *dv, uint32_t len,
                                                 uint32_t run, bool swap,
@@ -383,7 +386,7 @@ __device__ __forceinline__ void tile_sort_block(typename O::K *sk, uint32_t *sv,
     // 3. runs of ITEMS / 2 in registers, alternating direction (fixed per
     //    register, since base is a multiple of ITEMS)
 #pragma unroll
-    for (int k = 2; k < ITEMS; k <<= 1) {
+    for (int k = 2; k < (MERGE_ONLY ? 2 : ITEMS); k <<= 1) {
 #pragma unroll
         for (int j = k >> 1; j >= 1; j >>= 1) {
 #pragma unroll
@@ -403,7 +406,7 @@ __device__ __forceinline__ void tile_sort_block(typename O::K *sk, uint32_t *sv,
     //    changes only between stages.  At the last stage every block ascends
     //    and the keys are plain again: the tile holds T / run sorted runs.
     E cur_mask = E{};
-    for (uint32_t k = ITEMS; k <= run; k <<= 1) {
+    for (uint32_t k = MERGE_ONLY ? run : ITEMS; k <= run; k <<= 1) {
         const E mask = (k == run || (base & k) == 0) ? E{} : TE::FLIP;
         const E flip = mask ^ cur_mask;
         cur_mask = mask;
@@ -526,7 +529,7 @@ __device__ __forceinline__ void tile_sort_block(typename O::K *sk, uint32_t *sv,
     for (int i = 0; i < ITEMS; ++i) s[nat_idx<ITEMS>(base + i)] = r[i];
     __syncthreads();
     static_assert((uint32_t)(NT * ITEMS) / kSampleStride <= (uint32_t)NT, "one sample per thread");
-    if (tid * kSampleStride < len)
+    if (!MERGE_ONLY && tid * kSampleStride < len)
         stg(samples + tid, TE::key(s[nat_idx<ITEMS>(tid * kSampleStride)]));
 #pragma unroll 8
     for (int q = 0; q < ITEMS; ++q) {
@@ -595,6 +598,51 @@ static hipError_t tile_sort_t(const TaskRef<SortSeg> &tasks, uint32_t tiles, uin
     if (overflow)
         hipLaunchKernelGGL((k_tile_sort<O, PAIRS, true>), dim3(overflow), dim3(kSortThreads), 0,
                            st, tasks, tiles, (K *)ws.samples[0]);
+    return hipGetLastError();
+}
+
+// The in-tile steps of the loop's final network (qms_bitonic.hip): every
+// tile of T keys of the tasks holds a bitonic sequence, and the last stage
+// of the base case's network (its half-cleaners) sorts it in place.
+template <class O, bool PAIRS>
+__global__ __launch_bounds__(kSortThreads) void k_tile_merge(TaskRef<SortSeg> tasks,
+                                                             uint32_t items) {
+    using K = typename O::K;
+    constexpr uint32_t T = base_tile_of(PAIRS, sizeof(K) == 8);
+    if (blockIdx.x >= items) return;
+    uint32_t t, a;
+    const SortSeg g = task_of(tasks, blockIdx.x, &t, &a);
+    const uint64_t t0 = (uint64_t)t * T;
+    const uint32_t len = (uint32_t)(g.m - t0 < T ? g.m - t0 : T);
+    K *k = (K *)g.keys + t0;
+    uint32_t *v = PAIRS ? g.vals + t0 : nullptr;
+    tile_sort_block<O, PAIRS, true>(k, v, k, v, len, T, false, nullptr);
+}
+
+hipError_t launch_tile_merge(int dt, bool pairs, const TaskRef<SortSeg> &tasks, uint32_t items,
+                             hipStream_t st) {
+    if (items == 0) return hipSuccess;
+    const dim3 g(items), b(kSortThreads);
+    switch (dt) {
+    case 0:
+        if (pairs) hipLaunchKernelGGL((k_tile_merge<OrdU32, true>), g, b, 0, st, tasks, items);
+        else hipLaunchKernelGGL((k_tile_merge<OrdU32, false>), g, b, 0, st, tasks, items);
+        break;
+    case 1:
+        if (pairs) hipLaunchKernelGGL((k_tile_merge<OrdF32, true>), g, b, 0, st, tasks, items);
+        else hipLaunchKernelGGL((k_tile_merge<OrdF32, false>), g, b, 0, st, tasks, items);
+        break;
+    case 2:
+        if (pairs) hipLaunchKernelGGL((k_tile_merge<OrdU64, true>), g, b, 0, st, tasks, items);
+        else hipLaunchKernelGGL((k_tile_merge<OrdU64, false>), g, b, 0, st, tasks, items);
+        break;
+    case 3:
+        if (pairs) hipLaunchKernelGGL((k_tile_merge<OrdF64, true>), g, b, 0, st, tasks, items);
+        else hipLaunchKernelGGL((k_tile_merge<OrdF64, false>), g, b, 0, st, tasks, items);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -1,0 +1,226 @@
+// qms_bitonic.hip -- the sorting algorithm X that finishes the loop's last
+// range, in place, on gfx950.
+//
+// Sec. "QuickXsort and QuickMergesort" leaves X open: QuickXsort partitions,
+// sorts one side with X while the other serves as its buffer, and continues
+// on the rest.  The loop here runs until its range holds at most final_tile
+// keys and then sorts that range with a bitonic network (QuickMergeXsort's
+// idea of handing small blocks to another algorithm, applied once at the
+// loop level): every exchange is between two cells of the range, so no
+// memory beyond the range is used, and for a range of F keys the network
+// adds O(F log^2 F) comparisons to the n lg n + O(n) of the loop, which for
+// F << n is a negligible share.
+//
+// The network is the bitonic merge-sort in its all-ascending form, which
+// sorts any length: tiles of the base tile T are sorted first (the base
+// case); stage k then merges ascending runs of 2^(k-1) into runs of 2^k by
+// comparing position i with i ^ (2^k - 1) (the mirror step) and then i with
+// i + j for j = 2^(k-2), ..., 1 (half-cleaners), all ascending.  Positions at
+// or beyond the range's end act as +infinity: a pair whose upper position
+// lies outside is left alone, so the cells past the range are never read or
+// written.  Three kernels share the work of a stage:
+//   mirror     -- the mirror step, coalesced on both sides (the partner
+//                 positions run backwards);
+//   columns    -- up to four consecutive half-cleaner steps with j >= T in
+//                 one pass: a thread holds the 2, 4, 8 or 16 elements whose
+//                 positions differ only in those bits and exchanges them in
+//                 registers; rows are read and written as contiguous runs;
+//   tile       -- the half-cleaner steps j < T inside each tile of T keys:
+//                 the last stage of the base case's network (registers,
+//                 lane exchanges and the LDS).
+// Several ranges (a batch) share each launch through task tables.
+#include "qms_device.hpp"
+#include "qms_internal.hpp"
+#include "qms_prof.hpp"
+
+namespace qms {
+
+namespace {
+
+constexpr int kBitThreads = 256;            // mirror and column kernels
+constexpr uint32_t kMirrorPer = 8;          // mirror pairs per thread
+constexpr uint32_t kMirrorChunk = kBitThreads * kMirrorPer;
+
+// ---- mirror step of stage k -------------------------------------------------------
+// Pair t (t-th position of the lower halves of the 2^k blocks) is position
+// i = (t / 2^(k-1)) * 2^k + t % 2^(k-1) and its partner i ^ (2^k - 1).
+template <class O, bool PAIRS>
+__device__ __forceinline__ void mirror_item(TaskRef<SortSeg> tasks, uint32_t item, uint32_t k) {
+    using K = typename O::K;
+    uint32_t c, a;
+    const SortSeg g = task_of(tasks, item, &c, &a);
+    K *keys = (K *)g.keys;
+    uint32_t *vals = g.vals;
+    const uint64_t m = g.m, H = 1ull << (k - 1), B = 2 * H;
+    uint64_t pi[kMirrorPer], pp[kMirrorPer];
+    K x[kMirrorPer], y[kMirrorPer];
+    bool on[kMirrorPer];
+#pragma unroll
+    for (uint32_t q = 0; q < kMirrorPer; ++q) {
+        const uint64_t t = (uint64_t)c * kMirrorChunk + (uint64_t)q * kBitThreads + threadIdx.x;
+        const uint64_t i = (t / H) * B + (t % H);
+        const uint64_t p = i ^ (B - 1);
+        on[q] = p < m;
+        pi[q] = i;
+        pp[q] = p;
+        if (on[q]) {
+            x[q] = ldg(keys + i);
+            y[q] = ldg(keys + p);
+        }
+    }
+#pragma unroll
+    for (uint32_t q = 0; q < kMirrorPer; ++q) {
+        if (!on[q] || !(O::ord(y[q]) < O::ord(x[q]))) continue;
+        keys[pi[q]] = y[q];
+        keys[pp[q]] = x[q];
+        if (PAIRS) {
+            const uint32_t u = vals[pi[q]], w = vals[pp[q]];
+            vals[pi[q]] = w;
+            vals[pp[q]] = u;
+        }
+    }
+}
+
+template <class O, bool PAIRS>
+__global__ __launch_bounds__(kBitThreads) void k_bitonic_mirror(TaskRef<SortSeg> tasks,
+                                                                uint32_t items, uint32_t k) {
+    if (blockIdx.x < items) mirror_item<O, PAIRS>(tasks, blockIdx.x, k);
+}
+
+// ---- half-cleaner steps j = 2^hi, ..., 2^lo (j >= T) ------------------------------
+// Blocks of 2^(hi+1) positions; in a block, row r (bits lo..hi) and column
+// col (bits below lo): position blk * 2^(hi+1) + r * 2^lo + col.  A thread
+// owns one column of one block and its R = 2^(hi-lo+1) rows.
+template <class O, bool PAIRS, int R>
+__device__ __forceinline__ void columns_item(TaskRef<SortSeg> tasks, uint32_t item, uint32_t lo,
+                                             uint32_t hi) {
+    using K = typename O::K;
+    uint32_t c, a;
+    const SortSeg g = task_of(tasks, item, &c, &a);
+    K *keys = (K *)g.keys;
+    uint32_t *vals = g.vals;
+    const uint64_t m = g.m;
+    const uint32_t cpb = (1u << lo) / kBitThreads;  // column chunks per block
+    const uint64_t blk = c / cpb;
+    const uint64_t col = (uint64_t)(c % cpb) * kBitThreads + threadIdx.x;
+    const uint64_t base = (blk << (hi + 1)) + col;
+    K x[R];
+    uint32_t v[R];
+    bool on[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const uint64_t i = base + ((uint64_t)r << lo);
+        on[r] = i < m;
+        x[r] = on[r] ? O::ord(ldg(keys + i)) : key_max<K>();
+        if (PAIRS) v[r] = on[r] ? ldg(vals + i) : 0u;
+    }
+#pragma unroll
+    for (int d = R / 2; d >= 1; d /= 2) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (r & d) continue;
+            // the upper element outside the range is +infinity: no exchange
+            if (on[r + d] && x[r + d] < x[r]) {
+                const K t = x[r];
+                x[r] = x[r + d];
+                x[r + d] = t;
+                if (PAIRS) {
+                    const uint32_t u = v[r];
+                    v[r] = v[r + d];
+                    v[r + d] = u;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        if (!on[r]) continue;
+        const uint64_t i = base + ((uint64_t)r << lo);
+        keys[i] = O::unord(x[r]);
+        if (PAIRS) vals[i] = v[r];
+    }
+}
+
+template <class O, bool PAIRS, int R>
+__global__ __launch_bounds__(kBitThreads) void k_bitonic_columns(TaskRef<SortSeg> tasks,
+                                                                 uint32_t items, uint32_t lo,
+                                                                 uint32_t hi) {
+    if (blockIdx.x < items) columns_item<O, PAIRS, R>(tasks, blockIdx.x, lo, hi);
+}
+
+template <class O, bool PAIRS>
+static hipError_t bitonic_t(int dt, const BitonicLaunch &L, hipStream_t st) {
+    if (L.items == 0) return hipSuccess;
+    ProfScope prof(st, K_FINAL, L.bytes);
+    switch (L.kind) {
+    case BitonicLaunch::MIRROR:
+        hipLaunchKernelGGL((k_bitonic_mirror<O, PAIRS>), dim3(L.items), dim3(kBitThreads), 0, st,
+                           L.tasks, L.items, L.k);
+        break;
+    case BitonicLaunch::COLUMNS:
+        switch (L.hi - L.lo + 1) {
+        case 1:
+            hipLaunchKernelGGL((k_bitonic_columns<O, PAIRS, 2>), dim3(L.items), dim3(kBitThreads),
+                               0, st, L.tasks, L.items, L.lo, L.hi);
+            break;
+        case 2:
+            hipLaunchKernelGGL((k_bitonic_columns<O, PAIRS, 4>), dim3(L.items), dim3(kBitThreads),
+                               0, st, L.tasks, L.items, L.lo, L.hi);
+            break;
+        case 3:
+            hipLaunchKernelGGL((k_bitonic_columns<O, PAIRS, 8>), dim3(L.items), dim3(kBitThreads),
+                               0, st, L.tasks, L.items, L.lo, L.hi);
+            break;
+        case 4:
+            hipLaunchKernelGGL((k_bitonic_columns<O, PAIRS, 16>), dim3(L.items),
+                               dim3(kBitThreads), 0, st, L.tasks, L.items, L.lo, L.hi);
+            break;
+        default:
+            return hipErrorInvalidValue;
+        }
+        break;
+    case BitonicLaunch::TILE:
+        return launch_tile_merge(dt, PAIRS, L.tasks, L.items, st);
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+uint32_t bitonic_items(const BitonicLaunch &L, uint64_t m, uint32_t T) {
+    switch (L.kind) {
+    case BitonicLaunch::MIRROR: {
+        // the lower-half positions of every 2^k block the range reaches
+        const uint64_t H = 1ull << (L.k - 1), B = 2 * H;
+        const uint64_t pairs = (m + B - 1) / B * H;
+        return (uint32_t)((pairs + kMirrorChunk - 1) / kMirrorChunk);
+    }
+    case BitonicLaunch::COLUMNS: {
+        const uint64_t blocks = (m + (1ull << (L.hi + 1)) - 1) >> (L.hi + 1);
+        return (uint32_t)(blocks * ((1ull << L.lo) / kBitThreads));
+    }
+    case BitonicLaunch::TILE:
+        return (uint32_t)((m + T - 1) / T);
+    default:
+        return 0;
+    }
+}
+
+hipError_t launch_bitonic_pass(int dt, bool pairs, const BitonicLaunch &L, hipStream_t st) {
+    switch (dt) {
+    case 0:
+        return pairs ? bitonic_t<OrdU32, true>(dt, L, st) : bitonic_t<OrdU32, false>(dt, L, st);
+    case 1:
+        return pairs ? bitonic_t<OrdF32, true>(dt, L, st) : bitonic_t<OrdF32, false>(dt, L, st);
+    case 2:
+        return pairs ? bitonic_t<OrdU64, true>(dt, L, st) : bitonic_t<OrdU64, false>(dt, L, st);
+    case 3:
+        return pairs ? bitonic_t<OrdF64, true>(dt, L, st) : bitonic_t<OrdF64, false>(dt, L, st);
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace qms

@@ -148,6 +148,85 @@ size_t tab_arena_bytes(uint32_t segs) {
 
 const std::vector<std::array<uint64_t, kScheduleWords>> &last_schedule() { return g_schedule; }
 
+// Launches of the bitonic network for ranges of at most 2^K keys whose
+// tiles of T = 2^lt keys are sorted: per stage k (lt < k <= K) the mirror
+// step, the half-cleaner steps from 2^(k-2) down to T four at a time, and
+// the steps inside the tiles.
+static std::vector<BitonicLaunch> network_passes(uint32_t K, uint32_t lt) {
+    std::vector<BitonicLaunch> v;
+    for (uint32_t k = lt + 1; k <= K; ++k) {
+        BitonicLaunch L;
+        L.kind = BitonicLaunch::MIRROR;
+        L.k = k;
+        v.push_back(L);
+        for (int hi = (int)k - 2; hi >= (int)lt; hi -= 4) {
+            L = BitonicLaunch{};
+            L.kind = BitonicLaunch::COLUMNS;
+            L.k = k;
+            L.hi = (uint32_t)hi;
+            L.lo = (uint32_t)std::max<int>((int)lt, hi - 3);
+            v.push_back(L);
+        }
+        L = BitonicLaunch{};
+        L.kind = BitonicLaunch::TILE;
+        L.k = k;
+        v.push_back(L);
+    }
+    return v;
+}
+
+// Arena bytes of the network tables for `count` ranges of at most 2^K keys.
+static size_t network_table_bytes(size_t count, uint32_t K, uint32_t lt) {
+    const size_t launches = network_passes(K, lt).size();
+    return ((count * sizeof(SortSeg) + 255) & ~(size_t)255) +
+           launches * (((count + 1) * 4 + 255) & ~(size_t)255);
+}
+
+// X at the loop level: the ranges in xf (tiles already sorted in place by
+// the base case) are finished by the bitonic network, in place.  Stage k
+// takes the ranges of more than 2^(k-1) keys (xf is sorted by size, largest
+// first, so they are a prefix of the table).
+static int final_network(int dt, bool pairs, std::vector<SortSeg> &xf, Arena &ar, uint32_t T0,
+                         double elem_bytes, hipStream_t st) {
+    if (xf.empty()) return QMS_OK;
+    std::stable_sort(xf.begin(), xf.end(),
+                     [](const SortSeg &x, const SortSeg &y) { return x.m > y.m; });
+    const uint32_t lt = ceil_log2(T0), K = ceil_log2(xf[0].m);
+    const uint32_t n = (uint32_t)xf.size();
+    const size_t mark = ar.used;
+    size_t o_tab;
+    SortSeg *tab = ar.take<SortSeg>(n, &o_tab);
+    if (!tab) return set_error(QMS_ERR_NOMEM, "task table arena too small");
+    for (uint32_t a = 0; a < n; ++a) tab[a] = xf[a];
+    std::vector<BitonicLaunch> passes = network_passes(K, lt);
+    std::vector<size_t> o_pre(passes.size(), 0);
+    for (size_t i = 0; i < passes.size(); ++i) {
+        BitonicLaunch &L = passes[i];
+        uint32_t c = 0;  // ranges in stage k: more than 2^(k-1) keys
+        while (c < n && tab[c].m > (1ull << (L.k - 1))) ++c;
+        L.tasks.A = c;
+        if (c == 0) continue;
+        L.tasks.one = tab[0];
+        uint32_t *pre = ar.take<uint32_t>(c + 1, &o_pre[i]);
+        if (!pre) return set_error(QMS_ERR_NOMEM, "task table arena too small");
+        pre[0] = 0;
+        for (uint32_t a = 0; a < c; ++a) pre[a + 1] = pre[a] + bitonic_items(L, tab[a].m, T0);
+        L.items = pre[c];
+        for (uint32_t a = 0; a < c; ++a) L.bytes += 2.0 * elem_bytes * (double)tab[a].m;
+    }
+    int rc = upload(ar, mark, st);
+    if (rc != QMS_OK) return rc;
+    for (size_t i = 0; i < passes.size(); ++i) {
+        BitonicLaunch &L = passes[i];
+        if (L.tasks.A == 0) continue;
+        L.tasks.tab = ar.dev<SortSeg>(o_tab);
+        L.tasks.pre = ar.dev<uint32_t>(o_pre[i]);
+        const hipError_t e = launch_bitonic_pass(dt, pairs, L, st);
+        if (e != hipSuccess) return hip_error(e, "final bitonic network");
+    }
+    return QMS_OK;
+}
+
 // Sort a group of segments (count <= caps.segs, total keys < 2^32).
 static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
                       hipStream_t st, bool log, const Tuning &tune) {
@@ -187,28 +266,27 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
     auto kptr = [&](const Seg &g, uint64_t off) { return g.keys + ew * off; };
     auto vptr = [&](const Seg &g, uint64_t off) { return g.vals ? g.vals + off : nullptr; };
     // TF: a range that a partition round leaves with at most TF keys leaves
-    // the loop (a recursion stopper; the paper's recursion would continue
-    // down to T0): one Mergesort finishes it with the library's fixed scratch
-    // buffer as swap space (caps.final_cap elements per workspace, whatever n
-    // is; a workspace without that buffer runs the loop down to T0).
-    // A range is handed over only while the next round's buffer has room for
-    // it; otherwise it stays in the loop, so many arrays of a batch do not
-    // queue for the buffer round after round.  An input array of at most T0
-    // keys goes to the base
-    // case in place; every larger one is partitioned at least once, so its
-    // top level is always QuickMergesort's (partition, Mergesort of one side
-    // with the other side as its buffer).
-    const uint64_t final_cap = ws.caps.final_cap;
-    const uint64_t TF = std::max<uint64_t>(T0, std::min<uint64_t>(tune.final_tile, final_cap));
+    // the loop and is sorted in place by X, a bitonic network (QuickXsort
+    // with X at the loop level; the paper's loop continues down to T0, which
+    // final_tile = T0 reproduces).  An input array of at most T0 keys goes to
+    // the base case in place; every larger one is partitioned at least once,
+    // so its top level is always QuickMergesort's (partition, Mergesort of
+    // one side with the other side as its buffer).
+    const uint64_t TF = std::max<uint64_t>(T0, tune.final_tile);
+    // a final range: the base case sorts its tiles in place (L = 0), the
+    // network finishes it if it is longer than one tile
     auto final_task = [&](const Seg &g, uint32_t lo, uint32_t s) {
-        SortSeg f{kptr(g, lo), vptr(g, lo), nullptr, nullptr, s, 0, 0, T0, 0, 0};
-        if (s > T0) set_levels(f);
-        return f;
+        return SortSeg{kptr(g, lo), vptr(g, lo), nullptr, nullptr, s, 0, 0, T0, 0, 0};
     };
+    // per-key bytes of an element (key and payload), for the profile
+    const double elem_bytes = (wide ? 8.0 : 4.0) + (pairs ? 4.0 : 0.0);
+    // the network tables of one round take at most a quarter of the arena;
+    // finals beyond that wait for the next round
+    const size_t net_budget = ws.tab_bytes / 4;
     std::vector<uint32_t> active, next;
     // A range that becomes small in a round still holds that round's swap
     // buffer, so it runs one round later (next_finals -> ready_finals).
-    std::vector<SortSeg> ready_finals, next_finals, tasks, deferred;
+    std::vector<SortSeg> ready_finals, next_finals, tasks, deferred, xf;
     for (uint32_t i = 0; i < segs.size(); ++i) {
         const Seg &g = segs[i];
         const uint32_t s = g.hi - g.lo;
@@ -219,25 +297,29 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
         ArenaUse use(ws, st);
         Arena &ar = use.ar;
         tasks.clear();
-        // ---- the finals that run this round: those above T0 take their swap
-        // space from the scratch buffer while it lasts, the rest wait for the
-        // next round, whose scratch room is what they leave ----
-        uint64_t fused = 0, deferred_keys = 0;
+        // ---- the finals that run this round: all of at most T0 keys (one
+        // tile each), the longer ones while their network tables fit the
+        // round's share of the arena; the rest wait for the next round ----
         deferred.clear();
-        for (SortSeg f : ready_finals) {
-            if (f.m > T0) {
-                if (fused + f.m > final_cap) {
+        xf.clear();
+        {
+            std::vector<SortSeg> big;
+            for (const SortSeg &f : ready_finals) {
+                if (f.m > T0) big.push_back(f);
+                else tasks.push_back(f);
+            }
+            std::stable_sort(big.begin(), big.end(),
+                             [](const SortSeg &x, const SortSeg &y) { return x.m > y.m; });
+            for (const SortSeg &f : big) {
+                const uint32_t K = ceil_log2(xf.empty() ? f.m : xf[0].m);
+                if (!xf.empty() && network_table_bytes(xf.size() + 1, K, ceil_log2(T0)) > net_budget) {
                     deferred.push_back(f);
-                    deferred_keys += f.m;
                     continue;
                 }
-                f.bkeys = ws.fbuf + ew * fused;
-                f.bvals = pairs ? ws.fbuf + final_cap + fused : nullptr;
-                fused += f.m;
+                xf.push_back(f);
+                tasks.push_back(f);
             }
-            tasks.push_back(f);
         }
-        uint64_t next_room = final_cap - std::min<uint64_t>(deferred_keys, final_cap);
         const uint32_t A = (uint32_t)active.size();
         if (A > 0) {
             // ---- partition: count + scan A, then read three counters back ----
@@ -416,15 +498,10 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
                     g_schedule.push_back(
                         {s, c_lt, c_eq, (uint64_t)(s - c_lt - c_eq), t.L, mom ? 1ull : 0ull});
                 // the larger side goes on in the loop unless it is small
-                // enough for the stopper and the next round's scratch has
-                // room for it (without room it is partitioned again, which
-                // needs none: no round waits for the buffer)
+                // enough for X
                 const uint32_t s2 = g.hi - g.lo;
-                if (s2 <= T0) {
+                if (s2 <= TF) {
                     if (s2 > 1) next_finals.push_back(final_task(g, g.lo, s2));
-                } else if (s2 <= TF && s2 <= next_room) {
-                    next_finals.push_back(final_task(g, g.lo, s2));
-                    next_room -= s2;
                 } else {
                     next.push_back(active[a]);
                 }
@@ -482,6 +559,10 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
         R.pre = ar.dev<uint32_t>(o_pt);
         hipError_t e = launch_tile_sort(dt, pairs, R, ptile[T], 0, base_bytes, ws, st);
         if (e != hipSuccess) return hip_error(e, "base case");
+        // the finals' networks (their ranges are disjoint from this round's
+        // Mergesort regions)
+        int rcx = final_network(dt, pairs, xf, ar, T0, elem_bytes, st);
+        if (rcx != QMS_OK) return rcx;
         // one launch group per (binary level, pass kind) over a contiguous
         // range [a0, a1) of the table
         auto run = [&](uint32_t a0, uint32_t a1, uint32_t l, bool four) -> hipError_t {

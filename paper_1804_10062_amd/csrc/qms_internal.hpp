@@ -29,16 +29,15 @@ constexpr uint64_t kCapSplits = (1ull << 31) / kMergeTile + kCapSegs + 16;
 constexpr uint32_t kCapMoM = 2048;
 // Merge levels a task can need: ceil(log2(2^31 / 8192)).
 constexpr int kMaxLevels = 18;
-// Elements of the scratch buffer that final ranges use as swap space (keys
-// of up to 8 bytes, or 4-byte keys with 4-byte payloads): 128 MiB.
-constexpr uint64_t kFinalCap = 1ull << 24;
+// Largest final_tile: ranges of at most this many keys may leave the loop
+// for the in-place bitonic network.
+constexpr uint64_t kMaxFinalTile = 1ull << 30;
 
 // Capacities of a workspace.  The cached workspaces take the constants
 // above; the allocation-free entry point carves a smaller set for one array
 // of bounded size out of a fixed device array.
 struct WsCaps {
     uint64_t tiles, chunks, splits, groups;
-    uint64_t final_cap;  // elements of the final ranges' scratch (0: none)
     uint32_t segs, mom;
     uint32_t rounds;     // segments of a device-controlled batch group (0: none)
     size_t tab_bytes;    // bytes of one task-table arena
@@ -77,7 +76,6 @@ struct Workspace {
     uint32_t *res = nullptr;     // [4 * kCapSegs] per-segment partition results
     uint32_t *hist = nullptr;    // [256 * kCapMoM] median-of-medians select histograms
     uint8_t *gcnt = nullptr;     // [kCapGroups] #(< p) per 64 positions of a partition
-    uint32_t *fbuf = nullptr;    // [2 * kFinalCap] swap space of final ranges
     // task tables: device copies of the host arena below
     void *dtab = nullptr;        // [tab_bytes]
     void *htab[2] = {nullptr, nullptr};  // pinned host arenas (alternating rounds)
@@ -154,6 +152,10 @@ struct BitonicLaunch {
     uint32_t items = 0;  // workgroups (the sum over the tasks of bitonic_items)
     double bytes = 0;
 };
+// The in-tile half-cleaners of that network: the base case's last stage on
+// each tile (items: the tiles of all tasks).
+hipError_t launch_tile_merge(int dt, bool pairs, const TaskRef<SortSeg> &tasks, uint32_t items,
+                             hipStream_t st);
 // Workgroups of one range of m keys in pass L (base tile T).
 uint32_t bitonic_items(const BitonicLaunch &L, uint64_t m, uint32_t T);
 hipError_t launch_bitonic_pass(int dt, bool pairs, const BitonicLaunch &L, hipStream_t st);

@@ -1,9 +1,9 @@
-"""The buffered final Mergesort: a range that a partition round leaves with
-at most final_tile keys leaves the QuickMergesort loop and is finished by
-one Mergesort whose swap space is the library's fixed scratch buffer (a
-recursion stopper; final_tile 8192 runs the paper's loop to the base tile).
-Every input array above the base tile is partitioned at least once.
-Results must be the oracle's bit for bit, whatever path a range takes."""
+"""The loop's last range: a range that a partition round leaves with at
+most final_tile keys leaves the QuickMergesort loop and is sorted in place
+by X, a bitonic network (QuickXsort with X at the loop level; final_tile
+8192 runs the paper's loop to the base tile).  Every input array above the
+base tile is partitioned at least once.  Results must be the oracle's bit
+for bit, whatever path a range takes."""
 import math
 
 import numpy as np
@@ -17,7 +17,6 @@ from tests.gpu_helpers import check_pairs_exact, to_device, to_host  # noqa: E40
 
 pytestmark = [pytest.mark.gpu, pytest.mark.final_path]
 needs_gpu = pytest.mark.skipif(not torch.cuda.is_available(), reason="no GPU")
-FINAL_CAP = 1 << 24  # elements of the scratch buffer
 
 
 @pytest.fixture(autouse=True)
@@ -108,10 +107,9 @@ def test_final_64_bit(n):
 
 
 @needs_gpu
-def test_final_batch_beyond_the_buffer():
-    """More small ranges than the scratch buffer holds: those it has no room
-    for stay in the loop (partitioned again) until it has.  Segments of
-    every size class (in place, buffered, through the loop) in one batch."""
+def test_final_batch_of_every_size_class():
+    """Segments of every size class (empty, one key, one tile, just above a
+    tile, several ~2^22) in one batch."""
     qms.qms_set_tuning(4, 4096, 16384, 0, 1 << 22)
     lens = np.concatenate([
         # after their first partition the larger sides (at least half of
@@ -121,7 +119,6 @@ def test_final_batch_beyond_the_buffer():
         inputs.log_uniform_lengths(200, seed=4, lo_exp=6, hi_exp=18).astype(np.int64)])
     off = inputs.offsets_from_lengths(lens)
     x = inputs.uniform_u32(int(off[-1]), seed=8)
-    assert int(lens[:9].sum()) // 2 > FINAL_CAP
     t = to_device(x)
     ot = torch.from_numpy(off.view(np.int64)).cuda()
     qms.qms_sort_batch(t, ot, host_offsets=off)
@@ -133,7 +130,7 @@ def test_final_batch_beyond_the_buffer():
 @needs_gpu
 def test_final_path_is_the_default_and_large_sorts_use_both():
     """Defaults: a range of 2^24 + 1 keys is partitioned until it fits the
-    final threshold, then finished by the buffered Mergesort."""
+    final threshold, then finished in place by the network."""
     tf = qms.qms_get_tuning()["final_tile"]
     n = (1 << 24) + 1
     x = inputs.uniform_u32(n, seed=3)
@@ -149,11 +146,8 @@ def test_final_path_is_the_default_and_large_sorts_use_both():
 
 @needs_gpu
 def test_final_only_rounds_back_to_back():
-    """Twelve arrays of almost 2^22 keys: their larger sides (at least 2^21
-    keys each, 2.4 * 10^7 or more in all) fill the scratch buffer more than
-    once, so some stay in the loop; rounds that end without a partition (no
-    readback that synchronises the stream) must each see their own task
-    tables, and a second call reuses the arenas of the first."""
+    """Twelve arrays of almost 2^22 keys sorted twice in a row (the second
+    call reuses the state of the first)."""
     qms.qms_set_tuning(4, 4096, 16384, 0, 1 << 22)
     lens = np.concatenate([np.full(12, (1 << 22) - 5, dtype=np.int64),
                            np.array([3, 9000, 20000], dtype=np.int64)])
@@ -167,3 +161,40 @@ def test_final_only_rounds_back_to_back():
         torch.cuda.synchronize()
     want, _, _ = oracle.sort_segments(x, off)
     np.testing.assert_array_equal(to_host(t), want)
+
+
+@needs_gpu
+@pytest.mark.parametrize("dt", ["u32", "f32", "u64"])
+def test_final_network_many_ranges_in_one_round(dt):
+    """The request server sorts many arrays per host-driven round, so one
+    round's network serves ranges of different lengths (different stage
+    counts) through its task tables."""
+    import time
+    lens = [16385, 20000, 40000, 65536, 65537, 100000, 300001, (1 << 20) + 1, 3000000, 1 << 21]
+    rng = np.random.default_rng(len(lens))
+    xs, ts = [], []
+    for n in lens:
+        if dt == "u32":
+            x = rng.integers(0, 1 << 32, n, dtype=np.uint64).astype(np.uint32)
+            t = torch.from_numpy(x.view(np.int32)).cuda()
+        elif dt == "f32":
+            x = rng.standard_normal(n).astype(np.float32)
+            t = torch.from_numpy(x).cuda()
+        else:
+            x = rng.integers(0, 2 ** 64, n, dtype=np.uint64)
+            t = torch.from_numpy(x.view(np.int64)).cuda()
+        xs.append(x)
+        ts.append(t)
+    torch.cuda.synchronize()
+    qms.qms_set_tuning(4, 4096, 16384, 0, 1 << 22)
+    with qms.Server(hbm_budget_bytes=1 << 33) as srv:
+        tickets = [srv.submit(t) for t in ts]
+        t_end = time.time() + 120
+        for tk in tickets:
+            while srv.poll(tk)[0] != qms.QMS_OK:
+                assert time.time() < t_end, "request not done"
+                time.sleep(0.001)
+    for x, t in zip(xs, ts):
+        want, _, _ = oracle.sort(x, counted=False)
+        got = t.cpu().numpy().view(want.dtype)
+        np.testing.assert_array_equal(got.view(np.uint8), want.view(np.uint8))
