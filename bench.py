@@ -18,13 +18,17 @@ One JSON line goes to stdout with, besides the contract fields:
                 timed region (events around ~500 launches per sort add a few
                 percent, so the headline region runs without them); `traffic` is the
                 HBM traffic per launch measured by rocprofv3 counters
-                (profiles/k_merge_traffic.json) while the kernel source is
-                unchanged since that measurement, else null;
+                (profiles/pmc_qms_sort_u32_2e28.json) while the kernel source
+                is unchanged since that measurement, else null;
+  kernel_rooflines  the other hot kernels against their own bounds: the base
+                case against the VALU issue peak (VALU instructions per sort
+                from the same counter file over its event-timed time), the
+                partition exchange against HBM with its measured traffic;
   whole_sort    every algorithmic byte of the executed schedule (base case,
                 merge passes, counting, exchange) over the time per sort,
                 against the same peak;
-  cpu_baseline  the CPU oracle (single thread) on a bounded sample of the
-                same workload (the first 2^26 keys), in Gkeys/s;
+  cpu_baseline  the CPU oracle (single thread, pinned to one core) on the
+                whole 2^28-key workload, in Gkeys/s;
   kernels       per-kernel-class launches, time and achieved GB/s;
   distributions Gkeys/s of the three inputs, and of 2^26 key/payload pairs
                 (Zipf(1.1) keys over [0, 2^10), payload = index);
@@ -48,8 +52,8 @@ if ROOT not in sys.path:
 
 N_KEYS = 1 << 28
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_merge_traffic.json")
-MERGE_SRC = os.path.join(ROOT, "paper_1804_10062_amd", "csrc", "qms_merge.hip")
+PMC_FILE = os.path.join(ROOT, "profiles", "pmc_qms_sort_u32_2e28.json")
+VALU_PEAK = 256 * 2.4e9  # wave64 VALU instructions per second (one per CU per cycle)
 
 
 def parse():
@@ -105,21 +109,17 @@ def _oracle_on_one_core(keys):
     return dt, core
 
 
-def merge_source_hash() -> str:
-    return hashlib.sha256(open(MERGE_SRC, "rb").read()).hexdigest()[:16]
-
-
-def measured_traffic():
-    """HBM bytes per merge-pass launch (k_merge and k_merge4 together) from
-    the committed rocprofv3 counter summary, if it was taken on the current
-    kernel source."""
+def measured_kernel(name: str):
+    """The rocprofv3 counter record of one kernel from the committed summary
+    (per sort of the headline workload), if the kernel's source file is
+    unchanged since it was taken; else None."""
     try:
-        d = json.load(open(TRAFFIC_FILE))
-    except (OSError, ValueError):
+        d = json.load(open(PMC_FILE))
+        k = d["kernels"][name]
+        h = hashlib.sha256(open(os.path.join(ROOT, k["source"]), "rb").read()).hexdigest()[:16]
+    except (OSError, ValueError, KeyError):
         return None
-    if d.get("source_sha256_16") != merge_source_hash():
-        return None
-    return d.get("bytes_per_launch")
+    return k if h == k.get("source_sha256_16") else None
 
 
 def time_sorts(copies, qms, torch, profile: bool):
@@ -473,7 +473,9 @@ def main():
     prof = {k: v for k, v in prof.items() if not k.startswith("merge_level_")}
     mk = prof["merge"]
     achieved = (mk["bytes"] / 1e9) / (mk["total_ms"] / 1e3)
-    traffic = measured_traffic()
+    pm = measured_kernel("k_merge4")
+    traffic = (None if pm is None else
+               round((pm["fetch_bytes_per_sort"] + pm["write_bytes_per_sort"]) / pm["dispatches_per_sort"]))
     roofline = {
         "kernel": "swap-merge pass (k_merge4, k_merge)",
         "bound": "hbm",
@@ -489,6 +491,37 @@ def main():
         "copy_GBs": round(copy_gbs, 1),
         "frac_of_copy": round(achieved / copy_gbs, 4),
     }
+    # the base case against the VALU issue peak, the exchange against HBM
+    # with its measured traffic, the split searches' fetches
+    kernel_rooflines = {}
+    tk, pv = prof.get("tile_sort"), measured_kernel("k_tile_sort")
+    if tk and pv and "SQ_INSTS_VALU_per_sort" in pv:
+        rate = pv["SQ_INSTS_VALU_per_sort"] / (tk["total_ms"] / K / 1e3)
+        kernel_rooflines["tile_sort"] = {
+            "kernel": "k_tile_sort (bitonic base case)", "bound": "alu",
+            "achieved": round(rate / 1e9, 1), "peak": round(VALU_PEAK / 1e9, 1),
+            "unit": "G wave64 VALU instructions/s", "frac": round(rate / VALU_PEAK, 4),
+            "valu_instructions_per_key": round(
+                pv["SQ_INSTS_VALU_per_sort"] * 64 / (tk["bytes"] / K / 8.0), 1),
+            "hbm_GBs": round(tk["bytes"] / 1e9 / (tk["total_ms"] / 1e3), 1)}
+    sk, ps = prof.get("part_swap"), measured_kernel("k_part_swap")
+    if sk and ps:
+        t = sk["total_ms"] / K / 1e3
+        tb = ps["fetch_bytes_per_sort"] + ps["write_bytes_per_sort"]
+        alg = sk["bytes"] / K
+        kernel_rooflines["part_swap"] = {
+            "kernel": "k_part_swap (rank-matched exchange, pass A)", "bound": "hbm",
+            "achieved": round(tb / t / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(tb / t / 1e9 / HBM_PEAK_GBS, 4),
+            "frac_of_copy": round(tb / t / 1e9 / copy_gbs, 4),
+            "traffic_per_sort": tb, "algorithmic_per_sort": round(alg),
+            "traffic_over_algorithmic": round(tb / alg, 3) if alg else None}
+    ms_, pm_ = prof.get("merge_split"), measured_kernel("k_merge_split")
+    if ms_ and pm_:
+        kernel_rooflines["merge_split"] = {
+            "kernel": "k_merge_split (merge-path searches)", "bound": "latency",
+            "ms_per_sort": round(ms_["total_ms"] / K, 3),
+            "fetch_GB_per_sort": round(pm_["fetch_bytes_per_sort"] / 1e9, 3)}
     # the whole sort against the same peak: all algorithmic bytes of the
     # executed schedule (base case, merge passes, counting, pass-A exchange)
     # over the headline time per sort
@@ -684,6 +717,7 @@ def main():
         "batched": batched,
         "serving": serving,
         "kernels": kernels,
+        "kernel_rooflines": kernel_rooflines,
         "merge_levels": merge_levels,
         "copy_GBs": round(copy_gbs, 1),
     }

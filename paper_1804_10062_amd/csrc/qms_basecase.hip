@@ -112,7 +112,7 @@ template <>
 struct TileElem<true, uint64_t> {
     using E = WideIdx;
     static constexpr int ITEMS = kBaseTileWidePairs / kSortThreads;  // 4
-    static constexpr uint32_t IBITS = 11;
+    static constexpr uint32_t IBITS = 31 - __builtin_clz(kBaseTileWidePairs);  // log2 of the tile
     static constexpr E FLIP = WideIdx{~0ull, (1u << IBITS) - 1, 0};
     static constexpr bool F64 = false;
     __device__ static E make(uint64_t k, uint32_t i) { return WideIdx{k, i, 0}; }

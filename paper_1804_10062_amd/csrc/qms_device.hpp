@@ -23,7 +23,10 @@ constexpr int kWaves = kBlock / kWave;
 constexpr int kSortThreads = 512;      // threads of the base-case workgroup
 constexpr uint32_t kBaseTileKeys = 16384;  // base-case tile, keys only
 constexpr uint32_t kBaseTilePairs = 8192;  // base-case tile, key/payload pairs
-constexpr uint32_t kBaseTileWidePairs = 2048;  // 64-bit keys with payloads
+#ifndef QMS_WIDE_PAIR_TILE
+#define QMS_WIDE_PAIR_TILE 2048
+#endif
+constexpr uint32_t kBaseTileWidePairs = QMS_WIDE_PAIR_TILE;  // 64-bit keys with payloads
 // The base tile of a sort: keys only, key/payload pairs or 64-bit keys, or
 // 64-bit keys with payloads (whose 128-bit network elements fill the LDS
 // four times as fast).
