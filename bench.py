@@ -122,7 +122,7 @@ def measured_kernel(name: str):
     return k if h == k.get("source_sha256_16") else None
 
 
-def time_sorts(copies, qms, torch, profile: bool):
+def time_sorts(copies, qms, torch, profile: bool, dtype=None):
     """Sort every tensor in `copies` (one step each); returns (seconds, profile)."""
     stream = torch.cuda.current_stream()
     torch.cuda.synchronize()
@@ -130,7 +130,7 @@ def time_sorts(copies, qms, torch, profile: bool):
         qms.qms_profile_begin()
     t0 = time.perf_counter()
     for t in copies:
-        qms.qms_sort(t, stream=stream)
+        qms.qms_sort(t, stream=stream, dtype=dtype)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = qms.qms_profile_end() if profile else None
@@ -588,6 +588,35 @@ def main():
         dists["u64_2e27"] = round(n64 / (sec2 / args.dist_steps) / 1e9, 3)
         dists["u64_2e27_GB_per_s_keys"] = round(8 * n64 / (sec2 / args.dist_steps) / 1e9, 1)
         del ws64, last, hi, lo
+        # expensive comparisons (Experiments section: a comparator that
+        # applies the logarithm to the integer keys): a random order of
+        # 1..2^26 sorted with the plain uint32 order and with QMS_U32_LOG,
+        # whose every comparison evaluates two double logarithms, at the
+        # automatic X_THRESH and at 2048 (fewer network comparisons per key)
+        print("[bench] log comparator", file=sys.stderr, flush=True)
+        from paper_1804_10062_amd import autotune
+        nl = 1 << 26
+        s3 = torch.from_numpy(inputs.permutation_u32(nl, seed=11).view(np.int32)).to(dev)
+        want = torch.arange(1, nl + 1, dtype=torch.int64, device=dev)
+        logcmp = {"workload": "a random order of 1..2^26 (uint32), SplitMix64-keyed Feistel permutation, seed 11"}
+        try:
+            for label, bt in (("auto", 0), ("2048", 2048)):
+                qms.qms_set_tuning(4, 4096, 16384, bt, 1 << 22)
+                for name, code in (("plain", qms.QMS_U32), ("log", qms.QMS_U32_LOG)):
+                    cps = [s3.clone() for _ in range(3)]
+                    time_sorts(cps[:1], qms, torch, profile=False, dtype=code)
+                    sec3, _ = time_sorts(cps[1:], qms, torch, profile=False, dtype=code)
+                    if not bool((cps[-1].to(torch.int64) == want).all()):
+                        print(f"bench.py: log comparator {name} output wrong", file=sys.stderr)
+                        sys.exit(1)
+                    logcmp[f"{name}_Gkeys_per_s_x_{label}"] = round(nl / (sec3 / 2) / 1e9, 3)
+                    del cps
+        finally:
+            autotune.reset_tuning()
+        logcmp["log_over_plain_time_x_auto"] = round(
+            logcmp["plain_Gkeys_per_s_x_auto"] / logcmp["log_Gkeys_per_s_x_auto"], 2)
+        dists["log_comparator_2e26"] = logcmp
+        del s3, want
 
     # QuickMergeXsort's threshold (Sec. "QuickMergeXsort"): the same uniform
     # workload with the Mergesort stopping at runs of base_tile keys; the

@@ -21,6 +21,14 @@
  *     binary64 by the same total order; 8-byte aligned, with or without
  *     payloads (with payloads their merge passes are 2-way and their base
  *     tile is 2048 keys).
+ *   - QMS_U32_LOG: uint32 keys under an expensive comparison, the
+ *     logarithm of each key in double precision evaluated inside every
+ *     comparison (the comparator of the paper's Experiments section that
+ *     makes element comparisons costly).  log is strictly increasing and
+ *     double precision separates the logarithms of distinct keys below
+ *     2^32, so the result is the QMS_U32 sort; what changes is the cost of
+ *     each comparison in the partition, the merges and the base case.  Keys
+ *     only (QMS_ERR_UNSUPPORTED with payloads).
  *   - Payloads (qms_sort_pairs, qms_sort_batch with vals) are uint32 words in
  *     a separate array (structure of arrays); every move of a key moves its
  *     payload.  The sort is not stable: payload order among equal keys is
@@ -52,7 +60,13 @@
 extern "C" {
 #endif
 
-typedef enum { QMS_U32 = 0, QMS_F32 = 1, QMS_U64 = 2, QMS_F64 = 3 } qms_dtype;
+typedef enum {
+    QMS_U32 = 0,
+    QMS_F32 = 1,
+    QMS_U64 = 2,
+    QMS_F64 = 3,
+    QMS_U32_LOG = 4 /* uint32 keys compared by log(key) (see above) */
+} qms_dtype;
 
 typedef enum {
     QMS_OK = 0,

@@ -296,6 +296,8 @@ DeviceScope::~DeviceScope() {
 static int sort_entry(void *d_keys, uint32_t *d_vals, uint64_t n, int dt, hipStream_t stream,
                       bool pairs) {
     if (!dtype_known(dt)) return set_error(QMS_ERR_UNSUPPORTED, "unknown dtype");
+    if (pairs && !dtype_takes_payloads(dt))
+        return set_error(QMS_ERR_UNSUPPORTED, "QMS_U32_LOG sorts keys without payloads");
     if (n <= 1) return QMS_OK;
     if (d_keys == nullptr || (pairs && d_vals == nullptr))
         return set_error(QMS_ERR_INVALID, "NULL pointer with n > 1");

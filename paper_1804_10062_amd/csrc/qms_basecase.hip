@@ -55,6 +55,19 @@ struct TileElem<false, uint32_t> {
     __device__ static uint32_t key(E x) { return x; }
     __device__ static uint32_t index(E) { return 0; }
 };
+// Keys in log order: the same layout, compared through the order's own
+// comparison (no single-instruction min/max applies).
+template <>
+struct TileElem<false, LogKey> {
+    using E = LogKey;
+    static constexpr int ITEMS = kBaseTileKeys / kSortThreads;  // 32
+    static constexpr E FLIP = LogKey{~0u};
+    static constexpr bool F64 = false;
+    __device__ static E make(uint32_t k, uint32_t) { return LogKey{k}; }
+    __device__ static E pad(uint32_t) { return LogKey{0xFFFFFFFFu}; }
+    __device__ static uint32_t key(E x) { return x.k; }
+    __device__ static uint32_t index(E) { return 0; }
+};
 // Key/payload pairs: bit 52 (the lowest exponent bit of a double), the key in
 // bits 13..44 and the element's index in the tile in bits 0..12.  Every
 // element is then a positive normal double, so one v_min_f64 and one
@@ -164,10 +177,16 @@ __device__ __forceinline__ uint64_t keep_side(uint64_t x, uint64_t y, bool keep_
 __device__ __forceinline__ WideIdx keep_side(WideIdx x, WideIdx y, bool keep_min, WideIdx) {
     return (x < y) == keep_min ? x : y;  // elements never tie
 }
+__device__ __forceinline__ LogKey keep_side(LogKey x, LogKey y, bool keep_min, LogKey) {
+    return (x < y) == keep_min ? x : y;
+}
 
 // The partner lane's element (xor of the lane index).
 __device__ __forceinline__ uint32_t shfl_xor_elem(uint32_t v, int m) { return __shfl_xor(v, m, kWave); }
 __device__ __forceinline__ uint64_t shfl_xor_elem(uint64_t v, int m) { return __shfl_xor(v, m, kWave); }
+__device__ __forceinline__ LogKey shfl_xor_elem(LogKey v, int m) {
+    return LogKey{(uint32_t)__shfl_xor((int)v.k, m, kWave)};
+}
 __device__ __forceinline__ WideIdx shfl_xor_elem(WideIdx v, int m) {
     return WideIdx{__shfl_xor(v.k, m, kWave), (uint32_t)__shfl_xor((int)v.i, m, kWave), 0};
 }
@@ -324,7 +343,7 @@ __device__ __forceinline__ void tile_sort_block(typename O::K *sk, uint32_t *sv,
                                                 uint32_t run, bool swap,
                                                 typename O::K *samples) {
     using K = typename O::K;
-    using TE = TileElem<PAIRS, K>;
+    using TE = TileElem<PAIRS, typename O::NetKey>;
     using E = typename TE::E;
     constexpr int ITEMS = TE::ITEMS;
     constexpr int NT = kSortThreads;
@@ -429,7 +448,7 @@ __device__ __forceinline__ void tile_sort_block(typename O::K *sk, uint32_t *sv,
                 r[i] = keep_side(r[i], s[(uint32_t)i * NT + pt], keep_min, bound);
         }
         // partners in other lanes of the wave
-        if constexpr (sizeof(E) == 4) {
+        if constexpr (std::is_same_v<E, uint32_t>) {
             switch (j / ITEMS) {  // lane masks j / ITEMS down to 1
             case 32:
                 lane_step_u32<32>(r, lane);
@@ -640,6 +659,10 @@ hipError_t launch_tile_merge(int dt, bool pairs, const TaskRef<SortSeg> &tasks, 
         if (pairs) hipLaunchKernelGGL((k_tile_merge<OrdF64, true>), g, b, 0, st, tasks, items);
         else hipLaunchKernelGGL((k_tile_merge<OrdF64, false>), g, b, 0, st, tasks, items);
         break;
+    case 4:
+        if (pairs) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_tile_merge<OrdLogU32, false>), g, b, 0, st, tasks, items);
+        break;
     default:
         return hipErrorInvalidValue;
     }
@@ -662,6 +685,9 @@ hipError_t launch_tile_sort(int dt, bool pairs, const TaskRef<SortSeg> &tasks, u
     case 3:
         return pairs ? tile_sort_t<OrdF64, true>(tasks, tiles, overflow, bytes, ws, st)
                      : tile_sort_t<OrdF64, false>(tasks, tiles, overflow, bytes, ws, st);
+    case 4:
+        return pairs ? hipErrorInvalidValue
+                     : tile_sort_t<OrdLogU32, false>(tasks, tiles, overflow, bytes, ws, st);
     default:
         return hipErrorInvalidValue;
     }

@@ -15,6 +15,8 @@ extern "C" int qms_sort_batch(void *d_keys, uint32_t *d_vals, const uint64_t *d_
                               hipStream_t stream) {
     try {
         if (!dtype_known(dt)) return set_error(QMS_ERR_UNSUPPORTED, "unknown dtype");
+        if (d_vals && !dtype_takes_payloads(dt))
+            return set_error(QMS_ERR_UNSUPPORTED, "QMS_U32_LOG sorts keys without payloads");
         if (num_segments == 0) return QMS_OK;
         if (d_keys == nullptr || d_offsets == nullptr)
             return set_error(QMS_ERR_INVALID, "NULL keys or offsets");

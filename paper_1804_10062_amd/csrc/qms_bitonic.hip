@@ -70,7 +70,7 @@ __device__ __forceinline__ void mirror_item(TaskRef<SortSeg> tasks, uint32_t ite
     }
 #pragma unroll
     for (uint32_t q = 0; q < kMirrorPer; ++q) {
-        if (!on[q] || !(O::ord(y[q]) < O::ord(x[q]))) continue;
+        if (!on[q] || !O::lt(O::ord(y[q]), O::ord(x[q]))) continue;
         keys[pi[q]] = y[q];
         keys[pp[q]] = x[q];
         if (PAIRS) {
@@ -120,7 +120,7 @@ __device__ __forceinline__ void columns_item(TaskRef<SortSeg> tasks, uint32_t it
         for (int r = 0; r < R; ++r) {
             if (r & d) continue;
             // the upper element outside the range is +infinity: no exchange
-            if (on[r + d] && x[r + d] < x[r]) {
+            if (on[r + d] && O::lt(x[r + d], x[r])) {
                 const K t = x[r];
                 x[r] = x[r + d];
                 x[r + d] = t;
@@ -218,6 +218,8 @@ hipError_t launch_bitonic_pass(int dt, bool pairs, const BitonicLaunch &L, hipSt
         return pairs ? bitonic_t<OrdU64, true>(dt, L, st) : bitonic_t<OrdU64, false>(dt, L, st);
     case 3:
         return pairs ? bitonic_t<OrdF64, true>(dt, L, st) : bitonic_t<OrdF64, false>(dt, L, st);
+    case 4:
+        return pairs ? hipErrorInvalidValue : bitonic_t<OrdLogU32, false>(dt, L, st);
     default:
         return hipErrorInvalidValue;
     }

@@ -234,16 +234,22 @@ __device__ __forceinline__ T task_of(const TaskRef<T> &r, uint32_t g, uint32_t *
 // bits) after an order map applied in registers on load (and undone on
 // store).  The policy carries the key type, so kernels templated on it read
 // and write keys of the right width.
+// lt(a, b) compares two mapped keys; NetKey is the element type of the base
+// case's network for keys without payloads.
 struct OrdU32 {
     using K = uint32_t;
+    using NetKey = uint32_t;
     __device__ __forceinline__ static uint32_t ord(uint32_t x) { return x; }
     __device__ __forceinline__ static uint32_t unord(uint32_t x) { return x; }
+    __device__ __forceinline__ static bool lt(uint32_t a, uint32_t b) { return a < b; }
 };
 // IEEE-754 binary32 total order: negative values have all bits flipped,
 // non-negative values get the sign bit set; unsigned order of the result is
 // the total order (-NaN < -inf < ... < -0 < +0 < ... < +inf < +NaN).
 struct OrdF32 {
     using K = uint32_t;
+    using NetKey = uint32_t;
+    __device__ __forceinline__ static bool lt(uint32_t a, uint32_t b) { return a < b; }
     __device__ __forceinline__ static uint32_t ord(uint32_t u) {
         return u ^ ((uint32_t)((int32_t)u >> 31) | 0x80000000u);
     }
@@ -254,11 +260,15 @@ struct OrdF32 {
 // 64-bit keys: unsigned, and IEEE-754 binary64 by the same total order.
 struct OrdU64 {
     using K = uint64_t;
+    using NetKey = uint64_t;
+    __device__ __forceinline__ static bool lt(uint64_t a, uint64_t b) { return a < b; }
     __device__ __forceinline__ static uint64_t ord(uint64_t x) { return x; }
     __device__ __forceinline__ static uint64_t unord(uint64_t x) { return x; }
 };
 struct OrdF64 {
     using K = uint64_t;
+    using NetKey = uint64_t;
+    __device__ __forceinline__ static bool lt(uint64_t a, uint64_t b) { return a < b; }
     __device__ __forceinline__ static uint64_t ord(uint64_t u) {
         return u ^ ((uint64_t)((int64_t)u >> 63) | 0x8000000000000000ull);
     }
@@ -266,6 +276,37 @@ struct OrdF64 {
         return k ^ ((uint64_t)((int64_t)(~k) >> 63) | 0x8000000000000000ull);
     }
 };
+// An expensive comparison (the paper's Experiments section sorts integers
+// with a comparator that applies the logarithm to them): uint32 keys
+// ordered by log(key) in double precision, evaluated at every comparison.
+// log is strictly increasing and double precision separates the logarithms
+// of any two distinct integers below 2^32 (their gap is at least about
+// 2^-32, the spacing of doubles near 22 is 2^-48), so the order is the
+// integers' own (log 0 = -inf comes first) and the sorted output is the
+// plain uint32 sort.  Equality is integer equality.
+__device__ __forceinline__ bool log_less(uint32_t a, uint32_t b) {
+    return log((double)a) < log((double)b);
+}
+// The network element of that order: the complement still reverses it
+// (any order-reversing map of the integers reverses an increasing function
+// of them), so the base case's descending-block representation holds.
+struct LogKey {
+    uint32_t k;
+};
+__device__ __forceinline__ bool operator<(LogKey a, LogKey b) { return log_less(a.k, b.k); }
+__device__ __forceinline__ LogKey operator^(LogKey a, LogKey b) { return LogKey{a.k ^ b.k}; }
+__device__ __forceinline__ LogKey &operator^=(LogKey &a, LogKey b) {
+    a.k ^= b.k;
+    return a;
+}
+struct OrdLogU32 {
+    using K = uint32_t;
+    using NetKey = LogKey;
+    __device__ __forceinline__ static uint32_t ord(uint32_t x) { return x; }
+    __device__ __forceinline__ static uint32_t unord(uint32_t x) { return x; }
+    __device__ __forceinline__ static bool lt(uint32_t a, uint32_t b) { return log_less(a, b); }
+};
+
 // The largest key of a width (the merge sentinel, the base case's padding).
 template <class K>
 __device__ __forceinline__ constexpr K key_max() { return ~K(0); }

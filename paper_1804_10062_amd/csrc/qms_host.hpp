@@ -32,7 +32,9 @@ int set_error(int code, const std::string &msg);
 int hip_error(hipError_t e, const char *where);
 int check_device_ptr(const void *p, const char *what, int *device, uintptr_t align = 4);
 // dtype codes of qms.h: 32-bit (QMS_U32, QMS_F32) or 64-bit (QMS_U64, QMS_F64)
-inline bool dtype_known(int dt) { return dt >= 0 && dt <= 3; }
+inline bool dtype_known(int dt) { return dt >= 0 && dt <= 4; }
+// the log-order comparison sorts keys without payloads
+inline bool dtype_takes_payloads(int dt) { return dt != QMS_U32_LOG; }
 inline bool dtype_wide(int dt) { return dt == 2 || dt == 3; }
 // Exclusive use of the workspace of (device, stream) for one sort: taking
 // the lease waits for another thread's sort on the same stream to end.

@@ -172,7 +172,7 @@ __device__ __forceinline__ uint64_t group_count_before(const typename O::K *Y,
                                                        typename O::K x, bool strict) {
     using K = typename O::K;
     constexpr uint64_t S = kSampleStride;
-    auto before = [&](K v) { return strict ? v < x : v <= x; };
+    auto before = [&](K v) { return strict ? O::lt(v, x) : !O::lt(x, v); };
     const uint64_t u =
         group_first_false(0, (nY + S - 1) / S, [&](uint64_t i) { return before(ldg(Ys + i)); });
     const uint64_t lo = u == 0 ? 0 : (u - 1) * S + 1;
@@ -217,14 +217,14 @@ __device__ __forceinline__ void merge_split_item(TaskRef<SortSeg> tasks, uint32_
     if (!active) lo = hi = 0;
     // coarse: first u in [1, hi / S] without Q(u)
     const uint64_t f = group_first_false(1, active ? hi / S + 1 : 1, [&](uint64_t u) {
-        return d - u * S >= nB || ldg(As + u - 1) <= ldg(Bs + (d - u * S) / S);
+        return d - u * S >= nB || !O::lt(ldg(Bs + (d - u * S) / S), ldg(As + u - 1));
     });
     const uint64_t u1 = f - 1;
     const uint64_t wl = u1 >= 1 ? max(lo, (u1 - 1) * S + 1) : lo;
     const uint64_t wh = min(hi, (u1 + 1) * S - 1);
     // fine: the first i in [wl, wh) with A[i] > B[d - 1 - i], else wh
     const uint64_t c = group_first_false(wl, wh, [&](uint64_t i) {
-        return O::ord(ldg(A + i)) <= O::ord(ldg(B + d - 1 - i));
+        return !O::lt(O::ord(ldg(B + d - 1 - i)), O::ord(ldg(A + i)));
     });
     if (active && gid % kSplitLanes == 0 && half == 0) splits[g.split_off + tile] = (uint32_t)c;
     if constexpr (BOUNDS) {
@@ -232,7 +232,7 @@ __device__ __forceinline__ void merge_split_item(TaskRef<SortSeg> tasks, uint32_
         K x = 0;
         if (active) {
             const bool fromA =
-                c < nA && (d - c >= nB || O::ord(ldg(A + c)) <= O::ord(ldg(B + (d - c))));
+                c < nA && (d - c >= nB || !O::lt(O::ord(ldg(B + (d - c))), O::ord(ldg(A + c))));
             x = O::ord(ldg(fromA ? A + c : B + (d - c)));
         }
         const Merge4Geom g4 = merge4_geom(g.m, W, tile);
@@ -412,15 +412,15 @@ __global__ __launch_bounds__(kBlock) void k_merge4_ends(TaskRef<SortSeg> tasks, 
 // With `from`, also the LDS index each output was read from (to carry
 // payloads along).  With HI the elements are 64-bit key/payload words and
 // only their upper halves (the keys) are compared.
-template <bool HI, class T>
+template <class O, bool HI, class T>
 __device__ __forceinline__ bool lds_le(T a, T b) {
     if constexpr (HI) {
-        return (uint32_t)(a >> 32) <= (uint32_t)(b >> 32);
+        return !O::lt((uint32_t)(b >> 32), (uint32_t)(a >> 32));
     } else {
-        return a <= b;
+        return !O::lt(b, a);
     }
 }
-template <int N, bool FROM = false, class T = uint32_t, bool HI = false>
+template <class O, int N, bool FROM = false, class T = uint32_t, bool HI = false>
 __device__ __forceinline__ void merge_lds(const T *sk, uint32_t x0, uint32_t nx, uint32_t y0,
                                           uint32_t ny, uint32_t d, T (&out)[N],
                                           uint32_t *from = nullptr) {
@@ -428,7 +428,7 @@ __device__ __forceinline__ void merge_lds(const T *sk, uint32_t x0, uint32_t nx,
     uint32_t lo = d > ny ? d - ny : 0, hi = d < nx ? d : nx;
     while (lo < hi) {
         const uint32_t mid = (lo + hi) >> 1;
-        if (lds_le<HI>(X[mid], Y[d - 1 - mid])) lo = mid + 1;
+        if (lds_le<O, HI>(X[mid], Y[d - 1 - mid])) lo = mid + 1;
         else hi = mid;
     }
     uint32_t i = lo;
@@ -436,7 +436,7 @@ __device__ __forceinline__ void merge_lds(const T *sk, uint32_t x0, uint32_t nx,
 #pragma unroll
     for (int q = 0; q < N; ++q) {
         const T kx = X[i], ky = Yd[q - (int)i];
-        const bool takeX = i < nx && lds_le<HI>(kx, ky);
+        const bool takeX = i < nx && lds_le<O, HI>(kx, ky);
         out[q] = takeX ? kx : ky;
         if constexpr (FROM) from[q] = takeX ? x0 + i : y0 + d + q - i;
         i += takeX;
@@ -467,14 +467,14 @@ constexpr int kMerge4Slack = kMerge4NBig + 1;
 // elements of type L: the keys, or for key/payload pairs 64-bit words with
 // the key in the upper half (HI), so that a payload moves with its key.
 constexpr uint32_t kMerge4Lds = 2 * kMerge4Pair + 2 + kMerge4Slack;  // elements of the LDS tile
-template <int N, int NT, bool HI, class L>
+template <class O, int N, int NT, bool HI, class L>
 __device__ __forceinline__ void merge4_halves(L *sk, uint32_t c1, uint32_t c2, uint32_t c3,
                                               uint32_t cnt, uint32_t tid) {
     const bool cd = tid >= NT / 2;
     const uint32_t d = (cd ? tid - NT / 2 : tid) * N;
     const uint32_t base = cd ? c2 + 1 : 0, nx = cd ? c3 - c2 : c1, n = cd ? cnt - c2 : c2;
     L o[N];
-    if (d < n) merge_lds<N, false, L, HI>(sk, base, nx, base + nx, n - nx, d, o);
+    if (d < n) merge_lds<O, N, false, L, HI>(sk, base, nx, base + nx, n - nx, d, o);
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < N; ++q)
@@ -483,11 +483,11 @@ __device__ __forceinline__ void merge4_halves(L *sk, uint32_t c1, uint32_t c2, u
 }
 // The merged pairs sk[0, c2) and sk[c2 + 1, cnt + 1) merged into sk[0, cnt),
 // N outputs per thread.
-template <int N, bool HI, class L>
+template <class O, int N, bool HI, class L>
 __device__ __forceinline__ void merge4_final(L *sk, uint32_t c2, uint32_t cnt, uint32_t tid) {
     L o[N];
     const uint32_t d = tid * N;
-    if (d < cnt) merge_lds<N, false, L, HI>(sk, 0, c2, c2 + 1, cnt - c2, d, o);
+    if (d < cnt) merge_lds<O, N, false, L, HI>(sk, 0, c2, c2 + 1, cnt - c2, d, o);
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < N; ++q)
@@ -612,13 +612,13 @@ __device__ __forceinline__ void merge4_item(TaskRef<SortSeg> tasks, uint32_t ite
     static_assert((uint32_t)kMerge4NBig * (NT / 2) >= SP && (uint32_t)kMerge4NBig * NT >= 2 * SP,
                   "outputs per thread cover the largest tile");
     if (c2 <= S / 2 && cnt - c2 <= S / 2)
-        merge4_halves<2 * S / NT / 2 + kMergeOdd, NT, PAIRS>(sk, c1, c2, c3, cnt, tid);
+        merge4_halves<O, 2 * S / NT / 2 + kMergeOdd, NT, PAIRS>(sk, c1, c2, c3, cnt, tid);
     else
-        merge4_halves<kMerge4NBig, NT, PAIRS>(sk, c1, c2, c3, cnt, tid);
+        merge4_halves<O, kMerge4NBig, NT, PAIRS>(sk, c1, c2, c3, cnt, tid);
     if (cnt <= S)
-        merge4_final<S / NT + kMergeOdd, PAIRS>(sk, c2, cnt, tid);
+        merge4_final<O, S / NT + kMergeOdd, PAIRS>(sk, c2, cnt, tid);
     else
-        merge4_final<kMerge4NBig, PAIRS>(sk, c2, cnt, tid);
+        merge4_final<O, kMerge4NBig, PAIRS>(sk, c2, cnt, tid);
     // samples of the output runs: every kSampleStride-th position of the group
     {
         constexpr uint32_t SS = kSampleStride;
@@ -727,7 +727,7 @@ __device__ __forceinline__ void merge_block(typename O::K *S, uint32_t *SV, type
     uint32_t ov[PAIRS ? NM : 1];
     const uint32_t diag = tid * NM;
     if (diag < cnt) {
-        merge_lds<NM, PAIRS, K>(sk, 0, na, na, nb, diag, ok, from);
+        merge_lds<O, NM, PAIRS, K>(sk, 0, na, na, nb, diag, ok, from);
         if constexpr (PAIRS) {
 #pragma unroll
             for (int q = 0; q < NM; ++q) ov[q] = sv[min(from[q], cnt - 1)];
@@ -871,6 +871,8 @@ hipError_t launch_merge_pass(int dt, bool pairs, const MergeLaunch &M, const Wor
         return pairs ? merge_t<OrdU64, true>(M, ws, st) : merge_t<OrdU64, false>(M, ws, st);
     case 3:
         return pairs ? merge_t<OrdF64, true>(M, ws, st) : merge_t<OrdF64, false>(M, ws, st);
+    case 4:  // uint32 keys in log order (keys only)
+        return pairs ? hipErrorInvalidValue : merge_t<OrdLogU32, false>(M, ws, st);
     default:
         return hipErrorInvalidValue;
     }

@@ -87,7 +87,7 @@ __device__ __forceinline__ void part_count_item(TaskRef<PartSeg> tasks, uint32_t
             const uint64_t pos = b + (uint64_t)q * kBlock + threadIdx.x;
             const K x = O::ord(k[q]);
             const bool in = pos < te;
-            const bool less = in && x < p;
+            const bool less = in && O::lt(x, p);
             lt += less;
             eq += in && x == p;
             if (gcnt) {
@@ -148,7 +148,7 @@ __device__ __forceinline__ void block_count_range(const typename O::K *keys, uin
         for (int q = 0; q < 4; ++q) {
             const uint64_t pos = base + q * nth + threadIdx.x;
             const K x = O::ord(k[q]);
-            lt += pos < b && x < p;
+            lt += pos < b && O::lt(x, p);
             eq += pos < b && x == p;
         }
     }
@@ -627,9 +627,9 @@ __device__ __forceinline__ PassGeom pass_geom(const uint64_t *meta, uint64_t s) 
     }
     return g;
 }
-template <int PASS, class K>
+template <class O, int PASS, class K>
 __device__ __forceinline__ bool belongs_left(K k, K p) {
-    return PASS == 0 ? k < p : k <= p;
+    return PASS == 0 ? O::lt(k, p) : !O::lt(p, k);
 }
 
 // ---- split: position of the first misplaced element of every chunk ----------
@@ -692,7 +692,7 @@ __device__ __forceinline__ void part_split_item(TaskRef<PartSeg> tasks, uint32_t
                 const uint64_t a0 = ts + (uint64_t)(g0 + (uint32_t)hit) * kWave;
                 const uint64_t pos = a0 + (uint64_t)lane;
                 const bool in = pos < te;
-                const bool bl = belongs_left<PASS>(O::ord(ldg(keys + (in ? pos : te - 1))), p);
+                const bool bl = belongs_left<O, PASS>(O::ord(ldg(keys + (in ? pos : te - 1))), p);
                 const uint64_t m = __ballot(in && (side ? bl : !bl));
                 if (((m >> lane) & 1ull) && (uint32_t)__popcll(m & lanemask_lt()) == k)
                     sp[j] = (uint32_t)pos;
@@ -717,7 +717,7 @@ __device__ __forceinline__ void part_split_item(TaskRef<PartSeg> tasks, uint32_t
 #pragma unroll
         for (int q = 0; q < kQ; ++q) {
             const uint64_t pos = base + (uint64_t)q * kWave + lane;
-            const bool bl = belongs_left<PASS>(O::ord(kv[q]), p);
+            const bool bl = belongs_left<O, PASS>(O::ord(kv[q]), p);
             m[q] = __ballot(pos < x1 && (side ? bl : !bl));
         }
 #pragma unroll
@@ -798,7 +798,7 @@ __device__ __forceinline__ uint32_t ballot_subtile(const typename O::K *keys, ty
 #pragma unroll
     for (int q = 0; q < kPartItems; ++q) {
         const uint64_t pos = base + (uint64_t)q * kWave;
-        const bool bl = belongs_left<PASS>(O::ord(kv[q]), p);
+        const bool bl = belongs_left<O, PASS>(O::ord(kv[q]), p);
         m[q] = __ballot(pos < sc.end && (right ? bl : !bl));
         wcount += (uint32_t)__popcll(m[q]);
     }
@@ -1062,6 +1062,8 @@ hipError_t launch_partition_phase(int dt, bool pairs, const PartitionLaunch &L, 
         return pairs ? partition_t<OrdU64, true>(L, st) : partition_t<OrdU64, false>(L, st);
     case 3:
         return pairs ? partition_t<OrdF64, true>(L, st) : partition_t<OrdF64, false>(L, st);
+    case 4:
+        return pairs ? hipErrorInvalidValue : partition_t<OrdLogU32, false>(L, st);
     default:
         return hipErrorInvalidValue;
     }

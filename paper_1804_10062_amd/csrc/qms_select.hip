@@ -190,6 +190,8 @@ hipError_t launch_mom_pivot(int dt, const TaskRef<PartSeg> &tasks, uint32_t tile
     case 1: return mom_t<OrdF32>(tasks, tiles, overflow, init, ws, st);
     case 2: return mom_t<OrdU64>(tasks, tiles, overflow, init, ws, st);
     case 3: return mom_t<OrdF64>(tasks, tiles, overflow, init, ws, st);
+    // the log order is the integers' order: the radix select on the key bits
+    case 4: return mom_t<OrdU32>(tasks, tiles, overflow, init, ws, st);
     default: return hipErrorInvalidValue;
     }
 }

@@ -139,6 +139,40 @@ def uniform_f32(n: int, seed: int, stream: int = 4) -> np.ndarray:
     return ((u >> np.uint32(8)).astype(np.float32) * np.float32(2.0**-24)).astype(np.float32)
 
 
+def permutation_u32(n: int, seed: int, stream: int = 7) -> np.ndarray:
+    """A random order of 1..n (the paper's inputs: random permutations of
+    {1..n}).  Position i holds 1 + P(i) for a bijection P of [0, n): a
+    four-round balanced Feistel network on 2h-bit words (2^(2h) >= n) whose
+    round functions are SplitMix64 mixes of the other half, the round and
+    the (seed, stream) base; values that land at n or above are mapped again
+    until they fall inside [0, n) (cycle walking keeps it a bijection)."""
+    if n <= 0:
+        return np.zeros(0, dtype=np.uint32)
+    bits = max(2, int(n - 1).bit_length())
+    h = (bits + 1) // 2
+    mask = np.uint64((1 << h) - 1)
+    base = _mix(np.array([(seed * 0x100000001B3 + stream) % (1 << 64)], dtype=np.uint64))
+    rk = [_mix(base + np.full(1, r + 1, dtype=np.uint64) * _GAMMA)[0] for r in range(4)]
+
+    def feistel(x: np.ndarray) -> np.ndarray:
+        left, right = x >> np.uint64(h), x & mask
+        for r in range(4):
+            f = _mix(right ^ rk[r]) & mask
+            left, right = right, left ^ f
+        return (left << np.uint64(h)) | right
+
+    out = np.empty(n, dtype=np.uint32)
+    for a, c in _chunks(n):
+        b = a + c
+        v = feistel(np.arange(a, b, dtype=np.uint64))
+        bad = v >= np.uint64(n)
+        while bad.any():
+            v[bad] = feistel(v[bad])
+            bad = v >= np.uint64(n)
+        out[a:b] = (v + np.uint64(1)).astype(np.uint32)
+    return out
+
+
 def log_uniform_lengths(count: int, seed: int, lo_exp: int = 6,
                         hi_exp: int = 20, stream: int = 5) -> np.ndarray:
     """floor(2^(lo + (hi-lo) u)) clamped to [2^lo, 2^hi], u uniform in [0,1)."""

@@ -20,6 +20,7 @@ QMS_U32 = 0
 QMS_F32 = 1
 QMS_U64 = 2
 QMS_F64 = 3
+QMS_U32_LOG = 4  # uint32 keys compared by log(key) (an expensive comparison)
 
 QMS_OK = 0
 QMS_PENDING = 1
