@@ -84,12 +84,17 @@ typedef enum {
  * QuickMergesort"; pivot rule of Theorem 1: median of the keys at lo,
  * lo + (hi-lo)/2 and hi-1).
  *   d_keys  device pointer to n keys of type dt (4 or 8 bytes each).
- *   n       number of keys; 0 and 1 are no-ops returning QMS_OK.
- *   dt      QMS_U32, QMS_F32, QMS_U64 or QMS_F64.
+ *   n       number of keys; 0 and 1 are no-ops returning QMS_OK.  At most
+ *           2^32 + 2^25: a round whose range holds 2^32 keys or more
+ *           partitions it as blocks of 2^31 keys around the pivot of the
+ *           whole range and gathers the blocks' classes by in-place
+ *           rotations; the bound keeps every Mergesort side (at most half
+ *           a range) within the workspace's merge tables.
+ *   dt      QMS_U32, QMS_F32, QMS_U64, QMS_F64 or QMS_U32_LOG.
  *   stream  HIP stream to run on.
  * Errors: QMS_ERR_INVALID for NULL with n > 0 or a pointer that is not
- * device memory; QMS_ERR_ALIGN; QMS_ERR_UNSUPPORTED for an unknown dt;
- * QMS_ERR_NOMEM / QMS_ERR_HIP from the runtime.
+ * device memory; QMS_ERR_ALIGN; QMS_ERR_UNSUPPORTED for an unknown dt or
+ * n above the bound; QMS_ERR_NOMEM / QMS_ERR_HIP from the runtime.
  */
 int qms_sort(void *d_keys, uint64_t n, int dt, hipStream_t stream);
 

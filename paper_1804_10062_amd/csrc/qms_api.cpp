@@ -301,8 +301,8 @@ static int sort_entry(void *d_keys, uint32_t *d_vals, uint64_t n, int dt, hipStr
     if (n <= 1) return QMS_OK;
     if (d_keys == nullptr || (pairs && d_vals == nullptr))
         return set_error(QMS_ERR_INVALID, "NULL pointer with n > 1");
-    if (n >= (1ull << 32))
-        return set_error(QMS_ERR_UNSUPPORTED, "n must be below 2^32");
+    if (n > kMaxSortKeys)
+        return set_error(QMS_ERR_UNSUPPORTED, "n must be at most 2^32 + 2^25");
     int dev = 0, dev2 = 0;
     int rc = check_device_ptr(d_keys, "keys", &dev, dtype_wide(dt) ? 8 : 4);
     if (rc != QMS_OK) return rc;

@@ -54,7 +54,7 @@ struct Arena {
 
 struct Seg {
     uint32_t *keys, *vals;
-    uint32_t lo, hi;
+    uint64_t lo, hi;
     bool bad_split;  // the last round's smaller side held less than 1/16 of its range
 };
 
@@ -102,12 +102,10 @@ int upload(Arena &ar, size_t from, hipStream_t st) {
 
 thread_local std::vector<std::array<uint64_t, kScheduleWords>> g_schedule;
 
-// The median-of-medians pivots of the flagged segments of a round, in groups
+// The median-of-medians pivots of the table entries listed in idx, in groups
 // of at most caps.mom (one histogram each).
-int mom_pivots(int dt, const PartSeg *pt, uint32_t A, Arena &ar, Workspace &ws, hipStream_t st) {
-    std::vector<uint32_t> idx;
-    for (uint32_t a = 0; a < A; ++a)
-        if (pt[a].flags & kPivotMoM) idx.push_back(a);
+int mom_pivots(int dt, const PartSeg *pt, const std::vector<uint32_t> &idx, Arena &ar,
+               Workspace &ws, hipStream_t st) {
     for (size_t g0 = 0; g0 < idx.size(); g0 += ws.caps.mom) {
         const uint32_t n = (uint32_t)std::min<size_t>(ws.caps.mom, idx.size() - g0);
         const size_t mark = ar.used;
@@ -275,7 +273,7 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
     const uint64_t TF = std::max<uint64_t>(T0, tune.final_tile);
     // a final range: the base case sorts its tiles in place (L = 0), the
     // network finishes it if it is longer than one tile
-    auto final_task = [&](const Seg &g, uint32_t lo, uint32_t s) {
+    auto final_task = [&](const Seg &g, uint64_t lo, uint32_t s) {
         return SortSeg{kptr(g, lo), vptr(g, lo), nullptr, nullptr, s, 0, 0, T0, 0, 0};
     };
     // per-key bytes of an element (key and payload), for the profile
@@ -289,9 +287,9 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
     std::vector<SortSeg> ready_finals, next_finals, tasks, deferred, xf;
     for (uint32_t i = 0; i < segs.size(); ++i) {
         const Seg &g = segs[i];
-        const uint32_t s = g.hi - g.lo;
+        const uint64_t s = g.hi - g.lo;
         if (s > T0) active.push_back(i);
-        else if (s > 1) ready_finals.push_back(final_task(g, g.lo, s));
+        else if (s > 1) ready_finals.push_back(final_task(g, g.lo, (uint32_t)s));
     }
     while (!active.empty() || !ready_finals.empty()) {
         ArenaUse use(ws, st);
@@ -320,15 +318,40 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
                 tasks.push_back(f);
             }
         }
-        const uint32_t A = (uint32_t)active.size();
-        if (A > 0) {
-            // ---- partition: count + scan A, then read three counters back ----
+        if (!active.empty()) {
+            // ---- partition: count + scan A, then read three counters back.
+            // One table entry per range; a range of 2^32 keys or more takes
+            // blocks of at most kHugeBlock keys around the pivot of the whole
+            // range, gathered by rotations after the exchanges ----
+            struct Entry {
+                uint32_t seg;
+                uint64_t off;  // from the range's start
+                uint32_t s;
+            };
+            std::vector<Entry> ent;
+            std::vector<uint32_t> first_entry(active.size() + 1, 0);
+            for (size_t i = 0; i < active.size(); ++i) {
+                const Seg &g = segs[active[i]];
+                const uint64_t s = g.hi - g.lo;
+                first_entry[i] = (uint32_t)ent.size();
+                if (s < kHugeRange) {
+                    ent.push_back(Entry{(uint32_t)i, 0, (uint32_t)s});
+                } else {
+                    for (uint64_t o = 0; o < s; o += kHugeBlock)
+                        ent.push_back(Entry{(uint32_t)i, o, (uint32_t)std::min<uint64_t>(kHugeBlock, s - o)});
+                }
+            }
+            first_entry[active.size()] = (uint32_t)ent.size();
+            const uint32_t A = (uint32_t)ent.size();
+            if (A > ws.caps.segs) return set_error(QMS_ERR_UNSUPPORTED, "too many ranges for one round");
+            auto is_huge = [&](size_t i) { return first_entry[i + 1] - first_entry[i] > 1 ||
+                                                  segs[active[i]].hi - segs[active[i]].lo >= kHugeRange; };
             uint64_t sum_s = 0;
-            for (uint32_t i : active) sum_s += segs[i].hi - segs[i].lo;
+            for (const Entry &en : ent) sum_s += en.s;
             uint32_t TP = tune.partition_tile;
             for (;;) {
                 uint64_t tot = 0;
-                for (uint32_t i : active) tot += (segs[i].hi - segs[i].lo + TP - 1) / TP;
+                for (const Entry &en : ent) tot += (en.s + TP - 1) / TP;
                 if (tot <= ws.caps.tiles) break;
                 TP *= 2;
             }
@@ -338,15 +361,24 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
             uint32_t *ps = ar.take<uint32_t>(A + 1, &o_scan);
             if (!pt || !pc || !ps) return set_error(QMS_ERR_NOMEM, "task table arena too small");
             uint32_t toff = 0, coff = 0, max_nt = 0;
-            bool any_mom = false;
+            std::vector<uint32_t> mom_idx;
             pc[0] = 0;
             for (uint32_t a = 0; a < A; ++a) {
-                const Seg &g = segs[active[a]];
-                const uint32_t s = g.hi - g.lo;
+                const Entry &en = ent[a];
+                const size_t i = en.seg;
+                const Seg &g = segs[active[i]];
+                const uint32_t s = en.s;
                 const uint32_t nt = (s + TP - 1) / TP;
-                const uint32_t fl = g.bad_split ? kPivotMoM : 0u;
-                any_mom |= g.bad_split;
-                pt[a] = PartSeg{g.keys, g.vals, g.lo, s, toff, nt, coff, a, fl, 0};
+                // the pivot comes from the round state: the median of the
+                // medians of three (selected below), or for the blocks of a
+                // huge range the median of three of the whole range
+                const bool huge = is_huge(i);
+                const bool mom = g.bad_split && !huge;
+                if (mom) mom_idx.push_back(a);
+                const uint32_t fl = (mom || huge) ? kPivotMoM : 0u;
+                // the entry's keys start at its own first cell (position 0)
+                pt[a] = PartSeg{kptr(g, g.lo + en.off), vptr(g, g.lo + en.off), 0, s, toff, nt, coff,
+                                a, fl, 0};
                 toff += nt;
                 coff += (s + 4095) / 4096 + 2;
                 pc[a + 1] = toff;
@@ -362,9 +394,17 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
                 int rc = upload(ar, 0, st);
                 if (rc != QMS_OK) return rc;
             }
-            if (any_mom) {
-                int rc = mom_pivots(dt, pt, A, ar, ws, st);
+            if (!mom_idx.empty()) {
+                int rc = mom_pivots(dt, pt, mom_idx, ar, ws, st);
                 if (rc != QMS_OK) return rc;
+            }
+            for (size_t i = 0; i < active.size(); ++i) {
+                if (!is_huge(i)) continue;
+                const Seg &g = segs[active[i]];
+                const hipError_t e0 = launch_huge_pivot(dt, kptr(g, g.lo), g.hi - g.lo, ws.meta,
+                                                        first_entry[i],
+                                                        first_entry[i + 1] - first_entry[i], st);
+                if (e0 != hipSuccess) return hip_error(e0, "pivot of a huge range");
             }
             PartitionLaunch L{};
             L.tasks.A = A;
@@ -405,8 +445,9 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
                 const uint64_t c_lt = ws.h_res[4 * a], c_eq = ws.h_res[4 * a + 1];
                 const uint64_t X = ws.h_res[4 * a + 2];
                 // c_eq is 0 when the pivot-equal keys stay in the ">= p" side;
-                // then the "< p" side is not empty
-                if ((c_eq == 0 && c_lt == 0) || c_lt + c_eq > s)
+                // then the "< p" side is not empty (a block of a huge range
+                // need not hold the pivot: all its keys may exceed it)
+                if ((c_eq == 0 && c_lt == 0 && !is_huge(ent[a].seg)) || c_lt + c_eq > s)
                     return set_error(QMS_ERR_HIP, "partition returned inconsistent counts");
                 const uint64_t nch = chunk_count(X, s, tune.chunk_span);
                 ca[a + 1] = ca[a] + (uint32_t)nch;
@@ -461,29 +502,60 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
                     return hip_error(e, "swap B");
             }
 
+            // ---- a huge range: gather the blocks' classes, [< p | == p | > p]
+            // of each block, into those of the whole range (two rotations per
+            // block after the first) ----
+            std::vector<uint64_t> agg_lt(active.size(), 0), agg_eq(active.size(), 0);
+            for (size_t i = 0; i < active.size(); ++i) {
+                const Seg &g = segs[active[i]];
+                uint64_t nl = 0, ne = 0, ng = 0;  // classes gathered so far
+                for (uint32_t a = first_entry[i]; a < first_entry[i + 1]; ++a) {
+                    const uint64_t l = ws.h_res[4 * a], q = ws.h_res[4 * a + 1];
+                    const uint64_t r = ent[a].s - l - q;
+                    if (a > first_entry[i]) {
+                        const uint64_t pos0 = g.lo + nl + ne + ng;  // the block's first cell
+                        // its "<" part before the gathered "==" and ">" parts
+                        hipError_t e1 = launch_rotate(wide, pairs, g.keys, g.vals, g.lo + nl,
+                                                      pos0, pos0 + l, st);
+                        // its "==" part before the gathered ">" part
+                        if (e1 == hipSuccess)
+                            e1 = launch_rotate(wide, pairs, g.keys, g.vals, g.lo + nl + l + ne,
+                                               pos0 + l, pos0 + l + q, st);
+                        if (e1 != hipSuccess) return hip_error(e1, "gathering a huge range");
+                    }
+                    nl += l;
+                    ne += q;
+                    ng += r;
+                }
+                agg_lt[i] = nl;
+                agg_eq[i] = ne;
+            }
+
             // ---- side choice (Fig. 2 sort(): the smaller side is mergesorted
             // with the larger side as swap space; the loop keeps the larger) ----
             next.clear();
-            for (uint32_t a = 0; a < A; ++a) {
-                Seg &g = segs[active[a]];
-                const uint32_t s = g.hi - g.lo;
-                const uint32_t c_lt = ws.h_res[4 * a], c_eq = ws.h_res[4 * a + 1];
-                const uint32_t b1 = g.lo + c_lt, b2 = b1 + c_eq;
-                const uint32_t mL = c_lt, mR = g.hi - b2;
+            for (size_t i = 0; i < active.size(); ++i) {
+                Seg &g = segs[active[i]];
+                const uint64_t s = g.hi - g.lo;
+                const uint64_t c_lt = agg_lt[i], c_eq = agg_eq[i];
+                const uint64_t b1 = g.lo + c_lt, b2 = b1 + c_eq;
+                const uint64_t mL = c_lt, mR = g.hi - b2;
+                if (std::min(mL, mR) >= (1ull << 32))
+                    return set_error(QMS_ERR_UNSUPPORTED, "a Mergesort side of 2^32 keys or more");
                 SortSeg t{};
                 if (mL <= mR) {
                     t.keys = kptr(g, g.lo);
                     t.vals = vptr(g, g.lo);
                     t.bkeys = kptr(g, b2);
                     t.bvals = vptr(g, b2);
-                    t.m = mL;
+                    t.m = (uint32_t)mL;
                     g.lo = b2;
                 } else {
                     t.keys = kptr(g, b2);
                     t.vals = vptr(g, b2);
                     t.bkeys = kptr(g, b1 - mR);
                     t.bvals = vptr(g, b1 - mR);
-                    t.m = mR;
+                    t.m = (uint32_t)mR;
                     g.hi = b1;
                 }
                 set_levels(t);
@@ -491,19 +563,19 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
                 // [s/16, 15 s/16] makes the next pivot of this array the
                 // median of the medians of three; the one after returns to
                 // median-of-3
-                const bool mom = (pt[a].flags & kPivotMoM) != 0;
-                g.bad_split = (uint64_t)std::min(mL, mR) * 16 < s;
+                const bool mom = g.bad_split && !is_huge(i);
+                g.bad_split = std::min(mL, mR) * 16 < s;
                 if (t.m > 1) tasks.push_back(t);
                 if (log)
                     g_schedule.push_back(
                         {s, c_lt, c_eq, (uint64_t)(s - c_lt - c_eq), t.L, mom ? 1ull : 0ull});
                 // the larger side goes on in the loop unless it is small
                 // enough for X
-                const uint32_t s2 = g.hi - g.lo;
+                const uint64_t s2 = g.hi - g.lo;
                 if (s2 <= TF) {
-                    if (s2 > 1) next_finals.push_back(final_task(g, g.lo, s2));
+                    if (s2 > 1) next_finals.push_back(final_task(g, g.lo, (uint32_t)s2));
                 } else {
-                    next.push_back(active[a]);
+                    next.push_back(active[i]);
                 }
             }
             active.swap(next);
@@ -610,7 +682,7 @@ int mom_pivot_of(int dt, const uint32_t *keys, uint64_t n, Workspace &ws, hipStr
     ArenaUse use(ws, st);
     Arena &ar = use.ar;
     PartSeg seg{(uint32_t *)keys, nullptr, 0, (uint32_t)n, 0, 0, 0, 0, kPivotMoM, 0};
-    int rc = mom_pivots(dt, &seg, 1, ar, ws, st);
+    int rc = mom_pivots(dt, &seg, std::vector<uint32_t>{0}, ar, ws, st);
     if (rc != QMS_OK) return rc;
     uint64_t p = 0;
     hipError_t e = hipMemcpyAsync(&p, ws.meta + M_PIVOT, sizeof(p), hipMemcpyDeviceToHost, st);
@@ -636,12 +708,13 @@ int sort_segments(int dt, bool pairs, const HostSeg *segs, size_t count, Workspa
     for (size_t i = 0; i < count; ++i) {
         const HostSeg &h = segs[i];
         if (h.n <= 1) continue;
-        if (h.n >= (1ull << 32)) return set_error(QMS_ERR_UNSUPPORTED, "segment of 2^32 keys or more");
-        if (group.size() == ws.caps.segs || group_keys + h.n >= (1ull << 32)) {
+        if (h.n > kMaxSortKeys) return set_error(QMS_ERR_UNSUPPORTED, "array too large");
+        // an array of 2^32 keys or more is a group of its own
+        if (group.size() == ws.caps.segs || group_keys + h.n >= kHugeRange) {
             int rc = flush();
             if (rc != QMS_OK) return rc;
         }
-        group.push_back(Seg{h.keys, h.vals, 0, (uint32_t)h.n, false});
+        group.push_back(Seg{h.keys, h.vals, 0, h.n, false});
         group_keys += h.n;
     }
     return flush();

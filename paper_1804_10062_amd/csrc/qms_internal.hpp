@@ -29,6 +29,20 @@ constexpr uint64_t kCapSplits = (1ull << 31) / kMergeTile + kCapSegs + 16;
 constexpr uint32_t kCapMoM = 2048;
 // Merge levels a task can need: ceil(log2(2^31 / 8192)).
 constexpr int kMaxLevels = 18;
+// Ranges of at least kHugeRange keys are partitioned as blocks of at most
+// kHugeBlock keys (qms_huge.hip).  An array may hold up to kMaxSortKeys keys:
+// its Mergesort sides (at most half of a range) then stay within the merge
+// tables of a workspace (kCapSplits tiles of kMergeTile keys).
+#ifndef QMS_HUGE_RANGE_LOG2
+#define QMS_HUGE_RANGE_LOG2 32
+#endif
+#ifndef QMS_HUGE_BLOCK_LOG2
+#define QMS_HUGE_BLOCK_LOG2 31
+#endif
+constexpr uint64_t kHugeRange = 1ull << QMS_HUGE_RANGE_LOG2;
+constexpr uint64_t kHugeBlock = 1ull << QMS_HUGE_BLOCK_LOG2;
+static_assert(kHugeBlock < kHugeRange && kHugeRange <= (1ull << 32), "block partitions");
+constexpr uint64_t kMaxSortKeys = (1ull << 32) + (1ull << 25);
 // Largest final_tile: ranges of at most this many keys may leave the loop
 // for the in-place bitonic network.
 constexpr uint64_t kMaxFinalTile = 1ull << 30;
@@ -159,6 +173,14 @@ hipError_t launch_tile_merge(int dt, bool pairs, const TaskRef<SortSeg> &tasks, 
 // Workgroups of one range of m keys in pass L (base tile T).
 uint32_t bitonic_items(const BitonicLaunch &L, uint64_t m, uint32_t T);
 hipError_t launch_bitonic_pass(int dt, bool pairs, const BitonicLaunch &L, hipStream_t st);
+// Ranges of 2^32 keys or more (qms_huge.hip): the median of three of
+// [keys, keys + s) as the pivot of the `blocks` round-state slots from
+// slot0 on; the rotation of [a, c) at b (so that [b, c) comes before [a, b)),
+// positions in keys of the key width (wide: 64 bits), payloads alike.
+hipError_t launch_huge_pivot(int dt, const uint32_t *keys_words, uint64_t s, uint64_t *meta,
+                             uint32_t slot0, uint32_t blocks, hipStream_t st);
+hipError_t launch_rotate(bool wide, bool pairs, uint32_t *keys_words, uint32_t *vals, uint64_t a,
+                         uint64_t b, uint64_t c, hipStream_t st);
 // One merge pass (2-way or 4-way) of the tasks listed: every task's pass at
 // binary level `level`, or with `step` the step-th pass of every task (its
 // level from its level count).  tiles: merge tiles of the listed tasks

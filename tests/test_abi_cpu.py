@@ -43,7 +43,8 @@ def test_argument_errors_before_device_work():
     assert lib.qms_sort(None, 5, qms.QMS_U32, None) == qms.QMS_ERR_INVALID
     assert lib.qms_sort_pairs(None, None, 5, qms.QMS_U32, None) == qms.QMS_ERR_INVALID
     assert lib.qms_sort(ctypes.c_void_p(0x1002), 5, qms.QMS_U32, None) == qms.QMS_ERR_ALIGN
-    assert lib.qms_sort(ctypes.c_void_p(0x1000), 1 << 32, qms.QMS_U32, None) == qms.QMS_ERR_UNSUPPORTED
+    assert lib.qms_sort(ctypes.c_void_p(0x1000), (1 << 32) + (1 << 25) + 1, qms.QMS_U32,
+                            None) == qms.QMS_ERR_UNSUPPORTED
     assert lib.qms_sort_batch(None, None, None, None, 0, qms.QMS_U32, None) == qms.QMS_OK
     assert lib.qms_sort_batch(None, None, None, None, 3, qms.QMS_U32, None) == qms.QMS_ERR_INVALID
 

@@ -435,3 +435,17 @@ def test_mom_pivot_f32_total_order():
     x = inputs.normal_f32(3001, seed=2)
     p = np.array([oracle.mom_pivot(x)], dtype=np.uint32).view(np.float32)[0]
     assert np.count_nonzero(x <= p) >= 2 * (3001 // 6) and np.count_nonzero(x >= p) >= 2 * (3001 // 6)
+
+
+def test_weyl_sequence_with_duplicates_closed_form():
+    """The construction of the sort beyond 2^32 keys (test_gpu_huge.py),
+    over 12-bit words: key[j] = (A j + B) mod 2^12 for j < 2^12 (A odd: a
+    permutation of the words) followed by d copies of 7.  The oracle's sort
+    is 0..6, then d + 1 sevens, then 8..2^12 - 1."""
+    M, A, B, d = 1 << 12, 0x9E3779B1, 0x7F4A7C15, 300
+    x = np.concatenate([((A * np.arange(M, dtype=np.uint64) + B) % M).astype(np.uint32),
+                        np.full(d, 7, dtype=np.uint32)])
+    s, _, _ = oracle.sort(x)
+    i = np.arange(M + d, dtype=np.int64)
+    want = np.where(i <= 7, i, np.where(i <= 7 + d, 7, i - d))
+    np.testing.assert_array_equal(s.astype(np.int64), want)
