@@ -91,7 +91,12 @@ typedef enum {
  *           rotations; the bound keeps every Mergesort side (at most half
  *           a range) within the workspace's merge tables.
  *   dt      QMS_U32, QMS_F32, QMS_U64, QMS_F64 or QMS_U32_LOG.
- *   stream  HIP stream to run on.
+ *   stream  HIP stream to run on.  When `stream` is being captured into a
+ *           HIP graph, the call reads nothing back: its rounds are planned
+ *           on the device, as qms_sort_batch plans a batch of one array
+ *           (n below 2^32; the loop then runs down to the base tile), and
+ *           it returns at once.  A first call on the stream outside the
+ *           capture allocates the stream's workspace.
  * Errors: QMS_ERR_INVALID for NULL with n > 0 or a pointer that is not
  * device memory; QMS_ERR_ALIGN; QMS_ERR_UNSUPPORTED for an unknown dt or
  * n above the bound; QMS_ERR_NOMEM / QMS_ERR_HIP from the runtime.

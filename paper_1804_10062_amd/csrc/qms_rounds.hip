@@ -130,13 +130,14 @@ __device__ __forceinline__ uint32_t scan_carry(uint32_t v, uint32_t *tmp, uint32
 }
 
 // ---- init: segment states from the offsets ------------------------------------------
+// offsets == nullptr: one segment of single_n keys (a single array).
 __global__ __launch_bounds__(kBlock) void k_rounds_init(DevSeg *seg, const uint64_t *offsets,
-                                                        uint32_t j0, uint32_t nseg,
-                                                        uint32_t *keys_base, uint32_t *vals_base,
-                                                        uint32_t ew, uint32_t T0,
-                                                        uint32_t *work) {
+                                                        uint64_t single_n, uint32_t j0,
+                                                        uint32_t nseg, uint32_t *keys_base,
+                                                        uint32_t *vals_base, uint32_t ew,
+                                                        uint32_t T0, uint32_t *work) {
     for (uint32_t i = blockIdx.x * kBlock + threadIdx.x; i < nseg; i += gridDim.x * kBlock) {
-        const uint64_t a = offsets[j0 + i], b = offsets[j0 + i + 1];
+        const uint64_t a = offsets ? offsets[j0 + i] : 0, b = offsets ? offsets[j0 + i + 1] : single_n;
         const uint64_t n = b - a;
         DevSeg d;
         d.keys = keys_base + ew * a;
@@ -583,8 +584,9 @@ void carve_rounds_state(Workspace *ws, char *b, uint32_t segs) {
     ws->r_status = (uint32_t *)take(4 * 4);
 }
 
-// The batch [j0, j0 + count) of the offsets, all segments below 2^32 keys.
-// h_len: the host's copy of their lengths (for the schedule's bounds).
+// The segments [h_off[j], h_off[j + 1]) of a batch, all below 2^32 keys;
+// h_off: the host's copy of the offsets (for the schedule's bounds),
+// d_offsets: the device's, or nullptr for a single array (h_off = {0, n}).
 int sort_batch_device_rounds(int dt, bool pairs, char *keys_base, uint32_t *vals_base,
                              const uint64_t *d_offsets, const uint64_t *h_off, uint32_t nseg,
                              Workspace &ws, hipStream_t st) {
@@ -678,7 +680,7 @@ int sort_batch_device_rounds(int dt, bool pairs, char *keys_base, uint32_t *vals
         P.res = ws.res;
 
         hipLaunchKernelGGL(k_rounds_init, dim3(std::min<uint32_t>((G + kBlock - 1) / kBlock, 1024)),
-                           dim3(kBlock), 0, st, P.seg, d_offsets, g0, G, (uint32_t *)keys_base,
+                           dim3(kBlock), 0, st, P.seg, d_offsets, h_off[1], g0, G, (uint32_t *)keys_base,
                            vals_base, ew, T0, P.work);
         if ((e = hipGetLastError()) != hipSuccess) return hip_error(e, "round state init");
 

@@ -205,3 +205,60 @@ def test_graph_capture_20000_arrays():
         for j in picks:
             got = o[int(off[j]):int(off[j + 1])].cpu().numpy()
             np.testing.assert_array_equal(got.view(np.uint32), wants[j].view(np.uint32))
+
+
+@needs_gpu
+@pytest.mark.parametrize("kind", ["u32", "f32", "pairs", "u64"])
+@pytest.mark.parametrize("n", [5000, 16385, 1_000_003])
+def test_qms_sort_captured_in_a_graph(kind, n):
+    """qms_sort and qms_sort_pairs under stream capture: the rounds are
+    planned on the device (nothing read back), the graph replays bit-exact
+    with the oracle, with eager work between replays."""
+    rng = np.random.default_rng(n)
+    if kind == "f32":
+        x = inputs.normal_f32(n, seed=n % 7)
+        src = to_device(x)
+    elif kind == "u64":
+        x = rng.integers(0, 2 ** 64, n, dtype=np.uint64)
+        src = torch.from_numpy(x.view(np.int64)).cuda()
+    else:
+        x = inputs.uniform_u32(n, seed=n % 7) if kind == "u32" else inputs.make_keys("zipf", n, seed=3)
+        src = to_device(x)
+    pairs = kind == "pairs"
+    s = torch.cuda.Stream()
+    work = src.clone()
+    vals = torch.arange(n, dtype=torch.int32, device="cuda") if pairs else None
+
+    def run():
+        if pairs:
+            qms.qms_sort_pairs(work, vals, stream=s)
+        else:
+            qms.qms_sort(work, stream=s)
+
+    with torch.cuda.stream(s):
+        run()  # warm-up outside the capture: the stream's workspace
+    s.synchronize()
+    g = torch.cuda.CUDAGraph()
+    work.copy_(src)
+    if pairs:
+        vals.copy_(torch.arange(n, dtype=torch.int32, device="cuda"))
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=s):
+        run()
+    want, _, _ = oracle.sort(x, counted=False)
+    for _ in range(3):
+        work.copy_(src)
+        if pairs:
+            vals.copy_(torch.arange(n, dtype=torch.int32, device="cuda"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = work.cpu().numpy()
+        np.testing.assert_array_equal(got.view(np.uint8), want.view(np.uint8))
+        if pairs:
+            vo = vals.cpu().numpy().astype(np.int64)
+            assert np.array_equal(np.sort(vo), np.arange(n))
+            np.testing.assert_array_equal(x[vo], want)
+        _ = (src.float() * 2).sum().item()  # eager work between replays
+    with torch.cuda.stream(s):
+        qms.qms_batch_check(stream=s)
