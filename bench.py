@@ -647,10 +647,9 @@ def main():
         finally:
             autotune.reset_tuning()
 
-    # the recursion stopper: a range a partition round leaves with at most
-    # final_tile keys leaves the loop for one Mergesort into the fixed
-    # scratch buffer (8192: the loop runs down to the base tile, as in the
-    # paper)
+    # X at the loop level: a range a partition round leaves with at most
+    # final_tile keys leaves the loop and is sorted in place by the bitonic
+    # network (8192: the loop runs down to the base tile, as in the paper)
     final_sweep = None
     if not args.only_uniform and not args.no_threshold_sweep:
         from paper_1804_10062_amd import autotune

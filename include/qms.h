@@ -38,10 +38,11 @@
  *     results back to the host once per partition round, so they return
  *     only after the sort has completed on the stream.
  *   - Extra device memory: a library-owned workspace per (device, stream)
- *     of fixed size, about 400 MB (tile counters, run samples, round state
- *     and a 128 MiB scratch buffer for the last, small ranges; nothing
- *     proportional to n), allocated on first use and kept until
- *     qms_release_workspaces().
+ *     of fixed size, about 320 MB (tile counters, run samples, split
+ *     vectors, task tables and the round state of device-planned batches;
+ *     nothing proportional to n), allocated on first use and kept until
+ *     qms_release_workspaces().  Every sort is in place: no key or payload
+ *     is ever held outside the caller's arrays.
  *   - Return values are qms_status codes; no C++ exception crosses this
  *     interface.  The message of the last failure on the calling thread is
  *     available from qms_last_error().
@@ -160,8 +161,9 @@ int qms_batch_check(hipStream_t stream);
  * hipMalloc or hipFree, no pinned host memory, no events.  The kernels' tile
  * counters, split vectors and run samples live in a fixed 32 MiB device
  * array of the library (one per GPU, held until the process ends) instead
- * of a cached workspace, and the loop always runs down to the base tile
- * (final_tile is not used).  Calls on one GPU share that array: calls are
+ * of a cached workspace (the last ranges are finished in place, as by
+ * qms_sort, so no other buffer is needed).  Calls on one GPU share that
+ * array: calls are
  * serialised on the host, but calls whose GPU work overlaps (other streams
  * of the same device, not synchronised between the calls) race on it.  Like
  * qms_sort it reads partition results back once per round.
@@ -313,16 +315,20 @@ int qms_profile_end(qms_kernel_stat *out, int max_entries, int *n_out);
  *                   2048 for 64-bit keys, whose network costs more per
  *                   level than a merge level.
  *   final_tile      a range that a partition round leaves with at most this
- *                   many keys leaves the QuickMergesort loop (a recursion
- *                   stopper; the paper's loop continues to the base tile):
- *                   one Mergesort finishes it, its swap space taken from a
- *                   fixed 128 MiB scratch buffer of the workspace (2^24
- *                   elements, whatever n is; a round runs as many as fit).
- *                   Every input array above the base tile is partitioned at
- *                   least once; arrays of at most the base tile are sorted
- *                   in place by the base case.  A power of two in
- *                   [8192, 2^24]; 8192 keeps every range in the loop down to
- *                   the base tile, as in the paper.
+ *                   many keys leaves the QuickMergesort loop and is sorted
+ *                   in place by X = a bitonic network (QuickXsort with X at
+ *                   the loop level; the paper's loop continues to the base
+ *                   tile): tiles by the base case, then the network's
+ *                   stages above the tile, every exchange between two cells
+ *                   of the range.  It adds O(F log^2 F) comparisons for a
+ *                   range of F keys.  Every input array above the base tile
+ *                   is partitioned at least once; arrays of at most the
+ *                   base tile are sorted in place by the base case.  A
+ *                   power of two in [8192, 2^30]; 8192 keeps every range in
+ *                   the loop down to the base tile, as in the paper.  Used
+ *                   by the host-planned loop (qms_sort, qms_sort_pairs,
+ *                   qms_sort_noalloc, the server); device-planned rounds
+ *                   loop down to the base tile.
  * qms_set_tuning returns QMS_ERR_INVALID for values out of range (nothing is
  * changed then).  The package's autotuner (paper_1804_10062_amd/autotune.py)
  * picks them for a workload by timing sorts of a sample.

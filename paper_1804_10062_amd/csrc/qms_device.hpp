@@ -136,8 +136,8 @@ struct PartSeg {
 constexpr uint32_t kPivotMoM = 1;
 
 // One Mergesort of a round: m keys in the data region D, m cells of swap
-// space in the buffer region Bf (the other side of the partition, or the
-// library's scratch buffer for a final range), L merge levels over runs of
+// space in the buffer region Bf (the other side of the partition; a final
+// range has L = 0 and no buffer), L merge levels over runs of
 // w0 << level keys; the base case swaps into Bf when the pass count is odd.
 // The pointers address element 0 of each region (keys of the sort's width).
 struct SortSeg {
@@ -385,13 +385,26 @@ __device__ __forceinline__ uint64_t median3(uint64_t a, uint64_t b, uint64_t c) 
     return lo > m ? lo : m;
 }
 
+// Median of three order-mapped keys by the policy's comparison (three
+// comparisons, as Theorem 1's proof charges; for the integer orders the same
+// value as median3).
+template <class O>
+__device__ __forceinline__ typename O::K median3_by(typename O::K a, typename O::K b,
+                                                    typename O::K c) {
+    using K = typename O::K;
+    const bool ba = O::lt(b, a);
+    const K lo = ba ? b : a, hi = ba ? a : b;
+    const K m = O::lt(c, hi) ? c : hi;
+    return O::lt(m, lo) ? lo : m;
+}
+
 // Pivot of the range [lo, hi): median of the keys at lo, lo + s/2 and hi - 1.
 template <class O>
 __device__ __forceinline__ typename O::K pivot_of(const typename O::K *keys, uint64_t lo,
                                                   uint64_t hi) {
     const uint64_t s = hi - lo;
-    return median3(O::ord(ldg(keys + lo)), O::ord(ldg(keys + lo + s / 2)),
-                   O::ord(ldg(keys + hi - 1)));
+    return median3_by<O>(O::ord(ldg(keys + lo)), O::ord(ldg(keys + lo + s / 2)),
+                         O::ord(ldg(keys + hi - 1)));
 }
 
 }  // namespace qms

@@ -27,7 +27,7 @@ template <class O>
 __global__ void k_huge_pivot(const typename O::K *keys, uint64_t s, uint64_t *meta_all,
                              uint32_t slot0, uint32_t blocks) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const auto p = median3(O::ord(keys[0]), O::ord(keys[s / 2]), O::ord(keys[s - 1]));
+    const auto p = median3_by<O>(O::ord(keys[0]), O::ord(keys[s / 2]), O::ord(keys[s - 1]));
     for (uint32_t b = 0; b < blocks; ++b) meta_all[(uint64_t)(slot0 + b) * M_COUNT + M_PIVOT] = p;
 }
 
@@ -67,9 +67,12 @@ hipError_t launch_huge_pivot(int dt, const uint32_t *keys_words, uint64_t s, uin
                              uint32_t slot0, uint32_t blocks, hipStream_t st) {
     switch (dt) {
     case 0:
-    case 4:  // the log order is the integers' order
         hipLaunchKernelGGL(k_huge_pivot<OrdU32>, dim3(1), dim3(64), 0, st, keys_words, s, meta,
                            slot0, blocks);
+        break;
+    case 4:
+        hipLaunchKernelGGL(k_huge_pivot<OrdLogU32>, dim3(1), dim3(64), 0, st, keys_words, s,
+                           meta, slot0, blocks);
         break;
     case 1:
         hipLaunchKernelGGL(k_huge_pivot<OrdF32>, dim3(1), dim3(64), 0, st, keys_words, s, meta,

@@ -57,7 +57,7 @@ struct WsCaps {
     size_t tab_bytes;    // bytes of one task-table arena
 };
 WsCaps default_caps();
-// Caps for one array of at most nmax elements, no scratch buffer.
+// Caps for one array of at most nmax elements (no batch round state).
 WsCaps single_array_caps(uint64_t nmax);
 // Device bytes of a workspace with these caps (one block).
 size_t workspace_device_bytes(const WsCaps &c);

@@ -7,9 +7,9 @@
 // workspace; the host side keeps its small task-table arenas and readback
 // words in static host memory.  Nothing is allocated per call: no hipMalloc,
 // no hipFree, no pinned host memory, no events.  The array is sized for one
-// array of at most kNoAllocMaxKeys keys, so the loop runs down to the base
-// tile (the final ranges' scratch buffer of the cached workspaces is not
-// part of it).
+// array of at most kNoAllocMaxKeys keys; the loop's last ranges are sorted
+// in place by the bitonic X, as in qms_sort, so no buffer beyond it is
+// needed.
 //
 // Each device holds its own copy of `scratch` at its own address; host code
 // takes that address from hipGetSymbolAddress once per device (with the
