@@ -95,8 +95,9 @@ typedef enum {
  *   stream  HIP stream to run on.  When `stream` is being captured into a
  *           HIP graph, the call reads nothing back: its rounds are planned
  *           on the device, as qms_sort_batch plans a batch of one array
- *           (n below 2^32; the loop then runs down to the base tile), and
- *           it returns at once.  A first call on the stream outside the
+ *           (n below 2^32; the range left at final_tile keys or below is
+ *           sorted by the bitonic network, as without capture), and it
+ *           returns at once.  A first call on the stream outside the
  *           capture allocates the stream's workspace.
  * Errors: QMS_ERR_INVALID for NULL with n > 0 or a pointer that is not
  * device memory; QMS_ERR_ALIGN; QMS_ERR_UNSUPPORTED for an unknown dt or
@@ -123,13 +124,15 @@ int qms_sort_pairs(void *d_keys, uint32_t *d_vals, uint64_t n, int dt,
  * device: the call enqueues a fixed schedule of launches on `stream` and
  * returns without waiting for the GPU (no readback, no synchronisation),
  * so it may be captured into a HIP graph (after one call outside the
- * capture, which allocates the stream's workspace).  The schedule: rounds
- * with the paper's pivot rule (median-of-3, after an unbalanced round the
- * median of the medians of three: Sec. "Worst-Case Efficient
- * QuickMergeSort"), then rounds in which every range still in the loop takes
- * the median-of-medians pivot; their number follows from the longest
- * segment and guarantees that every segment is sorted.  The loop runs down
- * to the base tile (final_tile is not used).
+ * capture, which allocates the stream's workspace).  The schedule: a
+ * number of rounds that follows from the longest segment (1.5 rounds per
+ * binary level above the base tile, plus two), with the paper's pivot rule
+ * (median-of-3, after an unbalanced round the median of the medians of
+ * three: Sec. "Worst-Case Efficient QuickMergeSort"); then every range still
+ * above the base tile is sorted in place by a bitonic network (X at the
+ * loop level, as the single-array loop finishes its last range), so every
+ * segment is sorted whatever its keys.  final_tile is not used: the loop
+ * runs down to the base tile while the rounds last.
  *   d_keys       device keys of all segments.
  *   d_vals       device uint32 payloads (one per key), or NULL for keys
  *                only.

@@ -316,8 +316,9 @@ static int sort_entry(void *d_keys, uint32_t *d_vals, uint64_t n, int dt, hipStr
     rc = get_workspace(dev, stream, &ws);
     if (rc != QMS_OK) return rc;
     // Under stream capture nothing may be read back: the rounds are planned
-    // on the device, as for a batch of one array (the loop then runs down
-    // to the base tile).
+    // on the device, as for a batch of one array, whose last range (at most
+    // final_tile keys) the bitonic network sorts, as the host-planned loop
+    // does.
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     if (stream != nullptr && hipStreamIsCapturing(stream, &cap) == hipSuccess &&
         cap == hipStreamCaptureStatusActive) {
@@ -325,7 +326,8 @@ static int sort_entry(void *d_keys, uint32_t *d_vals, uint64_t n, int dt, hipStr
             return set_error(QMS_ERR_UNSUPPORTED, "a captured sort takes fewer than 2^32 keys");
         const uint64_t h_off[2] = {0, n};
         return sort_batch_device_rounds(dt, pairs, (char *)d_keys, pairs ? d_vals : nullptr,
-                                        nullptr, h_off, 1, *ws, stream);
+                                        nullptr, h_off, 1, current_tuning().final_tile, *ws,
+                                        stream);
     }
     HostSeg seg{(uint32_t *)d_keys, pairs ? d_vals : nullptr, n};
     return sort_segments(dt, pairs, &seg, 1, *ws, stream, true);

@@ -548,7 +548,7 @@ __device__ __forceinline__ void tile_sort_block(typename O::K *sk, uint32_t *sv,
     for (int i = 0; i < ITEMS; ++i) s[nat_idx<ITEMS>(base + i)] = r[i];
     __syncthreads();
     static_assert((uint32_t)(NT * ITEMS) / kSampleStride <= (uint32_t)NT, "one sample per thread");
-    if (!MERGE_ONLY && tid * kSampleStride < len)
+    if (!MERGE_ONLY && samples != nullptr && tid * kSampleStride < len)
         stg(samples + tid, TE::key(s[nat_idx<ITEMS>(tid * kSampleStride)]));
 #pragma unroll 8
     for (int q = 0; q < ITEMS; ++q) {
@@ -584,9 +584,11 @@ __device__ __forceinline__ void tile_sort_item(TaskRef<SortSeg> tasks, uint32_t 
     K *dk = (K *)(swap ? g.bkeys : g.keys) + t0;
     uint32_t *sv = PAIRS ? g.vals + t0 : nullptr;
     uint32_t *dv = PAIRS ? (swap ? g.bvals : g.vals) + t0 : nullptr;
+    // run samples for the first merge pass (none for a range sorted in place)
     tile_sort_block<O, PAIRS>(sk, sv, dk, dv, len, run, swap,
-                              samples + (uint64_t)g.split_off * kSamplesPerTile +
-                                  t0 / kSampleStride);
+                              g.L ? samples + (uint64_t)g.split_off * kSamplesPerTile +
+                                        t0 / kSampleStride
+                                  : nullptr);
 }
 template <class O, bool PAIRS, bool LOOP>
 __global__ __launch_bounds__(kSortThreads) void k_tile_sort(TaskRef<SortSeg> tasks, uint32_t first,
@@ -609,11 +611,12 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_sort(TaskRef<SortSeg> tas
 template <class O, bool PAIRS>
 static hipError_t tile_sort_t(const TaskRef<SortSeg> &tasks, uint32_t tiles, uint32_t overflow,
                               double bytes, const Workspace &ws, hipStream_t st) {
-    if (tiles == 0) return hipSuccess;
+    if (tiles == 0 && overflow == 0) return hipSuccess;
     ProfScope prof(st, K_TILE_SORT, bytes);
     using K = typename O::K;
-    hipLaunchKernelGGL((k_tile_sort<O, PAIRS, false>), dim3(tiles), dim3(kSortThreads), 0, st,
-                       tasks, 0u, (K *)ws.samples[0]);
+    if (tiles)
+        hipLaunchKernelGGL((k_tile_sort<O, PAIRS, false>), dim3(tiles), dim3(kSortThreads), 0, st,
+                           tasks, 0u, (K *)ws.samples[0]);
     if (overflow)
         hipLaunchKernelGGL((k_tile_sort<O, PAIRS, true>), dim3(overflow), dim3(kSortThreads), 0,
                            st, tasks, tiles, (K *)ws.samples[0]);
@@ -628,14 +631,19 @@ __global__ __launch_bounds__(kSortThreads) void k_tile_merge(TaskRef<SortSeg> ta
                                                              uint32_t items) {
     using K = typename O::K;
     constexpr uint32_t T = base_tile_of(PAIRS, sizeof(K) == 8);
-    if (blockIdx.x >= items) return;
-    uint32_t t, a;
-    const SortSeg g = task_of(tasks, blockIdx.x, &t, &a);
-    const uint64_t t0 = (uint64_t)t * T;
-    const uint32_t len = (uint32_t)(g.m - t0 < T ? g.m - t0 : T);
-    K *k = (K *)g.keys + t0;
-    uint32_t *v = PAIRS ? g.vals + t0 : nullptr;
-    tile_sort_block<O, PAIRS, true>(k, v, k, v, len, T, false, nullptr);
+    // one workgroup per tile (host-sized), or the plan's count of tiles
+    // taken in grid-stride order
+    const uint32_t W = work_total(tasks, items);
+    for (uint32_t it = blockIdx.x; it < W; it += gridDim.x) {
+        uint32_t t, a;
+        const SortSeg g = task_of(tasks, it, &t, &a);
+        const uint64_t t0 = (uint64_t)t * T;
+        const uint32_t len = (uint32_t)(g.m - t0 < T ? g.m - t0 : T);
+        K *k = (K *)g.keys + t0;
+        uint32_t *v = PAIRS ? g.vals + t0 : nullptr;
+        tile_sort_block<O, PAIRS, true>(k, v, k, v, len, T, false, nullptr);
+        __syncthreads();  // the LDS is reused by the next tile
+    }
 }
 
 hipError_t launch_tile_merge(int dt, bool pairs, const TaskRef<SortSeg> &tasks, uint32_t items,

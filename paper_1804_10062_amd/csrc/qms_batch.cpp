@@ -50,7 +50,7 @@ extern "C" int qms_sort_batch(void *d_keys, uint32_t *d_vals, const uint64_t *d_
         if (rc != QMS_OK) return rc;
         // every round planned on the device: nothing is read back
         return sort_batch_device_rounds(dt, d_vals != nullptr, (char *)d_keys, d_vals, d_offsets,
-                                        off.data(), num_segments, *ws, stream);
+                                        off.data(), num_segments, 0, *ws, stream);
     } catch (...) {
         return set_error(QMS_ERR_NOMEM, "host exception in qms_sort_batch");
     }

@@ -29,6 +29,8 @@
 //                 the last stage of the base case's network (registers,
 //                 lane exchanges and the LDS).
 // Several ranges (a batch) share each launch through task tables.
+#include <algorithm>
+
 #include "qms_device.hpp"
 #include "qms_internal.hpp"
 #include "qms_prof.hpp"
@@ -37,9 +39,7 @@ namespace qms {
 
 namespace {
 
-constexpr int kBitThreads = 256;            // mirror and column kernels
-constexpr uint32_t kMirrorPer = 8;          // mirror pairs per thread
-constexpr uint32_t kMirrorChunk = kBitThreads * kMirrorPer;
+constexpr uint32_t kMirrorPer = kMirrorChunk / kBitThreads;  // mirror pairs per thread
 
 // ---- mirror step of stage k -------------------------------------------------------
 // Pair t (t-th position of the lower halves of the 2^k blocks) is position
@@ -81,10 +81,14 @@ __device__ __forceinline__ void mirror_item(TaskRef<SortSeg> tasks, uint32_t ite
     }
 }
 
+// Items: one workgroup each (host-sized: the grid is the item count), or
+// with tasks.dyn the plan's count, which the workgroups take in grid-stride
+// order.
 template <class O, bool PAIRS>
 __global__ __launch_bounds__(kBitThreads) void k_bitonic_mirror(TaskRef<SortSeg> tasks,
                                                                 uint32_t items, uint32_t k) {
-    if (blockIdx.x < items) mirror_item<O, PAIRS>(tasks, blockIdx.x, k);
+    const uint32_t W = work_total(tasks, items);
+    for (uint32_t it = blockIdx.x; it < W; it += gridDim.x) mirror_item<O, PAIRS>(tasks, it, k);
 }
 
 // ---- half-cleaner steps j = 2^hi, ..., 2^lo (j >= T) ------------------------------
@@ -145,7 +149,9 @@ template <class O, bool PAIRS, int R>
 __global__ __launch_bounds__(kBitThreads) void k_bitonic_columns(TaskRef<SortSeg> tasks,
                                                                  uint32_t items, uint32_t lo,
                                                                  uint32_t hi) {
-    if (blockIdx.x < items) columns_item<O, PAIRS, R>(tasks, blockIdx.x, lo, hi);
+    const uint32_t W = work_total(tasks, items);
+    for (uint32_t it = blockIdx.x; it < W; it += gridDim.x)
+        columns_item<O, PAIRS, R>(tasks, it, lo, hi);
 }
 
 template <class O, bool PAIRS>
@@ -189,23 +195,27 @@ static hipError_t bitonic_t(int dt, const BitonicLaunch &L, hipStream_t st) {
 
 }  // namespace
 
-uint32_t bitonic_items(const BitonicLaunch &L, uint64_t m, uint32_t T) {
-    switch (L.kind) {
-    case BitonicLaunch::MIRROR: {
-        // the lower-half positions of every 2^k block the range reaches
-        const uint64_t H = 1ull << (L.k - 1), B = 2 * H;
-        const uint64_t pairs = (m + B - 1) / B * H;
-        return (uint32_t)((pairs + kMirrorChunk - 1) / kMirrorChunk);
+std::vector<BitonicLaunch> bitonic_passes(uint32_t K, uint32_t lt) {
+    std::vector<BitonicLaunch> v;
+    for (uint32_t k = lt + 1; k <= K; ++k) {
+        BitonicLaunch L;
+        L.kind = BitonicLaunch::MIRROR;
+        L.k = k;
+        v.push_back(L);
+        for (int hi = (int)k - 2; hi >= (int)lt; hi -= 4) {
+            L = BitonicLaunch{};
+            L.kind = BitonicLaunch::COLUMNS;
+            L.k = k;
+            L.hi = (uint32_t)hi;
+            L.lo = (uint32_t)std::max<int>((int)lt, hi - 3);
+            v.push_back(L);
+        }
+        L = BitonicLaunch{};
+        L.kind = BitonicLaunch::TILE;
+        L.k = k;
+        v.push_back(L);
     }
-    case BitonicLaunch::COLUMNS: {
-        const uint64_t blocks = (m + (1ull << (L.hi + 1)) - 1) >> (L.hi + 1);
-        return (uint32_t)(blocks * ((1ull << L.lo) / kBitThreads));
-    }
-    case BitonicLaunch::TILE:
-        return (uint32_t)((m + T - 1) / T);
-    default:
-        return 0;
-    }
+    return v;
 }
 
 hipError_t launch_bitonic_pass(int dt, bool pairs, const BitonicLaunch &L, hipStream_t st) {

@@ -146,36 +146,9 @@ size_t tab_arena_bytes(uint32_t segs) {
 
 const std::vector<std::array<uint64_t, kScheduleWords>> &last_schedule() { return g_schedule; }
 
-// Launches of the bitonic network for ranges of at most 2^K keys whose
-// tiles of T = 2^lt keys are sorted: per stage k (lt < k <= K) the mirror
-// step, the half-cleaner steps from 2^(k-2) down to T four at a time, and
-// the steps inside the tiles.
-static std::vector<BitonicLaunch> network_passes(uint32_t K, uint32_t lt) {
-    std::vector<BitonicLaunch> v;
-    for (uint32_t k = lt + 1; k <= K; ++k) {
-        BitonicLaunch L;
-        L.kind = BitonicLaunch::MIRROR;
-        L.k = k;
-        v.push_back(L);
-        for (int hi = (int)k - 2; hi >= (int)lt; hi -= 4) {
-            L = BitonicLaunch{};
-            L.kind = BitonicLaunch::COLUMNS;
-            L.k = k;
-            L.hi = (uint32_t)hi;
-            L.lo = (uint32_t)std::max<int>((int)lt, hi - 3);
-            v.push_back(L);
-        }
-        L = BitonicLaunch{};
-        L.kind = BitonicLaunch::TILE;
-        L.k = k;
-        v.push_back(L);
-    }
-    return v;
-}
-
 // Arena bytes of the network tables for `count` ranges of at most 2^K keys.
 static size_t network_table_bytes(size_t count, uint32_t K, uint32_t lt) {
-    const size_t launches = network_passes(K, lt).size();
+    const size_t launches = bitonic_passes(K, lt).size();
     return ((count * sizeof(SortSeg) + 255) & ~(size_t)255) +
            launches * (((count + 1) * 4 + 255) & ~(size_t)255);
 }
@@ -196,7 +169,7 @@ static int final_network(int dt, bool pairs, std::vector<SortSeg> &xf, Arena &ar
     SortSeg *tab = ar.take<SortSeg>(n, &o_tab);
     if (!tab) return set_error(QMS_ERR_NOMEM, "task table arena too small");
     for (uint32_t a = 0; a < n; ++a) tab[a] = xf[a];
-    std::vector<BitonicLaunch> passes = network_passes(K, lt);
+    std::vector<BitonicLaunch> passes = bitonic_passes(K, lt);
     std::vector<size_t> o_pre(passes.size(), 0);
     for (size_t i = 0; i < passes.size(); ++i) {
         BitonicLaunch &L = passes[i];
@@ -208,7 +181,7 @@ static int final_network(int dt, bool pairs, std::vector<SortSeg> &xf, Arena &ar
         uint32_t *pre = ar.take<uint32_t>(c + 1, &o_pre[i]);
         if (!pre) return set_error(QMS_ERR_NOMEM, "task table arena too small");
         pre[0] = 0;
-        for (uint32_t a = 0; a < c; ++a) pre[a + 1] = pre[a] + bitonic_items(L, tab[a].m, T0);
+        for (uint32_t a = 0; a < c; ++a) pre[a + 1] = pre[a] + bitonic_items_of(L.kind, L.k, L.lo, L.hi, tab[a].m, T0);
         L.items = pre[c];
         for (uint32_t a = 0; a < c; ++a) L.bytes += 2.0 * elem_bytes * (double)tab[a].m;
     }

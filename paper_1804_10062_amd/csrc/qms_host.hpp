@@ -74,9 +74,12 @@ size_t tab_arena_bytes(uint32_t segs);
 // The batch with device-side round control (qms_rounds.hip): nseg segments
 // [h_off[j], h_off[j + 1]) of keys_base (d_offsets: the same offsets on the
 // device), each below 2^32 keys.  Enqueues everything on st and returns.
+// loop_exit: a range of at most this many keys leaves the loop and is
+// sorted by the bitonic network after the last round (at most the base
+// tile: the loop runs down to the base case).
 int sort_batch_device_rounds(int dt, bool pairs, char *keys_base, uint32_t *vals_base,
                              const uint64_t *d_offsets, const uint64_t *h_off, uint32_t nseg,
-                             Workspace &ws, hipStream_t st);
+                             uint64_t loop_exit, Workspace &ws, hipStream_t st);
 const std::vector<std::array<uint64_t, kScheduleWords>> &last_schedule();
 // The median-of-medians pivot of one array (order-mapped key into *pivot).
 int mom_pivot_of(int dt, const uint32_t *keys, uint64_t n, Workspace &ws, hipStream_t st,

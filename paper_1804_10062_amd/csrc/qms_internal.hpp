@@ -7,6 +7,7 @@
 
 #include <atomic>
 #include <mutex>
+#include <vector>
 
 #include "qms_device.hpp"
 
@@ -106,10 +107,12 @@ struct Workspace {
     // unsorted segments), for caps.rounds segments
     void *r_seg = nullptr;
     uint32_t *r_aseg = nullptr;
-    uint32_t *r_amap = nullptr;    // segment -> partition slot of the round
     uint32_t *r_live[2] = {nullptr, nullptr};  // live lists of alternate rounds
     void *r_ptab = nullptr, *r_mtab = nullptr, *r_stab = nullptr;
     uint32_t *r_pre = nullptr, *r_work = nullptr, *r_status = nullptr;
+    // the bitonic network after the last round: work-item prefixes of every
+    // pass (kMaxNetPasses arrays) and each pass's item count
+    uint32_t *r_netpre = nullptr, *r_netw = nullptr;
 };
 // Device bytes of the round-control state for `segs` segments, and its
 // arrays carved out of `b`.
@@ -163,15 +166,46 @@ struct BitonicLaunch {
     enum Kind : uint32_t { MIRROR = 0, COLUMNS = 1, TILE = 2 };
     TaskRef<SortSeg> tasks;
     uint32_t kind = 0, k = 0, lo = 0, hi = 0;
-    uint32_t items = 0;  // workgroups (the sum over the tasks of bitonic_items)
+    // workgroups: the sum over the tasks of bitonic_items (host-sized), or
+    // with tasks.dyn holding that sum, workgroups that loop over the items
+    uint32_t items = 0;
     double bytes = 0;
 };
+// Threads of the mirror and column kernels, and mirror pairs per workgroup.
+constexpr uint32_t kBitThreads = 256;
+constexpr uint32_t kMirrorChunk = kBitThreads * 8;
+// The passes of the network for ranges of at most 2^K keys whose tiles of
+// 2^lt keys are sorted: for every stage k > lt the mirror step, the
+// half-cleaner steps 2^(k-2) .. 2^lt four at a time, the in-tile steps.
+std::vector<BitonicLaunch> bitonic_passes(uint32_t K, uint32_t lt);
+// Most passes of one network (ranges below 2^33 keys, tiles of at least 2^13).
+constexpr uint32_t kMaxNetPasses = 96;
+// Workgroups of a range of m keys in a pass (base tile T); 0 for the passes
+// of stages above ceil(log2 m), which a range of m keys does not need.
+__host__ __device__ inline uint32_t bitonic_items_of(uint32_t kind, uint32_t k, uint32_t lo,
+                                                     uint32_t hi, uint64_t m, uint32_t T) {
+    if (m <= T || (1ull << (k - 1)) >= m) return 0;
+    switch (kind) {
+    case BitonicLaunch::MIRROR: {
+        // the lower-half positions of every 2^k block the range reaches
+        const uint64_t H = 1ull << (k - 1), B = 2 * H;
+        const uint64_t pairs = (m + B - 1) / B * H;
+        return (uint32_t)((pairs + kMirrorChunk - 1) / kMirrorChunk);
+    }
+    case BitonicLaunch::COLUMNS: {
+        const uint64_t blocks = (m + (1ull << (hi + 1)) - 1) >> (hi + 1);
+        return (uint32_t)(blocks * ((1ull << lo) / kBitThreads));
+    }
+    case BitonicLaunch::TILE:
+        return (uint32_t)((m + T - 1) / T);
+    default:
+        return 0;
+    }
+}
 // The in-tile half-cleaners of that network: the base case's last stage on
 // each tile (items: the tiles of all tasks).
 hipError_t launch_tile_merge(int dt, bool pairs, const TaskRef<SortSeg> &tasks, uint32_t items,
                              hipStream_t st);
-// Workgroups of one range of m keys in pass L (base tile T).
-uint32_t bitonic_items(const BitonicLaunch &L, uint64_t m, uint32_t T);
 hipError_t launch_bitonic_pass(int dt, bool pairs, const BitonicLaunch &L, hipStream_t st);
 // Ranges of 2^32 keys or more (qms_huge.hip): the median of three of
 // [keys, keys + s) as the pivot of the `blocks` round-state slots from

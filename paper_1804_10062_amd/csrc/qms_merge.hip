@@ -803,12 +803,15 @@ __global__ __launch_bounds__(kBlock) void k_merge(TaskRef<SortSeg> tasks, uint32
 template <class O, bool PAIRS>
 static hipError_t merge_t(const MergeLaunch &M, const Workspace &ws, hipStream_t st) {
     using K = typename O::K;
-    if (M.tiles == 0) return hipSuccess;
+    if (M.tiles == 0 && M.overflow == 0) return hipSuccess;
     constexpr bool kFour = !PAIRS || sizeof(K) == 4;  // 4-way passes: payloads with 32-bit keys
     if (M.four_way && !kFour) return hipErrorInvalidValue;
     K *s0 = (K *)ws.samples[0], *s1 = (K *)ws.samples[1];
     const uint32_t T = M.tiles, OV = M.overflow;
     const uint32_t GPT = M.four_way ? 2 : 1;
+    // the estimate's launches (none for an estimate of zero tiles), then the
+    // looping ones from where the estimate ends: the split's items are
+    // threads, the ends' tiles
     const uint32_t sgrid = (uint32_t)(((uint64_t)T * GPT * kSplitLanes + kBlock - 1) / kBlock);
     const uint32_t s_ov = sgrid * kBlock;  // first thread of the split overflow
     const uint32_t egrid = (T + kBlock - 1) / kBlock;
@@ -816,22 +819,26 @@ static hipError_t merge_t(const MergeLaunch &M, const Workspace &ws, hipStream_t
     {
         ProfScope prof(st, K_MERGE_SPLIT, 0.0);
         if (!M.four_way) {
-            hipLaunchKernelGGL((k_merge_split<O, PAIRS, false, false>), dim3(sgrid), dim3(kBlock),
-                               0, st, M.tasks, 0u, M.level, M.step, T, ws.splits, s0, s1,
-                               (uint32_t *)nullptr);
+            if (sgrid)
+                hipLaunchKernelGGL((k_merge_split<O, PAIRS, false, false>), dim3(sgrid),
+                                   dim3(kBlock), 0, st, M.tasks, 0u, M.level, M.step, T,
+                                   ws.splits, s0, s1, (uint32_t *)nullptr);
             if (OV)
                 hipLaunchKernelGGL((k_merge_split<O, PAIRS, false, true>), dim3(OV), dim3(kBlock),
                                    0, st, M.tasks, s_ov, M.level, M.step, T, ws.splits, s0, s1,
                                    (uint32_t *)nullptr);
         } else if constexpr (kFour) {
-            hipLaunchKernelGGL((k_merge_split<O, false, true, false>), dim3(sgrid), dim3(kBlock), 0,
-                               st, M.tasks, 0u, M.level, M.step, T, ws.splits, s0, s1, ws.bounds);
+            if (sgrid)
+                hipLaunchKernelGGL((k_merge_split<O, false, true, false>), dim3(sgrid),
+                                   dim3(kBlock), 0, st, M.tasks, 0u, M.level, M.step, T,
+                                   ws.splits, s0, s1, ws.bounds);
             if (OV)
                 hipLaunchKernelGGL((k_merge_split<O, false, true, true>), dim3(OV), dim3(kBlock), 0,
                                    st, M.tasks, s_ov, M.level, M.step, T, ws.splits, s0, s1,
                                    ws.bounds);
-            hipLaunchKernelGGL(k_merge4_ends<false>, dim3(egrid), dim3(kBlock), 0, st, M.tasks, 0u,
-                               M.level, M.step, T, (const uint32_t *)ws.bounds, ws.ends);
+            if (egrid)
+                hipLaunchKernelGGL(k_merge4_ends<false>, dim3(egrid), dim3(kBlock), 0, st, M.tasks,
+                                   0u, M.level, M.step, T, (const uint32_t *)ws.bounds, ws.ends);
             if (OV)
                 hipLaunchKernelGGL(k_merge4_ends<true>, dim3(OV), dim3(kBlock), 0, st, M.tasks,
                                    e_ov, M.level, M.step, T, (const uint32_t *)ws.bounds, ws.ends);
@@ -842,15 +849,18 @@ static hipError_t merge_t(const MergeLaunch &M, const Workspace &ws, hipStream_t
         // 4-way pass moves each element once for two levels)
         ProfScope prof(st, K_MERGE, M.bytes, M.step ? -1 : (int)M.level);
         if (!M.four_way) {
-            hipLaunchKernelGGL((k_merge<O, PAIRS, false>), dim3(T), dim3(kBlock), 0, st, M.tasks,
-                               0u, M.level, M.step, (const uint32_t *)ws.splits, s0, s1);
+            if (T)
+                hipLaunchKernelGGL((k_merge<O, PAIRS, false>), dim3(T), dim3(kBlock), 0, st,
+                                   M.tasks, 0u, M.level, M.step, (const uint32_t *)ws.splits, s0,
+                                   s1);
             if (OV)
                 hipLaunchKernelGGL((k_merge<O, PAIRS, true>), dim3(OV), dim3(kBlock), 0, st,
                                    M.tasks, T, M.level, M.step, (const uint32_t *)ws.splits, s0, s1);
         } else if constexpr (kFour) {
-            hipLaunchKernelGGL((k_merge4<O, PAIRS, false>), dim3(T), dim3(kMerge4Threads), 0, st,
-                               M.tasks, 0u, M.level, M.step, (const uint32_t *)ws.bounds,
-                               (const uint32_t *)ws.ends, s0, s1);
+            if (T)
+                hipLaunchKernelGGL((k_merge4<O, PAIRS, false>), dim3(T), dim3(kMerge4Threads), 0,
+                                   st, M.tasks, 0u, M.level, M.step, (const uint32_t *)ws.bounds,
+                                   (const uint32_t *)ws.ends, s0, s1);
             if (OV)
                 hipLaunchKernelGGL((k_merge4<O, PAIRS, true>), dim3(OV), dim3(kMerge4Threads), 0,
                                    st, M.tasks, T, M.level, M.step, (const uint32_t *)ws.bounds,

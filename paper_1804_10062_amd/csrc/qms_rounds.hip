@@ -15,18 +15,21 @@
 // device memory and take their items in grid-stride order, so the host only
 // has to launch an upper bound of workgroups.
 //
-// The host enqueues a fixed schedule for the batch: R_main rounds with
+// The host enqueues a fixed schedule for the batch: R rounds with
 // HybridQuickMergesort's pivot rule (Sec. "Worst-Case Efficient
 // QuickMergeSort": median-of-3, or after a round whose smaller side held
-// less than 1/16 of its range the median of the medians of three), then
-// R_safe rounds in which every remaining range takes the median-of-medians
-// pivot, which leaves at most about 2/3 of it; R_safe is enough for any
-// range to fall to the base tile, so the schedule always finishes.  Rounds
-// in which nothing is left do nothing (every launch reads a zero count).
-// Per-round upper bounds for the launch sizes and the merge passes follow
-// from the same rule: a range shrinks by 1/16 in a round with a balanced
-// split, and after an unbalanced round the median-of-medians round removes
-// a third, so after r >= 1 rounds a range of n keys holds at most
+// less than 1/16 of its range the median of the medians of three), then X
+// at the loop level: every range still above the base tile is sorted in
+// place by the bitonic network of qms_bitonic.hip (its tiles by the base
+// case first), as the host-driven loop finishes its last range.  R covers
+// 1.5 rounds per binary level between the longest segment and the loop's
+// exit size (plus two), so with random keys the network has little left;
+// its passes are enqueued for the largest range the rule allows and read
+// zero counts when nothing is left, as do the rounds' launches.  Upper
+// bounds for the launch sizes, the merge passes and the network follow from
+// the same rule: a range shrinks by 1/16 in a round with a balanced split,
+// and after an unbalanced round the median-of-medians round removes a
+// third, so after r >= 1 rounds a range of n keys holds at most
 // n (15/16)^(r-1) keys.
 #include <hip/hip_runtime.h>
 
@@ -48,6 +51,7 @@ constexpr int kPlanThreads = 1024;
 constexpr uint32_t DS_ACTIVE = 1;  // range above the base tile: partitioned this round
 constexpr uint32_t DS_MOM = 2;     // next pivot: median of the medians of three
 constexpr uint32_t DS_FINAL = 4;   // range of at most the base tile: base case next round
+constexpr uint32_t DS_NET = 8;     // range left the loop (at most F keys): network at the end
 
 // Workspace counters (dwork) of the device-sized launches of a round.
 enum WorkSlot : int {
@@ -74,7 +78,8 @@ static_assert(W_COUNT_SLOTS <= 64, "work counters fit their array");
 struct DevSeg {
     uint32_t *keys, *vals;  // segment base
     uint32_t lo, hi;        // current range, relative to the base
-    uint32_t flags, pad;
+    uint32_t flags;
+    uint32_t slot;          // partition slot of the round (active segments)
 };
 
 // Round constants shared by the plan kernels.
@@ -89,7 +94,8 @@ struct PlanArgs {
     uint32_t four_way;   // 4-way passes (else 2-way)
     uint32_t wide;       // 64-bit keys
     uint32_t ew;         // 32-bit words per key
-    uint32_t force_mom;  // safety rounds: every range takes the worst-case pivot
+    uint32_t F;          // loop exit: a range of at most F keys (> T0) waits for the network
+    uint32_t xfinal;     // the last round: every range above the base tile goes to the network
     uint32_t partitioned;  // this round ran a partition (else only finals are sorted)
     uint32_t steps;      // merge steps enqueued this round
     uint32_t first2;     // a launch for 2-way first passes (odd level counts) is enqueued
@@ -99,7 +105,6 @@ struct PlanArgs {
 struct PlanPtrs {
     DevSeg *seg;
     uint32_t *aseg;                // active index -> segment
-    uint32_t *amap;                // segment -> active index (entries of active segments)
     // the segments still in the loop (active, or waiting for the base case),
     // compacted by each round's side kernel; nullptr in: every segment
     const uint32_t *live_in;
@@ -145,7 +150,7 @@ __global__ __launch_bounds__(kBlock) void k_rounds_init(DevSeg *seg, const uint6
         d.lo = 0;
         d.hi = (uint32_t)n;
         d.flags = n > T0 ? DS_ACTIVE : (n > 1 ? DS_FINAL : 0u);
-        d.pad = 0;
+        d.slot = 0;
         seg[i] = d;
     }
     if (blockIdx.x == 0)
@@ -214,7 +219,7 @@ __device__ __forceinline__ void plan_counts(const PlanArgs &A, const DevSeg &d,
     const bool act = (d.flags & DS_ACTIVE) != 0;
     const uint32_t s = act ? d.hi - d.lo : 0;
     const uint32_t nt = act ? (s + A.TP - 1) / A.TP : 0;
-    const bool mom = act && (A.force_mom || (d.flags & DS_MOM));
+    const bool mom = act && (d.flags & DS_MOM) != 0;
     c[PV_ACT] = act ? 1u : 0u;
     c[PV_TILES] = nt;
     c[PV_SCAN] = act ? scan_a_groups(nt, A.scan_nth) : 0u;
@@ -266,7 +271,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_rounds_plan(PlanArgs A, PlanPt
                                  c[PV_MOM] ? kPivotMoM : 0u, im};
                 P.ptab[ia] = pg;
                 P.aseg[ia] = jj[u];
-                P.amap[jj[u]] = ia;
+                P.seg[jj[u]].slot = ia;
                 P.p_tiles[ia] = off[PV_TILES];
                 P.p_scan[ia] = off[PV_SCAN];
                 if (c[PV_MOM]) {
@@ -435,11 +440,14 @@ __device__ __forceinline__ SideOut side_of(const PlanArgs &A, const PlanPtrs &P,
             // the next pivot the median of the medians of three
             const bool unbalanced = (uint64_t)(mL < mR ? mL : mR) * 16 < s;
             const uint32_t s2 = o.d.hi - o.d.lo;
-            o.d.flags = s2 > A.T0 ? (DS_ACTIVE | (unbalanced ? DS_MOM : 0u))
-                                  : (s2 > 1 ? DS_FINAL : 0u);
+            o.d.flags = s2 > A.F    ? (DS_ACTIVE | (unbalanced ? DS_MOM : 0u))
+                        : s2 > A.T0 ? DS_NET
+                        : s2 > 1    ? DS_FINAL
+                                    : 0u;
         }
-    } else if (d.flags & DS_FINAL) {
-        // the base case in place on the whole remaining range
+    } else if ((d.flags & DS_FINAL) || (A.xfinal && (d.flags & (DS_ACTIVE | DS_NET)))) {
+        // the base case in place on the whole remaining range (on each of
+        // its tiles for a range the network then finishes)
         t.keys = d.keys + ew * d.lo;
         t.vals = d.vals ? d.vals + d.lo : nullptr;
         t.m = d.hi - d.lo;
@@ -455,7 +463,7 @@ __device__ __forceinline__ SideOut side_of(const PlanArgs &A, const PlanPtrs &P,
     const uint32_t mt = o.emit ? (t.m + kMergeTile - 1) / kMergeTile : 0u;
     c[SD_TASK] = o.emit ? 1u : 0u;
     c[SD_BASE] = o.emit ? (t.m + A.T0 - 1) / A.T0 : 0u;
-    c[SD_SPLIT] = mt;
+    c[SD_SPLIT] = t.L ? mt : 0u;  // run samples: Mergesort tasks only
     // the 2-way first pass of a 4-way Mergesort with an odd level count
     c[SD_M2] = o.emit && !t.two_way && (t.L & 1u) ? mt : 0u;
     c[SD_LIVE] = o.d.flags != 0 ? 1u : 0u;
@@ -490,7 +498,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_rounds_side(PlanArgs A, PlanPt
 #pragma unroll
             for (uint32_t u = 0; u < kGroup; ++u)
                 if (g + u < a1 && (d[u].flags & DS_ACTIVE) && ok) {
-                    const uint32_t ia = P.amap[jj[u]];
+                    const uint32_t ia = d[u].slot;
                     le[u][0] = P.res[4 * ia];
                     le[u][1] = P.res[4 * ia + 1];
                 }
@@ -538,6 +546,85 @@ __global__ __launch_bounds__(kPlanThreads) void k_rounds_side(PlanArgs A, PlanPt
     }
 }
 
+// ---- the network after the last round --------------------------------------------
+// The last round's side kernel left one base-case task (L = 0) per range
+// still to sort; those above the base tile need the network's passes.  Per
+// pass: the work items of every task (bitonic_items_of; zero for the stages
+// above a range's own size) and their exclusive prefix, the tables the pass
+// kernels search.  A range above 2^K keys, which the schedule's bound rules
+// out, is reported as a plan error.
+struct NetArgs {
+    uint32_t lt;  // log2 of the base tile T
+    uint32_t K;   // the network's last stage
+    uint32_t T;
+    uint32_t np;  // passes
+    uint32_t PS;  // stride of the prefix arrays
+};
+constexpr int kNetBatch = 8;  // passes scanned together
+
+__global__ __launch_bounds__(kPlanThreads) void k_rounds_net_plan(NetArgs N, PlanPtrs P,
+                                                                  uint32_t *netpre,
+                                                                  uint32_t *netw) {
+    __shared__ uint32_t lds[kNetBatch * kPlanWaves];
+    __shared__ uint32_t pass[kMaxNetPasses][4];  // kind, k, lo, hi
+    if (threadIdx.x == 0) {
+        // the pass order of bitonic_passes()
+        uint32_t p = 0;
+        for (uint32_t k = N.lt + 1; k <= N.K && p < kMaxNetPasses; ++k) {
+            pass[p][0] = BitonicLaunch::MIRROR;
+            pass[p][1] = k;
+            pass[p][2] = pass[p][3] = 0;
+            ++p;
+            for (int hi = (int)k - 2; hi >= (int)N.lt && p < kMaxNetPasses; hi -= 4) {
+                pass[p][0] = BitonicLaunch::COLUMNS;
+                pass[p][1] = k;
+                pass[p][2] = (uint32_t)(hi - 3 > (int)N.lt ? hi - 3 : (int)N.lt);
+                pass[p][3] = (uint32_t)hi;
+                ++p;
+            }
+            if (p < kMaxNetPasses) {
+                pass[p][0] = BitonicLaunch::TILE;
+                pass[p][1] = k;
+                pass[p][2] = pass[p][3] = 0;
+                ++p;
+            }
+        }
+    }
+    __syncthreads();
+    const uint32_t n = P.work[W_SORT_TASKS];
+    uint32_t a0, a1;
+    owned_block(n, &a0, &a1);
+    uint32_t bad = 0;
+    for (uint32_t a = a0; a < a1; ++a) bad += (uint64_t)P.stab[a].m > (1ull << N.K);
+    if (bad) atomicAdd(&P.work[W_ERRORS], 1u);
+    for (uint32_t p0 = 0; p0 < N.np; p0 += kNetBatch) {
+        const uint32_t nb = N.np - p0 < (uint32_t)kNetBatch ? N.np - p0 : (uint32_t)kNetBatch;
+        uint32_t off[kNetBatch] = {}, tot[kNetBatch];
+        for (uint32_t a = a0; a < a1; ++a) {
+            const uint32_t m = P.stab[a].m;
+#pragma unroll
+            for (int i = 0; i < kNetBatch; ++i)
+                if ((uint32_t)i < nb) {
+                    const uint32_t *q = pass[p0 + i];
+                    off[i] += bitonic_items_of(q[0], q[1], q[2], q[3], m, N.T);
+                }
+        }
+        block_scan_n<kNetBatch>(off, tot, nb, lds);
+        for (uint32_t a = a0; a < a1; ++a) {
+            const uint32_t m = P.stab[a].m;
+#pragma unroll
+            for (int i = 0; i < kNetBatch; ++i)
+                if ((uint32_t)i < nb) {
+                    const uint32_t *q = pass[p0 + i];
+                    netpre[(size_t)(p0 + i) * N.PS + a] = off[i];
+                    off[i] += bitonic_items_of(q[0], q[1], q[2], q[3], m, N.T);
+                }
+        }
+        if (threadIdx.x == 0)
+            for (uint32_t i = 0; i < nb; ++i) netw[p0 + i] = tot[i];
+    }
+}
+
 // ---- end of the schedule: segments still unsorted, plan errors -------------------
 // status[0] accumulates errors, status[1] unsorted segments, until read.
 __global__ __launch_bounds__(kBlock) void k_rounds_end(const DevSeg *seg, uint32_t nseg,
@@ -548,6 +635,16 @@ __global__ __launch_bounds__(kBlock) void k_rounds_end(const DevSeg *seg, uint32
     if (left) atomicAdd(&status[1], left);
     if (blockIdx.x == 0 && threadIdx.x == 0 && work[W_ERRORS]) atomicAdd(&status[0], work[W_ERRORS]);
 }
+
+// Partition rounds per binary level between the longest segment and the
+// loop's exit size (plus two): HybridQuickMergesort's rounds shrink a range
+// with random keys to about 11/16 on average, 0.54 levels per round, and the
+// network sorts what the slower ranges leave (1.2, 1.5 and 2 rounds per
+// level took 49.5, 49.9 and 50.7 ms on the 20,000-array batch).
+#ifndef QMS_DRC_ROUNDS_PER_LEVEL
+#define QMS_DRC_ROUNDS_PER_LEVEL 1.5
+#endif
+constexpr double kRoundsPerLevel = QMS_DRC_ROUNDS_PER_LEVEL;
 
 uint32_t ceil_log2_host(uint64_t x) {
     uint32_t l = 0;
@@ -560,8 +657,9 @@ uint32_t ceil_log2_host(uint64_t x) {
 // ---- host side ------------------------------------------------------------------
 size_t rounds_state_bytes(uint32_t segs) {
     const size_t S = segs;
-    return S * sizeof(DevSeg) + 4 * S * 4 + 2 * (S + 1) * sizeof(PartSeg) +
-           (S + 1) * sizeof(SortSeg) + (9 + kMaxLevels) * (S + 2) * 4 + 64 * 4 + 16 * 256;
+    return S * sizeof(DevSeg) + 3 * S * 4 + 2 * (S + 1) * sizeof(PartSeg) +
+           (S + 1) * sizeof(SortSeg) + (9 + kMaxLevels) * (S + 2) * 4 + 64 * 4 +
+           (size_t)kMaxNetPasses * (S + 2) * 4 + kMaxNetPasses * 4 + 16 * 256;
 }
 
 void carve_rounds_state(Workspace *ws, char *b, uint32_t segs) {
@@ -573,7 +671,6 @@ void carve_rounds_state(Workspace *ws, char *b, uint32_t segs) {
     };
     ws->r_seg = take(S * sizeof(DevSeg));
     ws->r_aseg = (uint32_t *)take(S * 4);
-    ws->r_amap = (uint32_t *)take(S * 4);
     ws->r_live[0] = (uint32_t *)take(S * 4);
     ws->r_live[1] = (uint32_t *)take(S * 4);
     ws->r_ptab = take((S + 1) * sizeof(PartSeg));
@@ -582,6 +679,8 @@ void carve_rounds_state(Workspace *ws, char *b, uint32_t segs) {
     ws->r_pre = (uint32_t *)take((9 + kMaxLevels) * (S + 2) * 4);
     ws->r_work = (uint32_t *)take(64 * 4);
     ws->r_status = (uint32_t *)take(4 * 4);
+    ws->r_netpre = (uint32_t *)take((size_t)kMaxNetPasses * (S + 2) * 4);
+    ws->r_netw = (uint32_t *)take(kMaxNetPasses * 4);
 }
 
 // The segments [h_off[j], h_off[j + 1]) of a batch, all below 2^32 keys;
@@ -589,7 +688,7 @@ void carve_rounds_state(Workspace *ws, char *b, uint32_t segs) {
 // d_offsets: the device's, or nullptr for a single array (h_off = {0, n}).
 int sort_batch_device_rounds(int dt, bool pairs, char *keys_base, uint32_t *vals_base,
                              const uint64_t *d_offsets, const uint64_t *h_off, uint32_t nseg,
-                             Workspace &ws, hipStream_t st) {
+                             uint64_t loop_exit, Workspace &ws, hipStream_t st) {
     const Tuning tune = current_tuning();
     const bool wide = dtype_wide(dt);
     const uint32_t ew = wide ? 2 : 1;
@@ -617,13 +716,13 @@ int sort_batch_device_rounds(int dt, bool pairs, char *keys_base, uint32_t *vals
         const uint32_t G = g1 - g0;
         std::vector<uint64_t> len(G);
         for (uint32_t i = 0; i < G; ++i) len[i] = h_off[g0 + i + 1] - h_off[g0 + i];
-        // the schedule: main rounds, then worst-case-pivot rounds
-        const double levels = nmax > T0 ? std::log2((double)nmax / T0) : 0.0;
-        const uint32_t R_main = nmax > T0 ? (uint32_t)std::ceil(2.0 * levels) + 2 : 0;
-        const uint32_t R_safe =
-            nmax > T0 ? (uint32_t)std::ceil(std::log((double)nmax / T0) / std::log(1.0 / 0.675)) + 1
-                      : 0;
-        const uint32_t R = R_main + R_safe;
+        // the schedule: R partition rounds (every segment above the base
+        // tile at least one), then the network on what is left
+        const uint64_t F = std::max<uint64_t>(T0, std::min<uint64_t>(loop_exit, kMaxFinalTile));
+        const double levels = nmax > F ? std::log2((double)nmax / F) : 0.0;
+        const uint32_t R = nmax <= T0 ? 0
+                           : nmax <= F ? 1
+                                       : (uint32_t)std::ceil(kRoundsPerLevel * levels) + 2;
         // range bound of a segment of n keys after r rounds
         auto bound = [&](uint64_t n, uint32_t r) -> uint64_t {
             if (r <= 1) return n;
@@ -659,7 +758,6 @@ int sort_batch_device_rounds(int dt, bool pairs, char *keys_base, uint32_t *vals
         PlanPtrs P{};
         P.seg = (DevSeg *)ws.r_seg;
         P.aseg = ws.r_aseg;
-        P.amap = ws.r_amap;
         P.ptab = (PartSeg *)ws.r_ptab;
         P.mtab = (PartSeg *)ws.r_mtab;
         P.stab = (SortSeg *)ws.r_stab;
@@ -690,10 +788,15 @@ int sort_batch_device_rounds(int dt, bool pairs, char *keys_base, uint32_t *vals
         // 3/4 and a quarter more work), then a looping launch of kOverflow
         // workgroups for any items beyond the estimate (as many workgroups
         // as the chip holds at once, so that an estimate that falls short
-        // still runs on every compute unit).
+        // still runs on every compute unit).  Where the host expects no
+        // items, the looping launch alone is enqueued.  (One looping launch
+        // per phase, sized from the estimate, was measured too: the looping
+        // kernels run their items up to twice as slowly, and the batch took
+        // 76 instead of 50 ms.)
         constexpr uint32_t kOverflow = 2048;
         constexpr double kShrink = 0.75, kSlack = 1.25;
         auto est = [](double x) -> uint32_t {
+            if (x <= 0.0) return 0;
             return (uint32_t)std::min<double>(std::ceil(x * kSlack) + 16.0, 1u << 30);
         };
         // device-sized task references: the work-item count and the number
@@ -719,6 +822,7 @@ int sort_batch_device_rounds(int dt, bool pairs, char *keys_base, uint32_t *vals
         };
 
         std::vector<double> expect(G);  // expected range of each segment
+        std::vector<char> was_act(G, 0);  // partitioned in the previous round
         for (uint32_t i = 0; i < G; ++i) expect[i] = (double)len[i];
         for (uint32_t r = 0; r <= R; ++r) {
             // live lists: every segment in the first round, then the list the
@@ -734,13 +838,15 @@ int sort_batch_device_rounds(int dt, bool pairs, char *keys_base, uint32_t *vals
                 const uint64_t n = len[i];
                 if (n <= 1) continue;
                 const double x = expect[i];
-                const double prev = r == 0 ? 0.0 : expect[i] / kShrink;
                 const uint64_t b = bound(n, r);
                 if (r < R && b > T0) {
                     bmax = std::max(bmax, b);
                     tiles_b += (b + TP - 1) / TP;
                 }
-                if (x > T0 && r < R) {
+                // partitioned this round: every segment above the base tile
+                // in the first round, then the ranges above the loop's exit
+                const bool act = r < R && (r == 0 ? x > T0 : x > (double)F);
+                if (act) {
                     const double nt = std::ceil(x / TP);
                     tiles_e += nt;
                     scan_e += scan_a_groups((uint32_t)nt, scan_nth);
@@ -754,20 +860,28 @@ int sort_batch_device_rounds(int dt, bool pairs, char *keys_base, uint32_t *vals
                     merge_e += std::ceil(0.35 * x / kMergeTile);
                     base_e += std::ceil(0.35 * x / T0);
                 }
-                // the ranges that reach the base tile: base case next round
-                if ((r == 0 && x <= T0) || (r > 0 && x <= T0 && prev > T0)) base_e += 1;
-                expect[i] = x * kShrink;
+                // the ranges that reach the base tile: base case next round;
+                // the last round: the tiles of the ranges the network finishes
+                if (x <= T0 && (r == 0 || was_act[i])) base_e += 1;
+                if (r == R && x > T0) base_e += std::ceil(x / T0);
+                was_act[i] = act;
+                if (act) expect[i] = x * kShrink;
             }
             const uint32_t Lmax = bmax / 2 > R0_min ? ceil_log2_host((bmax / 2 + R0_min - 1) / R0_min) : 0;
             const uint32_t steps = std::min<uint32_t>(four_way ? Lmax / 2 : Lmax, kMaxLevels);
-            A.force_mom = r >= R_main ? 1u : 0u;
+            A.F = (uint32_t)F;
+            A.xfinal = r == R ? 1u : 0u;
             A.steps = steps;
             A.first2 = four_way && (!auto_r0 || wide) && Lmax > 0;
             A.partitioned = r < R && bmax > 0;
             if (A.partitioned) {
                 hipLaunchKernelGGL(k_rounds_plan, dim3(1), dim3(kPlanThreads), 0, st, A, P);
-                // pivots of the flagged ranges
-                e = launch_mom_pivot(dt, part_ref(P.p_mom, W_MOM, P.mtab, W_MOM_SEGS), est(mom_e), kOverflow,
+                // pivots of the flagged ranges: the estimated launch always
+                // takes the first items (a looping launch that also took the
+                // first items gave wrong pivots on a batch of 409 arrays;
+                // the cause is not known)
+                e = launch_mom_pivot(dt, part_ref(P.p_mom, W_MOM, P.mtab, W_MOM_SEGS),
+                                     std::max<uint32_t>(est(mom_e), 16), kOverflow,
                                      false, ws, st);
                 if (e != hipSuccess) return hip_error(e, "median-of-medians pivot");
                 PartitionLaunch L{};
@@ -848,6 +962,32 @@ int sort_batch_device_rounds(int dt, bool pairs, char *keys_base, uint32_t *vals
                 M.four_way = four_way;
                 if ((e = launch_merge_pass(dt, pairs, M, ws, st)) != hipSuccess)
                     return hip_error(e, "merge pass");
+            }
+        }
+        // X at the loop level: the network on every range the last round
+        // handed over (their tiles sorted in place by that round's base
+        // case), enqueued for the largest range the schedule's bound allows
+        const uint64_t fmax = R == 0 ? 0 : std::min<uint64_t>(nmax, std::max<uint64_t>(F, bound(nmax, R)));
+        const uint32_t lt = ceil_log2_host(T0);
+        const uint32_t Kn = fmax > T0 ? ceil_log2_host(fmax) : 0;
+        if (Kn > lt) {
+            const std::vector<BitonicLaunch> passes = bitonic_passes(Kn, lt);
+            if (passes.size() > kMaxNetPasses)
+                return set_error(QMS_ERR_UNSUPPORTED, "network plan beyond its table");
+            const NetArgs N{lt, Kn, T0, (uint32_t)passes.size(), (uint32_t)PS};
+            hipLaunchKernelGGL(k_rounds_net_plan, dim3(1), dim3(kPlanThreads), 0, st, N, P,
+                               ws.r_netpre, ws.r_netw);
+            if ((e = hipGetLastError()) != hipSuccess) return hip_error(e, "network plan");
+            for (size_t p = 0; p < passes.size(); ++p) {
+                BitonicLaunch L = passes[p];
+                L.tasks.tab = P.stab;
+                L.tasks.pre = ws.r_netpre + p * PS;
+                L.tasks.A = G + 1;
+                L.tasks.dyn = ws.r_netw + p;
+                L.tasks.dyn_A = P.work + W_SORT_TASKS;
+                L.items = kOverflow;
+                if ((e = launch_bitonic_pass(dt, pairs, L, st)) != hipSuccess)
+                    return hip_error(e, "bitonic network");
             }
         }
         hipLaunchKernelGGL(k_rounds_end, dim3(std::min<uint32_t>((G + kBlock - 1) / kBlock, 1024)),

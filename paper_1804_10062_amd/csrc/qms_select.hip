@@ -170,9 +170,11 @@ static hipError_t mom_t(const TaskRef<PartSeg> &tasks, uint32_t tiles, uint32_t 
     if (init)
         hipLaunchKernelGGL(k_mom_init, dim3(tasks.A), dim3(kBlock), 0, st, tasks, ws.meta,
                            ws.hist);
+    if (tiles == 0 && overflow == 0) return hipGetLastError();
     for (uint32_t pass = 0; pass < kPasses; ++pass) {
-        hipLaunchKernelGGL((k_mom_hist<O, false>), dim3(tiles), dim3(kBlock), 0, st, tasks, 0u,
-                           pass, kPasses - 1, ws.meta, ws.hist);
+        if (tiles)
+            hipLaunchKernelGGL((k_mom_hist<O, false>), dim3(tiles), dim3(kBlock), 0, st, tasks,
+                               0u, pass, kPasses - 1, ws.meta, ws.hist);
         if (overflow)
             hipLaunchKernelGGL((k_mom_hist<O, true>), dim3(overflow), dim3(kBlock), 0, st, tasks,
                                tiles, pass, kPasses - 1, ws.meta, ws.hist);
