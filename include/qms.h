@@ -38,7 +38,7 @@
  *     results back to the host once per partition round, so they return
  *     only after the sort has completed on the stream.
  *   - Extra device memory: a library-owned workspace per (device, stream)
- *     of fixed size, about 320 MB (tile counters, run samples, split
+ *     of fixed size, about 370 MB (tile counters, run samples, split
  *     vectors, task tables and the round state of device-planned batches;
  *     nothing proportional to n), allocated on first use and kept until
  *     qms_release_workspaces().  Every sort is in place: no key or payload

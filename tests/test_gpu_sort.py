@@ -289,10 +289,12 @@ def _sliced_sorted(t: torch.Tensor, step: int = 1 << 28) -> bool:
 @needs_gpu
 def test_array_above_2_31_keys():
     """2^31 + 2^20 + 7 uint32 keys (8.6 GB) from the device's seeded
-    generator.  The first partition round holds more keys than the per-64
-    counts cover (its chunk boundaries are found by walking whole tiles), and
-    its scan gives each of its workgroups several chunks of tiles.  Checks
-    that hold at any size: sorted, same multiset (both computed in slices)."""
+    generator.  Its first partition rounds use more than half of the per-64
+    counts, and the scan gives each of its workgroups several chunks of
+    tiles.  (A round beyond the per-64 counts, which locates its chunk
+    boundaries by walking whole tiles, is the first round of the 2^32 + 2^20
+    keys of test_gpu_huge.py.)  Checks that hold at any size: sorted, same
+    multiset (both computed in slices)."""
     n = (1 << 31) + (1 << 20) + 7
     gen = torch.Generator(device="cuda")
     gen.manual_seed(31)
