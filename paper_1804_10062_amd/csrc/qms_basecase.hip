@@ -402,10 +402,22 @@ __device__ __forceinline__ void tile_sort_block(typename O::K *sk, uint32_t *sv,
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) r[i] = s[nat_idx<ITEMS>(base + i)];
 
+    // A tile of len < T keys: its keys and padding sorted as the first P
+    // positions (P the power of two at or above len, at least ITEMS) are the
+    // sorted keys, so the network stops at runs of P (then all ascending) and
+    // waves wholly past P skip the compare-exchanges (they still take part in
+    // the barriers).  The last stage's half-cleaners of MERGE_ONLY start at
+    // P / 2: a partner at P or beyond is padding and never moves.
+    const uint32_t P = len >= T ? T : len <= (uint32_t)ITEMS ? (uint32_t)ITEMS
+                                                             : 2u << (31 - __builtin_clz(len - 1));
+    const uint32_t top = MERGE_ONLY ? run : (run < P ? run : P);
+    const bool wact = (tid & ~(uint32_t)(kWave - 1)) * (uint32_t)ITEMS < P;
+
     // 3. runs of ITEMS / 2 in registers, alternating direction (fixed per
     //    register, since base is a multiple of ITEMS)
 #pragma unroll
     for (int k = 2; k < (MERGE_ONLY ? 2 : ITEMS); k <<= 1) {
+        if (!wact) break;
 #pragma unroll
         for (int j = k >> 1; j >= 1; j >>= 1) {
 #pragma unroll
@@ -425,20 +437,24 @@ __device__ __forceinline__ void tile_sort_block(typename O::K *sk, uint32_t *sv,
     //    changes only between stages.  At the last stage every block ascends
     //    and the keys are plain again: the tile holds T / run sorted runs.
     E cur_mask = E{};
-    for (uint32_t k = MERGE_ONLY ? run : ITEMS; k <= run; k <<= 1) {
-        const E mask = (k == run || (base & k) == 0) ? E{} : TE::FLIP;
+    for (uint32_t k = MERGE_ONLY ? run : ITEMS; k <= top; k <<= 1) {
+        const E mask = (k == top || (base & k) == 0) ? E{} : TE::FLIP;
         const E flip = mask ^ cur_mask;
         cur_mask = mask;
 #pragma unroll
         for (int i = 0; i < ITEMS; ++i) r[i] ^= flip;
         const bool asc = true;
-        uint32_t j = k >> 1;
-        // partners in other waves: exchange through LDS
+        uint32_t j = (k < P ? k : P) >> 1;
+        // partners in other waves: exchange through LDS (partners of a
+        // thread before P lie before P)
         for (; j >= (uint32_t)kWave * ITEMS; j >>= 1) {
             __syncthreads();  // previous users of s are done
+            if (wact) {
 #pragma unroll
-            for (int i = 0; i < ITEMS; ++i) s[(uint32_t)i * NT + tid] = r[i];
+                for (int i = 0; i < ITEMS; ++i) s[(uint32_t)i * NT + tid] = r[i];
+            }
             __syncthreads();
+            if (!wact) continue;
             const uint32_t pt = tid ^ (j / ITEMS);
             const bool lower = (tid & (j / ITEMS)) == 0;
             const bool keep_min = asc == lower;
@@ -447,6 +463,7 @@ __device__ __forceinline__ void tile_sort_block(typename O::K *sk, uint32_t *sv,
             for (int i = 0; i < ITEMS; ++i)
                 r[i] = keep_side(r[i], s[(uint32_t)i * NT + pt], keep_min, bound);
         }
+        if (!wact) continue;
         // partners in other lanes of the wave
         if constexpr (std::is_same_v<E, uint32_t>) {
             switch (j / ITEMS) {  // lane masks j / ITEMS down to 1

@@ -70,7 +70,7 @@ def test_invalid_tuning_rejected_and_unchanged():
                 (4, 1 << 17, 16384), (4, 4096, (1 << 20) + 1),
                 (4, 4096, 16384, 1024), (4, 4096, 16384, 3072), (4, 4096, 16384, 32768),
                 (4, 4096, 16384, 0, 4096), (4, 4096, 16384, 0, 3 << 20),
-                (4, 4096, 16384, 0, 1 << 25)]:
+                (4, 4096, 16384, 0, 1 << 31)]:  # final_tile: a power of two in [8192, 2^30]
         with pytest.raises(qms.QmsError):
             qms.qms_set_tuning(*bad)
     assert qms.qms_get_tuning() == before
