@@ -116,6 +116,7 @@ struct Workspace {
     // the bitonic network after the last round: work-item prefixes of every
     // pass (kMaxNetPasses arrays) and each pass's item count
     uint32_t *r_netpre = nullptr, *r_netw = nullptr;
+    uint32_t *r_blk = nullptr;  // per-workgroup sums of the plans
 };
 // Device bytes of the round-control state for `segs` segments, and its
 // arrays carved out of `b`.

@@ -157,20 +157,28 @@ __global__ __launch_bounds__(kBlock) void k_rounds_init(DevSeg *seg, const uint6
         for (uint32_t i = threadIdx.x; i < W_COUNT_SLOTS; i += kBlock) work[i] = 0;
 }
 
-// ---- one-pass scans over per-thread blocks ----------------------------------------
-// The plan kernels run in one workgroup over up to a few ten thousand
-// segments.  Each thread takes a contiguous block of them, sums its counts
-// in a first pass, and all counts are scanned together (one barrier for the
-// wave totals); a second pass over the same block writes the tables from
-// the thread's offsets.  Loads are issued kGroup segments at a time, so a
-// block costs a few memory latencies, not one per segment.
+// ---- plans over many workgroups ------------------------------------------------------
+// A plan gives every entry of a list (the live segments, the partition
+// slots) its offsets in a phase's tables: exclusive prefixes of a few counts
+// per entry.  It takes two launches of kPB-thread workgroups, one entry per
+// thread: the first writes each workgroup's sums into blk, the second adds
+// the sums of the workgroups before its own to a workgroup scan and writes
+// the tables.  Whatever the plan reads from the round's counters is read by
+// the first launch and kept in blk's header, since the second launch's first
+// workgroup rewrites those counters.  (One 1,024-thread workgroup walking
+// all entries took 40 to 75 us per plan on 20,000 segments, most of it
+// dependent loads and register spills.)
 constexpr int kPlanWaves = kPlanThreads / kWave;
-constexpr uint32_t kGroup = 4;
+constexpr int kPB = 256;
+constexpr int kPBWaves = kPB / kWave;
+constexpr uint32_t kPlanBlocks = (kCapSegs + kPB - 1) / kPB;
+constexpr uint32_t kBlkStride = 32;  // values per workgroup (header first)
+enum BlkHeader { BH_N = 0, BH_OK };
 
 // Exclusive scan across the block (thread order) of the first n <= N of
 // the N values of every thread; v gets the prefixes, tot the block totals.
-// lds: N * kPlanWaves words.  Every thread of the block calls it.
-template <int N>
+// lds: N * WAVES words.  Every thread of the block calls it.
+template <int N, int WAVES>
 __device__ __forceinline__ void block_scan_n(uint32_t (&v)[N], uint32_t (&tot)[N], uint32_t n,
                                              uint32_t *lds) {
     const uint32_t lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
@@ -180,7 +188,7 @@ __device__ __forceinline__ void block_scan_n(uint32_t (&v)[N], uint32_t (&tot)[N
         inc[i] = 0;
         if ((uint32_t)i < n) {
             inc[i] = wave_inclusive_scan(v[i]);
-            if (lane == kWave - 1) lds[i * kPlanWaves + wave] = inc[i];
+            if (lane == kWave - 1) lds[i * WAVES + wave] = inc[i];
         }
     }
     __syncthreads();
@@ -188,8 +196,8 @@ __device__ __forceinline__ void block_scan_n(uint32_t (&v)[N], uint32_t (&tot)[N
     for (int i = 0; i < N; ++i) {
         uint32_t before = 0, all = 0;
         if ((uint32_t)i < n) {
-            for (uint32_t w = 0; w < (uint32_t)kPlanWaves; ++w) {
-                const uint32_t t = lds[i * kPlanWaves + w];
+            for (uint32_t w = 0; w < (uint32_t)WAVES; ++w) {
+                const uint32_t t = lds[i * WAVES + w];
                 before += w < wave ? t : 0u;
                 all += t;
             }
@@ -200,13 +208,52 @@ __device__ __forceinline__ void block_scan_n(uint32_t (&v)[N], uint32_t (&tot)[N
     __syncthreads();  // the LDS may be reused
 }
 
-// The block [*a0, *a1) of entries of a list of `count` entries that this
-// thread owns.
+// The block [*a0, *a1) of a list of `count` entries that this thread of a
+// kPlanThreads workgroup owns (one-workgroup plans).
 __device__ __forceinline__ void owned_block(uint32_t count, uint32_t *a0, uint32_t *a1) {
     const uint32_t per = (count + kPlanThreads - 1) / kPlanThreads;
     const uint32_t b = threadIdx.x * per;
     *a0 = b < count ? b : count;
     *a1 = b + per < count ? b + per : count;
+}
+
+// First launch of a plan: this workgroup's sums of the first n <= N counts.
+template <int N>
+__device__ __forceinline__ void plan_block_sums(uint32_t (&c)[N], uint32_t n, uint32_t *blk,
+                                                uint32_t *lds) {
+    uint32_t tot[N];
+    block_scan_n<N, kPBWaves>(c, tot, n, lds);
+    if (threadIdx.x == 0)
+        for (uint32_t i = 0; i < n; ++i) blk[(blockIdx.x + 1) * kBlkStride + i] = tot[i];
+}
+
+// Second launch: the sums of the nblk workgroups' first n counts before this
+// one (base) and over all of them (tot).  sh: kPlanBlocks * kBlkStride words.
+template <int N>
+__device__ __forceinline__ void plan_block_bases(const uint32_t *blk, uint32_t nblk, uint32_t n,
+                                                 uint32_t (&base)[N], uint32_t (&tot)[N],
+                                                 uint32_t *sh) {
+    for (uint32_t q = threadIdx.x; q < nblk * kBlkStride; q += kPB) sh[q] = blk[kBlkStride + q];
+    __syncthreads();
+    uint32_t mb = 0, mt = 0;
+    if (threadIdx.x < n)
+        for (uint32_t q = 0; q < nblk; ++q) {
+            const uint32_t v = sh[q * kBlkStride + threadIdx.x];
+            mb += q < blockIdx.x ? v : 0u;
+            mt += v;
+        }
+    __syncthreads();
+    if (threadIdx.x < n) {
+        sh[threadIdx.x] = mb;
+        sh[kBlkStride + threadIdx.x] = mt;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        base[i] = (uint32_t)i < n ? sh[i] : 0u;
+        tot[i] = (uint32_t)i < n ? sh[kBlkStride + i] : 0u;
+    }
+    __syncthreads();  // sh may be reused
 }
 
 // ---- plan of the partition: table, tile / scan / median-of-medians prefixes ----------
@@ -228,68 +275,62 @@ __device__ __forceinline__ void plan_counts(const PlanArgs &A, const DevSeg &d,
     c[PV_MOM_TILES] = mom ? mom_tiles_of(s) : 0u;
 }
 
-__global__ __launch_bounds__(kPlanThreads) void k_rounds_plan(PlanArgs A, PlanPtrs P) {
-    __shared__ uint32_t lds[PV_N * kPlanWaves];
-    const uint32_t n_live = P.live_in ? P.work[W_LIVE] : A.nseg;
-    uint32_t a0, a1;
-    owned_block(n_live, &a0, &a1);
-    uint32_t off[PV_N] = {}, tot[PV_N];
-    for (uint32_t g = a0; g < a1; g += kGroup) {
-        DevSeg d[kGroup];
-#pragma unroll
-        for (uint32_t u = 0; u < kGroup; ++u)
-            if (g + u < a1) d[u] = P.seg[P.live_in ? P.live_in[g + u] : g + u];
-#pragma unroll
-        for (uint32_t u = 0; u < kGroup; ++u)
-            if (g + u < a1) {
-                uint32_t c[PV_N];
-                plan_counts(A, d[u], c);
-#pragma unroll
-                for (int i = 0; i < PV_N; ++i) off[i] += c[i];
-            }
+__global__ __launch_bounds__(kPB) void k_rounds_plan_count(PlanArgs A, PlanPtrs P,
+                                                            uint32_t *blk) {
+    __shared__ uint32_t lds[PV_N * kPBWaves];
+    const uint32_t n = P.live_in ? P.work[W_LIVE] : A.nseg;
+    if (blockIdx.x == 0 && threadIdx.x == 0) blk[BH_N] = n;
+    if (blockIdx.x * kPB >= n) return;
+    const uint32_t a = blockIdx.x * kPB + threadIdx.x;
+    uint32_t c[PV_N] = {};
+    if (a < n) plan_counts(A, P.seg[P.live_in ? P.live_in[a] : a], c);
+    plan_block_sums<PV_N>(c, PV_N, blk, lds);
+}
+
+__global__ __launch_bounds__(kPB) void k_rounds_plan_write(PlanArgs A, PlanPtrs P,
+                                                            const uint32_t *blk) {
+    __shared__ uint32_t lds[PV_N * kPBWaves];
+    __shared__ uint32_t sh[kPlanBlocks * kBlkStride];
+    const uint32_t n = blk[BH_N];
+    const uint32_t nblk = (n + kPB - 1) / kPB;
+    if (blockIdx.x != 0 && blockIdx.x >= nblk) return;
+    uint32_t base[PV_N], tot[PV_N];
+    plan_block_bases<PV_N>(blk, nblk, PV_N, base, tot, sh);
+    const uint32_t a = blockIdx.x * kPB + threadIdx.x;
+    uint32_t jj = 0, c[PV_N] = {}, off[PV_N], t2[PV_N];
+    DevSeg d{};
+    if (a < n) {
+        jj = P.live_in ? P.live_in[a] : a;
+        d = P.seg[jj];
+        plan_counts(A, d, c);
     }
-    block_scan_n<PV_N>(off, tot, PV_N, lds);
-    for (uint32_t g = a0; g < a1; g += kGroup) {
-        uint32_t jj[kGroup];
-        DevSeg d[kGroup];
 #pragma unroll
-        for (uint32_t u = 0; u < kGroup; ++u)
-            if (g + u < a1) {
-                jj[u] = P.live_in ? P.live_in[g + u] : g + u;
-                d[u] = P.seg[jj[u]];
-            }
+    for (int i = 0; i < PV_N; ++i) off[i] = c[i];
+    block_scan_n<PV_N, kPBWaves>(off, t2, PV_N, lds);
 #pragma unroll
-        for (uint32_t u = 0; u < kGroup; ++u) {
-            if (g + u >= a1) continue;
-            uint32_t c[PV_N];
-            plan_counts(A, d[u], c);
-            if (c[PV_ACT]) {
-                const uint32_t ia = off[PV_ACT], im = off[PV_MOM];
-                const uint32_t s = d[u].hi - d[u].lo;
-                const PartSeg pg{d[u].keys, d[u].vals,         d[u].lo, s,
-                                 off[PV_TILES], c[PV_TILES], off[PV_CHUNK], ia,
-                                 c[PV_MOM] ? kPivotMoM : 0u, im};
-                P.ptab[ia] = pg;
-                P.aseg[ia] = jj[u];
-                P.seg[jj[u]].slot = ia;
-                P.p_tiles[ia] = off[PV_TILES];
-                P.p_scan[ia] = off[PV_SCAN];
-                if (c[PV_MOM]) {
-                    P.mtab[im] = pg;
-                    P.p_mom[im] = off[PV_MOM_TILES];
-                    uint64_t *meta = P.meta + (uint64_t)ia * M_COUNT;
-                    const uint64_t cm = s / 3;
-                    meta[M_MOM_RANK] = (cm - 1) / 2;
-                    meta[M_MOM_PREFIX] = 0;
-                    meta[M_MOM_DONE] = 0;
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < PV_N; ++i) off[i] += c[i];
+    for (int i = 0; i < PV_N; ++i) off[i] += base[i];
+    if (a < n && c[PV_ACT]) {
+        const uint32_t ia = off[PV_ACT], im = off[PV_MOM];
+        const uint32_t s = d.hi - d.lo;
+        const PartSeg pg{d.keys, d.vals, d.lo, s, off[PV_TILES], c[PV_TILES], off[PV_CHUNK], ia,
+                         c[PV_MOM] ? kPivotMoM : 0u, im};
+        P.ptab[ia] = pg;
+        P.aseg[ia] = jj;
+        P.seg[jj].slot = ia;
+        P.p_tiles[ia] = off[PV_TILES];
+        P.p_scan[ia] = off[PV_SCAN];
+        if (c[PV_MOM]) {
+            P.mtab[im] = pg;
+            P.p_mom[im] = off[PV_MOM_TILES];
+            uint64_t *meta = P.meta + (uint64_t)ia * M_COUNT;
+            const uint64_t cm = s / 3;
+            meta[M_MOM_RANK] = (cm - 1) / 2;
+            meta[M_MOM_PREFIX] = 0;
+            meta[M_MOM_DONE] = 0;
         }
     }
-    const uint32_t c_act = tot[PV_ACT], c_mom = tot[PV_MOM];
-    if (threadIdx.x == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const uint32_t c_act = tot[PV_ACT], c_mom = tot[PV_MOM];
         // a padding entry that no item reaches
         const PartSeg none{nullptr, nullptr, 0, 0, 0, 0, 0, 0, 0, 0};
         P.ptab[c_act] = none;
@@ -330,44 +371,47 @@ __device__ __forceinline__ void swap_counts(const PlanArgs &A, uint64_t s, uint6
     }
 }
 
-__global__ __launch_bounds__(kPlanThreads) void k_rounds_plan_swap(PlanArgs A, PlanPtrs P) {
-    __shared__ uint32_t lds[SV_N * kPlanWaves];
+__device__ __forceinline__ void swap_counts_of(const PlanArgs &A, const PlanPtrs &P, uint32_t a,
+                                               uint32_t (&c)[SV_N]) {
+    swap_counts(A, P.ptab[a].s, P.res[4 * a], P.res[4 * a + 1], P.res[4 * a + 2], c);
+}
+
+__global__ __launch_bounds__(kPB) void k_rounds_swap_count(PlanArgs A, PlanPtrs P,
+                                                            uint32_t *blk) {
+    __shared__ uint32_t lds[SV_N * kPBWaves];
     const uint32_t act = P.work[W_ACTIVE];
     const bool ok = P.work[W_TILES] != 0 || act == 0;
-    uint32_t a0, a1;
-    owned_block(ok ? act : 0u, &a0, &a1);
-    uint32_t off[SV_N] = {}, tot[SV_N];
-    for (int pass = 0; pass < 2; ++pass) {
-        if (pass == 1) block_scan_n<SV_N>(off, tot, SV_N, lds);
-        for (uint32_t g = a0; g < a1; g += kGroup) {
-            uint64_t s[kGroup], lt[kGroup], eq[kGroup], X[kGroup];
+    const uint32_t n = ok ? act : 0u;
+    if (blockIdx.x == 0 && threadIdx.x == 0) blk[BH_N] = n;
+    if (blockIdx.x * kPB >= n) return;
+    const uint32_t a = blockIdx.x * kPB + threadIdx.x;
+    uint32_t c[SV_N] = {};
+    if (a < n) swap_counts_of(A, P, a, c);
+    plan_block_sums<SV_N>(c, SV_N, blk, lds);
+}
+
+__global__ __launch_bounds__(kPB) void k_rounds_swap_write(PlanArgs A, PlanPtrs P,
+                                                            const uint32_t *blk) {
+    __shared__ uint32_t lds[SV_N * kPBWaves];
+    __shared__ uint32_t sh[kPlanBlocks * kBlkStride];
+    const uint32_t n = blk[BH_N];
+    const uint32_t nblk = (n + kPB - 1) / kPB;
+    if (blockIdx.x != 0 && blockIdx.x >= nblk) return;
+    uint32_t base[SV_N], tot[SV_N];
+    plan_block_bases<SV_N>(blk, nblk, SV_N, base, tot, sh);
+    const uint32_t a = blockIdx.x * kPB + threadIdx.x;
+    uint32_t c[SV_N] = {}, off[SV_N], t2[SV_N];
+    if (a < n) swap_counts_of(A, P, a, c);
 #pragma unroll
-            for (uint32_t u = 0; u < kGroup; ++u)
-                if (g + u < a1) {
-                    const uint32_t a = g + u;
-                    s[u] = P.ptab[a].s;
-                    lt[u] = P.res[4 * a];
-                    eq[u] = P.res[4 * a + 1];
-                    X[u] = P.res[4 * a + 2];
-                }
-#pragma unroll
-            for (uint32_t u = 0; u < kGroup; ++u) {
-                if (g + u >= a1) continue;
-                uint32_t c[SV_N];
-                swap_counts(A, s[u], lt[u], eq[u], X[u], c);
-                if (pass == 1) {
-                    const uint32_t a = g + u;
-                    P.p_wa[a] = off[SV_WA];
-                    P.p_ca[a] = off[SV_CA];
-                    P.p_wb[a] = off[SV_WB];
-                    P.p_cb[a] = off[SV_CB];
-                }
-#pragma unroll
-                for (int i = 0; i < SV_N; ++i) off[i] += c[i];
-            }
-        }
+    for (int i = 0; i < SV_N; ++i) off[i] = c[i];
+    block_scan_n<SV_N, kPBWaves>(off, t2, SV_N, lds);
+    if (a < n) {
+        P.p_wa[a] = base[SV_WA] + off[SV_WA];
+        P.p_ca[a] = base[SV_CA] + off[SV_CA];
+        P.p_wb[a] = base[SV_WB] + off[SV_WB];
+        P.p_cb[a] = base[SV_CB] + off[SV_CB];
     }
-    if (threadIdx.x == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
         P.work[W_SPLIT_A] = tot[SV_WA];
         P.work[W_SWAP_A] = tot[SV_CA];
         P.work[W_SPLIT_B] = tot[SV_WB];
@@ -473,62 +517,84 @@ __device__ __forceinline__ SideOut side_of(const PlanArgs &A, const PlanPtrs &P,
     return o;
 }
 
-__global__ __launch_bounds__(kPlanThreads) void k_rounds_side(PlanArgs A, PlanPtrs P) {
-    __shared__ uint32_t lds[SD_N * kPlanWaves];
+// One live entry: its segment, and its < p and == p counts when it was
+// partitioned this round.
+__device__ __forceinline__ void side_load(const PlanPtrs &P, uint32_t a, bool ok, uint32_t *jj,
+                                          DevSeg *d, uint32_t (&le)[2]) {
+    *jj = P.live_in ? P.live_in[a] : a;
+    *d = P.seg[*jj];
+    le[0] = le[1] = 0;
+    if ((d->flags & DS_ACTIVE) && ok) {
+        le[0] = P.res[4 * d->slot];
+        le[1] = P.res[4 * d->slot + 1];
+    }
+}
+
+__global__ __launch_bounds__(kPB) void k_rounds_side_count(PlanArgs A, PlanPtrs P,
+                                                            uint32_t *blk) {
+    __shared__ uint32_t lds[SD_N * kPBWaves];
     // with no partition this round, or one whose plan did not fit, ranges in
     // the loop stay as they are
     const bool ok = A.partitioned && (P.work[W_TILES] != 0 || P.work[W_ACTIVE] == 0);
-    const uint32_t n_live = P.live_in ? P.work[W_LIVE] : A.nseg;
+    const uint32_t n = P.live_in ? P.work[W_LIVE] : A.nseg;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        blk[BH_N] = n;
+        blk[BH_OK] = ok ? 1u : 0u;
+    }
+    if (blockIdx.x * kPB >= n) return;
+    const uint32_t a = blockIdx.x * kPB + threadIdx.x;
+    uint32_t c[SD_N] = {};
+    if (a < n) {
+        uint32_t jj, le[2];
+        DevSeg d;
+        side_load(P, a, ok, &jj, &d, le);
+        (void)side_of(A, P, d, ok, le, c);
+    }
+    plan_block_sums<SD_N>(c, SD_STEP0 + A.steps, blk, lds);
+}
+
+__global__ __launch_bounds__(kPB) void k_rounds_side_write(PlanArgs A, PlanPtrs P,
+                                                            const uint32_t *blk) {
+    __shared__ uint32_t lds[SD_N * kPBWaves];
+    __shared__ uint32_t sh[kPlanBlocks * kBlkStride];
+    const uint32_t n = blk[BH_N];
+    const bool ok = blk[BH_OK] != 0;
+    const uint32_t nblk = (n + kPB - 1) / kPB;
+    if (blockIdx.x != 0 && blockIdx.x >= nblk) return;
     const uint32_t nv = SD_STEP0 + A.steps;  // values to scan
-    uint32_t a0, a1;
-    owned_block(n_live, &a0, &a1);
-    uint32_t off[SD_N] = {}, tot[SD_N];
-    for (int pass = 0; pass < 2; ++pass) {
-        if (pass == 1) block_scan_n<SD_N>(off, tot, nv, lds);
-        for (uint32_t g = a0; g < a1; g += kGroup) {
-            uint32_t jj[kGroup];
-            DevSeg d[kGroup];
-            uint32_t le[kGroup][2];
+    uint32_t base[SD_N], tot[SD_N];
+    plan_block_bases<SD_N>(blk, nblk, nv, base, tot, sh);
+    const uint32_t a = blockIdx.x * kPB + threadIdx.x;
+    uint32_t jj = 0, c[SD_N] = {}, off[SD_N], t2[SD_N];
+    SideOut o{};
+    if (a < n) {
+        uint32_t le[2];
+        DevSeg d;
+        side_load(P, a, ok, &jj, &d, le);
+        o = side_of(A, P, d, ok, le, c);
+    }
 #pragma unroll
-            for (uint32_t u = 0; u < kGroup; ++u)
-                if (g + u < a1) {
-                    jj[u] = P.live_in ? P.live_in[g + u] : g + u;
-                    d[u] = P.seg[jj[u]];
-                }
+    for (int i = 0; i < SD_N; ++i) off[i] = c[i];
+    block_scan_n<SD_N, kPBWaves>(off, t2, nv, lds);
 #pragma unroll
-            for (uint32_t u = 0; u < kGroup; ++u)
-                if (g + u < a1 && (d[u].flags & DS_ACTIVE) && ok) {
-                    const uint32_t ia = d[u].slot;
-                    le[u][0] = P.res[4 * ia];
-                    le[u][1] = P.res[4 * ia + 1];
-                }
+    for (int i = 0; i < SD_N; ++i) off[i] += base[i];
+    if (a < n) {
+        if (o.write) P.seg[jj] = o.d;
+        if (c[SD_LIVE]) P.live_out[off[SD_LIVE]] = jj;
+        if (o.emit) {
+            const uint32_t idx = off[SD_TASK];
+            SortSeg t = o.t;
+            t.split_off = off[SD_SPLIT];
+            P.stab[idx] = t;
+            P.p_base[idx] = off[SD_BASE];
+            P.p_m2[idx] = off[SD_M2];
 #pragma unroll
-            for (uint32_t u = 0; u < kGroup; ++u) {
-                if (g + u >= a1) continue;
-                uint32_t c[SD_N];
-                const SideOut o = side_of(A, P, d[u], ok, le[u], c);
-                if (pass == 1) {
-                    if (o.write) P.seg[jj[u]] = o.d;
-                    if (c[SD_LIVE]) P.live_out[off[SD_LIVE]] = jj[u];
-                    if (o.emit) {
-                        const uint32_t idx = off[SD_TASK];
-                        SortSeg t = o.t;
-                        t.split_off = off[SD_SPLIT];
-                        P.stab[idx] = t;
-                        P.p_base[idx] = off[SD_BASE];
-                        P.p_m2[idx] = off[SD_M2];
-#pragma unroll
-                        for (uint32_t k = 0; k < (uint32_t)kMaxLevels; ++k)
-                            if (k < A.steps) P.p_step[k * (A.nseg + 2) + idx] = off[SD_STEP0 + k];
-                    }
-                }
-#pragma unroll
-                for (int i = 0; i < SD_N; ++i) off[i] += c[i];
-            }
+            for (uint32_t k = 0; k < (uint32_t)kMaxLevels; ++k)
+                if (k < A.steps) P.p_step[k * (A.nseg + 2) + idx] = off[SD_STEP0 + k];
         }
     }
-    const uint32_t c_task = tot[SD_TASK];
-    if (threadIdx.x == 0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const uint32_t c_task = tot[SD_TASK];
         SortSeg none{};
         P.stab[c_task] = none;
         const bool fits = tot[SD_SPLIT] <= A.cap_splits;
@@ -609,7 +675,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_rounds_net_plan(NetArgs N, Pla
                     off[i] += bitonic_items_of(q[0], q[1], q[2], q[3], m, N.T);
                 }
         }
-        block_scan_n<kNetBatch>(off, tot, nb, lds);
+        block_scan_n<kNetBatch, kPlanWaves>(off, tot, nb, lds);
         for (uint32_t a = a0; a < a1; ++a) {
             const uint32_t m = P.stab[a].m;
 #pragma unroll
@@ -659,7 +725,8 @@ size_t rounds_state_bytes(uint32_t segs) {
     const size_t S = segs;
     return S * sizeof(DevSeg) + 3 * S * 4 + 2 * (S + 1) * sizeof(PartSeg) +
            (S + 1) * sizeof(SortSeg) + (9 + kMaxLevels) * (S + 2) * 4 + 64 * 4 +
-           (size_t)kMaxNetPasses * (S + 2) * 4 + kMaxNetPasses * 4 + 16 * 256;
+           (size_t)kMaxNetPasses * (S + 2) * 4 + kMaxNetPasses * 4 +
+           (size_t)(kPlanBlocks + 1) * kBlkStride * 4 + 16 * 256;
 }
 
 void carve_rounds_state(Workspace *ws, char *b, uint32_t segs) {
@@ -681,6 +748,7 @@ void carve_rounds_state(Workspace *ws, char *b, uint32_t segs) {
     ws->r_status = (uint32_t *)take(4 * 4);
     ws->r_netpre = (uint32_t *)take((size_t)kMaxNetPasses * (S + 2) * 4);
     ws->r_netw = (uint32_t *)take(kMaxNetPasses * 4);
+    ws->r_blk = (uint32_t *)take((size_t)(kPlanBlocks + 1) * kBlkStride * 4);
 }
 
 // The segments [h_off[j], h_off[j + 1]) of a batch, all below 2^32 keys;
@@ -821,6 +889,7 @@ int sort_batch_device_rounds(int dt, bool pairs, char *keys_base, uint32_t *vals
             return r;
         };
 
+        const uint32_t NBp = (G + kPB - 1) / kPB;  // plan workgroups
         std::vector<double> expect(G);  // expected range of each segment
         std::vector<char> was_act(G, 0);  // partitioned in the previous round
         for (uint32_t i = 0; i < G; ++i) expect[i] = (double)len[i];
@@ -875,7 +944,9 @@ int sort_batch_device_rounds(int dt, bool pairs, char *keys_base, uint32_t *vals
             A.first2 = four_way && (!auto_r0 || wide) && Lmax > 0;
             A.partitioned = r < R && bmax > 0;
             if (A.partitioned) {
-                hipLaunchKernelGGL(k_rounds_plan, dim3(1), dim3(kPlanThreads), 0, st, A, P);
+                hipLaunchKernelGGL(k_rounds_plan_count, dim3(NBp), dim3(kPB), 0, st, A, P, ws.r_blk);
+                hipLaunchKernelGGL(k_rounds_plan_write, dim3(NBp), dim3(kPB), 0, st, A, P,
+                                   (const uint32_t *)ws.r_blk);
                 // pivots of the flagged ranges: the estimated launch always
                 // takes the first items (a looping launch that also took the
                 // first items gave wrong pivots on a batch of 409 arrays;
@@ -920,7 +991,9 @@ int sort_batch_device_rounds(int dt, bool pairs, char *keys_base, uint32_t *vals
                 if ((rc = phase(6, part_ref(P.p_scan, W_SCAN, P.ptab), est(scan_e), 1,
                                 "partition scan")) != QMS_OK)
                     return rc;
-                hipLaunchKernelGGL(k_rounds_plan_swap, dim3(1), dim3(kPlanThreads), 0, st, A, P);
+                hipLaunchKernelGGL(k_rounds_swap_count, dim3(NBp), dim3(kPB), 0, st, A, P, ws.r_blk);
+                hipLaunchKernelGGL(k_rounds_swap_write, dim3(NBp), dim3(kPB), 0, st, A, P,
+                                   (const uint32_t *)ws.r_blk);
                 if ((rc = phase(1, part_ref(P.p_wa, W_SPLIT_A, P.ptab), est(2 * chunks_e), kWaves,
                                 "split A")) != QMS_OK)
                     return rc;
@@ -937,7 +1010,9 @@ int sort_batch_device_rounds(int dt, bool pairs, char *keys_base, uint32_t *vals
                     return rc;
             }
             // side choice (or, after the last round, the finals alone)
-            hipLaunchKernelGGL(k_rounds_side, dim3(1), dim3(kPlanThreads), 0, st, A, P);
+            hipLaunchKernelGGL(k_rounds_side_count, dim3(NBp), dim3(kPB), 0, st, A, P, ws.r_blk);
+            hipLaunchKernelGGL(k_rounds_side_write, dim3(NBp), dim3(kPB), 0, st, A, P,
+                               (const uint32_t *)ws.r_blk);
             e = launch_tile_sort(dt, pairs, sort_ref(P.p_base, W_BASE), est(base_e), kOverflow, 0.0,
                                  ws, st);
             if (e != hipSuccess) return hip_error(e, "base case");
