@@ -125,7 +125,7 @@ int qms_sort_pairs(void *d_keys, uint32_t *d_vals, uint64_t n, int dt,
  * returns without waiting for the GPU (no readback, no synchronisation),
  * so it may be captured into a HIP graph (after one call outside the
  * capture, which allocates the stream's workspace).  The schedule: a
- * number of rounds that follows from the longest segment (1.5 rounds per
+ * number of rounds that follows from the longest segment (1.2 rounds per
  * binary level above the base tile, plus two), with the paper's pivot rule
  * (median-of-3, after an unbalanced round the median of the medians of
  * three: Sec. "Worst-Case Efficient QuickMergeSort"); then every range still

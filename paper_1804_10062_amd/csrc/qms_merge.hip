@@ -199,7 +199,7 @@ __device__ __forceinline__ void merge_split_item(TaskRef<SortSeg> tasks, uint32_
     const uint32_t half = (gid / kSplitLanes) % GPT;
     const bool active = w < total;
     uint32_t tile = 0, a = 0;
-    const SortSeg g = task_of(tasks, active ? w : total - 1, &tile, &a);
+    const SortSeg g = task_of_lanes(tasks, active ? w : total - 1, &tile, &a);
     const uint32_t level = task_level(g, level_arg, step);
     const K *samples = samples_in<K>(g, level, samples0, samples1);
     const Regions rg = level_regions(g, level);

@@ -311,7 +311,7 @@ __device__ __forceinline__ void part_scan_a_item(TaskRef<PartSeg> tasks, uint32_
     uint32_t *tmp = lds.tmp, *csum = lds.csum, *stage = lds.stage;
     using K = typename O::K;
     uint32_t kgrp, a;
-    const PartSeg g = task_of(tasks, item, &kgrp, &a);
+    const PartSeg g = task_of_wave(tasks, item, &kgrp, &a);
     const K *keys = (const K *)g.keys + g.lo;
     const uint32_t *LT = cnt_lt_all + g.tile_off;
     const uint32_t *EQ = cnt_eq_all + g.tile_off;
@@ -647,7 +647,7 @@ __device__ __forceinline__ void part_split_item(TaskRef<PartSeg> tasks, uint32_t
                                                 uint32_t *spR_all, const uint8_t *gcnt,
                                                 const uint64_t *meta_all) {
     uint32_t w, a;
-    const PartSeg g = task_of(tasks, gw, &w, &a);
+    const PartSeg g = task_of_wave(tasks, gw, &w, &a);
     const uint64_t *meta = meta_all + (uint64_t)g.slot * M_COUNT;
     const uint32_t X = (uint32_t)meta[PASS == 0 ? M_XA : M_XB];
     const uint32_t rc = (uint32_t)meta[PASS == 0 ? M_RCA : M_RCB];

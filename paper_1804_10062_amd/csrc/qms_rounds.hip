@@ -22,7 +22,7 @@
 // at the loop level: every range still above the base tile is sorted in
 // place by the bitonic network of qms_bitonic.hip (its tiles by the base
 // case first), as the host-driven loop finishes its last range.  R covers
-// 1.5 rounds per binary level between the longest segment and the loop's
+// 1.2 rounds per binary level between the longest segment and the loop's
 // exit size (plus two), so with random keys the network has little left;
 // its passes are enqueued for the largest range the rule allows and read
 // zero counts when nothing is left, as do the rounds' launches.  Upper
@@ -705,10 +705,11 @@ __global__ __launch_bounds__(kBlock) void k_rounds_end(const DevSeg *seg, uint32
 // Partition rounds per binary level between the longest segment and the
 // loop's exit size (plus two): HybridQuickMergesort's rounds shrink a range
 // with random keys to about 11/16 on average, 0.54 levels per round, and the
-// network sorts what the slower ranges leave (1.2, 1.5 and 2 rounds per
-// level took 49.5, 49.9 and 50.7 ms on the 20,000-array batch).
+// network sorts what the slower ranges leave (on the 20,000-array batch 1.2,
+// 1.5 and 2 rounds per level took 49.5, 49.9 and 50.7 ms with the first
+// plan kernels, 46.7 and 46.9 ms with the present ones).
 #ifndef QMS_DRC_ROUNDS_PER_LEVEL
-#define QMS_DRC_ROUNDS_PER_LEVEL 1.5
+#define QMS_DRC_ROUNDS_PER_LEVEL 1.2
 #endif
 constexpr double kRoundsPerLevel = QMS_DRC_ROUNDS_PER_LEVEL;
 
@@ -854,14 +855,18 @@ int sort_batch_device_rounds(int dt, bool pairs, char *keys_base, uint32_t *vals
         // for as many items as the host expects (a median-of-3 round leaves
         // a range about 11/16 of its size on average; the estimate takes
         // 3/4 and a quarter more work), then a looping launch of kOverflow
-        // workgroups for any items beyond the estimate (as many workgroups
-        // as the chip holds at once, so that an estimate that falls short
-        // still runs on every compute unit).  Where the host expects no
+        // workgroups for any items beyond the estimate (four per compute
+        // unit, so that an estimate that falls short still runs on every
+        // compute unit; 2,048 cost 0.3 ms more on the 20,000-array batch,
+        // whose overflow launches are nearly all empty).  Where the host expects no
         // items, the looping launch alone is enqueued.  (One looping launch
         // per phase, sized from the estimate, was measured too: the looping
         // kernels run their items up to twice as slowly, and the batch took
         // 76 instead of 50 ms.)
-        constexpr uint32_t kOverflow = 2048;
+#ifndef QMS_DRC_OVERFLOW
+#define QMS_DRC_OVERFLOW 1024
+#endif
+        constexpr uint32_t kOverflow = QMS_DRC_OVERFLOW;
         constexpr double kShrink = 0.75, kSlack = 1.25;
         auto est = [](double x) -> uint32_t {
             if (x <= 0.0) return 0;

@@ -87,7 +87,7 @@ __device__ __forceinline__ void mom_hist_item(TaskRef<PartSeg> tasks, uint32_t i
     using K = typename O::K;
     constexpr uint32_t kBits = 8 * sizeof(K);
     uint32_t t, a;
-    const PartSeg g = task_of(tasks, item, &t, &a);
+    const PartSeg g = task_of_wave(tasks, item, &t, &a);
     const K *keys = (const K *)g.keys + g.lo;
     const uint64_t c = g.s / 3;
     const K prefix = (K)meta_all[(uint64_t)g.slot * M_COUNT + M_MOM_PREFIX];
