@@ -601,7 +601,7 @@ def main():
         logcmp = {"workload": "a random order of 1..2^26 (uint32), SplitMix64-keyed Feistel permutation, seed 11"}
         try:
             for label, bt in (("auto", 0), ("2048", 2048)):
-                qms.qms_set_tuning(4, 4096, 16384, bt, 1 << 22)
+                qms.qms_set_tuning(4, 4096, 16384, bt, 0)
                 for name, code in (("plain", qms.QMS_U32), ("log", qms.QMS_U32_LOG)):
                     cps = [s3.clone() for _ in range(3)]
                     time_sorts(cps[:1], qms, torch, profile=False, dtype=code)
@@ -649,13 +649,14 @@ def main():
 
     # X at the loop level: a range a partition round leaves with at most
     # final_tile keys leaves the loop and is sorted in place by the bitonic
-    # network (8192: the loop runs down to the base tile, as in the paper)
+    # network (8192: the loop runs down to the base tile, as in the paper;
+    # the automatic default is 2^24 for these keys)
     final_sweep = None
     if not args.only_uniform and not args.no_threshold_sweep:
         from paper_1804_10062_amd import autotune
         final_sweep = {}
         try:
-            for ft in (8192, 1 << 18, 1 << 20, 1 << 22, 1 << 24):
+            for ft in (8192, 1 << 18, 1 << 20, 1 << 22, 1 << 24, 1 << 25):
                 print(f"[bench] final_tile {ft}", file=sys.stderr, flush=True)
                 d = autotune.DEFAULTS
                 qms.qms_set_tuning(d[0], d[1], d[2], d[3], ft)

@@ -326,12 +326,15 @@ int qms_profile_end(qms_kernel_stat *out, int max_entries, int *n_out);
  *                   of the range.  It adds O(F log^2 F) comparisons for a
  *                   range of F keys.  Every input array above the base tile
  *                   is partitioned at least once; arrays of at most the
- *                   base tile are sorted in place by the base case.  A
- *                   power of two in [8192, 2^30]; 8192 keeps every range in
- *                   the loop down to the base tile, as in the paper.  Used
- *                   by the host-planned loop (qms_sort, qms_sort_pairs,
- *                   qms_sort_noalloc, the server); device-planned rounds
- *                   loop down to the base tile.
+ *                   base tile are sorted in place by the base case.  0
+ *                   (automatic, the default): 2^24 keys, or 2^20 for
+ *                   QMS_U32_LOG, whose network comparisons cost the most
+ *                   time; else a power of two in [8192, 2^30]; 8192 keeps
+ *                   every range in the loop down to the base tile, as in
+ *                   the paper.  Used by the host-planned loop (qms_sort,
+ *                   qms_sort_pairs, qms_sort_noalloc, the server) and by
+ *                   qms_sort under capture; qms_sort_batch loops down to
+ *                   the base tile.
  * qms_set_tuning returns QMS_ERR_INVALID for values out of range (nothing is
  * changed then).  The package's autotuner (paper_1804_10062_amd/autotune.py)
  * picks them for a workload by timing sorts of a sample.

@@ -21,11 +21,11 @@ FIELDS = ("merge_ways", "partition_tile", "chunk_span", "base_tile", "final_tile
 # (merge_ways, partition_tile, chunk_span, base_tile, final_tile); base_tile
 # is QuickMergeXsort's X_THRESH, the run width at which the Mergesort calls
 # the base case (0: automatic).  final_tile (the range size at or below
-# which a single array's range leaves the loop for one buffered Mergesort)
-# does not apply to batches, whose rounds are planned on the device and run
-# down to the base tile, so it stays at its default here.
+# which a single array's range leaves the loop for the in-place network;
+# 0: automatic) does not apply to batches, whose rounds are planned on the
+# device and run down to the base tile, so it stays at its default here.
 CANDIDATES: Tuple[Tuple[int, int, int, int, int], ...] = tuple(
-    c + (1 << 22,) for c in itertools.product((4, 2), (4096, 8192), (16384, 32768), (0, 8192)))
+    c + (0,) for c in itertools.product((4, 2), (4096, 8192), (16384, 32768), (0, 8192)))
 
 
 def _time_batch(keys, offsets, vals, ref_keys, ref_vals, reps: int, stream,
@@ -74,7 +74,7 @@ def autotune_batch(keys, offsets, vals=None, host_offsets=None,
     return {"best": {f: best[f] for f in FIELDS}, "trials": trials}
 
 
-DEFAULTS = (4, 4096, 16384, 0, 1 << 22)
+DEFAULTS = (4, 4096, 16384, 0, 0)
 
 
 def reset_tuning() -> None:

@@ -326,7 +326,7 @@ static int sort_entry(void *d_keys, uint32_t *d_vals, uint64_t n, int dt, hipStr
             return set_error(QMS_ERR_UNSUPPORTED, "a captured sort takes fewer than 2^32 keys");
         const uint64_t h_off[2] = {0, n};
         return sort_batch_device_rounds(dt, pairs, (char *)d_keys, pairs ? d_vals : nullptr,
-                                        nullptr, h_off, 1, current_tuning().final_tile, *ws,
+                                        nullptr, h_off, 1, loop_exit_keys(current_tuning(), dt), *ws,
                                         stream);
     }
     HostSeg seg{(uint32_t *)d_keys, pairs ? d_vals : nullptr, n};
@@ -380,8 +380,8 @@ int qms_set_tuning(const qms_tuning *t) {
     if (bt != 0 && (bt < (uint32_t)kMergeTile || bt > kBaseTileKeys || (bt & (bt - 1)) != 0))
         return set_error(QMS_ERR_INVALID, "base_tile must be 0 or a power of two in [2048, 16384]");
     const uint32_t ft = t->final_tile;
-    if (ft < kBaseTilePairs || ft > kMaxFinalTile || (ft & (ft - 1)) != 0)
-        return set_error(QMS_ERR_INVALID, "final_tile must be a power of two in [8192, 2^30]");
+    if (ft != 0 && (ft < kBaseTilePairs || ft > kMaxFinalTile || (ft & (ft - 1)) != 0))
+        return set_error(QMS_ERR_INVALID, "final_tile must be 0 or a power of two in [8192, 2^30]");
     std::lock_guard<std::mutex> lock(g_tuning_mutex);
     g_tuning.final_tile = ft;
     g_tuning.merge_ways = t->merge_ways;

@@ -243,7 +243,7 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
     // the base case in place; every larger one is partitioned at least once,
     // so its top level is always QuickMergesort's (partition, Mergesort of
     // one side with the other side as its buffer).
-    const uint64_t TF = std::max<uint64_t>(T0, tune.final_tile);
+    const uint64_t TF = std::max<uint64_t>(T0, loop_exit_keys(tune, dt));
     // a final range: the base case sorts its tiles in place (L = 0), the
     // network finishes it if it is longer than one tile
     auto final_task = [&](const Seg &g, uint64_t lo, uint32_t s) {

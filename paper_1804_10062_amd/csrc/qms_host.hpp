@@ -18,15 +18,24 @@ constexpr int kScheduleWords = 6;
 // Run-time tunables (qms_set_tuning): merge arity of key-only sorts, the
 // first partition counting tile, the target positions per exchange chunk,
 // the Mergesort's base-case run width (QuickMergeXsort's X_THRESH), the
-// size below which a range leaves the loop for one buffered Mergesort.
+// size at or below which a range leaves the loop for the in-place network.
 struct Tuning {
     uint32_t merge_ways = 4;
     uint32_t partition_tile = kPartSub;
     uint32_t chunk_span = (uint32_t)kChunkSpan;
-    uint32_t base_tile = 0;  // automatic
-    uint32_t final_tile = 1u << 22;
+    uint32_t base_tile = 0;   // automatic
+    uint32_t final_tile = 0;  // automatic
 };
 Tuning current_tuning();
+// The loop's exit size for keys of type dt: final_tile, or when automatic
+// 2^24 keys, and 2^20 for the logarithm comparison, whose network
+// comparisons are what the time goes to (2^28 uint32 keys: 24.6, 24.9, 25.3,
+// 25.0 and 23.6 Gkeys/s at 2^22 .. 2^26; 2^26 keys by logarithm: 1.54
+// Gkeys/s at 2^22, 1.44 at 2^24).
+inline uint64_t loop_exit_keys(const Tuning &t, int dt) {
+    if (t.final_tile) return t.final_tile;
+    return dt == 4 ? (1ull << 20) : (1ull << 24);
+}
 
 int set_error(int code, const std::string &msg);
 int hip_error(hipError_t e, const char *where);

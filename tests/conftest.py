@@ -12,7 +12,7 @@ def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU")
     config.addinivalue_line("markers", "slow: long-running CPU test")
     config.addinivalue_line(
-        "markers", "final_path: GPU test of the buffered final Mergesort (library defaults)")
+        "markers", "final_path: GPU test of the loop's in-place final network (library defaults)")
 
 
 @pytest.fixture(autouse=True)

@@ -131,7 +131,7 @@ def test_final_batch_of_every_size_class():
 def test_final_path_is_the_default_and_large_sorts_use_both():
     """Defaults: a range of 2^24 + 1 keys is partitioned until it fits the
     final threshold, then finished in place by the network."""
-    tf = qms.qms_get_tuning()["final_tile"]
+    tf = qms.qms_get_tuning()["final_tile"] or (1 << 24)  # 0: automatic, 2^24 for uint32
     n = (1 << 24) + 1
     x = inputs.uniform_u32(n, seed=3)
     t = to_device(x)
