@@ -167,7 +167,7 @@ hipError_t launch_tile_sort(int dt, bool pairs, const TaskRef<SortSeg> &tasks, u
 // steps 2^hi .. 2^lo (j >= T), or the steps below T inside each tile.
 // tasks: the ranges (keys, vals, m), tiles already sorted by the base case.
 struct BitonicLaunch {
-    enum Kind : uint32_t { MIRROR = 0, COLUMNS = 1, TILE = 2 };
+    enum Kind : uint32_t { MIRROR = 0, COLUMNS = 1, TILE = 2, MIRROR_COLUMNS = 3 };
     TaskRef<SortSeg> tasks;
     uint32_t kind = 0, k = 0, lo = 0, hi = 0;
     // workgroups: the sum over the tasks of bitonic_items (host-sized), or
@@ -179,8 +179,9 @@ struct BitonicLaunch {
 constexpr uint32_t kBitThreads = 256;
 constexpr uint32_t kMirrorChunk = kBitThreads * 8;
 // The passes of the network for ranges of at most 2^K keys whose tiles of
-// 2^lt keys are sorted: for every stage k > lt the mirror step, the
-// half-cleaner steps 2^(k-2) .. 2^lt four at a time, the in-tile steps.
+// 2^lt keys are sorted: for every stage k > lt the mirror step with the
+// first (up to four) half-cleaner steps 2^(k-2) .. in one pass, the further
+// steps down to 2^lt four at a time, the in-tile steps.
 std::vector<BitonicLaunch> bitonic_passes(uint32_t K, uint32_t lt);
 // Most passes of one network (ranges below 2^33 keys, tiles of at least 2^13).
 constexpr uint32_t kMaxNetPasses = 96;
@@ -198,6 +199,12 @@ __host__ __device__ inline uint32_t bitonic_items_of(uint32_t kind, uint32_t k, 
     }
     case BitonicLaunch::COLUMNS: {
         const uint64_t blocks = (m + (1ull << (hi + 1)) - 1) >> (hi + 1);
+        return (uint32_t)(blocks * ((1ull << lo) / kBitThreads));
+    }
+    case BitonicLaunch::MIRROR_COLUMNS: {
+        // one thread per column of the lower half of every 2^k block (it
+        // also holds the mirrored column of the upper half)
+        const uint64_t blocks = (m + (1ull << k) - 1) >> k;
         return (uint32_t)(blocks * ((1ull << lo) / kBitThreads));
     }
     case BitonicLaunch::TILE:

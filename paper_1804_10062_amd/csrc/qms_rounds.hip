@@ -620,11 +620,11 @@ __global__ __launch_bounds__(kPB) void k_rounds_side_write(PlanArgs A, PlanPtrs 
 // kernels search.  A range above 2^K keys, which the schedule's bound rules
 // out, is reported as a plan error.
 struct NetArgs {
-    uint32_t lt;  // log2 of the base tile T
     uint32_t K;   // the network's last stage
-    uint32_t T;
+    uint32_t T;   // base tile
     uint32_t np;  // passes
     uint32_t PS;  // stride of the prefix arrays
+    uint32_t pass[kMaxNetPasses];  // bitonic_passes(): kind | k << 8 | lo << 16 | hi << 24
 };
 constexpr int kNetBatch = 8;  // passes scanned together
 
@@ -633,28 +633,12 @@ __global__ __launch_bounds__(kPlanThreads) void k_rounds_net_plan(NetArgs N, Pla
                                                                   uint32_t *netw) {
     __shared__ uint32_t lds[kNetBatch * kPlanWaves];
     __shared__ uint32_t pass[kMaxNetPasses][4];  // kind, k, lo, hi
-    if (threadIdx.x == 0) {
-        // the pass order of bitonic_passes()
-        uint32_t p = 0;
-        for (uint32_t k = N.lt + 1; k <= N.K && p < kMaxNetPasses; ++k) {
-            pass[p][0] = BitonicLaunch::MIRROR;
-            pass[p][1] = k;
-            pass[p][2] = pass[p][3] = 0;
-            ++p;
-            for (int hi = (int)k - 2; hi >= (int)N.lt && p < kMaxNetPasses; hi -= 4) {
-                pass[p][0] = BitonicLaunch::COLUMNS;
-                pass[p][1] = k;
-                pass[p][2] = (uint32_t)(hi - 3 > (int)N.lt ? hi - 3 : (int)N.lt);
-                pass[p][3] = (uint32_t)hi;
-                ++p;
-            }
-            if (p < kMaxNetPasses) {
-                pass[p][0] = BitonicLaunch::TILE;
-                pass[p][1] = k;
-                pass[p][2] = pass[p][3] = 0;
-                ++p;
-            }
-        }
+    for (uint32_t p = threadIdx.x; p < N.np; p += kPlanThreads) {
+        const uint32_t w = N.pass[p];
+        pass[p][0] = w & 255u;
+        pass[p][1] = (w >> 8) & 255u;
+        pass[p][2] = (w >> 16) & 255u;
+        pass[p][3] = w >> 24;
     }
     __syncthreads();
     const uint32_t n = P.work[W_SORT_TASKS];
@@ -1054,7 +1038,13 @@ int sort_batch_device_rounds(int dt, bool pairs, char *keys_base, uint32_t *vals
             const std::vector<BitonicLaunch> passes = bitonic_passes(Kn, lt);
             if (passes.size() > kMaxNetPasses)
                 return set_error(QMS_ERR_UNSUPPORTED, "network plan beyond its table");
-            const NetArgs N{lt, Kn, T0, (uint32_t)passes.size(), (uint32_t)PS};
+            NetArgs N{};
+            N.K = Kn;
+            N.T = T0;
+            N.np = (uint32_t)passes.size();
+            N.PS = (uint32_t)PS;
+            for (size_t p = 0; p < passes.size(); ++p)
+                N.pass[p] = passes[p].kind | passes[p].k << 8 | passes[p].lo << 16 | passes[p].hi << 24;
             hipLaunchKernelGGL(k_rounds_net_plan, dim3(1), dim3(kPlanThreads), 0, st, N, P,
                                ws.r_netpre, ws.r_netw);
             if ((e = hipGetLastError()) != hipSuccess) return hip_error(e, "network plan");

@@ -2,8 +2,9 @@
 loop's last ranges (the library's final X), simulated on the CPU.
 
 The library sorts tiles of T = 2^lt keys with the base case and then runs,
-for every stage k > lt, a mirror step (position i against i ^ (2^k - 1)),
-the half-cleaner steps 2^(k-2) .. T grouped four at a time, and the steps
+for every stage k > lt, a mirror step (position i against i ^ (2^k - 1))
+together with the first (up to four) half-cleaner steps 2^(k-2) .. in one
+pass, the further half-cleaner steps down to T four at a time, and the steps
 below T inside the tiles, all ascending; positions at or past the range's
 end act as +infinity.  This file replays exactly that sequence of
 compare-exchanges with numpy and checks that it sorts ranges of any
@@ -18,11 +19,15 @@ import pytest
 
 
 def network_passes(K: int, lt: int):
-    """(kind, k, lo, hi) in launch order, as the driver builds them."""
+    """(kind, k, lo, hi) in launch order, as the library builds them."""
     out = []
     for k in range(lt + 1, K + 1):
-        out.append(("mirror", k, 0, 0))
         hi = k - 2
+        if hi < lt:
+            out.append(("mirror", k, 0, 0))
+        else:
+            out.append(("mirror_columns", k, max(lt, hi - 3), hi))
+            hi -= 4
         while hi >= lt:
             out.append(("columns", k, max(lt, hi - 3), hi))
             hi -= 4
@@ -56,11 +61,11 @@ def run_network(keys, lt: int) -> np.ndarray:
         return x
     K = math.ceil(math.log2(m))
     for kind, k, lo, hi in network_passes(K, lt):
-        if kind == "mirror":
+        if kind in ("mirror", "mirror_columns"):
             i = np.arange(m)
             i = i[(i >> (k - 1)) & 1 == 0]
             _cmpx(x, i, i ^ ((1 << k) - 1))
-        elif kind == "columns":
+        if kind in ("columns", "mirror_columns"):
             for s in range(hi, lo - 1, -1):
                 _half_cleaner(x, 1 << s)
         else:
@@ -70,16 +75,20 @@ def run_network(keys, lt: int) -> np.ndarray:
 
 
 def test_pass_order_covers_every_step_once():
-    """Stage k: one mirror step, then the half-cleaners 2^(k-2) .. 2^0,
-    each exactly once and in decreasing order."""
+    """Stage k: one mirror step first, then the half-cleaners 2^(k-2) ..
+    2^0, each exactly once and in decreasing order; the mirror shares a pass
+    with the first of them whenever one lies above the tile."""
     lt = 4
     for K in range(lt + 1, 14):
         for k in range(lt + 1, K + 1):
             steps = []
+            kinds = [kind for kind, kk, *_ in network_passes(K, lt) if kk == k]
+            assert kinds[0] == ("mirror" if k - 2 < lt else "mirror_columns")
+            assert kinds.count("mirror") + kinds.count("mirror_columns") == 1
             for kind, kk, lo, hi in network_passes(K, lt):
                 if kk != k:
                     continue
-                if kind == "columns":
+                if kind in ("columns", "mirror_columns"):
                     assert 1 <= hi - lo + 1 <= 4 and lo >= lt
                     steps += list(range(hi, lo - 1, -1))
                 elif kind == "tile":
