@@ -587,7 +587,10 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
             t.two_way = two ? 1u : 0u;
             stab[a] = t;
             ptile[a + 1] = ptile[a] + (t.m + T0 - 1) / T0;
-            pmerge[a + 1] = pmerge[a] + (t.m + kMergeTile - 1) / kMergeTile;
+            // merge splits and run samples: Mergesort tasks only (a range
+            // sorted in place, L = 0, writes no samples, so the finals of a
+            // round take no room there whatever their number)
+            pmerge[a + 1] = pmerge[a] + (t.L ? (t.m + kMergeTile - 1) / kMergeTile : 0u);
             base_bytes += ((merge_passes(t.L, two) & 1) ? 16.0 : 8.0) * w * (double)t.m;
             maxL = std::max(maxL, t.L);
             if (!by_parity || (t.L & 1u) == 0) E = a + 1;
