@@ -327,9 +327,11 @@ int qms_profile_end(qms_kernel_stat *out, int max_entries, int *n_out);
  *                   range of F keys.  Every input array above the base tile
  *                   is partitioned at least once; arrays of at most the
  *                   base tile are sorted in place by the base case.  0
- *                   (automatic, the default): 2^24 keys, or 2^20 for
- *                   QMS_U32_LOG, whose network comparisons cost the most
- *                   time; else a power of two in [8192, 2^30]; 8192 keeps
+ *                   (automatic, the default): 2^24 keys for 32-bit keys,
+ *                   2^23 for QMS_U64 and QMS_F64, 2^22 for QMS_U32_LOG,
+ *                   whose network comparisons cost the most time (the
+ *                   sizes measured fastest for each type); else a power
+ *                   of two in [8192, 2^30]; 8192 keeps
  *                   every range in the loop down to the base tile, as in
  *                   the paper.  Used by the host-planned loop (qms_sort,
  *                   qms_sort_pairs, qms_sort_noalloc, the server) and by

@@ -28,13 +28,18 @@ struct Tuning {
 };
 Tuning current_tuning();
 // The loop's exit size for keys of type dt: final_tile, or when automatic
-// 2^24 keys, and 2^20 for the logarithm comparison, whose network
-// comparisons are what the time goes to (2^28 uint32 keys: 24.6, 24.9, 25.3,
-// 25.0 and 23.6 Gkeys/s at 2^22 .. 2^26; 2^26 keys by logarithm: 1.54
-// Gkeys/s at 2^22, 1.44 at 2^24).
+// the size measured fastest for that type: 2^24 keys for 32-bit keys (with
+// or without payloads), 2^23 for 64-bit keys, whose network passes move
+// twice the bytes, and 2^22 for the logarithm comparison, whose network
+// comparisons are what the time goes to.  Measured on 2^28 uint32 keys
+// (25.3, 25.8, 25.5 Gkeys/s at 2^23, 2^24, 2^25), 2^26 key/payload pairs
+// (9.8, 10.0, 10.3, 9.4 at 2^22 .. 2^25), 2^27 uint64 keys (11.02, 11.09,
+// 10.90, 10.16 at 2^22 .. 2^25) and 2^26 keys by logarithm (1.34, 1.44,
+// 1.56, 1.54, 1.44 at 2^20 .. 2^24).
 inline uint64_t loop_exit_keys(const Tuning &t, int dt) {
     if (t.final_tile) return t.final_tile;
-    return dt == 4 ? (1ull << 20) : (1ull << 24);
+    if (dt == 4) return 1ull << 22;
+    return (dt == 2 || dt == 3) ? (1ull << 23) : (1ull << 24);
 }
 
 int set_error(int code, const std::string &msg);
