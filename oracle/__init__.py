@@ -126,6 +126,8 @@ def _load():
     lib.qmso_merge.restype = None
     lib.qmso_mom_pivot.argtypes = [u32p, sz, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
     lib.qmso_mom_pivot.restype = ctypes.c_uint32
+    lib.qmso64_mom_pivot.argtypes = [u64p, sz, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    lib.qmso64_mom_pivot.restype = ctypes.c_uint64
     _lib = lib
     return lib
 
@@ -309,17 +311,19 @@ def merge(keys, begin1: int, end1: int, target: int, endtarget: int, vals=None):
 
 def mom_pivot(keys: np.ndarray) -> int:
     """Median of the floor(n/3) medians of (keys[3i], keys[3i+1], keys[3i+2])
-    (Sec. "Worst-Case Efficient QuickMergeSort", reading R7), as the 32-bit
-    pattern of the pivot; float32 keys are compared by the total order."""
+    (Sec. "Worst-Case Efficient QuickMergeSort", reading R7), as the bit
+    pattern of the pivot (32 or 64 bits by the key width); float keys are
+    compared by the total order.  Other integer arrays are taken as uint32."""
     x = np.ascontiguousarray(keys)
     if x.size < 3:
         raise ValueError("the pivot needs n >= 3")
-    is_f32 = x.dtype == np.float32
-    xb = x.view(np.uint32) if is_f32 else x.astype(np.uint32, copy=False)
+    if x.dtype not in (np.float32, np.uint32, np.float64, np.uint64):
+        x = x.astype(np.uint32, copy=False)
+    words, is_f = _as_words(x)
     lib = _load()
     ok = ctypes.c_int()
-    p = lib.qmso_mom_pivot(xb.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), xb.size,
-                           int(is_f32), ctypes.byref(ok))
+    fn = lib.qmso64_mom_pivot if _wide(words) else lib.qmso_mom_pivot
+    p = fn(_ptr(words), words.size, is_f, ctypes.byref(ok))
     if not ok.value:
         raise MemoryError("oracle mom_pivot")
     return int(p)

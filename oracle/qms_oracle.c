@@ -404,43 +404,46 @@ void QMSO_FN(sort_segments)(qkey_t *keys, uint32_t *vals,
     }
 }
 
-#if QMSO_COUNTING && QMSO_KEY_BITS == 32
-static int cmp_u32(const void *x, const void *y)
+#if QMSO_COUNTING
+static int cmp_key(const void *x, const void *y)
 {
-    uint32_t a = *(const uint32_t *)x, b = *(const uint32_t *)y;
+    qkey_t a = *(const qkey_t *)x, b = *(const qkey_t *)y;
     return (a > b) - (a < b);
 }
 
 /* R7: the median of the floor(n/3) medians of three (MoMQuickMergesort's
  * pivot, Sec. "Worst-Case Efficient QuickMergeSort"), as the key bits of the
- * input (is_f32: compared by R6).  n >= 3.  Returns 0 and sets *ok = 0 if
- * memory runs out. */
-uint32_t qmso_mom_pivot(const uint32_t *keys, size_t n, int is_f32, int *ok)
+ * input (is_f32: compared by R6, binary32 or binary64 by the key width).
+ * n >= 3.  Returns 0 and sets *ok = 0 if memory runs out.  Exported from the
+ * counting builds as qmso_mom_pivot and qmso64_mom_pivot. */
+qkey_t QMSO_FN(mom_pivot)(const qkey_t *keys, size_t n, int is_f32, int *ok)
 {
     size_t c = n / 3;
-    uint32_t *med = malloc((c ? c : 1) * sizeof(uint32_t));
+    qkey_t *med = malloc((c ? c : 1) * sizeof(qkey_t));
     *ok = med != NULL && c > 0;
     if (!*ok) {
         free(med);
         return 0;
     }
     for (size_t i = 0; i < c; i++) {
-        uint32_t x = keys[3 * i], y = keys[3 * i + 1], z = keys[3 * i + 2];
+        qkey_t x = keys[3 * i], y = keys[3 * i + 1], z = keys[3 * i + 2];
         if (is_f32) {
             x = f32_bits_to_key(x);
             y = f32_bits_to_key(y);
             z = f32_bits_to_key(z);
         }
         /* median of three: the one that is neither the smallest nor the largest */
-        uint32_t lo = x < y ? x : y, hi = x < y ? y : x;
+        qkey_t lo = x < y ? x : y, hi = x < y ? y : x;
         med[i] = z < lo ? lo : (z > hi ? hi : z);
     }
-    qsort(med, c, sizeof(uint32_t), cmp_u32);
-    uint32_t p = med[(c - 1) / 2];
+    qsort(med, c, sizeof(qkey_t), cmp_key);
+    qkey_t p = med[(c - 1) / 2];
     free(med);
     return is_f32 ? key_to_f32_bits(p) : p;
 }
+#endif
 
+#if QMSO_COUNTING && QMSO_KEY_BITS == 32
 /* The pieces below are exported only from the counting build, for tests
  * that pin the individual routines: the partition, the Mergesort into a
  * target (msort), the Mergesort with a buffer (out) and the exchange merge

@@ -408,6 +408,68 @@ def test_mom_pivot_brute_force_small_words():
             assert oracle.mom_pivot(x) == _mom_pivot_by_counting(x)
 
 
+def test_mom_pivot_64_bit_brute_force():
+    """The 64-bit build's pivot by order-statistic counting on Python ints:
+    words over values that differ only above bit 31 (a build that compared
+    or kept 32 bits would tie or truncate them), then random 64-bit words."""
+    vals = [0, 1 << 33, (1 << 63) + 5, (1 << 64) - 1]
+    for n in range(3, 7):
+        for w in itertools.product(vals, repeat=n):
+            x = np.array(w, dtype=np.uint64)
+            assert oracle.mom_pivot(x) == _mom_pivot_by_counting(x), w
+    rng = np.random.default_rng(6)
+    for n in (8, 31, 100, 301):
+        for _ in range(20):
+            x = rng.integers(0, 2 ** 64, n, dtype=np.uint64)
+            assert oracle.mom_pivot(x) == _mom_pivot_by_counting(x)
+
+
+def test_mom_pivot_64_bit_agrees_with_32_bit_build():
+    """Keys below 2^32 widened to 64 bits have the same pivot in both builds."""
+    rng = np.random.default_rng(7)
+    for n in (3, 10, 1000, 4097):
+        x = rng.integers(0, 2 ** 32, n, dtype=np.uint64)
+        assert oracle.mom_pivot(x) == oracle.mom_pivot(x.astype(np.uint32))
+
+
+def test_mom_pivot_float64_numeric_order():
+    """Finite doubles of one sign per zero: the total order is the numeric
+    order, so counting on the float values gives the pivot."""
+    rng = np.random.default_rng(8)
+    for n in (3, 5, 100, 999):
+        for _ in range(10):
+            x = rng.standard_normal(n) * 10.0 ** rng.integers(-300, 300, n)
+            x[x == 0] = 1.0
+            p = oracle.mom_pivot(x)
+            c = n // 3
+            med = [sorted(x[3 * i:3 * i + 3].tolist())[1] for i in range(c)]
+            k = (c - 1) // 2
+            want = next(v for v in med if sum(u < v for u in med) <= k < sum(u <= v for u in med))
+            assert np.array([p], dtype=np.uint64).view(np.float64)[0] == want
+
+
+def test_mom_pivot_float64_total_order_specials():
+    """-0 below +0, NaNs with the sign bit below -inf and without it above
+    +inf (the IEEE-754 total order), each as its own bit pattern."""
+    f = lambda v: np.array(v, dtype=np.float64)
+    bits = lambda a: a.view(np.uint64)
+    nz, pz = f([-0.0]), f([0.0])
+    # medians -0, +0, +0: the lower median of three is +0
+    x = np.concatenate([nz, nz, pz, pz, pz, nz, pz, pz, nz])
+    assert oracle.mom_pivot(x) == int(bits(pz)[0])
+    # medians -0, -0, +0: -0
+    x = np.concatenate([nz, nz, pz, nz, pz, nz, pz, pz, nz])
+    assert oracle.mom_pivot(x) == int(bits(nz)[0])
+    qnan = bits(f([np.nan]))[0] & np.uint64((1 << 63) - 1)
+    pos_nan, neg_nan = qnan, qnan | np.uint64(1 << 63)
+    words = np.array([neg_nan, neg_nan, pos_nan], dtype=np.uint64)
+    assert oracle.mom_pivot(words.view(np.float64)) == int(neg_nan)
+    words = np.array([pos_nan, bits(f([np.inf]))[0], pos_nan], dtype=np.uint64)
+    assert oracle.mom_pivot(words.view(np.float64)) == int(pos_nan)
+    words = np.array([neg_nan, bits(f([-np.inf]))[0], pos_nan], dtype=np.uint64)
+    assert oracle.mom_pivot(words.view(np.float64)) == int(bits(f([-np.inf]))[0])
+
+
 @pytest.mark.parametrize("kind", ["uniform", "sorted", "reverse", "equal", "zipf", "organ",
                                   "triples_low_high"])
 @pytest.mark.parametrize("n", [3, 4, 5, 17, 1000, 65537])
