@@ -36,11 +36,11 @@ MUTANTS = {
         "return (u & KEY_SIGN) ? ~u : (u | KEY_SIGN);",
         "return (u & KEY_SIGN) ? ~u : u;"),
     "mom_upper_median": (
-        "uint32_t p = med[(c - 1) / 2];",
-        "uint32_t p = med[c / 2];"),
+        "qkey_t p = med[(c - 1) / 2];",
+        "qkey_t p = med[c / 2];"),
     "mom_triples_overlap": (
-        "uint32_t x = keys[3 * i], y = keys[3 * i + 1], z = keys[3 * i + 2];",
-        "uint32_t x = keys[2 * i], y = keys[2 * i + 1], z = keys[2 * i + 2];"),
+        "qkey_t x = keys[3 * i], y = keys[3 * i + 1], z = keys[3 * i + 2];",
+        "qkey_t x = keys[2 * i], y = keys[2 * i + 1], z = keys[2 * i + 2];"),
     "mom_median_of_three_wrong": (
         "med[i] = z < lo ? lo : (z > hi ? hi : z);",
         "med[i] = z < lo ? z : (z > hi ? hi : z);"),
