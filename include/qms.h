@@ -261,13 +261,15 @@ uint64_t qms_last_schedule(uint64_t *out, uint64_t max_rounds);
  * qms_sort (dt).  At least 2 floor(n/6) keys are <= it and as many >= it.
  * The same kernels pick the pivot inside a sort after an unbalanced round;
  * this entry point runs them on a whole array, for tests and callers that
- * want the pivot alone.  d_keys: n 32-bit words on the current device
- * (read only); *pivot_out (host) gets the pivot's bits.  Synchronises
+ * want the pivot alone.  d_keys: n keys of dtype dt on the current device
+ * (read only; 8-byte aligned for 64-bit keys); pivot_out (host) gets the
+ * pivot's bits: 4 bytes for QMS_U32, QMS_F32 and QMS_U32_LOG (whose order
+ * is the integers' order), 8 bytes for QMS_U64 and QMS_F64.  Synchronises
  * `stream`.  Errors: QMS_ERR_INVALID for NULL pointers or n < 3,
- * QMS_ERR_UNSUPPORTED for n >= 2^32 or a dt other than QMS_U32 / QMS_F32,
- * QMS_ERR_HIP.
+ * QMS_ERR_ALIGN for misaligned keys, QMS_ERR_UNSUPPORTED for n >= 2^32 or
+ * an unknown dt, QMS_ERR_HIP.
  */
-int qms_mom_pivot(const void *d_keys, uint64_t n, int dt, uint32_t *pivot_out,
+int qms_mom_pivot(const void *d_keys, uint64_t n, int dt, void *pivot_out,
                   hipStream_t stream);
 
 /*

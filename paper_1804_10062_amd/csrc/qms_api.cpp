@@ -412,25 +412,38 @@ uint64_t qms_last_schedule(uint64_t *out, uint64_t max_rounds) {
     return n;
 }
 
-int qms_mom_pivot(const void *d_keys, uint64_t n, int dt, uint32_t *pivot_out,
+int qms_mom_pivot(const void *d_keys, uint64_t n, int dt, void *pivot_out,
                   hipStream_t stream) {
     try {
         if (!d_keys || !pivot_out) return set_error(QMS_ERR_INVALID, "NULL keys or output");
-        if (dt != QMS_U32 && dt != QMS_F32) return set_error(QMS_ERR_UNSUPPORTED, "the pivot entry point takes 32-bit keys (QMS_U32, QMS_F32)");
+        if (!dtype_known(dt)) return set_error(QMS_ERR_UNSUPPORTED, "unknown dtype");
         if (n < 3) return set_error(QMS_ERR_INVALID, "the pivot needs n >= 3");
         if (n >= (1ull << 32)) return set_error(QMS_ERR_UNSUPPORTED, "n must be below 2^32");
+        const bool wide = dtype_wide(dt);
         int dev = -1;
-        int rc = check_device_ptr(d_keys, "keys", &dev);
+        int rc = check_device_ptr(d_keys, "keys", &dev, wide ? 8 : 4);
         if (rc != QMS_OK) return rc;
         DeviceScope scope(dev);
         WorkspaceLease ws;
         rc = get_workspace(dev, stream, &ws);
         if (rc != QMS_OK) return rc;
-        uint32_t p = 0;
+        uint64_t p = 0;
         rc = mom_pivot_of(dt, (const uint32_t *)d_keys, n, *ws, stream, &p);
         if (rc != QMS_OK) return rc;
-        // order-mapped key back to the caller's bits
-        *pivot_out = dt == QMS_F32 ? (p ^ ((uint32_t)((int32_t)(~p) >> 31) | 0x80000000u)) : p;
+        // order-mapped key back to the caller's bits (the total order's map
+        // undone for floats; integers and the logarithm order map to themselves)
+        if (dt == QMS_F32) {
+            const uint32_t k = (uint32_t)p;
+            p = k ^ ((uint32_t)((int32_t)(~k) >> 31) | 0x80000000u);
+        } else if (dt == QMS_F64) {
+            p ^= (uint64_t)((int64_t)(~p) >> 63) | 0x8000000000000000ull;
+        }
+        if (wide) {
+            std::memcpy(pivot_out, &p, sizeof(uint64_t));
+        } else {
+            const uint32_t p32 = (uint32_t)p;
+            std::memcpy(pivot_out, &p32, sizeof(uint32_t));
+        }
         return QMS_OK;
     } catch (...) {
         return set_error(QMS_ERR_NOMEM, "host exception in qms_mom_pivot");

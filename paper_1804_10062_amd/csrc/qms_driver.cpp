@@ -654,7 +654,7 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
 }
 
 int mom_pivot_of(int dt, const uint32_t *keys, uint64_t n, Workspace &ws, hipStream_t st,
-                 uint32_t *pivot) {
+                 uint64_t *pivot) {
     ArenaUse use(ws, st);
     Arena &ar = use.ar;
     PartSeg seg{(uint32_t *)keys, nullptr, 0, (uint32_t)n, 0, 0, 0, 0, kPivotMoM, 0};
@@ -664,7 +664,7 @@ int mom_pivot_of(int dt, const uint32_t *keys, uint64_t n, Workspace &ws, hipStr
     hipError_t e = hipMemcpyAsync(&p, ws.meta + M_PIVOT, sizeof(p), hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return hip_error(e, "median-of-medians pivot readback");
-    *pivot = (uint32_t)p;
+    *pivot = p;
     return QMS_OK;
 }
 

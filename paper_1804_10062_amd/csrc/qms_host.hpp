@@ -95,9 +95,10 @@ int sort_batch_device_rounds(int dt, bool pairs, char *keys_base, uint32_t *vals
                              const uint64_t *d_offsets, const uint64_t *h_off, uint32_t nseg,
                              uint64_t loop_exit, Workspace &ws, hipStream_t st);
 const std::vector<std::array<uint64_t, kScheduleWords>> &last_schedule();
-// The median-of-medians pivot of one array (order-mapped key into *pivot).
+// The median-of-medians pivot of one array (order-mapped key into *pivot;
+// keys: the array's first word, 32- or 64-bit keys by dt).
 int mom_pivot_of(int dt, const uint32_t *keys, uint64_t n, Workspace &ws, hipStream_t st,
-                 uint32_t *pivot);
+                 uint64_t *pivot);
 
 // Makes `dev` current for the lifetime of the object.
 class DeviceScope {

@@ -123,7 +123,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.qms_profile_begin.restype = i32
     lib.qms_profile_end.argtypes = [ctypes.POINTER(KernelStat), i32, ctypes.POINTER(i32)]
     lib.qms_profile_end.restype = i32
-    lib.qms_mom_pivot.argtypes = [vp, u64, i32, u32p, vp]
+    lib.qms_mom_pivot.argtypes = [vp, u64, i32, vp, vp]
     lib.qms_mom_pivot.restype = i32
     lib.qms_set_tuning.argtypes = [ctypes.POINTER(Tuning)]
     lib.qms_set_tuning.restype = i32
@@ -245,12 +245,14 @@ def qms_last_schedule(max_rounds: int = 4096):
     return [tuple(buf[w * i:w * i + w]) for i in range(min(n, max_rounds))]
 
 
-def qms_mom_pivot(keys, stream=None) -> int:
-    """Median of the medians of the triples of `keys` (1-D device tensor,
-    uint32/int32 bits or float32), as the 32-bit pattern of the pivot."""
+def qms_mom_pivot(keys, stream=None, dtype: Optional[int] = None) -> int:
+    """Median of the medians of the triples of `keys` (1-D device tensor of
+    32- or 64-bit keys, dtype as in qms_sort), as the bit pattern of the
+    pivot (32 or 64 bits by the key width)."""
     _check_tensor(keys, "keys")
-    out = ctypes.c_uint32()
-    _check(load_library().qms_mom_pivot(keys.data_ptr(), keys.numel(), _dtype_code(keys),
+    dt = _dtype_code(keys) if dtype is None else dtype
+    out = ctypes.c_uint64() if dt in (QMS_U64, QMS_F64) else ctypes.c_uint32()
+    _check(load_library().qms_mom_pivot(keys.data_ptr(), keys.numel(), dt,
                                         ctypes.byref(out), _stream_handle(stream)),
            "qms_mom_pivot")
     return out.value

@@ -59,6 +59,46 @@ def test_mom_pivot_full_size_2_26():
     _pivot_parity(inputs.uniform_u32(1 << 26, seed=2))
 
 
+def _wide_to_device(x):
+    if x.dtype == np.float64:
+        return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    return torch.from_numpy(np.ascontiguousarray(x).view(np.int64)).cuda()
+
+
+@needs_gpu
+@pytest.mark.parametrize("n", [3, 7, 100, 8191, 24577, 100003, 1 << 20])
+def test_mom_pivot_u64(n):
+    """64-bit keys: eight 8-bit digit passes of the select, bit-exact with the
+    oracle's 64-bit build (keys spread over all 64 bits, and keys that differ
+    only in the upper word)."""
+    rng = np.random.default_rng(n)
+    x = rng.integers(0, 2 ** 64, n, dtype=np.uint64)
+    assert qms.qms_mom_pivot(_wide_to_device(x)) == oracle.mom_pivot(x)
+    hi = rng.integers(0, 5, n, dtype=np.uint64) << np.uint64(40)
+    y = hi | np.uint64(7)
+    assert qms.qms_mom_pivot(_wide_to_device(y)) == oracle.mom_pivot(y)
+
+
+@needs_gpu
+def test_mom_pivot_f64():
+    rng = np.random.default_rng(9)
+    x = rng.standard_normal(200003)
+    assert qms.qms_mom_pivot(_wide_to_device(x)) == oracle.mom_pivot(x)
+    specials = np.array([0.0, -0.0, np.inf, -np.inf, 5e-324, -5e-324, 1.7e308, -1.7e308],
+                        dtype=np.float64)
+    y = rng.permutation(np.tile(specials, 1001))
+    assert qms.qms_mom_pivot(_wide_to_device(y)) == oracle.mom_pivot(y)
+
+
+@needs_gpu
+def test_mom_pivot_log_order_is_the_integer_pivot():
+    """Under the logarithm comparison the order is the integers' own, so the
+    pivot is the plain uint32 one."""
+    x = inputs.uniform_u32(100003, seed=12)
+    got = qms.qms_mom_pivot(to_device(x), dtype=qms.QMS_U32_LOG)
+    assert got == oracle.mom_pivot(x)
+
+
 @needs_gpu
 def test_mom_pivot_rejects_short_input():
     t = to_device(np.array([1, 2], dtype=np.uint32))
