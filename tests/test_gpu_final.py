@@ -198,3 +198,48 @@ def test_final_network_many_ranges_in_one_round(dt):
         want, _, _ = oracle.sort(x, counted=False)
         got = t.cpu().numpy().view(want.dtype)
         np.testing.assert_array_equal(got.view(np.uint8), want.view(np.uint8))
+
+
+@needs_gpu
+@pytest.mark.parametrize("kind,n", [
+    ("u32", 3_000_017),                    # below the exit size: one round, then the network
+    ("u32", (1 << 24) + (1 << 22) + 3),    # above 2^24: several device-planned rounds
+    ("u64", (1 << 23) + 12_345),           # 64-bit keys leave at 2^23
+    ("log", (1 << 22) + 5),                # the logarithm order leaves at 2^22
+])
+def test_qms_sort_captured_at_the_default_exit_size(kind, n):
+    """qms_sort under stream capture with the library defaults: the device
+    plans the rounds down to the automatic exit size of the key type and the
+    network sorts what is left; every replay is the oracle's sort bit for
+    bit, with eager work between replays."""
+    rng = np.random.default_rng(n)
+    if kind == "u64":
+        x = rng.integers(0, 2 ** 64, n, dtype=np.uint64)
+        src = torch.from_numpy(x.view(np.int64)).cuda()
+        dt = qms.QMS_U64
+    else:
+        x = inputs.uniform_u32(n, seed=n % 11)
+        src = to_device(x)
+        dt = qms.QMS_U32_LOG if kind == "log" else qms.QMS_U32
+    s = torch.cuda.Stream()
+    work = src.clone()
+    with torch.cuda.stream(s):
+        qms.qms_sort(work, stream=s, dtype=dt)  # outside the capture: the stream's workspace
+    s.synchronize()
+    g = torch.cuda.CUDAGraph()
+    work.copy_(src)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g, stream=s):
+        qms.qms_sort(work, stream=s, dtype=dt)
+    want, _, _ = oracle.sort(x, counted=False)
+    for _ in range(2):
+        work.copy_(src)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = work.cpu().numpy()
+        np.testing.assert_array_equal(got.view(np.uint8), want.view(np.uint8))
+        _ = (src.float() * 2).sum().item()  # eager work between replays
+    with torch.cuda.stream(s):
+        qms.qms_batch_check(stream=s)
+    del g
