@@ -332,7 +332,11 @@ int qms_profile_end(qms_kernel_stat *out, int max_entries, int *n_out);
  *                   (automatic, the default): 2^24 keys for 32-bit keys,
  *                   2^23 for QMS_U64 and QMS_F64, 2^22 for QMS_U32_LOG,
  *                   whose network comparisons cost the most time (the
- *                   sizes measured fastest for each type); else a power
+ *                   sizes measured fastest for each type); when one loop
+ *                   sorts several arrays (a batch of the server), the
+ *                   smallest power of two p >= the base tile for which
+ *                   (arrays longer than p) * p reaches four times that
+ *                   size, if there is one below it; else a power
  *                   of two in [8192, 2^30]; 8192 keeps
  *                   every range in the loop down to the base tile, as in
  *                   the paper.  Used by the host-planned loop (qms_sort,

@@ -243,3 +243,40 @@ def test_qms_sort_captured_at_the_default_exit_size(kind, n):
     with torch.cuda.stream(s):
         qms.qms_batch_check(stream=s)
     del g
+
+
+@needs_gpu
+def test_server_batches_at_the_automatic_exit_size():
+    """The server sorts each batch of requests in one host-driven loop; with
+    the automatic exit size a batch whose requests still in the loop hold
+    enough keys together leaves it earlier than one array would (here about
+    80 requests of 2^20 keys per key type: the exit falls to 2^20 or below).
+    Mixed uint32 and float32 requests, a few small ones among them, each
+    bit-exact with the oracle."""
+    import time
+    rng = np.random.default_rng(2024)
+    sizes = (1 << 20) + rng.integers(0, 4096, 164)
+    sizes[:4] = [3, 16385, 5000, 300001]
+    xs, ts = [], []
+    for j, n in enumerate(sizes):
+        if j % 2:
+            x = rng.standard_normal(int(n)).astype(np.float32)
+            t = torch.from_numpy(x).cuda()
+        else:
+            x = rng.integers(0, 1 << 32, int(n), dtype=np.uint64).astype(np.uint32)
+            t = torch.from_numpy(x.view(np.int32)).cuda()
+        xs.append(x)
+        ts.append(t)
+    torch.cuda.synchronize()
+    assert qms.qms_get_tuning()["final_tile"] == 0
+    with qms.Server(hbm_budget_bytes=1 << 33) as srv:
+        tickets = [srv.submit(t) for t in ts]
+        t_end = time.time() + 120
+        for tk in tickets:
+            while srv.poll(tk)[0] != qms.QMS_OK:
+                assert time.time() < t_end, "request not done"
+                time.sleep(0.001)
+    for x, t in zip(xs, ts):
+        want, _, _ = oracle.sort(x, counted=False)
+        got = t.cpu().numpy().view(want.dtype)
+        np.testing.assert_array_equal(got.view(np.uint8), want.view(np.uint8))
