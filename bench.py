@@ -596,7 +596,9 @@ def main():
         # applies the logarithm to the integer keys): a random order of
         # 1..2^26 sorted with the plain uint32 order and with QMS_U32_LOG,
         # whose every comparison evaluates two double logarithms, at the
-        # automatic X_THRESH and at 2048 (fewer network comparisons per key)
+        # automatic X_THRESH (2048 for the logarithm order, 16384 for plain
+        # keys) and at 16384 (more network comparisons per key, fewer merge
+        # levels)
         print("[bench] log comparator", file=sys.stderr, flush=True)
         from paper_1804_10062_amd import autotune
         nl = 1 << 26
@@ -604,7 +606,7 @@ def main():
         want = torch.arange(1, nl + 1, dtype=torch.int64, device=dev)
         logcmp = {"workload": "a random order of 1..2^26 (uint32), SplitMix64-keyed Feistel permutation, seed 11"}
         try:
-            for label, bt in (("auto", 0), ("2048", 2048)):
+            for label, bt in (("auto", 0), ("16384", 16384)):
                 qms.qms_set_tuning(4, 4096, 16384, bt, 0)
                 for name, code in (("plain", qms.QMS_U32), ("log", qms.QMS_U32_LOG)):
                     cps = [s3.clone() for _ in range(3)]

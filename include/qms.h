@@ -318,7 +318,8 @@ int qms_profile_end(qms_kernel_stat *out, int max_entries, int *n_out);
  *                   merging four runs per pass takes half of that for a
  *                   Mergesort whose level count would otherwise be odd;
  *                   2048 for 64-bit keys, whose network costs more per
- *                   level than a merge level.
+ *                   level than a merge level, and for QMS_U32_LOG, whose
+ *                   network comparisons cost more than the merges'.
  *   final_tile      a range that a partition round leaves with at most this
  *                   many keys leaves the QuickMergesort loop and is sorted
  *                   in place by X = a bitonic network (QuickXsort with X at

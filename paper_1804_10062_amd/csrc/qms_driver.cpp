@@ -214,12 +214,16 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
     // sorts take half of it when that makes the level count even, so that
     // every pass merges four runs (no 2-way first pass); 64-bit keys take
     // runs of kMergeTile keys, since their 64-bit network costs more per
-    // level than a merge level (2^27 uint64: 11.0 against 10.6 Gkeys/s)
+    // level than a merge level (2^27 uint64: 11.0 against 10.6 Gkeys/s), and
+    // so does the logarithm order, whose network comparisons cost more than
+    // the merges' (QuickMergeXsort's trade-off; 2^26 keys: 1.95 against
+    // 1.56 Gkeys/s)
     const bool auto_r0 = tune.base_tile == 0;
+    const bool short_runs = wide || dt == QMS_U32_LOG;
     // 64-bit keys with payloads merge two runs per pass (a 4-way tile of
     // their 96-bit elements would not fit the LDS budget)
     const bool four_way_sort = tune.merge_ways == 4 && !(pairs && wide);
-    const uint32_t R0 = auto_r0 ? (wide ? (uint32_t)kMergeTile : T0) : std::min(T0, tune.base_tile);
+    const uint32_t R0 = auto_r0 ? (short_runs ? (uint32_t)kMergeTile : T0) : std::min(T0, tune.base_tile);
     auto levels = [](uint64_t m, uint32_t r) -> uint32_t {
         return m > r ? ceil_log2((m + r - 1) / r) : 0;
     };
@@ -227,7 +231,7 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
     auto set_levels = [&](SortSeg &t) {
         t.w0 = R0;
         t.L = levels(t.m, R0);
-        if (auto_r0 && four_way_sort && !wide && (t.L & 1u)) {
+        if (auto_r0 && four_way_sort && !short_runs && (t.L & 1u)) {
             t.w0 = R0 / 2;
             t.L = levels(t.m, t.w0);
         }

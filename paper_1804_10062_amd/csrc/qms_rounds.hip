@@ -749,9 +749,12 @@ int sort_batch_device_rounds(int dt, bool pairs, char *keys_base, uint32_t *vals
     const bool auto_r0 = tune.base_tile == 0;
     // 64-bit keys with payloads merge two runs per pass
     const bool four_way = tune.merge_ways == 4 && !(pairs && wide);
-    const uint32_t R0 = auto_r0 ? (wide ? (uint32_t)kMergeTile : T0) : std::min(T0, tune.base_tile);
+    // automatic runs of kMergeTile keys for 64-bit keys and the logarithm
+    // order (as the host-planned loop takes them), never halved
+    const bool short_runs = wide || dt == QMS_U32_LOG;
+    const uint32_t R0 = auto_r0 ? (short_runs ? (uint32_t)kMergeTile : T0) : std::min(T0, tune.base_tile);
     // the smallest run width a Mergesort can take (automatic: half of R0)
-    const uint32_t R0_min = (auto_r0 && four_way && !wide) ? R0 / 2 : R0;
+    const uint32_t R0_min = (auto_r0 && four_way && !short_runs) ? R0 / 2 : R0;
     const uint32_t S = ws.caps.segs;
     hipError_t e = hipSuccess;
 
@@ -801,7 +804,7 @@ int sort_batch_device_rounds(int dt, bool pairs, char *keys_base, uint32_t *vals
         A.span = tune.chunk_span;
         A.T0 = T0;
         A.R0 = R0;
-        A.auto_r0 = auto_r0;
+        A.auto_r0 = auto_r0 && !short_runs;
         A.four_way = four_way;
         A.wide = wide;
         A.ew = ew;
@@ -930,7 +933,7 @@ int sort_batch_device_rounds(int dt, bool pairs, char *keys_base, uint32_t *vals
             A.F = (uint32_t)F;
             A.xfinal = r == R ? 1u : 0u;
             A.steps = steps;
-            A.first2 = four_way && (!auto_r0 || wide) && Lmax > 0;
+            A.first2 = four_way && (!auto_r0 || short_runs) && Lmax > 0;
             A.partitioned = r < R && bmax > 0;
             if (A.partitioned) {
                 hipLaunchKernelGGL(k_rounds_plan_count, dim3(NBp), dim3(kPB), 0, st, A, P, ws.r_blk);

@@ -226,12 +226,14 @@ def test_qms_sort_captured_at_the_default_exit_size(kind, n):
     with torch.cuda.stream(s):
         qms.qms_sort(work, stream=s, dtype=dt)  # outside the capture: the stream's workspace
     s.synchronize()
+    want, _, _ = oracle.sort(x, counted=False)
+    # the eager call (host-planned rounds, the same defaults) is the oracle's too
+    np.testing.assert_array_equal(work.cpu().numpy().view(np.uint8), want.view(np.uint8))
     g = torch.cuda.CUDAGraph()
     work.copy_(src)
     torch.cuda.synchronize()
     with torch.cuda.graph(g, stream=s):
         qms.qms_sort(work, stream=s, dtype=dt)
-    want, _, _ = oracle.sort(x, counted=False)
     for _ in range(2):
         work.copy_(src)
         torch.cuda.synchronize()
