@@ -353,6 +353,15 @@ __device__ __forceinline__ void tile_sort_block(typename O::K *sk, uint32_t *sv,
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & (kWave - 1);
 
+    // A tile of len < T keys: its keys and padding sorted as the first P
+    // positions (P the power of two at or above len, at least ITEMS) are the
+    // sorted keys, so the network stops at runs of P (then all ascending) and
+    // waves wholly past P skip the compare-exchanges (they still take part in
+    // the barriers).  The last stage's half-cleaners of MERGE_ONLY start at
+    // P / 2: a partner at P or beyond is padding and never moves.
+    const uint32_t P = len >= T ? T : len <= (uint32_t)ITEMS ? (uint32_t)ITEMS
+                                                             : 2u << (31 - __builtin_clz(len - 1));
+
     // 1. coalesced loads (clamped indices, all issued together); in swap mode
     //    each thread then moves the buffer elements of exactly the source
     //    cells it has read into those cells
@@ -360,10 +369,34 @@ __device__ __forceinline__ void tile_sort_block(typename O::K *sk, uint32_t *sv,
         K kv[ITEMS];
 #pragma unroll
         for (int r = 0; r < ITEMS; ++r) kv[r] = ldg(sk + min((uint32_t)r * NT + tid, len - 1));
+        if constexpr (MERGE_ONLY) {
+            // As loaded, register r of a thread holds position r NT + tid, so
+            // the last stage's half-cleaners with strides of NT or more pair
+            // registers of one thread: they run here, before the elements go
+            // through LDS, ascending as every step of that stage (a partner
+            // past len is padding, which compares above every key and so
+            // never moves)
+            E x[ITEMS];
 #pragma unroll
-        for (int r = 0; r < ITEMS; ++r) {
-            const uint32_t e = (uint32_t)r * NT + tid;
-            s[nat_idx<ITEMS>(e)] = e < len ? TE::make(O::ord(kv[r]), e) : TE::pad(e);
+            for (int r = 0; r < ITEMS; ++r) {
+                const uint32_t e = (uint32_t)r * NT + tid;
+                x[r] = e < len ? TE::make(O::ord(kv[r]), e) : TE::pad(e);
+            }
+#pragma unroll
+            for (int q = ITEMS / 2; q >= 1; q >>= 1) {
+                if ((uint32_t)q * NT * 2 > P) continue;  // stride q NT, from P / 2 down
+#pragma unroll
+                for (int r = 0; r < ITEMS; ++r)
+                    if ((r & q) == 0) cmpx_elem<TE>(x[r], x[r | q], true);
+            }
+#pragma unroll
+            for (int r = 0; r < ITEMS; ++r) s[nat_idx<ITEMS>((uint32_t)r * NT + tid)] = x[r];
+        } else {
+#pragma unroll
+            for (int r = 0; r < ITEMS; ++r) {
+                const uint32_t e = (uint32_t)r * NT + tid;
+                s[nat_idx<ITEMS>(e)] = e < len ? TE::make(O::ord(kv[r]), e) : TE::pad(e);
+            }
         }
         if constexpr (PAIRS) {
 #pragma unroll
@@ -402,14 +435,6 @@ __device__ __forceinline__ void tile_sort_block(typename O::K *sk, uint32_t *sv,
 #pragma unroll
     for (int i = 0; i < ITEMS; ++i) r[i] = s[nat_idx<ITEMS>(base + i)];
 
-    // A tile of len < T keys: its keys and padding sorted as the first P
-    // positions (P the power of two at or above len, at least ITEMS) are the
-    // sorted keys, so the network stops at runs of P (then all ascending) and
-    // waves wholly past P skip the compare-exchanges (they still take part in
-    // the barriers).  The last stage's half-cleaners of MERGE_ONLY start at
-    // P / 2: a partner at P or beyond is padding and never moves.
-    const uint32_t P = len >= T ? T : len <= (uint32_t)ITEMS ? (uint32_t)ITEMS
-                                                             : 2u << (31 - __builtin_clz(len - 1));
     const uint32_t top = MERGE_ONLY ? run : (run < P ? run : P);
     const bool wact = (tid & ~(uint32_t)(kWave - 1)) * (uint32_t)ITEMS < P;
 
@@ -445,6 +470,8 @@ __device__ __forceinline__ void tile_sort_block(typename O::K *sk, uint32_t *sv,
         for (int i = 0; i < ITEMS; ++i) r[i] ^= flip;
         const bool asc = true;
         uint32_t j = (k < P ? k : P) >> 1;
+        // MERGE_ONLY: the strides of NT and more ran before the transposition
+        if constexpr (MERGE_ONLY) j = j < (uint32_t)NT / 2 ? j : (uint32_t)NT / 2;
         // partners in other waves: exchange through LDS (partners of a
         // thread before P lie before P)
         for (; j >= (uint32_t)kWave * ITEMS; j >>= 1) {
