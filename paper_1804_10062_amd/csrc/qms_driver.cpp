@@ -247,25 +247,12 @@ static int sort_group(int dt, bool pairs, std::vector<Seg> &segs, Workspace &ws,
     // the base case in place; every larger one is partitioned at least once,
     // so its top level is always QuickMergesort's (partition, Mergesort of
     // one side with the other side as its buffer).
-    // With several arrays in the group a round's fixed costs (its launches
-    // and the counters read back) are paid once for all of them, and so are
-    // the network's.  A group keeps looping while its arrays still in the
-    // loop hold enough keys together to make a round worth its costs: the
-    // exit size is the smallest power of two p >= T0 with (arrays longer
-    // than p) * p at least four times the one-array size (the factor
-    // measured on batches of serving requests: batches of tens of requests
-    // keep the one-array size, saturated batches of hundreds leave at about
-    // 2^18 keys, 1.8 times the throughput).
+    // several arrays in one loop leave it earlier (group_loop_exit)
     uint64_t TF = std::max<uint64_t>(T0, loop_exit_keys(tune, dt));
     if (tune.final_tile == 0 && segs.size() > 1) {
-        for (uint64_t p = T0; p < TF; p *= 2) {
-            uint64_t longer = 0;
-            for (const Seg &g : segs) longer += (g.hi - g.lo) > p;
-            if (longer * p >= 4 * TF) {
-                TF = p;
-                break;
-            }
-        }
+        std::vector<uint64_t> lens(segs.size());
+        for (size_t i = 0; i < segs.size(); ++i) lens[i] = segs[i].hi - segs[i].lo;
+        TF = group_loop_exit(TF, T0, lens.data(), lens.size());
     }
     // a final range: the base case sorts its tiles in place (L = 0), the
     // network finishes it if it is longer than one tile

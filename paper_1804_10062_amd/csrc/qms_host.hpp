@@ -41,6 +41,23 @@ inline uint64_t loop_exit_keys(const Tuning &t, int dt) {
     if (dt == 4) return 1ull << 22;
     return (dt == 2 || dt == 3) ? (1ull << 23) : (1ull << 24);
 }
+// The automatic exit size of one loop over several arrays of lengths
+// len[0..count) whose one-array exit size is `one`.  A round's fixed costs
+// (its launches and the counters read back) are paid once for all of them,
+// and so are the network's.  The group keeps looping while its arrays still
+// in the loop hold enough keys together to make a round worth those costs:
+// the smallest power of two p >= T0 with (arrays longer than p) * p at
+// least four times `one` (the factor measured on batches of serving
+// requests: batches of tens of requests keep the one-array size, saturated
+// batches of hundreds leave at about 2^18 keys), else `one`.
+inline uint64_t group_loop_exit(uint64_t one, uint64_t T0, const uint64_t *len, size_t count) {
+    for (uint64_t p = T0; p < one; p *= 2) {
+        uint64_t longer = 0;
+        for (size_t i = 0; i < count; ++i) longer += len[i] > p;
+        if (longer * p >= 4 * one) return p;
+    }
+    return one;
+}
 
 int set_error(int code, const std::string &msg);
 int hip_error(hipError_t e, const char *where);

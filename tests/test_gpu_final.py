@@ -282,3 +282,40 @@ def test_server_batches_at_the_automatic_exit_size():
         want, _, _ = oracle.sort(x, counted=False)
         got = t.cpu().numpy().view(want.dtype)
         np.testing.assert_array_equal(got.view(np.uint8), want.view(np.uint8))
+
+
+@needs_gpu
+@pytest.mark.parametrize("kind", ["u32", "u64"])
+def test_server_large_batches(kind):
+    """Server batches of about 100 large requests (2^21 keys, or 2^20 for
+    64-bit keys) with small ones among them, at the library defaults: the
+    batch's automatic exit falls to 2^20 keys or below.  Each request
+    bit-exact with the oracle."""
+    import time
+    rng = np.random.default_rng(7 if kind == "u32" else 8)
+    big = (1 << 21) if kind == "u32" else (1 << 20)
+    sizes = list(big + rng.integers(0, 4096, 100)) + list(rng.integers(2, 20000, 60)) + [2, 3, 16385]
+    xs, ts = [], []
+    for n in sizes:
+        if kind == "u32":
+            x = rng.integers(0, 1 << 32, int(n), dtype=np.uint64).astype(np.uint32)
+            t = torch.from_numpy(x.view(np.int32)).cuda()
+        else:
+            x = rng.integers(0, 2 ** 64, int(n), dtype=np.uint64)
+            t = torch.from_numpy(x.view(np.int64)).cuda()
+        xs.append(x)
+        ts.append(t)
+    torch.cuda.synchronize()
+    assert qms.qms_get_tuning()["final_tile"] == 0
+    with qms.Server(hbm_budget_bytes=1 << 34) as srv:
+        tickets = [srv.submit(t) for t in ts]
+        t_end = time.time() + 150
+        for tk in tickets:
+            while srv.poll(tk)[0] != qms.QMS_OK:
+                assert time.time() < t_end, "request not done"
+                time.sleep(0.001)
+        assert srv.stats()["batches"] >= 1
+    for x, t in zip(xs, ts):
+        want, _, _ = oracle.sort(x, counted=False)
+        got = t.cpu().numpy().view(want.dtype)
+        np.testing.assert_array_equal(got.view(np.uint8), want.view(np.uint8))
